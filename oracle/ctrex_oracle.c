@@ -1,0 +1,401 @@
+/*
+ * CPU FP64 oracle of the ray-driven projector pair — TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+ * may load this file's library.  It shares no code, header or constant with
+ * the HIP library; it is written to be read against the paper, not to be fast.
+ *
+ * What it computes (paper Sec. 2.2 geometry, Sec. 4.1 projection operator,
+ * Sec. 3.1 / 4.2.1 displacement warp, Sec. 3.4 / 4.2.2 angular sub-samples):
+ *
+ *   For projection p, sub-view s and pixel (iu, iv):
+ *     M = P[:, :3], source S = -M^-1 P[:, 3]          (the point P sends to 0)
+ *     d = M^-1 (iu, iv, 1)^T, normalised               (ray to the pixel centre)
+ *     the line S + t d is clipped to the voxel-centre hull [0, n_a - 1]^3 of
+ *     the index coordinates c = X + (n - 1)/2 (slab method) -> [t_in, t_out],
+ *     L = t_out - t_in, n = ceil(L / step), h = L / n   (midpoint rule)
+ *     samples c_i = S + (t_in + (i + 1/2) h) d, i = 0..n-1
+ *     optional warp: c_i' = c_i + tau_{p,s} U(c_i); a warped sample outside
+ *     the hull contributes nothing
+ *     y[p, iv, iu] = (1 / n_sub) sum_s sum_i h * trilinear(x, c_i')
+ *
+ *   The backprojector is the exact transpose: every sample scatters
+ *   (h / n_sub) * r[p, iv, iu] times its eight trilinear weights.
+ *
+ * Readings where the paper is silent: uniform Euclidean step adjusted per ray
+ * (instead of dominant-axis slices), integration over the voxel-centre hull,
+ * path-length weight h per sample, one ray per pixel centre, the mean over
+ * sub-views, and a pull-back warp evaluated at the undeformed sample.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ESINGULAR (-3)
+#define OR_ESOURCE_INSIDE (-4)
+
+typedef struct {
+    double S[3];    /* source in index coordinates (x, y, z) */
+    double Mi[9];   /* inverse of P[:, :3], row-major */
+    double tau;     /* time fraction of the sub-view (warp scale) */
+} view_t;
+
+typedef struct {
+    int nx, ny, nz;
+    const double *U;  /* [gz][gy][gx][3] displacement grid or NULL */
+    int gx, gy, gz;
+} warp_t;
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Source position and inverse matrix of one 3x4 view matrix (Sec. 2.2.1). */
+static int view_setup(const double *P, const int n[3], double tau, view_t *v)
+{
+    const double a = P[0], b = P[1], c = P[2];
+    const double d = P[4], e = P[5], f = P[6];
+    const double g = P[8], h = P[9], i = P[10];
+    double det = a * (e * i - f * h) - b * (d * i - f * g) + c * (d * h - e * g);
+    double fro = 0.0;
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k)
+            fro += P[4 * r + k] * P[4 * r + k];
+    fro = sqrt(fro);
+    if (!(fro > 0.0) || !(fabs(det) >= 1e-12 * fro * fro * fro))
+        return OR_ESINGULAR;
+    /* inverse = adjugate / det */
+    v->Mi[0] = (e * i - f * h) / det;
+    v->Mi[1] = (c * h - b * i) / det;
+    v->Mi[2] = (b * f - c * e) / det;
+    v->Mi[3] = (f * g - d * i) / det;
+    v->Mi[4] = (a * i - c * g) / det;
+    v->Mi[5] = (c * d - a * f) / det;
+    v->Mi[6] = (d * h - e * g) / det;
+    v->Mi[7] = (b * g - a * h) / det;
+    v->Mi[8] = (a * e - b * d) / det;
+    int inside = 1;
+    for (int r = 0; r < 3; ++r) {
+        double s = -(v->Mi[3 * r] * P[3] + v->Mi[3 * r + 1] * P[7] + v->Mi[3 * r + 2] * P[11]);
+        v->S[r] = s + 0.5 * (n[r] - 1); /* centred V frame -> index coordinates */
+        if (v->S[r] < 0.0 || v->S[r] > (double)(n[r] - 1))
+            inside = 0;
+    }
+    if (inside)
+        return OR_ESOURCE_INSIDE;
+    v->tau = tau;
+    return OR_OK;
+}
+
+/* Unit direction of the ray through pixel (u, v). */
+static void ray_direction(const view_t *v, double u, double w, double dir[3])
+{
+    double len = 0.0;
+    for (int r = 0; r < 3; ++r) {
+        dir[r] = v->Mi[3 * r] * u + v->Mi[3 * r + 1] * w + v->Mi[3 * r + 2];
+        len += dir[r] * dir[r];
+    }
+    len = sqrt(len);
+    for (int r = 0; r < 3; ++r)
+        dir[r] /= len;
+}
+
+/* Slab clipping of S + t dir against [0, n_a - 1] on every axis. */
+static int clip_hull(const double S[3], const double dir[3], const int n[3],
+                     double *t_in, double *t_out)
+{
+    double lo_t = -INFINITY, hi_t = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        double lo = 0.0, hi = (double)(n[a] - 1);
+        if (dir[a] == 0.0) {
+            if (S[a] < lo || S[a] > hi)
+                return 0;
+            continue;
+        }
+        double t1 = (lo - S[a]) / dir[a];
+        double t2 = (hi - S[a]) / dir[a];
+        double tmin = t1 < t2 ? t1 : t2;
+        double tmax = t1 < t2 ? t2 : t1;
+        if (tmin > lo_t) lo_t = tmin;
+        if (tmax < hi_t) hi_t = tmax;
+    }
+    *t_in = lo_t;
+    *t_out = hi_t;
+    return hi_t > lo_t;
+}
+
+/* Lower corner and fraction of a coordinate on an axis of n >= 2 nodes. */
+static void corner(double c, int n, int *i0, double *f)
+{
+    if (c < 0.0) c = 0.0;
+    if (c > (double)(n - 1)) c = (double)(n - 1);
+    int k = (int)floor(c);
+    if (k > n - 2) k = n - 2;
+    *i0 = k;
+    *f = c - (double)k;
+}
+
+/* Trilinear interpolation of a [nz][ny][nx] array with `comp` values per node. */
+static double trilinear(const double *vol, int nx, int ny, int nz, int comp, int which,
+                        const double c[3])
+{
+    int ix, iy, iz;
+    double fx, fy, fz;
+    corner(c[0], nx, &ix, &fx);
+    corner(c[1], ny, &iy, &fy);
+    corner(c[2], nz, &iz, &fz);
+    double acc = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double w = (dx ? fx : 1.0 - fx) * (dy ? fy : 1.0 - fy) * (dz ? fz : 1.0 - fz);
+                size_t idx = ((size_t)(iz + dz) * ny + (iy + dy)) * nx + (ix + dx);
+                acc += w * vol[idx * comp + which];
+            }
+    return acc;
+}
+
+/* Transpose of trilinear(): add val times the eight weights. */
+static void trilinear_scatter(double *vol, int nx, int ny, int nz, const double c[3], double val)
+{
+    int ix, iy, iz;
+    double fx, fy, fz;
+    corner(c[0], nx, &ix, &fx);
+    corner(c[1], ny, &iy, &fy);
+    corner(c[2], nz, &iz, &fz);
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double w = (dx ? fx : 1.0 - fx) * (dy ? fy : 1.0 - fy) * (dz ? fz : 1.0 - fz);
+                size_t idx = ((size_t)(iz + dz) * ny + (iy + dy)) * nx + (ix + dx);
+#pragma omp atomic
+                vol[idx] += w * val;
+            }
+}
+
+/* Pull-back warp of a sample (Sec. 3.1): c' = c + tau U(c).  The grid nodes span
+ * the hull (node k of an axis sits at c = k (n-1)/(g-1)); lookups are clamped
+ * to the grid.  Returns 0 when the warped sample leaves the hull. */
+static int warp_sample(const warp_t *w, double tau, double c[3])
+{
+    if (!w->U)
+        return 1;
+    const int n[3] = {w->nx, w->ny, w->nz};
+    const int g[3] = {w->gx, w->gy, w->gz};
+    double gc[3];
+    for (int a = 0; a < 3; ++a)
+        gc[a] = c[a] * (double)(g[a] - 1) / (double)(n[a] - 1);
+    double disp[3];
+    for (int comp = 0; comp < 3; ++comp)
+        disp[comp] = trilinear(w->U, w->gx, w->gy, w->gz, 3, comp, gc);
+    for (int a = 0; a < 3; ++a) {
+        c[a] += tau * disp[a];
+        if (c[a] < 0.0 || c[a] > (double)(n[a] - 1))
+            return 0;
+    }
+    return 1;
+}
+
+static int build_views(const double *P, int n_proj, int n_sub, const int n[3],
+                       const double *tau, view_t **out)
+{
+    view_t *tab = (view_t *)malloc(sizeof(view_t) * (size_t)n_proj * n_sub);
+    if (!tab)
+        return OR_EINVAL;
+    for (int k = 0; k < n_proj * n_sub; ++k) {
+        int st = view_setup(P + 12 * (size_t)k, n, tau ? tau[k] : 0.0, &tab[k]);
+        if (st != OR_OK) {
+            free(tab);
+            return st;
+        }
+    }
+    *out = tab;
+    return OR_OK;
+}
+
+static int check_dims(int n_proj, int n_sub, int nu, int nv, int nx, int ny, int nz, double step,
+                      const int *views, int n_views)
+{
+    if (n_proj < 1 || n_sub < 1 || nu < 1 || nv < 1 || nx < 2 || ny < 2 || nz < 2)
+        return OR_EINVAL;
+    if (!(step > 0.0) || n_views < 0)
+        return OR_EINVAL;
+    if (views)
+        for (int k = 0; k < n_views; ++k)
+            if (views[k] < 0 || views[k] >= n_proj)
+                return OR_EINVAL;
+    return OR_OK;
+}
+
+/*
+ * Forward projection.  P: [n_proj][n_sub][3][4]; vol: [nz][ny][nx];
+ * views: n_views projection indices (NULL = 0..n_proj-1, n_views = n_proj);
+ * sino: [n_views][nv][nu] output; U/tau optional warp; *n_samples = total
+ * number of ray samples (warped-out samples included).
+ */
+int oracle_forward(const double *P, int n_proj, int n_sub, int nu, int nv,
+                   int nx, int ny, int nz, double step, const double *vol,
+                   const int *views, int n_views, const double *U, int gx, int gy, int gz,
+                   const double *tau, double *sino, int64_t *n_samples)
+{
+    if (!views)
+        n_views = n_proj;
+    int st = check_dims(n_proj, n_sub, nu, nv, nx, ny, nz, step, views, n_views);
+    if (st != OR_OK)
+        return st;
+    if (U && (gx < 2 || gy < 2 || gz < 2 || !tau))
+        return OR_EINVAL;
+    const int n[3] = {nx, ny, nz};
+    view_t *tab;
+    st = build_views(P, n_proj, n_sub, n, tau, &tab);
+    if (st != OR_OK)
+        return st;
+    warp_t w = {nx, ny, nz, U, gx, gy, gz};
+    int64_t total = 0;
+#pragma omp parallel for collapse(2) schedule(dynamic, 4) reduction(+ : total)
+    for (int k = 0; k < n_views; ++k) {
+        for (int iv = 0; iv < nv; ++iv) {
+            int p = views ? views[k] : k;
+            for (int iu = 0; iu < nu; ++iu) {
+                double acc = 0.0;
+                for (int s = 0; s < n_sub; ++s) {
+                    const view_t *v = &tab[(size_t)p * n_sub + s];
+                    double dir[3], t_in, t_out;
+                    ray_direction(v, (double)iu, (double)iv, dir);
+                    if (!clip_hull(v->S, dir, n, &t_in, &t_out))
+                        continue;
+                    double L = t_out - t_in;
+                    int64_t ns = (int64_t)ceil(L / step);
+                    double h = L / (double)ns;
+                    total += ns;
+                    for (int64_t i = 0; i < ns; ++i) {
+                        double t = t_in + ((double)i + 0.5) * h;
+                        double c[3] = {v->S[0] + t * dir[0], v->S[1] + t * dir[1], v->S[2] + t * dir[2]};
+                        if (!warp_sample(&w, v->tau, c))
+                            continue;
+                        acc += h * trilinear(vol, nx, ny, nz, 1, 0, c);
+                    }
+                }
+                sino[((size_t)k * nv + iv) * nu + iu] = acc / (double)n_sub;
+            }
+        }
+    }
+    free(tab);
+    if (n_samples)
+        *n_samples = total;
+    return OR_OK;
+}
+
+/* Backprojection, the exact transpose of oracle_forward: vol += A^T sino. */
+int oracle_back(const double *P, int n_proj, int n_sub, int nu, int nv,
+                int nx, int ny, int nz, double step, const double *sino,
+                const int *views, int n_views, const double *U, int gx, int gy, int gz,
+                const double *tau, double *vol)
+{
+    if (!views)
+        n_views = n_proj;
+    int st = check_dims(n_proj, n_sub, nu, nv, nx, ny, nz, step, views, n_views);
+    if (st != OR_OK)
+        return st;
+    if (U && (gx < 2 || gy < 2 || gz < 2 || !tau))
+        return OR_EINVAL;
+    const int n[3] = {nx, ny, nz};
+    view_t *tab;
+    st = build_views(P, n_proj, n_sub, n, tau, &tab);
+    if (st != OR_OK)
+        return st;
+    warp_t w = {nx, ny, nz, U, gx, gy, gz};
+#pragma omp parallel for collapse(2) schedule(dynamic, 4)
+    for (int k = 0; k < n_views; ++k) {
+        for (int iv = 0; iv < nv; ++iv) {
+            int p = views ? views[k] : k;
+            for (int iu = 0; iu < nu; ++iu) {
+                double r = sino[((size_t)k * nv + iv) * nu + iu];
+                for (int s = 0; s < n_sub; ++s) {
+                    const view_t *v = &tab[(size_t)p * n_sub + s];
+                    double dir[3], t_in, t_out;
+                    ray_direction(v, (double)iu, (double)iv, dir);
+                    if (!clip_hull(v->S, dir, n, &t_in, &t_out))
+                        continue;
+                    double L = t_out - t_in;
+                    int64_t ns = (int64_t)ceil(L / step);
+                    double h = L / (double)ns;
+                    for (int64_t i = 0; i < ns; ++i) {
+                        double t = t_in + ((double)i + 0.5) * h;
+                        double c[3] = {v->S[0] + t * dir[0], v->S[1] + t * dir[1], v->S[2] + t * dir[2]};
+                        if (!warp_sample(&w, v->tau, c))
+                            continue;
+                        trilinear_scatter(vol, nx, ny, nz, c, h * r / (double)n_sub);
+                    }
+                }
+            }
+        }
+    }
+    free(tab);
+    return OR_OK;
+}
+
+/*
+ * The same ray sampler with the trilinear lookup replaced by the indicator of
+ * one ellipsoid ||Q (c - centre)|| <= 1 (index coordinates).  Used to pin the
+ * sample positions and path-length weights against exact chord lengths.
+ */
+int oracle_forward_indicator(const double *P, int n_proj, int n_sub, int nu, int nv,
+                             int nx, int ny, int nz, double step, const double *Q,
+                             const double *centre, double *sino)
+{
+    int st = check_dims(n_proj, n_sub, nu, nv, nx, ny, nz, step, NULL, n_proj);
+    if (st != OR_OK)
+        return st;
+    const int n[3] = {nx, ny, nz};
+    view_t *tab;
+    st = build_views(P, n_proj, n_sub, n, NULL, &tab);
+    if (st != OR_OK)
+        return st;
+#pragma omp parallel for collapse(2) schedule(dynamic, 4)
+    for (int p = 0; p < n_proj; ++p) {
+        for (int iv = 0; iv < nv; ++iv) {
+            for (int iu = 0; iu < nu; ++iu) {
+                double acc = 0.0;
+                for (int s = 0; s < n_sub; ++s) {
+                    const view_t *v = &tab[(size_t)p * n_sub + s];
+                    double dir[3], t_in, t_out;
+                    ray_direction(v, (double)iu, (double)iv, dir);
+                    if (!clip_hull(v->S, dir, n, &t_in, &t_out))
+                        continue;
+                    double L = t_out - t_in;
+                    int64_t ns = (int64_t)ceil(L / step);
+                    double h = L / (double)ns;
+                    for (int64_t i = 0; i < ns; ++i) {
+                        double t = t_in + ((double)i + 0.5) * h;
+                        double q2 = 0.0;
+                        for (int r = 0; r < 3; ++r) {
+                            double qr = 0.0;
+                            for (int a = 0; a < 3; ++a)
+                                qr += Q[3 * r + a] * (v->S[a] + t * dir[a] - centre[a]);
+                            q2 += qr * qr;
+                        }
+                        if (q2 <= 1.0)
+                            acc += h;
+                    }
+                }
+                sino[((size_t)p * nv + iv) * nu + iu] = acc / (double)n_sub;
+            }
+        }
+    }
+    free(tab);
+    return OR_OK;
+}

@@ -1,0 +1,146 @@
+"""Seeded phantoms: random ellipsoids, a cylinder background and foams.
+
+Coordinates are the centred voxel units of the V frame (voxel i of an axis of
+length n has its centre at i - (n-1)/2).  Volumes are numpy arrays laid out
+[nz][ny][nx] (x fastest).  Overlapping objects add their attenuation values,
+so a line integral through a set of ellipsoids is the sum of mu times chord.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Ellipsoid:
+    centre: np.ndarray   # (3,) V frame, order (x, y, z)
+    axes: np.ndarray     # (3,) semi-axes, voxel units
+    rot: np.ndarray      # (3,3) columns are the ellipsoid's axes in V
+    mu: float
+
+    def quadric(self):
+        """Q with ||Q (X - centre)|| <= 1 exactly inside."""
+        return np.diag(1.0 / self.axes) @ self.rot.T
+
+
+def _random_rotation(rng):
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+        [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+        [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)],
+    ])
+
+
+def random_ellipsoids(n, shape, semi_range, mu_range, rng, fov_radius=None,
+                      z_half=None):
+    """``n`` ellipsoids whose bounding spheres lie inside the FOV cylinder.
+
+    ``shape`` is (nz, ny, nx).  Semi-axes ~ U(semi_range), values ~ U(mu_range),
+    orientation uniform on SO(3), centres uniform in the allowed region.
+    """
+    nz, ny, nx = shape
+    if fov_radius is None:
+        fov_radius = 0.5 * (min(nx, ny) - 1)
+    if z_half is None:
+        z_half = 0.5 * (nz - 1)
+    out = []
+    while len(out) < n:
+        axes = rng.uniform(semi_range[0], semi_range[1], size=3)
+        r = float(axes.max())
+        rmax = fov_radius - r
+        zmax = z_half - r
+        if rmax <= 0 or zmax <= 0:
+            # the largest draw does not fit: shrink it to the region
+            axes = axes * min(fov_radius, z_half) / (r * 1.05)
+            r = float(axes.max())
+            rmax = fov_radius - r
+            zmax = z_half - r
+        rho = rmax * np.sqrt(rng.uniform())
+        phi = rng.uniform(0, 2 * np.pi)
+        cz = rng.uniform(-zmax, zmax)
+        centre = np.array([rho * np.cos(phi), rho * np.sin(phi), cz])
+        out.append(Ellipsoid(centre, axes, _random_rotation(rng),
+                             float(rng.uniform(mu_range[0], mu_range[1]))))
+    return out
+
+
+def _centres(n):
+    return np.arange(n, dtype=np.float64) - 0.5 * (n - 1)
+
+
+def voxelise_ellipsoids(ells, shape, supersample=1, dtype=np.float64):
+    """Point-sample (supersample=1) or box-average (k^3 sub-points) ellipsoids."""
+    nz, ny, nx = shape
+    vol = np.zeros(shape, dtype=np.float64)
+    k = int(supersample)
+    sub = (np.arange(k) + 0.5) / k - 0.5
+    cx, cy, cz = _centres(nx), _centres(ny), _centres(nz)
+    for e in ells:
+        Q = e.quadric()
+        r = float(e.axes.max()) + 1.0
+        lo = np.floor(e.centre - r + 0.5 * (np.array([nx, ny, nz]) - 1)).astype(int)
+        hi = np.ceil(e.centre + r + 0.5 * (np.array([nx, ny, nz]) - 1)).astype(int)
+        lo = np.maximum(lo, 0)
+        hi = np.minimum(hi, [nx - 1, ny - 1, nz - 1])
+        if np.any(hi < lo):
+            continue
+        xs = cx[lo[0]:hi[0] + 1]
+        ys = cy[lo[1]:hi[1] + 1]
+        zs = cz[lo[2]:hi[2] + 1]
+        acc = np.zeros((len(zs), len(ys), len(xs)))
+        for dz in sub:
+            for dy in sub:
+                for dx in sub:
+                    Z, Y, X = np.meshgrid(zs + dz, ys + dy, xs + dx, indexing="ij")
+                    D = np.stack([X - e.centre[0], Y - e.centre[1], Z - e.centre[2]], -1)
+                    q = D @ Q.T
+                    acc += (np.einsum("...i,...i->...", q, q) <= 1.0)
+        vol[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1] += e.mu * acc / k ** 3
+    return vol.astype(dtype)
+
+
+def cylinder_background(shape, radius, height, mu, dtype=np.float64):
+    """Uniform cylinder about the z axis, point-sampled at voxel centres."""
+    nz, ny, nx = shape
+    Z, Y, X = np.meshgrid(_centres(nz), _centres(ny), _centres(nx), indexing="ij")
+    inside = (X * X + Y * Y <= radius * radius) & (np.abs(Z) <= 0.5 * height)
+    return (mu * inside).astype(dtype)
+
+
+def foam_phantom(shape, rng, radius_frac=0.4, mu=0.5, n_voids=(20, 200),
+                 void_radius_frac=(0.01, 0.08), dtype=np.float64):
+    """Cylinder (radius 0.4 N) minus random non-overlapping spherical voids."""
+    nz, ny, nx = shape
+    N = min(nx, ny)
+    R = radius_frac * N
+    H = 0.9 * nz
+    k = int(rng.integers(n_voids[0], n_voids[1] + 1))
+    voids = []
+    tries = 0
+    while len(voids) < k and tries < 20000:
+        tries += 1
+        r = rng.uniform(void_radius_frac[0], void_radius_frac[1]) * N
+        rho = (R - r) * np.sqrt(rng.uniform())
+        phi = rng.uniform(0, 2 * np.pi)
+        z = rng.uniform(-(0.5 * H - r), 0.5 * H - r)
+        c = np.array([rho * np.cos(phi), rho * np.sin(phi), z])
+        if all(np.linalg.norm(c - c2) > r + r2 for c2, r2 in voids):
+            voids.append((c, r))
+    vol = cylinder_background(shape, R, H, mu)
+    Z, Y, X = np.meshgrid(_centres(nz), _centres(ny), _centres(nx), indexing="ij")
+    for c, r in voids:
+        d2 = (X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2
+        vol[d2 <= r * r] = 0.0
+    return vol.astype(dtype)
+
+
+def fov_mask(shape, radius):
+    """Boolean cylinder mask about the z axis (used for PSNR)."""
+    nz, ny, nx = shape
+    _, Y, X = np.meshgrid(_centres(nz), _centres(ny), _centres(nx), indexing="ij")
+    return (X * X + Y * Y) <= radius * radius

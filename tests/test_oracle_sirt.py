@@ -1,0 +1,167 @@
+"""Pins of the oracle's SIRT iteration (Eq. 1) and helper terms on tiny problems.
+
+The projector is turned into an explicit matrix column by column, so the
+iteration can be checked against linear algebra that does not run it: the
+closed-form power series, the spectral bound of the normalised operator, the
+monotone weighted residual, and convergence to the exact solution.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+SHAPE = (3, 4, 4)
+N_U = N_V = 6
+
+
+def _problem(n_proj=12):
+    P = synth.circular_cone(n_proj, N_U, N_V, 20.0, 40.0, 1.2, n_sub=1)
+    nvox = int(np.prod(SHAPE))
+    A = np.zeros((n_proj * N_V * N_U, nvox))
+    for j in range(nvox):
+        e = np.zeros(nvox)
+        e[j] = 1.0
+        A[:, j] = oracle.forward(P, SHAPE, N_U, N_V, e.reshape(SHAPE)).ravel()
+    return P, A
+
+
+def _recip(v):
+    out = np.zeros_like(v)
+    out[v > 0] = 1.0 / v[v > 0]
+    return out
+
+
+def test_weights_are_inverse_row_and_column_sums():
+    P, A = _problem()
+    Rw, Cw = oracle.sirt_weights(P, SHAPE, N_U, N_V)
+    np.testing.assert_allclose(Rw.ravel(), _recip(A.sum(1)), rtol=1e-12)
+    np.testing.assert_allclose(Cw.ravel(), _recip(A.sum(0)), rtol=1e-12)
+
+
+@pytest.mark.parametrize("alpha", [1.0, 1.7])
+def test_iterates_equal_power_series(alpha):
+    """x_k = sum_{j<k} (I - a C A^T R A)^j a C A^T R b for x_0 = 0."""
+    P, A = _problem()
+    rng = np.random.default_rng(1)
+    b = rng.uniform(0, 3, A.shape[0])
+    R = np.diag(_recip(A.sum(1)))
+    C = np.diag(_recip(A.sum(0)))
+    T = np.eye(A.shape[1]) - alpha * C @ A.T @ R @ A
+    g = alpha * C @ A.T @ R @ b
+    xk = np.zeros(A.shape[1])
+    term = g.copy()
+    for k in range(1, 6):
+        xk = xk + term
+        term = T @ term
+    x5, norms = oracle.sirt(P, SHAPE, N_U, N_V, b, 5, alpha=alpha)
+    np.testing.assert_allclose(x5.ravel(), xk, rtol=1e-10, atol=1e-12)
+    # the reported norms are ||b - A x_k|| for k = 0..4
+    x = np.zeros(A.shape[1])
+    want = []
+    for k in range(5):
+        want.append(np.linalg.norm(b - A @ x))
+        x = x + g + (T - np.eye(A.shape[1])) @ x
+    np.testing.assert_allclose(norms, want, rtol=1e-10)
+
+
+def test_normalised_operator_norm_at_most_one():
+    """||R^1/2 A C^1/2||_2 <= 1 for row/column-sum normalisations."""
+    _, A = _problem()
+    r = np.sqrt(_recip(A.sum(1)))
+    c = np.sqrt(_recip(A.sum(0)))
+    s = np.linalg.norm(r[:, None] * A * c[None, :], 2)
+    assert s <= 1.0 + 1e-12
+    assert s > 0.99   # attained by the positive Perron vector
+
+
+@pytest.mark.parametrize("alpha", [0.5, 1.0, 1.9])
+def test_weighted_residual_is_non_increasing(alpha):
+    P, A = _problem()
+    rng = np.random.default_rng(2)
+    b = A @ rng.uniform(0, 1, A.shape[1]) + 0.05 * rng.normal(size=A.shape[0])
+    Rw, Cw = oracle.sirt_weights(P, SHAPE, N_U, N_V)
+    x = np.zeros(SHAPE)
+    prev = np.inf
+    for _ in range(15):
+        res = b.reshape(Rw.shape) - oracle.forward(P, SHAPE, N_U, N_V, x)
+        wr = float(np.sum(Rw * res * res))
+        assert wr <= prev * (1 + 1e-12)
+        prev = wr
+        x, _ = oracle.sirt(P, SHAPE, N_U, N_V, b, 1, alpha=alpha, x0=x, weights=(Rw, Cw))
+
+
+def test_converges_to_exact_solution_of_consistent_system():
+    """Full column rank and b = A x_true: in w = C^-1/2 (x - x_true) one step is
+    the symmetric map I - a H, H = C^1/2 A^T R A C^1/2 with spectrum in (0, 1],
+    so ||x_k - x_true||_{C^-1} <= rho^k ||x_0 - x_true||_{C^-1} with
+    rho = max |1 - a lambda|; the bound is checked every 25 iterations."""
+    P, A = _problem(n_proj=16)
+    assert np.linalg.matrix_rank(A) == A.shape[1]
+    rng = np.random.default_rng(3)
+    x_true = rng.uniform(0, 1, A.shape[1])
+    b = A @ x_true
+    alpha = 1.9
+    r = _recip(A.sum(1))
+    c = _recip(A.sum(0))
+    H = np.sqrt(c)[:, None] * (A.T @ (r[:, None] * A)) * np.sqrt(c)[None, :]
+    lam = np.linalg.eigvalsh(H)
+    assert lam.min() > 0 and lam.max() <= 1 + 1e-12
+    rho = max(abs(1 - alpha * lam.min()), abs(1 - alpha * lam.max()))
+    Rw, Cw = oracle.sirt_weights(P, SHAPE, N_U, N_V)
+    cinv = _recip(Cw.ravel())
+    x = np.zeros(SHAPE)
+    e0 = float(np.sqrt(np.sum(cinv * x_true * x_true)))
+    for j in range(1, 21):
+        x, _ = oracle.sirt(P, SHAPE, N_U, N_V, b, 25, alpha=alpha, x0=x, weights=(Rw, Cw))
+        e = x.ravel() - x_true
+        ek = float(np.sqrt(np.sum(cinv * e * e)))
+        assert ek <= rho ** (25 * j) * e0 * (1 + 1e-9) + 1e-12
+    assert ek < 0.05 * e0
+
+
+def test_nonneg_clamps_iterates():
+    P, A = _problem()
+    b = -np.ones(A.shape[0])
+    x, _ = oracle.sirt(P, SHAPE, N_U, N_V, b, 3, nonneg=True)
+    assert x.min() == 0.0
+
+
+def test_tv_closed_form_ramp():
+    nz, ny, nx = 4, 5, 6
+    a, eps = 0.3, 1e-5
+    x = np.broadcast_to(a * np.arange(nx), (nz, ny, nx)).copy()
+    want = (nx - 1) * ny * nz * np.sqrt(a * a + eps * eps) + ny * nz * eps
+    assert oracle.tv(x, eps) == pytest.approx(want, rel=1e-13)
+
+
+def test_tv_gradient_matches_central_differences():
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=(5, 6, 7))
+    eps = 1e-2
+    g = oracle.tv_grad(x, eps)
+    h = 1e-6
+    for idx in [(0, 0, 0), (4, 5, 6), (2, 3, 1), (1, 0, 6), (3, 5, 0)]:
+        xp = x.copy()
+        xm = x.copy()
+        xp[idx] += h
+        xm[idx] -= h
+        fd = (oracle.tv(xp, eps) - oracle.tv(xm, eps)) / (2 * h)
+        assert g[idx] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+def test_psnr_closed_form():
+    t = np.zeros((2, 3, 4))
+    t[0, 0, 0] = 2.0
+    x = t + 0.1
+    assert oracle.psnr(x, t) == pytest.approx(10 * np.log10(4.0 / 0.01), rel=1e-12)
+
+
+def test_poisson_log_transform_is_unbiased_at_high_dose():
+    rng = np.random.default_rng(5)
+    y = np.full(200000, 1.3)
+    b = synth.poisson_log_transform(y, 1e6, rng)
+    assert abs(b.mean() - 1.3) < 2e-4
+    # standard deviation of -ln(counts / I0) ~ 1 / sqrt(I0 exp(-y))
+    assert b.std() == pytest.approx(1 / np.sqrt(1e6 * np.exp(-1.3)), rel=0.02)
