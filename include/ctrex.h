@@ -1,0 +1,200 @@
+/*
+ * ctrex.h — C ABI of the MI355X ray-driven projector library.
+ *
+ * The library evaluates the projection–correction–backprojection loop of the
+ * CTrex paper (arxiv 2609.30166): the forward projector A (Sec. 4.1,
+ * "Projection operator"), the detector-space correction R(p - A mu)
+ * (Sec. 4.1, "Correction kernel"), the backprojector A^T with voxel
+ * normalisation C (Sec. 4.1, "Backprojection operator") and the SIRT update of
+ * Eq. (1) (Sec. 2.3.1), over per-projection 3x4 view matrices (Sec. 2.2), with
+ * optional angular sub-samples (Sec. 3.4, 4.2.2) and a displacement-field warp
+ * applied during ray traversal (Sec. 3.1, 4.2.1).
+ *
+ * Conventions (all entry points):
+ *  - Volume frame V: voxel units, centred; voxel (ix, iy, iz) has its centre at
+ *    (ix - (nx-1)/2, iy - (ny-1)/2, iz - (nz-1)/2).  Volumes are contiguous
+ *    [nz][ny][nx] arrays (x fastest).
+ *  - View matrices: float64, row-major [n_proj][n_sub][3][4]; P (X, 1)^T is
+ *    proportional to (u, v, 1)^T with (u, v) in pixel-index units (pixel
+ *    (iu, iv) centred at (iu, iv)).  Only the line through the source and the
+ *    pixel centre matters, so P may carry any non-zero scale or sign.
+ *  - Sinograms: contiguous [n_views][n_v][n_u] (u fastest); row k belongs to
+ *    projection views[k] (or k when views == NULL).
+ *  - The ray of pixel (iu, iv) is clipped to the voxel-centre hull
+ *    [0, nx-1] x [0, ny-1] x [0, nz-1] (index coordinates), sampled at the
+ *    midpoints of n = ceil(L / step) equal parts of its chord L, each sample
+ *    interpolated trilinearly and weighted by its length L / n.  Sub-views
+ *    are averaged.  A warped sample that leaves the hull contributes zero.
+ *  - Device pointers are HIP device memory owned by the caller; host pointers
+ *    are read during the call only.  `stream` is a hipStream_t (NULL = the
+ *    null stream).  Launches are asynchronous on that stream unless stated.
+ *  - Every entry point returns CTREX_OK or a negative status; the message of
+ *    the last failure on a context is returned by ctrex_last_error().
+ *    Arguments are validated on the host before anything is launched; a
+ *    failed call launches nothing.  A context is not thread-safe, and calls on
+ *    one context must be ordered (one stream, or caller synchronisation).
+ */
+#ifndef CTREX_H
+#define CTREX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define CTREX_API __attribute__((visibility("default")))
+#else
+#define CTREX_API
+#endif
+
+typedef struct ctrex_ctx ctrex_ctx;
+
+/* Status codes. */
+#define CTREX_OK 0
+#define CTREX_EINVAL (-1)         /* bad argument (NULL pointer, bad enum, ...) */
+#define CTREX_ESHAPE (-2)         /* sizes inconsistent or out of range */
+#define CTREX_ESINGULAR (-3)      /* a view matrix's 3x3 block is singular */
+#define CTREX_ESOURCE_INSIDE (-4) /* a source lies inside the volume hull */
+#define CTREX_EDEVICE (-5)        /* HIP runtime error (including earlier faults) */
+#define CTREX_EWORKSPACE (-6)     /* workspace missing or too small */
+#define CTREX_ESTATE (-7)         /* call order: no geometry set, ... */
+#define CTREX_ENONFINITE (-8)     /* a residual norm came out NaN or Inf */
+
+/* Storage types of volumes and sinograms.  Arithmetic is always FP32 with FP32
+ * accumulation; geometry (inversion, clipping) is FP64.  16-bit stores round
+ * to nearest even. */
+#define CTREX_F32 0
+#define CTREX_BF16 1
+#define CTREX_F16 2
+
+/* Flags of ctrex_sirt_iterate. */
+#define CTREX_NONNEG 1u        /* clamp the volume at zero after every update */
+#define CTREX_BF16_GATHER 2u   /* ray-march a BF16 shadow of the FP32 volume */
+#define CTREX_F16_GATHER 4u    /* ray-march an FP16 shadow of the FP32 volume */
+#define CTREX_RECOMPUTE_WEIGHTS 8u /* rebuild R and C even if cached */
+
+/* Create a context bound to HIP device `device`. */
+CTREX_API int ctrex_create(ctrex_ctx **out, int device);
+
+/* Destroy a context (NULL is accepted).  Waits for the device first. */
+CTREX_API void ctrex_destroy(ctrex_ctx *ctx);
+
+/* Message of the last failed call on `ctx` (never NULL). */
+CTREX_API const char *ctrex_last_error(const ctrex_ctx *ctx);
+
+/*
+ * Sec. 2.2 (single-projection geometry, trajectory representation): install
+ * the per-projection geometry.  `view_matrices` is a host float64 array
+ * [n_proj][n_sub][3][4].  For every sub-view the library computes, in FP64,
+ * the inverse of the left 3x3 block M and the source S = -M^-1 P[:, 3]; it
+ * rejects |det M| < 1e-12 ||M||_F^3 (CTREX_ESINGULAR) and sources inside
+ * the hull (CTREX_ESOURCE_INSIDE).  Volume sides must be >= 2 and
+ * nx*ny*nz < 2^31; step > 0 with fewer than 2^24 steps along the hull
+ * diagonal.  The table is copied to the device
+ * synchronously.  Clears any motion field and invalidates cached SIRT weights.
+ */
+CTREX_API int ctrex_set_geometry(ctrex_ctx *ctx, const double *view_matrices, int32_t n_proj,
+                       int32_t n_sub, int32_t n_u, int32_t n_v, int32_t nx, int32_t ny,
+                       int32_t nz, double step);
+
+/*
+ * Sec. 3.1 / 4.2.1 (displacement field applied during ray traversal): every
+ * sample c of sub-view (p, s) is moved to c + tau[p][s] * U(c) before the
+ * lookup, U interpolated trilinearly from a device float32 grid
+ * `U_dev` [gz][gy][gx][3] (x, y, z components, voxel units) whose nodes span
+ * the hull (node k of an axis at index coordinate k (n-1)/(g-1)); lookups
+ * clamp to the grid.  `tau` is a host float64 [n_proj][n_sub] array.  The grid
+ * is copied (repacked) by the library; U_dev may be freed after the call,
+ * which synchronises the device.  U_dev == NULL removes the warp.  Grid sides
+ * must be >= 2.  Invalidates cached SIRT weights.
+ */
+CTREX_API int ctrex_set_motion(ctrex_ctx *ctx, const float *U_dev, int32_t gx, int32_t gy, int32_t gz,
+                     const double *tau);
+
+/*
+ * Sec. 4.1 (projection operator): sino = A vol for the projections in
+ * `views` (host int32 list of n_views indices in [0, n_proj), repeats
+ * allowed; NULL selects all projections in order).  `vol` has storage type
+ * vol_dtype and `sino` sino_dtype; the sinogram is overwritten.  With an
+ * empty list (n_views == 0) nothing happens and the pointers may be NULL.
+ */
+CTREX_API int ctrex_forward_project(ctrex_ctx *ctx, const void *vol, int32_t vol_dtype, void *sino,
+                          int32_t sino_dtype, const int32_t *views, int32_t n_views,
+                          void *stream);
+
+/*
+ * Sec. 4.1 (backprojection operator), as the exact transpose of
+ * ctrex_forward_project: vol (+)= A^T sino over the listed projections.
+ * `vol` is a device float32 volume; with accumulate == 0 it is zeroed first
+ * (also for an empty view list, where `sino` may be NULL).
+ * The scatter uses float32 atomics, so the summation order (and the last bits
+ * of the result) may differ from run to run.
+ */
+CTREX_API int ctrex_back_project(ctrex_ctx *ctx, const void *sino, int32_t sino_dtype, float *vol,
+                       int32_t accumulate, const int32_t *views, int32_t n_views,
+                       void *stream);
+
+/*
+ * Bytes of device workspace ctrex_sirt_iterate needs for n_views projections
+ * (n_views <= 0 means all) and `flags` (the gather shadows need room).
+ */
+CTREX_API int ctrex_sirt_workspace_bytes(const ctrex_ctx *ctx, int32_t n_views, uint32_t flags,
+                               size_t *bytes);
+
+/*
+ * Eq. (1) with the listed projections as the subset P_k (Sec. 2.3.1, 2.3.2):
+ *   vol <- vol + alpha C A^T R (sino - A vol), repeated n_iter times,
+ * with R = 1 / (A 1) and C = 1 / (A^T 1) (zero where a sum is zero).
+ * `vol` is the device float32 volume (in/out); `sino` the measured data
+ * (device, sino_dtype, [n_views][n_v][n_u]).  `workspace` is caller-owned
+ * device memory of at least ctrex_sirt_workspace_bytes(); it holds R, C and
+ * the intermediates, and R and C are kept there between calls for the same
+ * geometry, motion, view list and workspace (CTREX_RECOMPUTE_WEIGHTS forces
+ * a rebuild; the caller must not write the workspace in between).  With a
+ * BF16/F16 gather flag the rays march a 16-bit shadow of vol, refreshed
+ * after every update, while the update itself stays FP32.  The correction
+ * image R (sino - A vol) is stored in sino_dtype.  If `resid_norms` (host,
+ * n_iter doubles) is non-NULL the call waits for the stream and stores
+ * ||sino - A vol_k||_2 of every iterate k = 0..n_iter-1 (k = 0 is the input
+ * volume) and returns CTREX_ENONFINITE if any is NaN or Inf; otherwise it
+ * returns without waiting.
+ */
+CTREX_API int ctrex_sirt_iterate(ctrex_ctx *ctx, float *vol, const void *sino, int32_t sino_dtype,
+                       int32_t n_iter, float alpha, uint32_t flags, const int32_t *views,
+                       int32_t n_views, void *workspace, size_t workspace_bytes,
+                       double *resid_norms, void *stream);
+
+/*
+ * Exact number of ray samples (trilinear lookups) one forward projection of
+ * the listed projections performs, summed over sub-views; synchronous.
+ */
+CTREX_API int ctrex_sample_count(ctrex_ctx *ctx, const int32_t *views, int32_t n_views, int64_t *count,
+                       void *stream);
+
+/*
+ * Storage conversion of n elements between CTREX_F32/BF16/F16 device arrays
+ * (round to nearest even), for callers preparing 16-bit inputs.
+ */
+CTREX_API int ctrex_convert(ctrex_ctx *ctx, const void *src, int32_t src_dtype, void *dst,
+                  int32_t dst_dtype, int64_t n, void *stream);
+
+/*
+ * Kernel timing of ctrex_sirt_iterate (instrumentation, no effect on
+ * results).  With profiling enabled, every iteration records HIP events on
+ * the launch stream around its forward-projection-with-correction, its
+ * backprojection and its update launches.  ctrex_profile_read waits for the
+ * device, returns the summed milliseconds and launch counts of the three
+ * phases (ms[3], launches[3]: forward, back, update) since the last read,
+ * and clears them.  Enabling clears earlier records.
+ */
+CTREX_API int ctrex_profile_enable(ctrex_ctx *ctx, int32_t enable);
+CTREX_API int ctrex_profile_read(ctrex_ctx *ctx, double *ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTREX_H */

@@ -1,0 +1,671 @@
+// Host runtime of libctrex: the C ABI declared in include/ctrex.h.
+//
+// Owns the per-context device geometry table (FP64 source + inverse matrix
+// per sub-view), the repacked motion grid, device copies of view lists and a
+// small counter; every other buffer is the caller's.  Validation happens
+// before any launch, so a failing call leaves the device untouched.
+
+#include "../../include/ctrex.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <algorithm>
+#include <cstring>
+#include <limits>
+#include <list>
+#include <string>
+#include <vector>
+
+#include "ctrex_internal.h"
+
+using namespace ctrex;
+
+namespace {
+
+struct DeviceViewList {
+    std::vector<int32_t> host;
+    int32_t *dev = nullptr;
+};
+
+}  // namespace
+
+struct ctrex_ctx {
+    int device = 0;
+    std::string err;
+    // geometry
+    bool have_geom = false;
+    int n_proj = 0, n_sub = 0, n_u = 0, n_v = 0, nx = 0, ny = 0, nz = 0;
+    double step = 0.0;
+    std::vector<SubView> tab;
+    SubView *d_tab = nullptr;
+    double *d_P = nullptr;    // view matrices [n_proj * n_sub][12]
+    size_t P_cap = 0;
+    uint64_t generation = 0;  // bumps on geometry or motion change
+    // motion
+    float4 *d_U = nullptr;
+    int gx = 0, gy = 0, gz = 0;
+    int warp_margin = 0;  // ceil(max |tau| * max |U component|)
+    // cached device view lists (most recent first)
+    std::list<DeviceViewList> lists;
+    // small device scratch
+    unsigned long long *d_count = nullptr;
+    // SIRT weight cache key
+    const void *w_ws = nullptr;
+    uint64_t w_gen = 0;
+    std::vector<int32_t> w_views;
+    bool w_all = false;
+    bool w_valid = false;
+    // kernel timing (ctrex_profile_enable)
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_marks;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kResidCap = 1024;
+constexpr size_t kMaxLists = 64;
+
+int fail(ctrex_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+int hip_fail(ctrex_ctx *c, hipError_t e, const char *what) {
+    return fail(c, CTREX_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define CTREX_HIP(ctx, expr)                                   \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr); \
+    } while (0)
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool valid_dtype(int32_t t) { return t == CTREX_F32 || t == CTREX_BF16 || t == CTREX_F16; }
+size_t dtype_size(int32_t t) { return t == CTREX_F32 ? 4 : 2; }
+
+// Inverse of a 3x3 matrix through cyclic cofactors; returns the determinant.
+double invert3(const double m[3][3], double inv[3][3]) {
+    double cof[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            cof[i][j] = m[i1][j1] * m[i2][j2] - m[i1][j2] * m[i2][j1];
+        }
+    const double det = m[0][0] * cof[0][0] + m[0][1] * cof[0][1] + m[0][2] * cof[0][2];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) inv[j][i] = cof[i][j] / det;
+    return det;
+}
+
+// Select (and upload once) the device copy of a view list.  NULL = all views.
+int resolve_views(ctrex_ctx *c, const int32_t *views, int32_t n_views, const int32_t **dev,
+                  int32_t *count, hipStream_t stream) {
+    if (!views) {
+        *dev = nullptr;
+        *count = c->n_proj;
+        return CTREX_OK;
+    }
+    if (n_views < 0) return fail(c, CTREX_ESHAPE, "n_views must be >= 0 (got %d)", n_views);
+    for (int32_t k = 0; k < n_views; ++k)
+        if (views[k] < 0 || views[k] >= c->n_proj)
+            return fail(c, CTREX_ESHAPE, "views[%d] = %d outside [0, %d)", k, views[k], c->n_proj);
+    *count = n_views;
+    if (n_views == 0) {
+        *dev = nullptr;
+        return CTREX_OK;
+    }
+    for (auto it = c->lists.begin(); it != c->lists.end(); ++it) {
+        if (static_cast<int32_t>(it->host.size()) == n_views &&
+            std::memcmp(it->host.data(), views, sizeof(int32_t) * n_views) == 0) {
+            c->lists.splice(c->lists.begin(), c->lists, it);
+            *dev = c->lists.front().dev;
+            return CTREX_OK;
+        }
+    }
+    DeviceViewList l;
+    l.host.assign(views, views + n_views);
+    CTREX_HIP(c, hipMalloc(&l.dev, sizeof(int32_t) * n_views));
+    hipError_t e = hipMemcpyAsync(l.dev, l.host.data(), sizeof(int32_t) * n_views,
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        (void)hipFree(l.dev);
+        return hip_fail(c, e, "upload of view list");
+    }
+    c->lists.push_front(std::move(l));
+    while (c->lists.size() > kMaxLists) {
+        // the evicted list's last use was ordered before this synchronised upload
+        (void)hipFree(c->lists.back().dev);
+        c->lists.pop_back();
+    }
+    *dev = c->lists.front().dev;
+    return CTREX_OK;
+}
+
+RayGrid make_grid(const ctrex_ctx *c, const int32_t *dev_views, int32_t n_views) {
+    RayGrid g;
+    g.tab = c->d_tab;
+    g.views = dev_views;
+    g.n_views = n_views;
+    g.n_sub = c->n_sub;
+    g.n_u = c->n_u;
+    g.n_v = c->n_v;
+    g.nx = c->nx;
+    g.ny = c->ny;
+    g.nz = c->nz;
+    g.step = c->step;
+    g.tiles_u = (c->n_u + TILE_U - 1) / TILE_U;
+    g.tiles_v = (c->n_v + TILE_V - 1) / TILE_V;
+    const long long total = static_cast<long long>(g.tiles_u) * g.tiles_v * n_views;
+    g.total_blocks = static_cast<int>(total);
+    return g;
+}
+
+WarpGrid make_warp(const ctrex_ctx *c) {
+    WarpGrid w;
+    w.U = c->d_U;
+    w.gx = c->gx;
+    w.gy = c->gy;
+    w.gz = c->gz;
+    w.sx = c->d_U ? static_cast<float>(c->gx - 1) / static_cast<float>(c->nx - 1) : 0.0f;
+    w.sy = c->d_U ? static_cast<float>(c->gy - 1) / static_cast<float>(c->ny - 1) : 0.0f;
+    w.sz = c->d_U ? static_cast<float>(c->gz - 1) / static_cast<float>(c->nz - 1) : 0.0f;
+    w.margin = c->d_U ? c->warp_margin : 0;
+    return w;
+}
+
+int check_ready(ctrex_ctx *c) {
+    if (!c) return CTREX_EINVAL;
+    if (!c->have_geom) return fail(c, CTREX_ESTATE, "no geometry set (call ctrex_set_geometry)");
+    CTREX_HIP(c, hipSetDevice(c->device));
+    return CTREX_OK;
+}
+
+int check_blocks(ctrex_ctx *c, int32_t n_views) {
+    const long long tiles = static_cast<long long>((c->n_u + TILE_U - 1) / TILE_U) *
+                            ((c->n_v + TILE_V - 1) / TILE_V);
+    if (tiles * n_views > (1ll << 30))
+        return fail(c, CTREX_ESHAPE, "too many detector tiles in one call (%lld)", tiles * n_views);
+    const long long pix = static_cast<long long>(c->n_u) * c->n_v * n_views;
+    if (pix >= (1ll << 31))
+        return fail(c, CTREX_ESHAPE, "sinogram of %lld pixels exceeds 2^31 - 1", pix);
+    return CTREX_OK;
+}
+
+hipError_t take_event(ctrex_ctx *c, hipEvent_t *e) {
+    if (!c->ev_pool.empty()) {
+        *e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
+}
+
+// Record an event pair around `phase` when profiling (start = true opens it).
+struct PhaseTimer {
+    ctrex_ctx *c;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    int phase;
+    hipError_t begin() {
+        if (!c->profiling) return hipSuccess;
+        hipError_t e = take_event(c, &a);
+        if (e != hipSuccess) return e;
+        return hipEventRecord(a, s);
+    }
+    hipError_t end() {
+        if (!c->profiling) return hipSuccess;
+        hipEvent_t b;
+        hipError_t e = take_event(c, &b);
+        if (e != hipSuccess) return e;
+        e = hipEventRecord(b, s);
+        c->ev_marks.push_back({phase, {a, b}});
+        return e;
+    }
+};
+
+struct SirtLayout {
+    size_t R, r, C, z, shadow, partials, resid, total;
+};
+
+SirtLayout sirt_layout(const ctrex_ctx *c, int32_t n_views, uint32_t flags) {
+    const size_t rays = static_cast<size_t>(n_views) * c->n_u * c->n_v;
+    const size_t vox = static_cast<size_t>(c->nx) * c->ny * c->nz;
+    const bool g16 = (flags & (CTREX_BF16_GATHER | CTREX_F16_GATHER)) != 0;
+    const size_t tiles = static_cast<size_t>((c->n_u + TILE_U - 1) / TILE_U) *
+                         ((c->n_v + TILE_V - 1) / TILE_V) * n_views;
+    SirtLayout l;
+    size_t off = 0;
+    l.R = off;
+    off = align_up(off + 4 * rays);
+    l.r = off;
+    off = align_up(off + 4 * rays);
+    l.C = off;
+    off = align_up(off + 4 * vox);
+    l.z = off;
+    off = align_up(off + 4 * vox);
+    l.shadow = off;
+    off = align_up(off + (g16 ? 2 * vox : 0));
+    l.partials = off;
+    off = align_up(off + 8 * tiles);
+    l.resid = off;
+    off = align_up(off + 8 * kResidCap);
+    l.total = off;
+    return l;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ctrex_create(ctrex_ctx **out, int device) {
+    if (!out) return CTREX_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return CTREX_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return CTREX_EDEVICE;
+    ctrex_ctx *c = new ctrex_ctx();
+    c->device = device;
+    if (hipMalloc(&c->d_count, sizeof(unsigned long long)) != hipSuccess) {
+        delete c;
+        return CTREX_EDEVICE;
+    }
+    *out = c;
+    return CTREX_OK;
+}
+
+void ctrex_destroy(ctrex_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto &m : c->ev_marks) {
+        c->ev_pool.push_back(m.second.first);
+        c->ev_pool.push_back(m.second.second);
+    }
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->d_tab) (void)hipFree(c->d_tab);
+    if (c->d_P) (void)hipFree(c->d_P);
+    if (c->d_U) (void)hipFree(c->d_U);
+    if (c->d_count) (void)hipFree(c->d_count);
+    for (auto &l : c->lists) (void)hipFree(l.dev);
+    delete c;
+}
+
+const char *ctrex_last_error(const ctrex_ctx *c) {
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+int ctrex_set_geometry(ctrex_ctx *c, const double *P, int32_t n_proj, int32_t n_sub, int32_t n_u,
+                       int32_t n_v, int32_t nx, int32_t ny, int32_t nz, double step) {
+    if (!c) return CTREX_EINVAL;
+    if (!P) return fail(c, CTREX_EINVAL, "view_matrices is NULL");
+    if (n_proj < 1 || n_sub < 1 || n_u < 1 || n_v < 1)
+        return fail(c, CTREX_ESHAPE, "n_proj, n_sub, n_u, n_v must be >= 1");
+    if (nx < 2 || ny < 2 || nz < 2) return fail(c, CTREX_ESHAPE, "volume sides must be >= 2");
+    if (static_cast<long long>(nx) * ny * nz >= (1ll << 31))
+        return fail(c, CTREX_ESHAPE, "volume of %lld voxels exceeds 2^31 - 1",
+                    static_cast<long long>(nx) * ny * nz);
+    if (static_cast<long long>(n_proj) * n_sub > (1 << 24))
+        return fail(c, CTREX_ESHAPE, "too many sub-views");
+    if (!(step > 0.0) || !std::isfinite(step)) return fail(c, CTREX_EINVAL, "step must be > 0");
+    {
+        // the longest chord (the hull diagonal) must need fewer than 2^24 samples,
+        // so sample offsets stay exact in FP32 and every ray loop is short
+        const double diag = std::sqrt(double(nx - 1) * (nx - 1) + double(ny - 1) * (ny - 1) +
+                                      double(nz - 1) * (nz - 1));
+        if (diag / step >= double(1 << 24))
+            return fail(c, CTREX_EINVAL, "step %g too small for a hull diagonal of %g", step, diag);
+    }
+    CTREX_HIP(c, hipSetDevice(c->device));
+    const size_t m = static_cast<size_t>(n_proj) * n_sub;
+    std::vector<SubView> tab(m);
+    const double half[3] = {0.5 * (nx - 1), 0.5 * (ny - 1), 0.5 * (nz - 1)};
+    for (size_t k = 0; k < m; ++k) {
+        const double *p = P + 12 * k;
+        double M[3][3], Mi[3][3];
+        double fro = 0.0;
+        bool finite = true;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                M[i][j] = p[4 * i + j];
+                fro += M[i][j] * M[i][j];
+            }
+        for (int i = 0; i < 12; ++i) finite = finite && std::isfinite(p[i]);
+        if (!finite) return fail(c, CTREX_EINVAL, "view matrix %zu is not finite", k);
+        fro = std::sqrt(fro);
+        const double det = invert3(M, Mi);
+        if (!(fro > 0.0) || !(std::fabs(det) >= 1e-12 * fro * fro * fro))
+            return fail(c, CTREX_ESINGULAR, "view matrix %zu (projection %zu, sub-view %zu) is singular",
+                        k, k / n_sub, k % n_sub);
+        SubView &sv = tab[k];
+        bool inside = true;
+        for (int i = 0; i < 3; ++i) {
+            const double s = -(Mi[i][0] * p[3] + Mi[i][1] * p[7] + Mi[i][2] * p[11]);
+            sv.S[i] = s + half[i];
+            inside = inside && sv.S[i] >= 0.0 && sv.S[i] <= 2.0 * half[i];
+            for (int j = 0; j < 3; ++j) sv.Mi[3 * i + j] = Mi[i][j];
+        }
+        if (inside)
+            return fail(c, CTREX_ESOURCE_INSIDE, "source of view matrix %zu lies inside the volume", k);
+        sv.tau = 0.0;
+        sv.pad[0] = sv.pad[1] = sv.pad[2] = 0.0;
+    }
+    // commit
+    CTREX_HIP(c, hipDeviceSynchronize());
+    if (c->d_tab && c->tab.size() < m) {
+        CTREX_HIP(c, hipFree(c->d_tab));
+        c->d_tab = nullptr;
+    }
+    if (!c->d_tab) CTREX_HIP(c, hipMalloc(&c->d_tab, sizeof(SubView) * m));
+    CTREX_HIP(c, hipMemcpy(c->d_tab, tab.data(), sizeof(SubView) * m, hipMemcpyHostToDevice));
+    if (c->d_P && c->P_cap < m) {
+        CTREX_HIP(c, hipFree(c->d_P));
+        c->d_P = nullptr;
+    }
+    if (!c->d_P) {
+        CTREX_HIP(c, hipMalloc(&c->d_P, sizeof(double) * 12 * m));
+        c->P_cap = m;
+    }
+    CTREX_HIP(c, hipMemcpy(c->d_P, P, sizeof(double) * 12 * m, hipMemcpyHostToDevice));
+    if (c->d_U) {
+        CTREX_HIP(c, hipFree(c->d_U));
+        c->d_U = nullptr;
+    }
+    c->tab = std::move(tab);
+    c->n_proj = n_proj;
+    c->n_sub = n_sub;
+    c->n_u = n_u;
+    c->n_v = n_v;
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = nz;
+    c->step = step;
+    c->have_geom = true;
+    c->generation++;
+    c->w_valid = false;
+    return CTREX_OK;
+}
+
+int ctrex_set_motion(ctrex_ctx *c, const float *U_dev, int32_t gx, int32_t gy, int32_t gz,
+                     const double *tau) {
+    int st = check_ready(c);
+    if (st != CTREX_OK) return st;
+    if (!U_dev) {
+        CTREX_HIP(c, hipDeviceSynchronize());
+        if (c->d_U) CTREX_HIP(c, hipFree(c->d_U));
+        c->d_U = nullptr;
+        for (auto &sv : c->tab) sv.tau = 0.0;
+        CTREX_HIP(c, hipMemcpy(c->d_tab, c->tab.data(), sizeof(SubView) * c->tab.size(),
+                               hipMemcpyHostToDevice));
+        c->generation++;
+        c->w_valid = false;
+        return CTREX_OK;
+    }
+    if (!tau) return fail(c, CTREX_EINVAL, "tau is NULL");
+    if (gx < 2 || gy < 2 || gz < 2) return fail(c, CTREX_ESHAPE, "grid sides must be >= 2");
+    if (static_cast<long long>(gx) * gy * gz >= (1ll << 28))
+        return fail(c, CTREX_ESHAPE, "displacement grid too large");
+    for (size_t k = 0; k < c->tab.size(); ++k)
+        if (!std::isfinite(tau[k])) return fail(c, CTREX_EINVAL, "tau[%zu] is not finite", k);
+    const size_t nodes = static_cast<size_t>(gx) * gy * gz;
+    CTREX_HIP(c, hipDeviceSynchronize());
+    if (c->d_U) {
+        CTREX_HIP(c, hipFree(c->d_U));
+        c->d_U = nullptr;
+    }
+    // bound of the displacement on every axis, for the backprojector's bricks
+    std::vector<float> hostU(3 * nodes);
+    CTREX_HIP(c, hipMemcpy(hostU.data(), U_dev, sizeof(float) * 3 * nodes, hipMemcpyDeviceToHost));
+    double umax = 0.0, tmax = 0.0;
+    for (float v : hostU) {
+        if (!std::isfinite(v)) return fail(c, CTREX_EINVAL, "displacement grid is not finite");
+        umax = std::max(umax, static_cast<double>(std::fabs(v)));
+    }
+    for (size_t k = 0; k < c->tab.size(); ++k) tmax = std::max(tmax, std::fabs(tau[k]));
+    const double bound = umax * tmax;
+    if (bound > 64.0) return fail(c, CTREX_EINVAL, "displacement bound %g exceeds 64 voxels", bound);
+    CTREX_HIP(c, hipMalloc(&c->d_U, sizeof(float4) * nodes));
+    CTREX_HIP(c, launch_repack_warp(U_dev, c->d_U, nodes, nullptr));
+    c->warp_margin = static_cast<int>(std::ceil(bound * (1.0 + 1e-6) + 1e-6));
+    for (size_t k = 0; k < c->tab.size(); ++k) c->tab[k].tau = tau[k];
+    CTREX_HIP(c, hipMemcpy(c->d_tab, c->tab.data(), sizeof(SubView) * c->tab.size(),
+                           hipMemcpyHostToDevice));
+    CTREX_HIP(c, hipDeviceSynchronize());
+    c->gx = gx;
+    c->gy = gy;
+    c->gz = gz;
+    c->generation++;
+    c->w_valid = false;
+    return CTREX_OK;
+}
+
+int ctrex_forward_project(ctrex_ctx *c, const void *vol, int32_t vol_dtype, void *sino,
+                          int32_t sino_dtype, const int32_t *views, int32_t n_views,
+                          void *stream) {
+    int st = check_ready(c);
+    if (st != CTREX_OK) return st;
+    if (!valid_dtype(vol_dtype) || !valid_dtype(sino_dtype))
+        return fail(c, CTREX_EINVAL, "unknown dtype (%d, %d)", vol_dtype, sino_dtype);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t *dv;
+    int32_t nv;
+    if ((st = resolve_views(c, views, n_views, &dv, &nv, s)) != CTREX_OK) return st;
+    if (nv == 0) return CTREX_OK;  // nothing to project (pointers may be NULL)
+    if (!vol || !sino) return fail(c, CTREX_EINVAL, "vol and sino must be device pointers");
+    if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
+    const RayGrid g = make_grid(c, dv, nv);
+    FpExtra ex{nullptr, nullptr, nullptr};
+    CTREX_HIP(c, launch_forward(g, make_warp(c), vol, vol_dtype, sino, sino_dtype, FP_PLAIN, ex, s));
+    return CTREX_OK;
+}
+
+int ctrex_back_project(ctrex_ctx *c, const void *sino, int32_t sino_dtype, float *vol,
+                       int32_t accumulate, const int32_t *views, int32_t n_views, void *stream) {
+    int st = check_ready(c);
+    if (st != CTREX_OK) return st;
+    if (!vol) return fail(c, CTREX_EINVAL, "vol must be a device pointer");
+    if (!valid_dtype(sino_dtype)) return fail(c, CTREX_EINVAL, "unknown dtype %d", sino_dtype);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t *dv;
+    int32_t nv;
+    if ((st = resolve_views(c, views, n_views, &dv, &nv, s)) != CTREX_OK) return st;
+    if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
+    if (nv > 0 && !sino) return fail(c, CTREX_EINVAL, "sino must be a device pointer");
+    if (nv == 0) {
+        if (!accumulate)
+            CTREX_HIP(c, launch_fill_zero(vol, sizeof(float) * static_cast<size_t>(c->nx) * c->ny * c->nz, s));
+        return CTREX_OK;
+    }
+    const RayGrid g = make_grid(c, dv, nv);
+    CTREX_HIP(c, launch_back(g, make_warp(c), c->d_P, sino, sino_dtype, vol, accumulate ? 1 : 0,
+                             BP_PLAIN, s));
+    return CTREX_OK;
+}
+
+int ctrex_sirt_workspace_bytes(const ctrex_ctx *c, int32_t n_views, uint32_t flags,
+                               size_t *bytes) {
+    if (!c || !bytes) return CTREX_EINVAL;
+    if (!c->have_geom) return CTREX_ESTATE;
+    if (n_views <= 0) n_views = c->n_proj;
+    *bytes = sirt_layout(c, n_views, flags).total;
+    return CTREX_OK;
+}
+
+int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_dtype,
+                       int32_t n_iter, float alpha, uint32_t flags, const int32_t *views,
+                       int32_t n_views, void *workspace, size_t workspace_bytes,
+                       double *resid_norms, void *stream) {
+    int st = check_ready(c);
+    if (st != CTREX_OK) return st;
+    if (!vol || !sino) return fail(c, CTREX_EINVAL, "vol and sino must be device pointers");
+    if (!valid_dtype(sino_dtype)) return fail(c, CTREX_EINVAL, "unknown dtype %d", sino_dtype);
+    if (n_iter < 0) return fail(c, CTREX_EINVAL, "n_iter must be >= 0");
+    if (!std::isfinite(alpha)) return fail(c, CTREX_EINVAL, "alpha must be finite");
+    const uint32_t known = CTREX_NONNEG | CTREX_BF16_GATHER | CTREX_F16_GATHER |
+                           CTREX_RECOMPUTE_WEIGHTS;
+    if (flags & ~known) return fail(c, CTREX_EINVAL, "unknown flags 0x%x", flags & ~known);
+    if ((flags & CTREX_BF16_GATHER) && (flags & CTREX_F16_GATHER))
+        return fail(c, CTREX_EINVAL, "BF16 and F16 gathers are exclusive");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t *dv;
+    int32_t nv;
+    if ((st = resolve_views(c, views, n_views, &dv, &nv, s)) != CTREX_OK) return st;
+    if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
+    if (nv == 0) return fail(c, CTREX_ESHAPE, "empty view subset");
+    const SirtLayout L = sirt_layout(c, nv, flags);
+    if (!workspace) return fail(c, CTREX_EWORKSPACE, "workspace is NULL");
+    if (workspace_bytes < L.total)
+        return fail(c, CTREX_EWORKSPACE, "workspace of %zu bytes < %zu needed", workspace_bytes,
+                    L.total);
+    if (n_iter == 0) return CTREX_OK;
+    char *ws = static_cast<char *>(workspace);
+    float *Rw = reinterpret_cast<float *>(ws + L.R);
+    void *r = ws + L.r;
+    float *Cw = reinterpret_cast<float *>(ws + L.C);
+    float *z = reinterpret_cast<float *>(ws + L.z);
+    void *shadow = ws + L.shadow;
+    double *partials = reinterpret_cast<double *>(ws + L.partials);
+    double *resid = reinterpret_cast<double *>(ws + L.resid);
+    const size_t vox = static_cast<size_t>(c->nx) * c->ny * c->nz;
+    const int gdt = (flags & CTREX_BF16_GATHER) ? BF16 : (flags & CTREX_F16_GATHER) ? F16 : F32;
+    const int rdt = sino_dtype;  // the correction image takes the data's storage type
+    const RayGrid g = make_grid(c, dv, nv);
+    const WarpGrid w = make_warp(c);
+
+    // R and C for this geometry / motion / subset / workspace, kept between calls.
+    const bool cached = c->w_valid && c->w_ws == workspace && c->w_gen == c->generation &&
+                        (views == nullptr) == c->w_all &&
+                        (views == nullptr ||
+                         (static_cast<int32_t>(c->w_views.size()) == nv &&
+                          std::memcmp(c->w_views.data(), views, sizeof(int32_t) * nv) == 0)) &&
+                        !(flags & CTREX_RECOMPUTE_WEIGHTS);
+    if (!cached) {
+        c->w_valid = false;
+        FpExtra none{nullptr, nullptr, nullptr};
+        CTREX_HIP(c, launch_forward(g, w, nullptr, F32, Rw, F32, FP_RECIP_ONES, none, s));
+        CTREX_HIP(c, launch_back(g, w, c->d_P, nullptr, F32, Cw, 0, BP_ONES, s));
+        CTREX_HIP(c, launch_recip(Cw, vox, s));
+        c->w_ws = workspace;
+        c->w_gen = c->generation;
+        c->w_all = views == nullptr;
+        c->w_views.assign(views ? views : nullptr, views ? views + nv : nullptr);
+        c->w_valid = true;
+    }
+    const void *gather = vol;
+    if (gdt != F32) {
+        CTREX_HIP(c, launch_convert(vol, F32, shadow, gdt, vox, s));
+        gather = shadow;
+    }
+    std::vector<double> host_norms;
+    if (resid_norms) host_norms.reserve(n_iter);
+    FpExtra ex{sino, Rw, partials};
+    for (int32_t k = 0; k < n_iter; ++k) {
+        PhaseTimer t_fp{c, s, nullptr, 0}, t_bp{c, s, nullptr, 1}, t_up{c, s, nullptr, 2};
+        CTREX_HIP(c, t_fp.begin());
+        CTREX_HIP(c, launch_forward(g, w, gather, gdt, r, rdt, FP_CORRECT, ex, s));
+        CTREX_HIP(c, t_fp.end());
+        CTREX_HIP(c, launch_sum_partials(partials, g.total_blocks, resid + (k % kResidCap), s));
+        CTREX_HIP(c, t_bp.begin());
+        CTREX_HIP(c, launch_back(g, w, c->d_P, r, rdt, z, 0, BP_PLAIN, s));
+        CTREX_HIP(c, t_bp.end());
+        CTREX_HIP(c, t_up.begin());
+        CTREX_HIP(c, launch_update(vol, z, Cw, alpha, (flags & CTREX_NONNEG) ? 1 : 0,
+                                   gdt != F32 ? shadow : nullptr, gdt, vox, s));
+        CTREX_HIP(c, t_up.end());
+        if (resid_norms && ((k + 1) % kResidCap == 0 || k + 1 == n_iter)) {
+            const int cnt = (k % kResidCap) + 1;
+            std::vector<double> tmp(cnt);
+            CTREX_HIP(c, hipMemcpyAsync(tmp.data(), resid, sizeof(double) * cnt,
+                                        hipMemcpyDeviceToHost, s));
+            CTREX_HIP(c, hipStreamSynchronize(s));
+            host_norms.insert(host_norms.end(), tmp.begin(), tmp.end());
+        }
+    }
+    if (resid_norms) {
+        bool finite = true;
+        for (int32_t k = 0; k < n_iter; ++k) {
+            resid_norms[k] = std::sqrt(host_norms[k]);
+            finite = finite && std::isfinite(resid_norms[k]);
+        }
+        if (!finite) return fail(c, CTREX_ENONFINITE, "a residual norm is not finite");
+    }
+    return CTREX_OK;
+}
+
+int ctrex_sample_count(ctrex_ctx *c, const int32_t *views, int32_t n_views, int64_t *count,
+                       void *stream) {
+    int st = check_ready(c);
+    if (st != CTREX_OK) return st;
+    if (!count) return fail(c, CTREX_EINVAL, "count is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t *dv;
+    int32_t nv;
+    if ((st = resolve_views(c, views, n_views, &dv, &nv, s)) != CTREX_OK) return st;
+    if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
+    CTREX_HIP(c, launch_fill_zero(c->d_count, sizeof(unsigned long long), s));
+    CTREX_HIP(c, launch_sample_count(make_grid(c, dv, nv), c->d_count, s));
+    unsigned long long h = 0;
+    CTREX_HIP(c, hipMemcpyAsync(&h, c->d_count, sizeof h, hipMemcpyDeviceToHost, s));
+    CTREX_HIP(c, hipStreamSynchronize(s));
+    *count = static_cast<int64_t>(h);
+    return CTREX_OK;
+}
+
+int ctrex_profile_enable(ctrex_ctx *c, int32_t enable) {
+    if (!c) return CTREX_EINVAL;
+    CTREX_HIP(c, hipSetDevice(c->device));
+    CTREX_HIP(c, hipDeviceSynchronize());
+    for (auto &m : c->ev_marks) {
+        c->ev_pool.push_back(m.second.first);
+        c->ev_pool.push_back(m.second.second);
+    }
+    c->ev_marks.clear();
+    c->profiling = enable != 0;
+    return CTREX_OK;
+}
+
+int ctrex_profile_read(ctrex_ctx *c, double *ms, int64_t *launches) {
+    if (!c || !ms || !launches) return CTREX_EINVAL;
+    CTREX_HIP(c, hipSetDevice(c->device));
+    for (int i = 0; i < 3; ++i) {
+        ms[i] = 0.0;
+        launches[i] = 0;
+    }
+    for (auto &m : c->ev_marks) {
+        CTREX_HIP(c, hipEventSynchronize(m.second.second));
+        float t = 0.0f;
+        CTREX_HIP(c, hipEventElapsedTime(&t, m.second.first, m.second.second));
+        ms[m.first] += t;
+        launches[m.first] += 1;
+        c->ev_pool.push_back(m.second.first);
+        c->ev_pool.push_back(m.second.second);
+    }
+    c->ev_marks.clear();
+    return CTREX_OK;
+}
+
+int ctrex_convert(ctrex_ctx *c, const void *src, int32_t src_dtype, void *dst, int32_t dst_dtype,
+                  int64_t n, void *stream) {
+    if (!c) return CTREX_EINVAL;
+    if (!src || !dst) return fail(c, CTREX_EINVAL, "src and dst must be device pointers");
+    if (!valid_dtype(src_dtype) || !valid_dtype(dst_dtype))
+        return fail(c, CTREX_EINVAL, "unknown dtype");
+    if (n < 0) return fail(c, CTREX_ESHAPE, "n must be >= 0");
+    CTREX_HIP(c, hipSetDevice(c->device));
+    CTREX_HIP(c, launch_convert(src, src_dtype, dst, dst_dtype, static_cast<size_t>(n),
+                                static_cast<hipStream_t>(stream)));
+    return CTREX_OK;
+}
+
+}  // extern "C"

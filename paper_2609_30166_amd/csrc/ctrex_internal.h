@@ -1,0 +1,94 @@
+// Internal types shared by the host runtime and the HIP kernels of libctrex.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ctrex {
+
+// Per sub-view geometry as the kernels read it (one 128-byte entry per
+// (projection, sub-view)): source in index coordinates, inverse of the 3x3
+// block of the view matrix, and the warp time fraction.  FP64 (Sec. 2.2).
+struct alignas(16) SubView {
+    double S[3];
+    double Mi[9];
+    double tau;
+    double pad[3];
+};
+static_assert(sizeof(SubView) == 128, "SubView layout");
+
+// Storage types (match CTREX_F32 / CTREX_BF16 / CTREX_F16).
+enum DType : int { F32 = 0, BF16 = 1, F16 = 2 };
+
+// 16-bit brain-float storage (top half of an IEEE float).
+struct bf16_t {
+    uint16_t bits;
+};
+
+struct RayGrid {
+    const SubView *tab;  // [n_proj * n_sub]
+    const int *views;    // device list of n_views projection indices, or nullptr
+    int n_views;
+    int n_sub;
+    int n_u, n_v;
+    int nx, ny, nz;
+    double step;
+    // detector tiling of the launch
+    int tiles_u, tiles_v;
+    int total_blocks;    // tiles_u * tiles_v * n_views
+};
+
+struct WarpGrid {
+    const float4 *U;     // repacked [gz][gy][gx] (x, y, z, 0), or nullptr
+    int gx, gy, gz;
+    float sx, sy, sz;    // index -> grid coordinate scale (g - 1) / (n - 1)
+    int margin;          // whole voxels bounding |tau * U| on every axis
+};
+
+
+// Forward-projection modes.
+enum FpMode : int {
+    FP_PLAIN = 0,     // sino = A vol
+    FP_RECIP_ONES = 1,// out = 1 / (A 1), 0 where A 1 == 0 (the SIRT weight R)
+    FP_CORRECT = 2,   // out = R (b - A vol); per-block sums of (b - A vol)^2
+};
+
+struct FpExtra {
+    const void *b;       // measured sinogram (FP_CORRECT), storage type = out type
+    const float *R;      // detector weights (FP_CORRECT)
+    double *partials;    // [total_blocks] (FP_CORRECT)
+};
+
+// Backprojection modes.
+enum BpMode : int {
+    BP_PLAIN = 0,     // vol += A^T sino
+    BP_ONES = 1,      // vol += A^T 1 (sino ignored)
+};
+
+// Launchers (defined in the .hip translation units).  All asynchronous.
+hipError_t launch_forward(const RayGrid &g, const WarpGrid &w, const void *vol, int vol_dtype,
+                          void *out, int out_dtype, int mode, const FpExtra &ex,
+                          hipStream_t stream);
+// vol (+)= A^T sino; `Pmat` holds the view matrices [n_proj * n_sub][12] on the
+// device.  accumulate == 0 overwrites vol.
+hipError_t launch_back(const RayGrid &g, const WarpGrid &w, const double *Pmat, const void *sino,
+                       int sino_dtype, float *vol, int accumulate, int mode, hipStream_t stream);
+hipError_t launch_sample_count(const RayGrid &g, unsigned long long *count, hipStream_t stream);
+hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t stream);
+hipError_t launch_recip(float *a, size_t n, hipStream_t stream);
+hipError_t launch_update(float *x, const float *z, const float *C, float alpha, int nonneg,
+                         void *shadow, int shadow_dtype, size_t n, hipStream_t stream);
+hipError_t launch_convert(const void *src, int src_dtype, void *dst, int dst_dtype, size_t n,
+                          hipStream_t stream);
+hipError_t launch_sum_partials(const double *partials, int n, double *out, hipStream_t stream);
+hipError_t launch_repack_warp(const float *U, float4 *out, size_t n_nodes, hipStream_t stream);
+
+// Detector tile processed by one workgroup of the projectors.
+constexpr int TILE_U = 16;
+constexpr int TILE_V = 16;
+constexpr int PROJ_THREADS = TILE_U * TILE_V;
+constexpr int N_XCD = 8;
+
+}  // namespace ctrex

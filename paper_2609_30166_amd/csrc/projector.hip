@@ -1,0 +1,184 @@
+// Ray-driven forward projector and its exact-transpose backprojector (gfx950).
+//
+// One workgroup owns a 16x16 detector tile of one projection; each lane owns
+// one pixel ray.  The four wave64s of a workgroup take 8x8 quadrants so that
+// the 64 rays of a wave sample a compact patch of the volume at every step.
+// Workgroup ids are swizzled so that each XCD walks a contiguous run of
+// (tile, projection) pairs: consecutive projections of one tile revisit almost
+// the same voxels, which then stay in that XCD's L2.
+//
+// Per ray (Sec. 4.1, projection operator; Sec. 2.2 geometry):
+//   FP64: direction M^-1 (u, v, 1), slab clip to the voxel-centre hull,
+//         n = ceil(L / step), h = L / n, chord midpoint;
+//   FP32: samples c_i = mid + (i - (n-1)/2) h d, optional warp
+//         c_i' = c_i + tau U(c_i) (Sec. 3.1, 4.2.1), trilinear lookups,
+//         FP32 accumulation; sub-views averaged (Sec. 3.4, 4.2.2).
+// The backprojector walks the same samples and scatters h r / n_sub times
+// the trilinear weights with float atomics, so it is the transpose of the
+// forward operator sample by sample.
+
+#include "ray_common.h"
+
+namespace ctrex {
+namespace {
+
+using namespace dev;
+
+// ------------------------------------------------------- forward kernel ----
+template <typename TV, typename TS, int MODE, bool WARP>
+__global__ __launch_bounds__(PROJ_THREADS) void fp_kernel(RayGrid g, WarpGrid w,
+                                                          const TV *__restrict__ vol,
+                                                          TS *__restrict__ out, FpExtra ex) {
+    const TileCoord t = tile_coord(g);
+    if (!t.valid) return;  // uniform over the block
+    const VolDims d = vol_dims(g);
+    const bool active = t.iu < g.n_u && t.iv < g.n_v;
+    float y = 0.0f;
+    if (active) {
+        for (int s = 0; s < g.n_sub; ++s) {
+            const SubView &sv = g.tab[t.p * g.n_sub + s];
+            Ray r;
+            if (!setup_ray(sv, static_cast<double>(t.iu), static_cast<double>(t.iv), g.nx, g.ny,
+                           g.nz, g.step, r))
+                continue;
+            const float tau = static_cast<float>(sv.tau);
+            float acc0 = 0.0f, acc1 = 0.0f;
+            int i = 0;
+            for (; i + 1 < r.n; i += 2) {
+                const float k0 = r.k0 + static_cast<float>(i);
+                const float k1 = k0 + 1.0f;
+                float ax = fmaf(k0, r.hx, r.mx), ay = fmaf(k0, r.hy, r.my), az = fmaf(k0, r.hz, r.mz);
+                float bx = fmaf(k1, r.hx, r.mx), by = fmaf(k1, r.hy, r.my), bz = fmaf(k1, r.hz, r.mz);
+                bool ina = true, inb = true;
+                if (WARP) {
+                    ina = warp(w, d, tau, ax, ay, az);
+                    inb = warp(w, d, tau, bx, by, bz);
+                }
+                if (MODE == FP_RECIP_ONES) {
+                    acc0 += ina ? 1.0f : 0.0f;
+                    acc1 += inb ? 1.0f : 0.0f;
+                } else {
+                    const float va = gather(vol, d, corner_of(d, ax, ay, az));
+                    const float vb = gather(vol, d, corner_of(d, bx, by, bz));
+                    acc0 += ina ? va : 0.0f;
+                    acc1 += inb ? vb : 0.0f;
+                }
+            }
+            if (i < r.n) {
+                const float k0 = r.k0 + static_cast<float>(i);
+                float ax = fmaf(k0, r.hx, r.mx), ay = fmaf(k0, r.hy, r.my), az = fmaf(k0, r.hz, r.mz);
+                bool ina = true;
+                if (WARP) ina = warp(w, d, tau, ax, ay, az);
+                if (MODE == FP_RECIP_ONES) {
+                    acc0 += ina ? 1.0f : 0.0f;
+                } else {
+                    const float va = gather(vol, d, corner_of(d, ax, ay, az));
+                    acc0 += ina ? va : 0.0f;
+                }
+            }
+            y = fmaf(r.h, acc0 + acc1, y);
+        }
+        y /= static_cast<float>(g.n_sub);
+    }
+    const int pix = (t.k * g.n_v + t.iv) * g.n_u + t.iu;
+    if (MODE == FP_PLAIN) {
+        if (active) st(out, pix, y);
+    } else if (MODE == FP_RECIP_ONES) {
+        if (active) st(out, pix, y > 0.0f ? 1.0f / y : 0.0f);
+    } else {
+        double e2 = 0.0;
+        if (active) {
+            const float bval = ld(static_cast<const TS *>(ex.b), pix);
+            const float res = bval - y;
+            e2 = static_cast<double>(res) * static_cast<double>(res);
+            st(out, pix, ex.R[pix] * res);
+        }
+        block_sum_store(e2, ex.partials + t.lidx);
+    }
+}
+
+// ------------------------------------------------------ sample counting ----
+__global__ __launch_bounds__(PROJ_THREADS) void count_kernel(RayGrid g,
+                                                             unsigned long long *count) {
+    const TileCoord t = tile_coord(g);
+    if (!t.valid) return;
+    unsigned long long n = 0;
+    if (t.iu < g.n_u && t.iv < g.n_v) {
+        for (int s = 0; s < g.n_sub; ++s) {
+            Ray r;
+            if (setup_ray(g.tab[t.p * g.n_sub + s], static_cast<double>(t.iu),
+                          static_cast<double>(t.iv), g.nx, g.ny, g.nz, g.step, r))
+                n += static_cast<unsigned long long>(r.n);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(count, n);
+}
+
+inline dim3 proj_grid(const RayGrid &g) {
+    const int per = (g.total_blocks + N_XCD - 1) / N_XCD;
+    return dim3(static_cast<unsigned>(per * N_XCD));
+}
+
+template <typename TV, typename TS>
+hipError_t fp_dispatch_mode(const RayGrid &g, const WarpGrid &w, const void *vol, void *out,
+                            int mode, const FpExtra &ex, hipStream_t s) {
+    const dim3 grid = proj_grid(g), block(PROJ_THREADS);
+    const TV *v = static_cast<const TV *>(vol);
+    TS *o = static_cast<TS *>(out);
+    const bool wp = w.U != nullptr;
+#define CTREX_FP(M, W) hipLaunchKernelGGL((fp_kernel<TV, TS, M, W>), grid, block, 0, s, g, w, v, o, ex)
+    if (mode == FP_PLAIN) {
+        if (wp) CTREX_FP(FP_PLAIN, true); else CTREX_FP(FP_PLAIN, false);
+    } else if (mode == FP_CORRECT) {
+        if (wp) CTREX_FP(FP_CORRECT, true); else CTREX_FP(FP_CORRECT, false);
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef CTREX_FP
+    return hipGetLastError();
+}
+
+template <typename TV>
+hipError_t fp_dispatch_out(const RayGrid &g, const WarpGrid &w, const void *vol, void *out,
+                           int out_dtype, int mode, const FpExtra &ex, hipStream_t s) {
+    switch (out_dtype) {
+        case F32: return fp_dispatch_mode<TV, float>(g, w, vol, out, mode, ex, s);
+        case BF16: return fp_dispatch_mode<TV, bf16_t>(g, w, vol, out, mode, ex, s);
+        case F16: return fp_dispatch_mode<TV, _Float16>(g, w, vol, out, mode, ex, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_forward(const RayGrid &g, const WarpGrid &w, const void *vol, int vol_dtype,
+                          void *out, int out_dtype, int mode, const FpExtra &ex,
+                          hipStream_t stream) {
+    if (g.total_blocks <= 0) return hipSuccess;
+    if (mode == FP_RECIP_ONES) {
+        const dim3 grid = proj_grid(g), block(PROJ_THREADS);
+        float *o = static_cast<float *>(out);
+        if (w.U)
+            hipLaunchKernelGGL((fp_kernel<float, float, FP_RECIP_ONES, true>), grid, block, 0,
+                               stream, g, w, nullptr, o, ex);
+        else
+            hipLaunchKernelGGL((fp_kernel<float, float, FP_RECIP_ONES, false>), grid, block, 0,
+                               stream, g, w, nullptr, o, ex);
+        return hipGetLastError();
+    }
+    switch (vol_dtype) {
+        case F32: return fp_dispatch_out<float>(g, w, vol, out, out_dtype, mode, ex, stream);
+        case BF16: return fp_dispatch_out<bf16_t>(g, w, vol, out, out_dtype, mode, ex, stream);
+        case F16: return fp_dispatch_out<_Float16>(g, w, vol, out, out_dtype, mode, ex, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sample_count(const RayGrid &g, unsigned long long *count, hipStream_t stream) {
+    if (g.total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(count_kernel, proj_grid(g), dim3(PROJ_THREADS), 0, stream, g, count);
+    return hipGetLastError();
+}
+
+}  // namespace ctrex

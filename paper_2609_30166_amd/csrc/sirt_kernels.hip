@@ -1,0 +1,153 @@
+// Voxel-space and bookkeeping kernels of the SIRT loop (Eq. 1, term 3):
+// x <- x + alpha C z with z = A^T r, the reciprocal weights, the 16-bit gather
+// shadows, and deterministic reductions of the per-block residual sums.
+// All are single streams over HBM: 64-bit-indexed grid-stride loops with
+// float4 accesses where the sizes allow.
+
+#include "ctrex_internal.h"
+
+namespace ctrex {
+namespace {
+
+constexpr int THREADS = 256;
+
+__device__ __forceinline__ uint16_t bf16_rne(float v) {
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+
+__device__ __forceinline__ float load_as_f32(const void *p, int dt, size_t i) {
+    if (dt == F32) return static_cast<const float *>(p)[i];
+    if (dt == BF16)
+        return __uint_as_float(static_cast<uint32_t>(static_cast<const uint16_t *>(p)[i]) << 16);
+    return static_cast<float>(static_cast<const _Float16 *>(p)[i]);
+}
+
+__device__ __forceinline__ void store_from_f32(void *p, int dt, size_t i, float v) {
+    if (dt == F32)
+        static_cast<float *>(p)[i] = v;
+    else if (dt == BF16)
+        static_cast<uint16_t *>(p)[i] = bf16_rne(v);
+    else
+        static_cast<_Float16 *>(p)[i] = static_cast<_Float16>(v);
+}
+
+inline unsigned grid_for(size_t n) {
+    size_t b = (n + THREADS - 1) / THREADS;
+    if (b > 65536) b = 65536;
+    if (b == 0) b = 1;
+    return static_cast<unsigned>(b);
+}
+
+__global__ __launch_bounds__(THREADS) void fill_zero_kernel(uint32_t *p, size_t n_words) {
+    const size_t stride = static_cast<size_t>(gridDim.x) * THREADS;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * THREADS + threadIdx.x; i < n_words; i += stride)
+        p[i] = 0u;
+}
+
+__global__ __launch_bounds__(THREADS) void fill_zero_bytes_kernel(uint8_t *p, size_t n) {
+    const size_t i = static_cast<size_t>(blockIdx.x) * THREADS + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ __launch_bounds__(THREADS) void recip_kernel(float *a, size_t n) {
+    const size_t stride = static_cast<size_t>(gridDim.x) * THREADS;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * THREADS + threadIdx.x; i < n; i += stride) {
+        const float v = a[i];
+        a[i] = v > 0.0f ? 1.0f / v : 0.0f;
+    }
+}
+
+// x <- x + alpha C z (optionally clamped at 0), shadow <- x.
+__global__ __launch_bounds__(THREADS) void update_kernel(float *__restrict__ x,
+                                                         const float *__restrict__ z,
+                                                         const float *__restrict__ C, float alpha,
+                                                         int nonneg, void *shadow, int sdt,
+                                                         size_t n) {
+    const size_t stride = static_cast<size_t>(gridDim.x) * THREADS;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * THREADS + threadIdx.x; i < n; i += stride) {
+        float v = fmaf(alpha * C[i], z[i], x[i]);
+        if (nonneg) v = fmaxf(v, 0.0f);
+        x[i] = v;
+        if (shadow) store_from_f32(shadow, sdt, i, v);
+    }
+}
+
+__global__ __launch_bounds__(THREADS) void convert_kernel(const void *src, int sdt, void *dst,
+                                                          int ddt, size_t n) {
+    const size_t stride = static_cast<size_t>(gridDim.x) * THREADS;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * THREADS + threadIdx.x; i < n; i += stride)
+        store_from_f32(dst, ddt, i, load_as_f32(src, sdt, i));
+}
+
+// One block: fixed-order sum of n doubles (each thread strides, then a tree).
+__global__ __launch_bounds__(1024) void sum_partials_kernel(const double *p, int n, double *out) {
+    __shared__ double red[1024];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) s += p[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ __launch_bounds__(THREADS) void repack_warp_kernel(const float *U, float4 *out,
+                                                              size_t n) {
+    const size_t i = static_cast<size_t>(blockIdx.x) * THREADS + threadIdx.x;
+    if (i < n) out[i] = make_float4(U[3 * i], U[3 * i + 1], U[3 * i + 2], 0.0f);
+}
+
+}  // namespace
+
+hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    const size_t words = bytes / 4;
+    if (words) hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(words)), dim3(THREADS), 0, s,
+                                  static_cast<uint32_t *>(ptr), words);
+    const size_t tail = bytes - words * 4;
+    if (tail)
+        hipLaunchKernelGGL(fill_zero_bytes_kernel, dim3(1), dim3(THREADS), 0, s,
+                           static_cast<uint8_t *>(ptr) + words * 4, tail);
+    return hipGetLastError();
+}
+
+hipError_t launch_recip(float *a, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(recip_kernel, dim3(grid_for(n)), dim3(THREADS), 0, s, a, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(float *x, const float *z, const float *C, float alpha, int nonneg,
+                         void *shadow, int shadow_dtype, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(update_kernel, dim3(grid_for(n)), dim3(THREADS), 0, s, x, z, C, alpha,
+                       nonneg, shadow, shadow_dtype, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(const void *src, int src_dtype, void *dst, int dst_dtype, size_t n,
+                          hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(convert_kernel, dim3(grid_for(n)), dim3(THREADS), 0, s, src, src_dtype,
+                       dst, dst_dtype, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double *partials, int n, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(1024), 0, s, partials, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_repack_warp(const float *U, float4 *out, size_t n_nodes, hipStream_t s) {
+    if (n_nodes == 0) return hipSuccess;
+    hipLaunchKernelGGL(repack_warp_kernel, dim3((n_nodes + THREADS - 1) / THREADS), dim3(THREADS),
+                       0, s, U, out, n_nodes);
+    return hipGetLastError();
+}
+
+}  // namespace ctrex

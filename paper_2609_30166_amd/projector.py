@@ -1,0 +1,241 @@
+"""Python binding of the projector library: argument marshalling only.
+
+Every computation runs in libctrex's HIP kernels; torch tensors supply device
+memory and the current HIP stream.  Layouts: volumes [nz][ny][nx], sinograms
+[n_views][n_v][n_u], view matrices [n_proj][n_sub][3][4] float64 (see
+include/ctrex.h for the conventions).
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+_DT = {torch.float32: _lib.F32, torch.bfloat16: _lib.BF16, torch.float16: _lib.F16}
+_GATHER_FLAG = {torch.float32: 0, torch.bfloat16: _lib.BF16_GATHER,
+                torch.float16: _lib.F16_GATHER}
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _views_arg(views):
+    if views is None:
+        return None, 0, None
+    arr = np.ascontiguousarray(np.asarray(views, dtype=np.int32).ravel())
+    return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(arr.size), arr
+
+
+class Geometry:
+    """A projector context: per-projection view matrices, detector and volume.
+
+    ``P``: [n_proj][n_sub][3][4] (or [n_proj][3][4]) float64 view matrices;
+    ``shape``: (nz, ny, nx); ``step``: ray-march step in voxels.
+    ``U``/``tau``: optional displacement grid [gz][gy][gx][3] and time
+    fractions [n_proj][n_sub] of the warp applied during ray traversal.
+    """
+
+    def __init__(self, P, n_u, n_v, shape, step=0.5, device=None, U=None, tau=None):
+        P = np.ascontiguousarray(P, dtype=np.float64)
+        if P.ndim == 3:
+            P = P[:, None]
+        if P.ndim != 4 or P.shape[2:] != (3, 4):
+            raise ValueError("view matrices must be [n_proj][n_sub][3][4]")
+        self.P = P
+        self.n_proj, self.n_sub = P.shape[:2]
+        self.n_u, self.n_v = int(n_u), int(n_v)
+        self.shape = tuple(int(s) for s in shape)
+        self.step = float(step)
+        dev = torch.device(device if device is not None else "cuda")
+        if dev.type != "cuda":
+            raise ValueError("the projector runs on a HIP device")
+        self.device = torch.device("cuda", dev.index if dev.index is not None
+                                   else torch.cuda.current_device())
+        self._ctx = ctypes.c_void_p()
+        L = _lib.lib()
+        code = L.ctrex_create(ctypes.byref(self._ctx), self.device.index)
+        if code != _lib.OK:
+            raise _lib.CtrexError(code, "ctrex_create failed on %s" % self.device)
+        nz, ny, nx = self.shape
+        check(self._ctx, L.ctrex_set_geometry(
+            self._ctx, P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.n_proj,
+            self.n_sub, self.n_u, self.n_v, nx, ny, nz, self.step))
+        self._U = None
+        self._ws = {}
+        if U is not None:
+            self.set_motion(U, tau)
+
+    # ------------------------------------------------------------ lifecycle
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            _lib.lib().ctrex_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- helpers
+    def _check_tensor(self, t, shape, dtypes, name):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch tensor" % name)
+        if t.device != self.device:
+            raise ValueError("%s is on %s, the projector on %s" % (name, t.device, self.device))
+        if t.dtype not in dtypes:
+            raise TypeError("%s has dtype %s (allowed: %s)" % (name, t.dtype, dtypes))
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+
+    def n_views(self, views):
+        return self.n_proj if views is None else int(np.asarray(views).size)
+
+    def sino_shape(self, views=None):
+        return (self.n_views(views), self.n_v, self.n_u)
+
+    # ------------------------------------------------------------- geometry
+    def set_motion(self, U, tau):
+        """Install (or with U=None remove) the displacement-field warp."""
+        L = _lib.lib()
+        if U is None:
+            check(self._ctx, L.ctrex_set_motion(self._ctx, None, 0, 0, 0, None))
+            self._U = None
+            return
+        U = torch.as_tensor(U, dtype=torch.float32, device=self.device).contiguous()
+        if U.ndim != 4 or U.shape[3] != 3:
+            raise ValueError("U must be [gz][gy][gx][3]")
+        tau = np.ascontiguousarray(tau, dtype=np.float64).reshape(self.n_proj, self.n_sub)
+        gz, gy, gx = U.shape[:3]
+        check(self._ctx, L.ctrex_set_motion(self._ctx, ctypes.c_void_p(U.data_ptr()), gx, gy, gz,
+                                            tau.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        self._U = U
+
+    # ------------------------------------------------------------ operators
+    def forward(self, vol, views=None, out=None, out_dtype=torch.float32):
+        """sino = A vol (Sec. 4.1 projection operator)."""
+        self._check_tensor(vol, self.shape, _DT, "vol")
+        shape = self.sino_shape(views)
+        if out is None:
+            out = torch.empty(shape, dtype=out_dtype, device=self.device)
+        self._check_tensor(out, shape, _DT, "out")
+        vp, nv, _keep = _views_arg(views)
+        check(self._ctx, _lib.lib().ctrex_forward_project(
+            self._ctx, ctypes.c_void_p(vol.data_ptr()), _DT[vol.dtype],
+            ctypes.c_void_p(out.data_ptr()), _DT[out.dtype], vp, nv, _stream(self.device)))
+        return out
+
+    def back(self, sino, views=None, out=None, accumulate=False):
+        """vol (+)= A^T sino, the exact transpose of ``forward``."""
+        self._check_tensor(sino, self.sino_shape(views), _DT, "sino")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+            accumulate = False
+        self._check_tensor(out, self.shape, (torch.float32,), "out")
+        vp, nv, _keep = _views_arg(views)
+        check(self._ctx, _lib.lib().ctrex_back_project(
+            self._ctx, ctypes.c_void_p(sino.data_ptr()), _DT[sino.dtype],
+            ctypes.c_void_p(out.data_ptr()), 1 if accumulate else 0, vp, nv,
+            _stream(self.device)))
+        return out
+
+    def workspace_bytes(self, views=None, gather_dtype=torch.float32):
+        n = ctypes.c_size_t(0)
+        nv = 0 if views is None else self.n_views(views)
+        check(self._ctx, _lib.lib().ctrex_sirt_workspace_bytes(
+            self._ctx, nv, _GATHER_FLAG[gather_dtype], ctypes.byref(n)))
+        return int(n.value)
+
+    def workspace(self, views=None, gather_dtype=torch.float32):
+        """A caller-owned workspace buffer for ``sirt`` (uint8 tensor)."""
+        return torch.empty(self.workspace_bytes(views, gather_dtype), dtype=torch.uint8,
+                           device=self.device)
+
+    def sirt(self, vol, sino, n_iter, alpha=1.0, nonneg=False, gather_dtype=torch.float32,
+             views=None, workspace=None, norms=True, recompute_weights=False):
+        """Eq. (1): ``n_iter`` SIRT updates of ``vol`` (float32, in place).
+
+        Returns the residual norms ||sino - A vol_k|| (numpy) when ``norms``,
+        else None (and the call does not wait for the device).
+        """
+        self._check_tensor(vol, self.shape, (torch.float32,), "vol")
+        self._check_tensor(sino, self.sino_shape(views), _DT, "sino")
+        flags = _GATHER_FLAG[gather_dtype]
+        if nonneg:
+            flags |= _lib.NONNEG
+        if recompute_weights:
+            flags |= _lib.RECOMPUTE_WEIGHTS
+        if workspace is None:
+            key = (None if views is None else tuple(np.asarray(views).ravel().tolist()),
+                   gather_dtype)
+            workspace = self._ws.get(key)
+            if workspace is None:
+                workspace = self.workspace(views, gather_dtype)
+                self._ws = {key: workspace}
+        vp, nv, _keep = _views_arg(views)
+        out = np.zeros(max(int(n_iter), 0), dtype=np.float64) if norms else None
+        check(self._ctx, _lib.lib().ctrex_sirt_iterate(
+            self._ctx, ctypes.c_void_p(vol.data_ptr()), ctypes.c_void_p(sino.data_ptr()),
+            _DT[sino.dtype], int(n_iter), float(alpha), flags, vp, nv,
+            ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if norms else None,
+            _stream(self.device)))
+        return out
+
+    def sample_count(self, views=None):
+        """Exact number of trilinear samples of one forward projection."""
+        cnt = ctypes.c_int64(0)
+        vp, nv, _keep = _views_arg(views)
+        check(self._ctx, _lib.lib().ctrex_sample_count(self._ctx, vp, nv, ctypes.byref(cnt),
+                                                       _stream(self.device)))
+        return int(cnt.value)
+
+    def profile(self, enable=True):
+        """Start (or stop) recording kernel times inside ``sirt``."""
+        check(self._ctx, _lib.lib().ctrex_profile_enable(self._ctx, 1 if enable else 0))
+
+    def profile_read(self):
+        """{phase: (total_ms, launches)} for 'forward', 'back', 'update' since the
+        last read (waits for the device)."""
+        ms = (ctypes.c_double * 3)()
+        n = (ctypes.c_int64 * 3)()
+        check(self._ctx, _lib.lib().ctrex_profile_read(self._ctx, ms, n))
+        return {k: (ms[i], n[i]) for i, k in enumerate(("forward", "back", "update"))}
+
+    def convert(self, src, dtype):
+        """Storage conversion (round to nearest even) through the library."""
+        out = torch.empty(src.shape, dtype=dtype, device=self.device)
+        check(self._ctx, _lib.lib().ctrex_convert(
+            self._ctx, ctypes.c_void_p(src.data_ptr()), _DT[src.dtype],
+            ctypes.c_void_p(out.data_ptr()), _DT[dtype], src.numel(), _stream(self.device)))
+        return out
+
+
+class ForwardProject(torch.autograd.Function):
+    """y = A x with the exact-transpose backprojector as its backward."""
+
+    @staticmethod
+    def forward(ctx, vol, geom, views=None):
+        ctx.geom = geom
+        ctx.views = views
+        return geom.forward(vol.contiguous(), views)
+
+    @staticmethod
+    def backward(ctx, grad_y):
+        grad_x = None
+        if ctx.needs_input_grad[0]:
+            grad_x = ctx.geom.back(grad_y.contiguous().to(torch.float32), ctx.views)
+        return grad_x, None, None
+
+
+def project(vol, geom, views=None):
+    """Differentiable forward projection (autograd tape through the HIP pair)."""
+    return ForwardProject.apply(vol, geom, views)

@@ -107,9 +107,13 @@ def voxelise_ellipsoids(ells, shape, supersample=1, dtype=np.float64):
 def cylinder_background(shape, radius, height, mu, dtype=np.float64):
     """Uniform cylinder about the z axis, point-sampled at voxel centres."""
     nz, ny, nx = shape
-    Z, Y, X = np.meshgrid(_centres(nz), _centres(ny), _centres(nx), indexing="ij")
-    inside = (X * X + Y * Y <= radius * radius) & (np.abs(Z) <= 0.5 * height)
-    return (mu * inside).astype(dtype)
+    z = _centres(nz)
+    y = _centres(ny)[:, None]
+    x = _centres(nx)[None, :]
+    disc = (x * x + y * y <= radius * radius)
+    out = np.zeros(shape, dtype=dtype)
+    out[np.abs(z) <= 0.5 * height] = mu * disc
+    return out
 
 
 def foam_phantom(shape, rng, radius_frac=0.4, mu=0.5, n_voids=(20, 200),
@@ -132,15 +136,22 @@ def foam_phantom(shape, rng, radius_frac=0.4, mu=0.5, n_voids=(20, 200),
         if all(np.linalg.norm(c - c2) > r + r2 for c2, r2 in voids):
             voids.append((c, r))
     vol = cylinder_background(shape, R, H, mu)
-    Z, Y, X = np.meshgrid(_centres(nz), _centres(ny), _centres(nx), indexing="ij")
+    cz, cy, cx = _centres(nz), _centres(ny), _centres(nx)
     for c, r in voids:
+        # clear the void inside its bounding box only
+        lo = [max(int(np.floor(c[a] - r + 0.5 * (n - 1))), 0) for a, n in enumerate((nx, ny, nz))]
+        hi = [min(int(np.ceil(c[a] + r + 0.5 * (n - 1))), n - 1) for a, n in enumerate((nx, ny, nz))]
+        Z, Y, X = np.meshgrid(cz[lo[2]:hi[2] + 1], cy[lo[1]:hi[1] + 1], cx[lo[0]:hi[0] + 1],
+                              indexing="ij")
         d2 = (X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2
-        vol[d2 <= r * r] = 0.0
+        sub = vol[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1]
+        sub[d2 <= r * r] = 0.0
     return vol.astype(dtype)
 
 
 def fov_mask(shape, radius):
     """Boolean cylinder mask about the z axis (used for PSNR)."""
     nz, ny, nx = shape
-    _, Y, X = np.meshgrid(_centres(nz), _centres(ny), _centres(nx), indexing="ij")
-    return (X * X + Y * Y) <= radius * radius
+    y = _centres(ny)[:, None]
+    x = _centres(nx)[None, :]
+    return np.broadcast_to((x * x + y * y) <= radius * radius, shape)

@@ -1,0 +1,275 @@
+"""HIP path vs the CPU FP64 oracle through the C ABI (needs an MI355X).
+
+Bar: FP32 results within relative L2 1e-5 of the FP64 oracle on the same
+seeded inputs; integer results (sample counts) exact; error statuses exact.
+"""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth.configs import make_config, make_phantom
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def tiny(dev):
+    from paper_2609_30166_amd import Geometry
+
+    cfg = make_config("tiny")
+    x, _ = make_phantom(cfg, seed=0)
+    g = Geometry(cfg.P, cfg.n_u, cfg.n_v, cfg.shape, cfg.step, device=dev)
+    y_ref, n_ref = oracle.forward(cfg.P, cfg.shape, cfg.n_u, cfg.n_v, x.astype(np.float64),
+                                  cfg.step, return_count=True)
+    return cfg, x, g, y_ref, n_ref
+
+
+def test_forward_tiny_matches_oracle(tiny, dev):
+    cfg, x, g, y_ref, _ = tiny
+    y = g.forward(torch.from_numpy(x).to(dev)).cpu().numpy()
+    assert rel_l2(y, y_ref) <= TOL
+
+
+def test_sample_count_is_exact(tiny):
+    cfg, x, g, _, n_ref = tiny
+    assert g.sample_count() == n_ref
+    assert g.sample_count(views=[3, 7]) == oracle.forward(
+        cfg.P, cfg.shape, cfg.n_u, cfg.n_v, np.zeros(cfg.shape), cfg.step, views=[3, 7],
+        return_count=True)[1]
+
+
+def test_back_tiny_matches_oracle(tiny, dev):
+    cfg, x, g, y_ref, _ = tiny
+    rng = np.random.default_rng(1)
+    s = (y_ref + rng.normal(0, 0.5, y_ref.shape)).astype(np.float32)
+    z = g.back(torch.from_numpy(s).to(dev)).cpu().numpy()
+    z_ref = oracle.back(cfg.P, cfg.shape, cfg.n_u, cfg.n_v, s.astype(np.float64), cfg.step)
+    assert rel_l2(z, z_ref) <= TOL
+
+
+def test_back_accumulates(tiny, dev):
+    cfg, x, g, y_ref, _ = tiny
+    s = torch.from_numpy(y_ref.astype(np.float32)).to(dev)
+    z1 = g.back(s)
+    z2 = torch.ones_like(z1)
+    g.back(s, out=z2, accumulate=True)
+    np.testing.assert_allclose(z2.cpu().numpy(), z1.cpu().numpy() + 1.0, rtol=TOL, atol=1e-5)
+
+
+def test_sirt_five_iterations_match_oracle(tiny, dev):
+    cfg, x, g, y_ref, _ = tiny
+    b = y_ref.astype(np.float32)
+    v = torch.zeros(cfg.shape, dtype=torch.float32, device=dev)
+    norms = g.sirt(v, torch.from_numpy(b).to(dev), 5)
+    v_ref, n_ref = oracle.sirt(cfg.P, cfg.shape, cfg.n_u, cfg.n_v, b.astype(np.float64), 5,
+                               step=cfg.step)
+    assert rel_l2(v.cpu().numpy(), v_ref) <= TOL
+    np.testing.assert_allclose(norms, n_ref, rtol=TOL)
+    # a second call continues from the iterate, reusing the cached weights
+    norms2 = g.sirt(v, torch.from_numpy(b).to(dev), 2)
+    v_ref2, n_ref2 = oracle.sirt(cfg.P, cfg.shape, cfg.n_u, cfg.n_v, b.astype(np.float64), 2,
+                                 step=cfg.step, x0=v_ref)
+    assert rel_l2(v.cpu().numpy(), v_ref2) <= TOL
+    np.testing.assert_allclose(norms2, n_ref2, rtol=TOL)
+
+
+def test_adjoint_dot_product_on_gpu(tiny, dev):
+    cfg, x, g, _, _ = tiny
+    rng = np.random.default_rng(2)
+    xr = torch.from_numpy(rng.normal(size=cfg.shape).astype(np.float32)).to(dev)
+    yr = torch.from_numpy(rng.normal(size=(cfg.n_proj, cfg.n_v, cfg.n_u)).astype(np.float32)).to(dev)
+    Ax = g.forward(xr).double()
+    lhs = float((Ax * yr.double()).sum())
+    rhs = float((xr.double() * g.back(yr).double()).sum())
+    # random signs cancel in the sums, so normalise by ||A x|| ||y|| (Cauchy-Schwarz)
+    scale = float(Ax.norm() * yr.double().norm())
+    assert abs(lhs - rhs) <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("n_u,n_v,shape", [(37, 23, (21, 26, 30)), (16, 16, (2, 2, 2)),
+                                           (1, 1, (9, 9, 9)), (70, 9, (40, 12, 17))])
+def test_ragged_tiles_and_odd_volumes(dev, n_u, n_v, shape):
+    from paper_2609_30166_amd import Geometry
+
+    P = synth.circular_cone(7, n_u, n_v, 60.0, 110.0, 0.9, arc=4.0, det_offset_u=1.3)
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0, 1, shape).astype(np.float32)
+    g = Geometry(P, n_u, n_v, shape, 0.5, device=dev)
+    y = g.forward(torch.from_numpy(x).to(dev)).cpu().numpy()
+    y_ref = oracle.forward(P, shape, n_u, n_v, x.astype(np.float64))
+    assert rel_l2(y, y_ref) <= TOL
+    s = rng.normal(size=y_ref.shape).astype(np.float32)
+    z = g.back(torch.from_numpy(s).to(dev)).cpu().numpy()
+    z_ref = oracle.back(P, shape, n_u, n_v, s.astype(np.float64))
+    assert rel_l2(z, z_ref) <= TOL
+
+
+def test_view_subsets_with_repeats_and_empty(tiny, dev):
+    cfg, x, g, y_ref, _ = tiny
+    views = [59, 0, 17, 17, 30]
+    xt = torch.from_numpy(x).to(dev)
+    y = g.forward(xt, views=views).cpu().numpy()
+    assert rel_l2(y, y_ref[views]) <= TOL
+    empty = g.forward(xt, views=[])
+    assert empty.shape == (0, cfg.n_v, cfg.n_u)
+    z = g.back(torch.zeros((0, cfg.n_v, cfg.n_u), device=dev), views=[])
+    assert float(z.abs().max()) == 0.0
+    s = y_ref[views].astype(np.float32)
+    zb = g.back(torch.from_numpy(s).to(dev), views=views).cpu().numpy()
+    z_ref = oracle.back(cfg.P, cfg.shape, cfg.n_u, cfg.n_v, s.astype(np.float64), views=views)
+    assert rel_l2(zb, z_ref) <= TOL
+
+
+def _helical_small(warp):
+    shape = (24, 28, 32)
+    n_u, n_v = 48, 20
+    rng = np.random.default_rng(4)
+    P = synth.helical_cone(10, n_u, n_v, 90.0, 180.0, 1.5, 3.0, 6.0, n_sub=4)
+    P = synth.rigid_jitter(P, 0.5, 0.2, rng)
+    U = tau = None
+    if warp:
+        U = synth.smooth_displacement(6, 2.5, rng)
+        tau = synth.exposure_time_fractions(10, 4)
+    return shape, n_u, n_v, P, U, tau
+
+
+@pytest.mark.parametrize("warp", [False, True])
+def test_subviews_and_warp_match_oracle(dev, warp):
+    from paper_2609_30166_amd import Geometry
+
+    shape, n_u, n_v, P, U, tau = _helical_small(warp)
+    rng = np.random.default_rng(5)
+    ells = synth.random_ellipsoids(5, shape, (3.0, 8.0), (0.1, 1.0), rng, fov_radius=10.0)
+    x = synth.voxelise_ellipsoids(ells, shape).astype(np.float32)
+    g = Geometry(P, n_u, n_v, shape, 0.5, device=dev, U=U, tau=tau)
+    y = g.forward(torch.from_numpy(x).to(dev)).cpu().numpy()
+    y_ref, cnt = oracle.forward(P, shape, n_u, n_v, x.astype(np.float64), U=U, tau=tau,
+                                return_count=True)
+    assert rel_l2(y, y_ref) <= TOL
+    assert g.sample_count() == cnt
+    s = (y_ref + rng.normal(0, 0.2, y_ref.shape)).astype(np.float32)
+    z = g.back(torch.from_numpy(s).to(dev)).cpu().numpy()
+    z_ref = oracle.back(P, shape, n_u, n_v, s.astype(np.float64), U=U, tau=tau)
+    assert rel_l2(z, z_ref) <= TOL
+    v = torch.zeros(shape, dtype=torch.float32, device=dev)
+    norms = g.sirt(v, torch.from_numpy(y_ref.astype(np.float32)).to(dev), 3)
+    v_ref, n_ref = oracle.sirt(P, shape, n_u, n_v, y_ref, 3, U=U, tau=tau)
+    assert rel_l2(v.cpu().numpy(), v_ref) <= TOL
+    np.testing.assert_allclose(norms, n_ref, rtol=TOL)
+    if warp:
+        g.set_motion(None, None)
+        y0 = g.forward(torch.from_numpy(x).to(dev)).cpu().numpy()
+        assert rel_l2(y0, oracle.forward(P, shape, n_u, n_v, x.astype(np.float64))) <= TOL
+
+
+@pytest.mark.parametrize("dtype,bound", [("bfloat16", 8e-3), ("float16", 1e-3)])
+def test_16bit_storage_error_against_fp64(tiny, dev, dtype, bound):
+    """Storage precision extension: 16-bit volume and sinogram, FP32 arithmetic.
+    The error against FP64 is dominated by the output rounding (2^-9 for BF16,
+    2^-12 for FP16 relative, per value)."""
+    cfg, x, g, y_ref, _ = tiny
+    dt = getattr(torch, dtype)
+    x16 = torch.from_numpy(x).to(dev).to(dt)
+    y16 = g.forward(x16, out_dtype=dt).float().cpu().numpy()
+    err = rel_l2(y16, y_ref)
+    assert err <= bound
+    # the 16-bit gather itself (FP32 output) equals FP64 projection of the rounded volume
+    y32 = g.forward(x16).cpu().numpy()
+    xr = x16.float().cpu().numpy().astype(np.float64)
+    assert rel_l2(y32, oracle.forward(cfg.P, cfg.shape, cfg.n_u, cfg.n_v, xr, cfg.step)) <= TOL
+    # SIRT with the 16-bit shadow converges like FP32 within the storage error
+    b = torch.from_numpy(y_ref.astype(np.float32)).to(dev).to(dt)
+    v = torch.zeros(cfg.shape, dtype=torch.float32, device=dev)
+    n16 = g.sirt(v, b, 5, gather_dtype=dt)
+    v_ref, n_ref = oracle.sirt(cfg.P, cfg.shape, cfg.n_u, cfg.n_v,
+                               b.float().cpu().numpy().astype(np.float64), 5, step=cfg.step)
+    assert rel_l2(v.cpu().numpy(), v_ref) <= 4 * bound
+    assert n16[-1] < n16[0]
+
+
+def test_conversion_rounds_to_nearest_even(tiny, dev):
+    cfg, x, g, _, _ = tiny
+    vals = torch.tensor([1.0, 1.00390625, 1.01171875, -3.3, 65504.0, 1e-8, 0.0],
+                        dtype=torch.float32, device=dev)
+    for dt in (torch.bfloat16, torch.float16):
+        got = g.convert(vals, dt)
+        assert torch.equal(got.cpu(), vals.cpu().to(dt))
+
+
+def test_autograd_gradient_is_exact_transpose(tiny, dev):
+    from paper_2609_30166_amd import project
+
+    cfg, x, g, y_ref, _ = tiny
+    rng = np.random.default_rng(6)
+    b = torch.from_numpy((y_ref * 0.9).astype(np.float32)).to(dev)
+    xt = torch.from_numpy(x * 1.1).to(dev).requires_grad_(True)
+    loss = ((project(xt, g) - b) ** 2).sum()
+    loss.backward()
+    res = oracle.forward(cfg.P, cfg.shape, cfg.n_u, cfg.n_v, x.astype(np.float64) * 1.1) - \
+        y_ref * 0.9
+    want = 2 * oracle.back(cfg.P, cfg.shape, cfg.n_u, cfg.n_v, res)
+    assert rel_l2(xt.grad.cpu().numpy(), want) <= 1e-4
+    del rng
+
+
+def test_error_statuses(dev):
+    from paper_2609_30166_amd import Geometry, CtrexError
+    from paper_2609_30166_amd._lib import lib
+
+    shape = (8, 8, 8)
+    P = synth.circular_cone(4, 8, 8, 30.0, 60.0, 1.0)
+    bad = P.copy()
+    bad[2, 0, :, :3] = 0
+    with pytest.raises(CtrexError) as e:
+        Geometry(bad, 8, 8, shape, device=dev)
+    assert e.value.code == -3
+    inside = synth.view_matrix([0.5, 0, 0], [-30, 0, 0], [0, 1, 0], [0, 0, 1], 1, 1, 8, 8)
+    with pytest.raises(CtrexError) as e:
+        Geometry(inside[None, None], 8, 8, shape, device=dev)
+    assert e.value.code == -4
+    with pytest.raises(CtrexError) as e:
+        Geometry(P, 8, 8, (1, 8, 8), device=dev)
+    assert e.value.code == -2
+    g = Geometry(P, 8, 8, shape, device=dev)
+    x = torch.zeros(shape, device=dev)
+    with pytest.raises(CtrexError) as e:
+        g.forward(x, views=[0, 4])
+    assert e.value.code == -2
+    ws = torch.empty(16, dtype=torch.uint8, device=dev)
+    with pytest.raises(CtrexError) as e:
+        g.sirt(x, torch.zeros(g.sino_shape(), device=dev), 1, workspace=ws)
+    assert e.value.code == -6
+    # a context without geometry
+    L = lib()
+    ctx = ctypes.c_void_p()
+    assert L.ctrex_create(ctypes.byref(ctx), 0) == 0
+    cnt = ctypes.c_int64()
+    assert L.ctrex_sample_count(ctx, None, 0, ctypes.byref(cnt), None) == -7
+    assert b"geometry" in L.ctrex_last_error(ctx)
+    L.ctrex_destroy(ctx)
+    # non-finite residuals are reported
+    b = torch.full(g.sino_shape(), float("nan"), device=dev)
+    with pytest.raises(CtrexError) as e:
+        g.sirt(x, b, 1)
+    assert e.value.code == -8
