@@ -9,10 +9,12 @@
 //
 // Scattering every sample to HBM would cost eight L2 float atomics per
 // sample.  Here a workgroup owns a brick of the volume (up to 32x15x16
-// voxels) held in LDS for a whole chunk of projections, accumulated in FP64:
-// on gfx950 the LDS FP64 atomic add sustains about twelve times the lane
-// rate of the FP32 one, and the wider accumulator removes the FP32
-// summation error of long sums.  For every
+// voxels) held in LDS for a whole chunk of projections, accumulated as 64-bit
+// fixed point with LDS integer atomics: on gfx950 these sustain about twenty
+// times the lane rate of LDS FP32 atomic adds, the sums are exact (so the
+// result does not depend on the order of the atomics), and a scale bounded
+// from max|r| keeps the rounding of each contribution near 2^-50 of the
+// largest possible sum.  For every
 // (projection, sub-view) it bounds the detector pixels whose rays can reach
 // the brick (the projection of the brick grown by one voxel and the warp
 // bound), redoes those rays' FP64 set-up, clips their sample range to the
@@ -40,6 +42,8 @@ struct BrickGrid {
     int views_per_chunk;
     int total;            // nbx * nby * nbz * chunks
     int accumulate;       // add into vol (else overwrite; needs chunks == 1)
+    double cube_samples;  // max samples of one ray inside a side-2 cube
+    float *partials;      // [chunks][nx*ny*nz] per-chunk results when chunks > 1
 };
 
 // Project the 8 corners of an index-space box through the view matrix and
@@ -76,13 +80,25 @@ __device__ __forceinline__ bool project_box(const double *P, const double lo[3],
     return true;
 }
 
+// Round c * scale to the nearest integer (|c * scale| < 2^51) as a
+// two's-complement 64-bit value: adding 1.5 * 2^52 leaves the rounded integer
+// in the low mantissa bits of the double.
+__device__ __forceinline__ unsigned long long to_fixed(float c, double scale) {
+    const double magic = 6755399441055744.0;
+    const double t = fma(static_cast<double>(c), scale, magic);
+    return static_cast<unsigned long long>(__double_as_longlong(t) -
+                                           __double_as_longlong(magic));
+}
+
 template <typename TS, int MODE, bool WARP>
 __global__ __launch_bounds__(BP_THREADS) void bp_brick_kernel(RayGrid g, WarpGrid w,
                                                               const double *__restrict__ Pmat,
                                                               const TS *__restrict__ sino,
+                                                              const float *__restrict__ rmax,
                                                               float *__restrict__ vol,
                                                               BrickGrid bg) {
-    extern __shared__ double acc[];
+    extern __shared__ unsigned long long acc[];
+    __shared__ double red[BP_THREADS / 64];
     // ---- block -> (brick, projection chunk); XCD-aware so that one XCD
     // works on neighbouring bricks
     const int per = (bg.total + N_XCD - 1) / N_XCD;
@@ -98,8 +114,7 @@ __global__ __launch_bounds__(BP_THREADS) void bp_brick_kernel(RayGrid g, WarpGri
     const int ex = min(bg.bx, g.nx - x0), ey = min(bg.by, g.ny - y0), ez = min(bg.bz, g.nz - z0);
     const int sy = bg.sy, sz = bg.sz;
     const int nlds = sz * ez;
-    for (int i = threadIdx.x; i < nlds; i += BP_THREADS) acc[i] = 0.0;
-    __syncthreads();
+    for (int i = threadIdx.x; i < nlds; i += BP_THREADS) acc[i] = 0ull;
 
     const VolDims d = vol_dims(g);
     const float M = static_cast<float>(w.margin);
@@ -112,8 +127,39 @@ __global__ __launch_bounds__(BP_THREADS) void bp_brick_kernel(RayGrid g, WarpGri
     const float inv_sub = 1.0f / static_cast<float>(g.n_sub);
     const int k_first = chunk * bg.views_per_chunk;
     const int k_end = min(k_first + bg.views_per_chunk, g.n_views);
+    const int n_pairs = (k_end - k_first) * g.n_sub;
 
-    for (int k = k_first; k < k_end; ++k) {
+    // ---- fixed-point scale.  Every contribution to a voxel comes from a
+    // sample of a ray in some pair's pixel box lying in the voxel's corner
+    // cube (side 2); a ray has at most bg.cube_samples samples there and each
+    // contribution is at most step * max|r| / n_sub.  The bound on the sum
+    // picks the scale so that the 64-bit sums never reach 2^51.
+    double nrays = 0.0;
+    for (int q = threadIdx.x; q < n_pairs; q += BP_THREADS) {
+        const int k = k_first + q / g.n_sub;
+        const int p = g.views ? g.views[k] : k;
+        const int sv_idx = p * g.n_sub + q % g.n_sub;
+        int u0, u1, v0, v1;
+        if (project_box(Pmat + 12 * static_cast<size_t>(sv_idx), lod, hid, off, g.n_u, g.n_v, u0,
+                        u1, v0, v1))
+            nrays += (u0 <= u1 && v0 <= v1) ? double(u1 - u0 + 1) * double(v1 - v0 + 1) : 0.0;
+        else
+            nrays += double(g.n_u) * double(g.n_v);
+    }
+    for (int o = 32; o > 0; o >>= 1) nrays += __shfl_xor(nrays, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrays;
+    __syncthreads();
+    nrays = 0.0;
+    for (int i = 0; i < BP_THREADS / 64; ++i) nrays += red[i];
+    const double cmax = ((MODE == BP_ONES) ? 1.0 : static_cast<double>(*rmax)) * g.step *
+                        (1.0 + 1e-5) / g.n_sub;
+    const double bound = nrays * bg.cube_samples * cmax;
+    const bool bad = !(cmax < __builtin_inf());   // NaN or Inf in the input: propagate NaN
+    const bool any = bound > 0.0 && !bad;
+    const int kexp = any ? static_cast<int>(floor(50.0 - log2(bound))) : 0;
+    const double scale = ldexp(1.0, kexp);
+
+    for (int k = k_first; k < k_end && any; ++k) {
         const int p = g.views ? g.views[k] : k;
         for (int s = 0; s < g.n_sub; ++s) {
             const int sv_idx = p * g.n_sub + s;
@@ -127,8 +173,8 @@ __global__ __launch_bounds__(BP_THREADS) void bp_brick_kernel(RayGrid g, WarpGri
                 v1 = g.n_v - 1;
             }
             if (u0 > u1 || v0 > v1) continue;
-            // rays in 8x8 pixel blocks: one block per wave and pass, so the 64
-            // samples of an LDS atomic spread over rows and columns of the brick
+            // rays in 8x8 pixel blocks, one block per wave and pass; the wave
+            // then shares the blocks' samples evenly among its lanes
             const int bu = (u1 - u0 + 8) >> 3;
             const int nblk = bu * ((v1 - v0 + 8) >> 3);
             const float tau = static_cast<float>(sv.tau);
@@ -136,67 +182,137 @@ __global__ __launch_bounds__(BP_THREADS) void bp_brick_kernel(RayGrid g, WarpGri
             for (int blk = threadIdx.x >> 6; blk < nblk; blk += BP_THREADS / 64) {
                 const int iv = v0 + (blk / bu) * 8 + (lane >> 3);
                 const int iu = u0 + (blk % bu) * 8 + (lane & 7);
-                if (iu > u1 || iv > v1) continue;
-                const float rv = (MODE == BP_ONES) ? 1.0f
-                                                   : ld(sino, (k * g.n_v + iv) * g.n_u + iu);
-                if (rv == 0.0f) continue;
+                // ---- this lane's ray: its samples that can reach the brick
+                int len = 0;
+                float bk = 0.0f, wgt = 0.0f;
                 Ray r;
-                if (!setup_ray(sv, static_cast<double>(iu), static_cast<double>(iv), g.nx, g.ny,
-                               g.nz, g.step, r))
-                    continue;
-                // sample offsets k with mid + k h inside [lo, hi] on every axis
-                float kmin = r.k0, kmax = r.k0 + static_cast<float>(r.n - 1);
-                const float mv[3] = {r.mx, r.my, r.mz};
-                const float hv[3] = {r.hx, r.hy, r.hz};
-                bool hit = true;
+                r.mx = r.my = r.mz = r.hx = r.hy = r.hz = 0.0f;
+                const float rv = (iu > u1 || iv > v1) ? 0.0f
+                                 : (MODE == BP_ONES) ? 1.0f
+                                                     : ld(sino, (k * g.n_v + iv) * g.n_u + iu);
+                if (rv != 0.0f && setup_ray(sv, static_cast<double>(iu), static_cast<double>(iv),
+                                            g.nx, g.ny, g.nz, g.step, r)) {
+                    // sample offsets k with mid + k h inside [lo, hi] on every axis
+                    float kmin = r.k0, kmax = r.k0 + static_cast<float>(r.n - 1);
+                    const float mv[3] = {r.mx, r.my, r.mz};
+                    const float hv[3] = {r.hx, r.hy, r.hz};
+                    bool hit = true;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    if (hv[a] != 0.0f) {
-                        const float inv = 1.0f / hv[a];
-                        const float t1 = (lo[a] - mv[a]) * inv, t2 = (hi[a] - mv[a]) * inv;
-                        kmin = fmaxf(kmin, fminf(t1, t2) - 1.0f);
-                        kmax = fminf(kmax, fmaxf(t1, t2) + 1.0f);
-                    } else if (mv[a] < lo[a] || mv[a] > hi[a]) {
-                        hit = false;
+                    for (int a = 0; a < 3; ++a) {
+                        if (hv[a] != 0.0f) {
+                            const float inv = 1.0f / hv[a];
+                            const float t1 = (lo[a] - mv[a]) * inv, t2 = (hi[a] - mv[a]) * inv;
+                            kmin = fmaxf(kmin, fminf(t1, t2) - 1.0f);
+                            kmax = fminf(kmax, fmaxf(t1, t2) + 1.0f);
+                        } else if (mv[a] < lo[a] || mv[a] > hi[a]) {
+                            hit = false;
+                        }
+                    }
+                    if (hit && kmin <= kmax) {
+                        const int i0 = max(static_cast<int>(ceilf(kmin - r.k0)), 0);
+                        const int i1 = min(static_cast<int>(floorf(kmax - r.k0)), r.n - 1);
+                        len = max(i1 - i0 + 1, 0);
+                        bk = r.k0 + static_cast<float>(i0);
+                        wgt = r.h * rv * inv_sub;
                     }
                 }
-                if (!hit || kmin > kmax) continue;
-                const int i0 = max(static_cast<int>(ceilf(kmin - r.k0)), 0);
-                const int i1 = min(static_cast<int>(floorf(kmax - r.k0)), r.n - 1);
-                const float wgt = r.h * rv * inv_sub;
-                for (int i = i0; i <= i1; ++i) {
-                    const float kk = r.k0 + static_cast<float>(i);
-                    float cx = fmaf(kk, r.hx, r.mx), cy = fmaf(kk, r.hy, r.my),
-                          cz = fmaf(kk, r.hz, r.mz);
+                // ---- exclusive prefix of the segment lengths over the wave
+                int incl = len;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int t = __shfl_up(incl, o, 64);
+                    if (lane >= o) incl += t;
+                }
+                const int S = incl - len;
+                const int T = __shfl(incl, 63, 64);
+                if (T == 0) continue;   // uniform over the wave
+                const unsigned long long live = __ballot(len > 0);
+                // ---- lane takes samples [start, end) of the wave's T
+                const int start = (T * lane) >> 6, end = (T * (lane + 1)) >> 6;
+                int j = 0;   // last ray with S_j <= start: it owns sample `start`
+#pragma unroll
+                for (int st = 32; st > 0; st >>= 1) {
+                    const int t = j + st;
+                    if (__shfl(S, t, 64) <= start) j = t;
+                }
+                float cmx = __shfl(r.mx, j, 64), cmy = __shfl(r.my, j, 64), cmz = __shfl(r.mz, j, 64);
+                float chx = __shfl(r.hx, j, 64), chy = __shfl(r.hy, j, 64), chz = __shfl(r.hz, j, 64);
+                float cw = __shfl(wgt, j, 64);
+                float ck = __shfl(bk, j, 64) - static_cast<float>(__shfl(S, j, 64));
+                int cend = __shfl(incl, j, 64);
+                const int trips = (T + 63) >> 6;
+                int pos = start;
+                for (int it = 0; it < trips; ++it) {
+                    // wave-uniform hand-over to the next ray with samples
+                    const bool need = pos < end && pos == cend;
+                    if (__any(need)) {
+                        const unsigned long long rest =
+                            j < 63 ? (live & (~0ull << (j + 1))) : 0ull;
+                        const int jn = need && rest ? __ffsll(static_cast<long long>(rest)) - 1 : j;
+                        const float nmx = __shfl(r.mx, jn, 64), nmy = __shfl(r.my, jn, 64),
+                                    nmz = __shfl(r.mz, jn, 64), nhx = __shfl(r.hx, jn, 64),
+                                    nhy = __shfl(r.hy, jn, 64), nhz = __shfl(r.hz, jn, 64),
+                                    nw = __shfl(wgt, jn, 64);
+                        const float nk = __shfl(bk, jn, 64) - static_cast<float>(__shfl(S, jn, 64));
+                        const int ne = __shfl(incl, jn, 64);
+                        if (need) {
+                            j = jn;
+                            cmx = nmx; cmy = nmy; cmz = nmz;
+                            chx = nhx; chy = nhy; chz = nhz;
+                            cw = nw; ck = nk; cend = ne;
+                        }
+                    }
+                    if (pos >= end) continue;
+                    const float kk = ck + static_cast<float>(pos);
+                    ++pos;
+                    float cx = fmaf(kk, chx, cmx), cy = fmaf(kk, chy, cmy), cz = fmaf(kk, chz, cmz);
                     if (WARP && !warp(w, d, tau, cx, cy, cz)) continue;
                     int ix, iy, iz;
                     float fx, fy, fz;
                     corner_idx(d, cx, cy, cz, ix, iy, iz, fx, fy, fz);
                     const int lx = ix - x0, ly = iy - y0, lz = iz - z0;
+                    const float gx1 = fx, gx0 = 1.0f - fx;
+                    const float gy1 = fy, gy0 = 1.0f - fy;
+                    const float gz1 = fz * cw, gz0 = (1.0f - fz) * cw;
+                    const float w00 = gz0 * gy0, w01 = gz0 * gy1, w10 = gz1 * gy0, w11 = gz1 * gy1;
+                    if (lx >= 0 && lx + 1 < ex && ly >= 0 && ly + 1 < ey && lz >= 0 &&
+                        lz + 1 < ez) {
+                        // all eight corners inside the brick
+                        unsigned long long *ap = acc + (lz * sz + ly * sy + lx);
+                        atomicAdd(ap, to_fixed(w00 * gx0, scale));
+                        atomicAdd(ap + 1, to_fixed(w00 * gx1, scale));
+                        atomicAdd(ap + sy, to_fixed(w01 * gx0, scale));
+                        atomicAdd(ap + sy + 1, to_fixed(w01 * gx1, scale));
+                        atomicAdd(ap + sz, to_fixed(w10 * gx0, scale));
+                        atomicAdd(ap + sz + 1, to_fixed(w10 * gx1, scale));
+                        atomicAdd(ap + sz + sy, to_fixed(w11 * gx0, scale));
+                        atomicAdd(ap + sz + sy + 1, to_fixed(w11 * gx1, scale));
+                        continue;
+                    }
                     const bool x_0 = lx >= 0 && lx < ex, x_1 = lx + 1 >= 0 && lx + 1 < ex;
                     const bool y_0 = ly >= 0 && ly < ey, y_1 = ly + 1 >= 0 && ly + 1 < ey;
                     const bool z_0 = lz >= 0 && lz < ez, z_1 = lz + 1 >= 0 && lz + 1 < ez;
                     if (!((x_0 || x_1) && (y_0 || y_1) && (z_0 || z_1))) continue;
-                    const float gx1 = fx, gx0 = 1.0f - fx;
-                    const float gy1 = fy, gy0 = 1.0f - fy;
-                    const float gz1 = fz * wgt, gz0 = (1.0f - fz) * wgt;
-                    const float w00 = gz0 * gy0, w01 = gz0 * gy1, w10 = gz1 * gy0, w11 = gz1 * gy1;
                     const int base = lz * sz + ly * sy + lx;   // may be outside: guarded
-                    double *ap = acc + base;
-                    if (z_0 && y_0 && x_0) atomicAdd(ap, static_cast<double>(w00 * gx0));
-                    if (z_0 && y_0 && x_1) atomicAdd(ap + 1, static_cast<double>(w00 * gx1));
-                    if (z_0 && y_1 && x_0) atomicAdd(ap + sy, static_cast<double>(w01 * gx0));
-                    if (z_0 && y_1 && x_1) atomicAdd(ap + sy + 1, static_cast<double>(w01 * gx1));
-                    if (z_1 && y_0 && x_0) atomicAdd(ap + sz, static_cast<double>(w10 * gx0));
-                    if (z_1 && y_0 && x_1) atomicAdd(ap + sz + 1, static_cast<double>(w10 * gx1));
-                    if (z_1 && y_1 && x_0) atomicAdd(ap + sz + sy, static_cast<double>(w11 * gx0));
-                    if (z_1 && y_1 && x_1) atomicAdd(ap + sz + sy + 1, static_cast<double>(w11 * gx1));
+                    if (z_0 && y_0 && x_0) atomicAdd(acc + base, to_fixed(w00 * gx0, scale));
+                    if (z_0 && y_0 && x_1) atomicAdd(acc + base + 1, to_fixed(w00 * gx1, scale));
+                    if (z_0 && y_1 && x_0) atomicAdd(acc + base + sy, to_fixed(w01 * gx0, scale));
+                    if (z_0 && y_1 && x_1)
+                        atomicAdd(acc + base + sy + 1, to_fixed(w01 * gx1, scale));
+                    if (z_1 && y_0 && x_0) atomicAdd(acc + base + sz, to_fixed(w10 * gx0, scale));
+                    if (z_1 && y_0 && x_1)
+                        atomicAdd(acc + base + sz + 1, to_fixed(w10 * gx1, scale));
+                    if (z_1 && y_1 && x_0)
+                        atomicAdd(acc + base + sz + sy, to_fixed(w11 * gx0, scale));
+                    if (z_1 && y_1 && x_1)
+                        atomicAdd(acc + base + sz + sy + 1, to_fixed(w11 * gx1, scale));
                 }
             }
         }
     }
     __syncthreads();
     // ---- write the brick out (x fastest)
+    const double inv_scale = ldexp(1.0, -kexp);
     const int nvox = ex * ey * ez;
     for (int i = threadIdx.x; i < nvox; i += BP_THREADS) {
         const int lz = i / (ex * ey);
@@ -204,9 +320,11 @@ __global__ __launch_bounds__(BP_THREADS) void bp_brick_kernel(RayGrid g, WarpGri
         const int ly = rem / ex;
         const int lx = rem - ly * ex;
         float *dst = vol + (static_cast<size_t>(z0 + lz) * g.ny + (y0 + ly)) * g.nx + (x0 + lx);
-        const float v = static_cast<float>(acc[lz * sz + ly * sy + lx]);
+        const long long q = static_cast<long long>(acc[lz * sz + ly * sy + lx]);
+        const float v = bad ? __builtin_nanf("") : static_cast<float>(static_cast<double>(q) * inv_scale);
         if (bg.chunks > 1) {
-            if (v != 0.0f) unsafeAtomicAdd(dst, v);
+            // each chunk owns a slab; a fixed-order sum combines them
+            bg.partials[static_cast<size_t>(chunk) * g.nx * g.ny * g.nz + (dst - vol)] = v;
         } else if (bg.accumulate) {
             *dst += v;
         } else {
@@ -215,16 +333,24 @@ __global__ __launch_bounds__(BP_THREADS) void bp_brick_kernel(RayGrid g, WarpGri
     }
 }
 
-}  // namespace
+// vol[i] (+)= sum over chunks c of part[c][i], in chunk order.
+__global__ __launch_bounds__(256) void sum_chunks_kernel(const float *__restrict__ part, int chunks,
+                                                         size_t n, int accumulate,
+                                                         float *__restrict__ vol) {
+    const size_t stride = static_cast<size_t>(gridDim.x) * 256;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) {
+        float s = accumulate ? vol[i] : 0.0f;
+        for (int c = 0; c < chunks; ++c) s += part[static_cast<size_t>(c) * n + i];
+        vol[i] = s;
+    }
+}
 
-hipError_t launch_back(const RayGrid &g, const WarpGrid &w, const double *Pmat, const void *sino,
-                       int sino_dtype, float *vol, int accumulate, int mode, hipStream_t stream) {
-    if (g.n_views <= 0) return hipSuccess;
+BrickGrid plan_bricks(const RayGrid &g) {
     BrickGrid bg;
     bg.bx = min(32, g.nx);
     bg.by = min(15, g.ny);
     bg.bz = min(16, g.nz);
-    // FP64 cells span two 4-byte banks: odd row stride and a plane stride of
+    // 64-bit cells span two 4-byte banks: odd row stride and a plane stride of
     // 3 (mod 16) put neighbours along y, z and the diagonals in other banks
     bg.sy = bg.bx | 1;
     bg.sz = bg.sy * bg.by + ((3 - (bg.sy * bg.by) % 16) + 16) % 16;
@@ -240,36 +366,67 @@ hipError_t launch_back(const RayGrid &g, const WarpGrid &w, const double *Pmat, 
     bg.views_per_chunk = static_cast<int>((g.n_views + want - 1) / want);
     bg.chunks = (g.n_views + bg.views_per_chunk - 1) / bg.views_per_chunk;
     bg.total = static_cast<int>(bricks * bg.chunks);
+    // h >= step / 2 whenever a ray has two samples, and a side-2 cube holds a
+    // chord of at most 2 sqrt(3)
+    bg.cube_samples = floor(4.0 * 1.7320508075688772 / g.step) + 1.0;
+    bg.partials = nullptr;
+    bg.accumulate = 0;
+    return bg;
+}
+
+}  // namespace
+
+size_t back_scratch_bytes(const RayGrid &g) {
+    if (g.n_views <= 0) return 0;
+    const BrickGrid bg = plan_bricks(g);
+    return bg.chunks > 1 ? sizeof(float) * static_cast<size_t>(bg.chunks) * g.nx * g.ny * g.nz : 0;
+}
+
+hipError_t launch_back(const RayGrid &g, const WarpGrid &w, const double *Pmat, const void *sino,
+                       int sino_dtype, float *vol, int accumulate, int mode, float *scratch,
+                       float *part, hipStream_t stream) {
+    if (g.n_views <= 0) return hipSuccess;
+    BrickGrid bg = plan_bricks(g);
     bg.accumulate = accumulate;
-    if (bg.chunks > 1 && !accumulate) {
-        // chunks add into the volume: clear it first
-        hipError_t e = launch_fill_zero(vol, sizeof(float) * static_cast<size_t>(g.nx) * g.ny * g.nz,
-                                        stream);
-        if (e != hipSuccess) return e;
-    }
+    bg.partials = part;
+    if (bg.chunks > 1 && !part) return hipErrorInvalidValue;
     const int per = (bg.total + N_XCD - 1) / N_XCD;
     const dim3 grid(static_cast<unsigned>(per * N_XCD)), block(BP_THREADS);
-    const size_t shmem = sizeof(double) * static_cast<size_t>(bg.sz) * bg.bz;
+    const size_t shmem = sizeof(unsigned long long) * static_cast<size_t>(bg.sz) * bg.bz;
     const bool wp = w.U != nullptr;
+    const size_t nvol = static_cast<size_t>(g.nx) * g.ny * g.nz;
+    auto combine = [&]() -> hipError_t {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || bg.chunks <= 1) return e;
+        size_t blocks = (nvol + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        hipLaunchKernelGGL(sum_chunks_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                           stream, part, bg.chunks, nvol, accumulate, vol);
+        return hipGetLastError();
+    };
     if (mode == BP_ONES) {
         if (wp)
             hipLaunchKernelGGL((bp_brick_kernel<float, BP_ONES, true>), grid, block, shmem, stream,
-                               g, w, Pmat, nullptr, vol, bg);
+                               g, w, Pmat, nullptr, nullptr, vol, bg);
         else
             hipLaunchKernelGGL((bp_brick_kernel<float, BP_ONES, false>), grid, block, shmem,
-                               stream, g, w, Pmat, nullptr, vol, bg);
-        return hipGetLastError();
+                               stream, g, w, Pmat, nullptr, nullptr, vol, bg);
+        return combine();
     }
+    // max |r| over the sinogram sets the fixed-point scale
+    const size_t n_sino = static_cast<size_t>(g.n_views) * g.n_u * g.n_v;
+    hipError_t e = launch_max_abs(sino, sino_dtype, n_sino, scratch, stream);
+    if (e != hipSuccess) return e;
 #define CTREX_BP(T)                                                                              \
     {                                                                                            \
         const T *sp = static_cast<const T *>(sino);                                              \
         if (wp)                                                                                  \
             hipLaunchKernelGGL((bp_brick_kernel<T, BP_PLAIN, true>), grid, block, shmem, stream, \
-                               g, w, Pmat, sp, vol, bg);                                         \
+                               g, w, Pmat, sp, scratch, vol, bg);                                \
         else                                                                                     \
             hipLaunchKernelGGL((bp_brick_kernel<T, BP_PLAIN, false>), grid, block, shmem,        \
-                               stream, g, w, Pmat, sp, vol, bg);                                 \
-        return hipGetLastError();                                                                \
+                               stream, g, w, Pmat, sp, scratch, vol, bg);                        \
+        return combine();                                                                        \
     }
     switch (sino_dtype) {
         case F32: CTREX_BP(float)

@@ -50,6 +50,9 @@ struct ctrex_ctx {
     std::list<DeviceViewList> lists;
     // small device scratch
     unsigned long long *d_count = nullptr;
+    float *d_scalar = nullptr;  // max |r| of the backprojector's input
+    float *d_part = nullptr;    // per-chunk backprojection slabs (small volumes)
+    size_t part_cap = 0;
     // SIRT weight cache key
     const void *w_ws = nullptr;
     uint64_t w_gen = 0;
@@ -149,6 +152,24 @@ int resolve_views(ctrex_ctx *c, const int32_t *views, int32_t n_views, const int
         c->lists.pop_back();
     }
     *dev = c->lists.front().dev;
+    return CTREX_OK;
+}
+
+// Grow the context's backprojection slab buffer to what `g` needs.  The
+// device is synchronised before an old buffer is released.
+int ensure_part(ctrex_ctx *c, const RayGrid &g, float **out) {
+    const size_t need = back_scratch_bytes(g);
+    if (need > c->part_cap) {
+        if (c->d_part) {
+            CTREX_HIP(c, hipDeviceSynchronize());
+            CTREX_HIP(c, hipFree(c->d_part));
+            c->d_part = nullptr;
+            c->part_cap = 0;
+        }
+        CTREX_HIP(c, hipMalloc(&c->d_part, need));
+        c->part_cap = need;
+    }
+    *out = c->d_part;
     return CTREX_OK;
 }
 
@@ -276,7 +297,9 @@ int ctrex_create(ctrex_ctx **out, int device) {
     if (hipSetDevice(device) != hipSuccess) return CTREX_EDEVICE;
     ctrex_ctx *c = new ctrex_ctx();
     c->device = device;
-    if (hipMalloc(&c->d_count, sizeof(unsigned long long)) != hipSuccess) {
+    if (hipMalloc(&c->d_count, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&c->d_scalar, 4 * sizeof(float)) != hipSuccess) {
+        if (c->d_count) (void)hipFree(c->d_count);
         delete c;
         return CTREX_EDEVICE;
     }
@@ -297,6 +320,8 @@ void ctrex_destroy(ctrex_ctx *c) {
     if (c->d_P) (void)hipFree(c->d_P);
     if (c->d_U) (void)hipFree(c->d_U);
     if (c->d_count) (void)hipFree(c->d_count);
+    if (c->d_scalar) (void)hipFree(c->d_scalar);
+    if (c->d_part) (void)hipFree(c->d_part);
     for (auto &l : c->lists) (void)hipFree(l.dev);
     delete c;
 }
@@ -488,8 +513,10 @@ int ctrex_back_project(ctrex_ctx *c, const void *sino, int32_t sino_dtype, float
         return CTREX_OK;
     }
     const RayGrid g = make_grid(c, dv, nv);
+    float *part = nullptr;
+    if ((st = ensure_part(c, g, &part)) != CTREX_OK) return st;
     CTREX_HIP(c, launch_back(g, make_warp(c), c->d_P, sino, sino_dtype, vol, accumulate ? 1 : 0,
-                             BP_PLAIN, s));
+                             BP_PLAIN, c->d_scalar, part, s));
     return CTREX_OK;
 }
 
@@ -542,6 +569,8 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
     const int rdt = sino_dtype;  // the correction image takes the data's storage type
     const RayGrid g = make_grid(c, dv, nv);
     const WarpGrid w = make_warp(c);
+    float *part = nullptr;
+    if ((st = ensure_part(c, g, &part)) != CTREX_OK) return st;
 
     // R and C for this geometry / motion / subset / workspace, kept between calls.
     const bool cached = c->w_valid && c->w_ws == workspace && c->w_gen == c->generation &&
@@ -554,7 +583,7 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
         c->w_valid = false;
         FpExtra none{nullptr, nullptr, nullptr};
         CTREX_HIP(c, launch_forward(g, w, nullptr, F32, Rw, F32, FP_RECIP_ONES, none, s));
-        CTREX_HIP(c, launch_back(g, w, c->d_P, nullptr, F32, Cw, 0, BP_ONES, s));
+        CTREX_HIP(c, launch_back(g, w, c->d_P, nullptr, F32, Cw, 0, BP_ONES, c->d_scalar, part, s));
         CTREX_HIP(c, launch_recip(Cw, vox, s));
         c->w_ws = workspace;
         c->w_gen = c->generation;
@@ -577,7 +606,7 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
         CTREX_HIP(c, t_fp.end());
         CTREX_HIP(c, launch_sum_partials(partials, g.total_blocks, resid + (k % kResidCap), s));
         CTREX_HIP(c, t_bp.begin());
-        CTREX_HIP(c, launch_back(g, w, c->d_P, r, rdt, z, 0, BP_PLAIN, s));
+        CTREX_HIP(c, launch_back(g, w, c->d_P, r, rdt, z, 0, BP_PLAIN, c->d_scalar, part, s));
         CTREX_HIP(c, t_bp.end());
         CTREX_HIP(c, t_up.begin());
         CTREX_HIP(c, launch_update(vol, z, Cw, alpha, (flags & CTREX_NONNEG) ? 1 : 0,

@@ -72,9 +72,14 @@ hipError_t launch_forward(const RayGrid &g, const WarpGrid &w, const void *vol, 
                           void *out, int out_dtype, int mode, const FpExtra &ex,
                           hipStream_t stream);
 // vol (+)= A^T sino; `Pmat` holds the view matrices [n_proj * n_sub][12] on the
-// device.  accumulate == 0 overwrites vol.
+// device.  accumulate == 0 overwrites vol.  `scratch` is one device float;
+// `part` holds back_scratch_bytes(g) bytes (may be null when that is 0).
 hipError_t launch_back(const RayGrid &g, const WarpGrid &w, const double *Pmat, const void *sino,
-                       int sino_dtype, float *vol, int accumulate, int mode, hipStream_t stream);
+                       int sino_dtype, float *vol, int accumulate, int mode, float *scratch,
+                       float *part, hipStream_t stream);
+size_t back_scratch_bytes(const RayGrid &g);
+// *out = max |x_i| over n elements (out is overwritten).
+hipError_t launch_max_abs(const void *x, int dtype, size_t n, float *out, hipStream_t stream);
 hipError_t launch_sample_count(const RayGrid &g, unsigned long long *count, hipStream_t stream);
 hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t stream);
 hipError_t launch_recip(float *a, size_t n, hipStream_t stream);

@@ -96,6 +96,25 @@ __global__ __launch_bounds__(1024) void sum_partials_kernel(const double *p, int
     if (threadIdx.x == 0) *out = red[0];
 }
 
+// Block max of |x| folded into *out with an integer max on the float bits
+// (non-negative floats order like their bit patterns); NaN propagates as the
+// largest pattern.
+__global__ __launch_bounds__(THREADS) void max_abs_kernel(const void *x, int dt, size_t n,
+                                                          unsigned *out) {
+    __shared__ unsigned red[THREADS / 64];
+    unsigned m = 0u;
+    const size_t stride = static_cast<size_t>(gridDim.x) * THREADS;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * THREADS + threadIdx.x; i < n; i += stride)
+        m = max(m, __float_as_uint(fabsf(load_as_f32(x, dt, i))));
+    for (int o = 32; o > 0; o >>= 1) m = max(m, static_cast<unsigned>(__shfl_xor(m, o, 64)));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < THREADS / 64; ++i) m = max(m, red[i]);
+        atomicMax(out, m);
+    }
+}
+
 __global__ __launch_bounds__(THREADS) void repack_warp_kernel(const float *U, float4 *out,
                                                               size_t n) {
     const size_t i = static_cast<size_t>(blockIdx.x) * THREADS + threadIdx.x;
@@ -140,6 +159,16 @@ hipError_t launch_convert(const void *src, int src_dtype, void *dst, int dst_dty
 
 hipError_t launch_sum_partials(const double *partials, int n, double *out, hipStream_t s) {
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(1024), 0, s, partials, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_abs(const void *x, int dtype, size_t n, float *out, hipStream_t s) {
+    hipError_t e = launch_fill_zero(out, sizeof(float), s);
+    if (e != hipSuccess || n == 0) return e;
+    size_t blocks = (n + THREADS - 1) / THREADS;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(max_abs_kernel, dim3(static_cast<unsigned>(blocks)), dim3(THREADS), 0, s, x,
+                       dtype, n, reinterpret_cast<unsigned *>(out));
     return hipGetLastError();
 }
 
