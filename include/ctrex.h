@@ -182,6 +182,20 @@ CTREX_API int ctrex_convert(ctrex_ctx *ctx, const void *src, int32_t src_dtype, 
                   int32_t dst_dtype, int64_t n, void *stream);
 
 /*
+ * Total-variation regulariser for the differentiable loss
+ * ||A x - b||^2 + weight * TV(x) (an extension: the paper's Sec. 5 names
+ * regularisers among the learned or hybrid components its operators admit).
+ * TV(x) = sum_j sqrt(|D x_j|^2 + eps^2), D the forward differences along x, y
+ * and z with a zero difference at the last index of each axis.  `x` is a
+ * device float32 [nz][ny][nx] volume (any geometry; none needs to be set).
+ * If `value` (host) is non-NULL the call waits for the stream and stores
+ * TV(x), summed in FP64 in a fixed order.  If `grad` (device float32, same
+ * shape, not aliasing x) is non-NULL it is overwritten with weight * dTV/dx.
+ */
+CTREX_API int ctrex_tv(ctrex_ctx *ctx, const float *x, int32_t nx, int32_t ny, int32_t nz,
+                       float eps, float weight, double *value, float *grad, void *stream);
+
+/*
  * Kernel timing of ctrex_sirt_iterate (instrumentation, no effect on
  * results).  With profiling enabled, every iteration records HIP events on
  * the launch stream around its forward-projection-with-correction, its

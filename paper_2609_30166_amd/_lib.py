@@ -63,6 +63,8 @@ def lib():
             "ctrex_sample_count": (ctypes.c_int, [vp, ip, i32, ctypes.POINTER(ctypes.c_int64), vp]),
             "ctrex_convert": (ctypes.c_int, [vp, vp, i32, vp, i32, ctypes.c_int64, vp]),
             "ctrex_profile_enable": (ctypes.c_int, [vp, i32]),
+            "ctrex_tv": (ctypes.c_int, [vp, vp, i32, i32, i32, ctypes.c_float, ctypes.c_float, dp,
+                                        vp, vp]),
             "ctrex_profile_read": (ctypes.c_int, [vp, dp, ctypes.POINTER(ctypes.c_int64)]),
         }
         for name, (res, args) in sigs.items():

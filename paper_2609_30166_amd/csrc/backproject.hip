@@ -183,36 +183,38 @@ __global__ __launch_bounds__(BP_THREADS) void bp_brick_kernel(RayGrid g, WarpGri
                 const int iv = v0 + (blk / bu) * 8 + (lane >> 3);
                 const int iu = u0 + (blk % bu) * 8 + (lane & 7);
                 // ---- this lane's ray: its samples that can reach the brick
-                int len = 0;
-                float bk = 0.0f, wgt = 0.0f;
+                int len = 0, ib = 0;
+                float wgt = 0.0f;
                 Ray r;
-                r.mx = r.my = r.mz = r.hx = r.hy = r.hz = 0.0f;
+                r.bx = r.by = r.bz = r.sx = r.sy = r.sz = 0.0;
                 const float rv = (iu > u1 || iv > v1) ? 0.0f
                                  : (MODE == BP_ONES) ? 1.0f
                                                      : ld(sino, (k * g.n_v + iv) * g.n_u + iu);
                 if (rv != 0.0f && setup_ray(sv, static_cast<double>(iu), static_cast<double>(iv),
                                             g.nx, g.ny, g.nz, g.step, r)) {
-                    // sample offsets k with mid + k h inside [lo, hi] on every axis
-                    float kmin = r.k0, kmax = r.k0 + static_cast<float>(r.n - 1);
-                    const float mv[3] = {r.mx, r.my, r.mz};
-                    const float hv[3] = {r.hx, r.hy, r.hz};
+                    // sample indices i with b + i s inside [lo, hi] on every axis
+                    // (FP32 estimate widened by one sample; corners are checked
+                    // exactly below)
+                    float kmin = 0.0f, kmax = static_cast<float>(r.n - 1);
+                    const float bv[3] = {static_cast<float>(r.bx), static_cast<float>(r.by),
+                                         static_cast<float>(r.bz)};
+                    const float sv3[3] = {r.fx, r.fy, r.fz};
                     bool hit = true;
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        if (hv[a] != 0.0f) {
-                            const float inv = 1.0f / hv[a];
-                            const float t1 = (lo[a] - mv[a]) * inv, t2 = (hi[a] - mv[a]) * inv;
+                    for (int q = 0; q < 3; ++q) {
+                        if (sv3[q] != 0.0f) {
+                            const float inv = 1.0f / sv3[q];
+                            const float t1 = (lo[q] - bv[q]) * inv, t2 = (hi[q] - bv[q]) * inv;
                             kmin = fmaxf(kmin, fminf(t1, t2) - 1.0f);
                             kmax = fminf(kmax, fmaxf(t1, t2) + 1.0f);
-                        } else if (mv[a] < lo[a] || mv[a] > hi[a]) {
+                        } else if (bv[q] < lo[q] || bv[q] > hi[q]) {
                             hit = false;
                         }
                     }
                     if (hit && kmin <= kmax) {
-                        const int i0 = max(static_cast<int>(ceilf(kmin - r.k0)), 0);
-                        const int i1 = min(static_cast<int>(floorf(kmax - r.k0)), r.n - 1);
-                        len = max(i1 - i0 + 1, 0);
-                        bk = r.k0 + static_cast<float>(i0);
+                        ib = max(static_cast<int>(ceilf(kmin)), 0);
+                        const int ie = min(static_cast<int>(floorf(kmax)), r.n - 1);
+                        len = max(ie - ib + 1, 0);
                         wgt = r.h * rv * inv_sub;
                     }
                 }
@@ -235,11 +237,17 @@ __global__ __launch_bounds__(BP_THREADS) void bp_brick_kernel(RayGrid g, WarpGri
                     const int t = j + st;
                     if (__shfl(S, t, 64) <= start) j = t;
                 }
-                float cmx = __shfl(r.mx, j, 64), cmy = __shfl(r.my, j, 64), cmz = __shfl(r.mz, j, 64);
-                float chx = __shfl(r.hx, j, 64), chy = __shfl(r.hy, j, 64), chz = __shfl(r.hz, j, 64);
+                const int off_own = ib - S;   // sample index = off + pos
+                double cbx = __shfl(r.bx, j, 64), cby = __shfl(r.by, j, 64),
+                       cbz = __shfl(r.bz, j, 64), csx = __shfl(r.sx, j, 64),
+                       csy = __shfl(r.sy, j, 64), csz = __shfl(r.sz, j, 64);
                 float cw = __shfl(wgt, j, 64);
-                float ck = __shfl(bk, j, 64) - static_cast<float>(__shfl(S, j, 64));
+                int coff = __shfl(off_own, j, 64);
                 int cend = __shfl(incl, j, 64);
+                Ray cr;
+                Anchor an = {0, 0, 0, 0.0f, 0.0f, 0.0f};
+                GridAnchor ga = {0, 0, 0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                int seg = -1;
                 const int trips = (T + 63) >> 6;
                 int pos = start;
                 for (int it = 0; it < trips; ++it) {
@@ -249,27 +257,39 @@ __global__ __launch_bounds__(BP_THREADS) void bp_brick_kernel(RayGrid g, WarpGri
                         const unsigned long long rest =
                             j < 63 ? (live & (~0ull << (j + 1))) : 0ull;
                         const int jn = need && rest ? __ffsll(static_cast<long long>(rest)) - 1 : j;
-                        const float nmx = __shfl(r.mx, jn, 64), nmy = __shfl(r.my, jn, 64),
-                                    nmz = __shfl(r.mz, jn, 64), nhx = __shfl(r.hx, jn, 64),
-                                    nhy = __shfl(r.hy, jn, 64), nhz = __shfl(r.hz, jn, 64),
-                                    nw = __shfl(wgt, jn, 64);
-                        const float nk = __shfl(bk, jn, 64) - static_cast<float>(__shfl(S, jn, 64));
+                        const double nbx = __shfl(r.bx, jn, 64), nby = __shfl(r.by, jn, 64),
+                                     nbz = __shfl(r.bz, jn, 64), nsx = __shfl(r.sx, jn, 64),
+                                     nsy = __shfl(r.sy, jn, 64), nsz = __shfl(r.sz, jn, 64);
+                        const float nw = __shfl(wgt, jn, 64);
+                        const int noff = __shfl(off_own, jn, 64);
                         const int ne = __shfl(incl, jn, 64);
                         if (need) {
                             j = jn;
-                            cmx = nmx; cmy = nmy; cmz = nmz;
-                            chx = nhx; chy = nhy; chz = nhz;
-                            cw = nw; ck = nk; cend = ne;
+                            cbx = nbx; cby = nby; cbz = nbz;
+                            csx = nsx; csy = nsy; csz = nsz;
+                            cw = nw; coff = noff; cend = ne;
+                            seg = -1;
                         }
                     }
                     if (pos >= end) continue;
-                    const float kk = ck + static_cast<float>(pos);
+                    const int i = coff + pos;
                     ++pos;
-                    float cx = fmaf(kk, chx, cmx), cy = fmaf(kk, chy, cmy), cz = fmaf(kk, chz, cmz);
-                    if (WARP && !warp(w, d, tau, cx, cy, cz)) continue;
+                    const int sg = i & ~(SEG - 1);
+                    if (sg != seg) {
+                        cr.bx = cbx; cr.by = cby; cr.bz = cbz;
+                        cr.sx = csx; cr.sy = csy; cr.sz = csz;
+                        an = anchor_at(cr, sg);
+                        if (WARP) ga = grid_anchor(w, cbx, cby, cbz, csx, csy, csz, sg);
+                        seg = sg;
+                    }
+                    const float jj = static_cast<float>(i - sg);
+                    float cx = fmaf(jj, static_cast<float>(csx), an.ax),
+                          cy = fmaf(jj, static_cast<float>(csy), an.ay),
+                          cz = fmaf(jj, static_cast<float>(csz), an.az);
+                    if (WARP && !warp(w, d, tau, an, ga, jj, cx, cy, cz)) continue;
                     int ix, iy, iz;
                     float fx, fy, fz;
-                    corner_idx(d, cx, cy, cz, ix, iy, iz, fx, fy, fz);
+                    corner_idx(d, an, cx, cy, cz, ix, iy, iz, fx, fy, fz);
                     const int lx = ix - x0, ly = iy - y0, lz = iz - z0;
                     const float gx1 = fx, gx0 = 1.0f - fx;
                     const float gy1 = fy, gy0 = 1.0f - fy;

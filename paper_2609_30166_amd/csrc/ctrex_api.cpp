@@ -52,6 +52,7 @@ struct ctrex_ctx {
     unsigned long long *d_count = nullptr;
     float *d_scalar = nullptr;  // max |r| of the backprojector's input
     float *d_part = nullptr;    // per-chunk backprojection slabs (small volumes)
+    double *d_red = nullptr;    // 8192 block partials + 1 result (TV value)
     size_t part_cap = 0;
     // SIRT weight cache key
     const void *w_ws = nullptr;
@@ -198,9 +199,9 @@ WarpGrid make_warp(const ctrex_ctx *c) {
     w.gx = c->gx;
     w.gy = c->gy;
     w.gz = c->gz;
-    w.sx = c->d_U ? static_cast<float>(c->gx - 1) / static_cast<float>(c->nx - 1) : 0.0f;
-    w.sy = c->d_U ? static_cast<float>(c->gy - 1) / static_cast<float>(c->ny - 1) : 0.0f;
-    w.sz = c->d_U ? static_cast<float>(c->gz - 1) / static_cast<float>(c->nz - 1) : 0.0f;
+    w.sx = c->d_U ? double(c->gx - 1) / double(c->nx - 1) : 0.0;
+    w.sy = c->d_U ? double(c->gy - 1) / double(c->ny - 1) : 0.0;
+    w.sz = c->d_U ? double(c->gz - 1) / double(c->nz - 1) : 0.0;
     w.margin = c->d_U ? c->warp_margin : 0;
     return w;
 }
@@ -298,8 +299,10 @@ int ctrex_create(ctrex_ctx **out, int device) {
     ctrex_ctx *c = new ctrex_ctx();
     c->device = device;
     if (hipMalloc(&c->d_count, sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc(&c->d_scalar, 4 * sizeof(float)) != hipSuccess) {
+        hipMalloc(&c->d_scalar, 4 * sizeof(float)) != hipSuccess ||
+        hipMalloc(&c->d_red, sizeof(double) * 8193) != hipSuccess) {
         if (c->d_count) (void)hipFree(c->d_count);
+        if (c->d_scalar) (void)hipFree(c->d_scalar);
         delete c;
         return CTREX_EDEVICE;
     }
@@ -322,6 +325,7 @@ void ctrex_destroy(ctrex_ctx *c) {
     if (c->d_count) (void)hipFree(c->d_count);
     if (c->d_scalar) (void)hipFree(c->d_scalar);
     if (c->d_part) (void)hipFree(c->d_part);
+    if (c->d_red) (void)hipFree(c->d_red);
     for (auto &l : c->lists) (void)hipFree(l.dev);
     delete c;
 }
@@ -648,6 +652,29 @@ int ctrex_sample_count(ctrex_ctx *c, const int32_t *views, int32_t n_views, int6
     CTREX_HIP(c, hipMemcpyAsync(&h, c->d_count, sizeof h, hipMemcpyDeviceToHost, s));
     CTREX_HIP(c, hipStreamSynchronize(s));
     *count = static_cast<int64_t>(h);
+    return CTREX_OK;
+}
+
+int ctrex_tv(ctrex_ctx *c, const float *x, int32_t nx, int32_t ny, int32_t nz, float eps,
+             float weight, double *value, float *grad, void *stream) {
+    if (!c) return CTREX_EINVAL;
+    if (!x) return fail(c, CTREX_EINVAL, "x must be a device pointer");
+    if (nx < 1 || ny < 1 || nz < 1 || static_cast<long long>(nx) * ny * nz >= (1ll << 40))
+        return fail(c, CTREX_ESHAPE, "bad volume shape");
+    if (!(eps >= 0.0f) || !std::isfinite(eps) || !std::isfinite(weight))
+        return fail(c, CTREX_EINVAL, "eps must be finite and >= 0, weight finite");
+    if (grad == x) return fail(c, CTREX_EINVAL, "grad must not alias x");
+    CTREX_HIP(c, hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (grad) CTREX_HIP(c, launch_tv_grad(x, nx, ny, nz, eps, weight, grad, s));
+    if (value) {
+        const size_t n = static_cast<size_t>(nx) * ny * nz;
+        const int blocks = tv_blocks(n);
+        CTREX_HIP(c, launch_tv_value(x, nx, ny, nz, eps, c->d_red, s));
+        CTREX_HIP(c, launch_sum_partials(c->d_red, blocks, c->d_red + 8192, s));
+        CTREX_HIP(c, hipMemcpyAsync(value, c->d_red + 8192, sizeof(double), hipMemcpyDeviceToHost, s));
+        CTREX_HIP(c, hipStreamSynchronize(s));
+    }
     return CTREX_OK;
 }
 

@@ -43,7 +43,7 @@ struct RayGrid {
 struct WarpGrid {
     const float4 *U;     // repacked [gz][gy][gx] (x, y, z, 0), or nullptr
     int gx, gy, gz;
-    float sx, sy, sz;    // index -> grid coordinate scale (g - 1) / (n - 1)
+    double sx, sy, sz;   // index -> grid coordinate scale (g - 1) / (n - 1)
     int margin;          // whole voxels bounding |tau * U| on every axis
 };
 
@@ -89,6 +89,14 @@ hipError_t launch_convert(const void *src, int src_dtype, void *dst, int dst_dty
                           hipStream_t stream);
 hipError_t launch_sum_partials(const double *partials, int n, double *out, hipStream_t stream);
 hipError_t launch_repack_warp(const float *U, float4 *out, size_t n_nodes, hipStream_t stream);
+
+// Total variation: per-block FP64 partial sums (tv_blocks(n) of them) and the
+// weighted gradient.
+int tv_blocks(size_t n);
+hipError_t launch_tv_value(const float *x, int nx, int ny, int nz, float eps, double *partials,
+                           hipStream_t s);
+hipError_t launch_tv_grad(const float *x, int nx, int ny, int nz, float eps, float weight,
+                          float *g, hipStream_t s);
 
 // Detector tile processed by one workgroup of the projectors.
 constexpr int TILE_U = 16;

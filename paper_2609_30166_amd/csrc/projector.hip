@@ -9,13 +9,13 @@
 //
 // Per ray (Sec. 4.1, projection operator; Sec. 2.2 geometry):
 //   FP64: direction M^-1 (u, v, 1), slab clip to the voxel-centre hull,
-//         n = ceil(L / step), h = L / n, chord midpoint;
-//   FP32: samples c_i = mid + (i - (n-1)/2) h d, optional warp
-//         c_i' = c_i + tau U(c_i) (Sec. 3.1, 4.2.1), trilinear lookups,
-//         FP32 accumulation; sub-views averaged (Sec. 3.4, 4.2.2).
-// The backprojector walks the same samples and scatters h r / n_sub times
-// the trilinear weights with float atomics, so it is the transpose of the
-// forward operator sample by sample.
+//         n = ceil(L / step), h = L / n, samples t_in + (i + 1/2) h, and an
+//         anchor (integer voxel + FP32 remainder) every SEG samples;
+//   FP32: sample offsets from the anchor, optional warp
+//         c' = c + tau U(c) (Sec. 3.1, 4.2.1), trilinear lookups, FP32
+//         accumulation; sub-views averaged (Sec. 3.4, 4.2.2).
+// The backprojector (backproject.hip) walks the same samples with the same
+// arithmetic, so it is the transpose of this operator sample by sample.
 
 #include "ray_common.h"
 
@@ -43,37 +43,45 @@ __global__ __launch_bounds__(PROJ_THREADS) void fp_kernel(RayGrid g, WarpGrid w,
                 continue;
             const float tau = static_cast<float>(sv.tau);
             float acc0 = 0.0f, acc1 = 0.0f;
-            int i = 0;
-            for (; i + 1 < r.n; i += 2) {
-                const float k0 = r.k0 + static_cast<float>(i);
-                const float k1 = k0 + 1.0f;
-                float ax = fmaf(k0, r.hx, r.mx), ay = fmaf(k0, r.hy, r.my), az = fmaf(k0, r.hz, r.mz);
-                float bx = fmaf(k1, r.hx, r.mx), by = fmaf(k1, r.hy, r.my), bz = fmaf(k1, r.hz, r.mz);
-                bool ina = true, inb = true;
-                if (WARP) {
-                    ina = warp(w, d, tau, ax, ay, az);
-                    inb = warp(w, d, tau, bx, by, bz);
+            for (int i0 = 0; i0 < r.n; i0 += SEG) {
+                const Anchor an = anchor_at(r, i0);
+                GridAnchor ga;
+                if (WARP) ga = grid_anchor(w, r, i0);
+                const int cnt = min(SEG, r.n - i0);
+                int j = 0;
+                for (; j + 1 < cnt; j += 2) {
+                    const float j0 = static_cast<float>(j), j1 = j0 + 1.0f;
+                    float ax = fmaf(j0, r.fx, an.ax), ay = fmaf(j0, r.fy, an.ay),
+                          az = fmaf(j0, r.fz, an.az);
+                    float bx = fmaf(j1, r.fx, an.ax), by = fmaf(j1, r.fy, an.ay),
+                          bz = fmaf(j1, r.fz, an.az);
+                    bool ina = true, inb = true;
+                    if (WARP) {
+                        ina = warp(w, d, tau, an, ga, j0, ax, ay, az);
+                        inb = warp(w, d, tau, an, ga, j1, bx, by, bz);
+                    }
+                    if (MODE == FP_RECIP_ONES) {
+                        acc0 += ina ? 1.0f : 0.0f;
+                        acc1 += inb ? 1.0f : 0.0f;
+                    } else {
+                        const float va = gather(vol, d, corner_of(d, an, ax, ay, az));
+                        const float vb = gather(vol, d, corner_of(d, an, bx, by, bz));
+                        acc0 += ina ? va : 0.0f;
+                        acc1 += inb ? vb : 0.0f;
+                    }
                 }
-                if (MODE == FP_RECIP_ONES) {
-                    acc0 += ina ? 1.0f : 0.0f;
-                    acc1 += inb ? 1.0f : 0.0f;
-                } else {
-                    const float va = gather(vol, d, corner_of(d, ax, ay, az));
-                    const float vb = gather(vol, d, corner_of(d, bx, by, bz));
-                    acc0 += ina ? va : 0.0f;
-                    acc1 += inb ? vb : 0.0f;
-                }
-            }
-            if (i < r.n) {
-                const float k0 = r.k0 + static_cast<float>(i);
-                float ax = fmaf(k0, r.hx, r.mx), ay = fmaf(k0, r.hy, r.my), az = fmaf(k0, r.hz, r.mz);
-                bool ina = true;
-                if (WARP) ina = warp(w, d, tau, ax, ay, az);
-                if (MODE == FP_RECIP_ONES) {
-                    acc0 += ina ? 1.0f : 0.0f;
-                } else {
-                    const float va = gather(vol, d, corner_of(d, ax, ay, az));
-                    acc0 += ina ? va : 0.0f;
+                if (j < cnt) {
+                    const float j0 = static_cast<float>(j);
+                    float ax = fmaf(j0, r.fx, an.ax), ay = fmaf(j0, r.fy, an.ay),
+                          az = fmaf(j0, r.fz, an.az);
+                    bool ina = true;
+                    if (WARP) ina = warp(w, d, tau, an, ga, j0, ax, ay, az);
+                    if (MODE == FP_RECIP_ONES) {
+                        acc0 += ina ? 1.0f : 0.0f;
+                    } else {
+                        const float va = gather(vol, d, corner_of(d, an, ax, ay, az));
+                        acc0 += ina ? va : 0.0f;
+                    }
                 }
             }
             y = fmaf(r.h, acc0 + acc1, y);

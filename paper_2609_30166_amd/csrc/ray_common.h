@@ -26,12 +26,26 @@ __device__ __forceinline__ void st(bf16_t *p, int i, float v) { p[i].bits = f32_
 __device__ __forceinline__ void st(_Float16 *p, int i, float v) { p[i] = static_cast<_Float16>(v); }
 
 // ------------------------------------------------------------- ray set-up --
+// Sample i of a ray sits at b + i * s (index coordinates, FP64).  Positions
+// are never formed in absolute FP32 (its ulp at coordinate 512 is 3e-5):
+// every segment of SEG consecutive samples starts from an FP64 anchor split
+// into an integer voxel and an FP32 remainder in [0, 1), and the samples of
+// the segment are the anchor remainder plus j * s in FP32 (|j| < SEG), which
+// keeps positions within about 1e-6 voxel.  Forward and back projection use
+// the same arithmetic, so their samples agree bit for bit.
+constexpr int SEG = 32;
+
 struct Ray {
-    float mx, my, mz;   // chord midpoint (index coordinates)
-    float hx, hy, hz;   // step vector h * d
+    double bx, by, bz;  // position of sample 0
+    double sx, sy, sz;  // step vector h * d
+    float fx, fy, fz;   // step vector in FP32
     float h;            // sample weight (path length per sample)
-    float k0;           // -(n - 1) / 2: offset of sample 0 from the midpoint
     int n;              // number of samples
+};
+
+struct Anchor {
+    int ix, iy, iz;     // integer part of the segment's first sample
+    float ax, ay, az;   // remainder in [0, 1)
 };
 
 // FP64 clipping of one axis' slab.  Returns false when the ray misses.
@@ -49,7 +63,7 @@ __device__ __forceinline__ bool slab(double s, double d, double hi, double &t0, 
 
 // Ray through pixel centre (u, v) of sub-view sv, in FP64: unit direction
 // M^-1 (u, v, 1) / |.|, slab clip to the voxel-centre hull, n = ceil(L / step),
-// h = L / n and the chord midpoint.  Reciprocals are formed once (one
+// h = L / n, samples at t_in + (i + 1/2) h.  Reciprocals are formed once (one
 // division for the length, one per axis for the slabs); the sample count n
 // is then an integer function of correctly rounded FP64 values, so it differs
 // from a plain division-based evaluation only if L / step lies within an ulp
@@ -71,17 +85,34 @@ __device__ __forceinline__ bool setup_ray(const SubView &sv, double u, double v,
     const double L = t1 - t0;
     const double nd = ceil(L / step);
     const double h = L / nd;
-    const double tm = 0.5 * (t0 + t1);
-    r.mx = static_cast<float>(fma(tm, dx, sv.S[0]));
-    r.my = static_cast<float>(fma(tm, dy, sv.S[1]));
-    r.mz = static_cast<float>(fma(tm, dz, sv.S[2]));
-    r.hx = static_cast<float>(h * dx);
-    r.hy = static_cast<float>(h * dy);
-    r.hz = static_cast<float>(h * dz);
+    const double tb = fma(0.5, h, t0);
+    r.bx = fma(tb, dx, sv.S[0]);
+    r.by = fma(tb, dy, sv.S[1]);
+    r.bz = fma(tb, dz, sv.S[2]);
+    r.sx = h * dx;
+    r.sy = h * dy;
+    r.sz = h * dz;
+    r.fx = static_cast<float>(r.sx);
+    r.fy = static_cast<float>(r.sy);
+    r.fz = static_cast<float>(r.sz);
     r.h = static_cast<float>(h);
     r.n = static_cast<int>(nd);
-    r.k0 = -0.5f * static_cast<float>(r.n - 1);
     return true;
+}
+
+// Anchor of the segment whose first sample is i.
+__device__ __forceinline__ Anchor anchor_at(const Ray &r, int i) {
+    const double di = static_cast<double>(i);
+    const double px = fma(di, r.sx, r.bx), py = fma(di, r.sy, r.by), pz = fma(di, r.sz, r.bz);
+    const double fx = floor(px), fy = floor(py), fz = floor(pz);
+    Anchor a;
+    a.ix = static_cast<int>(fx);
+    a.iy = static_cast<int>(fy);
+    a.iz = static_cast<int>(fz);
+    a.ax = static_cast<float>(px - fx);
+    a.ay = static_cast<float>(py - fy);
+    a.az = static_cast<float>(pz - fz);
+    return a;
 }
 
 // ------------------------------------------------------------ trilinear ----
@@ -96,44 +127,52 @@ struct Corner {
     float fx, fy, fz;   // fractions in [0, 1]
 };
 
-// Lower corner i0 = min(floor(c), n - 2) of c clamped into [0, n - 1].
-__device__ __forceinline__ Corner corner_of(const VolDims &d, float cx, float cy, float cz) {
-    cx = fminf(fmaxf(cx, 0.0f), d.mx);
-    cy = fminf(fmaxf(cy, 0.0f), d.my);
-    cz = fminf(fmaxf(cz, 0.0f), d.mz);
-    const int ix = min(static_cast<int>(cx), d.nx - 2);
-    const int iy = min(static_cast<int>(cy), d.ny - 2);
-    const int iz = min(static_cast<int>(cz), d.nz - 2);
+// Lower corner and fraction on one axis of n >= 2 nodes for the position
+// i + l (i integer, l the FP32 local offset), as for the coordinate clamped
+// into [0, n - 1] with corner min(floor(c), n - 2).
+__device__ __forceinline__ void axis_corner(int i, float l, int n, int &k, float &f) {
+    const float fl = floorf(l);
+    k = i + static_cast<int>(fl);
+    f = l - fl;
+    if (k < 0) {
+        k = 0;
+        f = 0.0f;
+    }
+    if (k > n - 2) {
+        k = n - 2;
+        f = 1.0f;
+    }
+}
+
+// True when i + l lies in [0, n - 1].
+__device__ __forceinline__ bool axis_inside(int i, float l, int n) {
+    const float fl = floorf(l);
+    const int k = i + static_cast<int>(fl);
+    return k >= 0 && (k < n - 1 || (k == n - 1 && l == fl));
+}
+
+// Corner of the sample at local offsets (lx, ly, lz) from anchor a.
+__device__ __forceinline__ void corner_idx(const VolDims &d, const Anchor &a, float lx, float ly,
+                                           float lz, int &ix, int &iy, int &iz, float &fx,
+                                           float &fy, float &fz) {
+    axis_corner(a.ix, lx, d.nx, ix, fx);
+    axis_corner(a.iy, ly, d.ny, iy, fy);
+    axis_corner(a.iz, lz, d.nz, iz, fz);
+}
+
+__device__ __forceinline__ Corner corner_of(const VolDims &d, const Anchor &a, float lx, float ly,
+                                            float lz) {
+    int ix, iy, iz;
     Corner k;
-    k.fx = cx - static_cast<float>(ix);
-    k.fy = cy - static_cast<float>(iy);
-    k.fz = cz - static_cast<float>(iz);
+    corner_idx(d, a, lx, ly, lz, ix, iy, iz, k.fx, k.fy, k.fz);
     k.base = (iz * d.ny + iy) * d.nx + ix;
     return k;
 }
 
-// Same corner as corner_of(), returned as indices.
-__device__ __forceinline__ void corner_idx(const VolDims &d, float cx, float cy, float cz, int &ix,
-                                           int &iy, int &iz, float &fx, float &fy, float &fz) {
-    cx = fminf(fmaxf(cx, 0.0f), d.mx);
-    cy = fminf(fmaxf(cy, 0.0f), d.my);
-    cz = fminf(fmaxf(cz, 0.0f), d.mz);
-    ix = min(static_cast<int>(cx), d.nx - 2);
-    iy = min(static_cast<int>(cy), d.ny - 2);
-    iz = min(static_cast<int>(cz), d.nz - 2);
-    fx = cx - static_cast<float>(ix);
-    fy = cy - static_cast<float>(iy);
-    fz = cz - static_cast<float>(iz);
-}
-
-template <typename TV>
-__device__ __forceinline__ float gather(const TV *__restrict__ vol, const VolDims &d,
-                                        const Corner &k) {
-    const int b = k.base;
-    const float v000 = ld(vol, b), v001 = ld(vol, b + 1);
-    const float v010 = ld(vol, b + d.nx), v011 = ld(vol, b + d.nx + 1);
-    const float v100 = ld(vol, b + d.nxy), v101 = ld(vol, b + d.nxy + 1);
-    const float v110 = ld(vol, b + d.nxy + d.nx), v111 = ld(vol, b + d.nxy + d.nx + 1);
+// Trilinear blend of the eight corner values (x first, then y, then z).
+__device__ __forceinline__ float blend(const Corner &k, float v000, float v001, float v010,
+                                       float v011, float v100, float v101, float v110,
+                                       float v111) {
     const float a00 = fmaf(k.fx, v001 - v000, v000);
     const float a01 = fmaf(k.fx, v011 - v010, v010);
     const float a10 = fmaf(k.fx, v101 - v100, v100);
@@ -143,16 +182,74 @@ __device__ __forceinline__ float gather(const TV *__restrict__ vol, const VolDim
     return fmaf(k.fz, b1 - b0, b0);
 }
 
+template <typename TV>
+__device__ __forceinline__ float gather(const TV *__restrict__ vol, const VolDims &d,
+                                        const Corner &k) {
+    const int b = k.base;
+    return blend(k, ld(vol, b), ld(vol, b + 1), ld(vol, b + d.nx), ld(vol, b + d.nx + 1),
+                 ld(vol, b + d.nxy), ld(vol, b + d.nxy + 1), ld(vol, b + d.nxy + d.nx),
+                 ld(vol, b + d.nxy + d.nx + 1));
+}
+
+// FP32 volumes: each x-adjacent pair of corners is one 8-byte load (4-byte
+// aligned; gfx950 global loads accept it), halving the gather instructions.
+typedef float f32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+
+template <>
+__device__ __forceinline__ float gather<float>(const float *__restrict__ vol, const VolDims &d,
+                                               const Corner &k) {
+    const int b = k.base;
+    const f32x2_a4 p00 = *reinterpret_cast<const f32x2_a4 *>(vol + b);
+    const f32x2_a4 p01 = *reinterpret_cast<const f32x2_a4 *>(vol + b + d.nx);
+    const f32x2_a4 p10 = *reinterpret_cast<const f32x2_a4 *>(vol + b + d.nxy);
+    const f32x2_a4 p11 = *reinterpret_cast<const f32x2_a4 *>(vol + b + d.nxy + d.nx);
+    return blend(k, p00.x, p00.y, p01.x, p01.y, p10.x, p10.y, p11.x, p11.y);
+}
+
 // ----------------------------------------------------------------- warp ----
-// Displacement at c (trilinear over the node grid, clamped to the grid).
-__device__ __forceinline__ float3 displacement(const WarpGrid &w, float cx, float cy, float cz) {
-    float gx = fminf(fmaxf(cx * w.sx, 0.0f), static_cast<float>(w.gx - 1));
-    float gy = fminf(fmaxf(cy * w.sy, 0.0f), static_cast<float>(w.gy - 1));
-    float gz = fminf(fmaxf(cz * w.sz, 0.0f), static_cast<float>(w.gz - 1));
-    const int ix = min(static_cast<int>(gx), w.gx - 2);
-    const int iy = min(static_cast<int>(gy), w.gy - 2);
-    const int iz = min(static_cast<int>(gz), w.gz - 2);
-    const float fx = gx - ix, fy = gy - iy, fz = gz - iz;
+// The displacement grid is anchored like the ray: per segment, the grid
+// coordinate (b + i s) (g - 1) / (n - 1) of its first sample is split in FP64
+// into an integer node and an FP32 remainder, and the samples of the segment
+// add j times the FP32 grid step, so the trilinear weights of U are as exact
+// as the sample positions.
+struct GridAnchor {
+    int ix, iy, iz;      // integer grid node of the segment's first sample
+    float ax, ay, az;    // remainder in [0, 1)
+    float sx, sy, sz;    // grid step per sample
+};
+
+__device__ __forceinline__ GridAnchor grid_anchor(const WarpGrid &w, double bx, double by,
+                                                  double bz, double sx, double sy, double sz,
+                                                  int i) {
+    const double di = static_cast<double>(i);
+    const double px = fma(di, sx, bx) * w.sx, py = fma(di, sy, by) * w.sy,
+                 pz = fma(di, sz, bz) * w.sz;
+    const double fx = floor(px), fy = floor(py), fz = floor(pz);
+    GridAnchor a;
+    a.ix = static_cast<int>(fx);
+    a.iy = static_cast<int>(fy);
+    a.iz = static_cast<int>(fz);
+    a.ax = static_cast<float>(px - fx);
+    a.ay = static_cast<float>(py - fy);
+    a.az = static_cast<float>(pz - fz);
+    a.sx = static_cast<float>(sx * w.sx);
+    a.sy = static_cast<float>(sy * w.sy);
+    a.sz = static_cast<float>(sz * w.sz);
+    return a;
+}
+
+__device__ __forceinline__ GridAnchor grid_anchor(const WarpGrid &w, const Ray &r, int i) {
+    return grid_anchor(w, r.bx, r.by, r.bz, r.sx, r.sy, r.sz, i);
+}
+
+// Displacement at local sample j of the anchored segment (trilinear over the
+// node grid, lookups clamped to the grid).
+__device__ __forceinline__ float3 displacement(const WarpGrid &w, const GridAnchor &ga, float j) {
+    int ix, iy, iz;
+    float fx, fy, fz;
+    axis_corner(ga.ix, fmaf(j, ga.sx, ga.ax), w.gx, ix, fx);
+    axis_corner(ga.iy, fmaf(j, ga.sy, ga.ay), w.gy, iy, fy);
+    axis_corner(ga.iz, fmaf(j, ga.sz, ga.az), w.gz, iz, fz);
     const int sy = w.gx, sz = w.gx * w.gy;
     const int b = (iz * w.gy + iy) * w.gx + ix;
     const float4 u000 = w.U[b], u001 = w.U[b + 1], u010 = w.U[b + sy], u011 = w.U[b + sy + 1];
@@ -176,14 +273,17 @@ __device__ __forceinline__ float3 displacement(const WarpGrid &w, float cx, floa
     return r;
 }
 
-// Warp a sample; false if the warped sample leaves the hull.
-__device__ __forceinline__ bool warp(const WarpGrid &w, const VolDims &d, float tau, float &cx,
-                                     float &cy, float &cz) {
-    const float3 u = displacement(w, cx, cy, cz);
-    cx = fmaf(tau, u.x, cx);
-    cy = fmaf(tau, u.y, cy);
-    cz = fmaf(tau, u.z, cz);
-    return !(cx < 0.0f || cx > d.mx || cy < 0.0f || cy > d.my || cz < 0.0f || cz > d.mz);
+// Pull-back warp of local sample j (Sec. 3.1): l += tau U(sample); false if
+// the warped sample leaves the hull.
+__device__ __forceinline__ bool warp(const WarpGrid &w, const VolDims &d, float tau,
+                                     const Anchor &a, const GridAnchor &ga, float j, float &lx,
+                                     float &ly, float &lz) {
+    const float3 u = displacement(w, ga, j);
+    lx = fmaf(tau, u.x, lx);
+    ly = fmaf(tau, u.y, ly);
+    lz = fmaf(tau, u.z, lz);
+    return axis_inside(a.ix, lx, d.nx) && axis_inside(a.iy, ly, d.ny) &&
+           axis_inside(a.iz, lz, d.nz);
 }
 
 // ------------------------------------------------------------- tiling ------

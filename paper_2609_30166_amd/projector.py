@@ -210,6 +210,22 @@ class Geometry:
         check(self._ctx, _lib.lib().ctrex_profile_read(self._ctx, ms, n))
         return {k: (ms[i], n[i]) for i, k in enumerate(("forward", "back", "update"))}
 
+    def tv(self, x, eps=1e-5, weight=1.0, value=True, grad=False):
+        """Total variation of a float32 volume: returns (TV(x) or None,
+        weight * dTV/dx or None), both computed by the library's kernels."""
+        if x.dtype != torch.float32 or not x.is_contiguous() or x.ndim != 3:
+            raise ValueError("x must be a contiguous float32 [nz][ny][nx] tensor")
+        if x.device != self.device:
+            raise ValueError("x is on %s, the projector on %s" % (x.device, self.device))
+        nz, ny, nx = x.shape
+        g = torch.empty_like(x) if grad else None
+        v = ctypes.c_double(0.0)
+        check(self._ctx, _lib.lib().ctrex_tv(
+            self._ctx, ctypes.c_void_p(x.data_ptr()), nx, ny, nz, float(eps), float(weight),
+            ctypes.byref(v) if value else None, ctypes.c_void_p(g.data_ptr()) if grad else None,
+            _stream(self.device)))
+        return (v.value if value else None), g
+
     def convert(self, src, dtype):
         """Storage conversion (round to nearest even) through the library."""
         out = torch.empty(src.shape, dtype=dtype, device=self.device)
@@ -239,3 +255,32 @@ class ForwardProject(torch.autograd.Function):
 def project(vol, geom, views=None):
     """Differentiable forward projection (autograd tape through the HIP pair)."""
     return ForwardProject.apply(vol, geom, views)
+
+
+class TotalVariation(torch.autograd.Function):
+    """TV(x) (FP64 value) with the library's gradient kernel as backward."""
+
+    @staticmethod
+    def forward(ctx, vol, geom, eps=1e-5):
+        v, _ = geom.tv(vol.contiguous(), eps)
+        ctx.geom = geom
+        ctx.eps = eps
+        ctx.save_for_backward(vol)
+        return torch.tensor(v, dtype=torch.float64, device=vol.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (vol,) = ctx.saved_tensors
+        _, g = ctx.geom.tv(vol.contiguous(), ctx.eps, weight=1.0, value=False, grad=True)
+        return g * grad_out.to(torch.float32), None, None
+
+
+def total_variation(vol, geom, eps=1e-5):
+    return TotalVariation.apply(vol, geom, eps)
+
+
+def reconstruction_loss(vol, b, geom, lam=1e-3, eps=1e-5, views=None):
+    """||A x - b||^2 + lam TV(x), differentiable through the HIP operators
+    (residual summed in FP64)."""
+    r = project(vol, geom, views) - b
+    return (r.double() ** 2).sum() + lam * total_variation(vol, geom, eps)
