@@ -1,0 +1,155 @@
+/*
+ * ctrex_nn.h — C ABI of the learned-correction kernels (3D U-Net).
+ *
+ * The paper names learned components acting as correction terms between
+ * physics-based operator applications as the natural extension of its
+ * operator framework (Sec. 5); this library provides the kernels of such a
+ * correction: a 3D U-Net applied to the volume between unrolled SIRT
+ * iterations of Eq. (1), trained and run on the GPU by these kernels.
+ *
+ * Conventions:
+ *  - Activations are BF16, channels-last: element (z, y, x, c) of a tensor
+ *    with channel stride `cs` and channel offset `off` sits at
+ *    ((z * H + y) * W + x) * cs + off + c.  A stride larger than the channel
+ *    count lets a layer read or write a slice of a wider tensor (the skip
+ *    concatenations are built in place this way).  Volumes D x H x W need
+ *    D * H * W to be a multiple of 64 and, for the 2x pooling and up-sampling,
+ *    even sides.
+ *  - Convolution weights are packed BF16 `[taps][cout][cin]` (cin fastest);
+ *    3x3x3 taps are ordered (dz, dy, dx) with dx fastest, zero padding of 1.
+ *    ctrex_nn_pack_conv3 builds the forward packing from FP32 master weights
+ *    `[cout][cin][27]`, and the packing of the data gradient (taps mirrored,
+ *    in/out channels swapped).  Up-sampling weights (2x2x2, stride 2) are FP32
+ *    `[cin][cout][8]` (torch ConvTranspose3d order), packed as BF16
+ *    `[8][cout][cin]` and, for the data gradient, `[8][cin][cout]`.
+ *  - Arithmetic: BF16 x BF16 products accumulate in FP32 on the matrix cores
+ *    (v_mfma_f32_16x16x32_bf16); biases, losses and optimizer state are FP32.
+ *  - Channel counts: cin in {1, 16, 32, 64}, cout in {16, 32, 64} (the
+ *    3-level 16/32/64 U-Net); other values return CTREX_ESHAPE.
+ *  - All calls are asynchronous on `stream` (a hipStream_t, NULL = null
+ *    stream) unless stated; pointers are device memory owned by the caller;
+ *    statuses and ctrex_last_error() as in ctrex.h.
+ */
+#ifndef CTREX_NN_H
+#define CTREX_NN_H
+
+#include "ctrex.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CTREX_NN_RELU 1u       /* apply max(., 0) in the epilogue */
+#define CTREX_NN_ACCUMULATE 2u /* add into the output instead of overwriting */
+#define CTREX_NN_OUT_F32 4u    /* output tensor is FP32 (default BF16) */
+
+/*
+ * out = act(bias + conv3x3x3(in, w)) over a D x H x W volume (stride 1, zero
+ * padding 1).  `wt` is a packed BF16 [27][cout][cin] weight tensor, `bias` FP32
+ * [cout] or NULL.  With CTREX_NN_ACCUMULATE the result (after the activation)
+ * is added to `out`.  The data gradient of a convolution is this call with
+ * the dgrad packing of its weights (cin and cout swapped), no bias, no ReLU.
+ */
+CTREX_API int ctrex_nn_conv3(ctrex_ctx *ctx, const void *in, int32_t in_cs, int32_t in_off,
+                             int32_t cin, const void *wt, const float *bias, void *out,
+                             int32_t out_cs, int32_t out_off, int32_t cout, int32_t D, int32_t H,
+                             int32_t W, uint32_t flags, void *stream);
+
+/*
+ * Weight and bias gradients of ctrex_nn_conv3: dw[co][ci][tap] (FP32, same
+ * order as the master weights) = sum over voxels of dout[v][co] *
+ * in[v + tap][ci]; dbias[co] = sum over voxels of dout[v][co] (NULL skips).
+ * Results overwrite dw / dbias; sums are formed in FP32 per chunk of voxels
+ * and combined in a fixed order in FP64 (deterministic).  Uses the context's
+ * scratch memory (grown on demand, which synchronises the device).
+ */
+CTREX_API int ctrex_nn_conv3_wgrad(ctrex_ctx *ctx, const void *in, int32_t in_cs, int32_t in_off,
+                                   int32_t cin, const void *dout, int32_t dout_cs,
+                                   int32_t dout_off, int32_t cout, int32_t D, int32_t H, int32_t W,
+                                   float *dw, float *dbias, void *stream);
+
+/*
+ * 2x2x2 stride-2 transposed convolution (up-sampling): the input is
+ * D x H x W, the output 2D x 2H x 2W; out[2i + a][co] = bias[co] +
+ * sum_ci in[i][ci] w[a][co][ci], `wt` packed BF16 [8][cout][cin].
+ */
+CTREX_API int ctrex_nn_upconv2(ctrex_ctx *ctx, const void *in, int32_t in_cs, int32_t in_off,
+                               int32_t cin, const void *wt, const float *bias, void *out,
+                               int32_t out_cs, int32_t out_off, int32_t cout, int32_t D,
+                               int32_t H, int32_t W, uint32_t flags, void *stream);
+
+/*
+ * Data gradient of ctrex_nn_upconv2: din[i][ci] = sum_a sum_co
+ * dout[2i + a][co] w[a][co][ci] (`wt_d` packed BF16 [8][cin][cout]); D, H, W
+ * are the sizes of `din`.
+ */
+CTREX_API int ctrex_nn_upconv2_dgrad(ctrex_ctx *ctx, const void *dout, int32_t dout_cs,
+                                     int32_t dout_off, int32_t cout, const void *wt_d, void *din,
+                                     int32_t din_cs, int32_t din_off, int32_t cin, int32_t D,
+                                     int32_t H, int32_t W, uint32_t flags, void *stream);
+
+/*
+ * Weight and bias gradients of ctrex_nn_upconv2: dw[ci][co][a] (FP32, torch
+ * ConvTranspose3d order) and dbias[co] (NULL skips); D, H, W are the input
+ * sizes.  Deterministic, like ctrex_nn_conv3_wgrad.
+ */
+CTREX_API int ctrex_nn_upconv2_wgrad(ctrex_ctx *ctx, const void *in, int32_t in_cs,
+                                     int32_t in_off, int32_t cin, const void *dout,
+                                     int32_t dout_cs, int32_t dout_off, int32_t cout, int32_t D,
+                                     int32_t H, int32_t W, float *dw, float *dbias, void *stream);
+
+/* 2x2x2 max pooling: out[i][c] = max_a in[2i + a][c]; D, H, W are the input
+ * sizes; `out` is dense (channel stride = c). */
+CTREX_API int ctrex_nn_maxpool2(ctrex_ctx *ctx, const void *in, int32_t in_cs, int32_t in_off,
+                                int32_t c, void *out, int32_t D, int32_t H, int32_t W,
+                                void *stream);
+
+/* Backward of ctrex_nn_maxpool2: din[2i + a][c] += dout[i][c] for the first
+ * (in x, y, z order) maximum of each window; `din` shares the layout of `in`. */
+CTREX_API int ctrex_nn_maxpool2_backward(ctrex_ctx *ctx, const void *in, int32_t in_cs,
+                                         int32_t in_off, int32_t c, const void *dout, void *din,
+                                         int32_t D, int32_t H, int32_t W, void *stream);
+
+/* ReLU backward in place: g[v][c] = 0 where y[v][c] <= 0 (y, g share the
+ * channel stride/offset layout; n_vox voxels of c channels). */
+CTREX_API int ctrex_nn_relu_backward(ctrex_ctx *ctx, const void *y, void *g, int32_t cs,
+                                     int32_t off, int32_t c, int64_t n_vox, void *stream);
+
+/* Head and residual: out[v] = x[v] + b + sum_c h[c] act[v][c] (x, out FP32,
+ * act BF16 dense with c channels, h FP32 [c], b FP32 [1]). */
+CTREX_API int ctrex_nn_head(ctrex_ctx *ctx, const void *act, int32_t c, const float *h,
+                            const float *b, const float *x, float *out, int64_t n_vox,
+                            void *stream);
+
+/* Backward of ctrex_nn_head: dact[v][c] = dout[v] h[c] (BF16), dh[c] =
+ * sum_v dout[v] act[v][c], db = sum_v dout[v] (FP32, deterministic). */
+CTREX_API int ctrex_nn_head_backward(ctrex_ctx *ctx, const void *act, int32_t c, const float *h,
+                                     const float *dout, void *dact, float *dh, float *db,
+                                     int64_t n_vox, void *stream);
+
+/* Mean squared error over n values: *loss (host, optional; waits) =
+ * sum (a - t)^2 / n in FP64, grad (optional) = 2 (a - t) / n. */
+CTREX_API int ctrex_nn_mse(ctrex_ctx *ctx, const float *a, const float *t, int64_t n,
+                           double *loss, float *grad, void *stream);
+
+/* One Adam step over n FP32 parameters (bias-corrected, step >= 1). */
+CTREX_API int ctrex_nn_adam(ctrex_ctx *ctx, float *param, const float *grad, float *m, float *v,
+                            int64_t n, float lr, float beta1, float beta2, float eps,
+                            int32_t step, void *stream);
+
+/* Pack FP32 master weights [cout][cin][27] into BF16 forward [27][cout][cin]
+ * (`wt`, optional) and data-gradient [27][cin][cout] with mirrored taps
+ * (`wt_d`, optional). */
+CTREX_API int ctrex_nn_pack_conv3(ctrex_ctx *ctx, const float *w, int32_t cout, int32_t cin,
+                                  void *wt, void *wt_d, void *stream);
+
+/* Pack FP32 up-sampling weights [cin][cout][8] into BF16 [8][cout][cin]
+ * (`wt`, optional) and [8][cin][cout] (`wt_d`, optional). */
+CTREX_API int ctrex_nn_pack_upconv2(ctrex_ctx *ctx, const float *w, int32_t cin, int32_t cout,
+                                    void *wt, void *wt_d, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTREX_NN_H */

@@ -22,6 +22,7 @@ STATUS = {
 }
 F32, BF16, F16 = 0, 1, 2
 NONNEG, BF16_GATHER, F16_GATHER, RECOMPUTE_WEIGHTS = 1, 2, 4, 8
+NN_RELU, NN_ACCUMULATE, NN_OUT_F32 = 1, 2, 4
 
 
 class CtrexError(RuntimeError):
@@ -66,6 +67,31 @@ def lib():
             "ctrex_tv": (ctypes.c_int, [vp, vp, i32, i32, i32, ctypes.c_float, ctypes.c_float, dp,
                                         vp, vp]),
             "ctrex_profile_read": (ctypes.c_int, [vp, dp, ctypes.POINTER(ctypes.c_int64)]),
+            # learned-correction kernels (include/ctrex_nn.h)
+            "ctrex_nn_conv3": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, vp, vp, i32, i32, i32,
+                                              i32, i32, i32, u32, vp]),
+            "ctrex_nn_conv3_wgrad": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, i32, i32, i32,
+                                                    i32, i32, i32, vp, vp, vp]),
+            "ctrex_nn_upconv2": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, vp, vp, i32, i32, i32,
+                                                i32, i32, i32, u32, vp]),
+            "ctrex_nn_upconv2_dgrad": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, vp, i32, i32,
+                                                      i32, i32, i32, i32, u32, vp]),
+            "ctrex_nn_upconv2_wgrad": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, i32, i32, i32,
+                                                      i32, i32, i32, vp, vp, vp]),
+            "ctrex_nn_maxpool2": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, i32, i32, i32, vp]),
+            "ctrex_nn_maxpool2_backward": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, vp, i32, i32,
+                                                          i32, vp]),
+            "ctrex_nn_relu_backward": (ctypes.c_int, [vp, vp, vp, i32, i32, i32, ctypes.c_int64,
+                                                      vp]),
+            "ctrex_nn_head": (ctypes.c_int, [vp, vp, i32, vp, vp, vp, vp, ctypes.c_int64, vp]),
+            "ctrex_nn_head_backward": (ctypes.c_int, [vp, vp, i32, vp, vp, vp, vp, vp,
+                                                      ctypes.c_int64, vp]),
+            "ctrex_nn_mse": (ctypes.c_int, [vp, vp, vp, ctypes.c_int64, dp, vp, vp]),
+            "ctrex_nn_adam": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float,
+                                             ctypes.c_float, ctypes.c_float, ctypes.c_float, i32,
+                                             vp]),
+            "ctrex_nn_pack_conv3": (ctypes.c_int, [vp, vp, i32, i32, vp, vp, vp]),
+            "ctrex_nn_pack_upconv2": (ctypes.c_int, [vp, vp, i32, i32, vp, vp, vp]),
         }
         for name, (res, args) in sigs.items():
             fn = getattr(L, name)

@@ -17,80 +17,16 @@
 #include <string>
 #include <vector>
 
+#include "ctrex_ctx.h"
 #include "ctrex_internal.h"
 
 using namespace ctrex;
 
 namespace {
 
-struct DeviceViewList {
-    std::vector<int32_t> host;
-    int32_t *dev = nullptr;
-};
-
-}  // namespace
-
-struct ctrex_ctx {
-    int device = 0;
-    std::string err;
-    // geometry
-    bool have_geom = false;
-    int n_proj = 0, n_sub = 0, n_u = 0, n_v = 0, nx = 0, ny = 0, nz = 0;
-    double step = 0.0;
-    std::vector<SubView> tab;
-    SubView *d_tab = nullptr;
-    double *d_P = nullptr;    // view matrices [n_proj * n_sub][12]
-    size_t P_cap = 0;
-    uint64_t generation = 0;  // bumps on geometry or motion change
-    // motion
-    float4 *d_U = nullptr;
-    int gx = 0, gy = 0, gz = 0;
-    int warp_margin = 0;  // ceil(max |tau| * max |U component|)
-    // cached device view lists (most recent first)
-    std::list<DeviceViewList> lists;
-    // small device scratch
-    unsigned long long *d_count = nullptr;
-    float *d_scalar = nullptr;  // max |r| of the backprojector's input
-    float *d_part = nullptr;    // per-chunk backprojection slabs (small volumes)
-    double *d_red = nullptr;    // 8192 block partials + 1 result (TV value)
-    size_t part_cap = 0;
-    // SIRT weight cache key
-    const void *w_ws = nullptr;
-    uint64_t w_gen = 0;
-    std::vector<int32_t> w_views;
-    bool w_all = false;
-    bool w_valid = false;
-    // kernel timing (ctrex_profile_enable)
-    bool profiling = false;
-    std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_marks;
-};
-
-namespace {
-
 constexpr size_t kAlign = 256;
 constexpr int kResidCap = 1024;
 constexpr size_t kMaxLists = 64;
-
-int fail(ctrex_ctx *c, int code, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    if (c) c->err = buf;
-    return code;
-}
-
-int hip_fail(ctrex_ctx *c, hipError_t e, const char *what) {
-    return fail(c, CTREX_EDEVICE, "%s: %s", what, hipGetErrorString(e));
-}
-
-#define CTREX_HIP(ctx, expr)                                   \
-    do {                                                       \
-        hipError_t e_ = (expr);                                \
-        if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr); \
-    } while (0)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -155,6 +91,25 @@ int resolve_views(ctrex_ctx *c, const int32_t *views, int32_t n_views, const int
     *dev = c->lists.front().dev;
     return CTREX_OK;
 }
+
+}  // namespace
+
+int ctrex::ctx_scratch(ctrex_ctx *c, size_t bytes, void **out) {
+    if (bytes > c->scratch_cap) {
+        if (c->d_scratch) {
+            CTREX_HIP(c, hipDeviceSynchronize());
+            CTREX_HIP(c, hipFree(c->d_scratch));
+            c->d_scratch = nullptr;
+            c->scratch_cap = 0;
+        }
+        CTREX_HIP(c, hipMalloc(&c->d_scratch, bytes));
+        c->scratch_cap = bytes;
+    }
+    *out = c->d_scratch;
+    return CTREX_OK;
+}
+
+namespace {
 
 // Grow the context's backprojection slab buffer to what `g` needs.  The
 // device is synchronised before an old buffer is released.
@@ -326,6 +281,7 @@ void ctrex_destroy(ctrex_ctx *c) {
     if (c->d_scalar) (void)hipFree(c->d_scalar);
     if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_red) (void)hipFree(c->d_red);
+    if (c->d_scratch) (void)hipFree(c->d_scratch);
     for (auto &l : c->lists) (void)hipFree(l.dev);
     delete c;
 }

@@ -1,0 +1,87 @@
+// Context of the C ABI, shared by the runtime translation units.
+#pragma once
+
+#include <cstdarg>
+#include <cstdio>
+#include <list>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "ctrex_internal.h"
+
+namespace ctrex {
+
+struct DeviceViewList {
+    std::vector<int32_t> host;
+    int32_t *dev = nullptr;
+};
+
+}  // namespace ctrex
+
+struct ctrex_ctx {
+    int device = 0;
+    std::string err;
+    // geometry
+    bool have_geom = false;
+    int n_proj = 0, n_sub = 0, n_u = 0, n_v = 0, nx = 0, ny = 0, nz = 0;
+    double step = 0.0;
+    std::vector<ctrex::SubView> tab;
+    ctrex::SubView *d_tab = nullptr;
+    double *d_P = nullptr;    // view matrices [n_proj * n_sub][12]
+    size_t P_cap = 0;
+    uint64_t generation = 0;  // bumps on geometry or motion change
+    // motion
+    float4 *d_U = nullptr;
+    int gx = 0, gy = 0, gz = 0;
+    int warp_margin = 0;  // ceil(max |tau| * max |U component|)
+    // cached device view lists (most recent first)
+    std::list<ctrex::DeviceViewList> lists;
+    // small device scratch
+    unsigned long long *d_count = nullptr;
+    float *d_scalar = nullptr;  // max |r| of the backprojector's input
+    float *d_part = nullptr;    // per-chunk backprojection slabs (small volumes)
+    double *d_red = nullptr;    // 8192 block partials + 1 result (TV value)
+    void *d_scratch = nullptr;  // general scratch (learned-correction kernels)
+    size_t scratch_cap = 0;
+    size_t part_cap = 0;
+    // SIRT weight cache key
+    const void *w_ws = nullptr;
+    uint64_t w_gen = 0;
+    std::vector<int32_t> w_views;
+    bool w_all = false;
+    bool w_valid = false;
+    // kernel timing (ctrex_profile_enable)
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_marks;
+};
+
+
+namespace ctrex {
+
+inline int fail(ctrex_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+inline int hip_fail(ctrex_ctx *c, hipError_t e, const char *what) {
+    return fail(c, CTREX_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Grow the context's general scratch buffer to `bytes` (synchronises the
+// device when an old buffer has to be released).
+int ctx_scratch(ctrex_ctx *c, size_t bytes, void **out);
+
+}  // namespace ctrex
+
+#define CTREX_HIP(ctx, expr)                                               \
+    do {                                                                   \
+        hipError_t e_ = (expr);                                            \
+        if (e_ != hipSuccess) return ::ctrex::hip_fail((ctx), e_, #expr);  \
+    } while (0)

@@ -1,0 +1,917 @@
+// 3D U-Net kernels for the learned correction between SIRT iterations.
+//
+// Convolutions are implicit GEMMs on the gfx950 matrix cores
+// (v_mfma_f32_16x16x32_bf16: A 16x32, B 32x16, FP32 accumulate).  Lane layout
+// of that instruction: lane l holds A[l % 16][8 (l / 16) .. +8] and
+// B[8 (l / 16) .. +8][l % 16], and receives C[4 (l / 16) + j][l % 16], j < 4.
+// Activations are channels-last BF16, so the 8 consecutive K values a lane
+// needs (8 channels of one voxel and tap) are one 16-byte load; weights are
+// packed [tap][cout][cin] for the same reason.
+//
+//  * conv3_fwd: M = voxels (64 per wave), N = cout, K = 27 taps x cin.  The
+//    data gradient is the same kernel with mirrored taps and swapped channels.
+//  * conv3_wgrad: M = cout, N = cin, K = voxels, one tap per wave, partial
+//    sums per chunk of voxels combined in a fixed order.
+//  * upconv2_*: the 2x2x2 stride-2 transposed convolution as GEMMs over its 8
+//    sub-positions.
+//  * pooling, ReLU backward, head, loss, Adam and packing are elementwise.
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ctrex_internal.h"
+
+namespace ctrex {
+namespace nn {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16;
+
+constexpr int NT = 256;   // threads per workgroup (4 waves)
+constexpr int MB = 4;     // 16-voxel M blocks per wave (64 voxels)
+
+__device__ __forceinline__ float bf2f(u16 v) { return __uint_as_float(static_cast<uint32_t>(v) << 16); }
+__device__ __forceinline__ u16 f2bf(float v) {
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<u16>((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<u16>(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 load8(const u16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
+__device__ __forceinline__ bf16x8 zero8() {
+    bf16x8 z;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) z[e] = static_cast<__bf16>(0.0f);
+    return z;
+}
+__device__ __forceinline__ __bf16 as_bf(u16 v) { return __builtin_bit_cast(__bf16, v); }
+
+__device__ __forceinline__ f32x4 mma(const bf16x8 &a, const bf16x8 &b, const f32x4 &c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+struct Vox {
+    int z, y, x;
+};
+
+__device__ __forceinline__ Vox decode(long long v, int H, int W) {
+    Vox r;
+    r.x = static_cast<int>(v % W);
+    const long long t = v / W;
+    r.y = static_cast<int>(t % H);
+    r.z = static_cast<int>(t / H);
+    return r;
+}
+
+// Neighbour (voxel + tap offset) index or -1 outside the volume.
+__device__ __forceinline__ long long nbr(const Vox &p, int tap, int D, int H, int W) {
+    const int z = p.z + tap / 9 - 1, y = p.y + (tap / 3) % 3 - 1, x = p.x + tap % 3 - 1;
+    if (z < 0 || z >= D || y < 0 || y >= H || x < 0 || x >= W) return -1;
+    return (static_cast<long long>(z) * H + y) * W + x;
+}
+
+template <bool OUT_F32, bool RELU, bool ACC>
+__device__ __forceinline__ void store_out(void *out, long long idx, float val) {
+    if (RELU) val = fmaxf(val, 0.0f);
+    if (OUT_F32) {
+        float *o = static_cast<float *>(out) + idx;
+        *o = ACC ? *o + val : val;
+    } else {
+        u16 *o = static_cast<u16 *>(out) + idx;
+        *o = ACC ? f2bf(bf2f(*o) + val) : f2bf(val);
+    }
+}
+
+// ------------------------------------------------------------ conv 3x3x3 ----
+template <int CIN, int COUT, bool OUT_F32, bool RELU, bool ACC>
+__global__ __launch_bounds__(NT) void conv3_fwd_kernel(const u16 *__restrict__ in, int in_cs,
+                                                       int in_off, const u16 *__restrict__ wt,
+                                                       const float *__restrict__ bias, void *out,
+                                                       int out_cs, int out_off, int D, int H, int W) {
+    constexpr int NB = COUT / 16;
+    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    const long long nvox = static_cast<long long>(D) * H * W;
+    const long long base = (static_cast<long long>(blockIdx.x) * (NT / 64) + (threadIdx.x >> 6)) * 64;
+    if (base >= nvox) return;   // whole wave
+    Vox pa[MB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) pa[m] = decode(base + m * 16 + r, H, W);
+    f32x4 acc[MB][NB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    if constexpr (CIN == 1) {
+        // one K step: k = 8 g + e is the tap
+        bf16x8 a[MB], b[NB];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int tap = 8 * g + e;
+#pragma unroll
+            for (int m = 0; m < MB; ++m) {
+                const long long q = tap < 27 ? nbr(pa[m], tap, D, H, W) : -1;
+                a[m][e] = q >= 0 ? as_bf(in[q * in_cs + in_off]) : static_cast<__bf16>(0.0f);
+            }
+#pragma unroll
+            for (int n = 0; n < NB; ++n)
+                b[n][e] = tap < 27 ? as_bf(wt[tap * COUT + n * 16 + r]) : static_cast<__bf16>(0.0f);
+        }
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int n = 0; n < NB; ++n) acc[m][n] = mma(a[m], b[n], acc[m][n]);
+    } else if constexpr (CIN == 16) {
+        // K steps over pairs of taps: lanes g = 0, 1 take tap 2p, g = 2, 3 tap 2p + 1
+        for (int p = 0; p < 14; ++p) {
+            const int tap = 2 * p + (g >> 1);
+            const int ch = 8 * (g & 1);
+            bf16x8 a[MB], b[NB];
+#pragma unroll
+            for (int m = 0; m < MB; ++m) {
+                const long long q = tap < 27 ? nbr(pa[m], tap, D, H, W) : -1;
+                a[m] = q >= 0 ? load8(in + q * in_cs + in_off + ch) : zero8();
+            }
+#pragma unroll
+            for (int n = 0; n < NB; ++n)
+                b[n] = tap < 27 ? load8(wt + (tap * COUT + n * 16 + r) * CIN + ch) : zero8();
+#pragma unroll
+            for (int m = 0; m < MB; ++m)
+#pragma unroll
+                for (int n = 0; n < NB; ++n) acc[m][n] = mma(a[m], b[n], acc[m][n]);
+        }
+    } else {
+        for (int tap = 0; tap < 27; ++tap) {
+            long long q[MB];
+#pragma unroll
+            for (int m = 0; m < MB; ++m) q[m] = nbr(pa[m], tap, D, H, W);
+#pragma unroll
+            for (int ks = 0; ks < CIN / 32; ++ks) {
+                const int ch = ks * 32 + 8 * g;
+                bf16x8 a[MB], b[NB];
+#pragma unroll
+                for (int m = 0; m < MB; ++m)
+                    a[m] = q[m] >= 0 ? load8(in + q[m] * in_cs + in_off + ch) : zero8();
+#pragma unroll
+                for (int n = 0; n < NB; ++n) b[n] = load8(wt + (tap * COUT + n * 16 + r) * CIN + ch);
+#pragma unroll
+                for (int m = 0; m < MB; ++m)
+#pragma unroll
+                    for (int n = 0; n < NB; ++n) acc[m][n] = mma(a[m], b[n], acc[m][n]);
+            }
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+        const int co = n * 16 + r;
+        const float bco = bias ? bias[co] : 0.0f;
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const long long v = base + m * 16 + 4 * g + j;
+                store_out<OUT_F32, RELU, ACC>(out, v * out_cs + out_off + co, acc[m][n][j] + bco);
+            }
+    }
+}
+
+// Weight gradient, cin >= 16: wave = one tap; block = (voxel chunk, 4 taps).
+template <int CIN, int COUT>
+__global__ __launch_bounds__(NT) void conv3_wgrad_kernel(const u16 *__restrict__ in, int in_cs,
+                                                         int in_off, const u16 *__restrict__ dout,
+                                                         int dout_cs, int dout_off, int D, int H,
+                                                         int W, long long chunk,
+                                                         float *__restrict__ partial) {
+    constexpr int MBk = COUT / 16, NBk = CIN / 16;
+    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    const int tap = blockIdx.y * (NT / 64) + (threadIdx.x >> 6);
+    if (tap >= 27) return;
+    const long long nvox = static_cast<long long>(D) * H * W;
+    const long long v0 = static_cast<long long>(blockIdx.x) * chunk;
+    const long long v1 = v0 + chunk < nvox ? v0 + chunk : nvox;
+    f32x4 acc[MBk][NBk];
+#pragma unroll
+    for (int m = 0; m < MBk; ++m)
+#pragma unroll
+        for (int n = 0; n < NBk; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (long long vk = v0; vk < v1; vk += 32) {
+        bf16x8 a[MBk], b[NBk];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const long long v = vk + 8 * g + e;
+            const bool ok = v < v1;
+            const long long q = ok ? nbr(decode(v, H, W), tap, D, H, W) : -1;
+#pragma unroll
+            for (int m = 0; m < MBk; ++m)
+                a[m][e] = ok ? as_bf(dout[v * dout_cs + dout_off + m * 16 + r])
+                             : static_cast<__bf16>(0.0f);
+#pragma unroll
+            for (int n = 0; n < NBk; ++n)
+                b[n][e] = q >= 0 ? as_bf(in[q * in_cs + in_off + n * 16 + r])
+                                 : static_cast<__bf16>(0.0f);
+        }
+#pragma unroll
+        for (int m = 0; m < MBk; ++m)
+#pragma unroll
+            for (int n = 0; n < NBk; ++n) acc[m][n] = mma(a[m], b[n], acc[m][n]);
+    }
+    float *dst = partial + (static_cast<long long>(blockIdx.x) * 27 + tap) * COUT * CIN;
+#pragma unroll
+    for (int m = 0; m < MBk; ++m)
+#pragma unroll
+        for (int n = 0; n < NBk; ++n)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) dst[(m * 16 + 4 * g + j) * CIN + n * 16 + r] = acc[m][n][j];
+}
+
+// Weight gradient, cin == 1: N = taps (27 padded to 32), one wave per chunk.
+template <int COUT>
+__global__ __launch_bounds__(64) void conv3_wgrad_c1_kernel(const u16 *__restrict__ in, int in_cs,
+                                                            int in_off,
+                                                            const u16 *__restrict__ dout,
+                                                            int dout_cs, int dout_off, int D, int H,
+                                                            int W, long long chunk,
+                                                            float *__restrict__ partial) {
+    constexpr int MBk = COUT / 16;
+    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    const long long nvox = static_cast<long long>(D) * H * W;
+    const long long v0 = static_cast<long long>(blockIdx.x) * chunk;
+    const long long v1 = v0 + chunk < nvox ? v0 + chunk : nvox;
+    f32x4 acc[MBk][2];
+#pragma unroll
+    for (int m = 0; m < MBk; ++m) acc[m][0] = acc[m][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (long long vk = v0; vk < v1; vk += 32) {
+        bf16x8 a[MBk], b[2];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const long long v = vk + 8 * g + e;
+            const bool ok = v < v1;
+            const Vox p = decode(ok ? v : 0, H, W);
+#pragma unroll
+            for (int m = 0; m < MBk; ++m)
+                a[m][e] = ok ? as_bf(dout[v * dout_cs + dout_off + m * 16 + r])
+                             : static_cast<__bf16>(0.0f);
+#pragma unroll
+            for (int n = 0; n < 2; ++n) {
+                const int tap = n * 16 + r;
+                const long long q = ok && tap < 27 ? nbr(p, tap, D, H, W) : -1;
+                b[n][e] = q >= 0 ? as_bf(in[q * in_cs + in_off]) : static_cast<__bf16>(0.0f);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < MBk; ++m)
+#pragma unroll
+            for (int n = 0; n < 2; ++n) acc[m][n] = mma(a[m], b[n], acc[m][n]);
+    }
+    // partial layout [chunk][27][COUT][1]
+    float *dst = partial + static_cast<long long>(blockIdx.x) * 27 * COUT;
+#pragma unroll
+    for (int m = 0; m < MBk; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int tap = n * 16 + r;
+                if (tap < 27) dst[tap * COUT + m * 16 + 4 * g + j] = acc[m][n][j];
+            }
+}
+
+// dw[co][ci][tap] = sum over chunks of partial[c][tap][co][ci] (FP64, fixed order).
+__global__ __launch_bounds__(NT) void reduce_wgrad_kernel(const float *__restrict__ partial,
+                                                          int chunks, int taps, int cout, int cin,
+                                                          int tap_major_out,
+                                                          float *__restrict__ dw) {
+    const int n = taps * cout * cin;
+    const int i = blockIdx.x * NT + threadIdx.x;
+    if (i >= n) return;
+    // i enumerates the partial's [tap][co][ci] order
+    double s = 0.0;
+    for (int c = 0; c < chunks; ++c) s += static_cast<double>(partial[static_cast<long long>(c) * n + i]);
+    const int tap = i / (cout * cin);
+    const int rem = i - tap * cout * cin;
+    const int co = rem / cin, ci = rem - co * cin;
+    // conv3: master order [co][ci][tap]; upconv: [ci][co][tap]
+    const int o = tap_major_out ? (ci * cout + co) * taps + tap : (co * cin + ci) * taps + tap;
+    dw[o] = static_cast<float>(s);
+}
+
+// Per-channel sums over voxels: partial[block][c].
+__global__ __launch_bounds__(NT) void channel_sum_kernel(const u16 *__restrict__ x, int cs, int off,
+                                                         int c, long long nvox,
+                                                         double *__restrict__ partial) {
+    // thread t of the block handles channel t % c over voxels strided by NT / c
+    __shared__ double red[NT];
+    const int per = NT / c;   // c divides NT (16, 32, 64)
+    const int ch = threadIdx.x % c, lane_v = threadIdx.x / c;
+    double s = 0.0;
+    const long long stride = static_cast<long long>(gridDim.x) * per;
+    for (long long v = static_cast<long long>(blockIdx.x) * per + lane_v; v < nvox; v += stride)
+        s += static_cast<double>(bf2f(x[v * cs + off + ch]));
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < c) {
+        double t = 0.0;
+        for (int k = 0; k < per; ++k) t += red[k * c + threadIdx.x];
+        partial[static_cast<long long>(blockIdx.x) * c + threadIdx.x] = t;
+    }
+}
+
+// out[j] = sum_i partial[i * ld + j] for j < cols (FP64, fixed order).
+__global__ __launch_bounds__(64) void reduce_rows_kernel(const double *__restrict__ partial,
+                                                         int rows, int cols, int ld,
+                                                         float *__restrict__ out) {
+    const int j = blockIdx.x * 64 + threadIdx.x;
+    if (j >= cols) return;
+    double s = 0.0;
+    for (int i = 0; i < rows; ++i) s += partial[static_cast<long long>(i) * ld + j];
+    out[j] = static_cast<float>(s);
+}
+
+// ------------------------------------------------------ 2x transposed conv --
+template <int CIN, int COUT, bool OUT_F32, bool ACC>
+__global__ __launch_bounds__(NT) void upconv2_fwd_kernel(const u16 *__restrict__ in, int in_cs,
+                                                         int in_off, const u16 *__restrict__ wt,
+                                                         const float *__restrict__ bias, void *out,
+                                                         int out_cs, int out_off, int D, int H,
+                                                         int W) {
+    constexpr int NB = COUT / 16;
+    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    const long long nvox = static_cast<long long>(D) * H * W;
+    const long long base = (static_cast<long long>(blockIdx.x) * (NT / 64) + (threadIdx.x >> 6)) * 64;
+    if (base >= nvox) return;
+    const int H2 = 2 * H, W2 = 2 * W;
+    for (int a = 0; a < 8; ++a) {
+        f32x4 acc[MB][NB];
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < CIN / 32; ++ks) {
+            const int ch = ks * 32 + 8 * g;
+            bf16x8 av[MB], bv[NB];
+#pragma unroll
+            for (int m = 0; m < MB; ++m) av[m] = load8(in + (base + m * 16 + r) * in_cs + in_off + ch);
+#pragma unroll
+            for (int n = 0; n < NB; ++n) bv[n] = load8(wt + (a * COUT + n * 16 + r) * CIN + ch);
+#pragma unroll
+            for (int m = 0; m < MB; ++m)
+#pragma unroll
+                for (int n = 0; n < NB; ++n) acc[m][n] = mma(av[m], bv[n], acc[m][n]);
+        }
+        const int az = a >> 2, ay = (a >> 1) & 1, ax = a & 1;
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+            const int co = n * 16 + r;
+            const float bco = bias ? bias[co] : 0.0f;
+#pragma unroll
+            for (int m = 0; m < MB; ++m)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const Vox p = decode(base + m * 16 + 4 * g + j, H, W);
+                    const long long o =
+                        ((static_cast<long long>(2 * p.z + az) * H2) + (2 * p.y + ay)) * W2 +
+                        (2 * p.x + ax);
+                    store_out<OUT_F32, false, ACC>(out, o * out_cs + out_off + co, acc[m][n][j] + bco);
+                }
+        }
+    }
+}
+
+// din[i][ci] = sum_a sum_co dout[2i + a][co] wd[a][ci][co]; K = 8 COUT.
+template <int CIN, int COUT, bool ACC>
+__global__ __launch_bounds__(NT) void upconv2_dgrad_kernel(const u16 *__restrict__ dout, int dout_cs,
+                                                           int dout_off, const u16 *__restrict__ wd,
+                                                           u16 *__restrict__ din, int din_cs,
+                                                           int din_off, int D, int H, int W) {
+    constexpr int NB = CIN / 16;
+    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    const long long nvox = static_cast<long long>(D) * H * W;
+    const long long base = (static_cast<long long>(blockIdx.x) * (NT / 64) + (threadIdx.x >> 6)) * 64;
+    if (base >= nvox) return;
+    const int H2 = 2 * H, W2 = 2 * W;
+    Vox pa[MB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) pa[m] = decode(base + m * 16 + r, H, W);
+    f32x4 acc[MB][NB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < (8 * COUT) / 32; ++s) {
+        const int k0 = s * 32 + 8 * g;
+        const int a = k0 / COUT, co = k0 % COUT;
+        const int az = a >> 2, ay = (a >> 1) & 1, ax = a & 1;
+        bf16x8 av[MB], bv[NB];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            const long long o = ((static_cast<long long>(2 * pa[m].z + az) * H2) + (2 * pa[m].y + ay)) * W2 +
+                                (2 * pa[m].x + ax);
+            av[m] = load8(dout + o * dout_cs + dout_off + co);
+        }
+#pragma unroll
+        for (int n = 0; n < NB; ++n) bv[n] = load8(wd + (a * CIN + n * 16 + r) * COUT + co);
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int n = 0; n < NB; ++n) acc[m][n] = mma(av[m], bv[n], acc[m][n]);
+    }
+#pragma unroll
+    for (int n = 0; n < NB; ++n)
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const long long v = base + m * 16 + 4 * g + j;
+                store_out<false, false, ACC>(din, v * din_cs + din_off + n * 16 + r, acc[m][n][j]);
+            }
+}
+
+// dw partial[c][a][co][ci] = sum over the chunk of dout[2i + a][co] in[i][ci]; wave = a.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(NT) void upconv2_wgrad_kernel(const u16 *__restrict__ in, int in_cs,
+                                                           int in_off, const u16 *__restrict__ dout,
+                                                           int dout_cs, int dout_off, int D, int H,
+                                                           int W, long long chunk,
+                                                           float *__restrict__ partial) {
+    constexpr int MBk = COUT / 16, NBk = CIN / 16;
+    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    const int a = blockIdx.y * (NT / 64) + (threadIdx.x >> 6);   // 0..7
+    const int az = a >> 2, ay = (a >> 1) & 1, ax = a & 1;
+    const int H2 = 2 * H, W2 = 2 * W;
+    const long long nvox = static_cast<long long>(D) * H * W;
+    const long long v0 = static_cast<long long>(blockIdx.x) * chunk;
+    const long long v1 = v0 + chunk < nvox ? v0 + chunk : nvox;
+    f32x4 acc[MBk][NBk];
+#pragma unroll
+    for (int m = 0; m < MBk; ++m)
+#pragma unroll
+        for (int n = 0; n < NBk; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (long long vk = v0; vk < v1; vk += 32) {
+        bf16x8 av[MBk], bv[NBk];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const long long v = vk + 8 * g + e;
+            const bool ok = v < v1;
+            const Vox p = decode(ok ? v : 0, H, W);
+            const long long o = ((static_cast<long long>(2 * p.z + az) * H2) + (2 * p.y + ay)) * W2 +
+                                (2 * p.x + ax);
+#pragma unroll
+            for (int m = 0; m < MBk; ++m)
+                av[m][e] = ok ? as_bf(dout[o * dout_cs + dout_off + m * 16 + r])
+                              : static_cast<__bf16>(0.0f);
+#pragma unroll
+            for (int n = 0; n < NBk; ++n)
+                bv[n][e] = ok ? as_bf(in[v * in_cs + in_off + n * 16 + r]) : static_cast<__bf16>(0.0f);
+        }
+#pragma unroll
+        for (int m = 0; m < MBk; ++m)
+#pragma unroll
+            for (int n = 0; n < NBk; ++n) acc[m][n] = mma(av[m], bv[n], acc[m][n]);
+    }
+    float *dst = partial + (static_cast<long long>(blockIdx.x) * 8 + a) * COUT * CIN;
+#pragma unroll
+    for (int m = 0; m < MBk; ++m)
+#pragma unroll
+        for (int n = 0; n < NBk; ++n)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) dst[(m * 16 + 4 * g + j) * CIN + n * 16 + r] = acc[m][n][j];
+}
+
+// ---------------------------------------------------------- elementwise ----
+__global__ __launch_bounds__(NT) void maxpool2_kernel(const u16 *__restrict__ in, int in_cs, int in_off,
+                                                      int c, u16 *__restrict__ out, int D, int H,
+                                                      int W) {
+    const int Do = D / 2, Ho = H / 2, Wo = W / 2;
+    const long long n = static_cast<long long>(Do) * Ho * Wo * c;
+    const long long i = static_cast<long long>(blockIdx.x) * NT + threadIdx.x;
+    if (i >= n) return;
+    const int ch = static_cast<int>(i % c);
+    const Vox p = decode(i / c, Ho, Wo);
+    float m = -__builtin_inff();
+    for (int a = 0; a < 8; ++a) {
+        const long long q = (static_cast<long long>(2 * p.z + (a >> 2)) * H + 2 * p.y + ((a >> 1) & 1)) * W +
+                            2 * p.x + (a & 1);
+        m = fmaxf(m, bf2f(in[q * in_cs + in_off + ch]));
+    }
+    out[i] = f2bf(m);
+}
+
+__global__ __launch_bounds__(NT) void maxpool2_bwd_kernel(const u16 *__restrict__ in, int in_cs,
+                                                          int in_off, int c,
+                                                          const u16 *__restrict__ dout,
+                                                          u16 *__restrict__ din, int D, int H, int W) {
+    const int Do = D / 2, Ho = H / 2, Wo = W / 2;
+    const long long n = static_cast<long long>(Do) * Ho * Wo * c;
+    const long long i = static_cast<long long>(blockIdx.x) * NT + threadIdx.x;
+    if (i >= n) return;
+    const int ch = static_cast<int>(i % c);
+    const Vox p = decode(i / c, Ho, Wo);
+    float m = -__builtin_inff();
+    long long best = -1;
+    for (int a = 0; a < 8; ++a) {
+        const long long q = (static_cast<long long>(2 * p.z + (a >> 2)) * H + 2 * p.y + ((a >> 1) & 1)) * W +
+                            2 * p.x + (a & 1);
+        const float v = bf2f(in[q * in_cs + in_off + ch]);
+        if (v > m || best < 0) {
+            m = v;
+            best = q;
+        }
+    }
+    u16 *o = din + best * in_cs + in_off + ch;
+    *o = f2bf(bf2f(*o) + bf2f(dout[i]));
+}
+
+__global__ __launch_bounds__(NT) void relu_bwd_kernel(const u16 *__restrict__ y, u16 *__restrict__ gr,
+                                                      int cs, int off, int c, long long nvox) {
+    const long long i = static_cast<long long>(blockIdx.x) * NT + threadIdx.x;
+    if (i >= nvox * c) return;
+    const long long idx = (i / c) * cs + off + i % c;
+    if (!(bf2f(y[idx]) > 0.0f)) gr[idx] = 0;
+}
+
+__global__ __launch_bounds__(NT) void head_kernel(const u16 *__restrict__ act, int c,
+                                                  const float *__restrict__ h, const float *__restrict__ b,
+                                                  const float *__restrict__ x, float *__restrict__ out,
+                                                  long long n) {
+    const long long v = static_cast<long long>(blockIdx.x) * NT + threadIdx.x;
+    if (v >= n) return;
+    float s = b[0];
+    for (int k = 0; k < c; ++k) s = fmaf(h[k], bf2f(act[v * c + k]), s);
+    out[v] = x[v] + s;
+}
+
+// dact = dout h; per-block partial sums of dout * act[:, k] (k < C) and dout.
+template <int C>
+__global__ __launch_bounds__(NT) void head_bwd_kernel(const u16 *__restrict__ act,
+                                                      const float *__restrict__ h,
+                                                      const float *__restrict__ dout,
+                                                      u16 *__restrict__ dact, long long n,
+                                                      double *__restrict__ partial) {
+    __shared__ double red[NT];
+    double acc[C + 1];
+#pragma unroll
+    for (int k = 0; k <= C; ++k) acc[k] = 0.0;
+    const long long stride = static_cast<long long>(gridDim.x) * NT;
+    for (long long v = static_cast<long long>(blockIdx.x) * NT + threadIdx.x; v < n; v += stride) {
+        const float d = dout[v];
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            acc[k] += static_cast<double>(d) * bf2f(act[v * C + k]);
+            dact[v * C + k] = f2bf(d * h[k]);
+        }
+        acc[C] += d;
+    }
+#pragma unroll
+    for (int k = 0; k <= C; ++k) {
+        red[threadIdx.x] = acc[k];
+        __syncthreads();
+        for (int s2 = NT / 2; s2 > 0; s2 >>= 1) {
+            if (static_cast<int>(threadIdx.x) < s2) red[threadIdx.x] += red[threadIdx.x + s2];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[static_cast<long long>(blockIdx.x) * (C + 1) + k] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(NT) void mse_kernel(const float *__restrict__ a, const float *__restrict__ t,
+                                                 long long n, float scale, float *__restrict__ grad,
+                                                 double *__restrict__ partial) {
+    __shared__ double red[NT];
+    double s = 0.0;
+    const long long stride = static_cast<long long>(gridDim.x) * NT;
+    for (long long i = static_cast<long long>(blockIdx.x) * NT + threadIdx.x; i < n; i += stride) {
+        const float d = a[i] - t[i];
+        s += static_cast<double>(d) * d;
+        if (grad) grad[i] = scale * d;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = NT / 2; k > 0; k >>= 1) {
+        if (static_cast<int>(threadIdx.x) < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(NT) void adam_kernel(float *__restrict__ p, const float *__restrict__ gr,
+                                                  float *__restrict__ m, float *__restrict__ v,
+                                                  long long n, float lr, float b1, float b2, float eps,
+                                                  float c1, float c2) {
+    const long long i = static_cast<long long>(blockIdx.x) * NT + threadIdx.x;
+    if (i >= n) return;
+    const float gv = gr[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gv;
+    const float vi = b2 * v[i] + (1.0f - b2) * gv * gv;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// w [cout][cin][taps] -> wt [tap][cout][cin] and wt_d [taps-1-tap][cin][cout] (mirrored)
+__global__ __launch_bounds__(NT) void pack_kernel(const float *__restrict__ w, int cout, int cin,
+                                                  int taps, int mirror, u16 *__restrict__ wt,
+                                                  u16 *__restrict__ wt_d, int in_major) {
+    const int n = cout * cin * taps;
+    const int i = blockIdx.x * NT + threadIdx.x;
+    if (i >= n) return;
+    int co, ci, t;
+    if (in_major) {   // upconv master [cin][cout][taps]
+        ci = i / (cout * taps);
+        const int rem = i - ci * cout * taps;
+        co = rem / taps;
+        t = rem - co * taps;
+    } else {          // conv master [cout][cin][taps]
+        co = i / (cin * taps);
+        const int rem = i - co * cin * taps;
+        ci = rem / taps;
+        t = rem - ci * taps;
+    }
+    const u16 b = f2bf(w[i]);
+    if (wt) wt[(t * cout + co) * cin + ci] = b;
+    if (wt_d) {
+        const int td = mirror ? taps - 1 - t : t;
+        wt_d[(td * cin + ci) * cout + co] = b;
+    }
+}
+
+inline unsigned blocks_for(long long n, int per = NT) {
+    return static_cast<unsigned>((n + per - 1) / per);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers --
+template <int CI, int CO, bool F32, bool RELU, bool ACC>
+void conv3_go(dim3 grid, dim3 blk, hipStream_t s, const u16 *ip, int in_cs, int in_off,
+              const u16 *wp, const float *bias, void *out, int out_cs, int out_off, int D, int H,
+              int W) {
+    hipLaunchKernelGGL((conv3_fwd_kernel<CI, CO, F32, RELU, ACC>), grid, blk, 0, s, ip, in_cs,
+                       in_off, wp, bias, out, out_cs, out_off, D, H, W);
+}
+
+template <int CI, int CO>
+void conv3_pick(bool relu, bool acc, bool f32, dim3 grid, dim3 blk, hipStream_t s, const u16 *ip,
+                int in_cs, int in_off, const u16 *wp, const float *bias, void *out, int out_cs,
+                int out_off, int D, int H, int W) {
+    const int k = (f32 ? 4 : 0) | (relu ? 2 : 0) | (acc ? 1 : 0);
+#define GO(F, R, A) conv3_go<CI, CO, F, R, A>(grid, blk, s, ip, in_cs, in_off, wp, bias, out, out_cs, out_off, D, H, W)
+    switch (k) {
+        case 0: GO(false, false, false); break;
+        case 1: GO(false, false, true); break;
+        case 2: GO(false, true, false); break;
+        case 3: GO(false, true, true); break;
+        case 4: GO(true, false, false); break;
+        case 5: GO(true, false, true); break;
+        case 6: GO(true, true, false); break;
+        default: GO(true, true, true); break;
+    }
+#undef GO
+}
+
+hipError_t launch_conv3(const void *in, int in_cs, int in_off, int cin, const void *wt,
+                        const float *bias, void *out, int out_cs, int out_off, int cout, int D,
+                        int H, int W, bool relu, bool acc, bool out_f32, hipStream_t s) {
+    const long long nvox = static_cast<long long>(D) * H * W;
+    const dim3 grid(blocks_for(nvox, NT)), blk(NT);
+    const u16 *ip = static_cast<const u16 *>(in);
+    const u16 *wp = static_cast<const u16 *>(wt);
+#define CASE(CI, CO)                                                                             \
+    if (cin == CI && cout == CO) {                                                               \
+        conv3_pick<CI, CO>(relu, acc, out_f32, grid, blk, s, ip, in_cs, in_off, wp, bias, out,   \
+                           out_cs, out_off, D, H, W);                                            \
+        return hipGetLastError();                                                                \
+    }
+    CASE(1, 16)
+    CASE(16, 16)
+    CASE(16, 32)
+    CASE(32, 16)
+    CASE(32, 32)
+    CASE(32, 64)
+    CASE(64, 32)
+    CASE(64, 64)
+#undef CASE
+    return hipErrorInvalidValue;
+}
+
+long long wgrad_chunk(long long nvox) {
+    // about 2048 chunks on large volumes, at least 512 voxels each
+    long long chunk = (nvox + 2047) / 2048;
+    chunk = (chunk + 31) / 32 * 32;
+    return chunk < 512 ? 512 : chunk;
+}
+
+size_t conv3_wgrad_scratch(int cin, int cout, long long nvox) {
+    const long long chunks = (nvox + wgrad_chunk(nvox) - 1) / wgrad_chunk(nvox);
+    return sizeof(float) * static_cast<size_t>(chunks) * 27 * cin * cout;
+}
+
+hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin, const void *dout,
+                              int dout_cs, int dout_off, int cout, int D, int H, int W, float *dw,
+                              float *scratch, hipStream_t s) {
+    const long long nvox = static_cast<long long>(D) * H * W;
+    const long long chunk = wgrad_chunk(nvox);
+    const int chunks = static_cast<int>((nvox + chunk - 1) / chunk);
+    const u16 *ip = static_cast<const u16 *>(in), *dp = static_cast<const u16 *>(dout);
+    bool done = false;
+    if (cin == 1) {
+        if (cout == 16) {
+            hipLaunchKernelGGL((conv3_wgrad_c1_kernel<16>), dim3(chunks), dim3(64), 0, s, ip, in_cs,
+                               in_off, dp, dout_cs, dout_off, D, H, W, chunk, scratch);
+            done = true;
+        }
+    }
+#define CTREX_NN_WG(CI, CO)                                                                         \
+    if (!done && cin == CI && cout == CO) {                                                          \
+        hipLaunchKernelGGL((conv3_wgrad_kernel<CI, CO>), dim3(chunks, 7), dim3(NT), 0, s, ip, in_cs, \
+                           in_off, dp, dout_cs, dout_off, D, H, W, chunk, scratch);                  \
+        done = true;                                                                                 \
+    }
+    CTREX_NN_WG(16, 16)
+    CTREX_NN_WG(16, 32)
+    CTREX_NN_WG(32, 16)
+    CTREX_NN_WG(32, 32)
+    CTREX_NN_WG(32, 64)
+    CTREX_NN_WG(64, 32)
+    CTREX_NN_WG(64, 64)
+#undef CTREX_NN_WG
+    if (!done) return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int n = 27 * cout * cin;
+    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(n)), dim3(NT), 0, s, scratch, chunks, 27,
+                       cout, cin, 0, dw);
+    return hipGetLastError();
+}
+
+size_t channel_sum_scratch(int c) { return sizeof(double) * 1024 * static_cast<size_t>(c); }
+
+hipError_t launch_channel_sum(const void *x, int cs, int off, int c, long long nvox, float *out,
+                              double *scratch, hipStream_t s) {
+    const int blocks = 1024;
+    hipLaunchKernelGGL(channel_sum_kernel, dim3(blocks), dim3(NT), 0, s, static_cast<const u16 *>(x),
+                       cs, off, c, nvox, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(blocks_for(c, 64)), dim3(64), 0, s, scratch, blocks, c,
+                       c, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_upconv2(const void *in, int in_cs, int in_off, int cin, const void *wt,
+                          const float *bias, void *out, int out_cs, int out_off, int cout, int D,
+                          int H, int W, bool acc, bool out_f32, hipStream_t s) {
+    const long long nvox = static_cast<long long>(D) * H * W;
+    const dim3 grid(blocks_for(nvox, NT)), blk(NT);
+    const u16 *ip = static_cast<const u16 *>(in), *wp = static_cast<const u16 *>(wt);
+#define CTREX_NN_UP(CI, CO)                                                                           \
+    if (cin == CI && cout == CO) {                                                                    \
+        if (out_f32) {                                                                                \
+            if (acc) { hipLaunchKernelGGL((upconv2_fwd_kernel<CI, CO, true, true>), grid, blk, 0, s, ip, in_cs, in_off, wp, bias, out, out_cs, out_off, D, H, W); } \
+                else { hipLaunchKernelGGL((upconv2_fwd_kernel<CI, CO, true, false>), grid, blk, 0, s, ip, in_cs, in_off, wp, bias, out, out_cs, out_off, D, H, W); } \
+        } else {                                                                                      \
+            if (acc) { hipLaunchKernelGGL((upconv2_fwd_kernel<CI, CO, false, true>), grid, blk, 0, s, ip, in_cs, in_off, wp, bias, out, out_cs, out_off, D, H, W); } \
+                else { hipLaunchKernelGGL((upconv2_fwd_kernel<CI, CO, false, false>), grid, blk, 0, s, ip, in_cs, in_off, wp, bias, out, out_cs, out_off, D, H, W); } \
+        }                                                                                             \
+        return hipGetLastError();                                                                     \
+    }
+    CTREX_NN_UP(64, 32)
+    CTREX_NN_UP(32, 16)
+    CTREX_NN_UP(32, 32)
+    CTREX_NN_UP(64, 64)
+#undef CTREX_NN_UP
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_upconv2_dgrad(const void *dout, int dout_cs, int dout_off, int cout,
+                                const void *wd, void *din, int din_cs, int din_off, int cin, int D,
+                                int H, int W, bool acc, hipStream_t s) {
+    const long long nvox = static_cast<long long>(D) * H * W;
+    const dim3 grid(blocks_for(nvox, NT)), blk(NT);
+    const u16 *dp = static_cast<const u16 *>(dout), *wp = static_cast<const u16 *>(wd);
+    u16 *op = static_cast<u16 *>(din);
+#define CTREX_NN_UD(CI, CO)                                                                        \
+    if (cin == CI && cout == CO) {                                                                 \
+        if (acc) { hipLaunchKernelGGL((upconv2_dgrad_kernel<CI, CO, true>), grid, blk, 0, s, dp, dout_cs, dout_off, wp, op, din_cs, din_off, D, H, W); } \
+            else { hipLaunchKernelGGL((upconv2_dgrad_kernel<CI, CO, false>), grid, blk, 0, s, dp, dout_cs, dout_off, wp, op, din_cs, din_off, D, H, W); } \
+        return hipGetLastError();                                                                  \
+    }
+    CTREX_NN_UD(64, 32)
+    CTREX_NN_UD(32, 16)
+    CTREX_NN_UD(32, 32)
+    CTREX_NN_UD(64, 64)
+#undef CTREX_NN_UD
+    return hipErrorInvalidValue;
+}
+
+size_t upconv2_wgrad_scratch(int cin, int cout, long long nvox) {
+    const long long chunks = (nvox + wgrad_chunk(nvox) - 1) / wgrad_chunk(nvox);
+    return sizeof(float) * static_cast<size_t>(chunks) * 8 * cin * cout;
+}
+
+hipError_t launch_upconv2_wgrad(const void *in, int in_cs, int in_off, int cin, const void *dout,
+                                int dout_cs, int dout_off, int cout, int D, int H, int W,
+                                float *dw, float *scratch, hipStream_t s) {
+    const long long nvox = static_cast<long long>(D) * H * W;
+    const long long chunk = wgrad_chunk(nvox);
+    const int chunks = static_cast<int>((nvox + chunk - 1) / chunk);
+    const u16 *ip = static_cast<const u16 *>(in), *dp = static_cast<const u16 *>(dout);
+    bool done = false;
+#define CTREX_NN_UW(CI, CO)                                                                           \
+    if (!done && cin == CI && cout == CO) {                                                            \
+        hipLaunchKernelGGL((upconv2_wgrad_kernel<CI, CO>), dim3(chunks, 2), dim3(NT), 0, s, ip, in_cs, \
+                           in_off, dp, dout_cs, dout_off, D, H, W, chunk, scratch);                    \
+        done = true;                                                                                   \
+    }
+    CTREX_NN_UW(64, 32)
+    CTREX_NN_UW(32, 16)
+    CTREX_NN_UW(32, 32)
+    CTREX_NN_UW(64, 64)
+#undef CTREX_NN_UW
+    if (!done) return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int n = 8 * cout * cin;
+    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(n)), dim3(NT), 0, s, scratch, chunks, 8,
+                       cout, cin, 1, dw);
+    return hipGetLastError();
+}
+
+hipError_t launch_maxpool2(const void *in, int in_cs, int in_off, int c, void *out, int D, int H,
+                           int W, hipStream_t s) {
+    const long long n = static_cast<long long>(D / 2) * (H / 2) * (W / 2) * c;
+    hipLaunchKernelGGL(maxpool2_kernel, dim3(blocks_for(n)), dim3(NT), 0, s,
+                       static_cast<const u16 *>(in), in_cs, in_off, c, static_cast<u16 *>(out), D, H, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_maxpool2_bwd(const void *in, int in_cs, int in_off, int c, const void *dout,
+                               void *din, int D, int H, int W, hipStream_t s) {
+    const long long n = static_cast<long long>(D / 2) * (H / 2) * (W / 2) * c;
+    hipLaunchKernelGGL(maxpool2_bwd_kernel, dim3(blocks_for(n)), dim3(NT), 0, s,
+                       static_cast<const u16 *>(in), in_cs, in_off, c, static_cast<const u16 *>(dout),
+                       static_cast<u16 *>(din), D, H, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_relu_bwd(const void *y, void *g, int cs, int off, int c, long long nvox,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(relu_bwd_kernel, dim3(blocks_for(nvox * c)), dim3(NT), 0, s,
+                       static_cast<const u16 *>(y), static_cast<u16 *>(g), cs, off, c, nvox);
+    return hipGetLastError();
+}
+
+hipError_t launch_head(const void *act, int c, const float *h, const float *b, const float *x,
+                       float *out, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(head_kernel, dim3(blocks_for(n)), dim3(NT), 0, s, static_cast<const u16 *>(act),
+                       c, h, b, x, out, n);
+    return hipGetLastError();
+}
+
+size_t head_bwd_scratch(int c) { return sizeof(double) * 512 * static_cast<size_t>(c + 1); }
+
+hipError_t launch_head_bwd(const void *act, int c, const float *h, const float *dout, void *dact,
+                           float *dh, float *db, long long n, double *scratch, hipStream_t s) {
+    const int blocks = 512;
+    if (c != 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((head_bwd_kernel<16>), dim3(blocks), dim3(NT), 0, s,
+                       static_cast<const u16 *>(act), h, dout, static_cast<u16 *>(dact), n, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (dh) hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(64), 0, s, scratch, blocks, c, c + 1, dh);
+    if (db) hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(64), 0, s, scratch + c, blocks, 1, c + 1, db);
+    return hipGetLastError();
+}
+
+hipError_t launch_mse(const float *a, const float *t, long long n, float *grad, double *partial,
+                      int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(mse_kernel, dim3(blocks), dim3(NT), 0, s, a, t, n, 2.0f / static_cast<float>(n),
+                       grad, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, long long n, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t s) {
+    const float c1 = 1.0f - powf(b1, static_cast<float>(step));
+    const float c2 = 1.0f - powf(b2, static_cast<float>(step));
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n)), dim3(NT), 0, s, p, g, m, v, n, lr, b1, b2, eps,
+                       c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const float *w, int cout, int cin, int taps, bool mirror, void *wt,
+                       void *wt_d, bool in_major, hipStream_t s) {
+    const int n = cout * cin * taps;
+    hipLaunchKernelGGL(pack_kernel, dim3(blocks_for(n)), dim3(NT), 0, s, w, cout, cin, taps,
+                       mirror ? 1 : 0, static_cast<u16 *>(wt), static_cast<u16 *>(wt_d), in_major ? 1 : 0);
+    return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace ctrex

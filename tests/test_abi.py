@@ -32,10 +32,23 @@ def test_header_declares_the_boundary():
         assert need in names
 
 
-def test_every_declared_symbol_is_exported():
+@pytest.mark.parametrize("header", ["ctrex.h", "ctrex_nn.h"])
+def test_every_declared_symbol_is_exported(header):
     L = _lib()
-    for name in _declared("ctrex.h"):
+    names = _declared(header)
+    assert names
+    for name in names:
         assert hasattr(L, name), name
+
+
+def test_binding_covers_every_declared_symbol():
+    """Every entry point of the headers has a ctypes signature."""
+    from paper_2609_30166_amd import _lib as binding
+
+    src = open(binding.__file__).read()
+    for header in ("ctrex.h", "ctrex_nn.h"):
+        for name in _declared(header):
+            assert '"%s"' % name in src, name
 
 
 def test_create_without_device_reports_device_error():
