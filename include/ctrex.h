@@ -168,6 +168,20 @@ CTREX_API int ctrex_sirt_iterate(ctrex_ctx *ctx, float *vol, const void *sino, i
                        double *resid_norms, void *stream);
 
 /*
+ * Residual norm ||b - A vol||_2 of a volume against a measured sinogram over
+ * the listed projections: the data-consistency measure of the SIRT update
+ * (Eq. 1) and the acceptance test of a learned correction between
+ * iterations (Sec. 5 extension).  `vol` and `sino` are device arrays laid
+ * out as in ctrex_forward_project; the projection is not stored.  Residuals
+ * are formed in FP32 per detector pixel and squared and summed in FP64 in a
+ * fixed order (deterministic).  Writes *norm (host) and waits for `stream`;
+ * CTREX_ENONFINITE if the norm is not finite.
+ */
+CTREX_API int ctrex_residual_norm(ctrex_ctx *ctx, const void *vol, int32_t vol_dtype,
+                                  const void *sino, int32_t sino_dtype, const int32_t *views,
+                                  int32_t n_views, double *norm, void *stream);
+
+/*
  * Exact number of ray samples (trilinear lookups) one forward projection of
  * the listed projections performs, summed over sub-views; synchronous.
  */

@@ -61,6 +61,7 @@ def lib():
                                                           ctypes.POINTER(ctypes.c_size_t)]),
             "ctrex_sirt_iterate": (ctypes.c_int, [vp, vp, vp, i32, i32, ctypes.c_float, u32, ip,
                                                   i32, vp, ctypes.c_size_t, dp, vp]),
+            "ctrex_residual_norm": (ctypes.c_int, [vp, vp, i32, vp, i32, ip, i32, dp, vp]),
             "ctrex_sample_count": (ctypes.c_int, [vp, ip, i32, ctypes.POINTER(ctypes.c_int64), vp]),
             "ctrex_convert": (ctypes.c_int, [vp, vp, i32, vp, i32, ctypes.c_int64, vp]),
             "ctrex_profile_enable": (ctypes.c_int, [vp, i32]),

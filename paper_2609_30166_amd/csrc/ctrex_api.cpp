@@ -455,6 +455,40 @@ int ctrex_forward_project(ctrex_ctx *c, const void *vol, int32_t vol_dtype, void
     return CTREX_OK;
 }
 
+int ctrex_residual_norm(ctrex_ctx *c, const void *vol, int32_t vol_dtype, const void *sino,
+                        int32_t sino_dtype, const int32_t *views, int32_t n_views, double *norm,
+                        void *stream) {
+    int st = check_ready(c);
+    if (st != CTREX_OK) return st;
+    if (!norm) return fail(c, CTREX_EINVAL, "norm must be a host pointer");
+    if (!valid_dtype(vol_dtype) || !valid_dtype(sino_dtype))
+        return fail(c, CTREX_EINVAL, "unknown dtype (%d, %d)", vol_dtype, sino_dtype);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t *dv;
+    int32_t nv;
+    if ((st = resolve_views(c, views, n_views, &dv, &nv, s)) != CTREX_OK) return st;
+    *norm = 0.0;
+    if (nv == 0) return CTREX_OK;
+    if (!vol || !sino) return fail(c, CTREX_EINVAL, "vol and sino must be device pointers");
+    if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
+    const RayGrid g = make_grid(c, dv, nv);
+    void *scr;
+    if ((st = ctx_scratch(c, sizeof(double) * (static_cast<size_t>(g.total_blocks) + 1), &scr)))
+        return st;
+    double *part = static_cast<double *>(scr);
+    FpExtra ex{sino, nullptr, part};
+    // `out` is unused in this mode; the sinogram's storage type selects the kernel
+    CTREX_HIP(c, launch_forward(g, make_warp(c), vol, vol_dtype, nullptr, sino_dtype, FP_RESIDUAL,
+                                ex, s));
+    CTREX_HIP(c, launch_sum_partials(part, g.total_blocks, part + g.total_blocks, s));
+    double h = 0.0;
+    CTREX_HIP(c, hipMemcpyAsync(&h, part + g.total_blocks, sizeof h, hipMemcpyDeviceToHost, s));
+    CTREX_HIP(c, hipStreamSynchronize(s));
+    *norm = std::sqrt(h);
+    if (!std::isfinite(*norm)) return fail(c, CTREX_ENONFINITE, "the residual norm is not finite");
+    return CTREX_OK;
+}
+
 int ctrex_back_project(ctrex_ctx *c, const void *sino, int32_t sino_dtype, float *vol,
                        int32_t accumulate, const int32_t *views, int32_t n_views, void *stream) {
     int st = check_ready(c);

@@ -53,12 +53,13 @@ enum FpMode : int {
     FP_PLAIN = 0,     // sino = A vol
     FP_RECIP_ONES = 1,// out = 1 / (A 1), 0 where A 1 == 0 (the SIRT weight R)
     FP_CORRECT = 2,   // out = R (b - A vol); per-block sums of (b - A vol)^2
+    FP_RESIDUAL = 3,  // per-block sums of (b - A vol)^2 only (out unused)
 };
 
 struct FpExtra {
-    const void *b;       // measured sinogram (FP_CORRECT), storage type = out type
+    const void *b;       // measured sinogram (FP_CORRECT, FP_RESIDUAL), storage type = out type
     const float *R;      // detector weights (FP_CORRECT)
-    double *partials;    // [total_blocks] (FP_CORRECT)
+    double *partials;    // [total_blocks] (FP_CORRECT, FP_RESIDUAL)
 };
 
 // Backprojection modes.

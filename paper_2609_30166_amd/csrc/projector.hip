@@ -99,7 +99,7 @@ __global__ __launch_bounds__(PROJ_THREADS) void fp_kernel(RayGrid g, WarpGrid w,
             const float bval = ld(static_cast<const TS *>(ex.b), pix);
             const float res = bval - y;
             e2 = static_cast<double>(res) * static_cast<double>(res);
-            st(out, pix, ex.R[pix] * res);
+            if (MODE == FP_CORRECT) st(out, pix, ex.R[pix] * res);
         }
         block_sum_store(e2, ex.partials + t.lidx);
     }
@@ -140,6 +140,8 @@ hipError_t fp_dispatch_mode(const RayGrid &g, const WarpGrid &w, const void *vol
         if (wp) CTREX_FP(FP_PLAIN, true); else CTREX_FP(FP_PLAIN, false);
     } else if (mode == FP_CORRECT) {
         if (wp) CTREX_FP(FP_CORRECT, true); else CTREX_FP(FP_CORRECT, false);
+    } else if (mode == FP_RESIDUAL) {
+        if (wp) CTREX_FP(FP_RESIDUAL, true); else CTREX_FP(FP_RESIDUAL, false);
     } else {
         return hipErrorInvalidValue;
     }

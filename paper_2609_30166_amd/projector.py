@@ -190,6 +190,18 @@ class Geometry:
             _stream(self.device)))
         return out
 
+    def residual_norm(self, vol, sino, views=None):
+        """||sino - A vol||_2 (FP64 sum, computed by the library; waits)."""
+        self._check_tensor(vol, self.shape, _DT, "vol")
+        self._check_tensor(sino, self.sino_shape(views), _DT, "sino")
+        vp, nv, _keep = _views_arg(views)
+        out = ctypes.c_double(0.0)
+        check(self._ctx, _lib.lib().ctrex_residual_norm(
+            self._ctx, ctypes.c_void_p(vol.data_ptr()), _DT[vol.dtype],
+            ctypes.c_void_p(sino.data_ptr()), _DT[sino.dtype], vp, nv, ctypes.byref(out),
+            _stream(self.device)))
+        return out.value
+
     def sample_count(self, views=None):
         """Exact number of trilinear samples of one forward projection."""
         cnt = ctypes.c_int64(0)

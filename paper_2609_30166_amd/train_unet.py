@@ -1,0 +1,93 @@
+"""Train the correction network on generated phantoms and compare the learned
+pipeline with plain SIRT.
+
+    python -m paper_2609_30166_amd.train_unet --phantoms 512 --test 32 \
+        --out weights.npz --summary summary.json
+
+Training follows the stage-wise scheme of ``learned.train`` on the
+learned-correction configuration (256^3 volumes, 180 projections of 384^2
+pixels, Poisson noise at 1e4 incident photons); the summary holds the loss
+history and the held-out comparison (PSNR, ||A x - b||, wall time).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+import torch
+
+from synth import configs
+
+from . import learned
+from .unet import UNet
+
+
+def save(path, net, meta):
+    st = net.state_dict()
+    np.savez(path, step=st["step"], theta=st["theta"], m=st["m"], v=st["v"],
+             **{"p." + k: v for k, v in net.params().items()},
+             meta=json.dumps(meta))
+
+
+def load(path, device=None):
+    """A UNet with the parameters (and Adam state) stored by ``save``."""
+    z = np.load(path, allow_pickle=False)
+    params = {k[2:]: z[k] for k in z.files if k.startswith("p.")}
+    net = UNet(device, params=params)
+    net.load_state_dict(dict(theta=z["theta"], m=z["m"], v=z["v"], step=int(z["step"])))
+    return net
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--phantoms", type=int, default=512)
+    ap.add_argument("--test", type=int, default=32)
+    ap.add_argument("--stages", type=int, default=4)
+    ap.add_argument("--iters-per-stage", type=int, default=1)
+    ap.add_argument("--sirt-iters", type=int, default=50)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--resume", default=None, help="weights file to continue from")
+    ap.add_argument("--out", default="unet_weights.npz")
+    ap.add_argument("--summary", default=None)
+    a = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, flush=True)
+
+    cfg, geom = learned.learned_geometry()
+    net = load(a.resume, geom.device) if a.resume else UNet(geom.device, seed=a.seed)
+    seeds = list(configs.TRAIN_SEEDS)[:a.phantoms]
+    t0 = time.time()
+    hist = learned.train(geom, net, cfg, seeds, lr=a.lr, n_stages=a.stages,
+                         iters_per_stage=a.iters_per_stage, log=log)
+    t_train = time.time() - t0
+    meta = dict(config="learned", phantoms=a.phantoms, stages=a.stages,
+                iters_per_stage=a.iters_per_stage, lr=a.lr, seed=a.seed, train_s=t_train)
+    save(a.out, net, meta)
+    log("trained on %d phantoms in %.1f s -> %s" % (len(seeds), t_train, a.out))
+    summary = dict(meta=meta, loss_first=hist[:8].mean(0).tolist(),
+                   loss_last=hist[-8:].mean(0).tolist())
+    if a.test > 0:
+        res = learned.compare(geom, net, cfg, list(configs.TEST_SEEDS)[:a.test],
+                              sirt_iters=a.sirt_iters, n_stages=a.stages,
+                              iters_per_stage=a.iters_per_stage, log=log)
+        summary["compare"] = res
+        m = res["mean"]
+        log("mean PSNR: SIRT-%d %.2f dB, SIRT-%d %.2f dB, learned %.2f dB; time %.3f s vs "
+            "%.3f s (ratio %.3f); learned >= SIRT-%d PSNR on every phantom: %s" % (
+                a.sirt_iters, m["psnr_sirt"], a.stages * a.iters_per_stage,
+                m["psnr_sirt_same_budget"], m["psnr_learned"], m["t_learned"], m["t_sirt"],
+                res["time_ratio"], a.sirt_iters, res["learned_reaches_sirt_psnr"]))
+    if a.summary:
+        with open(a.summary, "w") as f:
+            json.dump(summary, f, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -109,3 +109,30 @@ def make_phantom(cfg, seed, supersample=1, dtype=np.float32):
     if ex.get("per_width"):
         vol /= float(min(nx, ny))
     return vol.astype(dtype), ells
+
+
+# Seeds of the learned-correction data sets: disjoint training and test ranges.
+TRAIN_SEEDS = range(0, 512)
+TEST_SEEDS = range(100000, 100032)
+
+
+def make_learned_phantom(cfg, seed, device, dtype=None):
+    """Training / test phantom of the learned-correction configuration,
+    synthesised with torch on ``device``: even seeds give random ellipsoids,
+    odd seeds a foam (cylinder of value 0.5 minus spherical voids), both in
+    per-volume-width units like ``make_phantom``.  Returns a float64 tensor
+    (or ``dtype``) laid out [nz][ny][nx]."""
+    import torch
+    rng = np.random.default_rng([seed, 7])
+    ex = cfg.extra
+    nz, ny, nx = cfg.shape
+    if seed % 2 == 0:
+        fov = ex.get("fov_radius", 0.45 * min(nx, ny))
+        ells = phantoms.random_ellipsoids(ex["n_ellipsoids"], cfg.shape, ex["semi"], ex["mu"],
+                                          rng, fov_radius=fov)
+        vol = phantoms.voxelise_ellipsoids_torch(ells, cfg.shape, device)
+    else:
+        vol = phantoms.foam_phantom_torch(cfg.shape, rng, device)
+    if ex.get("per_width"):
+        vol /= float(min(nx, ny))
+    return vol if dtype is None else vol.to(dtype)

@@ -120,21 +120,7 @@ def foam_phantom(shape, rng, radius_frac=0.4, mu=0.5, n_voids=(20, 200),
                  void_radius_frac=(0.01, 0.08), dtype=np.float64):
     """Cylinder (radius 0.4 N) minus random non-overlapping spherical voids."""
     nz, ny, nx = shape
-    N = min(nx, ny)
-    R = radius_frac * N
-    H = 0.9 * nz
-    k = int(rng.integers(n_voids[0], n_voids[1] + 1))
-    voids = []
-    tries = 0
-    while len(voids) < k and tries < 20000:
-        tries += 1
-        r = rng.uniform(void_radius_frac[0], void_radius_frac[1]) * N
-        rho = (R - r) * np.sqrt(rng.uniform())
-        phi = rng.uniform(0, 2 * np.pi)
-        z = rng.uniform(-(0.5 * H - r), 0.5 * H - r)
-        c = np.array([rho * np.cos(phi), rho * np.sin(phi), z])
-        if all(np.linalg.norm(c - c2) > r + r2 for c2, r2 in voids):
-            voids.append((c, r))
+    R, H, voids = foam_voids(shape, rng, radius_frac, n_voids, void_radius_frac)
     vol = cylinder_background(shape, R, H, mu)
     cz, cy, cx = _centres(nz), _centres(ny), _centres(nx)
     for c, r in voids:
@@ -155,3 +141,80 @@ def fov_mask(shape, radius):
     y = _centres(ny)[:, None]
     x = _centres(nx)[None, :]
     return np.broadcast_to((x * x + y * y) <= radius * radius, shape)
+
+
+# ------------------------------------------------------------- torch variants --
+# The same point-sampled definitions evaluated with torch on any device, so
+# large training sets can be synthesised where the volumes are used.  Object
+# parameters still come from the numpy generators above.
+
+def _torch_centres(n, device):
+    import torch
+    return torch.arange(n, dtype=torch.float64, device=device) - 0.5 * (n - 1)
+
+
+def voxelise_ellipsoids_torch(ells, shape, device, dtype=None):
+    """Point-sampled ellipsoids (``voxelise_ellipsoids`` with supersample=1)."""
+    import torch
+    nz, ny, nx = shape
+    vol = torch.zeros(shape, dtype=torch.float64, device=device)
+    cx, cy, cz = (_torch_centres(n, device) for n in (nx, ny, nz))
+    for e in ells:
+        Q = torch.as_tensor(e.quadric(), dtype=torch.float64, device=device)
+        r = float(e.axes.max()) + 1.0
+        lo = np.floor(e.centre - r + 0.5 * (np.array([nx, ny, nz]) - 1)).astype(int)
+        hi = np.ceil(e.centre + r + 0.5 * (np.array([nx, ny, nz]) - 1)).astype(int)
+        lo = np.maximum(lo, 0)
+        hi = np.minimum(hi, [nx - 1, ny - 1, nz - 1])
+        if np.any(hi < lo):
+            continue
+        xs = cx[lo[0]:hi[0] + 1] - float(e.centre[0])
+        ys = cy[lo[1]:hi[1] + 1] - float(e.centre[1])
+        zs = cz[lo[2]:hi[2] + 1] - float(e.centre[2])
+        Z, Y, X = torch.meshgrid(zs, ys, xs, indexing="ij")
+        D = torch.stack([X, Y, Z], -1)
+        q = D @ Q.T
+        inside = (q * q).sum(-1) <= 1.0
+        vol[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1] += e.mu * inside.to(torch.float64)
+    return vol if dtype is None else vol.to(dtype)
+
+
+def foam_voids(shape, rng, radius_frac=0.4, n_voids=(20, 200), void_radius_frac=(0.01, 0.08)):
+    """The cylinder radius, height and void list of ``foam_phantom`` (same draws)."""
+    nz, ny, nx = shape
+    N = min(nx, ny)
+    R = radius_frac * N
+    H = 0.9 * nz
+    k = int(rng.integers(n_voids[0], n_voids[1] + 1))
+    voids = []
+    tries = 0
+    while len(voids) < k and tries < 20000:
+        tries += 1
+        r = rng.uniform(void_radius_frac[0], void_radius_frac[1]) * N
+        rho = (R - r) * np.sqrt(rng.uniform())
+        phi = rng.uniform(0, 2 * np.pi)
+        z = rng.uniform(-(0.5 * H - r), 0.5 * H - r)
+        c = np.array([rho * np.cos(phi), rho * np.sin(phi), z])
+        if all(np.linalg.norm(c - c2) > r + r2 for c2, r2 in voids):
+            voids.append((c, r))
+    return R, H, voids
+
+
+def foam_phantom_torch(shape, rng, device, mu=0.5, dtype=None, **kw):
+    """``foam_phantom`` evaluated with torch (identical draws from ``rng``)."""
+    import torch
+    nz, ny, nx = shape
+    R, H, voids = foam_voids(shape, rng, **kw)
+    cz, cy, cx = (_torch_centres(n, device) for n in (nz, ny, nx))
+    disc = (cx[None, :] ** 2 + cy[:, None] ** 2) <= R * R
+    vol = torch.zeros(shape, dtype=torch.float64, device=device)
+    vol[torch.abs(cz) <= 0.5 * H] = mu * disc.to(torch.float64)
+    for c, r in voids:
+        lo = [max(int(np.floor(c[a] - r + 0.5 * (n - 1))), 0) for a, n in enumerate((nx, ny, nz))]
+        hi = [min(int(np.ceil(c[a] + r + 0.5 * (n - 1))), n - 1) for a, n in enumerate((nx, ny, nz))]
+        Z, Y, X = torch.meshgrid(cz[lo[2]:hi[2] + 1], cy[lo[1]:hi[1] + 1], cx[lo[0]:hi[0] + 1],
+                                 indexing="ij")
+        d2 = (X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2
+        sub = vol[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1]
+        sub[d2 <= r * r] = 0.0
+    return vol if dtype is None else vol.to(dtype)

@@ -1,0 +1,506 @@
+"""GPU parity of the learned-correction kernels and network against the FP64
+CPU reference (oracle/unet.py).
+
+Kernel tests feed BF16-representable inputs and weights, so the only
+difference left is FP32 accumulation on the matrix cores versus FP64: FP32
+outputs must agree to 1e-5 relative (L2 and max-norm scaled by the largest
+reference value).  BF16 outputs are compared within one BF16 rounding
+(2^-8 relative).
+
+Whole-network results go through about fifteen BF16-stored activations in
+the forward pass and as many stored gradients in the backward pass.  An
+oracle that rounds the same activations does not remove that noise: a single
+rounding that lands on the other side (FP32 versus FP64 accumulation) shifts
+its neighbours in the next layer, whose roundings then differ in turn, so
+after a few layers a fraction of all elements differ by one BF16 ulp.  The
+bound is therefore the BF16 storage error itself, RMS 2^-9 / sqrt(3) per
+stored tensor: sqrt(15) x 1.1e-3 = 4e-3 for the forward correction (tested
+at 1e-2), sqrt(30) x 1.1e-3 = 6e-3 for gradients (all parameters together at
+2e-2, each tensor at 5e-2).  A wiring mistake (concatenation order, a missing
+skip or pooling gradient, a transposed packing) gives O(1) errors.
+"""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _skip():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+@pytest.fixture(scope="module")
+def L():
+    _skip()
+    from paper_2609_30166_amd import _lib
+    return _lib
+
+
+@pytest.fixture(scope="module")
+def ctx(L):
+    c = ctypes.c_void_p()
+    assert L.lib().ctrex_create(ctypes.byref(c), 0) == 0
+    yield c
+    L.lib().ctrex_destroy(c)
+
+
+def _vp(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _bf(a):
+    """float64 numpy -> BF16-rounded float64 numpy."""
+    return torch.as_tensor(a, dtype=torch.float64).float().bfloat16().double().numpy()
+
+
+def _dev_bf(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).float().bfloat16().to(DEV)
+
+
+def _dev_f(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32).to(DEV)
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.detach().double().cpu().numpy()
+
+
+def _close(got, ref, rel=1e-5):
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    assert got.shape == ref.shape, (got.shape, ref.shape)
+    scale = max(np.abs(ref).max(), 1e-30)
+    err = np.abs(got - ref).max() / scale
+    l2 = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)
+    assert err <= rel and l2 <= rel, (err, l2)
+
+
+def _call(L, ctx, fn, *args):
+    code = getattr(L.lib(), fn)(ctx, *args)
+    if code != 0:
+        raise L.CtrexError(code, L.lib().ctrex_last_error(ctx).decode())
+
+
+def _pack_conv(L, ctx, w):
+    cout, cin, _ = w.shape
+    wt = torch.empty(27 * cin * cout, dtype=torch.bfloat16, device=DEV)
+    wd = torch.empty_like(wt)
+    wf = _dev_f(w)
+    _call(L, ctx, "ctrex_nn_pack_conv3", _vp(wf), cout, cin, _vp(wt), _vp(wd), None)
+    return wt, wd
+
+
+def _pack_up(L, ctx, w):
+    cin, cout, _ = w.shape
+    wt = torch.empty(8 * cin * cout, dtype=torch.bfloat16, device=DEV)
+    wd = torch.empty_like(wt)
+    wf = _dev_f(w)
+    _call(L, ctx, "ctrex_nn_pack_upconv2", _vp(wf), cin, cout, _vp(wt), _vp(wd), None)
+    return wt, wd
+
+
+SHAPES = [(8, 8, 16), (4, 12, 20)]   # 1024 and 960 voxels: full and ragged workgroups
+CONV_PAIRS = [(1, 16), (16, 16), (16, 32), (32, 16), (32, 32), (32, 64), (64, 32), (64, 64)]
+UP_PAIRS = [(64, 32), (32, 16)]
+
+
+def _rng(*s):
+    return np.random.default_rng([77, *s])
+
+
+# ----------------------------------------------------------------- conv3 ----
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("cin,cout", CONV_PAIRS)
+def test_conv3_forward_f32(L, ctx, shape, cin, cout):
+    from oracle import unet as ou
+    r = _rng(1, cin, cout, *shape)
+    x = _bf(r.normal(size=shape + (cin,)))
+    w = r.normal(0, 0.1, size=(cout, cin, 27))
+    b = r.normal(size=cout).astype(np.float32).astype(np.float64)
+    wt, _ = _pack_conv(L, ctx, w)
+    out = torch.empty(np.prod(shape) * cout, dtype=torch.float32, device=DEV)
+    xd, bd = _dev_bf(x), _dev_f(b)
+    _call(L, ctx, "ctrex_nn_conv3", _vp(xd), cin, 0, cin, _vp(wt), _vp(bd), _vp(out), cout, 0,
+          cout, *shape, L.NN_OUT_F32, None)
+    ref = ou.conv3(torch.tensor(x), torch.tensor(_bf(w)), torch.tensor(b)).numpy()
+    _close(_host(out).reshape(ref.shape), ref)
+
+
+@pytest.mark.parametrize("cin,cout", [(16, 32), (32, 16), (64, 64)])
+def test_conv3_slices_relu_accumulate_bf16(L, ctx, cin, cout):
+    """Input read from a channel slice of a wider tensor, output accumulated
+    (after ReLU) into a slice of another, BF16 storage."""
+    from oracle import unet as ou
+    shape = (4, 8, 8)
+    n = int(np.prod(shape))
+    r = _rng(2, cin, cout)
+    wide_in, off_in = cin + 16, 8
+    xw = _bf(r.normal(size=(n, wide_in)))
+    w = r.normal(0, 0.1, size=(cout, cin, 27))
+    b = r.normal(size=cout).astype(np.float32).astype(np.float64)
+    wide_out, off_out = cout + 32, 16
+    prev = _bf(r.normal(size=(n, wide_out)))
+    wt, _ = _pack_conv(L, ctx, w)
+    xd, bd, od = _dev_bf(xw), _dev_f(b), _dev_bf(prev)
+    _call(L, ctx, "ctrex_nn_conv3", _vp(xd), wide_in, off_in, cin, _vp(wt), _vp(bd), _vp(od),
+          wide_out, off_out, cout, *shape, L.NN_RELU | L.NN_ACCUMULATE, None)
+    got = _host(od)
+    x = xw[:, off_in:off_in + cin].reshape(shape + (cin,))
+    y = np.maximum(ou.conv3(torch.tensor(x), torch.tensor(_bf(w)), torch.tensor(b)).numpy(), 0)
+    y = y.reshape(n, cout)
+    # untouched channels bit-exact, written ones: one rounding of prev + y
+    np.testing.assert_array_equal(got[:, :off_out], prev[:, :off_out])
+    np.testing.assert_array_equal(got[:, off_out + cout:], prev[:, off_out + cout:])
+    old = prev[:, off_out:off_out + cout]
+    exact = old + y
+    d = np.abs(got[:, off_out:off_out + cout] - exact)
+    assert np.all(d <= 2.0 ** -8 * np.abs(exact) + 1e-5 * (np.abs(old) + np.abs(y)))
+
+
+@pytest.mark.parametrize("cin,cout", [(16, 16), (16, 32), (32, 64), (64, 32)])
+def test_conv3_data_gradient(L, ctx, cin, cout):
+    """The convolution with the dgrad packing is the input gradient."""
+    from oracle import unet as ou
+    shape = (4, 12, 20)
+    r = _rng(3, cin, cout)
+    x = torch.tensor(_bf(r.normal(size=shape + (cin,))), requires_grad=True)
+    w = _bf(r.normal(0, 0.1, size=(cout, cin, 27)))
+    g = _bf(r.normal(size=shape + (cout,)))
+    (ou.conv3(x, torch.tensor(w)) * torch.tensor(g)).sum().backward()
+    _, wd = _pack_conv(L, ctx, w)
+    gd = _dev_bf(g)
+    out = torch.empty(np.prod(shape) * cin, dtype=torch.float32, device=DEV)
+    _call(L, ctx, "ctrex_nn_conv3", _vp(gd), cout, 0, cout, _vp(wd), None, _vp(out), cin, 0, cin,
+          *shape, L.NN_OUT_F32, None)
+    _close(_host(out).reshape(shape + (cin,)), x.grad.numpy())
+
+
+@pytest.mark.parametrize("shape", SHAPES + [(16, 16, 32)])
+@pytest.mark.parametrize("cin,cout", CONV_PAIRS)
+def test_conv3_weight_gradient(L, ctx, shape, cin, cout):
+    from oracle import unet as ou
+    r = _rng(4, cin, cout, *shape)
+    x = _bf(r.normal(size=shape + (cin,)))
+    g = _bf(r.normal(size=shape + (cout,)))
+    w = torch.zeros((cout, cin, 27), dtype=torch.float64, requires_grad=True)
+    b = torch.zeros(cout, dtype=torch.float64, requires_grad=True)
+    (ou.conv3(torch.tensor(x), w, b) * torch.tensor(g)).sum().backward()
+    xd, gd = _dev_bf(x), _dev_bf(g)
+    dw = torch.empty(cout * cin * 27, dtype=torch.float32, device=DEV)
+    db = torch.empty(cout, dtype=torch.float32, device=DEV)
+    _call(L, ctx, "ctrex_nn_conv3_wgrad", _vp(xd), cin, 0, cin, _vp(gd), cout, 0, cout, *shape,
+          _vp(dw), _vp(db), None)
+    _close(_host(dw).reshape(cout, cin, 27), w.grad.numpy())
+    _close(_host(db), b.grad.numpy())
+
+
+def test_conv3_weight_gradient_on_slices(L, ctx):
+    from oracle import unet as ou
+    shape, cin, cout = (8, 8, 8), 32, 16
+    n = 512
+    r = _rng(5)
+    xw = _bf(r.normal(size=(n, 64)))
+    gw = _bf(r.normal(size=(n, 32)))
+    x, g = xw[:, 32:64].reshape(shape + (cin,)), gw[:, 16:32].reshape(shape + (cout,))
+    w = torch.zeros((cout, cin, 27), dtype=torch.float64, requires_grad=True)
+    (ou.conv3(torch.tensor(x), w) * torch.tensor(g)).sum().backward()
+    xd, gd = _dev_bf(xw), _dev_bf(gw)
+    dw = torch.empty(cout * cin * 27, dtype=torch.float32, device=DEV)
+    _call(L, ctx, "ctrex_nn_conv3_wgrad", _vp(xd), 64, 32, cin, _vp(gd), 32, 16, cout, *shape,
+          _vp(dw), None, None)
+    _close(_host(dw).reshape(cout, cin, 27), w.grad.numpy())
+
+
+# --------------------------------------------------------------- upconv2 ----
+@pytest.mark.parametrize("shape", [(4, 4, 4), (2, 6, 10), (8, 8, 16)])
+@pytest.mark.parametrize("cin,cout", UP_PAIRS)
+def test_upconv2_forward_and_gradients(L, ctx, shape, cin, cout):
+    from oracle import unet as ou
+    r = _rng(6, cin, cout, *shape)
+    n = int(np.prod(shape))
+    if n % 64:
+        pytest.skip("voxel count must be a multiple of 64")
+    x = torch.tensor(_bf(r.normal(size=shape + (cin,))), requires_grad=True)
+    w = torch.tensor(_bf(r.normal(0, 0.2, size=(cin, cout, 8))), requires_grad=True)
+    b = torch.tensor(r.normal(size=cout).astype(np.float32).astype(np.float64), requires_grad=True)
+    y = ou.upconv2(x, w, b)
+    g = _bf(r.normal(size=tuple(y.shape)))
+    (y * torch.tensor(g)).sum().backward()
+    wt, wd = _pack_up(L, ctx, w.detach().numpy())
+    xd, bd, gd = _dev_bf(x.detach().numpy()), _dev_f(b.detach().numpy()), _dev_bf(g)
+    out = torch.empty(8 * n * cout, dtype=torch.float32, device=DEV)
+    _call(L, ctx, "ctrex_nn_upconv2", _vp(xd), cin, 0, cin, _vp(wt), _vp(bd), _vp(out), cout, 0,
+          cout, *shape, L.NN_OUT_F32, None)
+    _close(_host(out).reshape(y.shape), y.detach().numpy())
+    # data gradient (BF16 output; compare within one rounding)
+    din = torch.empty(n * cin, dtype=torch.bfloat16, device=DEV)
+    _call(L, ctx, "ctrex_nn_upconv2_dgrad", _vp(gd), cout, 0, cout, _vp(wd), _vp(din), cin, 0,
+          cin, *shape, 0, None)
+    ref = x.grad.numpy().reshape(n, cin)
+    got = _host(din)
+    assert np.all(np.abs(got.reshape(n, cin) - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-6 * np.abs(ref).max())
+    dw = torch.empty(cin * cout * 8, dtype=torch.float32, device=DEV)
+    db = torch.empty(cout, dtype=torch.float32, device=DEV)
+    _call(L, ctx, "ctrex_nn_upconv2_wgrad", _vp(xd), cin, 0, cin, _vp(gd), cout, 0, cout, *shape,
+          _vp(dw), _vp(db), None)
+    _close(_host(dw).reshape(cin, cout, 8), w.grad.numpy())
+    _close(_host(db), b.grad.numpy())
+
+
+def test_upconv2_into_concat_slice(L, ctx):
+    from oracle import unet as ou
+    shape, cin, cout = (4, 4, 4), 32, 16
+    r = _rng(7)
+    x = _bf(r.normal(size=shape + (cin,)))
+    w = _bf(r.normal(0, 0.2, size=(cin, cout, 8)))
+    wt, _ = _pack_up(L, ctx, w)
+    n_out = 8 * 64
+    prev = _bf(r.normal(size=(n_out, 32)))
+    od = _dev_bf(prev)
+    xd = _dev_bf(x)
+    _call(L, ctx, "ctrex_nn_upconv2", _vp(xd), cin, 0, cin, _vp(wt), None, _vp(od), 32, 0, cout,
+          *shape, 0, None)
+    got = _host(od)
+    ref = ou.upconv2(torch.tensor(x), torch.tensor(w)).numpy().reshape(n_out, cout)
+    np.testing.assert_array_equal(got[:, 16:], prev[:, 16:])
+    assert np.all(np.abs(got[:, :16] - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-7)
+
+
+# --------------------------------------------------------- elementwise ops --
+def test_maxpool_and_backward_bit_exact(L, ctx):
+    from oracle import unet as ou
+    shape, c, cs, off = (4, 8, 12), 16, 32, 16
+    n = int(np.prod(shape))
+    r = _rng(8)
+    xw = _bf(np.round(r.normal(size=(n, cs)) * 4) / 4)   # ties inside windows
+    x = xw[:, off:off + c].reshape(shape + (c,))
+    xd = _dev_bf(xw)
+    po = torch.empty(n // 8 * c, dtype=torch.bfloat16, device=DEV)
+    _call(L, ctx, "ctrex_nn_maxpool2", _vp(xd), cs, off, c, _vp(po), *shape, None)
+    ref = ou.maxpool2(torch.tensor(x)).numpy()
+    np.testing.assert_array_equal(_host(po).reshape(ref.shape), ref)
+    d = _bf(r.normal(size=ref.shape))
+    dd = _dev_bf(d)
+    din = torch.zeros(n * cs, dtype=torch.bfloat16, device=DEV)
+    _call(L, ctx, "ctrex_nn_maxpool2_backward", _vp(xd), cs, off, c, _vp(dd), _vp(din), *shape,
+          None)
+    gref = ou.maxpool2_backward(torch.tensor(x), torch.tensor(d)).numpy().reshape(n, c)
+    got = _host(din).reshape(n, cs)
+    np.testing.assert_array_equal(got[:, off:off + c], gref)
+    assert np.all(got[:, :off] == 0) and np.all(got[:, off + c:] == 0)
+
+
+def test_relu_backward_bit_exact(L, ctx):
+    n, cs, off, c = 960, 48, 16, 32
+    r = _rng(9)
+    y = _bf(np.maximum(r.normal(size=(n, cs)), 0))
+    g = _bf(r.normal(size=(n, cs)))
+    yd, gd = _dev_bf(y), _dev_bf(g)
+    _call(L, ctx, "ctrex_nn_relu_backward", _vp(yd), _vp(gd), cs, off, c, n, None)
+    ref = g.copy()
+    sl = ref[:, off:off + c]
+    sl[y[:, off:off + c] <= 0] = 0
+    np.testing.assert_array_equal(_host(gd), ref)
+
+
+def test_head_forward_backward(L, ctx):
+    n = 4096
+    r = _rng(10)
+    act = _bf(np.maximum(r.normal(size=(n, 16)), 0))
+    h = r.normal(size=16).astype(np.float32).astype(np.float64)
+    bb = np.array([0.25])
+    x = r.normal(size=n).astype(np.float32).astype(np.float64)
+    dout = r.normal(size=n).astype(np.float32).astype(np.float64)
+    ad, hd, bd, xd, dd = _dev_bf(act), _dev_f(h), _dev_f(bb), _dev_f(x), _dev_f(dout)
+    out = torch.empty(n, dtype=torch.float32, device=DEV)
+    _call(L, ctx, "ctrex_nn_head", _vp(ad), 16, _vp(hd), _vp(bd), _vp(xd), _vp(out), n, None)
+    _close(_host(out), x + bb[0] + act @ h, rel=1e-6)
+    dact = torch.empty(n * 16, dtype=torch.bfloat16, device=DEV)
+    dh = torch.empty(16, dtype=torch.float32, device=DEV)
+    db = torch.empty(1, dtype=torch.float32, device=DEV)
+    _call(L, ctx, "ctrex_nn_head_backward", _vp(ad), 16, _vp(hd), _vp(dd), _vp(dact), _vp(dh),
+          _vp(db), n, None)
+    ref = np.outer(dout, h)
+    assert np.all(np.abs(_host(dact).reshape(n, 16) - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-30)
+    _close(_host(dh), dout @ act, rel=1e-6)
+    _close(_host(db), [dout.sum()], rel=1e-6)
+
+
+def test_mse_and_adam(L, ctx):
+    from oracle import unet as ou
+    n = 10000
+    r = _rng(11)
+    a = r.normal(size=n).astype(np.float32).astype(np.float64)
+    t = r.normal(size=n).astype(np.float32).astype(np.float64)
+    ad, td = _dev_f(a), _dev_f(t)
+    grad = torch.empty(n, dtype=torch.float32, device=DEV)
+    loss = ctypes.c_double()
+    _call(L, ctx, "ctrex_nn_mse", _vp(ad), _vp(td), n, ctypes.byref(loss), _vp(grad), None)
+    assert abs(loss.value - np.mean((a - t) ** 2)) <= 1e-6 * np.mean((a - t) ** 2)
+    _close(_host(grad), 2 * (a - t) / n, rel=1e-6)
+    p = r.normal(size=n)
+    g = r.normal(size=n)
+    m = r.normal(size=n) * 0.1
+    v = np.abs(r.normal(size=n)) * 0.01
+    pd, gd, md, vd = (_dev_f(q) for q in (p, g, m, v))
+    _call(L, ctx, "ctrex_nn_adam", _vp(pd), _vp(gd), _vp(md), _vp(vd), n, 1e-3, 0.9, 0.999, 1e-8,
+          7, None)
+    p32 = [q.astype(np.float32).astype(np.float64) for q in (p, g, m, v)]
+    # the kernel receives the hyperparameters as FP32 values
+    f = lambda s: float(np.float32(s))
+    pr, mr, vr = ou.adam_step(*p32, 7, lr=f(1e-3), b1=f(0.9), b2=f(0.999), eps=f(1e-8))
+    _close(_host(md), mr, rel=1e-6)
+    _close(_host(vd), vr, rel=1e-6)
+    _close(_host(pd) - p32[0], pr - p32[0], rel=1e-4)
+
+
+def test_invalid_arguments_are_rejected(L, ctx):
+    x = torch.zeros(64 * 16, dtype=torch.bfloat16, device=DEV)
+    w = torch.zeros(27 * 16 * 16, dtype=torch.bfloat16, device=DEV)
+    lib = L.lib()
+    # 48 input channels are not supported
+    assert lib.ctrex_nn_conv3(ctx, _vp(x), 48, 0, 48, _vp(w), None, _vp(x), 16, 0, 16, 4, 4, 4,
+                              0, None) == -2
+    # voxel count not a multiple of 64
+    assert lib.ctrex_nn_conv3(ctx, _vp(x), 16, 0, 16, _vp(w), None, _vp(x), 16, 0, 16, 3, 3, 3,
+                              0, None) == -2
+    # misaligned channel offset for vector loads
+    assert lib.ctrex_nn_conv3(ctx, _vp(x), 32, 4, 16, _vp(w), None, _vp(x), 16, 0, 16, 4, 4, 4,
+                              0, None) == -2
+    # odd sides cannot be pooled
+    assert lib.ctrex_nn_maxpool2(ctx, _vp(x), 16, 0, 16, _vp(x), 4, 4, 3, None) == -2
+    assert lib.ctrex_nn_conv3(ctx, None, 16, 0, 16, _vp(w), None, _vp(x), 16, 0, 16, 4, 4, 4, 0,
+                              None) == -1
+
+
+# ---------------------------------------------------------------- network --
+def _oracle_params(net):
+    """The network's parameters as the oracle sees them: weights BF16 (as
+    packed), biases and head FP32."""
+    p = {k: v.astype(np.float64) for k, v in net.params().items()}
+    for k in p:
+        if k.endswith(".w") and not k.startswith("head"):
+            p[k] = _bf(p[k])
+    return p
+
+
+def _net_close(got, ref):
+    """Network outputs: BF16-storage bound (relative L2 1e-2, max 3e-2)."""
+    scale = np.abs(ref).max()
+    l2 = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    err = np.abs(got - ref).max() / scale
+    assert l2 <= 1e-2 and err <= 3e-2, (l2, err)
+
+
+def _rand_net(seed, head_std=0.3):
+    from paper_2609_30166_amd.unet import UNet, param_shapes
+    r = _rng(20, seed)
+    params = {}
+    for k, s in param_shapes().items():
+        if k.endswith(".b"):
+            params[k] = r.normal(0, 0.05, size=s)
+        elif k == "head.w":
+            params[k] = r.normal(0, head_std, size=s)
+        else:
+            fan = s[1] * s[2] if k[:2] != "up" else s[0]
+            params[k] = r.normal(0, np.sqrt(2.0 / fan), size=s)
+    return UNet(DEV, params=params)
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (8, 16, 32)])
+def test_network_forward_matches_oracle(shape):
+    _skip()
+    from oracle import unet as ou
+    net = _rand_net(1)
+    x = _rng(21, *shape).uniform(0, 1, size=shape).astype(np.float32)
+    out = net.forward(_dev_f(x))
+    ref = ou.forward(x.astype(np.float64), _oracle_params(net), round_activations=True).numpy()
+    got = _host(out)
+    _net_close(got - x, ref - x)
+    # intermediate activations agree too (channels-last views)
+    tens = {}
+    ou.forward(x.astype(np.float64), _oracle_params(net), round_activations=True, tensors=tens)
+    acts = net.activations(_dev_f(x))
+    for k_gpu, k_or in (("a1", "a1"), ("p2", "p2"), ("b3", "b3"), ("d1", "d1")):
+        g, r = _host(acts[k_gpu]), tens[k_or].numpy()
+        assert np.linalg.norm(g - r) <= 1e-2 * np.linalg.norm(r), k_gpu
+    cat1 = _host(acts["cat1"])
+    np.testing.assert_allclose(cat1[..., 16:], tens["e1"].numpy(), rtol=2e-2, atol=1e-2)
+
+
+def test_network_gradients_match_oracle():
+    _skip()
+    from oracle import unet as ou
+    shape = (16, 16, 16)
+    net = _rand_net(2)
+    r = _rng(22)
+    x = r.uniform(0, 1, size=shape).astype(np.float32)
+    t = (x + 0.1 * r.normal(size=shape)).astype(np.float32)
+    xd, td = _dev_f(x), _dev_f(t)
+    out = net.forward(xd, train=True)
+    dout = torch.empty_like(out)
+    loss = net.mse(out, td, grad=dout)
+    net.backward(dout)
+    g_gpu = net.grads()
+    ploss, g_ref = ou.loss_and_grads(x.astype(np.float64), t.astype(np.float64), _oracle_params(net))
+    assert abs(loss - ploss) <= 1e-2 * ploss
+    num = den = 0.0
+    for k, gr in g_ref.items():
+        gg = g_gpu[k].astype(np.float64)
+        rel = np.linalg.norm(gg - gr) / max(np.linalg.norm(gr), 1e-30)
+        assert rel <= 5e-2, (k, rel)
+        num += np.sum((gg - gr) ** 2)
+        den += np.sum(gr ** 2)
+    assert np.sqrt(num / den) <= 2e-2
+
+
+def test_train_step_matches_oracle_adam_and_lowers_loss():
+    _skip()
+    from oracle import unet as ou
+    shape = (16, 16, 16)
+    net = _rand_net(3, head_std=0.05)
+    r = _rng(23)
+    x = r.uniform(0, 1, size=shape).astype(np.float32)
+    t = (0.8 * x).astype(np.float32)
+    xd, td = _dev_f(x), _dev_f(t)
+    p0 = net.params()
+    l0 = net.train_step(xd, td, lr=1e-3)
+    g = net.grads()
+    p1 = net.params()
+    for k in p0:
+        want, _, _ = ou.adam_step(p0[k].astype(np.float64), g[k].astype(np.float64),
+                                  np.zeros(p0[k].shape), np.zeros(p0[k].shape), 1)
+        np.testing.assert_allclose(p1[k], want, rtol=0, atol=2e-6)
+    losses = [l0] + [net.train_step(xd, td, lr=1e-3) for _ in range(30)]
+    assert losses[-1] < 0.7 * losses[0], losses[::5]
+
+
+def test_network_full_size_sampled_against_oracle():
+    """256^3 volume (the learned-correction configuration): the correction at
+    a 32^3 interior block equals the oracle's on a 96^3 crop around it: an
+    output voxel depends on inputs fewer than 32 voxels away (2 + 1 + 4 + 2 +
+    8 + 4 + 2 along each axis, pooling windows included), so the crop's own
+    zero padding cannot reach the block."""
+    _skip()
+    from oracle import unet as ou
+    N = 256
+    net = _rand_net(4)
+    g = torch.Generator(device="cpu").manual_seed(5)
+    x = torch.rand((N, N, N), generator=g, dtype=torch.float32)
+    out = _host(net.forward(x.to(DEV)))
+    assert np.all(np.isfinite(out))
+    c0 = 96   # crop [96, 192)^3, block [128, 160)^3
+    crop = x[c0:c0 + 96, c0:c0 + 96, c0:c0 + 96].double()
+    ref = ou.forward(crop, _oracle_params(net), round_activations=True).numpy()
+    blk = slice(32, 64)
+    got_b = out[c0 + 32:c0 + 64, c0 + 32:c0 + 64, c0 + 32:c0 + 64]
+    ref_b = ref[blk, blk, blk]
+    xb = crop.numpy()[blk, blk, blk]
+    _net_close(got_b - xb, ref_b - xb)
