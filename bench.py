@@ -12,14 +12,27 @@ number of trilinear samples of one forward projection.  Kernel times come
 from HIP events the library records on its launch stream inside the timed
 steps.  The CPU baseline is the FP64 oracle on a bounded view subset.
 
+The JSON line also carries, when the trained correction network is
+present, the time-to-PSNR comparison of the learned pipeline (4 stages of
+SIRT + U-Net) against 50 plain SIRT iterations on one held-out phantom of the
+learned-correction configuration (256^3, 180 x 384^2, Poisson noise).
+
+HBM traffic: ``roofline.traffic`` is read from the committed counter summary
+(two rocprofv3 --pmc passes, FETCH_SIZE then WRITE_SIZE, scaled by the
+same counters of a plain copy kernel of known size, ``--copy-calibrate``);
+it is null when the dominant kernel's sources changed since.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|bf16]
+                       [--copy-calibrate] [--no-learned]
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,6 +42,12 @@ sys.path.insert(0, ROOT)
 METRIC = "FP+BP Gsamples/s @512³×720 proj; time-to-PSNR learned vs plain SIRT"
 HBM_PEAK_GBS = 8000.0
 GATHER_BYTES = {"f32": 32, "bf16": 16}   # 8 voxel reads per sample
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_sirt_512cube_720x768sq.md")
+WEIGHTS_FILE = os.path.join(ROOT, "paper_2609_30166_amd", "weights", "unet_learned_256.npz")
+KERNEL_SOURCES = {
+    "bp_brick_kernel": ["backproject.hip", "ray_common.h", "ctrex_internal.h"],
+    "fp_kernel": ["projector.hip", "ray_common.h", "ctrex_internal.h"],
+}
 
 
 def _log(msg):
@@ -56,6 +75,77 @@ def cpu_baseline(cfg, x, n_views):
                                                                         t2 - t1)}
 
 
+def source_hash(kernel):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2609_30166_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, dtype):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary,
+    or None if absent or taken on other sources."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1)).get("%s/%s" % (kernel, dtype))
+    if not rec or rec.get("source_hash") != source_hash(kernel):
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def copy_calibration(dev):
+    """A plain copy of 2^27 floats (512 MiB read + 512 MiB written) through the
+    library's conversion kernel, for scaling the FETCH/WRITE counters."""
+    import torch
+    from paper_2609_30166_amd import _lib
+
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    import ctypes
+    ctx = ctypes.c_void_p()
+    L = _lib.lib()
+    _lib.check(None, L.ctrex_create(ctypes.byref(ctx), dev.index))
+    for _ in range(3):
+        _lib.check(ctx, L.ctrex_convert(ctx, ctypes.c_void_p(src.data_ptr()), _lib.F32,
+                                        ctypes.c_void_p(dst.data_ptr()), _lib.F32, n, None))
+    torch.cuda.synchronize()
+    L.ctrex_destroy(ctx)
+    _log("copy calibration: 3 copies of %d bytes" % (4 * n))
+
+
+def time_to_psnr(dev):
+    """Learned 4-stage pipeline vs 50 plain SIRT iterations on one held-out
+    phantom; None when the trained weights are not present."""
+    if not os.path.exists(WEIGHTS_FILE):
+        return None
+    from paper_2609_30166_amd import learned
+    from paper_2609_30166_amd.train_unet import load
+    from synth import configs
+
+    cfg, geom = learned.learned_geometry(device=dev)
+    net = load(WEIGHTS_FILE, dev)
+    seed = list(configs.TEST_SEEDS)[0]
+    res = learned.compare(geom, net, cfg, [seed], sirt_iters=50, n_stages=4,
+                          log=lambda s: _log("learned: " + s))
+    r = res["rows"][0]
+    return {"sirt_iters": 50, "stages": 4, "phantom_seed": seed,
+            "psnr_sirt_db": r["psnr_sirt"], "psnr_learned_db": r["psnr_learned"],
+            "psnr_sirt_4_db": r["psnr_sirt_same_budget"],
+            "resid_sirt": r["resid_sirt"], "resid_learned": r["resid_learned"],
+            "t_sirt_s": r["t_sirt"], "t_learned_s": r["t_learned"],
+            "time_ratio": r["t_learned"] / r["t_sirt"],
+            "reaches_sirt_psnr": bool(r["psnr_learned"] >= r["psnr_sirt"]),
+            "workload": "256^3, 180 projections of 384x384, Poisson I0=1e4, seeded held-out "
+                        "phantom; inference only"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +155,10 @@ def main():
     ap.add_argument("--cpu-views", type=int, default=2,
                     help="views of the CPU-oracle baseline sample (0 = skip)")
     ap.add_argument("--n-proj", type=int, default=720, help=argparse.SUPPRESS)
+    ap.add_argument("--copy-calibrate", action="store_true",
+                    help="also run a plain copy kernel of known size (counter calibration)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-vs-SIRT time-to-PSNR comparison")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -114,7 +208,7 @@ def main():
     fp_ms = prof["forward"][0] / max(prof["forward"][1], 1)
     bp_ms = prof["back"][0] / max(prof["back"][1], 1)
     up_ms = prof["update"][0] / max(prof["update"][1], 1)
-    dom, dom_ms = ("bp_kernel", bp_ms) if bp_ms >= fp_ms else ("fp_kernel", fp_ms)
+    dom, dom_ms = ("bp_brick_kernel", bp_ms) if bp_ms >= fp_ms else ("fp_kernel", fp_ms)
     achieved = GATHER_BYTES[args.dtype] * n_s / (dom_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
@@ -144,11 +238,19 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(dom, args.dtype),
             "basis": "gather-equivalent bytes: %d B per sample (8 voxel reads) x %d samples "
                      "per launch / mean launch time" % (GATHER_BYTES[args.dtype], n_s),
         },
     }
+    if args.copy_calibrate:
+        copy_calibration(dev)
+    del b, vol, ws, xt
+    g.close()
+    torch.cuda.empty_cache()
+    if not args.no_learned:
+        _log("learned pipeline vs SIRT-50 ...")
+        out["time_to_psnr"] = time_to_psnr(dev)
     if args.cpu_views > 0:
         _log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(cfg, x, args.cpu_views)

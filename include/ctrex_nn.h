@@ -115,17 +115,24 @@ CTREX_API int ctrex_nn_maxpool2_backward(ctrex_ctx *ctx, const void *in, int32_t
 CTREX_API int ctrex_nn_relu_backward(ctrex_ctx *ctx, const void *y, void *g, int32_t cs,
                                      int32_t off, int32_t c, int64_t n_vox, void *stream);
 
-/* Head and residual: out[v] = x[v] + b + sum_c h[c] act[v][c] (x, out FP32,
- * act BF16 dense with c channels, h FP32 [c], b FP32 [1]). */
-CTREX_API int ctrex_nn_head(ctrex_ctx *ctx, const void *act, int32_t c, const float *h,
-                            const float *b, const float *x, float *out, int64_t n_vox,
-                            void *stream);
+/* Network input: xb[v] = BF16(scale x[v]) (round to nearest even); x FP32.
+ * The scale brings volumes stored in small physical units (attenuation per
+ * volume width) to the O(1) range the network's biases work in. */
+CTREX_API int ctrex_nn_input(ctrex_ctx *ctx, const float *x, float scale, void *xb, int64_t n_vox,
+                             void *stream);
 
-/* Backward of ctrex_nn_head: dact[v][c] = dout[v] h[c] (BF16), dh[c] =
- * sum_v dout[v] act[v][c], db = sum_v dout[v] (FP32, deterministic). */
+/* Head and residual: out[v] = x[v] + out_scale (b + sum_c h[c] act[v][c])
+ * (x, out FP32, act BF16 dense with c channels, h FP32 [c], b FP32 [1]);
+ * out_scale = 1 / the input scale maps the correction back to x's units. */
+CTREX_API int ctrex_nn_head(ctrex_ctx *ctx, const void *act, int32_t c, const float *h,
+                            const float *b, const float *x, float out_scale, float *out,
+                            int64_t n_vox, void *stream);
+
+/* Backward of ctrex_nn_head: with d = out_scale dout, dact[v][c] = d[v] h[c]
+ * (BF16), dh[c] = sum_v d[v] act[v][c], db = sum_v d[v] (FP32, deterministic). */
 CTREX_API int ctrex_nn_head_backward(ctrex_ctx *ctx, const void *act, int32_t c, const float *h,
-                                     const float *dout, void *dact, float *dh, float *db,
-                                     int64_t n_vox, void *stream);
+                                     float out_scale, const float *dout, void *dact, float *dh,
+                                     float *db, int64_t n_vox, void *stream);
 
 /* Mean squared error over n values: *loss (host, optional; waits) =
  * sum (a - t)^2 / n in FP64, grad (optional) = 2 (a - t) / n. */

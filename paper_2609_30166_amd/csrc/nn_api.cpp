@@ -38,10 +38,12 @@ hipError_t launch_maxpool2_bwd(const void *in, int in_cs, int in_off, int c, con
 hipError_t launch_relu_bwd(const void *y, void *g, int cs, int off, int c, long long nvox,
                            hipStream_t s);
 hipError_t launch_head(const void *act, int c, const float *h, const float *b, const float *x,
-                       float *out, long long n, hipStream_t s);
+                       float scale, float *out, long long n, hipStream_t s);
+hipError_t launch_scale_bf16(const float *x, float scale, void *xb, long long n, hipStream_t s);
 size_t head_bwd_scratch(int c);
-hipError_t launch_head_bwd(const void *act, int c, const float *h, const float *dout, void *dact,
-                           float *dh, float *db, long long n, double *scratch, hipStream_t s);
+hipError_t launch_head_bwd(const void *act, int c, const float *h, float scale, const float *dout,
+                           void *dact, float *dh, float *db, long long n, double *scratch,
+                           hipStream_t s);
 hipError_t launch_mse(const float *a, const float *t, long long n, float *grad, double *partial,
                       int blocks, hipStream_t s);
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, long long n, float lr, float b1,
@@ -235,27 +237,42 @@ int ctrex_nn_relu_backward(ctrex_ctx *c, const void *y, void *g, int32_t cs, int
     return CTREX_OK;
 }
 
+int ctrex_nn_input(ctrex_ctx *c, const float *x, float scale, void *xb, int64_t n_vox,
+                   void *stream) {
+    int st = begin(c);
+    if (st) return st;
+    if (!x || !xb) return fail(c, CTREX_EINVAL, "NULL pointer");
+    if (n_vox < 0) return fail(c, CTREX_ESHAPE, "bad sizes");
+    if (!std::isfinite(scale) || scale == 0.0f) return fail(c, CTREX_EINVAL, "scale must be finite and non-zero");
+    if (n_vox == 0) return CTREX_OK;
+    CTREX_HIP(c, nn::launch_scale_bf16(x, scale, xb, n_vox, static_cast<hipStream_t>(stream)));
+    return CTREX_OK;
+}
+
 int ctrex_nn_head(ctrex_ctx *c, const void *act, int32_t ch, const float *h, const float *b,
-                  const float *x, float *out, int64_t n_vox, void *stream) {
+                  const float *x, float out_scale, float *out, int64_t n_vox, void *stream) {
     int st = begin(c);
     if (st) return st;
     if (!act || !h || !b || !x || !out) return fail(c, CTREX_EINVAL, "NULL pointer");
     if (ch < 1 || ch > 64 || n_vox < 0) return fail(c, CTREX_ESHAPE, "bad sizes");
+    if (!std::isfinite(out_scale)) return fail(c, CTREX_EINVAL, "out_scale must be finite");
     if (n_vox == 0) return CTREX_OK;
-    CTREX_HIP(c, nn::launch_head(act, ch, h, b, x, out, n_vox, static_cast<hipStream_t>(stream)));
+    CTREX_HIP(c, nn::launch_head(act, ch, h, b, x, out_scale, out, n_vox,
+                                 static_cast<hipStream_t>(stream)));
     return CTREX_OK;
 }
 
 int ctrex_nn_head_backward(ctrex_ctx *c, const void *act, int32_t ch, const float *h,
-                           const float *dout, void *dact, float *dh, float *db, int64_t n_vox,
-                           void *stream) {
+                           float out_scale, const float *dout, void *dact, float *dh, float *db,
+                           int64_t n_vox, void *stream) {
     int st = begin(c);
     if (st) return st;
     if (!act || !h || !dout || !dact) return fail(c, CTREX_EINVAL, "NULL pointer");
     if (ch != 16 || n_vox < 1) return fail(c, CTREX_ESHAPE, "the head takes 16 channels");
+    if (!std::isfinite(out_scale)) return fail(c, CTREX_EINVAL, "out_scale must be finite");
     void *scr;
     if ((st = ctx_scratch(c, nn::head_bwd_scratch(ch), &scr))) return st;
-    CTREX_HIP(c, nn::launch_head_bwd(act, ch, h, dout, dact, dh, db, n_vox,
+    CTREX_HIP(c, nn::launch_head_bwd(act, ch, h, out_scale, dout, dact, dh, db, n_vox,
                                      static_cast<double *>(scr), static_cast<hipStream_t>(stream)));
     return CTREX_OK;
 }

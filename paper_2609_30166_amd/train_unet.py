@@ -26,19 +26,21 @@ from . import learned
 from .unet import UNet
 
 
-def save(path, net, meta):
+def save(path, net, meta, optimizer_state=True):
+    """Parameters (and, optionally, the Adam moments and step) as .npz."""
     st = net.state_dict()
-    np.savez(path, step=st["step"], theta=st["theta"], m=st["m"], v=st["v"],
-             **{"p." + k: v for k, v in net.params().items()},
-             meta=json.dumps(meta))
+    extra = dict(step=st["step"], theta=st["theta"], m=st["m"], v=st["v"]) if optimizer_state else {}
+    np.savez(path, scale=np.float64(net.scale), meta=json.dumps(meta),
+             **{"p." + k: v for k, v in net.params().items()}, **extra)
 
 
 def load(path, device=None):
     """A UNet with the parameters (and Adam state) stored by ``save``."""
     z = np.load(path, allow_pickle=False)
     params = {k[2:]: z[k] for k in z.files if k.startswith("p.")}
-    net = UNet(device, params=params)
-    net.load_state_dict(dict(theta=z["theta"], m=z["m"], v=z["v"], step=int(z["step"])))
+    net = UNet(device, params=params, scale=float(z["scale"]))
+    if "theta" in z.files:
+        net.load_state_dict(dict(theta=z["theta"], m=z["m"], v=z["v"], step=int(z["step"])))
     return net
 
 
@@ -51,6 +53,12 @@ def main(argv=None):
     ap.add_argument("--sirt-iters", type=int, default=50)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--scale", type=float, default=None,
+                    help="network input scale (default: the volume width, since the "
+                         "configuration stores attenuation per volume width)")
+    ap.add_argument("--epochs", type=int, default=1)
+    ap.add_argument("--weights-only", default=None,
+                    help="also write the parameters alone (no optimizer state) here")
     ap.add_argument("--resume", default=None, help="weights file to continue from")
     ap.add_argument("--out", default="unet_weights.npz")
     ap.add_argument("--summary", default=None)
@@ -60,15 +68,23 @@ def main(argv=None):
         print(msg, flush=True)
 
     cfg, geom = learned.learned_geometry()
-    net = load(a.resume, geom.device) if a.resume else UNet(geom.device, seed=a.seed)
+    scale = a.scale if a.scale else float(min(cfg.shape[1:]))
+    net = load(a.resume, geom.device) if a.resume else UNet(geom.device, seed=a.seed, scale=scale)
     seeds = list(configs.TRAIN_SEEDS)[:a.phantoms]
     t0 = time.time()
-    hist = learned.train(geom, net, cfg, seeds, lr=a.lr, n_stages=a.stages,
-                         iters_per_stage=a.iters_per_stage, log=log)
+    hists = []
+    for ep in range(a.epochs):
+        log("epoch %d" % (ep + 1))
+        hists.append(learned.train(geom, net, cfg, seeds, lr=a.lr, n_stages=a.stages,
+                                   iters_per_stage=a.iters_per_stage, log=log))
+    hist = np.concatenate(hists)
     t_train = time.time() - t0
-    meta = dict(config="learned", phantoms=a.phantoms, stages=a.stages,
-                iters_per_stage=a.iters_per_stage, lr=a.lr, seed=a.seed, train_s=t_train)
+    meta = dict(config="learned", phantoms=a.phantoms, epochs=a.epochs, stages=a.stages,
+                iters_per_stage=a.iters_per_stage, lr=a.lr, seed=a.seed, scale=net.scale,
+                train_s=t_train, adam_steps=net.step)
     save(a.out, net, meta)
+    if a.weights_only:
+        save(a.weights_only, net, meta, optimizer_state=False)
     log("trained on %d phantoms in %.1f s -> %s" % (len(seeds), t_train, a.out))
     summary = dict(meta=meta, loss_first=hist[:8].mean(0).tolist(),
                    loss_last=hist[-8:].mean(0).tolist())

@@ -9,7 +9,11 @@ names as the extension of its operator framework (Sec. 5):
     level 3 (D/4 ...):      pool, conv 32->64, conv 64->64
     decoder level 2:        up 64->32, concat [up, e2], conv 64->32, conv 32->32
     decoder level 1:        up 32->16, concat [up, e1], conv 32->16, conv 16->16
-    head:                   out = x + b + sum_c h_c d1_c
+    head:                   out = x + (b + sum_c h_c d1_c) / s
+
+with the network reading s x: the fixed input scale s brings volumes stored in
+small physical units (attenuation per volume width) to the O(1) range the
+biases work in, and the head maps the correction back.
 
 Every 3x3x3 convolution is followed by ReLU; the up-sampling is a 2x2x2
 stride-2 transposed convolution.  Activations are BF16 channels-last in
@@ -75,10 +79,10 @@ class UNet:
     ``params``: optional {name: array} in the master layouts of
     ``param_shapes()`` (conv [cout][cin][27], up-sampling [cin][cout][8]);
     otherwise He-normal weights from ``seed`` with zero biases and a head of
-    standard deviation ``head_std``.
+    standard deviation ``head_std``.  ``scale``: the input scale s.
     """
 
-    def __init__(self, device=None, params=None, seed=0, head_std=1e-2):
+    def __init__(self, device=None, params=None, seed=0, head_std=1e-2, scale=1.0):
         dev = torch.device(device if device is not None else "cuda")
         if dev.type != "cuda":
             raise ValueError("the network runs on a HIP device")
@@ -98,6 +102,9 @@ class UNet:
             self._offsets[k] = (n, s)
             n += (size + 3) // 4 * 4
         self.n_params = n
+        self.scale = float(scale)
+        if not np.isfinite(self.scale) or self.scale <= 0:
+            raise ValueError("scale must be a positive finite number")
         self.theta = torch.zeros(n, dtype=torch.float32, device=self.device)
         self.grad = torch.zeros_like(self.theta)
         self.m = torch.zeros_like(self.theta)
@@ -160,12 +167,14 @@ class UNet:
     def state_dict(self):
         """Parameters, Adam moments and step (checkpoint)."""
         return dict(theta=self.theta.cpu().numpy().copy(), m=self.m.cpu().numpy().copy(),
-                    v=self.v.cpu().numpy().copy(), step=self.step)
+                    v=self.v.cpu().numpy().copy(), step=self.step, scale=self.scale)
 
     def load_state_dict(self, st):
         for name in ("theta", "m", "v"):
             getattr(self, name).copy_(torch.from_numpy(np.asarray(st[name], dtype=np.float32)))
         self.step = int(st["step"])
+        if "scale" in st:
+            self.scale = float(st["scale"])
         self._pack()
 
     def _pack(self):
@@ -241,10 +250,8 @@ class UNet:
         D, H, W = self.check_shape(x.shape)
         l1, l2, l3 = (D, H, W), (D // 2, H // 2, W // 2), (D // 4, H // 4, W // 4)
         b = self._buffers((D, H, W), train)
-        L = _lib.lib()
         n1 = D * H * W
-        check(self._ctx, L.ctrex_convert(self._ctx, _vp(x), _lib.F32, _vp(b["xb"]), _lib.BF16,
-                                         n1, self._s()))
+        self._call("ctrex_nn_input", _vp(x), self.scale, _vp(b["xb"]), n1, self._s())
         self._conv("e1a", b["xb"], 1, 0, b["a1"], 16, 0, l1)
         self._conv("e1b", b["a1"], 16, 0, b["cat1"], 32, 16, l1)
         self._pool(b["cat1"], 32, 16, 16, b["p1"], l1)
@@ -262,7 +269,7 @@ class UNet:
         if out is None:
             out = torch.empty_like(x)
         self._call("ctrex_nn_head", _vp(b["d1"]), 16, _vp(self.p("head.w")),
-                   _vp(self.p("head.b")), _vp(x), _vp(out), n1, self._s())
+                   _vp(self.p("head.b")), _vp(x), 1.0 / self.scale, _vp(out), n1, self._s())
         self._saved = (b, (l1, l2, l3)) if train else None
         return out
 
@@ -308,7 +315,8 @@ class UNet:
         n2, n3 = n1 // 8, n1 // 64
         g = self.grad
         # head and decoder level 1
-        self._call("ctrex_nn_head_backward", _vp(b["d1"]), 16, _vp(self.p("head.w")), _vp(dout),
+        self._call("ctrex_nn_head_backward", _vp(b["d1"]), 16, _vp(self.p("head.w")),
+                   1.0 / self.scale, _vp(dout),
                    _vp(b["g1a"]), _vp(self.p("head.w", g)), _vp(self.p("head.b", g)), n1,
                    self._s())
         self._relu_bwd(b["d1"], b["g1a"], 16, 0, 16, n1)

@@ -320,17 +320,29 @@ def test_head_forward_backward(L, ctx):
     dout = r.normal(size=n).astype(np.float32).astype(np.float64)
     ad, hd, bd, xd, dd = _dev_bf(act), _dev_f(h), _dev_f(bb), _dev_f(x), _dev_f(dout)
     out = torch.empty(n, dtype=torch.float32, device=DEV)
-    _call(L, ctx, "ctrex_nn_head", _vp(ad), 16, _vp(hd), _vp(bd), _vp(xd), _vp(out), n, None)
-    _close(_host(out), x + bb[0] + act @ h, rel=1e-6)
-    dact = torch.empty(n * 16, dtype=torch.bfloat16, device=DEV)
-    dh = torch.empty(16, dtype=torch.float32, device=DEV)
-    db = torch.empty(1, dtype=torch.float32, device=DEV)
-    _call(L, ctx, "ctrex_nn_head_backward", _vp(ad), 16, _vp(hd), _vp(dd), _vp(dact), _vp(dh),
-          _vp(db), n, None)
-    ref = np.outer(dout, h)
-    assert np.all(np.abs(_host(dact).reshape(n, 16) - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-30)
-    _close(_host(dh), dout @ act, rel=1e-6)
-    _close(_host(db), [dout.sum()], rel=1e-6)
+    for s in (1.0, 0.25):
+        _call(L, ctx, "ctrex_nn_head", _vp(ad), 16, _vp(hd), _vp(bd), _vp(xd), s, _vp(out), n,
+              None)
+        _close(_host(out), x + s * (bb[0] + act @ h), rel=1e-6)
+        dact = torch.empty(n * 16, dtype=torch.bfloat16, device=DEV)
+        dh = torch.empty(16, dtype=torch.float32, device=DEV)
+        db = torch.empty(1, dtype=torch.float32, device=DEV)
+        _call(L, ctx, "ctrex_nn_head_backward", _vp(ad), 16, _vp(hd), s, _vp(dd), _vp(dact),
+              _vp(dh), _vp(db), n, None)
+        ref = s * np.outer(dout, h)
+        assert np.all(np.abs(_host(dact).reshape(n, 16) - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-30)
+        _close(_host(dh), s * (dout @ act), rel=1e-6)
+        _close(_host(db), [s * dout.sum()], rel=1e-6)
+
+
+def test_scaled_input_conversion(L, ctx):
+    n = 5000
+    x = _rng(12).uniform(0, 0.01, size=n).astype(np.float32)
+    xd = _dev_f(x)
+    xb = torch.empty(n, dtype=torch.bfloat16, device=DEV)
+    _call(L, ctx, "ctrex_nn_input", _vp(xd), 256.0, _vp(xb), n, None)
+    want = torch.from_numpy(x * np.float32(256.0)).bfloat16()
+    assert torch.equal(xb.cpu(), want)
 
 
 def test_mse_and_adam(L, ctx):
@@ -399,7 +411,7 @@ def _net_close(got, ref):
     assert l2 <= 1e-2 and err <= 3e-2, (l2, err)
 
 
-def _rand_net(seed, head_std=0.3):
+def _rand_net(seed, head_std=0.3, scale=1.0):
     from paper_2609_30166_amd.unet import UNet, param_shapes
     r = _rng(20, seed)
     params = {}
@@ -411,22 +423,25 @@ def _rand_net(seed, head_std=0.3):
         else:
             fan = s[1] * s[2] if k[:2] != "up" else s[0]
             params[k] = r.normal(0, np.sqrt(2.0 / fan), size=s)
-    return UNet(DEV, params=params)
+    return UNet(DEV, params=params, scale=scale)
 
 
-@pytest.mark.parametrize("shape", [(16, 16, 16), (8, 16, 32)])
-def test_network_forward_matches_oracle(shape):
+@pytest.mark.parametrize("shape,scale", [((16, 16, 16), 1.0), ((8, 16, 32), 1.0),
+                                         ((16, 16, 16), 256.0)])
+def test_network_forward_matches_oracle(shape, scale):
     _skip()
     from oracle import unet as ou
-    net = _rand_net(1)
-    x = _rng(21, *shape).uniform(0, 1, size=shape).astype(np.float32)
+    net = _rand_net(1, scale=scale)
+    x = (_rng(21, *shape).uniform(0, 1, size=shape) / scale).astype(np.float32)
     out = net.forward(_dev_f(x))
-    ref = ou.forward(x.astype(np.float64), _oracle_params(net), round_activations=True).numpy()
+    ref = ou.forward(x.astype(np.float64), _oracle_params(net), round_activations=True,
+                     scale=scale).numpy()
     got = _host(out)
     _net_close(got - x, ref - x)
     # intermediate activations agree too (channels-last views)
     tens = {}
-    ou.forward(x.astype(np.float64), _oracle_params(net), round_activations=True, tensors=tens)
+    ou.forward(x.astype(np.float64), _oracle_params(net), round_activations=True, tensors=tens,
+               scale=scale)
     acts = net.activations(_dev_f(x))
     for k_gpu, k_or in (("a1", "a1"), ("p2", "p2"), ("b3", "b3"), ("d1", "d1")):
         g, r = _host(acts[k_gpu]), tens[k_or].numpy()
@@ -435,21 +450,23 @@ def test_network_forward_matches_oracle(shape):
     np.testing.assert_allclose(cat1[..., 16:], tens["e1"].numpy(), rtol=2e-2, atol=1e-2)
 
 
-def test_network_gradients_match_oracle():
+@pytest.mark.parametrize("scale", [1.0, 256.0])
+def test_network_gradients_match_oracle(scale):
     _skip()
     from oracle import unet as ou
     shape = (16, 16, 16)
-    net = _rand_net(2)
+    net = _rand_net(2, scale=scale)
     r = _rng(22)
-    x = r.uniform(0, 1, size=shape).astype(np.float32)
-    t = (x + 0.1 * r.normal(size=shape)).astype(np.float32)
+    x = (r.uniform(0, 1, size=shape) / scale).astype(np.float32)
+    t = (x + 0.1 * r.normal(size=shape) / scale).astype(np.float32)
     xd, td = _dev_f(x), _dev_f(t)
     out = net.forward(xd, train=True)
     dout = torch.empty_like(out)
     loss = net.mse(out, td, grad=dout)
     net.backward(dout)
     g_gpu = net.grads()
-    ploss, g_ref = ou.loss_and_grads(x.astype(np.float64), t.astype(np.float64), _oracle_params(net))
+    ploss, g_ref = ou.loss_and_grads(x.astype(np.float64), t.astype(np.float64),
+                                     _oracle_params(net), scale=scale)
     assert abs(loss - ploss) <= 1e-2 * ploss
     num = den = 0.0
     for k, gr in g_ref.items():

@@ -141,3 +141,14 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(p1, p0 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
     np.testing.assert_allclose(m, 0.1 * g)
     np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_input_scale_is_a_change_of_units():
+    """x + U(s x)/s equals (s x + U(s x)) / s: the scaled network is the
+    unscaled one applied in units where the volume is s times larger."""
+    p = unet.init_params(12, head_std=0.5)
+    x = _rng(13).uniform(0, 0.01, size=(8, 8, 8))
+    s = 256.0
+    a = unet.forward(x, p, scale=s).numpy()
+    b = unet.forward(s * x, p).numpy() / s
+    np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-18)
