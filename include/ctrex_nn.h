@@ -134,10 +134,13 @@ CTREX_API int ctrex_nn_head_backward(ctrex_ctx *ctx, const void *act, int32_t c,
                                      float out_scale, const float *dout, void *dact, float *dh,
                                      float *db, int64_t n_vox, void *stream);
 
-/* Mean squared error over n values: *loss (host, optional; waits) =
- * sum (a - t)^2 / n in FP64, grad (optional) = 2 (a - t) / n. */
+/* Weighted mean squared error over n values: *loss (host, optional; waits)
+ * = weight sum (a - t)^2 / n with the sum in FP64, grad (optional) =
+ * 2 weight (a - t) / n.  A weight of s^2 measures the error in the units of a
+ * network that reads s x, which keeps weight gradients well above Adam's
+ * epsilon when volumes are stored in small units. */
 CTREX_API int ctrex_nn_mse(ctrex_ctx *ctx, const float *a, const float *t, int64_t n,
-                           double *loss, float *grad, void *stream);
+                           float weight, double *loss, float *grad, void *stream);
 
 /* One Adam step over n FP32 parameters (bias-corrected, step >= 1). */
 CTREX_API int ctrex_nn_adam(ctrex_ctx *ctx, float *param, const float *grad, float *m, float *v,

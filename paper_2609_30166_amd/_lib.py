@@ -89,7 +89,8 @@ def lib():
                                              ctypes.c_int64, vp]),
             "ctrex_nn_head_backward": (ctypes.c_int, [vp, vp, i32, vp, ctypes.c_float, vp, vp, vp,
                                                       vp, ctypes.c_int64, vp]),
-            "ctrex_nn_mse": (ctypes.c_int, [vp, vp, vp, ctypes.c_int64, dp, vp, vp]),
+            "ctrex_nn_mse": (ctypes.c_int, [vp, vp, vp, ctypes.c_int64, ctypes.c_float, dp, vp,
+                                            vp]),
             "ctrex_nn_adam": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float,
                                              ctypes.c_float, ctypes.c_float, ctypes.c_float, i32,
                                              vp]),

@@ -905,10 +905,10 @@ hipError_t launch_head_bwd(const void *act, int c, const float *h, float scale, 
     return hipGetLastError();
 }
 
-hipError_t launch_mse(const float *a, const float *t, long long n, float *grad, double *partial,
-                      int blocks, hipStream_t s) {
-    hipLaunchKernelGGL(mse_kernel, dim3(blocks), dim3(NT), 0, s, a, t, n, 2.0f / static_cast<float>(n),
-                       grad, partial);
+hipError_t launch_mse(const float *a, const float *t, long long n, float weight, float *grad,
+                      double *partial, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(mse_kernel, dim3(blocks), dim3(NT), 0, s, a, t, n,
+                       static_cast<float>(2.0 * weight / static_cast<double>(n)), grad, partial);
     return hipGetLastError();
 }
 

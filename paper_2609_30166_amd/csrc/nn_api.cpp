@@ -44,8 +44,8 @@ size_t head_bwd_scratch(int c);
 hipError_t launch_head_bwd(const void *act, int c, const float *h, float scale, const float *dout,
                            void *dact, float *dh, float *db, long long n, double *scratch,
                            hipStream_t s);
-hipError_t launch_mse(const float *a, const float *t, long long n, float *grad, double *partial,
-                      int blocks, hipStream_t s);
+hipError_t launch_mse(const float *a, const float *t, long long n, float weight, float *grad,
+                      double *partial, int blocks, hipStream_t s);
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, long long n, float lr, float b1,
                        float b2, float eps, int step, hipStream_t s);
 hipError_t launch_pack(const float *w, int cout, int cin, int taps, bool mirror, void *wt,
@@ -277,24 +277,25 @@ int ctrex_nn_head_backward(ctrex_ctx *c, const void *act, int32_t ch, const floa
     return CTREX_OK;
 }
 
-int ctrex_nn_mse(ctrex_ctx *c, const float *a, const float *t, int64_t n, double *loss,
-                 float *grad, void *stream) {
+int ctrex_nn_mse(ctrex_ctx *c, const float *a, const float *t, int64_t n, float weight,
+                 double *loss, float *grad, void *stream) {
     int st = begin(c);
     if (st) return st;
     if (!a || !t) return fail(c, CTREX_EINVAL, "NULL pointer");
     if (n < 1) return fail(c, CTREX_ESHAPE, "n must be >= 1");
+    if (!std::isfinite(weight)) return fail(c, CTREX_EINVAL, "weight must be finite");
     const int blocks = 1024;
     void *scr;
     if ((st = ctx_scratch(c, sizeof(double) * (blocks + 1), &scr))) return st;
     double *part = static_cast<double *>(scr);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    CTREX_HIP(c, nn::launch_mse(a, t, n, grad, part, blocks, s));
+    CTREX_HIP(c, nn::launch_mse(a, t, n, weight, grad, part, blocks, s));
     if (loss) {
         CTREX_HIP(c, launch_sum_partials(part, blocks, part + blocks, s));
         double h = 0.0;
         CTREX_HIP(c, hipMemcpyAsync(&h, part + blocks, sizeof h, hipMemcpyDeviceToHost, s));
         CTREX_HIP(c, hipStreamSynchronize(s));
-        *loss = h / static_cast<double>(n);
+        *loss = static_cast<double>(weight) * h / static_cast<double>(n);
     }
     return CTREX_OK;
 }

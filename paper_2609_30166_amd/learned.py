@@ -109,24 +109,48 @@ class LearnedSirt:
         return x, stages
 
 
-def train(geom, net, cfg, seeds, lr=1e-3, n_stages=4, iters_per_stage=1, log=None,
-          log_every=8):
-    """Stage-wise training over the phantoms of ``seeds``; returns the loss
-    history [n_phantoms][n_stages]."""
+def train(geom, net, cfg, seeds, lr=1e-3, lr_final=None, n_stages=4, iters_per_stage=1,
+          crop=None, crop_steps=1, log=None, log_every=8, seed=0):
+    """Stage-wise training over the phantoms of ``seeds``.
+
+    Each stage runs the SIRT update(s) on the full volume, then takes
+    ``crop_steps`` Adam steps on random ``crop``^3 blocks of (iterate, truth)
+    (the whole volume when ``crop`` is None), then corrects the full volume
+    with the updated network to form the next stage's input.  The learning
+    rate falls linearly from ``lr`` to ``lr_final`` over the run.  Returns
+    per phantom and stage [loss of the SIRT iterate, loss after correction]
+    on the full volume (MSE to the truth, measured before the stage's steps
+    and after them)."""
+    rng = np.random.default_rng([seed, 23])
+    lr_final = lr if lr_final is None else lr_final
+    total = len(seeds) * n_stages * crop_steps
+    k_step = 0
     hist = []
     t0 = time.time()
-    for i, seed in enumerate(seeds):
-        x_true, b = make_sample(cfg, geom, seed)
+    nz, ny, nx = geom.shape
+    for i, pseed in enumerate(seeds):
+        x_true, b = make_sample(cfg, geom, pseed)
         x = torch.zeros(geom.shape, dtype=torch.float32, device=geom.device)
-        losses = []
+        rows = []
         for _ in range(n_stages):
             geom.sirt(x, b, iters_per_stage, norms=False)
-            losses.append(net.train_step(x, x_true, lr=lr))
+            before = net.mse(x, x_true)
+            for _ in range(crop_steps):
+                rate = lr + (lr_final - lr) * k_step / max(total - 1, 1)
+                k_step += 1
+                if crop:
+                    z0, y0, x0 = (int(rng.integers(0, n - crop + 1)) for n in (nz, ny, nx))
+                    sl = (slice(z0, z0 + crop), slice(y0, y0 + crop), slice(x0, x0 + crop))
+                    net.train_step(x[sl].contiguous(), x_true[sl].contiguous(), lr=rate)
+                else:
+                    net.train_step(x, x_true, lr=rate)
             x = net.forward(x)
-        hist.append(losses)
+            rows.append((before, net.mse(x, x_true)))
+        hist.append(rows)
         if log and (i % log_every == 0 or i + 1 == len(seeds)):
-            log("phantom %4d/%d seed %d  stage losses %s  %.1f s" % (
-                i + 1, len(seeds), seed, " ".join("%.3e" % v for v in losses), time.time() - t0))
+            log("phantom %4d/%d seed %d (%s) stage MSE sirt->corrected %s  lr %.2e  %.1f s" % (
+                i + 1, len(seeds), pseed, "ellipsoids" if pseed % 2 == 0 else "foam",
+                " ".join("%.2e->%.2e" % r for r in rows), rate, time.time() - t0))
     return np.asarray(hist)
 
 

@@ -52,6 +52,10 @@ def main(argv=None):
     ap.add_argument("--iters-per-stage", type=int, default=1)
     ap.add_argument("--sirt-iters", type=int, default=50)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-final", type=float, default=1e-4)
+    ap.add_argument("--crop", type=int, default=128,
+                    help="edge of the random training blocks (0 = whole volume)")
+    ap.add_argument("--crop-steps", type=int, default=8, help="Adam steps per stage sample")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--scale", type=float, default=None,
                     help="network input scale (default: the volume width, since the "
@@ -75,19 +79,23 @@ def main(argv=None):
     hists = []
     for ep in range(a.epochs):
         log("epoch %d" % (ep + 1))
-        hists.append(learned.train(geom, net, cfg, seeds, lr=a.lr, n_stages=a.stages,
-                                   iters_per_stage=a.iters_per_stage, log=log))
+        hists.append(learned.train(geom, net, cfg, seeds, lr=a.lr, lr_final=a.lr_final,
+                                   n_stages=a.stages, iters_per_stage=a.iters_per_stage,
+                                   crop=a.crop or None, crop_steps=a.crop_steps, log=log,
+                                   seed=a.seed + ep))
     hist = np.concatenate(hists)
     t_train = time.time() - t0
     meta = dict(config="learned", phantoms=a.phantoms, epochs=a.epochs, stages=a.stages,
-                iters_per_stage=a.iters_per_stage, lr=a.lr, seed=a.seed, scale=net.scale,
-                train_s=t_train, adam_steps=net.step)
+                iters_per_stage=a.iters_per_stage, lr=a.lr, lr_final=a.lr_final, crop=a.crop,
+                crop_steps=a.crop_steps, seed=a.seed, scale=net.scale, train_s=t_train,
+                adam_steps=net.step)
     save(a.out, net, meta)
     if a.weights_only:
         save(a.weights_only, net, meta, optimizer_state=False)
     log("trained on %d phantoms in %.1f s -> %s" % (len(seeds), t_train, a.out))
-    summary = dict(meta=meta, loss_first=hist[:8].mean(0).tolist(),
-                   loss_last=hist[-8:].mean(0).tolist())
+    summary = dict(meta=meta, mse_first=hist[:8].mean(0).tolist(),
+                   mse_last_ellipsoids=hist[-8::2].mean(0).tolist(),
+                   mse_last_foam=hist[-7::2].mean(0).tolist())
     if a.test > 0:
         res = learned.compare(geom, net, cfg, list(configs.TEST_SEEDS)[:a.test],
                               sirt_iters=a.sirt_iters, n_stages=a.stages,

@@ -365,10 +365,10 @@ class UNet:
         return self.grad
 
     # ------------------------------------------------------------- training
-    def mse(self, a, t, grad=None):
-        """Mean squared error (FP64 sum) and optionally its gradient into ``grad``."""
+    def mse(self, a, t, grad=None, weight=1.0):
+        """weight x mean squared error (FP64 sum), optionally its gradient into ``grad``."""
         loss = ctypes.c_double()
-        self._call("ctrex_nn_mse", _vp(a), _vp(t), a.numel(), ctypes.byref(loss),
+        self._call("ctrex_nn_mse", _vp(a), _vp(t), a.numel(), float(weight), ctypes.byref(loss),
                    _vp(grad) if grad is not None else None, self._s())
         return loss.value
 
@@ -379,10 +379,11 @@ class UNet:
         self._pack()
 
     def train_step(self, x, target, lr=1e-3):
-        """One Adam step on MSE(x + U(x), target); returns the loss before the step."""
+        """One Adam step on s^2 MSE(x + U(s x) / s, target), the error in the
+        network's own units; returns that loss before the step."""
         out = self.forward(x, train=True)
         b, _ = self._saved
-        loss = self.mse(out, target, grad=b["dout"])
+        loss = self.mse(out, target, grad=b["dout"], weight=self.scale ** 2)
         self.backward(b["dout"].view_as(x))
         self.adam(lr)
         return loss

@@ -354,9 +354,12 @@ def test_mse_and_adam(L, ctx):
     ad, td = _dev_f(a), _dev_f(t)
     grad = torch.empty(n, dtype=torch.float32, device=DEV)
     loss = ctypes.c_double()
-    _call(L, ctx, "ctrex_nn_mse", _vp(ad), _vp(td), n, ctypes.byref(loss), _vp(grad), None)
-    assert abs(loss.value - np.mean((a - t) ** 2)) <= 1e-6 * np.mean((a - t) ** 2)
-    _close(_host(grad), 2 * (a - t) / n, rel=1e-6)
+    for wgt in (1.0, 65536.0):
+        _call(L, ctx, "ctrex_nn_mse", _vp(ad), _vp(td), n, wgt, ctypes.byref(loss), _vp(grad),
+              None)
+        want = wgt * np.mean((a - t) ** 2)
+        assert abs(loss.value - want) <= 1e-6 * want
+        _close(_host(grad), 2 * wgt * (a - t) / n, rel=1e-6)
     p = r.normal(size=n)
     g = r.normal(size=n)
     m = r.normal(size=n) * 0.1
