@@ -125,6 +125,8 @@ def time_to_psnr(dev):
     phantom; None when the trained weights are not present."""
     if not os.path.exists(WEIGHTS_FILE):
         return None
+    import numpy as np
+
     from paper_2609_30166_amd import learned
     from paper_2609_30166_amd.train_unet import load
     from synth import configs
@@ -132,12 +134,14 @@ def time_to_psnr(dev):
     cfg, geom = learned.learned_geometry(device=dev)
     net = load(WEIGHTS_FILE, dev)
     seed = list(configs.TEST_SEEDS)[0]
-    res = learned.compare(geom, net, cfg, [seed], sirt_iters=50, n_stages=4,
-                          log=lambda s: _log("learned: " + s))
+    meta = json.loads(str(np.load(WEIGHTS_FILE, allow_pickle=False)["meta"]))
+    stages, per = int(meta.get("stages", 4)), int(meta.get("iters_per_stage", 1))
+    res = learned.compare(geom, net, cfg, [seed], sirt_iters=50, n_stages=stages,
+                          iters_per_stage=per, log=lambda s: _log("learned: " + s))
     r = res["rows"][0]
-    return {"sirt_iters": 50, "stages": 4, "phantom_seed": seed,
+    return {"sirt_iters": 50, "stages": stages, "iters_per_stage": per, "phantom_seed": seed,
             "psnr_sirt_db": r["psnr_sirt"], "psnr_learned_db": r["psnr_learned"],
-            "psnr_sirt_4_db": r["psnr_sirt_same_budget"],
+            "psnr_sirt_same_iterations_db": r["psnr_sirt_same_budget"],
             "resid_sirt": r["resid_sirt"], "resid_learned": r["resid_learned"],
             "t_sirt_s": r["t_sirt"], "t_learned_s": r["t_learned"],
             "time_ratio": r["t_learned"] / r["t_sirt"],

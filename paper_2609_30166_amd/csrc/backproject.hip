@@ -18,8 +18,8 @@
 // (projection, sub-view) it bounds the detector pixels whose rays can reach
 // the brick (the projection of the brick grown by one voxel and the warp
 // bound), redoes those rays' FP64 set-up, clips their sample range to the
-// grown brick, and adds with LDS float atomics the corners that fall inside
-// the brick.  A sample whose corner cube straddles a brick face is visited
+// grown brick, and adds with LDS 64-bit integer atomics the corners that
+// fall inside the brick.  A sample whose corner cube straddles a brick face is visited
 // by each brick it touches, and each adds only its own corners, so every
 // corner is added once.  There is no global atomic and no barrier inside the
 // projection loop; the brick is written out once at the end (with atomics
@@ -80,12 +80,13 @@ __device__ __forceinline__ bool project_box(const double *P, const double lo[3],
     return true;
 }
 
-// Round c * scale to the nearest integer (|c * scale| < 2^51) as a
-// two's-complement 64-bit value: adding 1.5 * 2^52 leaves the rounded integer
-// in the low mantissa bits of the double.
-__device__ __forceinline__ unsigned long long to_fixed(float c, double scale) {
+// Round w * g to the nearest integer (|w g| < 2^51) as a two's-complement
+// 64-bit value: adding 1.5 * 2^52 in the same FMA leaves the rounded integer
+// in the low mantissa bits of the double.  The fixed-point scale is folded
+// into w.
+__device__ __forceinline__ unsigned long long to_fixed(double w, double g) {
     const double magic = 6755399441055744.0;
-    const double t = fma(static_cast<double>(c), scale, magic);
+    const double t = fma(w, g, magic);
     return static_cast<unsigned long long>(__double_as_longlong(t) -
                                            __double_as_longlong(magic));
 }
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(BP_THREADS) void bp_brick_kernel(RayGrid g, WarpGri
                 double cbx = __shfl(r.bx, j, 64), cby = __shfl(r.by, j, 64),
                        cbz = __shfl(r.bz, j, 64), csx = __shfl(r.sx, j, 64),
                        csy = __shfl(r.sy, j, 64), csz = __shfl(r.sz, j, 64);
-                float cw = __shfl(wgt, j, 64);
+                double cws = static_cast<double>(__shfl(wgt, j, 64)) * scale;
                 int coff = __shfl(off_own, j, 64);
                 int cend = __shfl(incl, j, 64);
                 Ray cr;
@@ -267,7 +268,8 @@ __global__ __launch_bounds__(BP_THREADS) void bp_brick_kernel(RayGrid g, WarpGri
                             j = jn;
                             cbx = nbx; cby = nby; cbz = nbz;
                             csx = nsx; csy = nsy; csz = nsz;
-                            cw = nw; coff = noff; cend = ne;
+                            cws = static_cast<double>(nw) * scale;
+                            coff = noff; cend = ne;
                             seg = -1;
                         }
                     }
@@ -291,22 +293,25 @@ __global__ __launch_bounds__(BP_THREADS) void bp_brick_kernel(RayGrid g, WarpGri
                     float fx, fy, fz;
                     corner_idx(d, an, cx, cy, cz, ix, iy, iz, fx, fy, fz);
                     const int lx = ix - x0, ly = iy - y0, lz = iz - z0;
-                    const float gx1 = fx, gx0 = 1.0f - fx;
-                    const float gy1 = fy, gy0 = 1.0f - fy;
-                    const float gz1 = fz * cw, gz0 = (1.0f - fz) * cw;
-                    const float w00 = gz0 * gy0, w01 = gz0 * gy1, w10 = gz1 * gy0, w11 = gz1 * gy1;
+                    // corner weights in FP64 with the ray weight and the
+                    // fixed-point scale folded in: one FMA per corner below
+                    const double gx1 = fx, gx0 = 1.0f - fx;
+                    const double gy1 = fy, gy0 = 1.0f - fy;
+                    const double gz1 = fz * cws, gz0 = (1.0f - fz) * cws;
+                    const double w00 = gz0 * gy0, w01 = gz0 * gy1, w10 = gz1 * gy0,
+                                 w11 = gz1 * gy1;
                     if (lx >= 0 && lx + 1 < ex && ly >= 0 && ly + 1 < ey && lz >= 0 &&
                         lz + 1 < ez) {
                         // all eight corners inside the brick
                         unsigned long long *ap = acc + (lz * sz + ly * sy + lx);
-                        atomicAdd(ap, to_fixed(w00 * gx0, scale));
-                        atomicAdd(ap + 1, to_fixed(w00 * gx1, scale));
-                        atomicAdd(ap + sy, to_fixed(w01 * gx0, scale));
-                        atomicAdd(ap + sy + 1, to_fixed(w01 * gx1, scale));
-                        atomicAdd(ap + sz, to_fixed(w10 * gx0, scale));
-                        atomicAdd(ap + sz + 1, to_fixed(w10 * gx1, scale));
-                        atomicAdd(ap + sz + sy, to_fixed(w11 * gx0, scale));
-                        atomicAdd(ap + sz + sy + 1, to_fixed(w11 * gx1, scale));
+                        atomicAdd(ap, to_fixed(w00, gx0));
+                        atomicAdd(ap + 1, to_fixed(w00, gx1));
+                        atomicAdd(ap + sy, to_fixed(w01, gx0));
+                        atomicAdd(ap + sy + 1, to_fixed(w01, gx1));
+                        atomicAdd(ap + sz, to_fixed(w10, gx0));
+                        atomicAdd(ap + sz + 1, to_fixed(w10, gx1));
+                        atomicAdd(ap + sz + sy, to_fixed(w11, gx0));
+                        atomicAdd(ap + sz + sy + 1, to_fixed(w11, gx1));
                         continue;
                     }
                     const bool x_0 = lx >= 0 && lx < ex, x_1 = lx + 1 >= 0 && lx + 1 < ex;
@@ -314,18 +319,18 @@ __global__ __launch_bounds__(BP_THREADS) void bp_brick_kernel(RayGrid g, WarpGri
                     const bool z_0 = lz >= 0 && lz < ez, z_1 = lz + 1 >= 0 && lz + 1 < ez;
                     if (!((x_0 || x_1) && (y_0 || y_1) && (z_0 || z_1))) continue;
                     const int base = lz * sz + ly * sy + lx;   // may be outside: guarded
-                    if (z_0 && y_0 && x_0) atomicAdd(acc + base, to_fixed(w00 * gx0, scale));
-                    if (z_0 && y_0 && x_1) atomicAdd(acc + base + 1, to_fixed(w00 * gx1, scale));
-                    if (z_0 && y_1 && x_0) atomicAdd(acc + base + sy, to_fixed(w01 * gx0, scale));
+                    if (z_0 && y_0 && x_0) atomicAdd(acc + base, to_fixed(w00, gx0));
+                    if (z_0 && y_0 && x_1) atomicAdd(acc + base + 1, to_fixed(w00, gx1));
+                    if (z_0 && y_1 && x_0) atomicAdd(acc + base + sy, to_fixed(w01, gx0));
                     if (z_0 && y_1 && x_1)
-                        atomicAdd(acc + base + sy + 1, to_fixed(w01 * gx1, scale));
-                    if (z_1 && y_0 && x_0) atomicAdd(acc + base + sz, to_fixed(w10 * gx0, scale));
+                        atomicAdd(acc + base + sy + 1, to_fixed(w01, gx1));
+                    if (z_1 && y_0 && x_0) atomicAdd(acc + base + sz, to_fixed(w10, gx0));
                     if (z_1 && y_0 && x_1)
-                        atomicAdd(acc + base + sz + 1, to_fixed(w10 * gx1, scale));
+                        atomicAdd(acc + base + sz + 1, to_fixed(w10, gx1));
                     if (z_1 && y_1 && x_0)
-                        atomicAdd(acc + base + sz + sy, to_fixed(w11 * gx0, scale));
+                        atomicAdd(acc + base + sz + sy, to_fixed(w11, gx0));
                     if (z_1 && y_1 && x_1)
-                        atomicAdd(acc + base + sz + sy + 1, to_fixed(w11 * gx1, scale));
+                        atomicAdd(acc + base + sz + sy + 1, to_fixed(w11, gx1));
                 }
             }
         }

@@ -5,14 +5,15 @@ applications as the extension of its operator framework (Sec. 5).  Here the
 correction is the 3D U-Net of ``unet.UNet`` applied after each of a few
 unrolled SIRT iterations of Eq. (1), with the data residual as the judge:
 
-* stage k: one (or ``iters_per_stage``) SIRT update x <- x + alpha C A^T R
-  (b - A x) (libctrex ``ctrex_sirt_iterate``), then x~ = x + U(x);
+* stage k: ``iters_per_stage`` SIRT updates x <- x + alpha C A^T R (b - A x)
+  (libctrex ``ctrex_sirt_iterate``), then x~ = x + U_k(x) with the stage's
+  own network (or one network shared by all stages);
 * the correction is kept only if ||A x~ - b|| <= ||A x - b||
   (``ctrex_residual_norm``); otherwise it is discarded and the remaining
   stages run plain SIRT (the fallback);
-* training is stage-wise: MSE of x + U(x) to the true volume, Adam, batch 1,
-  the SIRT inputs of each stage taken from the pipeline as it stands (no
-  gradient through the projector), weights shared by all stages.
+* training is stage-wise: MSE of x + U_k(x) to the true volume, Adam, batch
+  1, the SIRT inputs of each stage taken from the pipeline as it stands (no
+  gradient through the projector).
 
 Every operator, network layer, loss and optimizer step runs in libctrex's
 kernels; this module sequences them.  Phantom and noise synthesis for
@@ -75,13 +76,22 @@ def psnr(x, x_true, mask):
     return float("inf") if mse == 0 else 10.0 * np.log10(rng * rng / mse)
 
 
+def _stage_nets(net, n_stages):
+    nets = list(net) if isinstance(net, (list, tuple)) else [net]
+    if len(nets) not in (1, n_stages):
+        raise ValueError("give one network or one per stage (%d)" % n_stages)
+    return nets if len(nets) == n_stages else nets * n_stages
+
+
 class LearnedSirt:
     """``n_stages`` x (SIRT update(s) + U-Net correction) with the residual
-    acceptance rule and plain-SIRT fallback."""
+    acceptance rule and plain-SIRT fallback.  ``net``: one UNet for all
+    stages or a list with one per stage."""
 
     def __init__(self, geom, net, n_stages=4, iters_per_stage=1, alpha=1.0):
-        self.geom, self.net = geom, net
+        self.geom = geom
         self.n_stages, self.iters = int(n_stages), int(iters_per_stage)
+        self.nets = _stage_nets(net, self.n_stages)
         self.alpha = float(alpha)
 
     def __call__(self, b, x=None):
@@ -97,7 +107,7 @@ class LearnedSirt:
                 stages.append(dict(stage=k, corrected=False, fallback=True))
                 continue
             rho = g.residual_norm(x, b)
-            xt = self.net.forward(x)
+            xt = self.nets[k].forward(x)
             rho_t = g.residual_norm(xt, b)
             ok = bool(rho_t <= rho)
             if ok:
@@ -122,6 +132,7 @@ def train(geom, net, cfg, seeds, lr=1e-3, lr_final=None, n_stages=4, iters_per_s
     on the full volume (MSE to the truth, measured before the stage's steps
     and after them)."""
     rng = np.random.default_rng([seed, 23])
+    nets = _stage_nets(net, n_stages)
     lr_final = lr if lr_final is None else lr_final
     total = len(seeds) * n_stages * crop_steps
     k_step = 0
@@ -132,7 +143,8 @@ def train(geom, net, cfg, seeds, lr=1e-3, lr_final=None, n_stages=4, iters_per_s
         x_true, b = make_sample(cfg, geom, pseed)
         x = torch.zeros(geom.shape, dtype=torch.float32, device=geom.device)
         rows = []
-        for _ in range(n_stages):
+        for k in range(n_stages):
+            net = nets[k]
             geom.sirt(x, b, iters_per_stage, norms=False)
             before = net.mse(x, x_true)
             for _ in range(crop_steps):

@@ -26,22 +26,36 @@ from . import learned
 from .unet import UNet
 
 
-def save(path, net, meta, optimizer_state=True):
-    """Parameters (and, optionally, the Adam moments and step) as .npz."""
-    st = net.state_dict()
-    extra = dict(step=st["step"], theta=st["theta"], m=st["m"], v=st["v"]) if optimizer_state else {}
-    np.savez(path, scale=np.float64(net.scale), meta=json.dumps(meta),
-             **{"p." + k: v for k, v in net.params().items()}, **extra)
+def save(path, nets, meta, optimizer_state=True):
+    """The stage networks' parameters (and, optionally, their Adam moments
+    and steps) as one .npz; keys are prefixed ``s<k>.``."""
+    nets = nets if isinstance(nets, (list, tuple)) else [nets]
+    arrays = dict(n_nets=np.int64(len(nets)), meta=json.dumps(meta))
+    for k, net in enumerate(nets):
+        pre = "s%d." % k
+        arrays[pre + "scale"] = np.float64(net.scale)
+        arrays.update({pre + "p." + n: v for n, v in net.params().items()})
+        if optimizer_state:
+            st = net.state_dict()
+            arrays.update({pre + "step": np.int64(st["step"]), pre + "theta": st["theta"],
+                           pre + "m": st["m"], pre + "v": st["v"]})
+    np.savez(path, **arrays)
 
 
 def load(path, device=None):
-    """A UNet with the parameters (and Adam state) stored by ``save``."""
+    """The list of stage UNets stored by ``save`` (with their Adam state
+    when present)."""
     z = np.load(path, allow_pickle=False)
-    params = {k[2:]: z[k] for k in z.files if k.startswith("p.")}
-    net = UNet(device, params=params, scale=float(z["scale"]))
-    if "theta" in z.files:
-        net.load_state_dict(dict(theta=z["theta"], m=z["m"], v=z["v"], step=int(z["step"])))
-    return net
+    nets = []
+    for k in range(int(z["n_nets"])):
+        pre = "s%d." % k
+        params = {n[len(pre) + 2:]: z[n] for n in z.files if n.startswith(pre + "p.")}
+        net = UNet(device, params=params, scale=float(z[pre + "scale"]))
+        if pre + "theta" in z.files:
+            net.load_state_dict(dict(theta=z[pre + "theta"], m=z[pre + "m"], v=z[pre + "v"],
+                                     step=int(z[pre + "step"])))
+        nets.append(net)
+    return nets
 
 
 def main(argv=None):
@@ -61,6 +75,10 @@ def main(argv=None):
                     help="network input scale (default: the volume width, since the "
                          "configuration stores attenuation per volume width)")
     ap.add_argument("--epochs", type=int, default=1)
+    ap.add_argument("--shared", action="store_true",
+                    help="one network for all stages (default: one per stage)")
+    ap.add_argument("--eval-only", action="store_true",
+                    help="skip training: evaluate the network of --resume")
     ap.add_argument("--weights-only", default=None,
                     help="also write the parameters alone (no optimizer state) here")
     ap.add_argument("--resume", default=None, help="weights file to continue from")
@@ -73,29 +91,35 @@ def main(argv=None):
 
     cfg, geom = learned.learned_geometry()
     scale = a.scale if a.scale else float(min(cfg.shape[1:]))
-    net = load(a.resume, geom.device) if a.resume else UNet(geom.device, seed=a.seed, scale=scale)
+    if a.resume:
+        net = load(a.resume, geom.device)
+    else:
+        n_nets = 1 if a.shared else a.stages
+        net = [UNet(geom.device, seed=a.seed + k, scale=scale) for k in range(n_nets)]
     seeds = list(configs.TRAIN_SEEDS)[:a.phantoms]
     t0 = time.time()
-    hists = []
-    for ep in range(a.epochs):
-        log("epoch %d" % (ep + 1))
-        hists.append(learned.train(geom, net, cfg, seeds, lr=a.lr, lr_final=a.lr_final,
-                                   n_stages=a.stages, iters_per_stage=a.iters_per_stage,
-                                   crop=a.crop or None, crop_steps=a.crop_steps, log=log,
-                                   seed=a.seed + ep))
-    hist = np.concatenate(hists)
-    t_train = time.time() - t0
-    meta = dict(config="learned", phantoms=a.phantoms, epochs=a.epochs, stages=a.stages,
-                iters_per_stage=a.iters_per_stage, lr=a.lr, lr_final=a.lr_final, crop=a.crop,
-                crop_steps=a.crop_steps, seed=a.seed, scale=net.scale, train_s=t_train,
-                adam_steps=net.step)
-    save(a.out, net, meta)
-    if a.weights_only:
-        save(a.weights_only, net, meta, optimizer_state=False)
-    log("trained on %d phantoms in %.1f s -> %s" % (len(seeds), t_train, a.out))
-    summary = dict(meta=meta, mse_first=hist[:8].mean(0).tolist(),
-                   mse_last_ellipsoids=hist[-8::2].mean(0).tolist(),
-                   mse_last_foam=hist[-7::2].mean(0).tolist())
+    summary = {}
+    if not a.eval_only:
+        hists = []
+        for ep in range(a.epochs):
+            log("epoch %d" % (ep + 1))
+            hists.append(learned.train(geom, net, cfg, seeds, lr=a.lr, lr_final=a.lr_final,
+                                       n_stages=a.stages, iters_per_stage=a.iters_per_stage,
+                                       crop=a.crop or None, crop_steps=a.crop_steps, log=log,
+                                       seed=a.seed + ep))
+        hist = np.concatenate(hists)
+        t_train = time.time() - t0
+        meta = dict(config="learned", phantoms=a.phantoms, epochs=a.epochs, stages=a.stages,
+                    iters_per_stage=a.iters_per_stage, lr=a.lr, lr_final=a.lr_final,
+                    crop=a.crop, crop_steps=a.crop_steps, seed=a.seed, scale=net[0].scale,
+                    train_s=t_train, networks=len(net), adam_steps=[n.step for n in net])
+        save(a.out, net, meta)
+        if a.weights_only:
+            save(a.weights_only, net, meta, optimizer_state=False)
+        log("trained on %d phantoms in %.1f s -> %s" % (len(seeds), t_train, a.out))
+        summary = dict(meta=meta, mse_first=hist[:8].mean(0).tolist(),
+                       mse_last_ellipsoids=hist[-8::2].mean(0).tolist(),
+                       mse_last_foam=hist[-7::2].mean(0).tolist())
     if a.test > 0:
         res = learned.compare(geom, net, cfg, list(configs.TEST_SEEDS)[:a.test],
                               sirt_iters=a.sirt_iters, n_stages=a.stages,

@@ -102,16 +102,22 @@ def test_training_checkpoint_resume_is_bitwise(tiny):
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
 def test_trained_network_gains_over_plain_sirt():
     """On a held-out phantom of the learned-correction configuration (256^3,
-    180 x 384^2, Poisson I0 = 1e4), the 4-stage pipeline beats plain SIRT
-    with the same 4 iterations in PSNR and keeps its corrections."""
+    180 x 384^2, Poisson I0 = 1e4), the staged pipeline beats plain SIRT
+    with the same number of iterations in PSNR and keeps its corrections."""
     from paper_2609_30166_amd import learned
     from paper_2609_30166_amd.train_unet import load
     from synth import configs
 
+    import json
+
     cfg, geom = learned.learned_geometry(device="cuda:0")
-    net = load(WEIGHTS, "cuda:0")
+    nets = load(WEIGHTS, "cuda:0")
+    meta = json.loads(str(np.load(WEIGHTS, allow_pickle=False)["meta"]))
+    per = int(meta["iters_per_stage"])
     seed = list(configs.TEST_SEEDS)[2]   # an ellipsoid phantom
-    res = learned.compare(geom, net, cfg, [seed], sirt_iters=8)
+    stages = int(meta["stages"])
+    res = learned.compare(geom, nets, cfg, [seed], sirt_iters=stages * per, n_stages=stages,
+                          iters_per_stage=per)
     r = res["rows"][0]
     assert r["accepted"] >= 1
     assert r["psnr_learned"] >= r["psnr_sirt_same_budget"] + 1.0, r
