@@ -121,18 +121,21 @@ CTREX_API int ctrex_nn_relu_backward(ctrex_ctx *ctx, const void *y, void *g, int
 CTREX_API int ctrex_nn_input(ctrex_ctx *ctx, const float *x, float scale, void *xb, int64_t n_vox,
                              void *stream);
 
-/* Head and residual: out[v] = x[v] + out_scale (b + sum_c h[c] act[v][c])
+/* Head and residual: out[v] = x[v] + m[v] out_scale (b + sum_c h[c] act[v][c])
  * (x, out FP32, act BF16 dense with c channels, h FP32 [c], b FP32 [1]);
- * out_scale = 1 / the input scale maps the correction back to x's units. */
+ * out_scale = 1 / the input scale maps the correction back to x's units;
+ * `mask` (FP32 [n_vox], NULL = all ones) confines the correction, e.g. to the
+ * scanned field of view. */
 CTREX_API int ctrex_nn_head(ctrex_ctx *ctx, const void *act, int32_t c, const float *h,
-                            const float *b, const float *x, float out_scale, float *out,
-                            int64_t n_vox, void *stream);
+                            const float *b, const float *x, float out_scale, const float *mask,
+                            float *out, int64_t n_vox, void *stream);
 
-/* Backward of ctrex_nn_head: with d = out_scale dout, dact[v][c] = d[v] h[c]
+/* Backward of ctrex_nn_head: with d = m out_scale dout, dact[v][c] = d[v] h[c]
  * (BF16), dh[c] = sum_v d[v] act[v][c], db = sum_v d[v] (FP32, deterministic). */
 CTREX_API int ctrex_nn_head_backward(ctrex_ctx *ctx, const void *act, int32_t c, const float *h,
-                                     float out_scale, const float *dout, void *dact, float *dh,
-                                     float *db, int64_t n_vox, void *stream);
+                                     float out_scale, const float *mask, const float *dout,
+                                     void *dact, float *dh, float *db, int64_t n_vox,
+                                     void *stream);
 
 /* Weighted mean squared error over n values: *loss (host, optional; waits)
  * = weight sum (a - t)^2 / n with the sum in FP64, grad (optional) =

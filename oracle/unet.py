@@ -11,8 +11,9 @@ network.  The network used here (readings stated with the project's design):
   3x3x3 convolutions (zero padding 1) with ReLU per level, 2x2x2 max pooling
   down, a 2x2x2 stride-2 transposed convolution up, skip concatenation
   [up-sampled, skip] along channels, a 1x1x1 head, and the residual output
-  x + U(s x) / s with a fixed input scale s (volumes stored per volume width
-  are brought to O(1) values);
+  x + m U(s x) / s with a fixed input scale s (volumes stored per volume
+  width are brought to O(1) values) and a per-voxel mask m confining the
+  correction (the scanned field of view);
 * the same weights after every one of the unrolled SIRT iterations of Eq. (1);
 * MSE loss to the true volume, Adam.
 
@@ -116,8 +117,8 @@ def _t(p, requires_grad=False):
             for k, v in p.items()}
 
 
-def forward(x, params, round_activations=False, tensors=None, scale=1.0):
-    """U-Net correction of a volume: x + U(scale x) / scale.
+def forward(x, params, round_activations=False, tensors=None, scale=1.0, mask=None):
+    """U-Net correction of a volume: x + mask U(scale x) / scale.
 
     ``x`` is a [D][H][W] array; D, H, W divisible by 4.  With
     ``round_activations`` every stored activation is rounded to BF16, as a
@@ -146,7 +147,10 @@ def forward(x, params, round_activations=False, tensors=None, scale=1.0):
     u1 = r(upconv2(d2, P["up1.w"], P["up1.b"]))
     a5 = cr("d1a", torch.cat([u1, e1], dim=-1))
     d1 = cr("d1b", a5)
-    out = x + (P["head.b"][0] + d1 @ P["head.w"]) / scale
+    corr = (P["head.b"][0] + d1 @ P["head.w"]) / scale
+    if mask is not None:
+        corr = corr * torch.as_tensor(np.asarray(mask), dtype=torch.float64)
+    out = x + corr
     if tensors is not None:
         tensors.update(dict(xin=xin, a1=a1, e1=e1, p1=p1, a2=a2, e2=e2, p2=p2, a3=a3, b3=b3,
                             u2=u2, a4=a4, d2=d2, u1=u1, a5=a5, d1=d1))
@@ -159,11 +163,11 @@ def mse(a, t):
     return ((a - t) ** 2).mean()
 
 
-def loss_and_grads(x, target, params, scale=1.0):
-    """MSE(x + U(scale x) / scale, target) and its gradient with respect to
-    every parameter (reverse-mode differentiation of the FP64 forward)."""
+def loss_and_grads(x, target, params, scale=1.0, mask=None):
+    """MSE(x + mask U(scale x) / scale, target) and its gradient with respect
+    to every parameter (reverse-mode differentiation of the FP64 forward)."""
     P = _t(params, requires_grad=True)
-    loss = mse(forward(x, P, scale=scale), target)
+    loss = mse(forward(x, P, scale=scale, mask=mask), target)
     loss.backward()
     return loss.item(), {k: v.grad.numpy().copy() for k, v in P.items()}
 

@@ -85,10 +85,10 @@ def lib():
             "ctrex_nn_relu_backward": (ctypes.c_int, [vp, vp, vp, i32, i32, i32, ctypes.c_int64,
                                                       vp]),
             "ctrex_nn_input": (ctypes.c_int, [vp, vp, ctypes.c_float, vp, ctypes.c_int64, vp]),
-            "ctrex_nn_head": (ctypes.c_int, [vp, vp, i32, vp, vp, vp, ctypes.c_float, vp,
+            "ctrex_nn_head": (ctypes.c_int, [vp, vp, i32, vp, vp, vp, ctypes.c_float, vp, vp,
                                              ctypes.c_int64, vp]),
             "ctrex_nn_head_backward": (ctypes.c_int, [vp, vp, i32, vp, ctypes.c_float, vp, vp, vp,
-                                                      vp, ctypes.c_int64, vp]),
+                                                      vp, vp, ctypes.c_int64, vp]),
             "ctrex_nn_mse": (ctypes.c_int, [vp, vp, vp, ctypes.c_int64, ctypes.c_float, dp, vp,
                                             vp]),
             "ctrex_nn_adam": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float,

@@ -212,7 +212,7 @@ struct PhaseTimer {
 };
 
 struct SirtLayout {
-    size_t R, r, C, z, shadow, partials, resid, total;
+    size_t R, r, C, z, shadow, vt, partials, resid, total;
 };
 
 SirtLayout sirt_layout(const ctrex_ctx *c, int32_t n_views, uint32_t flags) {
@@ -233,6 +233,8 @@ SirtLayout sirt_layout(const ctrex_ctx *c, int32_t n_views, uint32_t flags) {
     off = align_up(off + 4 * vox);
     l.shadow = off;
     off = align_up(off + (g16 ? 2 * vox : 0));
+    l.vt = off;   // y-fastest copy of the gathered volume
+    off = align_up(off + (g16 ? 2 : 4) * vox);
     l.partials = off;
     off = align_up(off + 8 * tiles);
     l.resid = off;
@@ -451,6 +453,11 @@ int ctrex_forward_project(ctrex_ctx *c, const void *vol, int32_t vol_dtype, void
     if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
     const RayGrid g = make_grid(c, dv, nv);
     FpExtra ex{nullptr, nullptr, nullptr};
+    // y-fastest copy for the projections whose rays run mainly along x
+    void *vt;
+    if ((st = ctx_scratch(c, dtype_size(vol_dtype) * c->nx * c->ny * c->nz, &vt))) return st;
+    CTREX_HIP(c, launch_transpose_xy(vol, vt, vol_dtype, c->nx, c->ny, c->nz, s));
+    ex.vol_t = vt;
     CTREX_HIP(c, launch_forward(g, make_warp(c), vol, vol_dtype, sino, sino_dtype, FP_PLAIN, ex, s));
     return CTREX_OK;
 }
@@ -472,11 +479,15 @@ int ctrex_residual_norm(ctrex_ctx *c, const void *vol, int32_t vol_dtype, const 
     if (!vol || !sino) return fail(c, CTREX_EINVAL, "vol and sino must be device pointers");
     if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
     const RayGrid g = make_grid(c, dv, nv);
+    const size_t vt_bytes = align_up(dtype_size(vol_dtype) * c->nx * c->ny * c->nz);
     void *scr;
-    if ((st = ctx_scratch(c, sizeof(double) * (static_cast<size_t>(g.total_blocks) + 1), &scr)))
+    if ((st = ctx_scratch(c, vt_bytes + sizeof(double) * (static_cast<size_t>(g.total_blocks) + 1),
+                          &scr)))
         return st;
-    double *part = static_cast<double *>(scr);
+    double *part = reinterpret_cast<double *>(static_cast<char *>(scr) + vt_bytes);
+    CTREX_HIP(c, launch_transpose_xy(vol, scr, vol_dtype, c->nx, c->ny, c->nz, s));
     FpExtra ex{sino, nullptr, part};
+    ex.vol_t = scr;
     // `out` is unused in this mode; the sinogram's storage type selects the kernel
     CTREX_HIP(c, launch_forward(g, make_warp(c), vol, vol_dtype, nullptr, sino_dtype, FP_RESIDUAL,
                                 ex, s));
@@ -590,9 +601,12 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
         CTREX_HIP(c, launch_convert(vol, F32, shadow, gdt, vox, s));
         gather = shadow;
     }
+    void *vt = ws + L.vt;
+    CTREX_HIP(c, launch_transpose_xy(gather, vt, gdt, c->nx, c->ny, c->nz, s));
     std::vector<double> host_norms;
     if (resid_norms) host_norms.reserve(n_iter);
     FpExtra ex{sino, Rw, partials};
+    ex.vol_t = vt;
     for (int32_t k = 0; k < n_iter; ++k) {
         PhaseTimer t_fp{c, s, nullptr, 0}, t_bp{c, s, nullptr, 1}, t_up{c, s, nullptr, 2};
         CTREX_HIP(c, t_fp.begin());
@@ -605,6 +619,8 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
         CTREX_HIP(c, t_up.begin());
         CTREX_HIP(c, launch_update(vol, z, Cw, alpha, (flags & CTREX_NONNEG) ? 1 : 0,
                                    gdt != F32 ? shadow : nullptr, gdt, vox, s));
+        if (k + 1 < n_iter)
+            CTREX_HIP(c, launch_transpose_xy(gather, vt, gdt, c->nx, c->ny, c->nz, s));
         CTREX_HIP(c, t_up.end());
         if (resid_norms && ((k + 1) % kResidCap == 0 || k + 1 == n_iter)) {
             const int cnt = (k % kResidCap) + 1;

@@ -60,6 +60,7 @@ struct FpExtra {
     const void *b;       // measured sinogram (FP_CORRECT, FP_RESIDUAL), storage type = out type
     const float *R;      // detector weights (FP_CORRECT)
     double *partials;    // [total_blocks] (FP_CORRECT, FP_RESIDUAL)
+    const void *vol_t = nullptr;  // optional y-fastest copy [nz][nx][ny] of the volume
 };
 
 // Backprojection modes.
@@ -86,6 +87,10 @@ hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t stream);
 hipError_t launch_recip(float *a, size_t n, hipStream_t stream);
 hipError_t launch_update(float *x, const float *z, const float *C, float alpha, int nonneg,
                          void *shadow, int shadow_dtype, size_t n, hipStream_t stream);
+// dst = src with x and y exchanged ([nz][ny][nx] -> [nz][nx][ny]); dtype
+// gives the element size.
+hipError_t launch_transpose_xy(const void *src, void *dst, int dtype, int nx, int ny, int nz,
+                               hipStream_t s);
 hipError_t launch_convert(const void *src, int src_dtype, void *dst, int dst_dtype, size_t n,
                           hipStream_t stream);
 hipError_t launch_sum_partials(const double *partials, int n, double *out, hipStream_t stream);

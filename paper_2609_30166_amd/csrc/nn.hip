@@ -535,16 +535,18 @@ __global__ __launch_bounds__(NT) void relu_bwd_kernel(const u16 *__restrict__ y,
     if (!(bf2f(y[idx]) > 0.0f)) gr[idx] = 0;
 }
 
-// out = x + scale (b + sum_k h_k act_k)
+// out = x + m scale (b + sum_k h_k act_k), m = mask[v] (1 without a mask)
 __global__ __launch_bounds__(NT) void head_kernel(const u16 *__restrict__ act, int c,
                                                   const float *__restrict__ h, const float *__restrict__ b,
                                                   const float *__restrict__ x, float scale,
+                                                  const float *__restrict__ mask,
                                                   float *__restrict__ out, long long n) {
     const long long v = static_cast<long long>(blockIdx.x) * NT + threadIdx.x;
     if (v >= n) return;
     float s = b[0];
     for (int k = 0; k < c; ++k) s = fmaf(h[k], bf2f(act[v * c + k]), s);
-    out[v] = fmaf(scale, s, x[v]);
+    const float sc = mask ? scale * mask[v] : scale;
+    out[v] = fmaf(sc, s, x[v]);
 }
 
 // xb = BF16(scale x)
@@ -554,10 +556,11 @@ __global__ __launch_bounds__(NT) void scale_bf16_kernel(const float *__restrict_
     if (i < n) xb[i] = f2bf(scale * x[i]);
 }
 
-// With d = scale dout: dact = d h; per-block partial sums of d act[:, k] (k < C) and d.
+// With d = mask scale dout: dact = d h; per-block partial sums of d act[:, k] (k < C) and d.
 template <int C>
 __global__ __launch_bounds__(NT) void head_bwd_kernel(const u16 *__restrict__ act,
                                                       const float *__restrict__ h, float scale,
+                                                      const float *__restrict__ mask,
                                                       const float *__restrict__ dout,
                                                       u16 *__restrict__ dact, long long n,
                                                       double *__restrict__ partial) {
@@ -567,7 +570,7 @@ __global__ __launch_bounds__(NT) void head_bwd_kernel(const u16 *__restrict__ ac
     for (int k = 0; k <= C; ++k) acc[k] = 0.0;
     const long long stride = static_cast<long long>(gridDim.x) * NT;
     for (long long v = static_cast<long long>(blockIdx.x) * NT + threadIdx.x; v < n; v += stride) {
-        const float d = scale * dout[v];
+        const float d = (mask ? scale * mask[v] : scale) * dout[v];
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             acc[k] += static_cast<double>(d) * bf2f(act[v * C + k]);
@@ -876,9 +879,9 @@ hipError_t launch_relu_bwd(const void *y, void *g, int cs, int off, int c, long 
 }
 
 hipError_t launch_head(const void *act, int c, const float *h, const float *b, const float *x,
-                       float scale, float *out, long long n, hipStream_t s) {
+                       float scale, const float *mask, float *out, long long n, hipStream_t s) {
     hipLaunchKernelGGL(head_kernel, dim3(blocks_for(n)), dim3(NT), 0, s, static_cast<const u16 *>(act),
-                       c, h, b, x, scale, out, n);
+                       c, h, b, x, scale, mask, out, n);
     return hipGetLastError();
 }
 
@@ -890,14 +893,14 @@ hipError_t launch_scale_bf16(const float *x, float scale, void *xb, long long n,
 
 size_t head_bwd_scratch(int c) { return sizeof(double) * 512 * static_cast<size_t>(c + 1); }
 
-hipError_t launch_head_bwd(const void *act, int c, const float *h, float scale, const float *dout,
-                           void *dact, float *dh, float *db, long long n, double *scratch,
-                           hipStream_t s) {
+hipError_t launch_head_bwd(const void *act, int c, const float *h, float scale, const float *mask,
+                           const float *dout, void *dact, float *dh, float *db, long long n,
+                           double *scratch, hipStream_t s) {
     const int blocks = 512;
     if (c != 16) return hipErrorInvalidValue;
     hipLaunchKernelGGL((head_bwd_kernel<16>), dim3(blocks), dim3(NT), 0, s,
-                       static_cast<const u16 *>(act), h, scale, dout, static_cast<u16 *>(dact), n,
-                       scratch);
+                       static_cast<const u16 *>(act), h, scale, mask, dout,
+                       static_cast<u16 *>(dact), n, scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (dh) hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(64), 0, s, scratch, blocks, c, c + 1, dh);

@@ -38,12 +38,12 @@ hipError_t launch_maxpool2_bwd(const void *in, int in_cs, int in_off, int c, con
 hipError_t launch_relu_bwd(const void *y, void *g, int cs, int off, int c, long long nvox,
                            hipStream_t s);
 hipError_t launch_head(const void *act, int c, const float *h, const float *b, const float *x,
-                       float scale, float *out, long long n, hipStream_t s);
+                       float scale, const float *mask, float *out, long long n, hipStream_t s);
 hipError_t launch_scale_bf16(const float *x, float scale, void *xb, long long n, hipStream_t s);
 size_t head_bwd_scratch(int c);
-hipError_t launch_head_bwd(const void *act, int c, const float *h, float scale, const float *dout,
-                           void *dact, float *dh, float *db, long long n, double *scratch,
-                           hipStream_t s);
+hipError_t launch_head_bwd(const void *act, int c, const float *h, float scale, const float *mask,
+                           const float *dout, void *dact, float *dh, float *db, long long n,
+                           double *scratch, hipStream_t s);
 hipError_t launch_mse(const float *a, const float *t, long long n, float weight, float *grad,
                       double *partial, int blocks, hipStream_t s);
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, long long n, float lr, float b1,
@@ -250,21 +250,22 @@ int ctrex_nn_input(ctrex_ctx *c, const float *x, float scale, void *xb, int64_t 
 }
 
 int ctrex_nn_head(ctrex_ctx *c, const void *act, int32_t ch, const float *h, const float *b,
-                  const float *x, float out_scale, float *out, int64_t n_vox, void *stream) {
+                  const float *x, float out_scale, const float *mask, float *out, int64_t n_vox,
+                  void *stream) {
     int st = begin(c);
     if (st) return st;
     if (!act || !h || !b || !x || !out) return fail(c, CTREX_EINVAL, "NULL pointer");
     if (ch < 1 || ch > 64 || n_vox < 0) return fail(c, CTREX_ESHAPE, "bad sizes");
     if (!std::isfinite(out_scale)) return fail(c, CTREX_EINVAL, "out_scale must be finite");
     if (n_vox == 0) return CTREX_OK;
-    CTREX_HIP(c, nn::launch_head(act, ch, h, b, x, out_scale, out, n_vox,
+    CTREX_HIP(c, nn::launch_head(act, ch, h, b, x, out_scale, mask, out, n_vox,
                                  static_cast<hipStream_t>(stream)));
     return CTREX_OK;
 }
 
 int ctrex_nn_head_backward(ctrex_ctx *c, const void *act, int32_t ch, const float *h,
-                           float out_scale, const float *dout, void *dact, float *dh, float *db,
-                           int64_t n_vox, void *stream) {
+                           float out_scale, const float *mask, const float *dout, void *dact,
+                           float *dh, float *db, int64_t n_vox, void *stream) {
     int st = begin(c);
     if (st) return st;
     if (!act || !h || !dout || !dact) return fail(c, CTREX_EINVAL, "NULL pointer");
@@ -272,7 +273,7 @@ int ctrex_nn_head_backward(ctrex_ctx *c, const void *act, int32_t ch, const floa
     if (!std::isfinite(out_scale)) return fail(c, CTREX_EINVAL, "out_scale must be finite");
     void *scr;
     if ((st = ctx_scratch(c, nn::head_bwd_scratch(ch), &scr))) return st;
-    CTREX_HIP(c, nn::launch_head_bwd(act, ch, h, out_scale, dout, dact, dh, db, n_vox,
+    CTREX_HIP(c, nn::launch_head_bwd(act, ch, h, out_scale, mask, dout, dact, dh, db, n_vox,
                                      static_cast<double *>(scr), static_cast<hipStream_t>(stream)));
     return CTREX_OK;
 }

@@ -25,6 +25,74 @@ namespace {
 using namespace dev;
 
 // ------------------------------------------------------- forward kernel ----
+// One ray's projection value: the mean over sub-views of the step-weighted
+// trilinear samples.  TL: gather from the y-fastest copy of the volume.
+template <typename TV, int MODE, bool WARP, bool TL>
+__device__ __forceinline__ float march(const RayGrid &g, const WarpGrid &w,
+                                       const TV *__restrict__ vol, const VolDims &d,
+                                       const TileCoord &t) {
+    float y = 0.0f;
+    for (int s = 0; s < g.n_sub; ++s) {
+        const SubView &sv = g.tab[t.p * g.n_sub + s];
+        Ray r;
+        if (!setup_ray(sv, static_cast<double>(t.iu), static_cast<double>(t.iv), g.nx, g.ny,
+                       g.nz, g.step, r))
+            continue;
+        const float tau = static_cast<float>(sv.tau);
+        float acc0 = 0.0f, acc1 = 0.0f;
+        for (int i0 = 0; i0 < r.n; i0 += SEG) {
+            const Anchor an = anchor_at(r, i0);
+            GridAnchor ga;
+            if (WARP) ga = grid_anchor(w, r, i0);
+            const int cnt = min(SEG, r.n - i0);
+            int j = 0;
+            for (; j + 1 < cnt; j += 2) {
+                const float j0 = static_cast<float>(j), j1 = j0 + 1.0f;
+                float ax = fmaf(j0, r.fx, an.ax), ay = fmaf(j0, r.fy, an.ay),
+                      az = fmaf(j0, r.fz, an.az);
+                float bx = fmaf(j1, r.fx, an.ax), by = fmaf(j1, r.fy, an.ay),
+                      bz = fmaf(j1, r.fz, an.az);
+                bool ina = true, inb = true;
+                if (WARP) {
+                    ina = warp(w, d, tau, an, ga, j0, ax, ay, az);
+                    inb = warp(w, d, tau, an, ga, j1, bx, by, bz);
+                }
+                if (MODE == FP_RECIP_ONES) {
+                    acc0 += ina ? 1.0f : 0.0f;
+                    acc1 += inb ? 1.0f : 0.0f;
+                } else {
+                    float va, vb;
+                    if (TL) {
+                        va = gather_t(vol, d, corner_of_t(d, an, ax, ay, az));
+                        vb = gather_t(vol, d, corner_of_t(d, an, bx, by, bz));
+                    } else {
+                        va = gather(vol, d, corner_of(d, an, ax, ay, az));
+                        vb = gather(vol, d, corner_of(d, an, bx, by, bz));
+                    }
+                    acc0 += ina ? va : 0.0f;
+                    acc1 += inb ? vb : 0.0f;
+                }
+            }
+            if (j < cnt) {
+                const float j0 = static_cast<float>(j);
+                float ax = fmaf(j0, r.fx, an.ax), ay = fmaf(j0, r.fy, an.ay),
+                      az = fmaf(j0, r.fz, an.az);
+                bool ina = true;
+                if (WARP) ina = warp(w, d, tau, an, ga, j0, ax, ay, az);
+                if (MODE == FP_RECIP_ONES) {
+                    acc0 += ina ? 1.0f : 0.0f;
+                } else {
+                    const float va = TL ? gather_t(vol, d, corner_of_t(d, an, ax, ay, az))
+                                        : gather(vol, d, corner_of(d, an, ax, ay, az));
+                    acc0 += ina ? va : 0.0f;
+                }
+            }
+        }
+        y = fmaf(r.h, acc0 + acc1, y);
+    }
+    return y / static_cast<float>(g.n_sub);
+}
+
 template <typename TV, typename TS, int MODE, bool WARP>
 __global__ __launch_bounds__(PROJ_THREADS) void fp_kernel(RayGrid g, WarpGrid w,
                                                           const TV *__restrict__ vol,
@@ -33,60 +101,16 @@ __global__ __launch_bounds__(PROJ_THREADS) void fp_kernel(RayGrid g, WarpGrid w,
     if (!t.valid) return;  // uniform over the block
     const VolDims d = vol_dims(g);
     const bool active = t.iu < g.n_u && t.iv < g.n_v;
+    // projections whose rays run mainly along x read the y-fastest copy
+    const TV *vt = static_cast<const TV *>(ex.vol_t);
+    const double uc = static_cast<double>((t.iu & ~(TILE_U - 1)) + TILE_U / 2);
+    const double vc = static_cast<double>((t.iv & ~(TILE_V - 1)) + TILE_V / 2);
+    const bool use_t = MODE != FP_RECIP_ONES && vt != nullptr &&
+                       x_major(g.tab[t.p * g.n_sub], uc, vc);
     float y = 0.0f;
     if (active) {
-        for (int s = 0; s < g.n_sub; ++s) {
-            const SubView &sv = g.tab[t.p * g.n_sub + s];
-            Ray r;
-            if (!setup_ray(sv, static_cast<double>(t.iu), static_cast<double>(t.iv), g.nx, g.ny,
-                           g.nz, g.step, r))
-                continue;
-            const float tau = static_cast<float>(sv.tau);
-            float acc0 = 0.0f, acc1 = 0.0f;
-            for (int i0 = 0; i0 < r.n; i0 += SEG) {
-                const Anchor an = anchor_at(r, i0);
-                GridAnchor ga;
-                if (WARP) ga = grid_anchor(w, r, i0);
-                const int cnt = min(SEG, r.n - i0);
-                int j = 0;
-                for (; j + 1 < cnt; j += 2) {
-                    const float j0 = static_cast<float>(j), j1 = j0 + 1.0f;
-                    float ax = fmaf(j0, r.fx, an.ax), ay = fmaf(j0, r.fy, an.ay),
-                          az = fmaf(j0, r.fz, an.az);
-                    float bx = fmaf(j1, r.fx, an.ax), by = fmaf(j1, r.fy, an.ay),
-                          bz = fmaf(j1, r.fz, an.az);
-                    bool ina = true, inb = true;
-                    if (WARP) {
-                        ina = warp(w, d, tau, an, ga, j0, ax, ay, az);
-                        inb = warp(w, d, tau, an, ga, j1, bx, by, bz);
-                    }
-                    if (MODE == FP_RECIP_ONES) {
-                        acc0 += ina ? 1.0f : 0.0f;
-                        acc1 += inb ? 1.0f : 0.0f;
-                    } else {
-                        const float va = gather(vol, d, corner_of(d, an, ax, ay, az));
-                        const float vb = gather(vol, d, corner_of(d, an, bx, by, bz));
-                        acc0 += ina ? va : 0.0f;
-                        acc1 += inb ? vb : 0.0f;
-                    }
-                }
-                if (j < cnt) {
-                    const float j0 = static_cast<float>(j);
-                    float ax = fmaf(j0, r.fx, an.ax), ay = fmaf(j0, r.fy, an.ay),
-                          az = fmaf(j0, r.fz, an.az);
-                    bool ina = true;
-                    if (WARP) ina = warp(w, d, tau, an, ga, j0, ax, ay, az);
-                    if (MODE == FP_RECIP_ONES) {
-                        acc0 += ina ? 1.0f : 0.0f;
-                    } else {
-                        const float va = gather(vol, d, corner_of(d, an, ax, ay, az));
-                        acc0 += ina ? va : 0.0f;
-                    }
-                }
-            }
-            y = fmaf(r.h, acc0 + acc1, y);
-        }
-        y /= static_cast<float>(g.n_sub);
+        y = use_t ? march<TV, MODE, WARP, true>(g, w, vt, d, t)
+                  : march<TV, MODE, WARP, false>(g, w, vol, d, t);
     }
     const int pix = (t.k * g.n_v + t.iv) * g.n_u + t.iu;
     if (MODE == FP_PLAIN) {

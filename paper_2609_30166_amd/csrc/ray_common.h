@@ -206,6 +206,47 @@ __device__ __forceinline__ float gather<float>(const float *__restrict__ vol, co
     return blend(k, p00.x, p00.y, p01.x, p01.y, p10.x, p10.y, p11.x, p11.y);
 }
 
+// The same gathers from a y-fastest copy of the volume ([nz][nx][ny]), used
+// for projections whose rays run mainly along x: a wave's samples then spread
+// over y and z, and with y fastest its neighbouring samples share cache lines
+// again.  The corner values and the blend are exactly those of `gather`.
+__device__ __forceinline__ Corner corner_of_t(const VolDims &d, const Anchor &a, float lx,
+                                              float ly, float lz) {
+    int ix, iy, iz;
+    Corner k;
+    corner_idx(d, a, lx, ly, lz, ix, iy, iz, k.fx, k.fy, k.fz);
+    k.base = (iz * d.nx + ix) * d.ny + iy;
+    return k;
+}
+
+template <typename TV>
+__device__ __forceinline__ float gather_t(const TV *__restrict__ vt, const VolDims &d,
+                                          const Corner &k) {
+    const int b = k.base;
+    return blend(k, ld(vt, b), ld(vt, b + d.ny), ld(vt, b + 1), ld(vt, b + d.ny + 1),
+                 ld(vt, b + d.nxy), ld(vt, b + d.nxy + d.ny), ld(vt, b + d.nxy + 1),
+                 ld(vt, b + d.nxy + d.ny + 1));
+}
+
+template <>
+__device__ __forceinline__ float gather_t<float>(const float *__restrict__ vt, const VolDims &d,
+                                                 const Corner &k) {
+    const int b = k.base;
+    const f32x2_a4 q00 = *reinterpret_cast<const f32x2_a4 *>(vt + b);               // (x, z)
+    const f32x2_a4 q01 = *reinterpret_cast<const f32x2_a4 *>(vt + b + d.ny);        // (x+1, z)
+    const f32x2_a4 q10 = *reinterpret_cast<const f32x2_a4 *>(vt + b + d.nxy);       // (x, z+1)
+    const f32x2_a4 q11 = *reinterpret_cast<const f32x2_a4 *>(vt + b + d.nxy + d.ny);
+    return blend(k, q00.x, q01.x, q00.y, q01.y, q10.x, q11.x, q10.y, q11.y);
+}
+
+// True when the central ray of the tile containing pixel (u, v) of sub-view
+// `sv` runs more along x than along y (uniform over a workgroup).
+__device__ __forceinline__ bool x_major(const SubView &sv, double u, double v) {
+    const double dx = sv.Mi[0] * u + sv.Mi[1] * v + sv.Mi[2];
+    const double dy = sv.Mi[3] * u + sv.Mi[4] * v + sv.Mi[5];
+    return fabs(dx) > fabs(dy);
+}
+
 // ----------------------------------------------------------------- warp ----
 // The displacement grid is anchored like the ray: per segment, the grid
 // coordinate (b + i s) (g - 1) / (n - 1) of its first sample is split in FP64

@@ -121,7 +121,40 @@ __global__ __launch_bounds__(THREADS) void repack_warp_kernel(const float *U, fl
     if (i < n) out[i] = make_float4(U[3 * i], U[3 * i + 1], U[3 * i + 2], 0.0f);
 }
 
+// dst[z][x][y] = src[z][y][x] through 32 x 32 LDS tiles (reads and writes
+// coalesced); T is the storage word (4 or 2 bytes).
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_xy_kernel(const T *__restrict__ src,
+                                                           T *__restrict__ dst, int nx, int ny) {
+    __shared__ T tile[32][33];
+    const size_t plane = static_cast<size_t>(blockIdx.z) * nx * ny;
+    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int j = ty; j < 32; j += 8) {
+        const int x = x0 + tx, y = y0 + j;
+        if (x < nx && y < ny) tile[j][tx] = src[plane + static_cast<size_t>(y) * nx + x];
+    }
+    __syncthreads();
+    for (int j = ty; j < 32; j += 8) {
+        const int y = y0 + tx, x = x0 + j;
+        if (x < nx && y < ny) dst[plane + static_cast<size_t>(x) * ny + y] = tile[tx][j];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_transpose_xy(const void *src, void *dst, int dtype, int nx, int ny, int nz,
+                               hipStream_t s) {
+    if (nx <= 0 || ny <= 0 || nz <= 0) return hipSuccess;
+    const dim3 grid((nx + 31) / 32, (ny + 31) / 32, nz), block(256);
+    if (dtype == F32)
+        hipLaunchKernelGGL(transpose_xy_kernel<uint32_t>, grid, block, 0, s,
+                           static_cast<const uint32_t *>(src), static_cast<uint32_t *>(dst), nx, ny);
+    else
+        hipLaunchKernelGGL(transpose_xy_kernel<uint16_t>, grid, block, 0, s,
+                           static_cast<const uint16_t *>(src), static_cast<uint16_t *>(dst), nx, ny);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t s) {
     if (bytes == 0) return hipSuccess;

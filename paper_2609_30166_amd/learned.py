@@ -6,8 +6,9 @@ correction is the 3D U-Net of ``unet.UNet`` applied after each of a few
 unrolled SIRT iterations of Eq. (1), with the data residual as the judge:
 
 * stage k: ``iters_per_stage`` SIRT updates x <- x + alpha C A^T R (b - A x)
-  (libctrex ``ctrex_sirt_iterate``), then x~ = x + U_k(x) with the stage's
-  own network (or one network shared by all stages);
+  (libctrex ``ctrex_sirt_iterate``), then x~ = x + m U_k(x) with the stage's
+  own network (or one network shared by all stages), m the scanned field of
+  view (the inscribed cylinder about the rotation axis);
 * the correction is kept only if ||A x~ - b|| <= ||A x - b||
   (``ctrex_residual_norm``); otherwise it is discarded and the remaining
   stages run plain SIRT (the fallback);
@@ -67,6 +68,11 @@ def fov_mask(shape, device):
     return disc.expand(nz, ny, nx)
 
 
+def fov_weight(shape, device):
+    """The field-of-view mask as float32 weights (1 inside, 0 outside)."""
+    return fov_mask(shape, device).to(torch.float32).contiguous()
+
+
 def psnr(x, x_true, mask):
     """10 log10(range^2 / MSE) with range = max - min of x_true, MSE in mask."""
     t = x_true.double()
@@ -88,11 +94,12 @@ class LearnedSirt:
     acceptance rule and plain-SIRT fallback.  ``net``: one UNet for all
     stages or a list with one per stage."""
 
-    def __init__(self, geom, net, n_stages=4, iters_per_stage=1, alpha=1.0):
+    def __init__(self, geom, net, n_stages=4, iters_per_stage=1, alpha=1.0, mask="fov"):
         self.geom = geom
         self.n_stages, self.iters = int(n_stages), int(iters_per_stage)
         self.nets = _stage_nets(net, self.n_stages)
         self.alpha = float(alpha)
+        self.mask = fov_weight(geom.shape, geom.device) if isinstance(mask, str) else mask
 
     def __call__(self, b, x=None):
         """Reconstruct from sinogram ``b``; returns (x, per-stage records)."""
@@ -107,7 +114,7 @@ class LearnedSirt:
                 stages.append(dict(stage=k, corrected=False, fallback=True))
                 continue
             rho = g.residual_norm(x, b)
-            xt = self.nets[k].forward(x)
+            xt = self.nets[k].forward(x, mask=self.mask)
             rho_t = g.residual_norm(xt, b)
             ok = bool(rho_t <= rho)
             if ok:
@@ -127,13 +134,16 @@ def train(geom, net, cfg, seeds, lr=1e-3, lr_final=None, n_stages=4, iters_per_s
     ``crop_steps`` Adam steps on random ``crop``^3 blocks of (iterate, truth)
     (the whole volume when ``crop`` is None), then corrects the full volume
     with the updated network to form the next stage's input.  The learning
-    rate falls linearly from ``lr`` to ``lr_final`` over the run.  Returns
+    rate falls linearly from ``lr`` to ``lr_final`` over the run.  The
+    correction is confined to the field of view, so the loss sees only the
+    errors there (outside it the output is the iterate itself).  Returns
     per phantom and stage [loss of the SIRT iterate, loss after correction]
     on the full volume (MSE to the truth, measured before the stage's steps
     and after them)."""
     rng = np.random.default_rng([seed, 23])
     nets = _stage_nets(net, n_stages)
     lr_final = lr if lr_final is None else lr_final
+    mask = fov_weight(geom.shape, geom.device)
     total = len(seeds) * n_stages * crop_steps
     k_step = 0
     hist = []
@@ -153,10 +163,11 @@ def train(geom, net, cfg, seeds, lr=1e-3, lr_final=None, n_stages=4, iters_per_s
                 if crop:
                     z0, y0, x0 = (int(rng.integers(0, n - crop + 1)) for n in (nz, ny, nx))
                     sl = (slice(z0, z0 + crop), slice(y0, y0 + crop), slice(x0, x0 + crop))
-                    net.train_step(x[sl].contiguous(), x_true[sl].contiguous(), lr=rate)
+                    net.train_step(x[sl].contiguous(), x_true[sl].contiguous(), lr=rate,
+                                   mask=mask[sl].contiguous())
                 else:
-                    net.train_step(x, x_true, lr=rate)
-            x = net.forward(x)
+                    net.train_step(x, x_true, lr=rate, mask=mask)
+            x = net.forward(x, mask=mask)
             rows.append((before, net.mse(x, x_true)))
         hist.append(rows)
         if log and (i % log_every == 0 or i + 1 == len(seeds)):

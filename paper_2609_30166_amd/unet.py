@@ -9,11 +9,12 @@ names as the extension of its operator framework (Sec. 5):
     level 3 (D/4 ...):      pool, conv 32->64, conv 64->64
     decoder level 2:        up 64->32, concat [up, e2], conv 64->32, conv 32->32
     decoder level 1:        up 32->16, concat [up, e1], conv 32->16, conv 16->16
-    head:                   out = x + (b + sum_c h_c d1_c) / s
+    head:                   out = x + m (b + sum_c h_c d1_c) / s
 
 with the network reading s x: the fixed input scale s brings volumes stored in
 small physical units (attenuation per volume width) to the O(1) range the
-biases work in, and the head maps the correction back.
+biases work in, and the head maps the correction back.  The optional mask m
+(per voxel) confines the correction, e.g. to the scanned field of view.
 
 Every 3x3x3 convolution is followed by ReLU; the up-sampling is a 2x2x2
 stride-2 transposed convolution.  Activations are BF16 channels-last in
@@ -243,10 +244,14 @@ class UNet:
         D, H, W = dims
         self._call("ctrex_nn_maxpool2", _vp(src), cs, off, c, _vp(dst), D, H, W, self._s())
 
-    def forward(self, x, out=None, train=False):
-        """x + U(x) for a float32 volume ``x`` [D][H][W] on the device."""
+    def forward(self, x, out=None, train=False, mask=None):
+        """x + m U(s x) / s for a float32 volume ``x`` [D][H][W] on the device;
+        ``mask``: optional float32 weights m of the same shape."""
         if x.dtype != torch.float32 or x.device != self.device or not x.is_contiguous():
             raise ValueError("x must be a contiguous float32 tensor on %s" % self.device)
+        if mask is not None and (mask.dtype != torch.float32 or mask.shape != x.shape or
+                                 mask.device != self.device or not mask.is_contiguous()):
+            raise ValueError("mask must be a contiguous float32 tensor shaped like x")
         D, H, W = self.check_shape(x.shape)
         l1, l2, l3 = (D, H, W), (D // 2, H // 2, W // 2), (D // 4, H // 4, W // 4)
         b = self._buffers((D, H, W), train)
@@ -269,8 +274,9 @@ class UNet:
         if out is None:
             out = torch.empty_like(x)
         self._call("ctrex_nn_head", _vp(b["d1"]), 16, _vp(self.p("head.w")),
-                   _vp(self.p("head.b")), _vp(x), 1.0 / self.scale, _vp(out), n1, self._s())
-        self._saved = (b, (l1, l2, l3)) if train else None
+                   _vp(self.p("head.b")), _vp(x), 1.0 / self.scale,
+                   _vp(mask) if mask is not None else None, _vp(out), n1, self._s())
+        self._saved = (b, (l1, l2, l3), mask) if train else None
         return out
 
     def activations(self, x):
@@ -310,13 +316,13 @@ class UNet:
         needs the preceding ``forward(..., train=True)``.  Overwrites ``grad``."""
         if self._saved is None:
             raise RuntimeError("backward needs a forward pass with train=True")
-        b, (l1, l2, l3) = self._saved
+        b, (l1, l2, l3), mask = self._saved
         n1 = l1[0] * l1[1] * l1[2]
         n2, n3 = n1 // 8, n1 // 64
         g = self.grad
         # head and decoder level 1
         self._call("ctrex_nn_head_backward", _vp(b["d1"]), 16, _vp(self.p("head.w")),
-                   1.0 / self.scale, _vp(dout),
+                   1.0 / self.scale, _vp(mask) if mask is not None else None, _vp(dout),
                    _vp(b["g1a"]), _vp(self.p("head.w", g)), _vp(self.p("head.b", g)), n1,
                    self._s())
         self._relu_bwd(b["d1"], b["g1a"], 16, 0, 16, n1)
@@ -378,11 +384,11 @@ class UNet:
                    self.n_params, lr, beta1, beta2, eps, self.step, self._s())
         self._pack()
 
-    def train_step(self, x, target, lr=1e-3):
-        """One Adam step on s^2 MSE(x + U(s x) / s, target), the error in the
+    def train_step(self, x, target, lr=1e-3, mask=None):
+        """One Adam step on s^2 MSE(x + m U(s x) / s, target), the error in the
         network's own units; returns that loss before the step."""
-        out = self.forward(x, train=True)
-        b, _ = self._saved
+        out = self.forward(x, train=True, mask=mask)
+        b = self._saved[0]
         loss = self.mse(out, target, grad=b["dout"], weight=self.scale ** 2)
         self.backward(b["dout"].view_as(x))
         self.adam(lr)

@@ -320,19 +320,23 @@ def test_head_forward_backward(L, ctx):
     dout = r.normal(size=n).astype(np.float32).astype(np.float64)
     ad, hd, bd, xd, dd = _dev_bf(act), _dev_f(h), _dev_f(bb), _dev_f(x), _dev_f(dout)
     out = torch.empty(n, dtype=torch.float32, device=DEV)
-    for s in (1.0, 0.25):
-        _call(L, ctx, "ctrex_nn_head", _vp(ad), 16, _vp(hd), _vp(bd), _vp(xd), s, _vp(out), n,
-              None)
-        _close(_host(out), x + s * (bb[0] + act @ h), rel=1e-6)
+    m = (r.uniform(size=n) < 0.7).astype(np.float64)
+    md = _dev_f(m)
+    for s, mm in ((1.0, None), (0.25, None), (0.5, m)):
+        mp = _vp(md) if mm is not None else None
+        w = s * (mm if mm is not None else np.ones(n))
+        _call(L, ctx, "ctrex_nn_head", _vp(ad), 16, _vp(hd), _vp(bd), _vp(xd), s, mp, _vp(out),
+              n, None)
+        _close(_host(out), x + w * (bb[0] + act @ h), rel=1e-6)
         dact = torch.empty(n * 16, dtype=torch.bfloat16, device=DEV)
         dh = torch.empty(16, dtype=torch.float32, device=DEV)
         db = torch.empty(1, dtype=torch.float32, device=DEV)
-        _call(L, ctx, "ctrex_nn_head_backward", _vp(ad), 16, _vp(hd), s, _vp(dd), _vp(dact),
+        _call(L, ctx, "ctrex_nn_head_backward", _vp(ad), 16, _vp(hd), s, mp, _vp(dd), _vp(dact),
               _vp(dh), _vp(db), n, None)
-        ref = s * np.outer(dout, h)
+        ref = np.outer(w * dout, h)
         assert np.all(np.abs(_host(dact).reshape(n, 16) - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-30)
-        _close(_host(dh), s * (dout @ act), rel=1e-6)
-        _close(_host(db), [s * dout.sum()], rel=1e-6)
+        _close(_host(dh), (w * dout) @ act, rel=1e-6)
+        _close(_host(db), [(w * dout).sum()], rel=1e-6)
 
 
 def test_scaled_input_conversion(L, ctx):
@@ -463,13 +467,17 @@ def test_network_gradients_match_oracle(scale):
     x = (r.uniform(0, 1, size=shape) / scale).astype(np.float32)
     t = (x + 0.1 * r.normal(size=shape) / scale).astype(np.float32)
     xd, td = _dev_f(x), _dev_f(t)
-    out = net.forward(xd, train=True)
+    m = None
+    if scale != 1.0:   # the scaled case also confines the correction to a cylinder
+        zz, yy, xx = np.meshgrid(*(np.arange(16) - 7.5,) * 3, indexing="ij")
+        m = (xx ** 2 + yy ** 2 <= 7.5 ** 2).astype(np.float32)
+    out = net.forward(xd, train=True, mask=_dev_f(m) if m is not None else None)
     dout = torch.empty_like(out)
     loss = net.mse(out, td, grad=dout)
     net.backward(dout)
     g_gpu = net.grads()
     ploss, g_ref = ou.loss_and_grads(x.astype(np.float64), t.astype(np.float64),
-                                     _oracle_params(net), scale=scale)
+                                     _oracle_params(net), scale=scale, mask=m)
     assert abs(loss - ploss) <= 1e-2 * ploss
     num = den = 0.0
     for k, gr in g_ref.items():

@@ -152,3 +152,14 @@ def test_input_scale_is_a_change_of_units():
     a = unet.forward(x, p, scale=s).numpy()
     b = unet.forward(s * x, p).numpy() / s
     np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-18)
+
+
+def test_mask_confines_the_correction():
+    p = unet.init_params(14, head_std=0.5)
+    x = _rng(15).uniform(0, 1, size=(8, 8, 8))
+    m = np.zeros((8, 8, 8))
+    m[2:6, 2:6, 2:6] = 1.0
+    full = unet.forward(x, p).numpy()
+    got = unet.forward(x, p, mask=m).numpy()
+    np.testing.assert_array_equal(got[m == 0], x[m == 0])
+    np.testing.assert_allclose(got[m == 1], full[m == 1], rtol=1e-14, atol=1e-14)
