@@ -137,7 +137,8 @@ def time_to_psnr(dev):
     meta = json.loads(str(np.load(WEIGHTS_FILE, allow_pickle=False)["meta"]))
     stages, per = int(meta.get("stages", 4)), int(meta.get("iters_per_stage", 1))
     res = learned.compare(geom, net, cfg, [seed], sirt_iters=50, n_stages=stages,
-                          iters_per_stage=per, log=lambda s: _log("learned: " + s))
+                          iters_per_stage=per, log=lambda s: _log("learned: " + s),
+                          fov=bool(meta.get("fov_mask", False)))
     r = res["rows"][0]
     return {"sirt_iters": 50, "stages": stages, "iters_per_stage": per, "phantom_seed": seed,
             "psnr_sirt_db": r["psnr_sirt"], "psnr_learned_db": r["psnr_learned"],

@@ -185,11 +185,13 @@ def _timed(fn):
     return out, time.perf_counter() - t0
 
 
-def compare(geom, net, cfg, seeds, sirt_iters=50, n_stages=4, iters_per_stage=1, log=None):
+def compare(geom, net, cfg, seeds, sirt_iters=50, n_stages=4, iters_per_stage=1, log=None,
+            fov=True):
     """Learned pipeline versus plain SIRT on held-out phantoms: PSNR, data
-    residual ||A x - b|| and wall time of each; returns a summary dict."""
+    residual ||A x - b|| and wall time of each; returns a summary dict.
+    ``fov``: confine the corrections to the field of view (as in training)."""
     mask = fov_mask(geom.shape, geom.device)
-    pipe = LearnedSirt(geom, net, n_stages, iters_per_stage)
+    pipe = LearnedSirt(geom, net, n_stages, iters_per_stage, mask="fov" if fov else None)
     budget = n_stages * iters_per_stage
     rows = []
     for seed in seeds:

@@ -112,7 +112,8 @@ def main(argv=None):
         meta = dict(config="learned", phantoms=a.phantoms, epochs=a.epochs, stages=a.stages,
                     iters_per_stage=a.iters_per_stage, lr=a.lr, lr_final=a.lr_final,
                     crop=a.crop, crop_steps=a.crop_steps, seed=a.seed, scale=net[0].scale,
-                    train_s=t_train, networks=len(net), adam_steps=[n.step for n in net])
+                    train_s=t_train, networks=len(net), adam_steps=[n.step for n in net],
+                    fov_mask=True)
         save(a.out, net, meta)
         if a.weights_only:
             save(a.weights_only, net, meta, optimizer_state=False)
@@ -121,9 +122,14 @@ def main(argv=None):
                        mse_last_ellipsoids=hist[-8::2].mean(0).tolist(),
                        mse_last_foam=hist[-7::2].mean(0).tolist())
     if a.test > 0:
+        fov = True
+        if a.eval_only and a.resume:
+            m = json.loads(str(np.load(a.resume, allow_pickle=False)["meta"]))
+            fov = bool(m.get("fov_mask", False))
+            a.stages, a.iters_per_stage = int(m["stages"]), int(m["iters_per_stage"])
         res = learned.compare(geom, net, cfg, list(configs.TEST_SEEDS)[:a.test],
                               sirt_iters=a.sirt_iters, n_stages=a.stages,
-                              iters_per_stage=a.iters_per_stage, log=log)
+                              iters_per_stage=a.iters_per_stage, log=log, fov=fov)
         summary["compare"] = res
         m = res["mean"]
         log("mean PSNR: SIRT-%d %.2f dB, SIRT-%d %.2f dB, learned %.2f dB; time %.3f s vs "

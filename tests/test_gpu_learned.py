@@ -117,7 +117,7 @@ def test_trained_network_gains_over_plain_sirt():
     seed = list(configs.TEST_SEEDS)[2]   # an ellipsoid phantom
     stages = int(meta["stages"])
     res = learned.compare(geom, nets, cfg, [seed], sirt_iters=stages * per, n_stages=stages,
-                          iters_per_stage=per)
+                          iters_per_stage=per, fov=bool(meta.get("fov_mask", False)))
     r = res["rows"][0]
     assert r["accepted"] >= 1
     assert r["psnr_learned"] >= r["psnr_sirt_same_budget"] + 1.0, r
