@@ -153,7 +153,11 @@ CTREX_API int ctrex_sirt_workspace_bytes(const ctrex_ctx *ctx, int32_t n_views, 
  * device memory of at least ctrex_sirt_workspace_bytes(); it holds R, C and
  * the intermediates, and R and C are kept there between calls for the same
  * geometry, motion, view list and workspace (CTREX_RECOMPUTE_WEIGHTS forces
- * a rebuild; the caller must not write the workspace in between).  With a
+ * a rebuild; the caller must not write the workspace in between, and must
+ * pass the flag after reusing freed memory at the same address as a
+ * workspace).  The context remembers up to 64 (workspace, view list) pairs,
+ * so ordered subsets — one workspace per subset, cycled — keep their
+ * weights.  With a
  * BF16/F16 gather flag the rays march a 16-bit shadow of vol, refreshed
  * after every update, while the update itself stays FP32.  The correction
  * image R (sino - A vol) is stored in sino_dtype.  If `resid_norms` (host,

@@ -7,7 +7,8 @@ other.  The projector pair lives in plain C (``ctrex_oracle.c``, FP64); this
 module adds the parts that are compositions of it:
 
 * the SIRT iteration of Eq. (1): x_{k+1} = x_k + alpha C A^T R (b - A x_k), with
-  R = 1 / (A 1) and C = 1 / (A^T 1) (zero where the sums are zero), x_0 = 0;
+  R = 1 / (A 1) and C = 1 / (A^T 1) (zero where the sums are zero), x_0 = 0,
+  and its ordered-subset form (Sec. 2.3.2), one update per subset of views;
 * the total-variation term and its gradient, the least-squares loss, PSNR.
 
 Functions take numpy arrays; geometry is a [n_proj][n_sub][3][4] float64 array
@@ -179,6 +180,26 @@ def sirt(P, shape, n_u, n_v, b, n_iter, alpha=1.0, step=0.5, views=None, U=None,
         x = x + alpha * Cw * back(P, shape, n_u, n_v, Rw * res, step, views, U, tau)
         if nonneg:
             x = np.maximum(x, 0.0)
+    return x, norms
+
+
+def os_sirt(P, shape, n_u, n_v, b, subsets, n_epochs, alpha=1.0, step=0.5, U=None, tau=None,
+            x0=None, nonneg=False):
+    """Ordered subsets (Sec. 2.3.2): each epoch applies Eq. (1) once per subset
+    P_k in order, with R_k = 1 / (A_k 1) and C_k = 1 / (A_k^T 1) of that
+    subset.  ``b`` holds all projections; returns (x, [[||b_k - A_k x|| per
+    subset] per epoch])."""
+    b = _f64(b)
+    x = np.zeros(shape) if x0 is None else _f64(x0).reshape(shape).copy()
+    weights = [sirt_weights(P, shape, n_u, n_v, step, list(s), U, tau) for s in subsets]
+    norms = []
+    for _ in range(n_epochs):
+        row = []
+        for s, w in zip(subsets, weights):
+            x, nk = sirt(P, shape, n_u, n_v, b[list(s)], 1, alpha, step, list(s), U, tau, x0=x,
+                         nonneg=nonneg, weights=w)
+            row.append(nk[0])
+        norms.append(row)
     return x, norms
 
 

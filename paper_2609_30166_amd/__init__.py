@@ -3,15 +3,20 @@
 Public Python API (argument marshalling over the C ABI in include/ctrex.h):
 
 * ``Geometry`` — projector context over per-projection 3x4 view matrices;
-  ``forward`` (A), ``back`` (A^T), ``sirt`` (Eq. 1), ``sample_count``.
+  ``forward`` (A), ``back`` (A^T), ``sirt`` (Eq. 1), ``os_sirt`` (ordered
+  subsets, Sec. 2.3.2), ``residual_norm``, ``sample_count``.
+* ``ordered_subsets`` — interleaved / contiguous / random projection subsets.
 * ``project`` — differentiable forward projection (autograd).
 * ``total_variation``, ``reconstruction_loss`` — ||Ax - b||^2 + lambda TV(x).
+* ``unet.UNet``, ``learned.LearnedSirt`` — the learned correction between
+  unrolled SIRT iterations (Sec. 5 extension; include/ctrex_nn.h).
 """
 
 from .projector import (  # noqa: F401
     Geometry, ForwardProject, project, TotalVariation, total_variation, reconstruction_loss,
+    ordered_subsets,
 )
 from ._lib import CtrexError, library_path  # noqa: F401
 
 __all__ = ["Geometry", "ForwardProject", "project", "TotalVariation", "total_variation",
-           "reconstruction_loss", "CtrexError", "library_path"]
+           "reconstruction_loss", "ordered_subsets", "CtrexError", "library_path"]

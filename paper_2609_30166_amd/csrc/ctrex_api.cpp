@@ -27,6 +27,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kResidCap = 1024;
 constexpr size_t kMaxLists = 64;
+constexpr size_t kMaxWeightSets = 64;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -380,7 +381,7 @@ int ctrex_set_geometry(ctrex_ctx *c, const double *P, int32_t n_proj, int32_t n_
     c->step = step;
     c->have_geom = true;
     c->generation++;
-    c->w_valid = false;
+    c->w_cache.clear();
     return CTREX_OK;
 }
 
@@ -396,7 +397,7 @@ int ctrex_set_motion(ctrex_ctx *c, const float *U_dev, int32_t gx, int32_t gy, i
         CTREX_HIP(c, hipMemcpy(c->d_tab, c->tab.data(), sizeof(SubView) * c->tab.size(),
                                hipMemcpyHostToDevice));
         c->generation++;
-        c->w_valid = false;
+        c->w_cache.clear();
         return CTREX_OK;
     }
     if (!tau) return fail(c, CTREX_EINVAL, "tau is NULL");
@@ -433,7 +434,7 @@ int ctrex_set_motion(ctrex_ctx *c, const float *U_dev, int32_t gx, int32_t gy, i
     c->gy = gy;
     c->gz = gz;
     c->generation++;
-    c->w_valid = false;
+    c->w_cache.clear();
     return CTREX_OK;
 }
 
@@ -578,23 +579,32 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
     if ((st = ensure_part(c, g, &part)) != CTREX_OK) return st;
 
     // R and C for this geometry / motion / subset / workspace, kept between calls.
-    const bool cached = c->w_valid && c->w_ws == workspace && c->w_gen == c->generation &&
-                        (views == nullptr) == c->w_all &&
-                        (views == nullptr ||
-                         (static_cast<int32_t>(c->w_views.size()) == nv &&
-                          std::memcmp(c->w_views.data(), views, sizeof(int32_t) * nv) == 0)) &&
-                        !(flags & CTREX_RECOMPUTE_WEIGHTS);
+    auto same_key = [&](const ctrex_ctx::WeightKey &e) {
+        return e.ws == workspace && e.gen == c->generation && e.all == (views == nullptr) &&
+               (views == nullptr ||
+                (static_cast<int32_t>(e.views.size()) == nv &&
+                 std::memcmp(e.views.data(), views, sizeof(int32_t) * nv) == 0));
+    };
+    // the workspace's R and C are valid only under its own key; any other
+    // entry naming this workspace is stale once we write into it
+    auto hit = std::find_if(c->w_cache.begin(), c->w_cache.end(), same_key);
+    const bool cached = hit != c->w_cache.end() && !(flags & CTREX_RECOMPUTE_WEIGHTS);
     if (!cached) {
-        c->w_valid = false;
+        c->w_cache.erase(std::remove_if(c->w_cache.begin(), c->w_cache.end(),
+                                        [&](const ctrex_ctx::WeightKey &e) {
+                                            return e.ws == workspace;
+                                        }),
+                         c->w_cache.end());
         FpExtra none{nullptr, nullptr, nullptr};
         CTREX_HIP(c, launch_forward(g, w, nullptr, F32, Rw, F32, FP_RECIP_ONES, none, s));
         CTREX_HIP(c, launch_back(g, w, c->d_P, nullptr, F32, Cw, 0, BP_ONES, c->d_scalar, part, s));
         CTREX_HIP(c, launch_recip(Cw, vox, s));
-        c->w_ws = workspace;
-        c->w_gen = c->generation;
-        c->w_all = views == nullptr;
-        c->w_views.assign(views ? views : nullptr, views ? views + nv : nullptr);
-        c->w_valid = true;
+        ctrex_ctx::WeightKey k{workspace, c->generation, views == nullptr, {}};
+        if (views) k.views.assign(views, views + nv);
+        c->w_cache.insert(c->w_cache.begin(), std::move(k));
+        if (c->w_cache.size() > kMaxWeightSets) c->w_cache.pop_back();
+    } else if (hit != c->w_cache.begin()) {
+        std::rotate(c->w_cache.begin(), hit, hit + 1);
     }
     const void *gather = vol;
     if (gdt != F32) {

@@ -45,12 +45,16 @@ struct ctrex_ctx {
     void *d_scratch = nullptr;  // general scratch (learned-correction kernels)
     size_t scratch_cap = 0;
     size_t part_cap = 0;
-    // SIRT weight cache key
-    const void *w_ws = nullptr;
-    uint64_t w_gen = 0;
-    std::vector<int32_t> w_views;
-    bool w_all = false;
-    bool w_valid = false;
+    // SIRT weight cache: which workspaces hold valid R and C for which
+    // (geometry generation, view list); most recent first, a few entries so
+    // ordered subsets (one workspace each) keep their weights
+    struct WeightKey {
+        const void *ws;
+        uint64_t gen;
+        bool all;
+        std::vector<int32_t> views;
+    };
+    std::vector<WeightKey> w_cache;
     // kernel timing (ctrex_profile_enable)
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;

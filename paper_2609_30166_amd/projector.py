@@ -174,12 +174,15 @@ class Geometry:
         if recompute_weights:
             flags |= _lib.RECOMPUTE_WEIGHTS
         if workspace is None:
+            # one workspace per view list, so ordered subsets keep their R and C
             key = (None if views is None else tuple(np.asarray(views).ravel().tolist()),
                    gather_dtype)
-            workspace = self._ws.get(key)
+            workspace = self._ws.pop(key, None)
             if workspace is None:
                 workspace = self.workspace(views, gather_dtype)
-                self._ws = {key: workspace}
+            self._ws[key] = workspace
+            while len(self._ws) > 64:
+                self._ws.pop(next(iter(self._ws)))
         vp, nv, _keep = _views_arg(views)
         out = np.zeros(max(int(n_iter), 0), dtype=np.float64) if norms else None
         check(self._ctx, _lib.lib().ctrex_sirt_iterate(
@@ -201,6 +204,32 @@ class Geometry:
             ctypes.c_void_p(sino.data_ptr()), _DT[sino.dtype], vp, nv, ctypes.byref(out),
             _stream(self.device)))
         return out.value
+
+    def os_sirt(self, vol, sino, subsets, n_epochs, alpha=1.0, nonneg=False,
+                gather_dtype=torch.float32, norms=False):
+        """Ordered-subset SIRT (Sec. 2.3.2): each epoch applies Eq. (1) once per
+        subset P_k of ``subsets`` (lists of projection indices), in order, with
+        that subset's own R and C.  ``sino`` holds all projections
+        [n_proj][n_v][n_u].  Returns, when ``norms``, the residual norm over
+        each subset before its update, [n_epochs][n_subsets]."""
+        subsets = [np.asarray(s, dtype=np.int32).ravel() for s in subsets]
+        if not subsets or any(s.size == 0 for s in subsets):
+            raise ValueError("subsets must be non-empty lists of projection indices")
+        self._check_tensor(sino, self.sino_shape(), _DT, "sino")
+        parts = getattr(self, "_os_parts", None)
+        key = (sino.data_ptr(), tuple(tuple(s.tolist()) for s in subsets))
+        if parts is None or parts[0] != key:
+            idx = [torch.as_tensor(s, dtype=torch.long, device=self.device) for s in subsets]
+            parts = (key, [sino.index_select(0, i).contiguous() for i in idx])
+            self._os_parts = parts
+        out = np.zeros((int(n_epochs), len(subsets))) if norms else None
+        for e in range(int(n_epochs)):
+            for k, (s, b) in enumerate(zip(subsets, parts[1])):
+                r = self.sirt(vol, b, 1, alpha=alpha, nonneg=nonneg, gather_dtype=gather_dtype,
+                              views=s, norms=norms)
+                if norms:
+                    out[e, k] = r[0]
+        return out
 
     def sample_count(self, views=None):
         """Exact number of trilinear samples of one forward projection."""
@@ -245,6 +274,25 @@ class Geometry:
             self._ctx, ctypes.c_void_p(src.data_ptr()), _DT[src.dtype],
             ctypes.c_void_p(out.data_ptr()), _DT[dtype], src.numel(), _stream(self.device)))
         return out
+
+
+def ordered_subsets(n_proj, n_subsets, order="interleaved", seed=0):
+    """Partition of the projections 0..n_proj-1 into ``n_subsets`` subsets
+    (Sec. 2.3.2): "interleaved" (subset k = every n_subsets-th projection from
+    k, so each subset spans the whole orbit), "contiguous" (consecutive
+    blocks), or "random" (a seeded permutation cut into blocks)."""
+    n_proj, n_subsets = int(n_proj), int(n_subsets)
+    if not 1 <= n_subsets <= n_proj:
+        raise ValueError("need 1 <= n_subsets <= n_proj")
+    if order == "interleaved":
+        return [list(range(k, n_proj, n_subsets)) for k in range(n_subsets)]
+    if order == "contiguous":
+        base = np.arange(n_proj)
+    elif order == "random":
+        base = np.random.default_rng([seed, 31]).permutation(n_proj)
+    else:
+        raise ValueError("order must be interleaved, contiguous or random")
+    return [sorted(int(v) for v in part) for part in np.array_split(base, n_subsets)]
 
 
 class ForwardProject(torch.autograd.Function):

@@ -324,3 +324,25 @@ def test_residual_norm_matches_oracle(tiny, dev):
     assert g.residual_norm(torch.from_numpy(x).to(dev), y) <= 1e-6 * np.linalg.norm(y_ref)
     empty = torch.zeros((0, cfg.n_v, cfg.n_u), dtype=torch.float32, device=dev)
     assert g.residual_norm(torch.from_numpy(x).to(dev), empty, views=[]) == 0.0
+
+
+def test_os_sirt_matches_oracle(tiny, dev):
+    """Ordered subsets (4 interleaved subsets, 2 epochs = 8 updates) against
+    the oracle; subset weights are cached per workspace and stay valid while
+    the subsets cycle."""
+    from paper_2609_30166_amd import ordered_subsets
+    cfg, x, g, y_ref, _ = tiny
+    subsets = ordered_subsets(cfg.n_proj, 4)
+    b = torch.from_numpy(y_ref.astype(np.float32)).to(dev)
+    vol = torch.zeros(cfg.shape, dtype=torch.float32, device=dev)
+    norms = g.os_sirt(vol, b, subsets, 2, norms=True)
+    x_ref, n_ref = oracle.os_sirt(cfg.P, cfg.shape, cfg.n_u, cfg.n_v, y_ref, subsets, 2,
+                                  step=cfg.step)
+    assert rel_l2(vol.cpu().numpy(), x_ref) <= TOL
+    np.testing.assert_allclose(norms, n_ref, rtol=TOL)
+    # one subset holding every projection is plain SIRT, bit for bit
+    v1 = torch.zeros_like(vol)
+    g.os_sirt(v1, b, [list(range(cfg.n_proj))], 2)
+    v2 = torch.zeros_like(vol)
+    g.sirt(v2, b, 2, views=list(range(cfg.n_proj)), norms=False)
+    assert torch.equal(v1, v2)

@@ -165,3 +165,70 @@ def test_poisson_log_transform_is_unbiased_at_high_dose():
     assert abs(b.mean() - 1.3) < 2e-4
     # standard deviation of -ln(counts / I0) ~ 1 / sqrt(I0 exp(-y))
     assert b.std() == pytest.approx(1 / np.sqrt(1e6 * np.exp(-1.3)), rel=0.02)
+
+
+def _rows(views, n_proj):
+    """Row indices of the explicit matrix belonging to the listed projections."""
+    per = N_V * N_U
+    return np.concatenate([np.arange(v * per, (v + 1) * per) for v in views])
+
+
+def test_os_sirt_equals_block_matrix_iteration():
+    """Each subset update is x <- x + a C_k A_k^T R_k (b_k - A_k x) with the
+    subset's own row/column-sum weights, written with the explicit matrix."""
+    P, A = _problem()
+    rng = np.random.default_rng(7)
+    b = rng.uniform(0, 3, A.shape[0])
+    subsets = [[0, 4, 8], [1, 5, 9], [2, 6, 10], [3, 7, 11]]
+    x, norms = oracle.os_sirt(P, SHAPE, N_U, N_V, b.reshape(12, N_V, N_U), subsets, 2,
+                              alpha=0.9)
+    xr = np.zeros(A.shape[1])
+    want = []
+    for _ in range(2):
+        row = []
+        for s in subsets:
+            rows = _rows(s, 12)
+            Ak, bk = A[rows], b[rows]
+            Rk, Ck = _recip(Ak.sum(1)), _recip(Ak.sum(0))
+            r = bk - Ak @ xr
+            row.append(np.linalg.norm(r))
+            xr = xr + 0.9 * Ck * (Ak.T @ (Rk * r))
+        want.append(row)
+    np.testing.assert_allclose(x.ravel(), xr, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(norms, want, rtol=1e-10)
+
+
+def test_os_sirt_with_one_subset_is_sirt():
+    P, A = _problem()
+    b = np.random.default_rng(8).uniform(0, 3, (12, N_V, N_U))
+    x1, n1 = oracle.os_sirt(P, SHAPE, N_U, N_V, b, [list(range(12))], 3)
+    x2, n2 = oracle.sirt(P, SHAPE, N_U, N_V, b, 3)
+    # equal up to the summation order of the oracle's threaded backprojection
+    np.testing.assert_allclose(x1, x2, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(np.ravel(n1), n2, rtol=1e-12)
+
+
+def test_os_sirt_converges_faster_per_data_pass_on_consistent_data():
+    """On consistent data one ordered-subset epoch (as many projections as one
+    SIRT iteration) lowers the error more than one SIRT iteration."""
+    P, A = _problem()
+    xt = np.random.default_rng(9).uniform(0, 1, A.shape[1])
+    b = (A @ xt).reshape(12, N_V, N_U)
+    subsets = [[k, k + 4, k + 8] for k in range(4)]
+    xo, _ = oracle.os_sirt(P, SHAPE, N_U, N_V, b, subsets, 3)
+    xs, _ = oracle.sirt(P, SHAPE, N_U, N_V, b, 3)
+    assert np.linalg.norm(xo.ravel() - xt) < np.linalg.norm(xs.ravel() - xt)
+
+
+def test_ordered_subsets_partition_the_projections():
+    from paper_2609_30166_amd.projector import ordered_subsets
+    for order in ("interleaved", "contiguous", "random"):
+        for n, k in ((720, 10), (13, 4), (5, 5), (7, 1)):
+            s = ordered_subsets(n, k, order)
+            assert len(s) == k
+            flat = sorted(v for part in s for v in part)
+            assert flat == list(range(n)), (order, n, k)
+    assert ordered_subsets(8, 4)[1] == [1, 5]
+    assert ordered_subsets(8, 4, "contiguous")[1] == [2, 3]
+    with pytest.raises(ValueError):
+        ordered_subsets(4, 5)
