@@ -115,6 +115,20 @@ CTREX_API int ctrex_set_motion(ctrex_ctx *ctx, const float *U_dev, int32_t gx, i
                      const double *tau);
 
 /*
+ * Weighted backprojection (Sec. 3.2, 4.3.2): voxel weights w_j in [0, 1]
+ * scale the correction each voxel accumulates in ctrex_sirt_iterate, so the
+ * update becomes vol <- vol + alpha C w (A^T R (sino - A vol)); regions of
+ * weight 0 keep their starting values (a reference volume passed as `vol`).
+ * Since w_j is constant per voxel this equals weighting every contribution
+ * inside the backprojection's accumulation.  `w_dev`: device FP32 array of
+ * nx*ny*nz weights in the volume layout, owned by the caller and kept alive
+ * while set (the library stores the pointer); NULL removes the weights.
+ * ctrex_back_project itself stays the exact transpose.  Needs a geometry;
+ * ctrex_set_geometry removes the weights.
+ */
+CTREX_API int ctrex_set_voxel_weights(ctrex_ctx *ctx, const float *w_dev);
+
+/*
  * Sec. 4.1 (projection operator): sino = A vol for the projections in
  * `views` (host int32 list of n_views indices in [0, n_proj), repeats
  * allowed; NULL selects all projections in order).  `vol` has storage type

@@ -167,8 +167,12 @@ def sirt_weights(P, shape, n_u, n_v, step=0.5, views=None, U=None, tau=None):
 
 
 def sirt(P, shape, n_u, n_v, b, n_iter, alpha=1.0, step=0.5, views=None, U=None, tau=None,
-         x0=None, nonneg=False, weights=None):
-    """Eq. (1) with a single subset: returns (x_n, [||b - A x_k||_2 for k < n])."""
+         x0=None, nonneg=False, weights=None, voxel_weights=None):
+    """Eq. (1) with a single subset: returns (x_n, [||b - A x_k||_2 for k < n]).
+
+    ``voxel_weights`` (weighted backprojection, Sec. 3.2): w_j in [0, 1]
+    scaling the correction voxel j receives, x <- x + alpha C w A^T R (b - A x).
+    """
     Rw, Cw = weights if weights is not None else sirt_weights(P, shape, n_u, n_v, step, views,
                                                               U, tau)
     b = _f64(b).reshape(Rw.shape)
@@ -177,7 +181,10 @@ def sirt(P, shape, n_u, n_v, b, n_iter, alpha=1.0, step=0.5, views=None, U=None,
     for _ in range(n_iter):
         res = b - forward(P, shape, n_u, n_v, x, step, views, U, tau)
         norms.append(float(np.sqrt(np.sum(res * res))))
-        x = x + alpha * Cw * back(P, shape, n_u, n_v, Rw * res, step, views, U, tau)
+        corr = back(P, shape, n_u, n_v, Rw * res, step, views, U, tau)
+        if voxel_weights is not None:
+            corr = _f64(voxel_weights).reshape(shape) * corr
+        x = x + alpha * Cw * corr
         if nonneg:
             x = np.maximum(x, 0.0)
     return x, norms

@@ -55,6 +55,7 @@ def lib():
             "ctrex_last_error": (ctypes.c_char_p, [vp]),
             "ctrex_set_geometry": (ctypes.c_int, [vp, dp, i32, i32, i32, i32, i32, i32, i32, d]),
             "ctrex_set_motion": (ctypes.c_int, [vp, vp, i32, i32, i32, dp]),
+            "ctrex_set_voxel_weights": (ctypes.c_int, [vp, vp]),
             "ctrex_forward_project": (ctypes.c_int, [vp, vp, i32, vp, i32, ip, i32, vp]),
             "ctrex_back_project": (ctypes.c_int, [vp, vp, i32, vp, i32, ip, i32, vp]),
             "ctrex_sirt_workspace_bytes": (ctypes.c_int, [vp, i32, u32,

@@ -380,6 +380,7 @@ int ctrex_set_geometry(ctrex_ctx *c, const double *P, int32_t n_proj, int32_t n_
     c->nz = nz;
     c->step = step;
     c->have_geom = true;
+    c->d_vw = nullptr;   // weights of another volume layout are void
     c->generation++;
     c->w_cache.clear();
     return CTREX_OK;
@@ -435,6 +436,13 @@ int ctrex_set_motion(ctrex_ctx *c, const float *U_dev, int32_t gx, int32_t gy, i
     c->gz = gz;
     c->generation++;
     c->w_cache.clear();
+    return CTREX_OK;
+}
+
+int ctrex_set_voxel_weights(ctrex_ctx *c, const float *w_dev) {
+    int st = check_ready(c);
+    if (st != CTREX_OK) return st;
+    c->d_vw = w_dev;
     return CTREX_OK;
 }
 
@@ -627,7 +635,7 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
         CTREX_HIP(c, launch_back(g, w, c->d_P, r, rdt, z, 0, BP_PLAIN, c->d_scalar, part, s));
         CTREX_HIP(c, t_bp.end());
         CTREX_HIP(c, t_up.begin());
-        CTREX_HIP(c, launch_update(vol, z, Cw, alpha, (flags & CTREX_NONNEG) ? 1 : 0,
+        CTREX_HIP(c, launch_update(vol, z, Cw, c->d_vw, alpha, (flags & CTREX_NONNEG) ? 1 : 0,
                                    gdt != F32 ? shadow : nullptr, gdt, vox, s));
         if (k + 1 < n_iter)
             CTREX_HIP(c, launch_transpose_xy(gather, vt, gdt, c->nx, c->ny, c->nz, s));

@@ -33,6 +33,7 @@ struct ctrex_ctx {
     uint64_t generation = 0;  // bumps on geometry or motion change
     // motion
     float4 *d_U = nullptr;
+    const float *d_vw = nullptr;   // caller's voxel weights (weighted backprojection)
     int gx = 0, gy = 0, gz = 0;
     int warp_margin = 0;  // ceil(max |tau| * max |U component|)
     // cached device view lists (most recent first)

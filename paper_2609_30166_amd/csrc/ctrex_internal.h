@@ -85,8 +85,9 @@ hipError_t launch_max_abs(const void *x, int dtype, size_t n, float *out, hipStr
 hipError_t launch_sample_count(const RayGrid &g, unsigned long long *count, hipStream_t stream);
 hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t stream);
 hipError_t launch_recip(float *a, size_t n, hipStream_t stream);
-hipError_t launch_update(float *x, const float *z, const float *C, float alpha, int nonneg,
-                         void *shadow, int shadow_dtype, size_t n, hipStream_t stream);
+// x <- x + alpha C w z (w optional voxel weights), clamp, 16-bit shadow
+hipError_t launch_update(float *x, const float *z, const float *C, const float *w, float alpha,
+                         int nonneg, void *shadow, int shadow_dtype, size_t n, hipStream_t stream);
 // dst = src with x and y exchanged ([nz][ny][nx] -> [nz][nx][ny]); dtype
 // gives the element size.
 hipError_t launch_transpose_xy(const void *src, void *dst, int dtype, int nx, int ny, int nz,

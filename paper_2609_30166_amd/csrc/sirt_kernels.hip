@@ -60,15 +60,18 @@ __global__ __launch_bounds__(THREADS) void recip_kernel(float *a, size_t n) {
     }
 }
 
-// x <- x + alpha C z (optionally clamped at 0), shadow <- x.
+// x <- x + alpha C w z (w: optional voxel weights; optionally clamped at 0),
+// shadow <- x.
 __global__ __launch_bounds__(THREADS) void update_kernel(float *__restrict__ x,
                                                          const float *__restrict__ z,
-                                                         const float *__restrict__ C, float alpha,
+                                                         const float *__restrict__ C,
+                                                         const float *__restrict__ w, float alpha,
                                                          int nonneg, void *shadow, int sdt,
                                                          size_t n) {
     const size_t stride = static_cast<size_t>(gridDim.x) * THREADS;
     for (size_t i = static_cast<size_t>(blockIdx.x) * THREADS + threadIdx.x; i < n; i += stride) {
-        float v = fmaf(alpha * C[i], z[i], x[i]);
+        const float g = w ? alpha * C[i] * w[i] : alpha * C[i];
+        float v = fmaf(g, z[i], x[i]);
         if (nonneg) v = fmaxf(v, 0.0f);
         x[i] = v;
         if (shadow) store_from_f32(shadow, sdt, i, v);
@@ -174,10 +177,10 @@ hipError_t launch_recip(float *a, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_update(float *x, const float *z, const float *C, float alpha, int nonneg,
-                         void *shadow, int shadow_dtype, size_t n, hipStream_t s) {
+hipError_t launch_update(float *x, const float *z, const float *C, const float *w, float alpha,
+                         int nonneg, void *shadow, int shadow_dtype, size_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(update_kernel, dim3(grid_for(n)), dim3(THREADS), 0, s, x, z, C, alpha,
+    hipLaunchKernelGGL(update_kernel, dim3(grid_for(n)), dim3(THREADS), 0, s, x, z, C, w, alpha,
                        nonneg, shadow, shadow_dtype, n);
     return hipGetLastError();
 }

@@ -67,6 +67,7 @@ class Geometry:
             self._ctx, P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.n_proj,
             self.n_sub, self.n_u, self.n_v, nx, ny, nz, self.step))
         self._U = None
+        self._vw = None
         self._ws = {}
         if U is not None:
             self.set_motion(U, tau)
@@ -118,6 +119,21 @@ class Geometry:
         check(self._ctx, L.ctrex_set_motion(self._ctx, ctypes.c_void_p(U.data_ptr()), gx, gy, gz,
                                             tau.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         self._U = U
+
+    def set_voxel_weights(self, w):
+        """Weighted backprojection (Sec. 3.2, 4.3.2): voxel weights w in [0, 1]
+        scaling each voxel's correction in ``sirt``/``os_sirt``; None removes
+        them.  The tensor is kept alive by this object while set."""
+        L = _lib.lib()
+        if w is None:
+            check(self._ctx, L.ctrex_set_voxel_weights(self._ctx, None))
+            self._vw = None
+            return
+        w = torch.as_tensor(w, dtype=torch.float32, device=self.device).contiguous()
+        if tuple(w.shape) != self.shape:
+            raise ValueError("weights must have the volume shape %s" % (self.shape,))
+        check(self._ctx, L.ctrex_set_voxel_weights(self._ctx, ctypes.c_void_p(w.data_ptr())))
+        self._vw = w
 
     # ------------------------------------------------------------ operators
     def forward(self, vol, views=None, out=None, out_dtype=torch.float32):

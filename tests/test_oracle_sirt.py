@@ -232,3 +232,25 @@ def test_ordered_subsets_partition_the_projections():
     assert ordered_subsets(8, 4, "contiguous")[1] == [2, 3]
     with pytest.raises(ValueError):
         ordered_subsets(4, 5)
+
+
+def test_weighted_backprojection_equals_diagonal_weight_iteration():
+    """Weighted backprojection (Sec. 3.2): x <- x + a C W A^T R (b - A x) with a
+    diagonal W; weight 0 keeps the reference value, weight 1 everywhere is SIRT."""
+    P, A = _problem()
+    rng = np.random.default_rng(10)
+    b = rng.uniform(0, 3, A.shape[0])
+    x0 = rng.uniform(0, 1, A.shape[1])
+    w = rng.uniform(0, 1, A.shape[1])
+    w[:8] = 0.0
+    x, _ = oracle.sirt(P, SHAPE, N_U, N_V, b, 3, alpha=0.8, x0=x0.reshape(SHAPE),
+                       voxel_weights=w.reshape(SHAPE))
+    R, C = _recip(A.sum(1)), _recip(A.sum(0))
+    xr = x0.copy()
+    for _ in range(3):
+        xr = xr + 0.8 * C * w * (A.T @ (R * (b - A @ xr)))
+    np.testing.assert_allclose(x.ravel(), xr, rtol=1e-10, atol=1e-12)
+    np.testing.assert_array_equal(x.ravel()[:8], x0[:8])
+    x1, _ = oracle.sirt(P, SHAPE, N_U, N_V, b, 2, voxel_weights=np.ones(SHAPE))
+    x2, _ = oracle.sirt(P, SHAPE, N_U, N_V, b, 2)
+    np.testing.assert_allclose(x1, x2, rtol=1e-12, atol=1e-15)
