@@ -67,6 +67,7 @@ def _load():
                                         dp, i, i, i, dp, dp]
             lib.oracle_forward_indicator.argtypes = [dp, i, i, i, i, i, i, i, ctypes.c_double,
                                                      dp, dp, dp]
+            lib.oracle_back_voxel.argtypes = [dp, i, i, i, i, i, i, i, dp, ip, i, dp]
             lib.oracle_num_threads.restype = i
             _lib = lib
     return _lib
@@ -137,6 +138,23 @@ def back(P, shape, n_u, n_v, sino, step=0.5, views=None, U=None, tau=None):
     return out
 
 
+def back_voxel(P, shape, n_u, n_v, sino, views=None):
+    """z = B y, float64 [nz][ny][nx]: the paper's voxel-driven backprojector
+    (Sec. 4.1), each voxel centre projected onto every listed detector image
+    and the image sampled bilinearly (zero outside), sub-views averaged."""
+    P, n_proj, n_sub = _geom(P)
+    nz, ny, nx = shape
+    v, nvw = _views(views, n_proj)
+    sino = _f64(sino).reshape(nvw, n_v, n_u)
+    out = np.zeros(shape)
+    st = _load().oracle_back_voxel(
+        _dp(P), n_proj, n_sub, n_u, n_v, nx, ny, nz, _dp(sino),
+        v.ctypes.data_as(ctypes.POINTER(ctypes.c_int)) if v is not None else None, nvw, _dp(out))
+    if st != OK:
+        raise OracleError(st)
+    return out
+
+
 def forward_indicator(P, shape, n_u, n_v, Q, centre_idx, step=0.5):
     """The forward sampler applied to the indicator of one ellipsoid."""
     P, n_proj, n_sub = _geom(P)
@@ -157,31 +175,42 @@ def _safe_recip(a):
     return out
 
 
-def sirt_weights(P, shape, n_u, n_v, step=0.5, views=None, U=None, tau=None):
-    """R = 1 / (A 1) in detector space and C = 1 / (A^T 1) in voxel space."""
+def _bp(voxel, P, shape, n_u, n_v, y, step, views, U, tau):
+    if voxel:
+        if U is not None:
+            raise ValueError("the voxel-driven backprojector has no motion warp")
+        return back_voxel(P, shape, n_u, n_v, y, views)
+    return back(P, shape, n_u, n_v, y, step, views, U, tau)
+
+
+def sirt_weights(P, shape, n_u, n_v, step=0.5, views=None, U=None, tau=None, voxel_bp=False):
+    """R = 1 / (A 1) in detector space and C = 1 / (B 1) in voxel space, B the
+    backprojector (A^T, or the voxel-driven one)."""
     ones_v = np.ones(shape)
     Rw = _safe_recip(forward(P, shape, n_u, n_v, ones_v, step, views, U, tau))
     ones_s = np.ones_like(Rw)
-    Cw = _safe_recip(back(P, shape, n_u, n_v, ones_s, step, views, U, tau))
+    Cw = _safe_recip(_bp(voxel_bp, P, shape, n_u, n_v, ones_s, step, views, U, tau))
     return Rw, Cw
 
 
 def sirt(P, shape, n_u, n_v, b, n_iter, alpha=1.0, step=0.5, views=None, U=None, tau=None,
-         x0=None, nonneg=False, weights=None, voxel_weights=None):
+         x0=None, nonneg=False, weights=None, voxel_weights=None, voxel_bp=False):
     """Eq. (1) with a single subset: returns (x_n, [||b - A x_k||_2 for k < n]).
 
     ``voxel_weights`` (weighted backprojection, Sec. 3.2): w_j in [0, 1]
     scaling the correction voxel j receives, x <- x + alpha C w A^T R (b - A x).
+    ``voxel_bp``: the paper's voxel-driven backprojector B in place of A^T
+    (and C = 1 / (B 1)).
     """
     Rw, Cw = weights if weights is not None else sirt_weights(P, shape, n_u, n_v, step, views,
-                                                              U, tau)
+                                                              U, tau, voxel_bp)
     b = _f64(b).reshape(Rw.shape)
     x = np.zeros(shape) if x0 is None else _f64(x0).reshape(shape).copy()
     norms = []
     for _ in range(n_iter):
         res = b - forward(P, shape, n_u, n_v, x, step, views, U, tau)
         norms.append(float(np.sqrt(np.sum(res * res))))
-        corr = back(P, shape, n_u, n_v, Rw * res, step, views, U, tau)
+        corr = _bp(voxel_bp, P, shape, n_u, n_v, Rw * res, step, views, U, tau)
         if voxel_weights is not None:
             corr = _f64(voxel_weights).reshape(shape) * corr
         x = x + alpha * Cw * corr

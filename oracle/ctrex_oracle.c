@@ -399,3 +399,71 @@ int oracle_forward_indicator(const double *P, int n_proj, int n_sub, int nu, int
     free(tab);
     return OR_OK;
 }
+
+/*
+ * The paper's voxel-driven backprojector (Sec. 4.1, backprojection operator),
+ * an unmatched alternative to the exact transpose: for voxel j with centre
+ * X_j in the V frame and every listed projection p and sub-view s, the
+ * detector point (u, v) with P (X_j, 1)^T proportional to (u, v, 1)^T samples
+ * the correction image bilinearly (pixel centres at integer u, v; pixels
+ * outside the detector count as zero):
+ *     z_j = sum_p (1 / n_sub) sum_s r_p(u, v).
+ * A point with a zero third component (in the source's detector-parallel
+ * plane) contributes nothing.  No path-length weight: the SIRT normalisation
+ * C = 1 / (B 1) absorbs the coverage (the paper's geometry-dependent
+ * normalisation).
+ */
+static double bilinear_image(const double *img, int nu, int nv, double u, double v)
+{
+    double fu0 = floor(u), fv0 = floor(v);
+    int u0 = (int)fu0, v0 = (int)fv0;
+    double fu = u - fu0, fv = v - fv0;
+    double acc = 0.0;
+    for (int dv = 0; dv < 2; ++dv) {
+        for (int du = 0; du < 2; ++du) {
+            int iu = u0 + du, iv = v0 + dv;
+            if (iu < 0 || iu >= nu || iv < 0 || iv >= nv)
+                continue;
+            double wgt = (du ? fu : 1.0 - fu) * (dv ? fv : 1.0 - fv);
+            acc += wgt * img[(size_t)iv * nu + iu];
+        }
+    }
+    return acc;
+}
+
+int oracle_back_voxel(const double *P, int n_proj, int n_sub, int nu, int nv, int nx, int ny,
+                      int nz, const double *sino, const int *views, int n_views, double *vol)
+{
+    if (!views)
+        n_views = n_proj;
+    if (n_proj < 1 || n_sub < 1 || nu < 1 || nv < 1 || nx < 1 || ny < 1 || nz < 1 || n_views < 0)
+        return OR_EINVAL;
+    for (int k = 0; k < n_views; ++k)
+        if (views && (views[k] < 0 || views[k] >= n_proj))
+            return OR_EINVAL;
+    const double ox = 0.5 * (nx - 1), oy = 0.5 * (ny - 1), oz = 0.5 * (nz - 1);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int iz = 0; iz < nz; ++iz) {
+        for (int iy = 0; iy < ny; ++iy) {
+            for (int ix = 0; ix < nx; ++ix) {
+                const double X = ix - ox, Y = iy - oy, Z = iz - oz;
+                double acc = 0.0;
+                for (int k = 0; k < n_views; ++k) {
+                    int p = views ? views[k] : k;
+                    const double *img = sino + (size_t)k * nu * nv;
+                    for (int s = 0; s < n_sub; ++s) {
+                        const double *M = P + 12 * ((size_t)p * n_sub + s);
+                        double a = M[0] * X + M[1] * Y + M[2] * Z + M[3];
+                        double b = M[4] * X + M[5] * Y + M[6] * Z + M[7];
+                        double w = M[8] * X + M[9] * Y + M[10] * Z + M[11];
+                        if (w == 0.0)
+                            continue;
+                        acc += bilinear_image(img, nu, nv, a / w, b / w) / (double)n_sub;
+                    }
+                }
+                vol[((size_t)iz * ny + iy) * nx + ix] += acc;
+            }
+        }
+    }
+    return OR_OK;
+}
