@@ -22,8 +22,12 @@ HBM traffic: ``roofline.traffic`` is read from the committed counter summary
 same counters of a plain copy kernel of known size, ``--copy-calibrate``);
 it is null when the dominant kernel's sources changed since.
 
+The ``voxel_bp`` object repeats the SIRT run with the paper's voxel-driven
+backprojector in place of the exact transpose (speed, and residual and PSNR
+after the same number of iterations).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|bf16]
-                       [--copy-calibrate] [--no-learned]
+                       [--copy-calibrate] [--no-learned] [--no-voxel-bp]
 """
 
 from __future__ import annotations
@@ -151,6 +155,51 @@ def time_to_psnr(dev):
                         "phantom; inference only"}
 
 
+def voxel_bp_comparison(g, b, sdt, xt, vol_exact, norms_exact, args, bp_ms_exact, ms_exact):
+    """The same SIRT run (warm-up + timed steps + one more) with the paper's
+    voxel-driven backprojector B and C = 1 / (B 1) in place of the exact
+    transpose: per-step and per-kernel times, and the residual norm and PSNR
+    reached after the same number of iterations as the exact-transpose run."""
+    import numpy as np
+    import torch
+
+    from paper_2609_30166_amd.learned import fov_mask, psnr
+
+    vol = torch.zeros_like(vol_exact)
+    ws = g.workspace(gather_dtype=sdt)
+    for _ in range(args.warmup):
+        g.sirt(vol, b, 1, gather_dtype=sdt, workspace=ws, norms=False, voxel_bp=True)
+    g.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.sirt(vol, b, 1, gather_dtype=sdt, workspace=ws, norms=False, voxel_bp=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.profile_read()
+    g.profile(False)
+    norms = g.sirt(vol, b, 1, gather_dtype=sdt, workspace=ws, voxel_bp=True)
+    mask = fov_mask(g.shape, g.device)
+    bp_ms = prof["back"][0] / max(prof["back"][1], 1)
+    n_vv = float(np.prod(g.shape)) * g.n_proj
+    res = {
+        "iterations": args.warmup + args.steps + 1,
+        "ms_per_step": 1e3 * (t1 - t0) / args.steps,
+        "fp_ms": prof["forward"][0] / max(prof["forward"][1], 1),
+        "bp_ms": bp_ms,
+        "update_ms": prof["update"][0] / max(prof["update"][1], 1),
+        "bp_voxel_views_per_s": n_vv / (bp_ms * 1e-3),
+        "bp_speedup_vs_exact": bp_ms_exact / bp_ms,
+        "step_speedup_vs_exact": ms_exact / (1e3 * (t1 - t0) / args.steps),
+        "residual_norm_after": float(norms[0]),
+        "residual_norm_after_exact": float(norms_exact[0]),
+        "psnr_db": psnr(vol, xt, mask),
+        "psnr_db_exact": psnr(vol_exact, xt, mask),
+    }
+    del ws, vol
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +213,8 @@ def main():
                     help="also run a plain copy kernel of known size (counter calibration)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-SIRT time-to-PSNR comparison")
+    ap.add_argument("--no-voxel-bp", action="store_true",
+                    help="skip the SIRT run with the voxel-driven backprojector")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -248,6 +299,9 @@ def main():
                      "per launch / mean launch time" % (GATHER_BYTES[args.dtype], n_s),
         },
     }
+    if not args.no_voxel_bp:
+        _log("SIRT with the voxel-driven backprojector ...")
+        out["voxel_bp"] = voxel_bp_comparison(g, b, sdt, xt, vol, norms, args, bp_ms, ms_step)
     if args.copy_calibrate:
         copy_calibration(dev)
     del b, vol, ws, xt

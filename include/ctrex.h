@@ -75,6 +75,7 @@ typedef struct ctrex_ctx ctrex_ctx;
 #define CTREX_BF16_GATHER 2u   /* ray-march a BF16 shadow of the FP32 volume */
 #define CTREX_F16_GATHER 4u    /* ray-march an FP16 shadow of the FP32 volume */
 #define CTREX_RECOMPUTE_WEIGHTS 8u /* rebuild R and C even if cached */
+#define CTREX_VOXEL_BP 16u     /* backproject with ctrex_back_project_voxel's B */
 
 /* Create a context bound to HIP device `device`. */
 CTREX_API int ctrex_create(ctrex_ctx **out, int device);
@@ -152,6 +153,25 @@ CTREX_API int ctrex_back_project(ctrex_ctx *ctx, const void *sino, int32_t sino_
                        void *stream);
 
 /*
+ * Sec. 4.1 (backprojection operator), the paper's voxel-driven form:
+ * vol (+)= B sino over the listed projections, where for voxel j with centre
+ * X_j (V frame, index coordinates centred on the volume) and each sub-view
+ * (p, s) the detector point (u, v), P_{p,s} (X_j, 1)^T ~ (u, v, 1)^T, samples
+ * the image of projection p bilinearly (pixel centres at integer u, v; zero
+ * beyond the border):  z_j = (1 / n_sub) sum_{p, s} r_p(u, v).  A view whose
+ * depth row vanishes at X_j (the voxel lies in the source's detector-parallel
+ * plane) contributes nothing.  B is not the transpose of
+ * ctrex_forward_project; ctrex_sirt_iterate pairs it with C = 1 / (B 1) under
+ * CTREX_VOXEL_BP.  Arguments, layouts and the empty list behave as in
+ * ctrex_back_project.  Each voxel is summed by one thread in FP64 in view
+ * order, so results are deterministic.  Needs n_u, n_v >= 2
+ * (CTREX_ESHAPE) and no motion field (CTREX_ESTATE).
+ */
+CTREX_API int ctrex_back_project_voxel(ctrex_ctx *ctx, const void *sino, int32_t sino_dtype,
+                                       float *vol, int32_t accumulate, const int32_t *views,
+                                       int32_t n_views, void *stream);
+
+/*
  * Bytes of device workspace ctrex_sirt_iterate needs for n_views projections
  * (n_views <= 0 means all) and `flags` (the gather shadows need room).
  */
@@ -161,7 +181,9 @@ CTREX_API int ctrex_sirt_workspace_bytes(const ctrex_ctx *ctx, int32_t n_views, 
 /*
  * Eq. (1) with the listed projections as the subset P_k (Sec. 2.3.1, 2.3.2):
  *   vol <- vol + alpha C A^T R (sino - A vol), repeated n_iter times,
- * with R = 1 / (A 1) and C = 1 / (A^T 1) (zero where a sum is zero).
+ * with R = 1 / (A 1) and C = 1 / (A^T 1) (zero where a sum is zero); with
+ * CTREX_VOXEL_BP the voxel-driven B of ctrex_back_project_voxel takes the
+ * place of A^T, and C = 1 / (B 1).
  * `vol` is the device float32 volume (in/out); `sino` the measured data
  * (device, sino_dtype, [n_views][n_v][n_u]).  `workspace` is caller-owned
  * device memory of at least ctrex_sirt_workspace_bytes(); it holds R, C and

@@ -68,6 +68,8 @@ def _load():
             lib.oracle_forward_indicator.argtypes = [dp, i, i, i, i, i, i, i, ctypes.c_double,
                                                      dp, dp, dp]
             lib.oracle_back_voxel.argtypes = [dp, i, i, i, i, i, i, i, dp, ip, i, dp]
+            lib.oracle_back_voxel_points.argtypes = [dp, i, i, i, i, i, i, i, dp, ip, i, ip, i,
+                                                     dp]
             lib.oracle_num_threads.restype = i
             _lib = lib
     return _lib
@@ -150,6 +152,23 @@ def back_voxel(P, shape, n_u, n_v, sino, views=None):
     st = _load().oracle_back_voxel(
         _dp(P), n_proj, n_sub, n_u, n_v, nx, ny, nz, _dp(sino),
         v.ctypes.data_as(ctypes.POINTER(ctypes.c_int)) if v is not None else None, nvw, _dp(out))
+    if st != OK:
+        raise OracleError(st)
+    return out
+
+
+def back_voxel_points(P, shape, n_u, n_v, sino, ijk, views=None):
+    """``back_voxel`` at the voxels ``ijk`` ([n][3] (ix, iy, iz)) only."""
+    P, n_proj, n_sub = _geom(P)
+    nz, ny, nx = shape
+    v, nvw = _views(views, n_proj)
+    sino = _f64(sino).reshape(nvw, n_v, n_u)
+    ijk = np.ascontiguousarray(np.asarray(ijk, dtype=np.int32).reshape(-1, 3))
+    out = np.zeros(ijk.shape[0])
+    st = _load().oracle_back_voxel_points(
+        _dp(P), n_proj, n_sub, n_u, n_v, nx, ny, nz, _dp(sino),
+        v.ctypes.data_as(ctypes.POINTER(ctypes.c_int)) if v is not None else None, nvw,
+        ijk.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ijk.shape[0], _dp(out))
     if st != OK:
         raise OracleError(st)
     return out

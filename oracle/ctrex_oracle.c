@@ -415,6 +415,10 @@ int oracle_forward_indicator(const double *P, int n_proj, int n_sub, int nu, int
  */
 static double bilinear_image(const double *img, int nu, int nv, double u, double v)
 {
+    /* every corner lies outside unless -1 < u < nu and -1 < v < nv (this also
+     * keeps the integer conversions below in range) */
+    if (!(u > -1.0 && u < nu && v > -1.0 && v < nv))
+        return 0.0;
     double fu0 = floor(u), fv0 = floor(v);
     int u0 = (int)fu0, v0 = (int)fv0;
     double fu = u - fu0, fv = v - fv0;
@@ -431,39 +435,74 @@ static double bilinear_image(const double *img, int nu, int nv, double u, double
     return acc;
 }
 
-int oracle_back_voxel(const double *P, int n_proj, int n_sub, int nu, int nv, int nx, int ny,
-                      int nz, const double *sino, const int *views, int n_views, double *vol)
+/* z_j for the voxel with centre (X, Y, Z) in the V frame. */
+static double voxel_sum(const double *P, int n_sub, int nu, int nv, const double *sino,
+                        const int *views, int n_views, double X, double Y, double Z)
 {
-    if (!views)
-        n_views = n_proj;
+    double acc = 0.0;
+    for (int k = 0; k < n_views; ++k) {
+        int p = views ? views[k] : k;
+        const double *img = sino + (size_t)k * nu * nv;
+        for (int s = 0; s < n_sub; ++s) {
+            const double *M = P + 12 * ((size_t)p * n_sub + s);
+            double a = M[0] * X + M[1] * Y + M[2] * Z + M[3];
+            double b = M[4] * X + M[5] * Y + M[6] * Z + M[7];
+            double w = M[8] * X + M[9] * Y + M[10] * Z + M[11];
+            if (w == 0.0)
+                continue;
+            acc += bilinear_image(img, nu, nv, a / w, b / w) / (double)n_sub;
+        }
+    }
+    return acc;
+}
+
+static int check_voxel_args(int n_proj, int n_sub, int nu, int nv, int nx, int ny, int nz,
+                            const int *views, int n_views)
+{
     if (n_proj < 1 || n_sub < 1 || nu < 1 || nv < 1 || nx < 1 || ny < 1 || nz < 1 || n_views < 0)
         return OR_EINVAL;
     for (int k = 0; k < n_views; ++k)
         if (views && (views[k] < 0 || views[k] >= n_proj))
             return OR_EINVAL;
+    return OR_OK;
+}
+
+int oracle_back_voxel(const double *P, int n_proj, int n_sub, int nu, int nv, int nx, int ny,
+                      int nz, const double *sino, const int *views, int n_views, double *vol)
+{
+    if (!views)
+        n_views = n_proj;
+    int st = check_voxel_args(n_proj, n_sub, nu, nv, nx, ny, nz, views, n_views);
+    if (st != OR_OK)
+        return st;
     const double ox = 0.5 * (nx - 1), oy = 0.5 * (ny - 1), oz = 0.5 * (nz - 1);
 #pragma omp parallel for collapse(2) schedule(static)
-    for (int iz = 0; iz < nz; ++iz) {
-        for (int iy = 0; iy < ny; ++iy) {
-            for (int ix = 0; ix < nx; ++ix) {
-                const double X = ix - ox, Y = iy - oy, Z = iz - oz;
-                double acc = 0.0;
-                for (int k = 0; k < n_views; ++k) {
-                    int p = views ? views[k] : k;
-                    const double *img = sino + (size_t)k * nu * nv;
-                    for (int s = 0; s < n_sub; ++s) {
-                        const double *M = P + 12 * ((size_t)p * n_sub + s);
-                        double a = M[0] * X + M[1] * Y + M[2] * Z + M[3];
-                        double b = M[4] * X + M[5] * Y + M[6] * Z + M[7];
-                        double w = M[8] * X + M[9] * Y + M[10] * Z + M[11];
-                        if (w == 0.0)
-                            continue;
-                        acc += bilinear_image(img, nu, nv, a / w, b / w) / (double)n_sub;
-                    }
-                }
-                vol[((size_t)iz * ny + iy) * nx + ix] += acc;
-            }
-        }
-    }
+    for (int iz = 0; iz < nz; ++iz)
+        for (int iy = 0; iy < ny; ++iy)
+            for (int ix = 0; ix < nx; ++ix)
+                vol[((size_t)iz * ny + iy) * nx + ix] +=
+                    voxel_sum(P, n_sub, nu, nv, sino, views, n_views, ix - ox, iy - oy, iz - oz);
+    return OR_OK;
+}
+
+/* The same sums for a list of voxels (ix, iy, iz) only: out[i] = z_{j_i}. */
+int oracle_back_voxel_points(const double *P, int n_proj, int n_sub, int nu, int nv, int nx,
+                             int ny, int nz, const double *sino, const int *views, int n_views,
+                             const int *ijk, int n_pts, double *out)
+{
+    if (!views)
+        n_views = n_proj;
+    int st = check_voxel_args(n_proj, n_sub, nu, nv, nx, ny, nz, views, n_views);
+    if (st != OR_OK)
+        return st;
+    for (int i = 0; i < n_pts; ++i)
+        if (ijk[3 * i] < 0 || ijk[3 * i] >= nx || ijk[3 * i + 1] < 0 || ijk[3 * i + 1] >= ny ||
+            ijk[3 * i + 2] < 0 || ijk[3 * i + 2] >= nz)
+            return OR_EINVAL;
+    const double ox = 0.5 * (nx - 1), oy = 0.5 * (ny - 1), oz = 0.5 * (nz - 1);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int i = 0; i < n_pts; ++i)
+        out[i] = voxel_sum(P, n_sub, nu, nv, sino, views, n_views, ijk[3 * i] - ox,
+                           ijk[3 * i + 1] - oy, ijk[3 * i + 2] - oz);
     return OR_OK;
 }

@@ -21,7 +21,7 @@ STATUS = {
     -5: "CTREX_EDEVICE", -6: "CTREX_EWORKSPACE", -7: "CTREX_ESTATE", -8: "CTREX_ENONFINITE",
 }
 F32, BF16, F16 = 0, 1, 2
-NONNEG, BF16_GATHER, F16_GATHER, RECOMPUTE_WEIGHTS = 1, 2, 4, 8
+NONNEG, BF16_GATHER, F16_GATHER, RECOMPUTE_WEIGHTS, VOXEL_BP = 1, 2, 4, 8, 16
 NN_RELU, NN_ACCUMULATE, NN_OUT_F32 = 1, 2, 4
 
 
@@ -58,6 +58,7 @@ def lib():
             "ctrex_set_voxel_weights": (ctypes.c_int, [vp, vp]),
             "ctrex_forward_project": (ctypes.c_int, [vp, vp, i32, vp, i32, ip, i32, vp]),
             "ctrex_back_project": (ctypes.c_int, [vp, vp, i32, vp, i32, ip, i32, vp]),
+            "ctrex_back_project_voxel": (ctypes.c_int, [vp, vp, i32, vp, i32, ip, i32, vp]),
             "ctrex_sirt_workspace_bytes": (ctypes.c_int, [vp, i32, u32,
                                                           ctypes.POINTER(ctypes.c_size_t)]),
             "ctrex_sirt_iterate": (ctypes.c_int, [vp, vp, vp, i32, i32, ctypes.c_float, u32, ip,

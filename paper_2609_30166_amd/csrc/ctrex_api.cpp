@@ -534,6 +534,31 @@ int ctrex_back_project(ctrex_ctx *c, const void *sino, int32_t sino_dtype, float
     return CTREX_OK;
 }
 
+int ctrex_back_project_voxel(ctrex_ctx *c, const void *sino, int32_t sino_dtype, float *vol,
+                             int32_t accumulate, const int32_t *views, int32_t n_views,
+                             void *stream) {
+    int st = check_ready(c);
+    if (st != CTREX_OK) return st;
+    if (!vol) return fail(c, CTREX_EINVAL, "vol must be a device pointer");
+    if (!valid_dtype(sino_dtype)) return fail(c, CTREX_EINVAL, "unknown dtype %d", sino_dtype);
+    if (c->d_U) return fail(c, CTREX_ESTATE, "the voxel-driven backprojector has no motion warp");
+    if (c->n_u < 2 || c->n_v < 2)
+        return fail(c, CTREX_ESHAPE, "the voxel-driven backprojector needs n_u, n_v >= 2");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t *dv;
+    int32_t nv;
+    if ((st = resolve_views(c, views, n_views, &dv, &nv, s)) != CTREX_OK) return st;
+    if (nv > 0 && !sino) return fail(c, CTREX_EINVAL, "sino must be a device pointer");
+    if (nv == 0) {
+        if (!accumulate)
+            CTREX_HIP(c, launch_fill_zero(vol, sizeof(float) * static_cast<size_t>(c->nx) * c->ny * c->nz, s));
+        return CTREX_OK;
+    }
+    CTREX_HIP(c, launch_back_voxel(make_grid(c, dv, nv), c->d_P, sino, sino_dtype, vol,
+                                   accumulate ? 1 : 0, 0, s));
+    return CTREX_OK;
+}
+
 int ctrex_sirt_workspace_bytes(const ctrex_ctx *c, int32_t n_views, uint32_t flags,
                                size_t *bytes) {
     if (!c || !bytes) return CTREX_EINVAL;
@@ -554,8 +579,13 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
     if (n_iter < 0) return fail(c, CTREX_EINVAL, "n_iter must be >= 0");
     if (!std::isfinite(alpha)) return fail(c, CTREX_EINVAL, "alpha must be finite");
     const uint32_t known = CTREX_NONNEG | CTREX_BF16_GATHER | CTREX_F16_GATHER |
-                           CTREX_RECOMPUTE_WEIGHTS;
+                           CTREX_RECOMPUTE_WEIGHTS | CTREX_VOXEL_BP;
     if (flags & ~known) return fail(c, CTREX_EINVAL, "unknown flags 0x%x", flags & ~known);
+    const bool vbp = (flags & CTREX_VOXEL_BP) != 0;
+    if (vbp && c->d_U)
+        return fail(c, CTREX_ESTATE, "the voxel-driven backprojector has no motion warp");
+    if (vbp && (c->n_u < 2 || c->n_v < 2))
+        return fail(c, CTREX_ESHAPE, "the voxel-driven backprojector needs n_u, n_v >= 2");
     if ((flags & CTREX_BF16_GATHER) && (flags & CTREX_F16_GATHER))
         return fail(c, CTREX_EINVAL, "BF16 and F16 gathers are exclusive");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -589,6 +619,7 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
     // R and C for this geometry / motion / subset / workspace, kept between calls.
     auto same_key = [&](const ctrex_ctx::WeightKey &e) {
         return e.ws == workspace && e.gen == c->generation && e.all == (views == nullptr) &&
+               e.voxel_bp == vbp &&
                (views == nullptr ||
                 (static_cast<int32_t>(e.views.size()) == nv &&
                  std::memcmp(e.views.data(), views, sizeof(int32_t) * nv) == 0));
@@ -605,9 +636,13 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
                          c->w_cache.end());
         FpExtra none{nullptr, nullptr, nullptr};
         CTREX_HIP(c, launch_forward(g, w, nullptr, F32, Rw, F32, FP_RECIP_ONES, none, s));
-        CTREX_HIP(c, launch_back(g, w, c->d_P, nullptr, F32, Cw, 0, BP_ONES, c->d_scalar, part, s));
+        if (vbp)
+            CTREX_HIP(c, launch_back_voxel(g, c->d_P, nullptr, F32, Cw, 0, 1, s));
+        else
+            CTREX_HIP(c, launch_back(g, w, c->d_P, nullptr, F32, Cw, 0, BP_ONES, c->d_scalar, part,
+                                     s));
         CTREX_HIP(c, launch_recip(Cw, vox, s));
-        ctrex_ctx::WeightKey k{workspace, c->generation, views == nullptr, {}};
+        ctrex_ctx::WeightKey k{workspace, c->generation, views == nullptr, vbp, {}};
         if (views) k.views.assign(views, views + nv);
         c->w_cache.insert(c->w_cache.begin(), std::move(k));
         if (c->w_cache.size() > kMaxWeightSets) c->w_cache.pop_back();
@@ -632,7 +667,10 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
         CTREX_HIP(c, t_fp.end());
         CTREX_HIP(c, launch_sum_partials(partials, g.total_blocks, resid + (k % kResidCap), s));
         CTREX_HIP(c, t_bp.begin());
-        CTREX_HIP(c, launch_back(g, w, c->d_P, r, rdt, z, 0, BP_PLAIN, c->d_scalar, part, s));
+        if (vbp)
+            CTREX_HIP(c, launch_back_voxel(g, c->d_P, r, rdt, z, 0, 0, s));
+        else
+            CTREX_HIP(c, launch_back(g, w, c->d_P, r, rdt, z, 0, BP_PLAIN, c->d_scalar, part, s));
         CTREX_HIP(c, t_bp.end());
         CTREX_HIP(c, t_up.begin());
         CTREX_HIP(c, launch_update(vol, z, Cw, c->d_vw, alpha, (flags & CTREX_NONNEG) ? 1 : 0,

@@ -47,12 +47,13 @@ struct ctrex_ctx {
     size_t scratch_cap = 0;
     size_t part_cap = 0;
     // SIRT weight cache: which workspaces hold valid R and C for which
-    // (geometry generation, view list); most recent first, a few entries so
+    // (geometry generation, view list, backprojector); most recent first, a few entries so
     // ordered subsets (one workspace each) keep their weights
     struct WeightKey {
         const void *ws;
         uint64_t gen;
         bool all;
+        bool voxel_bp;  // C = 1 / (B 1) of the voxel-driven backprojector
         std::vector<int32_t> views;
     };
     std::vector<WeightKey> w_cache;

@@ -80,6 +80,10 @@ hipError_t launch_back(const RayGrid &g, const WarpGrid &w, const double *Pmat, 
                        int sino_dtype, float *vol, int accumulate, int mode, float *scratch,
                        float *part, hipStream_t stream);
 size_t back_scratch_bytes(const RayGrid &g);
+// vol (+)= B sino with the voxel-driven backprojector (ones != 0: B 1, sino
+// ignored); deterministic, no scratch.  Needs n_u, n_v >= 2.
+hipError_t launch_back_voxel(const RayGrid &g, const double *Pmat, const void *sino, int sino_dtype,
+                             float *vol, int accumulate, int ones, hipStream_t stream);
 // *out = max |x_i| over n elements (out is overwritten).
 hipError_t launch_max_abs(const void *x, int dtype, size_t n, float *out, hipStream_t stream);
 hipError_t launch_sample_count(const RayGrid &g, unsigned long long *count, hipStream_t stream);

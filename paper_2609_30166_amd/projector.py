@@ -163,6 +163,22 @@ class Geometry:
             _stream(self.device)))
         return out
 
+    def back_voxel(self, sino, views=None, out=None, accumulate=False):
+        """vol (+)= B sino with the paper's voxel-driven backprojector (Sec. 4.1):
+        voxel centres projected onto each image and sampled bilinearly; not the
+        transpose of ``forward``.  No motion warp."""
+        self._check_tensor(sino, self.sino_shape(views), _DT, "sino")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+            accumulate = False
+        self._check_tensor(out, self.shape, (torch.float32,), "out")
+        vp, nv, _keep = _views_arg(views)
+        check(self._ctx, _lib.lib().ctrex_back_project_voxel(
+            self._ctx, ctypes.c_void_p(sino.data_ptr()), _DT[sino.dtype],
+            ctypes.c_void_p(out.data_ptr()), 1 if accumulate else 0, vp, nv,
+            _stream(self.device)))
+        return out
+
     def workspace_bytes(self, views=None, gather_dtype=torch.float32):
         n = ctypes.c_size_t(0)
         nv = 0 if views is None else self.n_views(views)
@@ -176,8 +192,9 @@ class Geometry:
                            device=self.device)
 
     def sirt(self, vol, sino, n_iter, alpha=1.0, nonneg=False, gather_dtype=torch.float32,
-             views=None, workspace=None, norms=True, recompute_weights=False):
+             views=None, workspace=None, norms=True, recompute_weights=False, voxel_bp=False):
         """Eq. (1): ``n_iter`` SIRT updates of ``vol`` (float32, in place).
+        ``voxel_bp``: backproject with ``back_voxel``'s B (C = 1 / (B 1)).
 
         Returns the residual norms ||sino - A vol_k|| (numpy) when ``norms``,
         else None (and the call does not wait for the device).
@@ -189,10 +206,12 @@ class Geometry:
             flags |= _lib.NONNEG
         if recompute_weights:
             flags |= _lib.RECOMPUTE_WEIGHTS
+        if voxel_bp:
+            flags |= _lib.VOXEL_BP
         if workspace is None:
             # one workspace per view list, so ordered subsets keep their R and C
             key = (None if views is None else tuple(np.asarray(views).ravel().tolist()),
-                   gather_dtype)
+                   gather_dtype, bool(voxel_bp))
             workspace = self._ws.pop(key, None)
             if workspace is None:
                 workspace = self.workspace(views, gather_dtype)
@@ -222,7 +241,7 @@ class Geometry:
         return out.value
 
     def os_sirt(self, vol, sino, subsets, n_epochs, alpha=1.0, nonneg=False,
-                gather_dtype=torch.float32, norms=False):
+                gather_dtype=torch.float32, norms=False, voxel_bp=False):
         """Ordered-subset SIRT (Sec. 2.3.2): each epoch applies Eq. (1) once per
         subset P_k of ``subsets`` (lists of projection indices), in order, with
         that subset's own R and C.  ``sino`` holds all projections
@@ -242,7 +261,7 @@ class Geometry:
         for e in range(int(n_epochs)):
             for k, (s, b) in enumerate(zip(subsets, parts[1])):
                 r = self.sirt(vol, b, 1, alpha=alpha, nonneg=nonneg, gather_dtype=gather_dtype,
-                              views=s, norms=norms)
+                              views=s, norms=norms, voxel_bp=voxel_bp)
                 if norms:
                     out[e, k] = r[0]
         return out

@@ -103,3 +103,16 @@ def test_sirt_with_voxel_backprojector_is_the_matrix_iteration():
         x = x + 0.7 * C * (B @ (R * (b - A @ x)))
     got, _ = oracle.sirt(P, shape, n_u, n_v, b, 3, alpha=0.7, voxel_bp=True)
     np.testing.assert_allclose(got.ravel(), x, rtol=1e-10, atol=1e-12)
+
+
+def test_points_variant_agrees_with_the_volume():
+    shape = (6, 5, 7)
+    n_u, n_v = 20, 18
+    P = synth.circular_cone(8, n_u, n_v, 25.0, 50.0, 1.0, n_sub=2)
+    rng = np.random.default_rng(11)
+    img = rng.uniform(-1, 1, (5, n_v, n_u))
+    views = [7, 0, 3, 3, 5]
+    vol = oracle.back_voxel(P, shape, n_u, n_v, img, views=views)
+    ijk = np.stack([rng.integers(0, n, 40) for n in (7, 5, 6)], 1)
+    pts = oracle.back_voxel_points(P, shape, n_u, n_v, img, ijk, views=views)
+    np.testing.assert_array_equal(pts, vol[ijk[:, 2], ijk[:, 1], ijk[:, 0]])
