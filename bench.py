@@ -51,6 +51,7 @@ WEIGHTS_FILE = os.path.join(ROOT, "paper_2609_30166_amd", "weights", "unet_learn
 KERNEL_SOURCES = {
     "bp_brick_kernel": ["backproject.hip", "ray_common.h", "ctrex_internal.h"],
     "fp_kernel": ["projector.hip", "ray_common.h", "ctrex_internal.h"],
+    "vbp_kernel": ["voxel_bp.hip", "ray_common.h", "ctrex_internal.h"],
 }
 
 

@@ -164,8 +164,8 @@ CTREX_API int ctrex_back_project(ctrex_ctx *ctx, const void *sino, int32_t sino_
  * ctrex_forward_project; ctrex_sirt_iterate pairs it with C = 1 / (B 1) under
  * CTREX_VOXEL_BP.  Arguments, layouts and the empty list behave as in
  * ctrex_back_project.  Each voxel is summed by one thread in FP64 in view
- * order, so results are deterministic.  Needs n_u, n_v >= 2
- * (CTREX_ESHAPE) and no motion field (CTREX_ESTATE).
+ * order, so results are deterministic.  Needs 2 <= n_u, n_v < 2^24 and
+ * n_u n_v < 2^30 (CTREX_ESHAPE) and no motion field (CTREX_ESTATE).
  */
 CTREX_API int ctrex_back_project_voxel(ctrex_ctx *ctx, const void *sino, int32_t sino_dtype,
                                        float *vol, int32_t accumulate, const int32_t *views,

@@ -534,6 +534,13 @@ int ctrex_back_project(ctrex_ctx *c, const void *sino, int32_t sino_dtype, float
     return CTREX_OK;
 }
 
+// Detector sizes the voxel-driven backprojector's bilinear lookups support
+// (2 x 2 footprint, 24-bit row products, 32-bit byte offsets per image).
+static bool voxel_bp_detector_ok(const ctrex_ctx *c) {
+    return c->n_u >= 2 && c->n_v >= 2 && c->n_u < (1 << 24) && c->n_v < (1 << 24) &&
+           static_cast<long long>(c->n_u) * c->n_v < (1ll << 30);
+}
+
 int ctrex_back_project_voxel(ctrex_ctx *c, const void *sino, int32_t sino_dtype, float *vol,
                              int32_t accumulate, const int32_t *views, int32_t n_views,
                              void *stream) {
@@ -542,8 +549,9 @@ int ctrex_back_project_voxel(ctrex_ctx *c, const void *sino, int32_t sino_dtype,
     if (!vol) return fail(c, CTREX_EINVAL, "vol must be a device pointer");
     if (!valid_dtype(sino_dtype)) return fail(c, CTREX_EINVAL, "unknown dtype %d", sino_dtype);
     if (c->d_U) return fail(c, CTREX_ESTATE, "the voxel-driven backprojector has no motion warp");
-    if (c->n_u < 2 || c->n_v < 2)
-        return fail(c, CTREX_ESHAPE, "the voxel-driven backprojector needs n_u, n_v >= 2");
+    if (!voxel_bp_detector_ok(c))
+        return fail(c, CTREX_ESHAPE, "the voxel-driven backprojector needs 2 <= n_u, n_v < 2^24 "
+                                     "and n_u n_v < 2^30");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int32_t *dv;
     int32_t nv;
@@ -584,8 +592,9 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
     const bool vbp = (flags & CTREX_VOXEL_BP) != 0;
     if (vbp && c->d_U)
         return fail(c, CTREX_ESTATE, "the voxel-driven backprojector has no motion warp");
-    if (vbp && (c->n_u < 2 || c->n_v < 2))
-        return fail(c, CTREX_ESHAPE, "the voxel-driven backprojector needs n_u, n_v >= 2");
+    if (vbp && !voxel_bp_detector_ok(c))
+        return fail(c, CTREX_ESHAPE, "the voxel-driven backprojector needs 2 <= n_u, n_v < 2^24 "
+                                     "and n_u n_v < 2^30");
     if ((flags & CTREX_BF16_GATHER) && (flags & CTREX_F16_GATHER))
         return fail(c, CTREX_EINVAL, "BF16 and F16 gathers are exclusive");
     hipStream_t s = static_cast<hipStream_t>(stream);

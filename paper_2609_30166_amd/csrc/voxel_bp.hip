@@ -37,39 +37,49 @@ constexpr int KZ = 8;
 
 typedef float f32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
 
-// Detector columns (c, c + 1) of one image row.
+// Detector columns (c, c + 1) at element `off` of an image.  The byte offset
+// is formed in 32 bits (images hold fewer than 2^30 pixels) and added to the
+// wave-uniform image base, so the loads take the scalar-base form.
 template <typename TS>
-__device__ __forceinline__ float2 row_pair(const TS *__restrict__ row, int c) {
-    return make_float2(dev::ld(row, c), dev::ld(row, c + 1));
+__device__ __forceinline__ const TS *at(const TS *img, unsigned off) {
+    return reinterpret_cast<const TS *>(reinterpret_cast<const char *>(img) +
+                                        off * static_cast<unsigned>(sizeof(TS)));
+}
+template <typename TS>
+__device__ __forceinline__ float2 row_pair(const TS *__restrict__ img, unsigned off) {
+    const TS *q = at(img, off);
+    return make_float2(dev::ld(q, 0), dev::ld(q, 1));
 }
 template <>
-__device__ __forceinline__ float2 row_pair<float>(const float *__restrict__ row, int c) {
-    const f32x2_a4 p = *reinterpret_cast<const f32x2_a4 *>(row + c);
+__device__ __forceinline__ float2 row_pair<float>(const float *__restrict__ img, unsigned off) {
+    const f32x2_a4 p = *reinterpret_cast<const f32x2_a4 *>(at(img, off));
     return make_float2(p.x, p.y);
 }
 
 // Bilinear sample of a detector image at (iu + fu, iv + fv) with zero
 // outside, for iu in [-1, nu - 1] and iv in [-1, nv - 1] (nu, nv >= 2).  The
-// loads always stay inside the image: the column pair starts at
-// clamp(iu, 0, nu - 2) and the rows are clamped, and the corners that fall
-// outside get weight 0.  ONES: the sum of the in-image weights (no loads).
+// loads stay inside the image for any (iu, iv): the column pair starts at
+// c = clamp(iu, 0, nu - 2) and both rows are clamped to [0, nv - 1]; the
+// weights (ea, eb) of the pair's two columns are those of columns iu and
+// iu + 1 moved to where they sit in the pair (0 for a column outside).
+// ONES: the sum of the in-image weights (no loads).
 template <typename TS, bool ONES>
 __device__ __forceinline__ float bilinear(const TS *__restrict__ img, int nu, int nv, int iu,
                                           int iv, float fu, float fv) {
-    const float wl = iu >= 0 ? 1.0f - fu : 0.0f;
-    const float wr = iu < nu - 1 ? fu : 0.0f;
     const float wt = iv >= 0 ? 1.0f - fv : 0.0f;
     const float wb = iv < nv - 1 ? fv : 0.0f;
-    if (ONES) return (wl + wr) * (wt + wb);
-    const int c = min(max(iu, 0), nu - 2);
-    const int r0 = max(iv, 0);
-    const int r1 = min(iv + 1, nv - 1);
-    const float2 p0 = row_pair(img + static_cast<size_t>(r0) * nu, c);
-    const float2 p1 = row_pair(img + static_cast<size_t>(r1) * nu, c);
-    // columns (iu, iu + 1) inside the pair loaded at (c, c + 1)
-    const float l0 = iu == nu - 1 ? p0.y : p0.x, q0 = iu < 0 ? p0.x : p0.y;
-    const float l1 = iu == nu - 1 ? p1.y : p1.x, q1 = iu < 0 ? p1.x : p1.y;
-    return wt * fmaf(wl, l0, wr * q0) + wb * fmaf(wl, l1, wr * q1);
+    // iu == -1: pair (0, 1) holds column iu + 1 first; iu == nu - 1: pair
+    // (nu - 2, nu - 1) holds column iu second
+    const float ea = iu < 0 ? fu : (iu == nu - 1 ? 0.0f : 1.0f - fu);
+    const float eb = iu < 0 ? 0.0f : (iu == nu - 1 ? 1.0f - fu : fu);
+    if (ONES) return (ea + eb) * (wt + wb);
+    const unsigned c = static_cast<unsigned>(min(max(iu, 0), nu - 2));
+    const unsigned r0 = static_cast<unsigned>(min(max(iv, 0), nv - 1));
+    const unsigned r1 = static_cast<unsigned>(min(max(iv + 1, 0), nv - 1));
+    // 24-bit products (full-rate multiply; detector sides are below 2^24)
+    const float2 p0 = row_pair(img, __umul24(r0, static_cast<unsigned>(nu)) + c);
+    const float2 p1 = row_pair(img, __umul24(r1, static_cast<unsigned>(nu)) + c);
+    return wt * fmaf(ea, p0.x, eb * p0.y) + wb * fmaf(ea, p1.x, eb * p1.y);
 }
 
 // Contribution at FP64 detector position (u, v), or 0 outside (-1, nu) x (-1, nv).
@@ -141,16 +151,22 @@ __global__ __launch_bounds__(VB_THREADS) void vbp_kernel(
                 const int iu0 = static_cast<int>(fu0), iv0 = static_cast<int>(fv0);
                 const float ru = static_cast<float>(u0 - fu0), rv = static_cast<float>(v0 - fv0);
                 const float duf = static_cast<float>(du), dvf = static_cast<float>(dv);
+                // branch-free over the column: every voxel's loads are issued
+                // (at clamped, in-image addresses) before any is consumed, and
+                // voxels off the detector or past the volume are selected out
 #pragma unroll
                 for (int k = 0; k < KZ; ++k) {
-                    if (k >= kn) break;
                     const float uf = fmaf(static_cast<float>(k), duf, ru);
                     const float vf = fmaf(static_cast<float>(k), dvf, rv);
-                    const float flu = floorf(uf), flv = floorf(vf);
-                    const int iu = iu0 + static_cast<int>(flu), iv = iv0 + static_cast<int>(flv);
-                    if (static_cast<unsigned>(iu + 1) <= static_cast<unsigned>(nu) &&
-                        static_cast<unsigned>(iv + 1) <= static_cast<unsigned>(nv))
-                        acc[k] += bilinear<TS, ONES>(img, nu, nv, iu, iv, uf - flu, vf - flv);
+                    const int iu = iu0 + static_cast<int>(floorf(uf));
+                    const int iv = iv0 + static_cast<int>(floorf(vf));
+                    const bool in = k < kn &&
+                                    static_cast<unsigned>(iu + 1) <= static_cast<unsigned>(nu) &&
+                                    static_cast<unsigned>(iv + 1) <= static_cast<unsigned>(nv);
+                    const float val = bilinear<TS, ONES>(img, nu, nv, iu, iv,
+                                                         __builtin_amdgcn_fractf(uf),
+                                                         __builtin_amdgcn_fractf(vf));
+                    acc[k] += in ? val : 0.0f;
                 }
             } else {
 #pragma unroll
@@ -203,7 +219,9 @@ hipError_t launch_typed(const RayGrid &g, const double *Pm, const void *sino, fl
 hipError_t launch_back_voxel(const RayGrid &g, const double *Pm, const void *sino, int sino_dtype,
                              float *vol, int accumulate, int ones, hipStream_t s) {
     if (g.n_views <= 0) return hipSuccess;
-    if (g.n_u < 2 || g.n_v < 2) return hipErrorInvalidValue;
+    if (g.n_u < 2 || g.n_v < 2 || g.n_u >= (1 << 24) || g.n_v >= (1 << 24) ||
+        static_cast<long long>(g.n_u) * g.n_v >= (1ll << 30))
+        return hipErrorInvalidValue;
     if (ones) return launch_typed<float>(g, Pm, nullptr, vol, accumulate, 1, s);
     switch (sino_dtype) {
     case F32: return launch_typed<float>(g, Pm, sino, vol, accumulate, 0, s);
