@@ -70,6 +70,11 @@ def _load():
             lib.oracle_back_voxel.argtypes = [dp, i, i, i, i, i, i, i, dp, ip, i, dp]
             lib.oracle_back_voxel_points.argtypes = [dp, i, i, i, i, i, i, i, dp, ip, i, ip, i,
                                                      dp]
+            d = ctypes.c_double
+            lib.oracle_forward_cyl.argtypes = [dp, i, i, i, i, i, i, i, d, d, dp, d, dp, ip, i,
+                                               dp, ctypes.POINTER(ctypes.c_int64)]
+            lib.oracle_back_voxel_cyl.argtypes = [dp, i, i, i, i, i, i, i, d, d, dp, dp, ip, i,
+                                                  dp]
             lib.oracle_num_threads.restype = i
             _lib = lib
     return _lib
@@ -172,6 +177,71 @@ def back_voxel_points(P, shape, n_u, n_v, sino, ijk, views=None):
     if st != OK:
         raise OracleError(st)
     return out
+
+
+def _pose(pose):
+    if pose is None:
+        return None
+    pose = np.ascontiguousarray(pose, dtype=np.float64).reshape(3, 4)
+    return pose
+
+
+def forward_cyl(P, cyl, n_u, n_v, vol, step=0.5, views=None, pose=None, return_count=False):
+    """y = A_cyl x, float64 [n_views][n_v][n_u]: the projector on the aligned
+    cylindrical domain (Sec. 3.5, 4.2.1).  ``cyl`` = (n_r, n_phi, n_z, dr, dz);
+    ``vol`` [n_z][n_phi][n_r]; ``pose`` an optional rigid 3x4 [R | t] taking V-frame
+    points to the cylinder frame."""
+    P, n_proj, n_sub = _geom(P)
+    n_r, n_phi, n_z, dr, dz = cyl
+    vol = _f64(vol).reshape(n_z, n_phi, n_r)
+    v, nvw = _views(views, n_proj)
+    out = np.zeros((nvw, n_v, n_u))
+    cnt = ctypes.c_int64(0)
+    pz = _pose(pose)
+    st = _load().oracle_forward_cyl(
+        _dp(P), n_proj, n_sub, n_u, n_v, int(n_r), int(n_phi), int(n_z), float(dr), float(dz),
+        _dp(pz), float(step), _dp(vol),
+        v.ctypes.data_as(ctypes.POINTER(ctypes.c_int)) if v is not None else None, nvw,
+        _dp(out), ctypes.byref(cnt))
+    if st != OK:
+        raise OracleError(st)
+    return (out, int(cnt.value)) if return_count else out
+
+
+def back_voxel_cyl(P, cyl, n_u, n_v, sino, views=None, pose=None):
+    """z = B_cyl y, float64 [n_z][n_phi][n_r]: the voxel-driven backprojector
+    over the polar voxels (Sec. 4.3.1): each voxel centre, mapped back to the
+    V frame, is projected and the image sampled bilinearly."""
+    P, n_proj, n_sub = _geom(P)
+    n_r, n_phi, n_z, dr, dz = cyl
+    v, nvw = _views(views, n_proj)
+    sino = _f64(sino).reshape(nvw, n_v, n_u)
+    out = np.zeros((int(n_z), int(n_phi), int(n_r)))
+    pz = _pose(pose)
+    st = _load().oracle_back_voxel_cyl(
+        _dp(P), n_proj, n_sub, n_u, n_v, int(n_r), int(n_phi), int(n_z), float(dr), float(dz),
+        _dp(pz), _dp(sino),
+        v.ctypes.data_as(ctypes.POINTER(ctypes.c_int)) if v is not None else None, nvw, _dp(out))
+    if st != OK:
+        raise OracleError(st)
+    return out
+
+
+def sirt_cyl(P, cyl, n_u, n_v, b, n_iter, alpha=1.0, step=0.5, views=None, pose=None, x0=None):
+    """Eq. (1) on the cylindrical domain with the voxel-driven backprojector:
+    x <- x + alpha C B R (b - A x), R = 1 / (A 1), C = 1 / (B 1)."""
+    n_r, n_phi, n_z = int(cyl[0]), int(cyl[1]), int(cyl[2])
+    shape = (n_z, n_phi, n_r)
+    Rw = _safe_recip(forward_cyl(P, cyl, n_u, n_v, np.ones(shape), step, views, pose))
+    Cw = _safe_recip(back_voxel_cyl(P, cyl, n_u, n_v, np.ones_like(Rw), views, pose))
+    b = _f64(b).reshape(Rw.shape)
+    x = np.zeros(shape) if x0 is None else _f64(x0).reshape(shape).copy()
+    norms = []
+    for _ in range(n_iter):
+        res = b - forward_cyl(P, cyl, n_u, n_v, x, step, views, pose)
+        norms.append(float(np.sqrt(np.sum(res * res))))
+        x = x + alpha * Cw * back_voxel_cyl(P, cyl, n_u, n_v, Rw * res, views, pose)
+    return x, norms
 
 
 def forward_indicator(P, shape, n_u, n_v, Q, centre_idx, step=0.5):

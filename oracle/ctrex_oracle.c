@@ -506,3 +506,268 @@ int oracle_back_voxel_points(const double *P, int n_proj, int n_sub, int nu, int
                            ijk[3 * i + 1] - oy, ijk[3 * i + 2] - oz);
     return OR_OK;
 }
+
+/*
+ * Aligned cylindrical volume domain (Sec. 3.5 aligned cylindrical coordinates;
+ * the projector's geometry-level modification and the backprojector's
+ * counterpart, Sec. 4.2.1 / 4.3.1).
+ *
+ * The volume lives on a polar grid about the z axis of a cylinder frame.  A
+ * point X of the V frame (the frame the view matrices act on, centred voxel
+ * units) has cylinder-frame coordinates Xc = Rp X + tp for a rigid pose
+ * [Rp | tp] (identity when none is given), and there
+ *     r = sqrt(xc^2 + yc^2),  phi = atan2(yc, xc),  z = zc.
+ * Grid nodes: ring i at r_i = (i + 1/2) dr (i < n_r), angle j at
+ * phi_j = 2 pi j / n_phi (periodic), slice k at z_k = (k - (n_z - 1)/2) dz;
+ * the volume is stored [n_z][n_phi][n_r], r fastest.  Continuous indices
+ *     a = r / dr - 1/2 (clamped to [0, n_r - 1]: the core r < dr/2 takes the
+ *         innermost ring's values), b = phi n_phi / (2 pi) mod n_phi,
+ *     c = z / dz + (n_z - 1)/2,
+ * and the value is trilinear in (a, b, c) with b periodic.  Rays are those of
+ * the Cartesian projector (source S = -M^-1 P[:, 3], direction M^-1 (u, v, 1)
+ * normalised, in the V frame), clipped to the hull r <= (n_r - 1/2) dr,
+ * |z| <= (n_z - 1) dz / 2 in place of the box, and sampled at the midpoints of
+ * n = ceil(L / step) equal parts, each weighted h = L / n; sub-views averaged.
+ * The backprojector is the voxel-driven one of the Cartesian case with the
+ * voxel centres (r_i cos phi_j, r_i sin phi_j, z_k) mapped back to the V frame,
+ * X = Rp^T (Xc - tp).
+ */
+typedef struct {
+    int nr, nphi, nz;
+    double dr, dz;
+    double R[9], t[3];   /* V frame -> cylinder frame */
+} cyl_t;
+
+static int cyl_init(cyl_t *c, int nr, int nphi, int nz, double dr, double dz, const double *pose)
+{
+    if (nr < 2 || nphi < 3 || nz < 2 || !(dr > 0.0) || !(dz > 0.0))
+        return OR_EINVAL;
+    c->nr = nr;
+    c->nphi = nphi;
+    c->nz = nz;
+    c->dr = dr;
+    c->dz = dz;
+    for (int r = 0; r < 3; ++r) {
+        for (int k = 0; k < 3; ++k)
+            c->R[3 * r + k] = pose ? pose[4 * r + k] : (r == k ? 1.0 : 0.0);
+        c->t[r] = pose ? pose[4 * r + 3] : 0.0;
+    }
+    return OR_OK;
+}
+
+static void cyl_frame(const cyl_t *c, const double X[3], double Xc[3])
+{
+    for (int r = 0; r < 3; ++r)
+        Xc[r] = c->R[3 * r] * X[0] + c->R[3 * r + 1] * X[1] + c->R[3 * r + 2] * X[2] + c->t[r];
+}
+
+static double cyl_rh(const cyl_t *c) { return (c->nr - 0.5) * c->dr; }
+static double cyl_hz(const cyl_t *c) { return 0.5 * (c->nz - 1) * c->dz; }
+
+/* Trilinear value of the polar grid at cylinder-frame point Xc. */
+static double cyl_value(const cyl_t *c, const double *vol, const double Xc[3])
+{
+    const double two_pi = 6.283185307179586476925287;
+    double r = sqrt(Xc[0] * Xc[0] + Xc[1] * Xc[1]);
+    double a = r / c->dr - 0.5;
+    if (a < 0.0) a = 0.0;
+    if (a > c->nr - 1) a = c->nr - 1;
+    double b = atan2(Xc[1], Xc[0]) / two_pi * c->nphi;
+    if (b < 0.0) b += c->nphi;
+    double z = Xc[2] / c->dz + 0.5 * (c->nz - 1);
+    if (z < 0.0) z = 0.0;
+    if (z > c->nz - 1) z = c->nz - 1;
+    int a0 = (int)floor(a), k0 = (int)floor(z), j0 = (int)floor(b);
+    if (a0 > c->nr - 2) a0 = c->nr - 2;
+    if (k0 > c->nz - 2) k0 = c->nz - 2;
+    double fa = a - a0, fz = z - k0, fb = b - floor(b);
+    if (j0 >= c->nphi) j0 -= c->nphi;
+    int j1 = j0 + 1 == c->nphi ? 0 : j0 + 1;
+    double acc = 0.0;
+    for (int dk = 0; dk < 2; ++dk)
+        for (int dj = 0; dj < 2; ++dj)
+            for (int da = 0; da < 2; ++da) {
+                double w = (da ? fa : 1.0 - fa) * (dj ? fb : 1.0 - fb) * (dk ? fz : 1.0 - fz);
+                int j = dj ? j1 : j0;
+                acc += w * vol[((size_t)(k0 + dk) * c->nphi + j) * c->nr + a0 + da];
+            }
+    return acc;
+}
+
+/* Clip the line Sc + t dc (cylinder frame) to the hull; 0 if it misses. */
+static int cyl_clip(const cyl_t *c, const double Sc[3], const double dc[3], double *t0, double *t1)
+{
+    double lo = -INFINITY, hi = INFINITY;
+    double Rh = cyl_rh(c), Hz = cyl_hz(c);
+    double A = dc[0] * dc[0] + dc[1] * dc[1];
+    double B = Sc[0] * dc[0] + Sc[1] * dc[1];
+    double C = Sc[0] * Sc[0] + Sc[1] * Sc[1] - Rh * Rh;
+    if (A == 0.0) {
+        if (C > 0.0)
+            return 0;
+    } else {
+        double disc = B * B - A * C;
+        if (disc < 0.0)
+            return 0;
+        double sq = sqrt(disc);
+        lo = (-B - sq) / A;
+        hi = (-B + sq) / A;
+    }
+    if (dc[2] == 0.0) {
+        if (fabs(Sc[2]) > Hz)
+            return 0;
+    } else {
+        double za = (-Hz - Sc[2]) / dc[2], zb = (Hz - Sc[2]) / dc[2];
+        double zmin = za < zb ? za : zb, zmax = za < zb ? zb : za;
+        if (zmin > lo) lo = zmin;
+        if (zmax < hi) hi = zmax;
+    }
+    *t0 = lo;
+    *t1 = hi;
+    return hi > lo;
+}
+
+/* Source (V frame) and inverse 3x3 block of one view matrix. */
+static int view_source(const double *P, double S[3], double Mi[9])
+{
+    const double a = P[0], b = P[1], c = P[2];
+    const double d = P[4], e = P[5], f = P[6];
+    const double g = P[8], h = P[9], i = P[10];
+    double det = a * (e * i - f * h) - b * (d * i - f * g) + c * (d * h - e * g);
+    double fro = 0.0;
+    for (int k = 0; k < 12; ++k)
+        if (k % 4 != 3)
+            fro += P[k] * P[k];
+    fro = sqrt(fro);
+    if (!(fro > 0.0) || !(fabs(det) >= 1e-12 * fro * fro * fro))
+        return OR_ESINGULAR;
+    Mi[0] = (e * i - f * h) / det;
+    Mi[1] = (c * h - b * i) / det;
+    Mi[2] = (b * f - c * e) / det;
+    Mi[3] = (f * g - d * i) / det;
+    Mi[4] = (a * i - c * g) / det;
+    Mi[5] = (c * d - a * f) / det;
+    Mi[6] = (d * h - e * g) / det;
+    Mi[7] = (b * g - a * h) / det;
+    Mi[8] = (a * e - b * d) / det;
+    for (int r = 0; r < 3; ++r)
+        S[r] = -(Mi[3 * r] * P[3] + Mi[3 * r + 1] * P[7] + Mi[3 * r + 2] * P[11]);
+    return OR_OK;
+}
+
+int oracle_forward_cyl(const double *P, int n_proj, int n_sub, int nu, int nv, int nr, int nphi,
+                       int nz, double dr, double dz, const double *pose, double step,
+                       const double *vol, const int *views, int n_views, double *out,
+                       int64_t *count)
+{
+    cyl_t c;
+    if (!views)
+        n_views = n_proj;
+    if (n_proj < 1 || n_sub < 1 || nu < 1 || nv < 1 || !(step > 0.0) || n_views < 0)
+        return OR_EINVAL;
+    if (cyl_init(&c, nr, nphi, nz, dr, dz, pose) != OR_OK)
+        return OR_EINVAL;
+    for (int k = 0; k < n_views; ++k)
+        if (views && (views[k] < 0 || views[k] >= n_proj))
+            return OR_EINVAL;
+    /* set-up per sub-view, rejecting singular views and sources inside the hull */
+    const size_t m = (size_t)n_proj * n_sub;
+    double *Ss = malloc(sizeof(double) * 3 * m), *Ms = malloc(sizeof(double) * 9 * m);
+    if (!Ss || !Ms) {
+        free(Ss);
+        free(Ms);
+        return OR_EINVAL;
+    }
+    int st = OR_OK;
+    for (size_t q = 0; q < m && st == OR_OK; ++q) {
+        st = view_source(P + 12 * q, Ss + 3 * q, Ms + 9 * q);
+        if (st == OR_OK) {
+            double Sc[3];
+            cyl_frame(&c, Ss + 3 * q, Sc);
+            if (Sc[0] * Sc[0] + Sc[1] * Sc[1] <= cyl_rh(&c) * cyl_rh(&c) &&
+                fabs(Sc[2]) <= cyl_hz(&c))
+                st = OR_ESOURCE_INSIDE;
+        }
+    }
+    if (st != OR_OK) {
+        free(Ss);
+        free(Ms);
+        return st;
+    }
+    int64_t total = 0;
+#pragma omp parallel for collapse(2) schedule(dynamic, 4) reduction(+ : total)
+    for (int k = 0; k < n_views; ++k) {
+        for (int iv = 0; iv < nv; ++iv) {
+            int p = views ? views[k] : k;
+            for (int iu = 0; iu < nu; ++iu) {
+                double y = 0.0;
+                for (int s = 0; s < n_sub; ++s) {
+                    const size_t q = (size_t)p * n_sub + s;
+                    const double *Mi = Ms + 9 * q;
+                    double d[3], len = 0.0, Sc[3], dc[3], t0, t1;
+                    for (int r = 0; r < 3; ++r) {
+                        d[r] = Mi[3 * r] * iu + Mi[3 * r + 1] * iv + Mi[3 * r + 2];
+                        len += d[r] * d[r];
+                    }
+                    len = sqrt(len);
+                    for (int r = 0; r < 3; ++r)
+                        d[r] /= len;
+                    cyl_frame(&c, Ss + 3 * q, Sc);
+                    for (int r = 0; r < 3; ++r)
+                        dc[r] = c.R[3 * r] * d[0] + c.R[3 * r + 1] * d[1] + c.R[3 * r + 2] * d[2];
+                    if (!cyl_clip(&c, Sc, dc, &t0, &t1))
+                        continue;
+                    double L = t1 - t0;
+                    int n = (int)ceil(L / step);
+                    if (n < 1)
+                        n = 1;
+                    double h = L / n, acc = 0.0;
+                    for (int i = 0; i < n; ++i) {
+                        double tt = t0 + (i + 0.5) * h, X[3];
+                        for (int r = 0; r < 3; ++r)
+                            X[r] = Sc[r] + tt * dc[r];
+                        acc += cyl_value(&c, vol, X);
+                    }
+                    y += h * acc;
+                    total += n;
+                }
+                out[((size_t)k * nv + iv) * nu + iu] = y / n_sub;
+            }
+        }
+    }
+    free(Ss);
+    free(Ms);
+    if (count)
+        *count = total;
+    return OR_OK;
+}
+
+int oracle_back_voxel_cyl(const double *P, int n_proj, int n_sub, int nu, int nv, int nr,
+                          int nphi, int nz, double dr, double dz, const double *pose,
+                          const double *sino, const int *views, int n_views, double *vol)
+{
+    cyl_t c;
+    const double two_pi = 6.283185307179586476925287;
+    if (!views)
+        n_views = n_proj;
+    if (cyl_init(&c, nr, nphi, nz, dr, dz, pose) != OR_OK)
+        return OR_EINVAL;
+    int st = check_voxel_args(n_proj, n_sub, nu, nv, nr, nphi, nz, views, n_views);
+    if (st != OR_OK)
+        return st;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < nphi; ++j)
+            for (int i = 0; i < nr; ++i) {
+                double r = (i + 0.5) * dr, phi = two_pi * j / nphi;
+                double Xc[3] = {r * cos(phi), r * sin(phi), (k - 0.5 * (nz - 1)) * dz};
+                double X[3];
+                /* X = Rp^T (Xc - tp) */
+                for (int q = 0; q < 3; ++q)
+                    X[q] = c.R[q] * (Xc[0] - c.t[0]) + c.R[3 + q] * (Xc[1] - c.t[1]) +
+                           c.R[6 + q] * (Xc[2] - c.t[2]);
+                vol[((size_t)k * nphi + j) * nr + i] +=
+                    voxel_sum(P, n_sub, nu, nv, sino, views, n_views, X[0], X[1], X[2]);
+            }
+    return OR_OK;
+}
