@@ -261,6 +261,69 @@ CTREX_API int ctrex_tv(ctrex_ctx *ctx, const float *x, int32_t nx, int32_t ny, i
 CTREX_API int ctrex_profile_enable(ctrex_ctx *ctx, int32_t enable);
 CTREX_API int ctrex_profile_read(ctrex_ctx *ctx, double *ms, int64_t *launches);
 
+/*
+ * Aligned cylindrical volume domain (Sec. 3.5; the projector's and the
+ * backprojector's geometry-level modifications, Sec. 4.2.1 and 4.3.1).
+ *
+ * The volume is a polar grid about the z axis of a cylinder frame, stored
+ * [n_z][n_phi][n_r] float (r fastest): ring i at radius (i + 1/2) dr, angle
+ * j at 2 pi j / n_phi (periodic), slice k at (k - (n_z - 1)/2) dz.  `pose`
+ * (host float64 [3][4] = [R | t], or NULL for the identity) is the rigid map
+ * X_c = R X + t from the V frame of the view matrices to the cylinder frame;
+ * R must be a rotation (|R^T R - I| <= 1e-9, det +1) or CTREX_EINVAL.
+ * The projector clips each ray of ctrex_forward_project to the hull
+ * r <= (n_r - 1/2) dr, |z| <= (n_z - 1) dz / 2 (not the box), samples it at
+ * the midpoints of n = ceil(L / step) equal parts (weight L / n each) and
+ * looks up the grid trilinearly in (r / dr - 1/2, phi n_phi / (2 pi),
+ * z / dz + (n_z - 1)/2), the radial index clamped to [0, n_r - 1] (the core
+ * r < dr/2 takes the innermost ring's values) and the angle periodic; sub-views
+ * are averaged.  The backprojector is the voxel-driven one of
+ * ctrex_back_project_voxel over the polar voxel centres.  ctrex_set_cylinder
+ * needs a geometry (its view matrices and step; the box sides of
+ * ctrex_set_geometry play no part here), computes every sub-view's source and
+ * ray map in the cylinder frame, and rejects sources inside the cylinder
+ * (CTREX_ESOURCE_INSIDE); n_r >= 2, n_phi >= 3, n_z >= 2, fewer than 2^31
+ * voxels (CTREX_ESHAPE); dr, dz > 0.  ctrex_set_geometry removes the
+ * cylinder.  The cylinder calls return CTREX_ESTATE without a cylinder or
+ * with a motion field set (no warp on this domain).
+ */
+CTREX_API int ctrex_set_cylinder(ctrex_ctx *ctx, int32_t n_r, int32_t n_phi, int32_t n_z,
+                                 double dr, double dz, const double *pose);
+
+/* sino = A_cyl vol over the listed projections (arguments as in
+ * ctrex_forward_project; `vol` is the polar grid). */
+CTREX_API int ctrex_forward_project_cyl(ctrex_ctx *ctx, const void *vol, int32_t vol_dtype,
+                                        void *sino, int32_t sino_dtype, const int32_t *views,
+                                        int32_t n_views, void *stream);
+
+/* vol (+)= B_cyl sino: the voxel-driven backprojector over the polar voxel
+ * centres (mapped to the V frame; arguments, determinism and detector limits
+ * as in ctrex_back_project_voxel). */
+CTREX_API int ctrex_back_project_cyl(ctrex_ctx *ctx, const void *sino, int32_t sino_dtype,
+                                     float *vol, int32_t accumulate, const int32_t *views,
+                                     int32_t n_views, void *stream);
+
+/* Exact number of samples of one cylindrical forward projection; synchronous. */
+CTREX_API int ctrex_sample_count_cyl(ctrex_ctx *ctx, const int32_t *views, int32_t n_views,
+                                     int64_t *count, void *stream);
+
+/* Workspace bytes of ctrex_sirt_iterate_cyl for n_views projections (<= 0: all). */
+CTREX_API int ctrex_sirt_workspace_bytes_cyl(const ctrex_ctx *ctx, int32_t n_views,
+                                             size_t *bytes);
+
+/*
+ * Eq. (1) on the cylindrical domain: vol <- vol + alpha C B R (sino - A vol)
+ * with A, B the cylinder operators above, R = 1 / (A 1), C = 1 / (B 1).
+ * Arguments, the workspace and its weight cache, and the residual norms as in
+ * ctrex_sirt_iterate; flags CTREX_NONNEG and CTREX_RECOMPUTE_WEIGHTS only
+ * (the volume is FP32; no voxel weights).
+ */
+CTREX_API int ctrex_sirt_iterate_cyl(ctrex_ctx *ctx, float *vol, const void *sino,
+                                     int32_t sino_dtype, int32_t n_iter, float alpha,
+                                     uint32_t flags, const int32_t *views, int32_t n_views,
+                                     void *workspace, size_t workspace_bytes,
+                                     double *resid_norms, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

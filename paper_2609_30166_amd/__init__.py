@@ -6,6 +6,8 @@ Public Python API (argument marshalling over the C ABI in include/ctrex.h):
   ``forward`` (A), ``back`` (A^T), ``sirt`` (Eq. 1), ``os_sirt`` (ordered
   subsets, Sec. 2.3.2), ``residual_norm``, ``sample_count``.
 * ``ordered_subsets`` — interleaved / contiguous / random projection subsets.
+* ``CylinderGeometry`` — the aligned cylindrical domain (polar grid, rigid
+  pose; Sec. 3.5, 4.2.1, 4.3.1): ``forward``, voxel-driven ``back``, ``sirt``.
 * ``project`` — differentiable forward projection (autograd).
 * ``total_variation``, ``reconstruction_loss`` — ||Ax - b||^2 + lambda TV(x).
 * ``unet.UNet``, ``learned.LearnedSirt`` — the learned correction between
@@ -16,7 +18,9 @@ from .projector import (  # noqa: F401
     Geometry, ForwardProject, project, TotalVariation, total_variation, reconstruction_loss,
     ordered_subsets,
 )
+from .cylinder import CylinderGeometry  # noqa: F401
 from ._lib import CtrexError, library_path  # noqa: F401
 
 __all__ = ["Geometry", "ForwardProject", "project", "TotalVariation", "total_variation",
-           "reconstruction_loss", "ordered_subsets", "CtrexError", "library_path"]
+           "reconstruction_loss", "ordered_subsets", "CylinderGeometry", "CtrexError",
+           "library_path"]

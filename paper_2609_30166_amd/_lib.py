@@ -59,6 +59,17 @@ def lib():
             "ctrex_forward_project": (ctypes.c_int, [vp, vp, i32, vp, i32, ip, i32, vp]),
             "ctrex_back_project": (ctypes.c_int, [vp, vp, i32, vp, i32, ip, i32, vp]),
             "ctrex_back_project_voxel": (ctypes.c_int, [vp, vp, i32, vp, i32, ip, i32, vp]),
+            "ctrex_set_cylinder": (ctypes.c_int, [vp, i32, i32, i32, ctypes.c_double,
+                                                  ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+            "ctrex_forward_project_cyl": (ctypes.c_int, [vp, vp, i32, vp, i32, ip, i32, vp]),
+            "ctrex_back_project_cyl": (ctypes.c_int, [vp, vp, i32, vp, i32, ip, i32, vp]),
+            "ctrex_sample_count_cyl": (ctypes.c_int, [vp, ip, i32, ctypes.POINTER(ctypes.c_int64),
+                                                      vp]),
+            "ctrex_sirt_workspace_bytes_cyl": (ctypes.c_int, [vp, i32,
+                                                              ctypes.POINTER(ctypes.c_size_t)]),
+            "ctrex_sirt_iterate_cyl": (ctypes.c_int, [vp, vp, vp, i32, i32, ctypes.c_float,
+                                                      ctypes.c_uint32, ip, i32, vp, ctypes.c_size_t,
+                                                      ctypes.POINTER(ctypes.c_double), vp]),
             "ctrex_sirt_workspace_bytes": (ctypes.c_int, [vp, i32, u32,
                                                           ctypes.POINTER(ctypes.c_size_t)]),
             "ctrex_sirt_iterate": (ctypes.c_int, [vp, vp, vp, i32, i32, ctypes.c_float, u32, ip,

@@ -279,6 +279,8 @@ void ctrex_destroy(ctrex_ctx *c) {
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->d_tab) (void)hipFree(c->d_tab);
     if (c->d_P) (void)hipFree(c->d_P);
+    if (c->d_tab_cyl) (void)hipFree(c->d_tab_cyl);
+    if (c->d_P_cyl) (void)hipFree(c->d_P_cyl);
     if (c->d_U) (void)hipFree(c->d_U);
     if (c->d_count) (void)hipFree(c->d_count);
     if (c->d_scalar) (void)hipFree(c->d_scalar);
@@ -371,6 +373,8 @@ int ctrex_set_geometry(ctrex_ctx *c, const double *P, int32_t n_proj, int32_t n_
         c->d_U = nullptr;
     }
     c->tab = std::move(tab);
+    c->P_host.assign(P, P + 12 * m);
+    c->have_cyl = false;   // its tables derive from the view matrices
     c->n_proj = n_proj;
     c->n_sub = n_sub;
     c->n_u = n_u;
@@ -563,7 +567,7 @@ int ctrex_back_project_voxel(ctrex_ctx *c, const void *sino, int32_t sino_dtype,
         return CTREX_OK;
     }
     CTREX_HIP(c, launch_back_voxel(make_grid(c, dv, nv), c->d_P, sino, sino_dtype, vol,
-                                   accumulate ? 1 : 0, 0, s));
+                                   accumulate ? 1 : 0, 0, VoxelGrid{}, s));
     return CTREX_OK;
 }
 
@@ -628,7 +632,7 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
     // R and C for this geometry / motion / subset / workspace, kept between calls.
     auto same_key = [&](const ctrex_ctx::WeightKey &e) {
         return e.ws == workspace && e.gen == c->generation && e.all == (views == nullptr) &&
-               e.voxel_bp == vbp &&
+               e.kind == (vbp ? 1 : 0) &&
                (views == nullptr ||
                 (static_cast<int32_t>(e.views.size()) == nv &&
                  std::memcmp(e.views.data(), views, sizeof(int32_t) * nv) == 0));
@@ -646,12 +650,12 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
         FpExtra none{nullptr, nullptr, nullptr};
         CTREX_HIP(c, launch_forward(g, w, nullptr, F32, Rw, F32, FP_RECIP_ONES, none, s));
         if (vbp)
-            CTREX_HIP(c, launch_back_voxel(g, c->d_P, nullptr, F32, Cw, 0, 1, s));
+            CTREX_HIP(c, launch_back_voxel(g, c->d_P, nullptr, F32, Cw, 0, 1, VoxelGrid{}, s));
         else
             CTREX_HIP(c, launch_back(g, w, c->d_P, nullptr, F32, Cw, 0, BP_ONES, c->d_scalar, part,
                                      s));
         CTREX_HIP(c, launch_recip(Cw, vox, s));
-        ctrex_ctx::WeightKey k{workspace, c->generation, views == nullptr, vbp, {}};
+        ctrex_ctx::WeightKey k{workspace, c->generation, views == nullptr, vbp ? 1 : 0, {}};
         if (views) k.views.assign(views, views + nv);
         c->w_cache.insert(c->w_cache.begin(), std::move(k));
         if (c->w_cache.size() > kMaxWeightSets) c->w_cache.pop_back();
@@ -677,7 +681,7 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
         CTREX_HIP(c, launch_sum_partials(partials, g.total_blocks, resid + (k % kResidCap), s));
         CTREX_HIP(c, t_bp.begin());
         if (vbp)
-            CTREX_HIP(c, launch_back_voxel(g, c->d_P, r, rdt, z, 0, 0, s));
+            CTREX_HIP(c, launch_back_voxel(g, c->d_P, r, rdt, z, 0, 0, VoxelGrid{}, s));
         else
             CTREX_HIP(c, launch_back(g, w, c->d_P, r, rdt, z, 0, BP_PLAIN, c->d_scalar, part, s));
         CTREX_HIP(c, t_bp.end());
@@ -792,6 +796,337 @@ int ctrex_convert(ctrex_ctx *c, const void *src, int32_t src_dtype, void *dst, i
     CTREX_HIP(c, hipSetDevice(c->device));
     CTREX_HIP(c, launch_convert(src, src_dtype, dst, dst_dtype, static_cast<size_t>(n),
                                 static_cast<hipStream_t>(stream)));
+    return CTREX_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ aligned cylindrical domain --
+
+namespace {
+
+int check_cyl_ready(ctrex_ctx *c) {
+    int st = check_ready(c);
+    if (st != CTREX_OK) return st;
+    if (!c->have_cyl)
+        return fail(c, CTREX_ESTATE, "no cylindrical domain set (call ctrex_set_cylinder)");
+    if (c->d_U) return fail(c, CTREX_ESTATE, "the cylindrical domain has no motion warp");
+    return CTREX_OK;
+}
+
+RayGrid make_grid_cyl(const ctrex_ctx *c, const int32_t *dev_views, int32_t n_views) {
+    RayGrid g = make_grid(c, dev_views, n_views);
+    g.tab = c->d_tab_cyl;
+    g.nx = c->cyl_nr;
+    g.ny = c->cyl_nphi;
+    g.nz = c->cyl_nz;
+    return g;
+}
+
+CylGrid cyl_of(const ctrex_ctx *c) {
+    return make_cyl_grid(c->cyl_nr, c->cyl_nphi, c->cyl_nz, c->cyl_dr, c->cyl_dz);
+}
+
+VoxelGrid cyl_voxels(const ctrex_ctx *c) {
+    VoxelGrid v;
+    v.cyl = 1;
+    v.dr = c->cyl_dr;
+    v.dz = c->cyl_dz;
+    return v;
+}
+
+struct CylLayout {
+    size_t R, r, C, z, partials, resid, total;
+};
+
+CylLayout cyl_layout(const ctrex_ctx *c, int32_t n_views) {
+    const size_t rays = static_cast<size_t>(n_views) * c->n_u * c->n_v;
+    const size_t vox = static_cast<size_t>(c->cyl_nr) * c->cyl_nphi * c->cyl_nz;
+    const size_t tiles = static_cast<size_t>((c->n_u + TILE_U - 1) / TILE_U) *
+                         ((c->n_v + TILE_V - 1) / TILE_V) * n_views;
+    CylLayout l;
+    size_t off = 0;
+    l.R = off;
+    off = align_up(off + 4 * rays);
+    l.r = off;
+    off = align_up(off + 4 * rays);
+    l.C = off;
+    off = align_up(off + 4 * vox);
+    l.z = off;
+    off = align_up(off + 4 * vox);
+    l.partials = off;
+    off = align_up(off + 8 * tiles);
+    l.resid = off;
+    off = align_up(off + 8 * kResidCap);
+    l.total = off;
+    return l;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ctrex_set_cylinder(ctrex_ctx *c, int32_t n_r, int32_t n_phi, int32_t n_z, double dr,
+                       double dz, const double *pose) {
+    int st = check_ready(c);
+    if (st != CTREX_OK) return st;
+    if (n_r < 2 || n_phi < 3 || n_z < 2)
+        return fail(c, CTREX_ESHAPE, "need n_r >= 2, n_phi >= 3, n_z >= 2");
+    if (static_cast<long long>(n_r) * n_phi * n_z >= (1ll << 31))
+        return fail(c, CTREX_ESHAPE, "cylindrical volume exceeds 2^31 - 1 voxels");
+    if (!(dr > 0.0) || !(dz > 0.0) || !std::isfinite(dr) || !std::isfinite(dz))
+        return fail(c, CTREX_EINVAL, "dr and dz must be finite and > 0");
+    double R[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}}, t[3] = {0, 0, 0};
+    if (pose) {
+        for (int i = 0; i < 12; ++i)
+            if (!std::isfinite(pose[i])) return fail(c, CTREX_EINVAL, "pose is not finite");
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j) R[i][j] = pose[4 * i + j];
+            t[i] = pose[4 * i + 3];
+        }
+        // a rotation: R^T R = I and det R = +1
+        double err = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double d = -(i == j ? 1.0 : 0.0);
+                for (int k = 0; k < 3; ++k) d += R[k][i] * R[k][j];
+                err = std::max(err, std::fabs(d));
+            }
+        double inv[3][3];
+        if (err > 1e-9 || invert3(R, inv) < 0.0)
+            return fail(c, CTREX_EINVAL, "pose is not a rotation plus translation");
+    }
+    const double rh = (n_r - 0.5) * dr, hz = 0.5 * (n_z - 1) * dz;
+    if (std::sqrt(4.0 * rh * rh + 4.0 * hz * hz) / c->step >= double(1 << 24))
+        return fail(c, CTREX_EINVAL, "step %g too small for the cylinder", c->step);
+    const size_t m = static_cast<size_t>(c->n_proj) * c->n_sub;
+    std::vector<SubView> tab(m);
+    std::vector<double> Pc(12 * m);
+    for (size_t k = 0; k < m; ++k) {
+        const double *p = c->P_host.data() + 12 * k;
+        double M[3][3], Mi[3][3], S[3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) M[i][j] = p[4 * i + j];
+        (void)invert3(M, Mi);   // ctrex_set_geometry checked it is regular
+        for (int i = 0; i < 3; ++i) S[i] = -(Mi[i][0] * p[3] + Mi[i][1] * p[7] + Mi[i][2] * p[11]);
+        SubView &sv = tab[k];
+        for (int i = 0; i < 3; ++i) {
+            sv.S[i] = R[i][0] * S[0] + R[i][1] * S[1] + R[i][2] * S[2] + t[i];
+            for (int j = 0; j < 3; ++j)
+                sv.Mi[3 * i + j] = R[i][0] * Mi[0][j] + R[i][1] * Mi[1][j] + R[i][2] * Mi[2][j];
+        }
+        sv.tau = 0.0;
+        sv.pad[0] = sv.pad[1] = sv.pad[2] = 0.0;
+        if (sv.S[0] * sv.S[0] + sv.S[1] * sv.S[1] <= rh * rh && std::fabs(sv.S[2]) <= hz)
+            return fail(c, CTREX_ESOURCE_INSIDE,
+                        "source of view matrix %zu lies inside the cylinder", k);
+        // P T^-1 with T^-1 = [R^T, -R^T t]: maps cylinder-frame points like P maps V-frame ones
+        double *q = Pc.data() + 12 * k;
+        for (int i = 0; i < 3; ++i) {
+            double lin = p[4 * i + 3];
+            for (int j = 0; j < 3; ++j) {
+                double a = 0.0;
+                for (int l = 0; l < 3; ++l) a += p[4 * i + l] * R[j][l];
+                q[4 * i + j] = a;
+                lin -= a * t[j];
+            }
+            q[4 * i + 3] = lin;
+        }
+    }
+    CTREX_HIP(c, hipDeviceSynchronize());
+    if (c->cyl_cap < m) {
+        if (c->d_tab_cyl) CTREX_HIP(c, hipFree(c->d_tab_cyl));
+        if (c->d_P_cyl) CTREX_HIP(c, hipFree(c->d_P_cyl));
+        c->d_tab_cyl = nullptr;
+        c->d_P_cyl = nullptr;
+        c->cyl_cap = 0;
+        CTREX_HIP(c, hipMalloc(&c->d_tab_cyl, sizeof(SubView) * m));
+        CTREX_HIP(c, hipMalloc(&c->d_P_cyl, sizeof(double) * 12 * m));
+        c->cyl_cap = m;
+    }
+    CTREX_HIP(c, hipMemcpy(c->d_tab_cyl, tab.data(), sizeof(SubView) * m, hipMemcpyHostToDevice));
+    CTREX_HIP(c, hipMemcpy(c->d_P_cyl, Pc.data(), sizeof(double) * 12 * m, hipMemcpyHostToDevice));
+    c->cyl_nr = n_r;
+    c->cyl_nphi = n_phi;
+    c->cyl_nz = n_z;
+    c->cyl_dr = dr;
+    c->cyl_dz = dz;
+    c->have_cyl = true;
+    c->generation++;
+    c->w_cache.clear();
+    return CTREX_OK;
+}
+
+int ctrex_forward_project_cyl(ctrex_ctx *c, const void *vol, int32_t vol_dtype, void *sino,
+                              int32_t sino_dtype, const int32_t *views, int32_t n_views,
+                              void *stream) {
+    int st = check_cyl_ready(c);
+    if (st != CTREX_OK) return st;
+    if (!valid_dtype(vol_dtype) || !valid_dtype(sino_dtype))
+        return fail(c, CTREX_EINVAL, "unknown dtype (%d, %d)", vol_dtype, sino_dtype);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t *dv;
+    int32_t nv;
+    if ((st = resolve_views(c, views, n_views, &dv, &nv, s)) != CTREX_OK) return st;
+    if (nv == 0) return CTREX_OK;
+    if (!vol || !sino) return fail(c, CTREX_EINVAL, "vol and sino must be device pointers");
+    if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
+    FpExtra ex{nullptr, nullptr, nullptr};
+    CTREX_HIP(c, launch_forward_cyl(make_grid_cyl(c, dv, nv), cyl_of(c), vol, vol_dtype, sino,
+                                    sino_dtype, FP_PLAIN, ex, s));
+    return CTREX_OK;
+}
+
+int ctrex_back_project_cyl(ctrex_ctx *c, const void *sino, int32_t sino_dtype, float *vol,
+                           int32_t accumulate, const int32_t *views, int32_t n_views,
+                           void *stream) {
+    int st = check_cyl_ready(c);
+    if (st != CTREX_OK) return st;
+    if (!vol) return fail(c, CTREX_EINVAL, "vol must be a device pointer");
+    if (!valid_dtype(sino_dtype)) return fail(c, CTREX_EINVAL, "unknown dtype %d", sino_dtype);
+    if (!voxel_bp_detector_ok(c))
+        return fail(c, CTREX_ESHAPE, "the voxel-driven backprojector needs 2 <= n_u, n_v < 2^24 "
+                                     "and n_u n_v < 2^30");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t *dv;
+    int32_t nv;
+    if ((st = resolve_views(c, views, n_views, &dv, &nv, s)) != CTREX_OK) return st;
+    if (nv > 0 && !sino) return fail(c, CTREX_EINVAL, "sino must be a device pointer");
+    if (nv == 0) {
+        if (!accumulate)
+            CTREX_HIP(c, launch_fill_zero(vol, sizeof(float) * static_cast<size_t>(c->cyl_nr) *
+                                                   c->cyl_nphi * c->cyl_nz, s));
+        return CTREX_OK;
+    }
+    CTREX_HIP(c, launch_back_voxel(make_grid_cyl(c, dv, nv), c->d_P_cyl, sino, sino_dtype, vol,
+                                   accumulate ? 1 : 0, 0, cyl_voxels(c), s));
+    return CTREX_OK;
+}
+
+int ctrex_sample_count_cyl(ctrex_ctx *c, const int32_t *views, int32_t n_views, int64_t *count,
+                           void *stream) {
+    int st = check_cyl_ready(c);
+    if (st != CTREX_OK) return st;
+    if (!count) return fail(c, CTREX_EINVAL, "count is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t *dv;
+    int32_t nv;
+    if ((st = resolve_views(c, views, n_views, &dv, &nv, s)) != CTREX_OK) return st;
+    if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
+    CTREX_HIP(c, launch_fill_zero(c->d_count, sizeof(unsigned long long), s));
+    CTREX_HIP(c, launch_sample_count_cyl(make_grid_cyl(c, dv, nv), cyl_of(c), c->d_count, s));
+    unsigned long long h = 0;
+    CTREX_HIP(c, hipMemcpyAsync(&h, c->d_count, sizeof h, hipMemcpyDeviceToHost, s));
+    CTREX_HIP(c, hipStreamSynchronize(s));
+    *count = static_cast<int64_t>(h);
+    return CTREX_OK;
+}
+
+int ctrex_sirt_workspace_bytes_cyl(const ctrex_ctx *c, int32_t n_views, size_t *bytes) {
+    if (!c || !bytes) return CTREX_EINVAL;
+    if (!c->have_geom || !c->have_cyl) return CTREX_ESTATE;
+    if (n_views <= 0) n_views = c->n_proj;
+    *bytes = cyl_layout(c, n_views).total;
+    return CTREX_OK;
+}
+
+int ctrex_sirt_iterate_cyl(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_dtype,
+                           int32_t n_iter, float alpha, uint32_t flags, const int32_t *views,
+                           int32_t n_views, void *workspace, size_t workspace_bytes,
+                           double *resid_norms, void *stream) {
+    int st = check_cyl_ready(c);
+    if (st != CTREX_OK) return st;
+    if (!vol || !sino) return fail(c, CTREX_EINVAL, "vol and sino must be device pointers");
+    if (!valid_dtype(sino_dtype)) return fail(c, CTREX_EINVAL, "unknown dtype %d", sino_dtype);
+    if (n_iter < 0) return fail(c, CTREX_EINVAL, "n_iter must be >= 0");
+    if (!std::isfinite(alpha)) return fail(c, CTREX_EINVAL, "alpha must be finite");
+    const uint32_t known = CTREX_NONNEG | CTREX_RECOMPUTE_WEIGHTS;
+    if (flags & ~known) return fail(c, CTREX_EINVAL, "unsupported flags 0x%x", flags & ~known);
+    if (!voxel_bp_detector_ok(c))
+        return fail(c, CTREX_ESHAPE, "the voxel-driven backprojector needs 2 <= n_u, n_v < 2^24 "
+                                     "and n_u n_v < 2^30");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t *dv;
+    int32_t nv;
+    if ((st = resolve_views(c, views, n_views, &dv, &nv, s)) != CTREX_OK) return st;
+    if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
+    if (nv == 0) return fail(c, CTREX_ESHAPE, "empty view subset");
+    const CylLayout L = cyl_layout(c, nv);
+    if (!workspace) return fail(c, CTREX_EWORKSPACE, "workspace is NULL");
+    if (workspace_bytes < L.total)
+        return fail(c, CTREX_EWORKSPACE, "workspace of %zu bytes < %zu needed", workspace_bytes,
+                    L.total);
+    if (n_iter == 0) return CTREX_OK;
+    char *ws = static_cast<char *>(workspace);
+    float *Rw = reinterpret_cast<float *>(ws + L.R);
+    void *r = ws + L.r;
+    float *Cw = reinterpret_cast<float *>(ws + L.C);
+    float *z = reinterpret_cast<float *>(ws + L.z);
+    double *partials = reinterpret_cast<double *>(ws + L.partials);
+    double *resid = reinterpret_cast<double *>(ws + L.resid);
+    const size_t vox = static_cast<size_t>(c->cyl_nr) * c->cyl_nphi * c->cyl_nz;
+    const RayGrid g = make_grid_cyl(c, dv, nv);
+    const CylGrid cg = cyl_of(c);
+    const VoxelGrid vg = cyl_voxels(c);
+    auto same_key = [&](const ctrex_ctx::WeightKey &e) {
+        return e.ws == workspace && e.gen == c->generation && e.all == (views == nullptr) &&
+               e.kind == 2 &&
+               (views == nullptr ||
+                (static_cast<int32_t>(e.views.size()) == nv &&
+                 std::memcmp(e.views.data(), views, sizeof(int32_t) * nv) == 0));
+    };
+    auto hit = std::find_if(c->w_cache.begin(), c->w_cache.end(), same_key);
+    const bool cached = hit != c->w_cache.end() && !(flags & CTREX_RECOMPUTE_WEIGHTS);
+    if (!cached) {
+        c->w_cache.erase(std::remove_if(c->w_cache.begin(), c->w_cache.end(),
+                                        [&](const ctrex_ctx::WeightKey &e) {
+                                            return e.ws == workspace;
+                                        }),
+                         c->w_cache.end());
+        FpExtra none{nullptr, nullptr, nullptr};
+        CTREX_HIP(c, launch_forward_cyl(g, cg, nullptr, F32, Rw, F32, FP_RECIP_ONES, none, s));
+        CTREX_HIP(c, launch_back_voxel(g, c->d_P_cyl, nullptr, F32, Cw, 0, 1, vg, s));
+        CTREX_HIP(c, launch_recip(Cw, vox, s));
+        ctrex_ctx::WeightKey k{workspace, c->generation, views == nullptr, 2, {}};
+        if (views) k.views.assign(views, views + nv);
+        c->w_cache.insert(c->w_cache.begin(), std::move(k));
+        if (c->w_cache.size() > kMaxWeightSets) c->w_cache.pop_back();
+    } else if (hit != c->w_cache.begin()) {
+        std::rotate(c->w_cache.begin(), hit, hit + 1);
+    }
+    std::vector<double> host_norms;
+    if (resid_norms) host_norms.reserve(n_iter);
+    FpExtra ex{sino, Rw, partials};
+    for (int32_t k = 0; k < n_iter; ++k) {
+        PhaseTimer t_fp{c, s, nullptr, 0}, t_bp{c, s, nullptr, 1}, t_up{c, s, nullptr, 2};
+        CTREX_HIP(c, t_fp.begin());
+        CTREX_HIP(c, launch_forward_cyl(g, cg, vol, F32, r, sino_dtype, FP_CORRECT, ex, s));
+        CTREX_HIP(c, t_fp.end());
+        CTREX_HIP(c, launch_sum_partials(partials, g.total_blocks, resid + (k % kResidCap), s));
+        CTREX_HIP(c, t_bp.begin());
+        CTREX_HIP(c, launch_back_voxel(g, c->d_P_cyl, r, sino_dtype, z, 0, 0, vg, s));
+        CTREX_HIP(c, t_bp.end());
+        CTREX_HIP(c, t_up.begin());
+        CTREX_HIP(c, launch_update(vol, z, Cw, nullptr, alpha, (flags & CTREX_NONNEG) ? 1 : 0,
+                                   nullptr, F32, vox, s));
+        CTREX_HIP(c, t_up.end());
+        if (resid_norms && ((k + 1) % kResidCap == 0 || k + 1 == n_iter)) {
+            const int cnt = (k % kResidCap) + 1;
+            std::vector<double> tmp(cnt);
+            CTREX_HIP(c, hipMemcpyAsync(tmp.data(), resid, sizeof(double) * cnt,
+                                        hipMemcpyDeviceToHost, s));
+            CTREX_HIP(c, hipStreamSynchronize(s));
+            host_norms.insert(host_norms.end(), tmp.begin(), tmp.end());
+        }
+    }
+    if (resid_norms) {
+        bool finite = true;
+        for (int32_t k = 0; k < n_iter; ++k) {
+            resid_norms[k] = std::sqrt(host_norms[k]);
+            finite = finite && std::isfinite(resid_norms[k]);
+        }
+        if (!finite) return fail(c, CTREX_ENONFINITE, "a residual norm is not finite");
+    }
     return CTREX_OK;
 }
 

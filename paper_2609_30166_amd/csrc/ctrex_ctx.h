@@ -30,6 +30,14 @@ struct ctrex_ctx {
     ctrex::SubView *d_tab = nullptr;
     double *d_P = nullptr;    // view matrices [n_proj * n_sub][12]
     size_t P_cap = 0;
+    std::vector<double> P_host;  // the same, as set
+    // aligned cylindrical domain (ctrex_set_cylinder)
+    bool have_cyl = false;
+    int cyl_nr = 0, cyl_nphi = 0, cyl_nz = 0;
+    double cyl_dr = 0.0, cyl_dz = 0.0;
+    ctrex::SubView *d_tab_cyl = nullptr;  // sources and R_p M^-1 in the cylinder frame
+    double *d_P_cyl = nullptr;            // P T^-1: matrices acting on cylinder-frame points
+    size_t cyl_cap = 0;
     uint64_t generation = 0;  // bumps on geometry or motion change
     // motion
     float4 *d_U = nullptr;
@@ -53,7 +61,7 @@ struct ctrex_ctx {
         const void *ws;
         uint64_t gen;
         bool all;
-        bool voxel_bp;  // C = 1 / (B 1) of the voxel-driven backprojector
+        int kind;       // 0: C = 1/(A^T 1); 1: C = 1/(B 1) voxel-driven; 2: cylindrical domain
         std::vector<int32_t> views;
     };
     std::vector<WeightKey> w_cache;

@@ -80,10 +80,36 @@ hipError_t launch_back(const RayGrid &g, const WarpGrid &w, const double *Pmat, 
                        int sino_dtype, float *vol, int accumulate, int mode, float *scratch,
                        float *part, hipStream_t stream);
 size_t back_scratch_bytes(const RayGrid &g);
+// Where the voxel-driven backprojector's voxel centres sit: the Cartesian
+// grid of the RayGrid (cyl == 0), or the polar grid of the cylindrical domain
+// (cyl != 0: g.nx = n_r rings at (i + 1/2) dr, g.ny = n_phi angles 2 pi j /
+// n_phi, g.nz = n_z slices (k - (n_z - 1)/2) dz, in the frame the matrices
+// act on).
+struct VoxelGrid {
+    int cyl = 0;
+    double dr = 1.0, dz = 1.0;
+};
+
 // vol (+)= B sino with the voxel-driven backprojector (ones != 0: B 1, sino
 // ignored); deterministic, no scratch.  Needs n_u, n_v >= 2.
 hipError_t launch_back_voxel(const RayGrid &g, const double *Pmat, const void *sino, int sino_dtype,
-                             float *vol, int accumulate, int ones, hipStream_t stream);
+                             float *vol, int accumulate, int ones, const VoxelGrid &vg,
+                             hipStream_t stream);
+
+// The aligned cylindrical domain: polar grid [nz][nphi][nr] about the z axis
+// of the cylinder frame; the RayGrid's table then holds every sub-view's
+// source and R_p M^-1 in that frame.
+struct CylGrid {
+    int nr, nphi, nz;
+    float inv_dr, inv_dz, half_z, phi_scale;  // 1/dr, 1/dz, (nz-1)/2, nphi/(2 pi)
+    double rh2, hz;                           // hull radius^2 and half height
+};
+CylGrid make_cyl_grid(int nr, int nphi, int nz, double dr, double dz);
+hipError_t launch_forward_cyl(const RayGrid &g, const CylGrid &c, const void *vol, int vol_dtype,
+                              void *out, int out_dtype, int mode, const FpExtra &ex,
+                              hipStream_t stream);
+hipError_t launch_sample_count_cyl(const RayGrid &g, const CylGrid &c, unsigned long long *count,
+                                   hipStream_t stream);
 // *out = max |x_i| over n elements (out is overwritten).
 hipError_t launch_max_abs(const void *x, int dtype, size_t n, float *out, hipStream_t stream);
 hipError_t launch_sample_count(const RayGrid &g, unsigned long long *count, hipStream_t stream);

@@ -105,7 +105,7 @@ template <typename TS, bool ONES>
 __global__ __launch_bounds__(VB_THREADS) void vbp_kernel(
     const double *__restrict__ Pm, const int *__restrict__ views, int n_views, int n_sub, int nu,
     int nv, int nx, int ny, int nz, int tiles_y, int tiles_z, const TS *__restrict__ sino,
-    float *__restrict__ vol, int accumulate) {
+    float *__restrict__ vol, int accumulate, VoxelGrid vg) {
     int t = xcd_tile(blockIdx.x, gridDim.x);
     const int tz = t % tiles_z;
     t /= tiles_z;
@@ -116,7 +116,24 @@ __global__ __launch_bounds__(VB_THREADS) void vbp_kernel(
     if (ix >= nx || iy >= ny) return;  // no barriers below
     const int z0 = tz * KZ;
     const int kn = min(KZ, nz - z0);
-    const double X = ix - 0.5 * (nx - 1), Y = iy - 0.5 * (ny - 1), Z0 = z0 - 0.5 * (nz - 1);
+    // the column's top voxel centre and its step along the column
+    double X, Y, Z0, sz;
+    if (vg.cyl) {
+        // polar grid: ring ix, angle iy, slice z0
+        const double r = (ix + 0.5) * vg.dr;
+        const double phi = 6.283185307179586476925287 * iy / ny;
+        double sn, cs;
+        sincos(phi, &sn, &cs);
+        X = r * cs;
+        Y = r * sn;
+        Z0 = (z0 - 0.5 * (nz - 1)) * vg.dz;
+        sz = vg.dz;
+    } else {
+        X = ix - 0.5 * (nx - 1);
+        Y = iy - 0.5 * (ny - 1);
+        Z0 = z0 - 0.5 * (nz - 1);
+        sz = 1.0;
+    }
     const size_t img_px = static_cast<size_t>(nu) * nv;
     double acc[KZ];
 #pragma unroll
@@ -130,14 +147,16 @@ __global__ __launch_bounds__(VB_THREADS) void vbp_kernel(
             const double a0 = fma(M[0], X, fma(M[1], Y, fma(M[2], Z0, M[3])));
             const double b0 = fma(M[4], X, fma(M[5], Y, fma(M[6], Z0, M[7])));
             const double w0 = fma(M[8], X, fma(M[9], Y, fma(M[10], Z0, M[11])));
-            bool fast = M[10] == 0.0 && w0 != 0.0;
+            // change of (a, b, w) per voxel down the column
+            const double ca = M[2] * sz, cb = M[6] * sz, cw = M[10] * sz;
+            bool fast = cw == 0.0 && w0 != 0.0;
             double u0 = 0.0, v0 = 0.0, du = 0.0, dv = 0.0;
             if (fast) {
                 const double r = 1.0 / w0;
                 u0 = a0 * r;
                 v0 = b0 * r;
-                du = M[2] * r;
-                dv = M[6] * r;
+                du = ca * r;
+                dv = cb * r;
                 fast = fabs(u0) < 16777216.0 && fabs(v0) < 16777216.0 && fabs(du) < 65536.0 &&
                        fabs(dv) < 65536.0;
             }
@@ -172,10 +191,10 @@ __global__ __launch_bounds__(VB_THREADS) void vbp_kernel(
 #pragma unroll
                 for (int k = 0; k < KZ; ++k) {
                     if (k >= kn) break;
-                    const double w = fma(static_cast<double>(k), M[10], w0);
+                    const double w = fma(static_cast<double>(k), cw, w0);
                     if (w == 0.0) continue;
-                    const double u = fma(static_cast<double>(k), M[2], a0) / w;
-                    const double v = fma(static_cast<double>(k), M[6], b0) / w;
+                    const double u = fma(static_cast<double>(k), ca, a0) / w;
+                    const double v = fma(static_cast<double>(k), cb, b0) / w;
                     acc[k] += sample_at<TS, ONES>(img, nu, nv, u, v);
                 }
             }
@@ -195,7 +214,7 @@ __global__ __launch_bounds__(VB_THREADS) void vbp_kernel(
 
 template <typename TS>
 hipError_t launch_typed(const RayGrid &g, const double *Pm, const void *sino, float *vol,
-                        int accumulate, int ones, hipStream_t s) {
+                        int accumulate, int ones, const VoxelGrid &vg, hipStream_t s) {
     const int tiles_x = (g.nx + VB_TX - 1) / VB_TX;
     const int tiles_y = (g.ny + VB_TY - 1) / VB_TY;
     const int tiles_z = (g.nz + KZ - 1) / KZ;
@@ -206,27 +225,28 @@ hipError_t launch_typed(const RayGrid &g, const double *Pm, const void *sino, fl
     if (ones)
         hipLaunchKernelGGL((vbp_kernel<TS, true>), grid, block, 0, s, Pm, g.views, g.n_views,
                            g.n_sub, g.n_u, g.n_v, g.nx, g.ny, g.nz, tiles_y, tiles_z, src, vol,
-                           accumulate);
+                           accumulate, vg);
     else
         hipLaunchKernelGGL((vbp_kernel<TS, false>), grid, block, 0, s, Pm, g.views, g.n_views,
                            g.n_sub, g.n_u, g.n_v, g.nx, g.ny, g.nz, tiles_y, tiles_z, src, vol,
-                           accumulate);
+                           accumulate, vg);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_back_voxel(const RayGrid &g, const double *Pm, const void *sino, int sino_dtype,
-                             float *vol, int accumulate, int ones, hipStream_t s) {
+                             float *vol, int accumulate, int ones, const VoxelGrid &vg,
+                             hipStream_t s) {
     if (g.n_views <= 0) return hipSuccess;
     if (g.n_u < 2 || g.n_v < 2 || g.n_u >= (1 << 24) || g.n_v >= (1 << 24) ||
         static_cast<long long>(g.n_u) * g.n_v >= (1ll << 30))
         return hipErrorInvalidValue;
-    if (ones) return launch_typed<float>(g, Pm, nullptr, vol, accumulate, 1, s);
+    if (ones) return launch_typed<float>(g, Pm, nullptr, vol, accumulate, 1, vg, s);
     switch (sino_dtype) {
-    case F32: return launch_typed<float>(g, Pm, sino, vol, accumulate, 0, s);
-    case BF16: return launch_typed<bf16_t>(g, Pm, sino, vol, accumulate, 0, s);
-    case F16: return launch_typed<_Float16>(g, Pm, sino, vol, accumulate, 0, s);
+    case F32: return launch_typed<float>(g, Pm, sino, vol, accumulate, 0, vg, s);
+    case BF16: return launch_typed<bf16_t>(g, Pm, sino, vol, accumulate, 0, vg, s);
+    case F16: return launch_typed<_Float16>(g, Pm, sino, vol, accumulate, 0, vg, s);
     default: return hipErrorInvalidValue;
     }
 }
