@@ -218,3 +218,31 @@ def foam_phantom_torch(shape, rng, device, mu=0.5, dtype=None, **kw):
         sub = vol[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1]
         sub[d2 <= r * r] = 0.0
     return vol if dtype is None else vol.to(dtype)
+
+
+def vial_polar(n_r, n_phi, n_z, dr, dz, rng, dtype=np.float32):
+    """A vial-like object on the polar grid [n_z][n_phi][n_r] of the aligned
+    cylindrical domain (ring i at (i + 1/2) dr, angle 2 pi j / n_phi, slice
+    (k - (n_z - 1)/2) dz): a glass wall (mu 1.0) at 80-90 % of the radius, a
+    fill (mu 0.3) below 75 % of the height with concentric layers of +-0.05
+    and seeded spherical voids, empty above."""
+    r = (np.arange(n_r) + 0.5) * dr
+    z = (np.arange(n_z) - 0.5 * (n_z - 1)) * dz
+    R, H = n_r * dr, 0.5 * (n_z - 1) * dz
+    wall = ((r >= 0.8 * R) & (r <= 0.9 * R)).astype(np.float64)
+    fill = (r < 0.8 * R) * (0.3 + 0.05 * np.sign(np.sin(r / (0.04 * R))))
+    vol = np.empty((n_z, n_phi, n_r), dtype=dtype)
+    below = z < 0.5 * H
+    prof = wall[None, :] + fill[None, :] * below[:, None]          # [n_z][n_r]
+    vol[:] = prof[:, None, :]
+    # voids: balls in the fill, carved on the polar grid
+    phi = 2 * np.pi * np.arange(n_phi) / n_phi
+    for _ in range(int(rng.integers(8, 16))):
+        cr, cphi = rng.uniform(0.1, 0.6) * R, rng.uniform(0, 2 * np.pi)
+        cz, rad = rng.uniform(-H, 0.4 * H), rng.uniform(0.03, 0.08) * R
+        ks = np.nonzero(np.abs(z - cz) <= rad)[0]
+        for k in ks:
+            d2 = (r[None, :] * np.cos(phi)[:, None] - cr * np.cos(cphi)) ** 2 + \
+                 (r[None, :] * np.sin(phi)[:, None] - cr * np.sin(cphi)) ** 2 + (z[k] - cz) ** 2
+            vol[k][d2 <= rad * rad] = 0.0
+    return vol
