@@ -143,13 +143,16 @@ def time_to_psnr(dev):
     seed = list(configs.TEST_SEEDS)[0]
     meta = json.loads(str(np.load(WEIGHTS_FILE, allow_pickle=False)["meta"]))
     stages, per = int(meta.get("stages", 4)), int(meta.get("iters_per_stage", 1))
+    subsets = int(meta.get("subsets", 0)) or None
     res = learned.compare(geom, net, cfg, [seed], sirt_iters=50, n_stages=stages,
                           iters_per_stage=per, log=lambda s: _log("learned: " + s),
-                          fov=bool(meta.get("fov_mask", False)))
+                          fov=bool(meta.get("fov_mask", False)), subsets=subsets)
     r = res["rows"][0]
     return {"sirt_iters": 50, "stages": stages, "iters_per_stage": per, "phantom_seed": seed,
+            "physics_steps": res["physics"],
             "psnr_sirt_db": r["psnr_sirt"], "psnr_learned_db": r["psnr_learned"],
-            "psnr_sirt_same_iterations_db": r["psnr_sirt_same_budget"],
+            "psnr_physics_alone_same_steps_db": r["psnr_sirt_same_budget"],
+            "t_physics_alone_s": r["t_same_budget"],
             "resid_sirt": r["resid_sirt"], "resid_learned": r["resid_learned"],
             "t_sirt_s": r["t_sirt"], "t_learned_s": r["t_learned"],
             "time_ratio": r["t_learned"] / r["t_sirt"],

@@ -6,9 +6,11 @@ correction is the 3D U-Net of ``unet.UNet`` applied after each of a few
 unrolled SIRT iterations of Eq. (1), with the data residual as the judge:
 
 * stage k: ``iters_per_stage`` SIRT updates x <- x + alpha C A^T R (b - A x)
-  (libctrex ``ctrex_sirt_iterate``), then x~ = x + m U_k(x) with the stage's
-  own network (or one network shared by all stages), m the scanned field of
-  view (the inscribed cylinder about the rotation axis);
+  (libctrex ``ctrex_sirt_iterate``) — or, with ``subsets``, that many epochs
+  of ordered-subset SIRT (Sec. 2.3.2: Eq. (1) once per subset of
+  projections, each with its own R and C) — then x~ = x + m U_k(x) with the
+  stage's own network (or one network shared by all stages), m the scanned
+  field of view (the inscribed cylinder about the rotation axis);
 * the correction is kept only if ||A x~ - b|| <= ||A x - b||
   (``ctrex_residual_norm``); otherwise it is discarded and the remaining
   stages run plain SIRT (the fallback);
@@ -31,7 +33,7 @@ import torch
 
 from synth import configs, noise
 
-from .projector import Geometry
+from .projector import Geometry, ordered_subsets
 from .unet import UNet
 
 
@@ -82,6 +84,22 @@ def psnr(x, x_true, mask):
     return float("inf") if mse == 0 else 10.0 * np.log10(rng * rng / mse)
 
 
+def _subsets(geom, subsets):
+    """None (plain SIRT), a subset count (interleaved subsets) or explicit lists."""
+    if subsets is None or isinstance(subsets, (list, tuple)):
+        return subsets
+    return ordered_subsets(geom.n_proj, int(subsets)) if int(subsets) > 1 else None
+
+
+def physics(geom, x, b, iters, subsets=None, alpha=1.0):
+    """``iters`` SIRT iterations of Eq. (1), or ``iters`` OS-SIRT epochs over
+    ``subsets`` (lists of projections); in place, no host wait."""
+    if subsets is None:
+        geom.sirt(x, b, iters, alpha=alpha, norms=False)
+    else:
+        geom.os_sirt(x, b, subsets, iters, alpha=alpha)
+
+
 def _stage_nets(net, n_stages):
     nets = list(net) if isinstance(net, (list, tuple)) else [net]
     if len(nets) not in (1, n_stages):
@@ -94,8 +112,10 @@ class LearnedSirt:
     acceptance rule and plain-SIRT fallback.  ``net``: one UNet for all
     stages or a list with one per stage."""
 
-    def __init__(self, geom, net, n_stages=4, iters_per_stage=1, alpha=1.0, mask="fov"):
+    def __init__(self, geom, net, n_stages=4, iters_per_stage=1, alpha=1.0, mask="fov",
+                 subsets=None):
         self.geom = geom
+        self.subsets = _subsets(geom, subsets)
         self.n_stages, self.iters = int(n_stages), int(iters_per_stage)
         self.nets = _stage_nets(net, self.n_stages)
         self.alpha = float(alpha)
@@ -109,7 +129,7 @@ class LearnedSirt:
         stages = []
         fallback = False
         for k in range(self.n_stages):
-            g.sirt(x, b, self.iters, alpha=self.alpha, norms=False)
+            physics(g, x, b, self.iters, self.subsets, self.alpha)
             if fallback:
                 stages.append(dict(stage=k, corrected=False, fallback=True))
                 continue
@@ -127,7 +147,7 @@ class LearnedSirt:
 
 
 def train(geom, net, cfg, seeds, lr=1e-3, lr_final=None, n_stages=4, iters_per_stage=1,
-          crop=None, crop_steps=1, log=None, log_every=8, seed=0):
+          crop=None, crop_steps=1, log=None, log_every=8, seed=0, subsets=None):
     """Stage-wise training over the phantoms of ``seeds``.
 
     Each stage runs the SIRT update(s) on the full volume, then takes
@@ -142,6 +162,7 @@ def train(geom, net, cfg, seeds, lr=1e-3, lr_final=None, n_stages=4, iters_per_s
     and after them)."""
     rng = np.random.default_rng([seed, 23])
     nets = _stage_nets(net, n_stages)
+    subsets = _subsets(geom, subsets)
     lr_final = lr if lr_final is None else lr_final
     mask = fov_weight(geom.shape, geom.device)
     total = len(seeds) * n_stages * crop_steps
@@ -155,7 +176,7 @@ def train(geom, net, cfg, seeds, lr=1e-3, lr_final=None, n_stages=4, iters_per_s
         rows = []
         for k in range(n_stages):
             net = nets[k]
-            geom.sirt(x, b, iters_per_stage, norms=False)
+            physics(geom, x, b, iters_per_stage, subsets)
             before = net.mse(x, x_true)
             for _ in range(crop_steps):
                 rate = lr + (lr_final - lr) * k_step / max(total - 1, 1)
@@ -186,12 +207,17 @@ def _timed(fn):
 
 
 def compare(geom, net, cfg, seeds, sirt_iters=50, n_stages=4, iters_per_stage=1, log=None,
-            fov=True):
+            fov=True, subsets=None):
     """Learned pipeline versus plain SIRT on held-out phantoms: PSNR, data
     residual ||A x - b|| and wall time of each; returns a summary dict.
-    ``fov``: confine the corrections to the field of view (as in training)."""
+    ``fov``: confine the corrections to the field of view (as in training).
+    ``subsets``: the pipeline's physics steps are OS-SIRT epochs; the
+    same-budget baseline (``psnr_sirt_same_budget``) is always the pipeline's
+    own physics steps without corrections, so it isolates the networks."""
     mask = fov_mask(geom.shape, geom.device)
-    pipe = LearnedSirt(geom, net, n_stages, iters_per_stage, mask="fov" if fov else None)
+    subsets = _subsets(geom, subsets)
+    pipe = LearnedSirt(geom, net, n_stages, iters_per_stage, mask="fov" if fov else None,
+                       subsets=subsets)
     budget = n_stages * iters_per_stage
     rows = []
     for seed in seeds:
@@ -200,18 +226,19 @@ def compare(geom, net, cfg, seeds, sirt_iters=50, n_stages=4, iters_per_stage=1,
         # warm caches (SIRT weights, view lists, network buffers) outside the timings
         if not rows:
             geom.sirt(z(), b, 1, norms=False)
+            physics(geom, z(), b, 1, subsets)
             pipe(b)
         xs = z()
         _, t_sirt = _timed(lambda: geom.sirt(xs, b, sirt_iters, norms=False))
         xb = z()
-        geom.sirt(xb, b, budget, norms=False)
+        _, t_budget = _timed(lambda: physics(geom, xb, b, budget, subsets))
         (xl, st), t_learned = _timed(lambda: pipe(b))
         row = dict(seed=int(seed),
                    psnr_sirt=psnr(xs, x_true, mask), psnr_sirt_same_budget=psnr(xb, x_true, mask),
                    psnr_learned=psnr(xl, x_true, mask),
                    resid_sirt=geom.residual_norm(xs, b), resid_learned=geom.residual_norm(xl, b),
                    resid_true=geom.residual_norm(x_true, b),
-                   t_sirt=t_sirt, t_learned=t_learned,
+                   t_sirt=t_sirt, t_learned=t_learned, t_same_budget=t_budget,
                    accepted=sum(1 for s in st if s.get("corrected")))
         rows.append(row)
         if log:
@@ -224,5 +251,6 @@ def compare(geom, net, cfg, seeds, sirt_iters=50, n_stages=4, iters_per_stage=1,
     mean = {k: float(np.mean([r[k] for r in rows])) for k in keys}
     reached = all(r["psnr_learned"] >= r["psnr_sirt"] for r in rows)
     return dict(rows=rows, mean=mean, sirt_iters=sirt_iters, n_stages=n_stages,
+                physics="SIRT" if subsets is None else "OS-SIRT, %d subsets" % len(subsets),
                 learned_reaches_sirt_psnr=bool(reached),
                 time_ratio=mean["t_learned"] / mean["t_sirt"])

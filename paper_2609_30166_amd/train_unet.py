@@ -75,6 +75,9 @@ def main(argv=None):
                     help="network input scale (default: the volume width, since the "
                          "configuration stores attenuation per volume width)")
     ap.add_argument("--epochs", type=int, default=1)
+    ap.add_argument("--subsets", type=int, default=0,
+                    help="physics steps: OS-SIRT epochs over this many interleaved "
+                         "projection subsets (0 or 1: plain SIRT iterations)")
     ap.add_argument("--shared", action="store_true",
                     help="one network for all stages (default: one per stage)")
     ap.add_argument("--eval-only", action="store_true",
@@ -106,14 +109,14 @@ def main(argv=None):
             hists.append(learned.train(geom, net, cfg, seeds, lr=a.lr, lr_final=a.lr_final,
                                        n_stages=a.stages, iters_per_stage=a.iters_per_stage,
                                        crop=a.crop or None, crop_steps=a.crop_steps, log=log,
-                                       seed=a.seed + ep))
+                                       seed=a.seed + ep, subsets=a.subsets or None))
         hist = np.concatenate(hists)
         t_train = time.time() - t0
         meta = dict(config="learned", phantoms=a.phantoms, epochs=a.epochs, stages=a.stages,
                     iters_per_stage=a.iters_per_stage, lr=a.lr, lr_final=a.lr_final,
                     crop=a.crop, crop_steps=a.crop_steps, seed=a.seed, scale=net[0].scale,
                     train_s=t_train, networks=len(net), adam_steps=[n.step for n in net],
-                    fov_mask=True)
+                    fov_mask=True, subsets=a.subsets)
         save(a.out, net, meta)
         if a.weights_only:
             save(a.weights_only, net, meta, optimizer_state=False)
@@ -127,14 +130,16 @@ def main(argv=None):
             m = json.loads(str(np.load(a.resume, allow_pickle=False)["meta"]))
             fov = bool(m.get("fov_mask", False))
             a.stages, a.iters_per_stage = int(m["stages"]), int(m["iters_per_stage"])
+            a.subsets = int(m.get("subsets", 0))
         res = learned.compare(geom, net, cfg, list(configs.TEST_SEEDS)[:a.test],
                               sirt_iters=a.sirt_iters, n_stages=a.stages,
-                              iters_per_stage=a.iters_per_stage, log=log, fov=fov)
+                              iters_per_stage=a.iters_per_stage, log=log, fov=fov,
+                              subsets=a.subsets or None)
         summary["compare"] = res
         m = res["mean"]
-        log("mean PSNR: SIRT-%d %.2f dB, SIRT-%d %.2f dB, learned %.2f dB; time %.3f s vs "
-            "%.3f s (ratio %.3f); learned >= SIRT-%d PSNR on every phantom: %s" % (
-                a.sirt_iters, m["psnr_sirt"], a.stages * a.iters_per_stage,
+        log("mean PSNR: SIRT-%d %.2f dB, physics alone (%s, %d steps) %.2f dB, learned %.2f dB; "
+            "time %.3f s vs %.3f s (ratio %.3f); learned >= SIRT-%d PSNR on every phantom: %s" % (
+                a.sirt_iters, m["psnr_sirt"], res["physics"], a.stages * a.iters_per_stage,
                 m["psnr_sirt_same_budget"], m["psnr_learned"], m["t_learned"], m["t_sirt"],
                 res["time_ratio"], a.sirt_iters, res["learned_reaches_sirt_psnr"]))
     if a.summary:

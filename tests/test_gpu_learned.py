@@ -65,6 +65,20 @@ def test_identity_network_is_kept_and_changes_nothing(tiny):
     assert torch.equal(x, ref)
 
 
+def test_ordered_subset_stages_with_identity_network_are_os_sirt(tiny):
+    """With ordered-subset physics steps (Sec. 2.3.2) and a zero head, the
+    pipeline is exactly OS-SIRT: one epoch per stage over the same subsets."""
+    from paper_2609_30166_amd import ordered_subsets
+    from paper_2609_30166_amd.learned import LearnedSirt
+    cfg, g, xt, b = tiny
+    net = _net(head_std=0.0)
+    x, stages = LearnedSirt(g, net, n_stages=3, subsets=4)(b)
+    assert all(s["corrected"] for s in stages)
+    ref = torch.zeros_like(x)
+    g.os_sirt(ref, b, ordered_subsets(cfg.n_proj, 4), 3)
+    assert torch.equal(x, ref)
+
+
 def test_rejection_happens_at_the_stage_that_hurts(tiny):
     """Stage-by-stage check of the rule against residual norms recomputed
     independently by the library."""
@@ -102,8 +116,9 @@ def test_training_checkpoint_resume_is_bitwise(tiny):
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
 def test_trained_network_gains_over_plain_sirt():
     """On a held-out phantom of the learned-correction configuration (256^3,
-    180 x 384^2, Poisson I0 = 1e4), the staged pipeline beats plain SIRT
-    with the same number of iterations in PSNR and keeps its corrections."""
+    180 x 384^2, Poisson I0 = 1e4), the staged pipeline beats its own physics
+    steps without corrections (the same SIRT iterations or OS-SIRT epochs) in
+    PSNR and keeps its corrections."""
     from paper_2609_30166_amd import learned
     from paper_2609_30166_amd.train_unet import load
     from synth import configs
@@ -117,7 +132,8 @@ def test_trained_network_gains_over_plain_sirt():
     seed = list(configs.TEST_SEEDS)[2]   # an ellipsoid phantom
     stages = int(meta["stages"])
     res = learned.compare(geom, nets, cfg, [seed], sirt_iters=stages * per, n_stages=stages,
-                          iters_per_stage=per, fov=bool(meta.get("fov_mask", False)))
+                          iters_per_stage=per, fov=bool(meta.get("fov_mask", False)),
+                          subsets=int(meta.get("subsets", 0)) or None)
     r = res["rows"][0]
     assert r["accepted"] >= 1
     assert r["psnr_learned"] >= r["psnr_sirt_same_budget"] + 1.0, r
