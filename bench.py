@@ -12,10 +12,11 @@ number of trilinear samples of one forward projection.  Kernel times come
 from HIP events the library records on its launch stream inside the timed
 steps.  The CPU baseline is the FP64 oracle on a bounded view subset.
 
-The JSON line also carries, when the trained correction network is
-present, the time-to-PSNR comparison of the learned pipeline (4 stages of
-SIRT + U-Net) against 50 plain SIRT iterations on one held-out phantom of the
-learned-correction configuration (256^3, 180 x 384^2, Poisson noise).
+The JSON line also carries, when the trained correction networks are
+present, the time-to-PSNR comparison of the learned pipeline (4 stages of an
+ordered-subset SIRT epoch + U-Net) against 50 plain SIRT iterations on one
+held-out phantom of the learned-correction configuration (256^3, 180 x 384^2,
+Poisson noise).
 
 HBM traffic: ``roofline.traffic`` is read from the committed counter summary
 (two rocprofv3 --pmc passes, FETCH_SIZE then WRITE_SIZE, scaled by the

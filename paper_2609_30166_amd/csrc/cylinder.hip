@@ -131,15 +131,30 @@ __device__ __forceinline__ float cyl_march(const RayGrid &g, const CylGrid &c,
             y += static_cast<float>(L);   // n samples of weight h
             continue;
         }
-        float acc = 0.0f;
-        for (int i = 0; i < n; ++i) {
-            const double tt = fma(i + 0.5, h, t0);
-            const float x = static_cast<float>(fma(tt, d[0], sv.S[0]));
-            const float yy = static_cast<float>(fma(tt, d[1], sv.S[1]));
-            const float z = static_cast<float>(fma(tt, d[2], sv.S[2]));
-            acc += cyl_sample(vol, c, x, yy, z);
+        // four independent samples per iteration keep several lookups in flight
+        float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f, acc3 = 0.0f;
+        int i = 0;
+        for (; i + 3 < n; i += 4) {
+            float xs[4], ys[4], zs[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double tt = fma(i + q + 0.5, h, t0);
+                xs[q] = static_cast<float>(fma(tt, d[0], sv.S[0]));
+                ys[q] = static_cast<float>(fma(tt, d[1], sv.S[1]));
+                zs[q] = static_cast<float>(fma(tt, d[2], sv.S[2]));
+            }
+            acc0 += cyl_sample(vol, c, xs[0], ys[0], zs[0]);
+            acc1 += cyl_sample(vol, c, xs[1], ys[1], zs[1]);
+            acc2 += cyl_sample(vol, c, xs[2], ys[2], zs[2]);
+            acc3 += cyl_sample(vol, c, xs[3], ys[3], zs[3]);
         }
-        y = fmaf(static_cast<float>(h), acc, y);
+        for (; i < n; ++i) {
+            const double tt = fma(i + 0.5, h, t0);
+            acc0 += cyl_sample(vol, c, static_cast<float>(fma(tt, d[0], sv.S[0])),
+                               static_cast<float>(fma(tt, d[1], sv.S[1])),
+                               static_cast<float>(fma(tt, d[2], sv.S[2])));
+        }
+        y = fmaf(static_cast<float>(h), (acc0 + acc1) + (acc2 + acc3), y);
     }
     return y / static_cast<float>(g.n_sub);
 }
