@@ -314,19 +314,27 @@ class Geometry:
 def ordered_subsets(n_proj, n_subsets, order="interleaved", seed=0):
     """Partition of the projections 0..n_proj-1 into ``n_subsets`` subsets
     (Sec. 2.3.2): "interleaved" (subset k = every n_subsets-th projection from
-    k, so each subset spans the whole orbit), "contiguous" (consecutive
-    blocks), or "random" (a seeded permutation cut into blocks)."""
+    k, so each subset spans the whole orbit), "bitreversal" (the interleaved
+    subsets visited in bit-reversed index order, so consecutive subsets sit
+    far apart on the orbit: the geometry-ordered schedule of ART/OS methods),
+    "contiguous" (consecutive blocks), or "random" (a seeded permutation cut
+    into blocks).  The list order is the visiting order."""
     n_proj, n_subsets = int(n_proj), int(n_subsets)
     if not 1 <= n_subsets <= n_proj:
         raise ValueError("need 1 <= n_subsets <= n_proj")
-    if order == "interleaved":
-        return [list(range(k, n_proj, n_subsets)) for k in range(n_subsets)]
+    if order in ("interleaved", "bitreversal"):
+        subs = [list(range(k, n_proj, n_subsets)) for k in range(n_subsets)]
+        if order == "bitreversal":
+            bits = max(1, (n_subsets - 1).bit_length())
+            rev = lambda k: int(format(k, "0%db" % bits)[::-1], 2)
+            subs = [subs[k] for k in sorted(range(n_subsets), key=rev)]
+        return subs
     if order == "contiguous":
         base = np.arange(n_proj)
     elif order == "random":
         base = np.random.default_rng([seed, 31]).permutation(n_proj)
     else:
-        raise ValueError("order must be interleaved, contiguous or random")
+        raise ValueError("order must be interleaved, bitreversal, contiguous or random")
     return [sorted(int(v) for v in part) for part in np.array_split(base, n_subsets)]
 
 

@@ -222,7 +222,7 @@ def test_os_sirt_converges_faster_per_data_pass_on_consistent_data():
 
 def test_ordered_subsets_partition_the_projections():
     from paper_2609_30166_amd.projector import ordered_subsets
-    for order in ("interleaved", "contiguous", "random"):
+    for order in ("interleaved", "bitreversal", "contiguous", "random"):
         for n, k in ((720, 10), (13, 4), (5, 5), (7, 1)):
             s = ordered_subsets(n, k, order)
             assert len(s) == k
@@ -230,6 +230,10 @@ def test_ordered_subsets_partition_the_projections():
             assert flat == list(range(n)), (order, n, k)
     assert ordered_subsets(8, 4)[1] == [1, 5]
     assert ordered_subsets(8, 4, "contiguous")[1] == [2, 3]
+    # bit-reversed visiting order of the interleaved subsets: 0, 4, 2, 6, 1, 5, 3, 7
+    br = ordered_subsets(16, 8, "bitreversal")
+    assert [part[0] for part in br] == [0, 4, 2, 6, 1, 5, 3, 7]
+    assert [part[0] for part in ordered_subsets(30, 6, "bitreversal")] == [0, 4, 2, 1, 5, 3]
     with pytest.raises(ValueError):
         ordered_subsets(4, 5)
 
