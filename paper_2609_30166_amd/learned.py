@@ -3,7 +3,7 @@
 The paper names learned correction terms between physics-based operator
 applications as the extension of its operator framework (Sec. 5).  Here the
 correction is the 3D U-Net of ``unet.UNet`` applied after each of a few
-unrolled SIRT iterations of Eq. (1), with the data residual as the judge:
+unrolled SIRT iterations of Eq. (1), with the data residual as the arbiter:
 
 * stage k: ``iters_per_stage`` SIRT updates x <- x + alpha C A^T R (b - A x)
   (libctrex ``ctrex_sirt_iterate``) — or, with ``subsets``, that many epochs
