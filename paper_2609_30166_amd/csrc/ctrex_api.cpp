@@ -28,6 +28,9 @@ constexpr size_t kAlign = 256;
 constexpr int kResidCap = 1024;
 constexpr size_t kMaxLists = 64;
 constexpr size_t kMaxWeightSets = 64;
+// FP32 volumes are gathered from corner-packed copies (two 16-byte loads per
+// sample instead of four 8-byte ones); 16-bit volumes from the plain copies.
+constexpr bool kPackedCorners = true;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -234,8 +237,8 @@ SirtLayout sirt_layout(const ctrex_ctx *c, int32_t n_views, uint32_t flags) {
     off = align_up(off + 4 * vox);
     l.shadow = off;
     off = align_up(off + (g16 ? 2 * vox : 0));
-    l.vt = off;   // y-fastest copy of the gathered volume
-    off = align_up(off + (g16 ? 2 : 4) * vox);
+    l.vt = off;   // y-fastest copy of the gathered volume, or the two corner-packed copies
+    off = align_up(off + (g16 ? 2 * vox : kPackedCorners ? 2 * sizeof(float4) * vox : 4 * vox));
     l.partials = off;
     off = align_up(off + 8 * tiles);
     l.resid = off;
@@ -466,11 +469,23 @@ int ctrex_forward_project(ctrex_ctx *c, const void *vol, int32_t vol_dtype, void
     if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
     const RayGrid g = make_grid(c, dv, nv);
     FpExtra ex{nullptr, nullptr, nullptr};
-    // y-fastest copy for the projections whose rays run mainly along x
-    void *vt;
-    if ((st = ctx_scratch(c, dtype_size(vol_dtype) * c->nx * c->ny * c->nz, &vt))) return st;
-    CTREX_HIP(c, launch_transpose_xy(vol, vt, vol_dtype, c->nx, c->ny, c->nz, s));
-    ex.vol_t = vt;
+    const size_t vox = static_cast<size_t>(c->nx) * c->ny * c->nz;
+    if (kPackedCorners && vol_dtype == F32) {
+        // corner-packed copies, x- and y-fastest
+        void *pk;
+        if ((st = ctx_scratch(c, 2 * sizeof(float4) * vox, &pk))) return st;
+        float4 *p4 = static_cast<float4 *>(pk);
+        CTREX_HIP(c, launch_pack_corners(static_cast<const float *>(vol), p4, p4 + vox, c->nx,
+                                         c->ny, c->nz, s));
+        ex.p4 = p4;
+        ex.p4t = p4 + vox;
+    } else {
+        // y-fastest copy for the projections whose rays run mainly along x
+        void *vt;
+        if ((st = ctx_scratch(c, dtype_size(vol_dtype) * vox, &vt))) return st;
+        CTREX_HIP(c, launch_transpose_xy(vol, vt, vol_dtype, c->nx, c->ny, c->nz, s));
+        ex.vol_t = vt;
+    }
     CTREX_HIP(c, launch_forward(g, make_warp(c), vol, vol_dtype, sino, sino_dtype, FP_PLAIN, ex, s));
     return CTREX_OK;
 }
@@ -492,15 +507,25 @@ int ctrex_residual_norm(ctrex_ctx *c, const void *vol, int32_t vol_dtype, const 
     if (!vol || !sino) return fail(c, CTREX_EINVAL, "vol and sino must be device pointers");
     if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
     const RayGrid g = make_grid(c, dv, nv);
-    const size_t vt_bytes = align_up(dtype_size(vol_dtype) * c->nx * c->ny * c->nz);
+    const size_t vox = static_cast<size_t>(c->nx) * c->ny * c->nz;
+    const bool packed = kPackedCorners && vol_dtype == F32;
+    const size_t vt_bytes = align_up(packed ? 2 * sizeof(float4) * vox : dtype_size(vol_dtype) * vox);
     void *scr;
     if ((st = ctx_scratch(c, vt_bytes + sizeof(double) * (static_cast<size_t>(g.total_blocks) + 1),
                           &scr)))
         return st;
     double *part = reinterpret_cast<double *>(static_cast<char *>(scr) + vt_bytes);
-    CTREX_HIP(c, launch_transpose_xy(vol, scr, vol_dtype, c->nx, c->ny, c->nz, s));
     FpExtra ex{sino, nullptr, part};
-    ex.vol_t = scr;
+    if (packed) {
+        float4 *p4 = static_cast<float4 *>(scr);
+        CTREX_HIP(c, launch_pack_corners(static_cast<const float *>(vol), p4, p4 + vox, c->nx,
+                                         c->ny, c->nz, s));
+        ex.p4 = p4;
+        ex.p4t = p4 + vox;
+    } else {
+        CTREX_HIP(c, launch_transpose_xy(vol, scr, vol_dtype, c->nx, c->ny, c->nz, s));
+        ex.vol_t = scr;
+    }
     // `out` is unused in this mode; the sinogram's storage type selects the kernel
     CTREX_HIP(c, launch_forward(g, make_warp(c), vol, vol_dtype, nullptr, sino_dtype, FP_RESIDUAL,
                                 ex, s));
@@ -668,11 +693,22 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
         gather = shadow;
     }
     void *vt = ws + L.vt;
-    CTREX_HIP(c, launch_transpose_xy(gather, vt, gdt, c->nx, c->ny, c->nz, s));
+    const bool packed = kPackedCorners && gdt == F32;
+    float4 *p4 = static_cast<float4 *>(vt);
+    auto refresh_copies = [&]() -> hipError_t {
+        if (packed) return launch_pack_corners(vol, p4, p4 + vox, c->nx, c->ny, c->nz, s);
+        return launch_transpose_xy(gather, vt, gdt, c->nx, c->ny, c->nz, s);
+    };
+    CTREX_HIP(c, refresh_copies());
     std::vector<double> host_norms;
     if (resid_norms) host_norms.reserve(n_iter);
     FpExtra ex{sino, Rw, partials};
-    ex.vol_t = vt;
+    if (packed) {
+        ex.p4 = p4;
+        ex.p4t = p4 + vox;
+    } else {
+        ex.vol_t = vt;
+    }
     for (int32_t k = 0; k < n_iter; ++k) {
         PhaseTimer t_fp{c, s, nullptr, 0}, t_bp{c, s, nullptr, 1}, t_up{c, s, nullptr, 2};
         CTREX_HIP(c, t_fp.begin());
@@ -688,8 +724,7 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
         CTREX_HIP(c, t_up.begin());
         CTREX_HIP(c, launch_update(vol, z, Cw, c->d_vw, alpha, (flags & CTREX_NONNEG) ? 1 : 0,
                                    gdt != F32 ? shadow : nullptr, gdt, vox, s));
-        if (k + 1 < n_iter)
-            CTREX_HIP(c, launch_transpose_xy(gather, vt, gdt, c->nx, c->ny, c->nz, s));
+        if (k + 1 < n_iter) CTREX_HIP(c, refresh_copies());
         CTREX_HIP(c, t_up.end());
         if (resid_norms && ((k + 1) % kResidCap == 0 || k + 1 == n_iter)) {
             const int cnt = (k % kResidCap) + 1;

@@ -61,6 +61,12 @@ struct FpExtra {
     const float *R;      // detector weights (FP_CORRECT)
     double *partials;    // [total_blocks] (FP_CORRECT, FP_RESIDUAL)
     const void *vol_t = nullptr;  // optional y-fastest copy [nz][nx][ny] of the volume
+    // optional corner-packed copies of an FP32 volume (element (x, y, z) = the
+    // four corners v(x, y), v(x+1, y), v(x, y+1), v(x+1, y+1) of slice z):
+    // x-fastest [nz][ny][nx] and y-fastest [nz][nx][ny]; when set they replace
+    // vol and vol_t in the gathers
+    const float4 *p4 = nullptr;
+    const float4 *p4t = nullptr;
 };
 
 // Backprojection modes.
@@ -121,6 +127,9 @@ hipError_t launch_update(float *x, const float *z, const float *C, const float *
 // dst = src with x and y exchanged ([nz][ny][nx] -> [nz][nx][ny]); dtype
 // gives the element size.
 hipError_t launch_transpose_xy(const void *src, void *dst, int dtype, int nx, int ny, int nz,
+                               hipStream_t s);
+// p4 / p4t = the corner-packed copies of FpExtra (either may be null).
+hipError_t launch_pack_corners(const float *vol, float4 *p4, float4 *p4t, int nx, int ny, int nz,
                                hipStream_t s);
 hipError_t launch_convert(const void *src, int src_dtype, void *dst, int dst_dtype, size_t n,
                           hipStream_t stream);

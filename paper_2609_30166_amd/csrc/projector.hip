@@ -25,11 +25,23 @@ namespace {
 using namespace dev;
 
 // ------------------------------------------------------- forward kernel ----
+// Gather from a corner-packed copy: the eight corners of a sample are the two
+// 16-byte elements of its lower corner in slices z and z + 1, holding the
+// values of the pair loads of `gather` / `gather_t` in the same order.
+__device__ __forceinline__ float gather_p4(const float4 *__restrict__ p4, const VolDims &d,
+                                           const Corner &k) {
+    const float4 a = p4[k.base];
+    const float4 b = p4[k.base + d.nxy];
+    return blend(k, a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w);
+}
+
 // One ray's projection value: the mean over sub-views of the step-weighted
-// trilinear samples.  TL: gather from the y-fastest copy of the volume.
-template <typename TV, int MODE, bool WARP, bool TL>
+// trilinear samples.  TL: gather from the y-fastest copy of the volume; PK:
+// from the corner-packed copy `pk` (y-fastest when TL).
+template <typename TV, int MODE, bool WARP, bool TL, bool PK>
 __device__ __forceinline__ float march(const RayGrid &g, const WarpGrid &w,
-                                       const TV *__restrict__ vol, const VolDims &d,
+                                       const TV *__restrict__ vol,
+                                       const float4 *__restrict__ pk, const VolDims &d,
                                        const TileCoord &t) {
     float y = 0.0f;
     for (int s = 0; s < g.n_sub; ++s) {
@@ -62,7 +74,12 @@ __device__ __forceinline__ float march(const RayGrid &g, const WarpGrid &w,
                     acc1 += inb ? 1.0f : 0.0f;
                 } else {
                     float va, vb;
-                    if (TL) {
+                    if (PK) {
+                        va = gather_p4(pk, d, TL ? corner_of_t(d, an, ax, ay, az)
+                                                 : corner_of(d, an, ax, ay, az));
+                        vb = gather_p4(pk, d, TL ? corner_of_t(d, an, bx, by, bz)
+                                                 : corner_of(d, an, bx, by, bz));
+                    } else if (TL) {
                         va = gather_t(vol, d, corner_of_t(d, an, ax, ay, az));
                         vb = gather_t(vol, d, corner_of_t(d, an, bx, by, bz));
                     } else {
@@ -82,8 +99,11 @@ __device__ __forceinline__ float march(const RayGrid &g, const WarpGrid &w,
                 if (MODE == FP_RECIP_ONES) {
                     acc0 += ina ? 1.0f : 0.0f;
                 } else {
-                    const float va = TL ? gather_t(vol, d, corner_of_t(d, an, ax, ay, az))
-                                        : gather(vol, d, corner_of(d, an, ax, ay, az));
+                    const float va =
+                        PK ? gather_p4(pk, d, TL ? corner_of_t(d, an, ax, ay, az)
+                                                 : corner_of(d, an, ax, ay, az))
+                        : TL ? gather_t(vol, d, corner_of_t(d, an, ax, ay, az))
+                             : gather(vol, d, corner_of(d, an, ax, ay, az));
                     acc0 += ina ? va : 0.0f;
                 }
             }
@@ -105,12 +125,16 @@ __global__ __launch_bounds__(PROJ_THREADS) void fp_kernel(RayGrid g, WarpGrid w,
     const TV *vt = static_cast<const TV *>(ex.vol_t);
     const double uc = static_cast<double>((t.iu & ~(TILE_U - 1)) + TILE_U / 2);
     const double vc = static_cast<double>((t.iv & ~(TILE_V - 1)) + TILE_V / 2);
-    const bool use_t = MODE != FP_RECIP_ONES && vt != nullptr &&
-                       x_major(g.tab[t.p * g.n_sub], uc, vc);
+    const bool xm = MODE != FP_RECIP_ONES && x_major(g.tab[t.p * g.n_sub], uc, vc);
+    const bool pk = MODE != FP_RECIP_ONES && ex.p4 != nullptr;
     float y = 0.0f;
     if (active) {
-        y = use_t ? march<TV, MODE, WARP, true>(g, w, vt, d, t)
-                  : march<TV, MODE, WARP, false>(g, w, vol, d, t);
+        if (pk)
+            y = (xm && ex.p4t) ? march<TV, MODE, WARP, true, true>(g, w, vol, ex.p4t, d, t)
+                               : march<TV, MODE, WARP, false, true>(g, w, vol, ex.p4, d, t);
+        else
+            y = (xm && vt) ? march<TV, MODE, WARP, true, false>(g, w, vt, nullptr, d, t)
+                           : march<TV, MODE, WARP, false, false>(g, w, vol, nullptr, d, t);
     }
     const int pix = (t.k * g.n_v + t.iv) * g.n_u + t.iu;
     if (MODE == FP_PLAIN) {

@@ -144,7 +144,49 @@ __global__ __launch_bounds__(256) void transpose_xy_kernel(const T *__restrict__
     }
 }
 
+// Corner-packed copies: element (x, y, z) holds v(x, y), v(x+1, y), v(x, y+1),
+// v(x+1, y+1) of slice z (indices clamped at the last row and column, whose
+// elements the gathers never read).  XF: x-fastest layout, else y-fastest.
+template <bool XF>
+__global__ __launch_bounds__(THREADS) void pack_corners_kernel(const float *__restrict__ v,
+                                                               float4 *__restrict__ out, int nx,
+                                                               int ny, size_t n) {
+    const size_t stride = static_cast<size_t>(gridDim.x) * THREADS;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * THREADS + threadIdx.x; i < n; i += stride) {
+        int x, y;
+        size_t z;
+        if (XF) {
+            x = static_cast<int>(i % nx);
+            const size_t r = i / nx;
+            y = static_cast<int>(r % ny);
+            z = r / ny;
+        } else {
+            y = static_cast<int>(i % ny);
+            const size_t r = i / ny;
+            x = static_cast<int>(r % nx);
+            z = r / nx;
+        }
+        const int x1 = min(x + 1, nx - 1), y1 = min(y + 1, ny - 1);
+        const float *s = v + z * nx * ny;
+        out[i] = make_float4(s[static_cast<size_t>(y) * nx + x], s[static_cast<size_t>(y) * nx + x1],
+                             s[static_cast<size_t>(y1) * nx + x], s[static_cast<size_t>(y1) * nx + x1]);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_pack_corners(const float *vol, float4 *p4, float4 *p4t, int nx, int ny, int nz,
+                               hipStream_t s) {
+    const size_t n = static_cast<size_t>(nx) * ny * nz;
+    if (n == 0) return hipSuccess;
+    if (p4)
+        hipLaunchKernelGGL(pack_corners_kernel<true>, dim3(grid_for(n)), dim3(THREADS), 0, s, vol,
+                           p4, nx, ny, n);
+    if (p4t)
+        hipLaunchKernelGGL(pack_corners_kernel<false>, dim3(grid_for(n)), dim3(THREADS), 0, s,
+                           vol, p4t, nx, ny, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_transpose_xy(const void *src, void *dst, int dtype, int nx, int ny, int nz,
                                hipStream_t s) {
