@@ -871,7 +871,7 @@ VoxelGrid cyl_voxels(const ctrex_ctx *c) {
 }
 
 struct CylLayout {
-    size_t R, r, C, z, partials, resid, total;
+    size_t R, r, C, z, p4, partials, resid, total;
 };
 
 CylLayout cyl_layout(const ctrex_ctx *c, int32_t n_views) {
@@ -889,6 +889,8 @@ CylLayout cyl_layout(const ctrex_ctx *c, int32_t n_views) {
     off = align_up(off + 4 * vox);
     l.z = off;
     off = align_up(off + 4 * vox);
+    l.p4 = off;   // corner-packed copy of the volume
+    off = align_up(off + (kPackedCorners ? sizeof(float4) * vox : 0));
     l.partials = off;
     off = align_up(off + 8 * tiles);
     l.resid = off;
@@ -1007,6 +1009,14 @@ int ctrex_forward_project_cyl(ctrex_ctx *c, const void *vol, int32_t vol_dtype, 
     if (!vol || !sino) return fail(c, CTREX_EINVAL, "vol and sino must be device pointers");
     if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
     FpExtra ex{nullptr, nullptr, nullptr};
+    if (kPackedCorners && vol_dtype == F32) {
+        void *pk;
+        const size_t vox = static_cast<size_t>(c->cyl_nr) * c->cyl_nphi * c->cyl_nz;
+        if ((st = ctx_scratch(c, sizeof(float4) * vox, &pk))) return st;
+        CTREX_HIP(c, launch_pack_polar(static_cast<const float *>(vol), static_cast<float4 *>(pk),
+                                       c->cyl_nr, c->cyl_nphi, c->cyl_nz, s));
+        ex.p4 = static_cast<const float4 *>(pk);
+    }
     CTREX_HIP(c, launch_forward_cyl(make_grid_cyl(c, dv, nv), cyl_of(c), vol, vol_dtype, sino,
                                     sino_dtype, FP_PLAIN, ex, s));
     return CTREX_OK;
@@ -1132,9 +1142,12 @@ int ctrex_sirt_iterate_cyl(ctrex_ctx *c, float *vol, const void *sino, int32_t s
     std::vector<double> host_norms;
     if (resid_norms) host_norms.reserve(n_iter);
     FpExtra ex{sino, Rw, partials};
+    float4 *p4 = kPackedCorners ? reinterpret_cast<float4 *>(ws + L.p4) : nullptr;
+    ex.p4 = p4;
     for (int32_t k = 0; k < n_iter; ++k) {
         PhaseTimer t_fp{c, s, nullptr, 0}, t_bp{c, s, nullptr, 1}, t_up{c, s, nullptr, 2};
         CTREX_HIP(c, t_fp.begin());
+        if (p4) CTREX_HIP(c, launch_pack_polar(vol, p4, c->cyl_nr, c->cyl_nphi, c->cyl_nz, s));
         CTREX_HIP(c, launch_forward_cyl(g, cg, vol, F32, r, sino_dtype, FP_CORRECT, ex, s));
         CTREX_HIP(c, t_fp.end());
         CTREX_HIP(c, launch_sum_partials(partials, g.total_blocks, resid + (k % kResidCap), s));

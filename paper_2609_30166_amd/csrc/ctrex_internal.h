@@ -131,6 +131,10 @@ hipError_t launch_transpose_xy(const void *src, void *dst, int dtype, int nx, in
 // p4 / p4t = the corner-packed copies of FpExtra (either may be null).
 hipError_t launch_pack_corners(const float *vol, float4 *p4, float4 *p4t, int nx, int ny, int nz,
                                hipStream_t s);
+// Corner-packed copy of a polar volume [nz][nphi][nr]: element (k, j, a) holds
+// v(a, j), v(a+1, j), v(a, j+1), v(a+1, j+1) of slice k, the angle periodic.
+hipError_t launch_pack_polar(const float *vol, float4 *p4, int nr, int nphi, int nz,
+                             hipStream_t s);
 hipError_t launch_convert(const void *src, int src_dtype, void *dst, int dst_dtype, size_t n,
                           hipStream_t stream);
 hipError_t launch_sum_partials(const double *partials, int n, double *out, hipStream_t stream);

@@ -115,9 +115,45 @@ __device__ __forceinline__ float cyl_sample(const TV *__restrict__ vol, const Cy
     return fmaf(fz, s1 - s0, s0);
 }
 
-template <typename TV, int MODE>
+// The same lookup from the corner-packed copy: the four (ring, angle) corners
+// of slices k0 and k0 + 1 are one 16-byte element each, in the order of the
+// radial pairs above.
+__device__ __forceinline__ float cyl_sample_p4(const float4 *__restrict__ p4, const CylGrid &c,
+                                               float x, float y, float z) {
+    const float r = sqrtf(fmaf(x, x, y * y));
+    float a = fmaf(r, c.inv_dr, -0.5f);
+    a = fminf(fmaxf(a, 0.0f), static_cast<float>(c.nr - 1));
+    float b = atan2f(y, x) * c.phi_scale;
+    if (b < 0.0f) b += static_cast<float>(c.nphi);
+    float zz = fmaf(z, c.inv_dz, c.half_z);
+    zz = fminf(fmaxf(zz, 0.0f), static_cast<float>(c.nz - 1));
+    const int a0 = min(static_cast<int>(a), c.nr - 2);
+    const int k0 = min(static_cast<int>(zz), c.nz - 2);
+    const float fb_floor = floorf(b);
+    int j0 = static_cast<int>(fb_floor);
+    if (j0 >= c.nphi) j0 -= c.nphi;
+    const float fa = a - static_cast<float>(a0), fz = zz - static_cast<float>(k0),
+                fb = b - fb_floor;
+    const int plane = c.nphi * c.nr;
+    const int base = k0 * plane + j0 * c.nr + a0;
+    const float4 e0 = p4[base], e1 = p4[base + plane];
+    const float q00 = fmaf(fa, e0.y - e0.x, e0.x), q01 = fmaf(fa, e0.w - e0.z, e0.z);
+    const float q10 = fmaf(fa, e1.y - e1.x, e1.x), q11 = fmaf(fa, e1.w - e1.z, e1.z);
+    const float s0 = fmaf(fb, q01 - q00, q00), s1 = fmaf(fb, q11 - q10, q10);
+    return fmaf(fz, s1 - s0, s0);
+}
+
+template <typename TV, bool PK>
+__device__ __forceinline__ float cyl_lookup(const TV *__restrict__ vol,
+                                            const float4 *__restrict__ p4, const CylGrid &c,
+                                            float x, float y, float z) {
+    return PK ? cyl_sample_p4(p4, c, x, y, z) : cyl_sample(vol, c, x, y, z);
+}
+
+template <typename TV, int MODE, bool PK>
 __device__ __forceinline__ float cyl_march(const RayGrid &g, const CylGrid &c,
-                                           const TV *__restrict__ vol, const TileCoord &t) {
+                                           const TV *__restrict__ vol,
+                                           const float4 *__restrict__ p4, const TileCoord &t) {
     float y = 0.0f;
     for (int s = 0; s < g.n_sub; ++s) {
         const SubView &sv = g.tab[t.p * g.n_sub + s];
@@ -143,16 +179,16 @@ __device__ __forceinline__ float cyl_march(const RayGrid &g, const CylGrid &c,
                 ys[q] = static_cast<float>(fma(tt, d[1], sv.S[1]));
                 zs[q] = static_cast<float>(fma(tt, d[2], sv.S[2]));
             }
-            acc0 += cyl_sample(vol, c, xs[0], ys[0], zs[0]);
-            acc1 += cyl_sample(vol, c, xs[1], ys[1], zs[1]);
-            acc2 += cyl_sample(vol, c, xs[2], ys[2], zs[2]);
-            acc3 += cyl_sample(vol, c, xs[3], ys[3], zs[3]);
+            acc0 += cyl_lookup<TV, PK>(vol, p4, c, xs[0], ys[0], zs[0]);
+            acc1 += cyl_lookup<TV, PK>(vol, p4, c, xs[1], ys[1], zs[1]);
+            acc2 += cyl_lookup<TV, PK>(vol, p4, c, xs[2], ys[2], zs[2]);
+            acc3 += cyl_lookup<TV, PK>(vol, p4, c, xs[3], ys[3], zs[3]);
         }
         for (; i < n; ++i) {
             const double tt = fma(i + 0.5, h, t0);
-            acc0 += cyl_sample(vol, c, static_cast<float>(fma(tt, d[0], sv.S[0])),
-                               static_cast<float>(fma(tt, d[1], sv.S[1])),
-                               static_cast<float>(fma(tt, d[2], sv.S[2])));
+            acc0 += cyl_lookup<TV, PK>(vol, p4, c, static_cast<float>(fma(tt, d[0], sv.S[0])),
+                                       static_cast<float>(fma(tt, d[1], sv.S[1])),
+                                       static_cast<float>(fma(tt, d[2], sv.S[2])));
         }
         y = fmaf(static_cast<float>(h), (acc0 + acc1) + (acc2 + acc3), y);
     }
@@ -166,7 +202,10 @@ __global__ __launch_bounds__(PROJ_THREADS) void fp_cyl_kernel(RayGrid g, CylGrid
     const TileCoord t = tile_coord(g);
     if (!t.valid) return;  // uniform over the block
     const bool active = t.iu < g.n_u && t.iv < g.n_v;
-    const float y = active ? cyl_march<TV, MODE>(g, c, vol, t) : 0.0f;
+    float y = 0.0f;
+    if (active)
+        y = (MODE != FP_RECIP_ONES && ex.p4) ? cyl_march<TV, MODE, true>(g, c, vol, ex.p4, t)
+                                             : cyl_march<TV, MODE, false>(g, c, vol, nullptr, t);
     const int pix = (t.k * g.n_v + t.iv) * g.n_u + t.iu;
     if (MODE == FP_PLAIN) {
         if (active) st(out, pix, y);

@@ -173,7 +173,32 @@ __global__ __launch_bounds__(THREADS) void pack_corners_kernel(const float *__re
     }
 }
 
+__global__ __launch_bounds__(THREADS) void pack_polar_kernel(const float *__restrict__ v,
+                                                             float4 *__restrict__ out, int nr,
+                                                             int nphi, size_t n) {
+    const size_t stride = static_cast<size_t>(gridDim.x) * THREADS;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * THREADS + threadIdx.x; i < n; i += stride) {
+        const int a = static_cast<int>(i % nr);
+        const size_t r = i / nr;
+        const int j = static_cast<int>(r % nphi);
+        const size_t k = r / nphi;
+        const int a1 = min(a + 1, nr - 1), j1 = j + 1 == nphi ? 0 : j + 1;
+        const float *s = v + k * nr * nphi;
+        out[i] = make_float4(s[static_cast<size_t>(j) * nr + a], s[static_cast<size_t>(j) * nr + a1],
+                             s[static_cast<size_t>(j1) * nr + a], s[static_cast<size_t>(j1) * nr + a1]);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_pack_polar(const float *vol, float4 *p4, int nr, int nphi, int nz,
+                             hipStream_t s) {
+    const size_t n = static_cast<size_t>(nr) * nphi * nz;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(pack_polar_kernel, dim3(grid_for(n)), dim3(THREADS), 0, s, vol, p4, nr,
+                       nphi, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_pack_corners(const float *vol, float4 *p4, float4 *p4t, int nx, int ny, int nz,
                                hipStream_t s) {
