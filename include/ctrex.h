@@ -135,6 +135,11 @@ CTREX_API int ctrex_set_voxel_weights(ctrex_ctx *ctx, const float *w_dev);
  * allowed; NULL selects all projections in order).  `vol` has storage type
  * vol_dtype and `sino` sino_dtype; the sinogram is overwritten.  With an
  * empty list (n_views == 0) nothing happens and the pointers may be NULL.
+ * The rays gather from context-owned copies of `vol` made at the start of
+ * the call: for float32, two corner-packed copies (x- and y-fastest, 16 bytes
+ * per voxel each: a voxel's four corner values in its z slice); for 16-bit
+ * storage, one y-fastest copy.  The results do not depend on which copy a
+ * ray reads.
  */
 CTREX_API int ctrex_forward_project(ctrex_ctx *ctx, const void *vol, int32_t vol_dtype, void *sino,
                           int32_t sino_dtype, const int32_t *views, int32_t n_views,
@@ -145,8 +150,11 @@ CTREX_API int ctrex_forward_project(ctrex_ctx *ctx, const void *vol, int32_t vol
  * ctrex_forward_project: vol (+)= A^T sino over the listed projections.
  * `vol` is a device float32 volume; with accumulate == 0 it is zeroed first
  * (also for an empty view list, where `sino` may be NULL).
- * The scatter uses float32 atomics, so the summation order (and the last bits
- * of the result) may differ from run to run.
+ * Contributions are summed as 64-bit fixed-point integers (scale chosen from
+ * max |sino| so no sum overflows), so the result is bitwise reproducible
+ * from run to run.  Context-owned scratch holds max |sino| and, when the
+ * projections are split into several chunks, one float32 partial volume per
+ * chunk (summed in a fixed order).
  */
 CTREX_API int ctrex_back_project(ctrex_ctx *ctx, const void *sino, int32_t sino_dtype, float *vol,
                        int32_t accumulate, const int32_t *views, int32_t n_views,

@@ -18,10 +18,12 @@
 // (projection, sub-view) it bounds the detector pixels whose rays can reach
 // the brick (the projection of the brick grown by one voxel and the warp
 // bound), redoes those rays' FP64 set-up, clips their sample range to the
-// grown brick, and adds with LDS 64-bit integer atomics the corners that
-// fall inside the brick.  A sample whose corner cube straddles a brick face is visited
-// by each brick it touches, and each adds only its own corners, so every
-// corner is added once.  There is no global atomic and no barrier inside the
+// grown brick, and adds its eight corners with LDS 64-bit integer atomics.
+// The LDS brick carries one halo cell on each side in x and y, which takes
+// the corners that fall outside the brick there and is never written out; a
+// corner outside in z gets weight zero.  A sample whose corner cube straddles
+// a brick face is visited by each brick it touches, and each keeps only its
+// own corners, so every corner is counted once.  There is no global atomic and no barrier inside the
 // projection loop; the brick is written out once at the end (with atomics
 // only when several projection chunks share a brick).
 
@@ -38,9 +40,19 @@ using namespace dev;
 // ~200 bytes per lane of spills at the 64-register budget).
 constexpr int BP_THREADS = 1024;
 
+// Largest brick, and its LDS layout: rows of BRICK_X + 2 cells (halo on both
+// sides, padded to an odd stride) and planes of BRICK_Y + 2 rows.  64-bit
+// cells span two 4-byte banks; the odd row stride and a plane stride of 3
+// (mod 16) put neighbours along y, z and the diagonals in other banks.  Two
+// bricks (2 x 76 KB) share a CU's 160 KB of LDS.
+constexpr int BRICK_X = 32, BRICK_Y = 15, BRICK_Z = 16;
+constexpr int LDS_SY = (BRICK_X + 2) | 1;
+constexpr int LDS_SZ = LDS_SY * (BRICK_Y + 2);
+constexpr int LDS_CELLS = LDS_SZ * BRICK_Z;
+static_assert(LDS_SZ % 16 == 3, "plane stride");
+
 struct BrickGrid {
-    int bx, by, bz;       // brick size (voxels)
-    int sy, sz;           // LDS row / plane strides (padded against bank conflicts)
+    int bx, by, bz;       // brick size (voxels), at most BRICK_X x BRICK_Y x BRICK_Z
     int nbx, nby, nbz;    // bricks per axis
     int chunks;           // projection chunks per brick
     int views_per_chunk;
@@ -84,6 +96,35 @@ __device__ __forceinline__ bool project_box(const double *P, const double lo[3],
     return true;
 }
 
+// Wave-uniform values computed by vector instructions (LDS reads, FP64 or
+// float conversions) stay in vector registers unless moved to scalar ones;
+// at 64 vector registers per lane they would be spilled.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uni(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double uni(double x) {
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<int>(b)));
+    const int hi = __builtin_amdgcn_readfirstlane(static_cast<int>(b >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | lo);
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave with DPP lane moves:
+// shifts by 1, 2, 4, 8 within each row of 16 lanes (zero shifted in), then
+// the last lane of row 0 added to row 1 and of row 2 to row 3 (row broadcast
+// 15), then lane 31 added to rows 2 and 3 (row broadcast 31).  No LDS and no
+// per-lane addresses.
+__device__ __forceinline__ int wave_inclusive_sum(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15 -> rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31 -> rows 2, 3
+    return x;
+}
+
 // Round w * g to the nearest integer (|w g| < 2^51) as a two's-complement
 // 64-bit value: adding 1.5 * 2^52 in the same FMA leaves the rounded integer
 // in the low mantissa bits of the double.  The fixed-point scale is folded
@@ -102,7 +143,7 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
                                                               const float *__restrict__ rmax,
                                                               float *__restrict__ vol,
                                                               BrickGrid bg) {
-    extern __shared__ unsigned long long acc[];
+    __shared__ unsigned long long acc[LDS_CELLS];
     __shared__ double red[BP_THREADS / 64];
     // ---- block -> (brick, projection chunk); XCD-aware so that one XCD
     // works on neighbouring bricks
@@ -117,19 +158,20 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
     const int ibz = b / bg.nby;
     const int x0 = ibx * bg.bx, y0 = iby * bg.by, z0 = ibz * bg.bz;
     const int ex = min(bg.bx, g.nx - x0), ey = min(bg.by, g.ny - y0), ez = min(bg.bz, g.nz - z0);
-    const int sy = bg.sy, sz = bg.sz;
-    const int nlds = sz * ez;
+    const int nlds = LDS_SZ * ez;
     for (int i = threadIdx.x; i < nlds; i += BP_THREADS) acc[i] = 0ull;
+    // cell (lx, ly, lz) of the brick, lx in [-1, ex], ly in [-1, ey]
+    unsigned long long *const cell0 = acc + LDS_SY + 1;
 
     const VolDims d = vol_dims(g);
     const float M = static_cast<float>(w.margin);
     // samples with an (unwarped) position in [lo, hi] can touch the brick
-    const float lo[3] = {x0 - 1.0f - M, y0 - 1.0f - M, z0 - 1.0f - M};
-    const float hi[3] = {static_cast<float>(x0 + ex) + M, static_cast<float>(y0 + ey) + M,
-                         static_cast<float>(z0 + ez) + M};
+    const float lo[3] = {uni(x0 - 1.0f - M), uni(y0 - 1.0f - M), uni(z0 - 1.0f - M)};
+    const float hi[3] = {uni(static_cast<float>(x0 + ex) + M), uni(static_cast<float>(y0 + ey) + M),
+                         uni(static_cast<float>(z0 + ez) + M)};
     const double lod[3] = {lo[0], lo[1], lo[2]}, hid[3] = {hi[0], hi[1], hi[2]};
     const double off[3] = {0.5 * (g.nx - 1), 0.5 * (g.ny - 1), 0.5 * (g.nz - 1)};
-    const float inv_sub = 1.0f / static_cast<float>(g.n_sub);
+    const float inv_sub = uni(1.0f / static_cast<float>(g.n_sub));
     const int k_first = chunk * bg.views_per_chunk;
     const int k_end = min(k_first + bg.views_per_chunk, g.n_views);
     const int n_pairs = (k_end - k_first) * g.n_sub;
@@ -160,9 +202,9 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
                         (1.0 + 1e-5) / g.n_sub;
     const double bound = nrays * bg.cube_samples * cmax;
     const bool bad = !(cmax < __builtin_inf());   // NaN or Inf in the input: propagate NaN
-    const bool any = bound > 0.0 && !bad;
-    const int kexp = any ? static_cast<int>(floor(50.0 - log2(bound))) : 0;
-    const double scale = ldexp(1.0, kexp);
+    const bool any = uni(static_cast<int>(bound > 0.0 && !bad)) != 0;
+    const int kexp = uni(any ? static_cast<int>(floor(50.0 - log2(bound))) : 0);
+    const double scale = uni(ldexp(1.0, kexp));
 
     // each wave takes whole (projection, sub-view) pairs, so a pair's pixel
     // box is projected once, by the wave that walks its rays
@@ -170,7 +212,7 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
     for (int q = wave; q < n_pairs && any; q += BP_THREADS / 64) {
         const int k = k_first + q / g.n_sub;
         const int s = q - (q / g.n_sub) * g.n_sub;
-        const int p = g.views ? g.views[k] : k;
+        const int p = uni(g.views ? g.views[k] : k);
         {
             const int sv_idx = p * g.n_sub + s;
             const SubView &sv = g.tab[sv_idx];
@@ -182,12 +224,16 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
                 v0 = 0;
                 v1 = g.n_v - 1;
             }
+            u0 = uni(u0);
+            u1 = uni(u1);
+            v0 = uni(v0);
+            v1 = uni(v1);
             if (u0 > u1 || v0 > v1) continue;
             // rays in 8x8 pixel blocks, one block per pass; the wave shares
             // each block's samples evenly among its lanes
             const int bu = (u1 - u0 + 8) >> 3;
             const int nblk = bu * ((v1 - v0 + 8) >> 3);
-            const float tau = static_cast<float>(sv.tau);
+            const float tau = uni(static_cast<float>(sv.tau));
             const int lane = threadIdx.x & 63;
             for (int blk = 0; blk < nblk; ++blk) {
                 const int iv = v0 + (blk / bu) * 8 + (lane >> 3);
@@ -229,14 +275,9 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
                     }
                 }
                 // ---- exclusive prefix of the segment lengths over the wave
-                int incl = len;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int t = __shfl_up(incl, o, 64);
-                    if (lane >= o) incl += t;
-                }
+                const int incl = wave_inclusive_sum(len);
                 const int S = incl - len;
-                const int T = __shfl(incl, 63, 64);
+                const int T = __builtin_amdgcn_readlane(incl, 63);
                 if (T == 0) continue;   // uniform over the wave
                 const unsigned long long live = __ballot(len > 0);
                 // ---- lane takes samples [start, end) of the wave's T
@@ -301,44 +342,33 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
                     float fx, fy, fz;
                     corner_idx(d, an, cx, cy, cz, ix, iy, iz, fx, fy, fz);
                     const int lx = ix - x0, ly = iy - y0, lz = iz - z0;
+                    const bool z_0 = lz >= 0 && lz < ez, z_1 = lz + 1 >= 0 && lz + 1 < ez;
+                    // no corner in the brick
+                    if (!(lx >= -1 && lx < ex && ly >= -1 && ly < ey && (z_0 || z_1))) continue;
                     // corner weights in FP64 with the ray weight and the
-                    // fixed-point scale folded in: one FMA per corner below
+                    // fixed-point scale folded in: one FMA per corner below.
+                    // x and y neighbours outside the brick land in the halo;
+                    // a z neighbour outside gets weight zero and a plane
+                    // clamped into the brick (adding an integer zero changes
+                    // no sum), so every lane issues the same eight atomics.
                     const double gx1 = fx, gx0 = 1.0f - fx;
                     const double gy1 = fy, gy0 = 1.0f - fy;
-                    const double gz1 = fz * cws, gz0 = (1.0f - fz) * cws;
+                    const double gz1 = (z_1 ? fz : 0.0f) * cws,
+                                 gz0 = (z_0 ? 1.0f - fz : 0.0f) * cws;
                     const double w00 = gz0 * gy0, w01 = gz0 * gy1, w10 = gz1 * gy0,
                                  w11 = gz1 * gy1;
-                    if (lx >= 0 && lx + 1 < ex && ly >= 0 && ly + 1 < ey && lz >= 0 &&
-                        lz + 1 < ez) {
-                        // all eight corners inside the brick
-                        unsigned long long *ap = acc + (lz * sz + ly * sy + lx);
-                        atomicAdd(ap, to_fixed(w00, gx0));
-                        atomicAdd(ap + 1, to_fixed(w00, gx1));
-                        atomicAdd(ap + sy, to_fixed(w01, gx0));
-                        atomicAdd(ap + sy + 1, to_fixed(w01, gx1));
-                        atomicAdd(ap + sz, to_fixed(w10, gx0));
-                        atomicAdd(ap + sz + 1, to_fixed(w10, gx1));
-                        atomicAdd(ap + sz + sy, to_fixed(w11, gx0));
-                        atomicAdd(ap + sz + sy + 1, to_fixed(w11, gx1));
-                        continue;
-                    }
-                    const bool x_0 = lx >= 0 && lx < ex, x_1 = lx + 1 >= 0 && lx + 1 < ex;
-                    const bool y_0 = ly >= 0 && ly < ey, y_1 = ly + 1 >= 0 && ly + 1 < ey;
-                    const bool z_0 = lz >= 0 && lz < ez, z_1 = lz + 1 >= 0 && lz + 1 < ez;
-                    if (!((x_0 || x_1) && (y_0 || y_1) && (z_0 || z_1))) continue;
-                    const int base = lz * sz + ly * sy + lx;   // may be outside: guarded
-                    if (z_0 && y_0 && x_0) atomicAdd(acc + base, to_fixed(w00, gx0));
-                    if (z_0 && y_0 && x_1) atomicAdd(acc + base + 1, to_fixed(w00, gx1));
-                    if (z_0 && y_1 && x_0) atomicAdd(acc + base + sy, to_fixed(w01, gx0));
-                    if (z_0 && y_1 && x_1)
-                        atomicAdd(acc + base + sy + 1, to_fixed(w01, gx1));
-                    if (z_1 && y_0 && x_0) atomicAdd(acc + base + sz, to_fixed(w10, gx0));
-                    if (z_1 && y_0 && x_1)
-                        atomicAdd(acc + base + sz + 1, to_fixed(w10, gx1));
-                    if (z_1 && y_1 && x_0)
-                        atomicAdd(acc + base + sz + sy, to_fixed(w11, gx0));
-                    if (z_1 && y_1 && x_1)
-                        atomicAdd(acc + base + sz + sy + 1, to_fixed(w11, gx1));
+                    const int row = __mul24(ly, LDS_SY) + lx;
+                    unsigned long long *const a0 = cell0 + (__mul24(max(lz, 0), LDS_SZ) + row);
+                    unsigned long long *const a1 =
+                        cell0 + (__mul24(min(lz + 1, ez - 1), LDS_SZ) + row);
+                    atomicAdd(a0, to_fixed(w00, gx0));
+                    atomicAdd(a0 + 1, to_fixed(w00, gx1));
+                    atomicAdd(a0 + LDS_SY, to_fixed(w01, gx0));
+                    atomicAdd(a0 + LDS_SY + 1, to_fixed(w01, gx1));
+                    atomicAdd(a1, to_fixed(w10, gx0));
+                    atomicAdd(a1 + 1, to_fixed(w10, gx1));
+                    atomicAdd(a1 + LDS_SY, to_fixed(w11, gx0));
+                    atomicAdd(a1 + LDS_SY + 1, to_fixed(w11, gx1));
                 }
             }
         }
@@ -353,7 +383,7 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
         const int ly = rem / ex;
         const int lx = rem - ly * ex;
         float *dst = vol + (static_cast<size_t>(z0 + lz) * g.ny + (y0 + ly)) * g.nx + (x0 + lx);
-        const long long q = static_cast<long long>(acc[lz * sz + ly * sy + lx]);
+        const long long q = static_cast<long long>(cell0[lz * LDS_SZ + ly * LDS_SY + lx]);
         const float v = bad ? __builtin_nanf("") : static_cast<float>(static_cast<double>(q) * inv_scale);
         if (bg.chunks > 1) {
             // each chunk owns a slab; a fixed-order sum combines them
@@ -380,13 +410,9 @@ __global__ __launch_bounds__(256) void sum_chunks_kernel(const float *__restrict
 
 BrickGrid plan_bricks(const RayGrid &g) {
     BrickGrid bg;
-    bg.bx = min(32, g.nx);
-    bg.by = min(15, g.ny);
-    bg.bz = min(16, g.nz);
-    // 64-bit cells span two 4-byte banks: odd row stride and a plane stride of
-    // 3 (mod 16) put neighbours along y, z and the diagonals in other banks
-    bg.sy = bg.bx | 1;
-    bg.sz = bg.sy * bg.by + ((3 - (bg.sy * bg.by) % 16) + 16) % 16;
+    bg.bx = min(BRICK_X, g.nx);
+    bg.by = min(BRICK_Y, g.ny);
+    bg.bz = min(BRICK_Z, g.nz);
     bg.nbx = (g.nx + bg.bx - 1) / bg.bx;
     bg.nby = (g.ny + bg.by - 1) / bg.by;
     bg.nbz = (g.nz + bg.bz - 1) / bg.bz;
@@ -425,7 +451,7 @@ hipError_t launch_back(const RayGrid &g, const WarpGrid &w, const double *Pmat, 
     if (bg.chunks > 1 && !part) return hipErrorInvalidValue;
     const int per = (bg.total + N_XCD - 1) / N_XCD;
     const dim3 grid(static_cast<unsigned>(per * N_XCD)), block(BP_THREADS);
-    const size_t shmem = sizeof(unsigned long long) * static_cast<size_t>(bg.sz) * bg.bz;
+    const size_t shmem = 0;   // the brick is static LDS
     const bool wp = w.U != nullptr;
     const size_t nvol = static_cast<size_t>(g.nx) * g.ny * g.nz;
     auto combine = [&]() -> hipError_t {
