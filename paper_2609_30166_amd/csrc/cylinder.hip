@@ -195,8 +195,19 @@ __device__ __forceinline__ float cyl_march(const RayGrid &g, const CylGrid &c,
     return y / static_cast<float>(g.n_sub);
 }
 
+// Occupancy cap for the FP32 (polar corner-packed) gathers, as for the
+// Cartesian projector: 1104 ms at the 4 waves per SIMD its registers allow,
+// 1014 ms at 3, 932 ms at 2 (256 x 1608 x 512 polar grid, 720 x 768^2,
+// results bitwise identical).  16-bit volumes and the ray-length mode (no
+// gathers) keep the default.
+template <typename TV, int MODE>
+constexpr int fp_cyl_max_waves() {
+    return (sizeof(TV) == 4 && MODE != FP_RECIP_ONES) ? 2 : 8;
+}
+
 template <typename TV, typename TS, int MODE>
-__global__ __launch_bounds__(PROJ_THREADS) void fp_cyl_kernel(RayGrid g, CylGrid c,
+__global__ __launch_bounds__(PROJ_THREADS) __attribute__((amdgpu_waves_per_eu(1, fp_cyl_max_waves<TV, MODE>())))
+void fp_cyl_kernel(RayGrid g, CylGrid c,
                                                               const TV *__restrict__ vol,
                                                               TS *__restrict__ out, FpExtra ex) {
     const TileCoord t = tile_coord(g);

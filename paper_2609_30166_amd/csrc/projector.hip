@@ -113,8 +113,20 @@ __device__ __forceinline__ float march(const RayGrid &g, const WarpGrid &w,
     return y / static_cast<float>(g.n_sub);
 }
 
+// Occupancy cap.  The FP32 rays gather from the corner-packed copies; at the
+// 5 waves per SIMD their registers allow, more concurrent rays evict each
+// other's patches from L1 and L2.  Measured at 512^3 x 720 x 768^2 (results
+// bitwise identical): 866 ms at 5 waves, 782 ms at 3, 876 ms at 2, 1066 ms at
+// 8.  The warped and 16-bit variants, and the ray-length mode (no gathers),
+// keep the default.
+template <typename TV, int MODE, bool WARP>
+constexpr int fp_max_waves() {
+    return (sizeof(TV) == 4 && !WARP && MODE != FP_RECIP_ONES) ? 3 : 8;
+}
+
 template <typename TV, typename TS, int MODE, bool WARP>
-__global__ __launch_bounds__(PROJ_THREADS) void fp_kernel(RayGrid g, WarpGrid w,
+__global__ __launch_bounds__(PROJ_THREADS) __attribute__((amdgpu_waves_per_eu(1, fp_max_waves<TV, MODE, WARP>())))
+void fp_kernel(RayGrid g, WarpGrid w,
                                                           const TV *__restrict__ vol,
                                                           TS *__restrict__ out, FpExtra ex) {
     const TileCoord t = tile_coord(g);
