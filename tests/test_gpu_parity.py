@@ -375,3 +375,35 @@ def test_weighted_backprojection_matches_oracle(tiny, dev):
     want2, _ = oracle.sirt(cfg.P, cfg.shape, cfg.n_u, cfg.n_v, y_ref, 1, step=cfg.step,
                            x0=ref.astype(np.float64))
     assert rel_l2(v2.cpu().numpy(), want2) <= TOL
+
+
+def test_one_voxel_edge_bricks(dev):
+    """Volume sides 32 + 1, 15 + 1 and 16 + 1 voxels: the backprojector's last
+    brick along every axis is one voxel thick, so its halo cells in x and y
+    and its clamped planes in z are all exercised.  Forward, back and two
+    SIRT iterations (which also build the weight sums) against the oracle."""
+    from paper_2609_30166_amd import Geometry
+
+    shape, n_u, n_v = (17, 16, 33), 80, 40
+    P = synth.circular_cone(9, n_u, n_v, 60.0, 110.0, 0.9, arc=5.0, det_offset_u=0.7)
+    rng = np.random.default_rng(11)
+    x = rng.uniform(0, 1, shape).astype(np.float32)
+    g = Geometry(P, n_u, n_v, shape, 0.5, device=dev)
+    y = g.forward(torch.from_numpy(x).to(dev)).cpu().numpy()
+    y_ref = oracle.forward(P, shape, n_u, n_v, x.astype(np.float64))
+    assert rel_l2(y, y_ref) <= TOL
+    s = rng.normal(size=y_ref.shape).astype(np.float32)
+    z = g.back(torch.from_numpy(s).to(dev)).cpu().numpy()
+    z_ref = oracle.back(P, shape, n_u, n_v, s.astype(np.float64))
+    # the one-voxel slabs receive rays
+    assert np.abs(z_ref[16]).sum() > 0 and np.abs(z_ref[:, 15]).sum() > 0
+    assert np.abs(z_ref[:, :, 32]).sum() > 0
+    assert rel_l2(z, z_ref) <= TOL
+    for sl in (np.s_[16], np.s_[:, 15], np.s_[:, :, 32]):
+        assert rel_l2(z[sl], z_ref[sl]) <= TOL
+    b = y_ref.astype(np.float32)
+    v = torch.zeros(shape, dtype=torch.float32, device=dev)
+    norms = g.sirt(v, torch.from_numpy(b).to(dev), 2)
+    v_ref, n_ref = oracle.sirt(P, shape, n_u, n_v, b.astype(np.float64), 2)
+    assert rel_l2(v.cpu().numpy(), v_ref) <= TOL
+    np.testing.assert_allclose(norms, n_ref, rtol=TOL)
