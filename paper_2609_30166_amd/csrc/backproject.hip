@@ -23,9 +23,10 @@
 // the corners that fall outside the brick there and is never written out; a
 // corner outside in z gets weight zero.  A sample whose corner cube straddles
 // a brick face is visited by each brick it touches, and each keeps only its
-// own corners, so every corner is counted once.  There is no global atomic and no barrier inside the
-// projection loop; the brick is written out once at the end (with atomics
-// only when several projection chunks share a brick).
+// own corners, so every corner is counted once.  There is no global atomic
+// and no barrier inside the projection loop; the brick is written out once
+// at the end (into a partial volume per projection chunk, summed in a fixed
+// order, when several chunks share a brick).
 
 #include "ray_common.h"
 
@@ -36,8 +37,9 @@ using namespace dev;
 
 // 16 waves per workgroup and two workgroups (two LDS bricks) per CU: 8 waves
 // per SIMD hide the latency of the FP64 set-up and the LDS atomics better than
-// 4 waves with no register spills (measured: 7% faster at 512^3 x 720 despite
-// ~200 bytes per lane of spills at the 64-register budget).
+// 4 waves with no register spills (measured 7% faster at 512^3 x 720).  At the
+// 64-register budget the kernel spills ~160 bytes per lane, all in the ray
+// set-up of each pixel block; the per-sample path reloads nothing.
 constexpr int BP_THREADS = 1024;
 
 // Largest brick, and its LDS layout: rows of BRICK_X + 2 cells (halo on both
@@ -114,7 +116,7 @@ __device__ __forceinline__ double uni(double x) {
 // shifts by 1, 2, 4, 8 within each row of 16 lanes (zero shifted in), then
 // the last lane of row 0 added to row 1 and of row 2 to row 3 (row broadcast
 // 15), then lane 31 added to rows 2 and 3 (row broadcast 31).  No LDS and no
-// per-lane addresses.
+// per-lane addresses.  Called with all 64 lanes of the wave active.
 __device__ __forceinline__ int wave_inclusive_sum(int x) {
     x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
     x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
