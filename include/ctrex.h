@@ -181,7 +181,9 @@ CTREX_API int ctrex_back_project_voxel(ctrex_ctx *ctx, const void *sino, int32_t
 
 /*
  * Bytes of device workspace ctrex_sirt_iterate needs for n_views projections
- * (n_views <= 0 means all) and `flags` (the gather shadows need room).
+ * (n_views <= 0 means all): R and the correction image (one value per ray
+ * each), C (one value per voxel) and per-tile residual partials.  `flags` is
+ * accepted for compatibility and does not change the size.
  */
 CTREX_API int ctrex_sirt_workspace_bytes(const ctrex_ctx *ctx, int32_t n_views, uint32_t flags,
                                size_t *bytes);
@@ -194,14 +196,18 @@ CTREX_API int ctrex_sirt_workspace_bytes(const ctrex_ctx *ctx, int32_t n_views, 
  * place of A^T, and C = 1 / (B 1).
  * `vol` is the device float32 volume (in/out); `sino` the measured data
  * (device, sino_dtype, [n_views][n_v][n_u]).  `workspace` is caller-owned
- * device memory of at least ctrex_sirt_workspace_bytes(); it holds R, C and
- * the intermediates, and R and C are kept there between calls for the same
+ * device memory of at least ctrex_sirt_workspace_bytes(); it holds R, C, the
+ * correction image and residual partials, and R and C are kept there between
+ * calls for the same
  * geometry, motion, view list and workspace (CTREX_RECOMPUTE_WEIGHTS forces
  * a rebuild; the caller must not write the workspace in between, and must
  * pass the flag after reusing freed memory at the same address as a
  * workspace).  The context remembers up to 64 (workspace, view list) pairs,
  * so ordered subsets — one workspace per subset, cycled — keep their
- * weights.  With a
+ * weights.  The volume-sized intermediates (the correction volume, a 16-bit
+ * shadow and the copies of vol the rays gather from: 32 bytes per voxel in
+ * FP32) live in context-owned scratch shared by all workspaces, allocated
+ * (or grown) on first use.  With a
  * BF16/F16 gather flag the rays march a 16-bit shadow of vol, refreshed
  * after every update, while the update itself stays FP32.  The correction
  * image R (sino - A vol) is stored in sino_dtype.  If `resid_norms` (host,
@@ -322,9 +328,10 @@ CTREX_API int ctrex_sirt_workspace_bytes_cyl(const ctrex_ctx *ctx, int32_t n_vie
 /*
  * Eq. (1) on the cylindrical domain: vol <- vol + alpha C B R (sino - A vol)
  * with A, B the cylinder operators above, R = 1 / (A 1), C = 1 / (B 1).
- * Arguments, the workspace and its weight cache, and the residual norms as in
- * ctrex_sirt_iterate; flags CTREX_NONNEG and CTREX_RECOMPUTE_WEIGHTS only
- * (the volume is FP32; no voxel weights).
+ * Arguments, the workspace and its weight cache, the context scratch (here
+ * the correction volume and the packed copy of vol, 20 bytes per voxel) and
+ * the residual norms as in ctrex_sirt_iterate; flags CTREX_NONNEG and
+ * CTREX_RECOMPUTE_WEIGHTS only (the volume is FP32; no voxel weights).
  */
 CTREX_API int ctrex_sirt_iterate_cyl(ctrex_ctx *ctx, float *vol, const void *sino,
                                      int32_t sino_dtype, int32_t n_iter, float alpha,

@@ -215,14 +215,22 @@ struct PhaseTimer {
     }
 };
 
+// The caller's workspace holds what a (workspace, view list) pair keeps:
+// R, the correction image r, C and the residual partials.  The per-call
+// volume-sized intermediates (the correction volume z, a 16-bit shadow and
+// the copies the rays gather from) live in the context's scratch, which all
+// workspaces share, so ordered subsets cost one volume (C) per subset.
 struct SirtLayout {
-    size_t R, r, C, z, shadow, vt, partials, resid, total;
+    size_t R, r, C, partials, resid, total;
 };
 
-SirtLayout sirt_layout(const ctrex_ctx *c, int32_t n_views, uint32_t flags) {
+struct SirtScratch {
+    size_t z, shadow, vt, total;
+};
+
+SirtLayout sirt_layout(const ctrex_ctx *c, int32_t n_views) {
     const size_t rays = static_cast<size_t>(n_views) * c->n_u * c->n_v;
     const size_t vox = static_cast<size_t>(c->nx) * c->ny * c->nz;
-    const bool g16 = (flags & (CTREX_BF16_GATHER | CTREX_F16_GATHER)) != 0;
     const size_t tiles = static_cast<size_t>((c->n_u + TILE_U - 1) / TILE_U) *
                          ((c->n_v + TILE_V - 1) / TILE_V) * n_views;
     SirtLayout l;
@@ -233,16 +241,25 @@ SirtLayout sirt_layout(const ctrex_ctx *c, int32_t n_views, uint32_t flags) {
     off = align_up(off + 4 * rays);
     l.C = off;
     off = align_up(off + 4 * vox);
+    l.partials = off;
+    off = align_up(off + 8 * tiles);
+    l.resid = off;
+    off = align_up(off + 8 * kResidCap);
+    l.total = off;
+    return l;
+}
+
+SirtScratch sirt_scratch(const ctrex_ctx *c, uint32_t flags) {
+    const size_t vox = static_cast<size_t>(c->nx) * c->ny * c->nz;
+    const bool g16 = (flags & (CTREX_BF16_GATHER | CTREX_F16_GATHER)) != 0;
+    SirtScratch l;
+    size_t off = 0;
     l.z = off;
     off = align_up(off + 4 * vox);
     l.shadow = off;
     off = align_up(off + (g16 ? 2 * vox : 0));
     l.vt = off;   // y-fastest copy of the gathered volume, or the two corner-packed copies
     off = align_up(off + (g16 ? 2 * vox : kPackedCorners ? 2 * sizeof(float4) * vox : 4 * vox));
-    l.partials = off;
-    off = align_up(off + 8 * tiles);
-    l.resid = off;
-    off = align_up(off + 8 * kResidCap);
     l.total = off;
     return l;
 }
@@ -601,7 +618,8 @@ int ctrex_sirt_workspace_bytes(const ctrex_ctx *c, int32_t n_views, uint32_t fla
     if (!c || !bytes) return CTREX_EINVAL;
     if (!c->have_geom) return CTREX_ESTATE;
     if (n_views <= 0) n_views = c->n_proj;
-    *bytes = sirt_layout(c, n_views, flags).total;
+    (void)flags;   // the gather flags change only the context's scratch
+    *bytes = sirt_layout(c, n_views).total;
     return CTREX_OK;
 }
 
@@ -632,7 +650,7 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
     if ((st = resolve_views(c, views, n_views, &dv, &nv, s)) != CTREX_OK) return st;
     if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
     if (nv == 0) return fail(c, CTREX_ESHAPE, "empty view subset");
-    const SirtLayout L = sirt_layout(c, nv, flags);
+    const SirtLayout L = sirt_layout(c, nv);
     if (!workspace) return fail(c, CTREX_EWORKSPACE, "workspace is NULL");
     if (workspace_bytes < L.total)
         return fail(c, CTREX_EWORKSPACE, "workspace of %zu bytes < %zu needed", workspace_bytes,
@@ -642,10 +660,14 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
     float *Rw = reinterpret_cast<float *>(ws + L.R);
     void *r = ws + L.r;
     float *Cw = reinterpret_cast<float *>(ws + L.C);
-    float *z = reinterpret_cast<float *>(ws + L.z);
-    void *shadow = ws + L.shadow;
     double *partials = reinterpret_cast<double *>(ws + L.partials);
     double *resid = reinterpret_cast<double *>(ws + L.resid);
+    const SirtScratch SL = sirt_scratch(c, flags);
+    void *scr;
+    if ((st = ctx_scratch(c, SL.total, &scr)) != CTREX_OK) return st;
+    char *sc = static_cast<char *>(scr);
+    float *z = reinterpret_cast<float *>(sc + SL.z);
+    void *shadow = sc + SL.shadow;
     const size_t vox = static_cast<size_t>(c->nx) * c->ny * c->nz;
     const int gdt = (flags & CTREX_BF16_GATHER) ? BF16 : (flags & CTREX_F16_GATHER) ? F16 : F32;
     const int rdt = sino_dtype;  // the correction image takes the data's storage type
@@ -692,7 +714,7 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
         CTREX_HIP(c, launch_convert(vol, F32, shadow, gdt, vox, s));
         gather = shadow;
     }
-    void *vt = ws + L.vt;
+    void *vt = sc + SL.vt;
     const bool packed = kPackedCorners && gdt == F32;
     float4 *p4 = static_cast<float4 *>(vt);
     auto refresh_copies = [&]() -> hipError_t {
@@ -870,8 +892,10 @@ VoxelGrid cyl_voxels(const ctrex_ctx *c) {
     return v;
 }
 
+// As for the Cartesian SIRT: the workspace keeps R, r, C and the partials;
+// the correction volume and the packed copy live in the context's scratch.
 struct CylLayout {
-    size_t R, r, C, z, p4, partials, resid, total;
+    size_t R, r, C, partials, resid, total;
 };
 
 CylLayout cyl_layout(const ctrex_ctx *c, int32_t n_views) {
@@ -887,10 +911,6 @@ CylLayout cyl_layout(const ctrex_ctx *c, int32_t n_views) {
     off = align_up(off + 4 * rays);
     l.C = off;
     off = align_up(off + 4 * vox);
-    l.z = off;
-    off = align_up(off + 4 * vox);
-    l.p4 = off;   // corner-packed copy of the volume
-    off = align_up(off + (kPackedCorners ? sizeof(float4) * vox : 0));
     l.partials = off;
     off = align_up(off + 8 * tiles);
     l.resid = off;
@@ -1106,10 +1126,16 @@ int ctrex_sirt_iterate_cyl(ctrex_ctx *c, float *vol, const void *sino, int32_t s
     float *Rw = reinterpret_cast<float *>(ws + L.R);
     void *r = ws + L.r;
     float *Cw = reinterpret_cast<float *>(ws + L.C);
-    float *z = reinterpret_cast<float *>(ws + L.z);
     double *partials = reinterpret_cast<double *>(ws + L.partials);
     double *resid = reinterpret_cast<double *>(ws + L.resid);
     const size_t vox = static_cast<size_t>(c->cyl_nr) * c->cyl_nphi * c->cyl_nz;
+    // scratch: the correction volume z, then the corner-packed copy
+    const size_t z_bytes = align_up(4 * vox);
+    void *scr;
+    if ((st = ctx_scratch(c, z_bytes + (kPackedCorners ? sizeof(float4) * vox : 0), &scr)) !=
+        CTREX_OK)
+        return st;
+    float *z = static_cast<float *>(scr);
     const RayGrid g = make_grid_cyl(c, dv, nv);
     const CylGrid cg = cyl_of(c);
     const VoxelGrid vg = cyl_voxels(c);
@@ -1142,7 +1168,8 @@ int ctrex_sirt_iterate_cyl(ctrex_ctx *c, float *vol, const void *sino, int32_t s
     std::vector<double> host_norms;
     if (resid_norms) host_norms.reserve(n_iter);
     FpExtra ex{sino, Rw, partials};
-    float4 *p4 = kPackedCorners ? reinterpret_cast<float4 *>(ws + L.p4) : nullptr;
+    float4 *p4 = kPackedCorners ? reinterpret_cast<float4 *>(static_cast<char *>(scr) + z_bytes)
+                                : nullptr;
     ex.p4 = p4;
     for (int32_t k = 0; k < n_iter; ++k) {
         PhaseTimer t_fp{c, s, nullptr, 0}, t_bp{c, s, nullptr, 1}, t_up{c, s, nullptr, 2};
