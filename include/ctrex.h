@@ -136,10 +136,9 @@ CTREX_API int ctrex_set_voxel_weights(ctrex_ctx *ctx, const float *w_dev);
  * vol_dtype and `sino` sino_dtype; the sinogram is overwritten.  With an
  * empty list (n_views == 0) nothing happens and the pointers may be NULL.
  * The rays gather from context-owned copies of `vol` made at the start of
- * the call: for float32, two corner-packed copies (x- and y-fastest, 16 bytes
- * per voxel each: a voxel's four corner values in its z slice); for 16-bit
- * storage, one y-fastest copy.  The results do not depend on which copy a
- * ray reads.
+ * the call: two corner-packed copies (x- and y-fastest; each element holds a
+ * voxel's four corner values in its z slice: 16 bytes for float32, 8 bytes
+ * for 16-bit storage).  The results do not depend on which copy a ray reads.
  */
 CTREX_API int ctrex_forward_project(ctrex_ctx *ctx, const void *vol, int32_t vol_dtype, void *sino,
                           int32_t sino_dtype, const int32_t *views, int32_t n_views,
@@ -206,8 +205,8 @@ CTREX_API int ctrex_sirt_workspace_bytes(const ctrex_ctx *ctx, int32_t n_views, 
  * so ordered subsets — one workspace per subset, cycled — keep their
  * weights.  The volume-sized intermediates (the correction volume, a 16-bit
  * shadow and the copies of vol the rays gather from: 32 bytes per voxel in
- * FP32) live in context-owned scratch shared by all workspaces, allocated
- * (or grown) on first use.  With a
+ * FP32, 16 with a 16-bit gather) live in context-owned scratch shared by all
+ * workspaces, allocated (or grown) on first use.  With a
  * BF16/F16 gather flag the rays march a 16-bit shadow of vol, refreshed
  * after every update, while the update itself stays FP32.  The correction
  * image R (sino - A vol) is stored in sino_dtype.  If `resid_norms` (host,

@@ -31,6 +31,8 @@ constexpr size_t kMaxWeightSets = 64;
 // FP32 volumes are gathered from corner-packed copies (two 16-byte loads per
 // sample instead of four 8-byte ones); 16-bit volumes from the plain copies.
 constexpr bool kPackedCorners = true;
+// The same for 16-bit volumes: two corner-packed copies of 8 bytes per voxel.
+constexpr bool kPacked16 = true;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -258,8 +260,9 @@ SirtScratch sirt_scratch(const ctrex_ctx *c, uint32_t flags) {
     off = align_up(off + 4 * vox);
     l.shadow = off;
     off = align_up(off + (g16 ? 2 * vox : 0));
-    l.vt = off;   // y-fastest copy of the gathered volume, or the two corner-packed copies
-    off = align_up(off + (g16 ? 2 * vox : kPackedCorners ? 2 * sizeof(float4) * vox : 4 * vox));
+    l.vt = off;   // the two corner-packed copies of the gathered volume, or its y-fastest copy
+    off = align_up(off + (g16 ? (kPacked16 ? 2 * sizeof(uint2) * vox : 2 * vox)
+                              : (kPackedCorners ? 2 * sizeof(float4) * vox : 4 * vox)));
     l.total = off;
     return l;
 }
@@ -496,6 +499,15 @@ int ctrex_forward_project(ctrex_ctx *c, const void *vol, int32_t vol_dtype, void
                                          c->ny, c->nz, s));
         ex.p4 = p4;
         ex.p4t = p4 + vox;
+    } else if (kPacked16 && vol_dtype != F32) {
+        // 16-bit corner-packed copies, x- and y-fastest
+        void *pk;
+        if ((st = ctx_scratch(c, 2 * sizeof(uint2) * vox, &pk))) return st;
+        uint2 *p2 = static_cast<uint2 *>(pk);
+        CTREX_HIP(c, launch_pack_corners16(static_cast<const uint16_t *>(vol), p2, p2 + vox,
+                                           c->nx, c->ny, c->nz, s));
+        ex.p2 = p2;
+        ex.p2t = p2 + vox;
     } else {
         // y-fastest copy for the projections whose rays run mainly along x
         void *vt;
@@ -526,7 +538,10 @@ int ctrex_residual_norm(ctrex_ctx *c, const void *vol, int32_t vol_dtype, const 
     const RayGrid g = make_grid(c, dv, nv);
     const size_t vox = static_cast<size_t>(c->nx) * c->ny * c->nz;
     const bool packed = kPackedCorners && vol_dtype == F32;
-    const size_t vt_bytes = align_up(packed ? 2 * sizeof(float4) * vox : dtype_size(vol_dtype) * vox);
+    const bool packed16 = kPacked16 && vol_dtype != F32;
+    const size_t vt_bytes = align_up(packed     ? 2 * sizeof(float4) * vox
+                                     : packed16 ? 2 * sizeof(uint2) * vox
+                                                : dtype_size(vol_dtype) * vox);
     void *scr;
     if ((st = ctx_scratch(c, vt_bytes + sizeof(double) * (static_cast<size_t>(g.total_blocks) + 1),
                           &scr)))
@@ -539,6 +554,12 @@ int ctrex_residual_norm(ctrex_ctx *c, const void *vol, int32_t vol_dtype, const 
                                          c->ny, c->nz, s));
         ex.p4 = p4;
         ex.p4t = p4 + vox;
+    } else if (packed16) {
+        uint2 *p2 = static_cast<uint2 *>(scr);
+        CTREX_HIP(c, launch_pack_corners16(static_cast<const uint16_t *>(vol), p2, p2 + vox,
+                                           c->nx, c->ny, c->nz, s));
+        ex.p2 = p2;
+        ex.p2t = p2 + vox;
     } else {
         CTREX_HIP(c, launch_transpose_xy(vol, scr, vol_dtype, c->nx, c->ny, c->nz, s));
         ex.vol_t = scr;
@@ -716,9 +737,14 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
     }
     void *vt = sc + SL.vt;
     const bool packed = kPackedCorners && gdt == F32;
+    const bool packed16 = kPacked16 && gdt != F32;
     float4 *p4 = static_cast<float4 *>(vt);
+    uint2 *p2 = static_cast<uint2 *>(vt);
     auto refresh_copies = [&]() -> hipError_t {
         if (packed) return launch_pack_corners(vol, p4, p4 + vox, c->nx, c->ny, c->nz, s);
+        if (packed16)
+            return launch_pack_corners16(static_cast<const uint16_t *>(gather), p2, p2 + vox,
+                                         c->nx, c->ny, c->nz, s);
         return launch_transpose_xy(gather, vt, gdt, c->nx, c->ny, c->nz, s);
     };
     CTREX_HIP(c, refresh_copies());
@@ -728,6 +754,9 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
     if (packed) {
         ex.p4 = p4;
         ex.p4t = p4 + vox;
+    } else if (packed16) {
+        ex.p2 = p2;
+        ex.p2t = p2 + vox;
     } else {
         ex.vol_t = vt;
     }

@@ -67,6 +67,10 @@ struct FpExtra {
     // vol and vol_t in the gathers
     const float4 *p4 = nullptr;
     const float4 *p4t = nullptr;
+    // the same for a 16-bit volume: element (x, y, z) = the four 16-bit
+    // corners in the order above, two to a 32-bit word, low half first
+    const uint2 *p2 = nullptr;
+    const uint2 *p2t = nullptr;
 };
 
 // Backprojection modes.
@@ -131,6 +135,9 @@ hipError_t launch_transpose_xy(const void *src, void *dst, int dtype, int nx, in
 // p4 / p4t = the corner-packed copies of FpExtra (either may be null).
 hipError_t launch_pack_corners(const float *vol, float4 *p4, float4 *p4t, int nx, int ny, int nz,
                                hipStream_t s);
+// The same corner-packed copies of a 16-bit volume (BF16 or F16 bits).
+hipError_t launch_pack_corners16(const uint16_t *vol, uint2 *p2, uint2 *p2t, int nx, int ny,
+                                 int nz, hipStream_t s);
 // Corner-packed copy of a polar volume [nz][nphi][nr]: element (k, j, a) holds
 // v(a, j), v(a+1, j), v(a, j+1), v(a+1, j+1) of slice k, the angle periodic.
 hipError_t launch_pack_polar(const float *vol, float4 *p4, int nr, int nphi, int nz,

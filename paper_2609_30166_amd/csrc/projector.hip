@@ -35,13 +35,47 @@ __device__ __forceinline__ float gather_p4(const float4 *__restrict__ p4, const 
     return blend(k, a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w);
 }
 
+// 16-bit volumes: the four corners of a slice are one 8-byte element, two to a
+// 32-bit word (low half first), widened exactly as `ld` widens them.
+__device__ __forceinline__ float widen_lo(bf16_t, uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float widen_hi(bf16_t, uint32_t w) {
+    return __uint_as_float(w & 0xffff0000u);
+}
+__device__ __forceinline__ float widen_lo(_Float16, uint32_t w) {
+    return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(w)));
+}
+__device__ __forceinline__ float widen_hi(_Float16, uint32_t w) {
+    return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(w >> 16)));
+}
+
+template <typename TV>
+__device__ __forceinline__ float gather_p2(const uint2 *__restrict__ p2, const VolDims &d,
+                                           const Corner &k) {
+    const uint2 a = p2[k.base];
+    const uint2 b = p2[k.base + d.nxy];
+    const TV t{};
+    return blend(k, widen_lo(t, a.x), widen_hi(t, a.x), widen_lo(t, a.y), widen_hi(t, a.y),
+                 widen_lo(t, b.x), widen_hi(t, b.x), widen_lo(t, b.y), widen_hi(t, b.y));
+}
+
+// The packed gather for the volume's storage type: float4 elements for FP32,
+// uint2 elements for 16-bit volumes.
+template <typename TV>
+__device__ __forceinline__ float gather_pk(const void *__restrict__ pk, const VolDims &d,
+                                           const Corner &k) {
+    if constexpr (sizeof(TV) == 4)
+        return gather_p4(static_cast<const float4 *>(pk), d, k);
+    else
+        return gather_p2<TV>(static_cast<const uint2 *>(pk), d, k);
+}
+
 // One ray's projection value: the mean over sub-views of the step-weighted
 // trilinear samples.  TL: gather from the y-fastest copy of the volume; PK:
-// from the corner-packed copy `pk` (y-fastest when TL).
+// from the corner-packed copy `pk` (y-fastest when TL; element type by TV).
 template <typename TV, int MODE, bool WARP, bool TL, bool PK>
 __device__ __forceinline__ float march(const RayGrid &g, const WarpGrid &w,
                                        const TV *__restrict__ vol,
-                                       const float4 *__restrict__ pk, const VolDims &d,
+                                       const void *__restrict__ pk, const VolDims &d,
                                        const TileCoord &t) {
     float y = 0.0f;
     for (int s = 0; s < g.n_sub; ++s) {
@@ -75,9 +109,9 @@ __device__ __forceinline__ float march(const RayGrid &g, const WarpGrid &w,
                 } else {
                     float va, vb;
                     if (PK) {
-                        va = gather_p4(pk, d, TL ? corner_of_t(d, an, ax, ay, az)
+                        va = gather_pk<TV>(pk, d, TL ? corner_of_t(d, an, ax, ay, az)
                                                  : corner_of(d, an, ax, ay, az));
-                        vb = gather_p4(pk, d, TL ? corner_of_t(d, an, bx, by, bz)
+                        vb = gather_pk<TV>(pk, d, TL ? corner_of_t(d, an, bx, by, bz)
                                                  : corner_of(d, an, bx, by, bz));
                     } else if (TL) {
                         va = gather_t(vol, d, corner_of_t(d, an, ax, ay, az));
@@ -100,7 +134,7 @@ __device__ __forceinline__ float march(const RayGrid &g, const WarpGrid &w,
                     acc0 += ina ? 1.0f : 0.0f;
                 } else {
                     const float va =
-                        PK ? gather_p4(pk, d, TL ? corner_of_t(d, an, ax, ay, az)
+                        PK ? gather_pk<TV>(pk, d, TL ? corner_of_t(d, an, ax, ay, az)
                                                  : corner_of(d, an, ax, ay, az))
                         : TL ? gather_t(vol, d, corner_of_t(d, an, ax, ay, az))
                              : gather(vol, d, corner_of(d, an, ax, ay, az));
@@ -138,12 +172,17 @@ void fp_kernel(RayGrid g, WarpGrid w,
     const double uc = static_cast<double>((t.iu & ~(TILE_U - 1)) + TILE_U / 2);
     const double vc = static_cast<double>((t.iv & ~(TILE_V - 1)) + TILE_V / 2);
     const bool xm = MODE != FP_RECIP_ONES && x_major(g.tab[t.p * g.n_sub], uc, vc);
-    const bool pk = MODE != FP_RECIP_ONES && ex.p4 != nullptr;
+    // corner-packed copies of the volume's storage type
+    const void *pkx = sizeof(TV) == 4 ? static_cast<const void *>(ex.p4)
+                                      : static_cast<const void *>(ex.p2);
+    const void *pky = sizeof(TV) == 4 ? static_cast<const void *>(ex.p4t)
+                                      : static_cast<const void *>(ex.p2t);
+    const bool pk = MODE != FP_RECIP_ONES && pkx != nullptr;
     float y = 0.0f;
     if (active) {
         if (pk)
-            y = (xm && ex.p4t) ? march<TV, MODE, WARP, true, true>(g, w, vol, ex.p4t, d, t)
-                               : march<TV, MODE, WARP, false, true>(g, w, vol, ex.p4, d, t);
+            y = (xm && pky) ? march<TV, MODE, WARP, true, true>(g, w, vol, pky, d, t)
+                            : march<TV, MODE, WARP, false, true>(g, w, vol, pkx, d, t);
         else
             y = (xm && vt) ? march<TV, MODE, WARP, true, false>(g, w, vt, nullptr, d, t)
                            : march<TV, MODE, WARP, false, false>(g, w, vol, nullptr, d, t);

@@ -173,6 +173,33 @@ __global__ __launch_bounds__(THREADS) void pack_corners_kernel(const float *__re
     }
 }
 
+template <bool XF>
+__global__ __launch_bounds__(THREADS) void pack_corners16_kernel(const uint16_t *__restrict__ v,
+                                                                 uint2 *__restrict__ out, int nx,
+                                                                 int ny, size_t n) {
+    const size_t stride = static_cast<size_t>(gridDim.x) * THREADS;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * THREADS + threadIdx.x; i < n; i += stride) {
+        int x, y;
+        size_t z;
+        if (XF) {
+            x = static_cast<int>(i % nx);
+            const size_t r = i / nx;
+            y = static_cast<int>(r % ny);
+            z = r / ny;
+        } else {
+            y = static_cast<int>(i % ny);
+            const size_t r = i / ny;
+            x = static_cast<int>(r % nx);
+            z = r / nx;
+        }
+        const int x1 = min(x + 1, nx - 1), y1 = min(y + 1, ny - 1);
+        const uint16_t *s = v + z * nx * ny;
+        const uint32_t c00 = s[static_cast<size_t>(y) * nx + x], c10 = s[static_cast<size_t>(y) * nx + x1];
+        const uint32_t c01 = s[static_cast<size_t>(y1) * nx + x], c11 = s[static_cast<size_t>(y1) * nx + x1];
+        out[i] = make_uint2(c00 | (c10 << 16), c01 | (c11 << 16));
+    }
+}
+
 __global__ __launch_bounds__(THREADS) void pack_polar_kernel(const float *__restrict__ v,
                                                              float4 *__restrict__ out, int nr,
                                                              int nphi, size_t n) {
@@ -210,6 +237,19 @@ hipError_t launch_pack_corners(const float *vol, float4 *p4, float4 *p4t, int nx
     if (p4t)
         hipLaunchKernelGGL(pack_corners_kernel<false>, dim3(grid_for(n)), dim3(THREADS), 0, s,
                            vol, p4t, nx, ny, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_corners16(const uint16_t *vol, uint2 *p2, uint2 *p2t, int nx, int ny,
+                                 int nz, hipStream_t s) {
+    const size_t n = static_cast<size_t>(nx) * ny * nz;
+    if (n == 0) return hipSuccess;
+    if (p2)
+        hipLaunchKernelGGL(pack_corners16_kernel<true>, dim3(grid_for(n)), dim3(THREADS), 0, s,
+                           vol, p2, nx, ny, n);
+    if (p2t)
+        hipLaunchKernelGGL(pack_corners16_kernel<false>, dim3(grid_for(n)), dim3(THREADS), 0, s,
+                           vol, p2t, nx, ny, n);
     return hipGetLastError();
 }
 

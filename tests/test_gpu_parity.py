@@ -407,3 +407,21 @@ def test_one_voxel_edge_bricks(dev):
     v_ref, n_ref = oracle.sirt(P, shape, n_u, n_v, b.astype(np.float64), 2)
     assert rel_l2(v.cpu().numpy(), v_ref) <= TOL
     np.testing.assert_allclose(norms, n_ref, rtol=TOL)
+
+
+@pytest.mark.parametrize("dtype", ["bfloat16", "float16"])
+def test_16bit_gather_sirt_first_iteration_exact(tiny, dev, dtype):
+    """SIRT with a 16-bit gather, started from a volume that 16 bits hold
+    exactly: the first iteration's rays see no rounding, so its increment and
+    residual norm equal the FP64 oracle's (FP32 data, FP32 update)."""
+    cfg, x, g, y_ref, _ = tiny
+    dt = getattr(torch, dtype)
+    x0 = torch.from_numpy(0.5 * x).to(dev).to(dt).float()
+    b = y_ref.astype(np.float32)
+    v = x0.clone()
+    norms = g.sirt(v, torch.from_numpy(b).to(dev), 1, gather_dtype=dt)
+    x0d = x0.cpu().numpy().astype(np.float64)
+    v_ref, n_ref = oracle.sirt(cfg.P, cfg.shape, cfg.n_u, cfg.n_v, b.astype(np.float64), 1,
+                               step=cfg.step, x0=x0d)
+    assert rel_l2(v.cpu().numpy() - x0d, v_ref - x0d) <= TOL
+    np.testing.assert_allclose(norms, n_ref, rtol=TOL)
