@@ -194,8 +194,10 @@ __global__ __launch_bounds__(THREADS) void pack_corners16_kernel(const uint16_t 
         }
         const int x1 = min(x + 1, nx - 1), y1 = min(y + 1, ny - 1);
         const uint16_t *s = v + z * nx * ny;
-        const uint32_t c00 = s[static_cast<size_t>(y) * nx + x], c10 = s[static_cast<size_t>(y) * nx + x1];
-        const uint32_t c01 = s[static_cast<size_t>(y1) * nx + x], c11 = s[static_cast<size_t>(y1) * nx + x1];
+        const uint32_t c00 = s[static_cast<size_t>(y) * nx + x],
+                       c10 = s[static_cast<size_t>(y) * nx + x1];
+        const uint32_t c01 = s[static_cast<size_t>(y1) * nx + x],
+                       c11 = s[static_cast<size_t>(y1) * nx + x1];
         out[i] = make_uint2(c00 | (c10 << 16), c01 | (c11 << 16));
     }
 }
