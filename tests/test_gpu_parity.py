@@ -425,3 +425,19 @@ def test_16bit_gather_sirt_first_iteration_exact(tiny, dev, dtype):
                                step=cfg.step, x0=x0d)
     assert rel_l2(v.cpu().numpy() - x0d, v_ref - x0d) <= TOL
     np.testing.assert_allclose(norms, n_ref, rtol=TOL)
+
+
+@pytest.mark.parametrize("dtype", ["bfloat16", "float16"])
+def test_residual_norm_of_a_16bit_volume(tiny, dev, dtype):
+    """||b - A x|| with the volume stored in 16 bits: the rays gather the
+    16-bit values exactly, so the norm equals the oracle's for the rounded
+    volume (relative 1e-5)."""
+    cfg, x, g, y_ref, _ = tiny
+    dt = getattr(torch, dtype)
+    x16 = torch.from_numpy(x).to(dev).to(dt)
+    xr = x16.float().cpu().numpy().astype(np.float64)
+    y_r = oracle.forward(cfg.P, cfg.shape, cfg.n_u, cfg.n_v, xr, cfg.step)
+    b = (y_ref + np.random.default_rng(8).normal(0, 0.3, y_ref.shape)).astype(np.float32)
+    want = float(np.linalg.norm(b.astype(np.float64) - y_r))
+    got = g.residual_norm(x16, torch.from_numpy(b).to(dev))
+    assert abs(got - want) <= TOL * want
