@@ -225,7 +225,8 @@ CTREX_API int ctrex_sirt_iterate(ctrex_ctx *ctx, float *vol, const void *sino, i
  * the listed projections: the data-consistency measure of the SIRT update
  * (Eq. 1) and the acceptance test of a learned correction between
  * iterations (Sec. 5 extension).  `vol` and `sino` are device arrays laid
- * out as in ctrex_forward_project; the projection is not stored.  Residuals
+ * out as in ctrex_forward_project, whose context-owned gather copies it
+ * shares; the projection is not stored.  Residuals
  * are formed in FP32 per detector pixel and squared and summed in FP64 in a
  * fixed order (deterministic).  Writes *norm (host) and waits for `stream`;
  * CTREX_ENONFINITE if the norm is not finite.
