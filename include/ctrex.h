@@ -28,6 +28,12 @@
  *  - Device pointers are HIP device memory owned by the caller; host pointers
  *    are read during the call only.  `stream` is a hipStream_t (NULL = the
  *    null stream).  Launches are asynchronous on that stream unless stated.
+ *  - Buffers: every volume- or sinogram-sized intermediate lives in memory the
+ *    caller provides (Sec. 2.1: the reconstruction control prepares the
+ *    volume buffers): the SIRT workspace argument, and the device scratch
+ *    attached with ctrex_set_scratch and sized by ctrex_scratch_bytes.  The
+ *    context itself keeps only its geometry table, the repacked motion grid,
+ *    device copies of up to 64 recent view lists and a few reduction cells.
  *  - Every entry point returns CTREX_OK or a negative status; the message of
  *    the last failure on a context is returned by ctrex_last_error().
  *    Arguments are validated on the host before anything is launched; a
@@ -79,6 +85,26 @@ typedef struct ctrex_ctx ctrex_ctx;
 
 /* Create a context bound to HIP device `device`. */
 CTREX_API int ctrex_create(ctrex_ctx **out, int device);
+
+/*
+ * Device scratch the projector calls need (Sec. 2.1: buffers are prepared by
+ * the reconstruction control, here the caller).  ctrex_scratch_bytes returns
+ * the bytes the calls of the current geometry (and cylindrical domain, if
+ * set) need for view lists of up to n_views entries (n_views <= 0: n_proj):
+ * the correction volume (4 bytes per voxel), a 16-bit shadow (2), the
+ * copies of the volume the rays gather from (32 for FP32, 16 for 16-bit;
+ * the backprojector's per-chunk partial volumes reuse that region) and the
+ * residual partials (8 per 16x16 detector tile per view).  CTREX_ESTATE
+ * without a geometry.
+ * ctrex_set_scratch attaches `bytes` of device memory at `dev` (NULL, 0
+ * detaches).  The library keeps the pointer: the memory must stay allocated
+ * and must not be written by the caller while calls that use it may run.
+ * Calls that need more scratch than is attached return CTREX_EWORKSPACE
+ * before launching anything; the library never allocates it itself.  The
+ * learned-correction calls of ctrex_nn.h use the same attachment.
+ */
+CTREX_API int ctrex_scratch_bytes(const ctrex_ctx *ctx, int32_t n_views, size_t *bytes);
+CTREX_API int ctrex_set_scratch(ctrex_ctx *ctx, void *dev, size_t bytes);
 
 /* Destroy a context (NULL is accepted).  Waits for the device first. */
 CTREX_API void ctrex_destroy(ctrex_ctx *ctx);
@@ -135,10 +161,11 @@ CTREX_API int ctrex_set_voxel_weights(ctrex_ctx *ctx, const float *w_dev);
  * allowed; NULL selects all projections in order).  `vol` has storage type
  * vol_dtype and `sino` sino_dtype; the sinogram is overwritten.  With an
  * empty list (n_views == 0) nothing happens and the pointers may be NULL.
- * The rays gather from context-owned copies of `vol` made at the start of
- * the call: two corner-packed copies (x- and y-fastest; each element holds a
- * voxel's four corner values in its z slice: 16 bytes for float32, 8 bytes
- * for 16-bit storage).  The results do not depend on which copy a ray reads.
+ * The rays gather from copies of `vol` written into the attached scratch at
+ * the start of the call: two corner-packed copies (x- and y-fastest; each
+ * element holds a voxel's four corner values in its z slice: 16 bytes for
+ * float32, 8 bytes for 16-bit storage).  The results do not depend on which
+ * copy a ray reads.
  */
 CTREX_API int ctrex_forward_project(ctrex_ctx *ctx, const void *vol, int32_t vol_dtype, void *sino,
                           int32_t sino_dtype, const int32_t *views, int32_t n_views,
@@ -151,13 +178,23 @@ CTREX_API int ctrex_forward_project(ctrex_ctx *ctx, const void *vol, int32_t vol
  * (also for an empty view list, where `sino` may be NULL).
  * Contributions are summed as 64-bit fixed-point integers (scale chosen from
  * max |sino| so no sum overflows), so the result is bitwise reproducible
- * from run to run.  Context-owned scratch holds max |sino| and, when the
- * projections are split into several chunks, one float32 partial volume per
- * chunk (summed in a fixed order).
+ * from run to run.  A context cell holds max |sino|; when the projections
+ * are split into several chunks (small volumes), the attached scratch holds
+ * one float32 partial volume per chunk (summed in a fixed order).
  */
 CTREX_API int ctrex_back_project(ctrex_ctx *ctx, const void *sino, int32_t sino_dtype, float *vol,
                        int32_t accumulate, const int32_t *views, int32_t n_views,
                        void *stream);
+
+/*
+ * vol (+)= scale A^T sino: ctrex_back_project with every contribution
+ * multiplied by the finite factor `scale` (inside the fixed-point sums, so
+ * no extra pass over the volume).  The gradient of the data term of Eq. (1),
+ * 2 A^T (A x - b), is ctrex_data_residual's r backprojected with scale 2.
+ */
+CTREX_API int ctrex_back_project_scaled(ctrex_ctx *ctx, const void *sino, int32_t sino_dtype,
+                                        float scale, float *vol, int32_t accumulate,
+                                        const int32_t *views, int32_t n_views, void *stream);
 
 /*
  * Sec. 4.1 (backprojection operator), the paper's voxel-driven form:
@@ -205,8 +242,8 @@ CTREX_API int ctrex_sirt_workspace_bytes(const ctrex_ctx *ctx, int32_t n_views, 
  * so ordered subsets — one workspace per subset, cycled — keep their
  * weights.  The volume-sized intermediates (the correction volume, a 16-bit
  * shadow and the copies of vol the rays gather from: 32 bytes per voxel in
- * FP32, 16 with a 16-bit gather) live in context-owned scratch shared by all
- * workspaces, allocated (or grown) on first use.  With a
+ * FP32, 16 with a 16-bit gather) live in the attached scratch, shared by all
+ * workspaces.  With a
  * BF16/F16 gather flag the rays march a 16-bit shadow of vol, refreshed
  * after every update, while the update itself stays FP32.  The correction
  * image R (sino - A vol) is stored in sino_dtype.  If `resid_norms` (host,
@@ -225,8 +262,8 @@ CTREX_API int ctrex_sirt_iterate(ctrex_ctx *ctx, float *vol, const void *sino, i
  * the listed projections: the data-consistency measure of the SIRT update
  * (Eq. 1) and the acceptance test of a learned correction between
  * iterations (Sec. 5 extension).  `vol` and `sino` are device arrays laid
- * out as in ctrex_forward_project, whose context-owned gather copies it
- * shares; the projection is not stored.  Residuals
+ * out as in ctrex_forward_project; the gather copies and per-tile partials
+ * go to the attached scratch, and the projection is not stored.  Residuals
  * are formed in FP32 per detector pixel and squared and summed in FP64 in a
  * fixed order (deterministic).  Writes *norm (host) and waits for `stream`;
  * CTREX_ENONFINITE if the norm is not finite.
@@ -234,6 +271,23 @@ CTREX_API int ctrex_sirt_iterate(ctrex_ctx *ctx, float *vol, const void *sino, i
 CTREX_API int ctrex_residual_norm(ctrex_ctx *ctx, const void *vol, int32_t vol_dtype,
                                   const void *sino, int32_t sino_dtype, const int32_t *views,
                                   int32_t n_views, double *norm, void *stream);
+
+/*
+ * Data term of Eq. (1) for the differentiable loss ||A vol - b||^2 (the
+ * residual b - A mu of the correction kernel, Sec. 4.1, with the opposite
+ * sign): over the listed projections, r = scale (A vol - b) is stored in
+ * `r` (device, sino_dtype, [n_views][n_v][n_u]; NULL: not stored) and
+ * sum (A vol - b)^2 in `sq_sum` (one device float64; NULL: not computed).
+ * Residuals are formed in FP32 per pixel; their squares are summed in FP64
+ * in a fixed order (deterministic).  `b` has sino_dtype.  Asynchronous (no
+ * host wait).  An empty view list zeroes *sq_sum and stores nothing.  The
+ * gather copies and partials use the attached scratch, as in
+ * ctrex_residual_norm.  At least one of r and sq_sum must be non-NULL.
+ */
+CTREX_API int ctrex_data_residual(ctrex_ctx *ctx, const void *vol, int32_t vol_dtype,
+                                  const void *b, void *r, int32_t sino_dtype, float scale,
+                                  const int32_t *views, int32_t n_views, double *sq_sum,
+                                  void *stream);
 
 /*
  * Exact number of ray samples (trilinear lookups) one forward projection of
@@ -328,7 +382,7 @@ CTREX_API int ctrex_sirt_workspace_bytes_cyl(const ctrex_ctx *ctx, int32_t n_vie
 /*
  * Eq. (1) on the cylindrical domain: vol <- vol + alpha C B R (sino - A vol)
  * with A, B the cylinder operators above, R = 1 / (A 1), C = 1 / (B 1).
- * Arguments, the workspace and its weight cache, the context scratch (here
+ * Arguments, the workspace and its weight cache, the attached scratch (here
  * the correction volume and the packed copy of vol, 20 bytes per voxel) and
  * the residual norms as in ctrex_sirt_iterate; flags CTREX_NONNEG and
  * CTREX_RECOMPUTE_WEIGHTS only (the volume is FP32; no voxel weights).

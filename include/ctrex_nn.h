@@ -29,6 +29,10 @@
  *  - All calls are asynchronous on `stream` (a hipStream_t, NULL = null
  *    stream) unless stated; pointers are device memory owned by the caller;
  *    statuses and ctrex_last_error() as in ctrex.h.
+ *  - The weight-gradient, head-gradient and loss calls keep per-chunk partial
+ *    sums in the device scratch attached to the context with
+ *    ctrex_set_scratch; ctrex_nn_scratch_bytes gives the size one layer
+ *    needs.  The library allocates none itself.
  */
 #ifndef CTREX_NN_H
 #define CTREX_NN_H
@@ -42,6 +46,15 @@ extern "C" {
 #define CTREX_NN_RELU 1u       /* apply max(., 0) in the epilogue */
 #define CTREX_NN_ACCUMULATE 2u /* add into the output instead of overwriting */
 #define CTREX_NN_OUT_F32 4u    /* output tensor is FP32 (default BF16) */
+
+/*
+ * Bytes of attached scratch (ctrex_set_scratch) that the learned-correction
+ * calls need for a layer of cin -> cout channels over n_vox voxels (the
+ * input volume of a weight gradient): the maximum over the weight and bias
+ * gradients of the convolution and the transposed convolution, the head's
+ * gradient and the loss.  A network needs the maximum over its layers.
+ */
+CTREX_API int ctrex_nn_scratch_bytes(int32_t cin, int32_t cout, int64_t n_vox, size_t *bytes);
 
 /*
  * out = act(bias + conv3x3x3(in, w)) over a D x H x W volume (stride 1, zero
@@ -60,8 +73,9 @@ CTREX_API int ctrex_nn_conv3(ctrex_ctx *ctx, const void *in, int32_t in_cs, int3
  * order as the master weights) = sum over voxels of dout[v][co] *
  * in[v + tap][ci]; dbias[co] = sum over voxels of dout[v][co] (NULL skips).
  * Results overwrite dw / dbias; sums are formed in FP32 per chunk of voxels
- * and combined in a fixed order in FP64 (deterministic).  Uses the context's
- * scratch memory (grown on demand, which synchronises the device).
+ * and combined in a fixed order in FP64 (deterministic).  The per-chunk
+ * partial sums go to the scratch attached with ctrex_set_scratch (sized by
+ * ctrex_nn_scratch_bytes; CTREX_EWORKSPACE when too small).
  */
 CTREX_API int ctrex_nn_conv3_wgrad(ctrex_ctx *ctx, const void *in, int32_t in_cs, int32_t in_off,
                                    int32_t cin, const void *dout, int32_t dout_cs,

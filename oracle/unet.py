@@ -14,7 +14,9 @@ network.  The network used here (readings stated with the project's design):
   x + m U(s x) / s with a fixed input scale s (volumes stored per volume
   width are brought to O(1) values) and a per-voxel mask m confining the
   correction (the scanned field of view);
-* the same weights after every one of the unrolled SIRT iterations of Eq. (1);
+* one such network per unrolled stage: the pipeline applies a separate set
+  of weights after each stage's physics iterations of Eq. (1) (this module
+  evaluates one network; the stage loop is not part of the reference);
 * MSE loss to the true volume, Adam.
 
 Tensors are channels-last, [D][H][W][C], as torch float64 CPU tensors.

@@ -58,6 +58,12 @@ def lib():
             "ctrex_set_voxel_weights": (ctypes.c_int, [vp, vp]),
             "ctrex_forward_project": (ctypes.c_int, [vp, vp, i32, vp, i32, ip, i32, vp]),
             "ctrex_back_project": (ctypes.c_int, [vp, vp, i32, vp, i32, ip, i32, vp]),
+            "ctrex_back_project_scaled": (ctypes.c_int, [vp, vp, i32, ctypes.c_float, vp, i32, ip,
+                                                         i32, vp]),
+            "ctrex_scratch_bytes": (ctypes.c_int, [vp, i32, ctypes.POINTER(ctypes.c_size_t)]),
+            "ctrex_set_scratch": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
+            "ctrex_data_residual": (ctypes.c_int, [vp, vp, i32, vp, vp, i32, ctypes.c_float, ip,
+                                                   i32, vp, vp]),
             "ctrex_back_project_voxel": (ctypes.c_int, [vp, vp, i32, vp, i32, ip, i32, vp]),
             "ctrex_set_cylinder": (ctypes.c_int, [vp, i32, i32, i32, ctypes.c_double,
                                                   ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
@@ -82,6 +88,8 @@ def lib():
                                         vp, vp]),
             "ctrex_profile_read": (ctypes.c_int, [vp, dp, ctypes.POINTER(ctypes.c_int64)]),
             # learned-correction kernels (include/ctrex_nn.h)
+            "ctrex_nn_scratch_bytes": (ctypes.c_int, [i32, i32, ctypes.c_int64,
+                                                      ctypes.POINTER(ctypes.c_size_t)]),
             "ctrex_nn_conv3": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, vp, vp, i32, i32, i32,
                                               i32, i32, i32, u32, vp]),
             "ctrex_nn_conv3_wgrad": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, i32, i32, i32,

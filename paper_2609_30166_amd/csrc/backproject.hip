@@ -60,6 +60,7 @@ struct BrickGrid {
     int views_per_chunk;
     int total;            // nbx * nby * nbz * chunks
     int accumulate;       // add into vol (else overwrite; needs chunks == 1)
+    float wscale;         // every contribution is multiplied by this factor
     double cube_samples;  // max samples of one ray inside a side-2 cube
     float *partials;      // [chunks][nx*ny*nz] per-chunk results when chunks > 1
 };
@@ -173,7 +174,8 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
                          uni(static_cast<float>(z0 + ez) + M)};
     const double lod[3] = {lo[0], lo[1], lo[2]}, hid[3] = {hi[0], hi[1], hi[2]};
     const double off[3] = {0.5 * (g.nx - 1), 0.5 * (g.ny - 1), 0.5 * (g.nz - 1)};
-    const float inv_sub = uni(1.0f / static_cast<float>(g.n_sub));
+    // 1 / n_sub and the caller's factor (1 unless scaled; exact when a power of 2)
+    const float inv_sub = uni(bg.wscale / static_cast<float>(g.n_sub));
     const int k_first = chunk * bg.views_per_chunk;
     const int k_end = min(k_first + bg.views_per_chunk, g.n_views);
     const int n_pairs = (k_end - k_first) * g.n_sub;
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
     nrays = 0.0;
     for (int i = 0; i < BP_THREADS / 64; ++i) nrays += red[i];
     const double cmax = ((MODE == BP_ONES) ? 1.0 : static_cast<double>(*rmax)) * g.step *
-                        (1.0 + 1e-5) / g.n_sub;
+                        (1.0 + 1e-5) * fabs(static_cast<double>(bg.wscale)) / g.n_sub;
     const double bound = nrays * bg.cube_samples * cmax;
     const bool bad = !(cmax < __builtin_inf());   // NaN or Inf in the input: propagate NaN
     const bool any = uni(static_cast<int>(bound > 0.0 && !bad)) != 0;
@@ -410,7 +412,7 @@ __global__ __launch_bounds__(256) void sum_chunks_kernel(const float *__restrict
     }
 }
 
-BrickGrid plan_bricks(const RayGrid &g) {
+BrickGrid plan_bricks(const RayGrid &g, int cap_chunks) {
     BrickGrid bg;
     bg.bx = min(BRICK_X, g.nx);
     bg.by = min(BRICK_Y, g.ny);
@@ -423,6 +425,7 @@ BrickGrid plan_bricks(const RayGrid &g) {
     long long want = (2048 + bricks - 1) / bricks;
     const long long max_chunks = (g.n_views + 3) / 4;
     if (want > max_chunks) want = max_chunks;
+    if (cap_chunks > 0 && want > cap_chunks) want = cap_chunks;
     if (want < 1) want = 1;
     bg.views_per_chunk = static_cast<int>((g.n_views + want - 1) / want);
     bg.chunks = (g.n_views + bg.views_per_chunk - 1) / bg.views_per_chunk;
@@ -432,23 +435,25 @@ BrickGrid plan_bricks(const RayGrid &g) {
     bg.cube_samples = floor(4.0 * 1.7320508075688772 / g.step) + 1.0;
     bg.partials = nullptr;
     bg.accumulate = 0;
+    bg.wscale = 1.0f;
     return bg;
 }
 
 }  // namespace
 
-size_t back_scratch_bytes(const RayGrid &g) {
+size_t back_scratch_bytes(const RayGrid &g, int max_chunks) {
     if (g.n_views <= 0) return 0;
-    const BrickGrid bg = plan_bricks(g);
+    const BrickGrid bg = plan_bricks(g, max_chunks);
     return bg.chunks > 1 ? sizeof(float) * static_cast<size_t>(bg.chunks) * g.nx * g.ny * g.nz : 0;
 }
 
 hipError_t launch_back(const RayGrid &g, const WarpGrid &w, const double *Pmat, const void *sino,
                        int sino_dtype, float *vol, int accumulate, int mode, float *scratch,
-                       float *part, hipStream_t stream) {
+                       float *part, hipStream_t stream, float scale, int max_chunks) {
     if (g.n_views <= 0) return hipSuccess;
-    BrickGrid bg = plan_bricks(g);
+    BrickGrid bg = plan_bricks(g, max_chunks);
     bg.accumulate = accumulate;
+    bg.wscale = scale;
     bg.partials = part;
     if (bg.chunks > 1 && !part) return hipErrorInvalidValue;
     const int per = (bg.total + N_XCD - 1) / N_XCD;

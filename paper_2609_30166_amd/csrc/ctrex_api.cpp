@@ -2,8 +2,10 @@
 //
 // Owns the per-context device geometry table (FP64 source + inverse matrix
 // per sub-view), the repacked motion grid, device copies of view lists and a
-// small counter; every other buffer is the caller's.  Validation happens
-// before any launch, so a failing call leaves the device untouched.
+// few fixed-size reduction cells; every volume- or sinogram-sized buffer is
+// the caller's (the workspace of the SIRT calls and the scratch attached with
+// ctrex_set_scratch).  Validation happens before any launch, so a failing call
+// leaves the device untouched.
 
 #include "../../include/ctrex.h"
 
@@ -101,39 +103,17 @@ int resolve_views(ctrex_ctx *c, const int32_t *views, int32_t n_views, const int
 }  // namespace
 
 int ctrex::ctx_scratch(ctrex_ctx *c, size_t bytes, void **out) {
-    if (bytes > c->scratch_cap) {
-        if (c->d_scratch) {
-            CTREX_HIP(c, hipDeviceSynchronize());
-            CTREX_HIP(c, hipFree(c->d_scratch));
-            c->d_scratch = nullptr;
-            c->scratch_cap = 0;
-        }
-        CTREX_HIP(c, hipMalloc(&c->d_scratch, bytes));
-        c->scratch_cap = bytes;
-    }
-    *out = c->d_scratch;
+    *out = c->user_scratch;
+    if (bytes == 0) return CTREX_OK;
+    if (!c->user_scratch || c->user_scratch_bytes < bytes)
+        return fail(c, CTREX_EWORKSPACE,
+                    "this call needs %zu bytes of device scratch, %zu attached "
+                    "(ctrex_set_scratch; size from ctrex_scratch_bytes)",
+                    bytes, c->user_scratch_bytes);
     return CTREX_OK;
 }
 
 namespace {
-
-// Grow the context's backprojection slab buffer to what `g` needs.  The
-// device is synchronised before an old buffer is released.
-int ensure_part(ctrex_ctx *c, const RayGrid &g, float **out) {
-    const size_t need = back_scratch_bytes(g);
-    if (need > c->part_cap) {
-        if (c->d_part) {
-            CTREX_HIP(c, hipDeviceSynchronize());
-            CTREX_HIP(c, hipFree(c->d_part));
-            c->d_part = nullptr;
-            c->part_cap = 0;
-        }
-        CTREX_HIP(c, hipMalloc(&c->d_part, need));
-        c->part_cap = need;
-    }
-    *out = c->d_part;
-    return CTREX_OK;
-}
 
 RayGrid make_grid(const ctrex_ctx *c, const int32_t *dev_views, int32_t n_views) {
     RayGrid g;
@@ -220,14 +200,21 @@ struct PhaseTimer {
 // The caller's workspace holds what a (workspace, view list) pair keeps:
 // R, the correction image r, C and the residual partials.  The per-call
 // volume-sized intermediates (the correction volume z, a 16-bit shadow and
-// the copies the rays gather from) live in the context's scratch, which all
-// workspaces share, so ordered subsets cost one volume (C) per subset.
+// the copies the rays gather from) live in the scratch the caller attaches
+// (ctrex_set_scratch), which all workspaces share, so ordered subsets cost
+// one volume (C) per subset.
 struct SirtLayout {
     size_t R, r, C, partials, resid, total;
 };
 
-struct SirtScratch {
-    size_t z, shadow, vt, total;
+// The caller's scratch (ctrex_set_scratch), as the Cartesian projector calls
+// use it: the correction volume z, a 16-bit shadow, one region shared by the
+// gather copies of the forward projector (FP32: two corner-packed copies of
+// 16 bytes per voxel; 16-bit: 8 bytes each) and the backprojector's
+// per-chunk partial volumes (never live at the same time), and the residual
+// partials.  Each call needs the prefix up to the last region it uses.
+struct ProjScratch {
+    size_t z, shadow, shared, partials, total;
 };
 
 SirtLayout sirt_layout(const ctrex_ctx *c, int32_t n_views) {
@@ -251,19 +238,70 @@ SirtLayout sirt_layout(const ctrex_ctx *c, int32_t n_views) {
     return l;
 }
 
-SirtScratch sirt_scratch(const ctrex_ctx *c, uint32_t flags) {
+size_t packed_bytes(const ctrex_ctx *c, int vol_dtype) {
     const size_t vox = static_cast<size_t>(c->nx) * c->ny * c->nz;
-    const bool g16 = (flags & (CTREX_BF16_GATHER | CTREX_F16_GATHER)) != 0;
-    SirtScratch l;
+    if (vol_dtype == F32) return kPackedCorners ? 2 * sizeof(float4) * vox : 4 * vox;
+    return kPacked16 ? 2 * sizeof(uint2) * vox : 2 * vox;
+}
+
+ProjScratch proj_scratch(const ctrex_ctx *c, int32_t n_views) {
+    const size_t vox = static_cast<size_t>(c->nx) * c->ny * c->nz;
+    const size_t tiles = static_cast<size_t>((c->n_u + TILE_U - 1) / TILE_U) *
+                         ((c->n_v + TILE_V - 1) / TILE_V) * static_cast<size_t>(n_views);
+    const size_t slabs = n_views > 0 ? back_scratch_bytes(make_grid(c, nullptr, n_views)) : 0;
+    ProjScratch l;
     size_t off = 0;
     l.z = off;
     off = align_up(off + 4 * vox);
     l.shadow = off;
-    off = align_up(off + (g16 ? 2 * vox : 0));
-    l.vt = off;   // the two corner-packed copies of the gathered volume, or its y-fastest copy
-    off = align_up(off + (g16 ? (kPacked16 ? 2 * sizeof(uint2) * vox : 2 * vox)
-                              : (kPackedCorners ? 2 * sizeof(float4) * vox : 4 * vox)));
+    off = align_up(off + 2 * vox);
+    l.shared = off;
+    off = align_up(off + std::max(packed_bytes(c, F32), slabs));
+    l.partials = off;
+    off = align_up(off + 8 * (tiles + 1));
     l.total = off;
+    return l;
+}
+
+// The cylindrical domain's calls: the correction volume, then the
+// corner-packed copy of the polar volume (16 bytes per voxel).
+struct CylScratch {
+    size_t z, packed, total;
+};
+
+// Write the copies of `vol` the rays gather from into `dst` (the shared
+// region of the scratch) and point `ex` at them.
+int make_gather_copies(ctrex_ctx *c, const void *vol, int vol_dtype, void *dst, FpExtra &ex,
+                       hipStream_t s) {
+    const size_t vox = static_cast<size_t>(c->nx) * c->ny * c->nz;
+    if (kPackedCorners && vol_dtype == F32) {
+        // corner-packed copies, x- and y-fastest
+        float4 *p4 = static_cast<float4 *>(dst);
+        CTREX_HIP(c, launch_pack_corners(static_cast<const float *>(vol), p4, p4 + vox, c->nx,
+                                         c->ny, c->nz, s));
+        ex.p4 = p4;
+        ex.p4t = p4 + vox;
+    } else if (kPacked16 && vol_dtype != F32) {
+        // 16-bit corner-packed copies, x- and y-fastest
+        uint2 *p2 = static_cast<uint2 *>(dst);
+        CTREX_HIP(c, launch_pack_corners16(static_cast<const uint16_t *>(vol), p2, p2 + vox,
+                                           c->nx, c->ny, c->nz, s));
+        ex.p2 = p2;
+        ex.p2t = p2 + vox;
+    } else {
+        // y-fastest copy for the projections whose rays run mainly along x
+        CTREX_HIP(c, launch_transpose_xy(vol, dst, vol_dtype, c->nx, c->ny, c->nz, s));
+        ex.vol_t = dst;
+    }
+    return CTREX_OK;
+}
+
+CylScratch cyl_scratch(const ctrex_ctx *c) {
+    const size_t vox = static_cast<size_t>(c->cyl_nr) * c->cyl_nphi * c->cyl_nz;
+    CylScratch l;
+    l.z = 0;
+    l.packed = align_up(4 * vox);
+    l.total = align_up(l.packed + (kPackedCorners ? sizeof(float4) * vox : 0));
     return l;
 }
 
@@ -307,9 +345,7 @@ void ctrex_destroy(ctrex_ctx *c) {
     if (c->d_U) (void)hipFree(c->d_U);
     if (c->d_count) (void)hipFree(c->d_count);
     if (c->d_scalar) (void)hipFree(c->d_scalar);
-    if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_red) (void)hipFree(c->d_red);
-    if (c->d_scratch) (void)hipFree(c->d_scratch);
     for (auto &l : c->lists) (void)hipFree(l.dev);
     delete c;
 }
@@ -488,33 +524,12 @@ int ctrex_forward_project(ctrex_ctx *c, const void *vol, int32_t vol_dtype, void
     if (!vol || !sino) return fail(c, CTREX_EINVAL, "vol and sino must be device pointers");
     if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
     const RayGrid g = make_grid(c, dv, nv);
+    const ProjScratch SL = proj_scratch(c, nv);
+    void *scr;
+    if ((st = ctx_scratch(c, SL.shared + packed_bytes(c, vol_dtype), &scr))) return st;
     FpExtra ex{nullptr, nullptr, nullptr};
-    const size_t vox = static_cast<size_t>(c->nx) * c->ny * c->nz;
-    if (kPackedCorners && vol_dtype == F32) {
-        // corner-packed copies, x- and y-fastest
-        void *pk;
-        if ((st = ctx_scratch(c, 2 * sizeof(float4) * vox, &pk))) return st;
-        float4 *p4 = static_cast<float4 *>(pk);
-        CTREX_HIP(c, launch_pack_corners(static_cast<const float *>(vol), p4, p4 + vox, c->nx,
-                                         c->ny, c->nz, s));
-        ex.p4 = p4;
-        ex.p4t = p4 + vox;
-    } else if (kPacked16 && vol_dtype != F32) {
-        // 16-bit corner-packed copies, x- and y-fastest
-        void *pk;
-        if ((st = ctx_scratch(c, 2 * sizeof(uint2) * vox, &pk))) return st;
-        uint2 *p2 = static_cast<uint2 *>(pk);
-        CTREX_HIP(c, launch_pack_corners16(static_cast<const uint16_t *>(vol), p2, p2 + vox,
-                                           c->nx, c->ny, c->nz, s));
-        ex.p2 = p2;
-        ex.p2t = p2 + vox;
-    } else {
-        // y-fastest copy for the projections whose rays run mainly along x
-        void *vt;
-        if ((st = ctx_scratch(c, dtype_size(vol_dtype) * vox, &vt))) return st;
-        CTREX_HIP(c, launch_transpose_xy(vol, vt, vol_dtype, c->nx, c->ny, c->nz, s));
-        ex.vol_t = vt;
-    }
+    if ((st = make_gather_copies(c, vol, vol_dtype, static_cast<char *>(scr) + SL.shared, ex, s)))
+        return st;
     CTREX_HIP(c, launch_forward(g, make_warp(c), vol, vol_dtype, sino, sino_dtype, FP_PLAIN, ex, s));
     return CTREX_OK;
 }
@@ -536,34 +551,13 @@ int ctrex_residual_norm(ctrex_ctx *c, const void *vol, int32_t vol_dtype, const 
     if (!vol || !sino) return fail(c, CTREX_EINVAL, "vol and sino must be device pointers");
     if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
     const RayGrid g = make_grid(c, dv, nv);
-    const size_t vox = static_cast<size_t>(c->nx) * c->ny * c->nz;
-    const bool packed = kPackedCorners && vol_dtype == F32;
-    const bool packed16 = kPacked16 && vol_dtype != F32;
-    const size_t vt_bytes = align_up(packed     ? 2 * sizeof(float4) * vox
-                                     : packed16 ? 2 * sizeof(uint2) * vox
-                                                : dtype_size(vol_dtype) * vox);
+    const ProjScratch SL = proj_scratch(c, nv);
     void *scr;
-    if ((st = ctx_scratch(c, vt_bytes + sizeof(double) * (static_cast<size_t>(g.total_blocks) + 1),
-                          &scr)))
-        return st;
-    double *part = reinterpret_cast<double *>(static_cast<char *>(scr) + vt_bytes);
+    if ((st = ctx_scratch(c, SL.total, &scr))) return st;
+    double *part = reinterpret_cast<double *>(static_cast<char *>(scr) + SL.partials);
     FpExtra ex{sino, nullptr, part};
-    if (packed) {
-        float4 *p4 = static_cast<float4 *>(scr);
-        CTREX_HIP(c, launch_pack_corners(static_cast<const float *>(vol), p4, p4 + vox, c->nx,
-                                         c->ny, c->nz, s));
-        ex.p4 = p4;
-        ex.p4t = p4 + vox;
-    } else if (packed16) {
-        uint2 *p2 = static_cast<uint2 *>(scr);
-        CTREX_HIP(c, launch_pack_corners16(static_cast<const uint16_t *>(vol), p2, p2 + vox,
-                                           c->nx, c->ny, c->nz, s));
-        ex.p2 = p2;
-        ex.p2t = p2 + vox;
-    } else {
-        CTREX_HIP(c, launch_transpose_xy(vol, scr, vol_dtype, c->nx, c->ny, c->nz, s));
-        ex.vol_t = scr;
-    }
+    if ((st = make_gather_copies(c, vol, vol_dtype, static_cast<char *>(scr) + SL.shared, ex, s)))
+        return st;
     // `out` is unused in this mode; the sinogram's storage type selects the kernel
     CTREX_HIP(c, launch_forward(g, make_warp(c), vol, vol_dtype, nullptr, sino_dtype, FP_RESIDUAL,
                                 ex, s));
@@ -576,12 +570,19 @@ int ctrex_residual_norm(ctrex_ctx *c, const void *vol, int32_t vol_dtype, const 
     return CTREX_OK;
 }
 
-int ctrex_back_project(ctrex_ctx *c, const void *sino, int32_t sino_dtype, float *vol,
-                       int32_t accumulate, const int32_t *views, int32_t n_views, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// vol (+)= scale A^T sino: ctrex_back_project and ctrex_back_project_scaled.
+int back_project_common(ctrex_ctx *c, const void *sino, int32_t sino_dtype, float scale,
+                        float *vol, int32_t accumulate, const int32_t *views, int32_t n_views,
+                        void *stream) {
     int st = check_ready(c);
     if (st != CTREX_OK) return st;
     if (!vol) return fail(c, CTREX_EINVAL, "vol must be a device pointer");
     if (!valid_dtype(sino_dtype)) return fail(c, CTREX_EINVAL, "unknown dtype %d", sino_dtype);
+    if (!std::isfinite(scale)) return fail(c, CTREX_EINVAL, "scale must be finite");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int32_t *dv;
     int32_t nv;
@@ -594,11 +595,31 @@ int ctrex_back_project(ctrex_ctx *c, const void *sino, int32_t sino_dtype, float
         return CTREX_OK;
     }
     const RayGrid g = make_grid(c, dv, nv);
-    float *part = nullptr;
-    if ((st = ensure_part(c, g, &part)) != CTREX_OK) return st;
+    const ProjScratch SL = proj_scratch(c, nv);
+    const size_t slabs = back_scratch_bytes(g);
+    void *scr = nullptr;
+    if (slabs && (st = ctx_scratch(c, SL.shared + slabs, &scr))) return st;
+    float *part = slabs ? reinterpret_cast<float *>(static_cast<char *>(scr) + SL.shared) : nullptr;
     CTREX_HIP(c, launch_back(g, make_warp(c), c->d_P, sino, sino_dtype, vol, accumulate ? 1 : 0,
-                             BP_PLAIN, c->d_scalar, part, s));
+                             BP_PLAIN, c->d_scalar, part, s, scale));
     return CTREX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ctrex_back_project(ctrex_ctx *c, const void *sino, int32_t sino_dtype, float *vol,
+                       int32_t accumulate, const int32_t *views, int32_t n_views, void *stream) {
+    return back_project_common(c, sino, sino_dtype, 1.0f, vol, accumulate, views, n_views,
+                               stream);
+}
+
+int ctrex_back_project_scaled(ctrex_ctx *c, const void *sino, int32_t sino_dtype, float scale,
+                              float *vol, int32_t accumulate, const int32_t *views,
+                              int32_t n_views, void *stream) {
+    return back_project_common(c, sino, sino_dtype, scale, vol, accumulate, views, n_views,
+                               stream);
 }
 
 // Detector sizes the voxel-driven backprojector's bilinear lookups support
@@ -683,19 +704,23 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
     float *Cw = reinterpret_cast<float *>(ws + L.C);
     double *partials = reinterpret_cast<double *>(ws + L.partials);
     double *resid = reinterpret_cast<double *>(ws + L.resid);
-    const SirtScratch SL = sirt_scratch(c, flags);
+    const int gdt = (flags & CTREX_BF16_GATHER) ? BF16 : (flags & CTREX_F16_GATHER) ? F16 : F32;
+    const RayGrid g = make_grid(c, dv, nv);
+    // scratch: z, the 16-bit shadow, and the gather copies, whose region the
+    // backprojector's partial volumes reuse (the copies are rebuilt after the
+    // update that follows it)
+    const ProjScratch SL = proj_scratch(c, nv);
+    const size_t slabs = back_scratch_bytes(g);
     void *scr;
-    if ((st = ctx_scratch(c, SL.total, &scr)) != CTREX_OK) return st;
+    if ((st = ctx_scratch(c, SL.shared + std::max(packed_bytes(c, gdt), slabs), &scr)) != CTREX_OK)
+        return st;
     char *sc = static_cast<char *>(scr);
     float *z = reinterpret_cast<float *>(sc + SL.z);
     void *shadow = sc + SL.shadow;
     const size_t vox = static_cast<size_t>(c->nx) * c->ny * c->nz;
-    const int gdt = (flags & CTREX_BF16_GATHER) ? BF16 : (flags & CTREX_F16_GATHER) ? F16 : F32;
     const int rdt = sino_dtype;  // the correction image takes the data's storage type
-    const RayGrid g = make_grid(c, dv, nv);
     const WarpGrid w = make_warp(c);
-    float *part = nullptr;
-    if ((st = ensure_part(c, g, &part)) != CTREX_OK) return st;
+    float *part = slabs ? reinterpret_cast<float *>(sc + SL.shared) : nullptr;
 
     // R and C for this geometry / motion / subset / workspace, kept between calls.
     auto same_key = [&](const ctrex_ctx::WeightKey &e) {
@@ -735,7 +760,7 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
         CTREX_HIP(c, launch_convert(vol, F32, shadow, gdt, vox, s));
         gather = shadow;
     }
-    void *vt = sc + SL.vt;
+    void *vt = sc + SL.shared;
     const bool packed = kPackedCorners && gdt == F32;
     const bool packed16 = kPacked16 && gdt != F32;
     float4 *p4 = static_cast<float4 *>(vt);
@@ -885,6 +910,59 @@ int ctrex_convert(ctrex_ctx *c, const void *src, int32_t src_dtype, void *dst, i
     return CTREX_OK;
 }
 
+int ctrex_scratch_bytes(const ctrex_ctx *c, int32_t n_views, size_t *bytes) {
+    if (!c || !bytes) return CTREX_EINVAL;
+    if (!c->have_geom) return CTREX_ESTATE;
+    if (n_views <= 0) n_views = c->n_proj;
+    size_t need = proj_scratch(c, n_views).total;
+    if (c->have_cyl) need = std::max(need, cyl_scratch(c).total);
+    *bytes = need;
+    return CTREX_OK;
+}
+
+int ctrex_set_scratch(ctrex_ctx *c, void *dev, size_t bytes) {
+    if (!c) return CTREX_EINVAL;
+    if (!dev && bytes) return fail(c, CTREX_EINVAL, "NULL scratch with a non-zero size");
+    c->user_scratch = bytes ? dev : nullptr;
+    c->user_scratch_bytes = dev ? bytes : 0;
+    return CTREX_OK;
+}
+
+int ctrex_data_residual(ctrex_ctx *c, const void *vol, int32_t vol_dtype, const void *b, void *r,
+                        int32_t sino_dtype, float scale, const int32_t *views, int32_t n_views,
+                        double *sq_sum, void *stream) {
+    int st = check_ready(c);
+    if (st != CTREX_OK) return st;
+    if (!valid_dtype(vol_dtype) || !valid_dtype(sino_dtype))
+        return fail(c, CTREX_EINVAL, "unknown dtype (%d, %d)", vol_dtype, sino_dtype);
+    if (!r && !sq_sum) return fail(c, CTREX_EINVAL, "neither r nor sq_sum requested");
+    if (!std::isfinite(scale)) return fail(c, CTREX_EINVAL, "scale must be finite");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t *dv;
+    int32_t nv;
+    if ((st = resolve_views(c, views, n_views, &dv, &nv, s)) != CTREX_OK) return st;
+    if (nv == 0) {
+        if (sq_sum) CTREX_HIP(c, launch_fill_zero(sq_sum, sizeof(double), s));
+        return CTREX_OK;
+    }
+    if (!vol || !b) return fail(c, CTREX_EINVAL, "vol and b must be device pointers");
+    if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
+    const RayGrid g = make_grid(c, dv, nv);
+    const ProjScratch SL = proj_scratch(c, nv);
+    void *scr;
+    if ((st = ctx_scratch(c, SL.total, &scr))) return st;
+    double *part = reinterpret_cast<double *>(static_cast<char *>(scr) + SL.partials);
+    // the correction epilogue without R stores rscale (b - A vol) = scale (A vol - b)
+    FpExtra ex{b, nullptr, part};
+    ex.rscale = -scale;
+    if ((st = make_gather_copies(c, vol, vol_dtype, static_cast<char *>(scr) + SL.shared, ex, s)))
+        return st;
+    CTREX_HIP(c, launch_forward(g, make_warp(c), vol, vol_dtype, r, sino_dtype,
+                                r ? FP_CORRECT : FP_RESIDUAL, ex, s));
+    if (sq_sum) CTREX_HIP(c, launch_sum_partials(part, g.total_blocks, sq_sum, s));
+    return CTREX_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------ aligned cylindrical domain --
@@ -922,7 +1000,7 @@ VoxelGrid cyl_voxels(const ctrex_ctx *c) {
 }
 
 // As for the Cartesian SIRT: the workspace keeps R, r, C and the partials;
-// the correction volume and the packed copy live in the context's scratch.
+// the correction volume and the packed copy live in the attached scratch.
 struct CylLayout {
     size_t R, r, C, partials, resid, total;
 };
@@ -1059,12 +1137,13 @@ int ctrex_forward_project_cyl(ctrex_ctx *c, const void *vol, int32_t vol_dtype, 
     if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
     FpExtra ex{nullptr, nullptr, nullptr};
     if (kPackedCorners && vol_dtype == F32) {
-        void *pk;
-        const size_t vox = static_cast<size_t>(c->cyl_nr) * c->cyl_nphi * c->cyl_nz;
-        if ((st = ctx_scratch(c, sizeof(float4) * vox, &pk))) return st;
-        CTREX_HIP(c, launch_pack_polar(static_cast<const float *>(vol), static_cast<float4 *>(pk),
-                                       c->cyl_nr, c->cyl_nphi, c->cyl_nz, s));
-        ex.p4 = static_cast<const float4 *>(pk);
+        const CylScratch CL = cyl_scratch(c);
+        void *scr;
+        if ((st = ctx_scratch(c, CL.total, &scr))) return st;
+        float4 *pk = reinterpret_cast<float4 *>(static_cast<char *>(scr) + CL.packed);
+        CTREX_HIP(c, launch_pack_polar(static_cast<const float *>(vol), pk, c->cyl_nr, c->cyl_nphi,
+                                       c->cyl_nz, s));
+        ex.p4 = pk;
     }
     CTREX_HIP(c, launch_forward_cyl(make_grid_cyl(c, dv, nv), cyl_of(c), vol, vol_dtype, sino,
                                     sino_dtype, FP_PLAIN, ex, s));
@@ -1159,12 +1238,10 @@ int ctrex_sirt_iterate_cyl(ctrex_ctx *c, float *vol, const void *sino, int32_t s
     double *resid = reinterpret_cast<double *>(ws + L.resid);
     const size_t vox = static_cast<size_t>(c->cyl_nr) * c->cyl_nphi * c->cyl_nz;
     // scratch: the correction volume z, then the corner-packed copy
-    const size_t z_bytes = align_up(4 * vox);
+    const CylScratch CL = cyl_scratch(c);
     void *scr;
-    if ((st = ctx_scratch(c, z_bytes + (kPackedCorners ? sizeof(float4) * vox : 0), &scr)) !=
-        CTREX_OK)
-        return st;
-    float *z = static_cast<float *>(scr);
+    if ((st = ctx_scratch(c, CL.total, &scr)) != CTREX_OK) return st;
+    float *z = reinterpret_cast<float *>(static_cast<char *>(scr) + CL.z);
     const RayGrid g = make_grid_cyl(c, dv, nv);
     const CylGrid cg = cyl_of(c);
     const VoxelGrid vg = cyl_voxels(c);
@@ -1197,7 +1274,7 @@ int ctrex_sirt_iterate_cyl(ctrex_ctx *c, float *vol, const void *sino, int32_t s
     std::vector<double> host_norms;
     if (resid_norms) host_norms.reserve(n_iter);
     FpExtra ex{sino, Rw, partials};
-    float4 *p4 = kPackedCorners ? reinterpret_cast<float4 *>(static_cast<char *>(scr) + z_bytes)
+    float4 *p4 = kPackedCorners ? reinterpret_cast<float4 *>(static_cast<char *>(scr) + CL.packed)
                                 : nullptr;
     ex.p4 = p4;
     for (int32_t k = 0; k < n_iter; ++k) {

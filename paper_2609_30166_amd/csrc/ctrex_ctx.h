@@ -46,14 +46,14 @@ struct ctrex_ctx {
     int warp_margin = 0;  // ceil(max |tau| * max |U component|)
     // cached device view lists (most recent first)
     std::list<ctrex::DeviceViewList> lists;
-    // small device scratch
+    // small fixed-size device scratch, allocated by ctrex_create
     unsigned long long *d_count = nullptr;
     float *d_scalar = nullptr;  // max |r| of the backprojector's input
-    float *d_part = nullptr;    // per-chunk backprojection slabs (small volumes)
     double *d_red = nullptr;    // 8192 block partials + 1 result (TV value)
-    void *d_scratch = nullptr;  // general scratch (learned-correction kernels)
-    size_t scratch_cap = 0;
-    size_t part_cap = 0;
+    // caller-owned device scratch for the per-call volume-sized intermediates
+    // (ctrex_set_scratch); the library never allocates these itself
+    void *user_scratch = nullptr;
+    size_t user_scratch_bytes = 0;
     // SIRT weight cache: which workspaces hold valid R and C for which
     // (geometry generation, view list, backprojector); most recent first, a few entries so
     // ordered subsets (one workspace each) keep their weights
@@ -88,8 +88,8 @@ inline int hip_fail(ctrex_ctx *c, hipError_t e, const char *what) {
     return fail(c, CTREX_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Grow the context's general scratch buffer to `bytes` (synchronises the
-// device when an old buffer has to be released).
+// The caller's scratch attached with ctrex_set_scratch, if it holds at least
+// `bytes`; otherwise CTREX_EWORKSPACE naming the size needed.
 int ctx_scratch(ctrex_ctx *c, size_t bytes, void **out);
 
 }  // namespace ctrex

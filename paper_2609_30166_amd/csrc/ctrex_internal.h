@@ -58,8 +58,9 @@ enum FpMode : int {
 
 struct FpExtra {
     const void *b;       // measured sinogram (FP_CORRECT, FP_RESIDUAL), storage type = out type
-    const float *R;      // detector weights (FP_CORRECT)
+    const float *R;      // detector weights (FP_CORRECT); nullptr: the constant rscale
     double *partials;    // [total_blocks] (FP_CORRECT, FP_RESIDUAL)
+    float rscale = 1.0f; // FP_CORRECT without R: out = rscale (b - A vol)
     const void *vol_t = nullptr;  // optional y-fastest copy [nz][nx][ny] of the volume
     // optional corner-packed copies of an FP32 volume (element (x, y, z) = the
     // four corners v(x, y), v(x+1, y), v(x, y+1), v(x+1, y+1) of slice z):
@@ -83,13 +84,15 @@ enum BpMode : int {
 hipError_t launch_forward(const RayGrid &g, const WarpGrid &w, const void *vol, int vol_dtype,
                           void *out, int out_dtype, int mode, const FpExtra &ex,
                           hipStream_t stream);
-// vol (+)= A^T sino; `Pmat` holds the view matrices [n_proj * n_sub][12] on the
-// device.  accumulate == 0 overwrites vol.  `scratch` is one device float;
-// `part` holds back_scratch_bytes(g) bytes (may be null when that is 0).
+// vol (+)= scale A^T sino; `Pmat` holds the view matrices [n_proj * n_sub][12]
+// on the device.  accumulate == 0 overwrites vol.  `scratch` is one device
+// float; `part` holds back_scratch_bytes(g, max_chunks) bytes (may be null
+// when that is 0).  max_chunks > 0 caps the number of projection chunks that
+// write separate partial volumes (fewer, larger chunks; 0 = no cap).
 hipError_t launch_back(const RayGrid &g, const WarpGrid &w, const double *Pmat, const void *sino,
                        int sino_dtype, float *vol, int accumulate, int mode, float *scratch,
-                       float *part, hipStream_t stream);
-size_t back_scratch_bytes(const RayGrid &g);
+                       float *part, hipStream_t stream, float scale = 1.0f, int max_chunks = 0);
+size_t back_scratch_bytes(const RayGrid &g, int max_chunks = 0);
 // Where the voxel-driven backprojector's voxel centres sit: the Cartesian
 // grid of the RayGrid (cyl == 0), or the polar grid of the cylindrical domain
 // (cyl != 0: g.nx = n_r rings at (i + 1/2) dr, g.ny = n_phi angles 2 pi j /

@@ -57,6 +57,8 @@ using namespace ctrex;
 
 namespace {
 
+constexpr int kMseBlocks = 1024;   // per-block partials of ctrex_nn_mse
+
 bool chan_ok(int c) { return c == 16 || c == 32 || c == 64; }
 
 int check_vol(ctrex_ctx *c, int D, int H, int W, bool even) {
@@ -105,6 +107,18 @@ int ctrex_nn_conv3(ctrex_ctx *c, const void *in, int32_t in_cs, int32_t in_off, 
     CTREX_HIP(c, nn::launch_conv3(in, in_cs, in_off, cin, wt, bias, out, out_cs, out_off, cout, D,
                                   H, W, flags & CTREX_NN_RELU, flags & CTREX_NN_ACCUMULATE,
                                   flags & CTREX_NN_OUT_F32, static_cast<hipStream_t>(stream)));
+    return CTREX_OK;
+}
+
+int ctrex_nn_scratch_bytes(int32_t cin, int32_t cout, int64_t n_vox, size_t *bytes) {
+    if (!bytes) return CTREX_EINVAL;
+    if (cin < 1 || cout < 1 || cin > 64 || cout > 64 || n_vox < 1) return CTREX_ESHAPE;
+    size_t need = std::max(nn::conv3_wgrad_scratch(cin, cout, n_vox),
+                           nn::upconv2_wgrad_scratch(cin, cout, n_vox));
+    need = std::max(need, nn::channel_sum_scratch(cout));
+    need = std::max(need, nn::head_bwd_scratch(16));
+    need = std::max(need, sizeof(double) * (kMseBlocks + 1));
+    *bytes = need;
     return CTREX_OK;
 }
 
@@ -285,7 +299,7 @@ int ctrex_nn_mse(ctrex_ctx *c, const float *a, const float *t, int64_t n, float 
     if (!a || !t) return fail(c, CTREX_EINVAL, "NULL pointer");
     if (n < 1) return fail(c, CTREX_ESHAPE, "n must be >= 1");
     if (!std::isfinite(weight)) return fail(c, CTREX_EINVAL, "weight must be finite");
-    const int blocks = 1024;
+    const int blocks = kMseBlocks;
     void *scr;
     if ((st = ctx_scratch(c, sizeof(double) * (blocks + 1), &scr))) return st;
     double *part = static_cast<double *>(scr);

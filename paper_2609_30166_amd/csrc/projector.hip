@@ -198,7 +198,7 @@ void fp_kernel(RayGrid g, WarpGrid w,
             const float bval = ld(static_cast<const TS *>(ex.b), pix);
             const float res = bval - y;
             e2 = static_cast<double>(res) * static_cast<double>(res);
-            if (MODE == FP_CORRECT) st(out, pix, ex.R[pix] * res);
+            if (MODE == FP_CORRECT) st(out, pix, (ex.R ? ex.R[pix] : ex.rscale) * res);
         }
         block_sum_store(e2, ex.partials + t.lidx);
     }

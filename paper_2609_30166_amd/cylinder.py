@@ -60,6 +60,7 @@ class CylinderGeometry:
         if out is None:
             out = torch.empty(shape, dtype=out_dtype, device=self.device)
         self._g._check_tensor(out, shape, _DT, "out")
+        self._g._scratch(views)
         vp, nv, _keep = _views_arg(views)
         check(self._ctx, _lib.lib().ctrex_forward_project_cyl(
             self._ctx, ctypes.c_void_p(vol.data_ptr()), _DT[vol.dtype],
@@ -106,6 +107,7 @@ class CylinderGeometry:
             workspace = self._ws.get(key)
             if workspace is None:
                 workspace = self._ws[key] = self.workspace(views)
+        self._g._scratch(views)
         vp, nv, _keep = _views_arg(views)
         out = np.zeros(max(int(n_iter), 0), dtype=np.float64) if norms else None
         check(self._ctx, _lib.lib().ctrex_sirt_iterate_cyl(

@@ -69,6 +69,7 @@ class Geometry:
         self._U = None
         self._vw = None
         self._ws = {}
+        self._scr = None
         if U is not None:
             self.set_motion(U, tau)
 
@@ -77,6 +78,7 @@ class Geometry:
         if getattr(self, "_ctx", None) and self._ctx.value:
             _lib.lib().ctrex_destroy(self._ctx)
             self._ctx = ctypes.c_void_p()
+        self._scr = None
 
     def __del__(self):
         try:
@@ -96,6 +98,21 @@ class Geometry:
             raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
         if not t.is_contiguous():
             raise ValueError("%s must be contiguous" % name)
+
+    def _scratch(self, views=None):
+        """Attach device scratch (a uint8 tensor this object owns) holding what
+        the library's calls over ``views`` need; grown when a longer view list
+        or a cylindrical domain needs more."""
+        nv = 0 if views is None else self.n_views(views)
+        n = ctypes.c_size_t(0)
+        check(self._ctx, _lib.lib().ctrex_scratch_bytes(self._ctx, nv, ctypes.byref(n)))
+        need = int(n.value)
+        if self._scr is None or self._scr.numel() < need:
+            check(self._ctx, _lib.lib().ctrex_set_scratch(self._ctx, None, 0))
+            self._scr = None
+            self._scr = torch.empty(need, dtype=torch.uint8, device=self.device)
+            check(self._ctx, _lib.lib().ctrex_set_scratch(
+                self._ctx, ctypes.c_void_p(self._scr.data_ptr()), need))
 
     def n_views(self, views):
         return self.n_proj if views is None else int(np.asarray(views).size)
@@ -143,24 +160,33 @@ class Geometry:
         if out is None:
             out = torch.empty(shape, dtype=out_dtype, device=self.device)
         self._check_tensor(out, shape, _DT, "out")
+        self._scratch(views)
         vp, nv, _keep = _views_arg(views)
         check(self._ctx, _lib.lib().ctrex_forward_project(
             self._ctx, ctypes.c_void_p(vol.data_ptr()), _DT[vol.dtype],
             ctypes.c_void_p(out.data_ptr()), _DT[out.dtype], vp, nv, _stream(self.device)))
         return out
 
-    def back(self, sino, views=None, out=None, accumulate=False):
-        """vol (+)= A^T sino, the exact transpose of ``forward``."""
+    def back(self, sino, views=None, out=None, accumulate=False, scale=1.0):
+        """vol (+)= scale A^T sino, the exact transpose of ``forward`` (the
+        factor is applied inside the library's fixed-point sums)."""
         self._check_tensor(sino, self.sino_shape(views), _DT, "sino")
         if out is None:
             out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
             accumulate = False
         self._check_tensor(out, self.shape, (torch.float32,), "out")
+        self._scratch(views)
         vp, nv, _keep = _views_arg(views)
-        check(self._ctx, _lib.lib().ctrex_back_project(
-            self._ctx, ctypes.c_void_p(sino.data_ptr()), _DT[sino.dtype],
-            ctypes.c_void_p(out.data_ptr()), 1 if accumulate else 0, vp, nv,
-            _stream(self.device)))
+        if scale == 1.0:
+            check(self._ctx, _lib.lib().ctrex_back_project(
+                self._ctx, ctypes.c_void_p(sino.data_ptr()), _DT[sino.dtype],
+                ctypes.c_void_p(out.data_ptr()), 1 if accumulate else 0, vp, nv,
+                _stream(self.device)))
+        else:
+            check(self._ctx, _lib.lib().ctrex_back_project_scaled(
+                self._ctx, ctypes.c_void_p(sino.data_ptr()), _DT[sino.dtype], float(scale),
+                ctypes.c_void_p(out.data_ptr()), 1 if accumulate else 0, vp, nv,
+                _stream(self.device)))
         return out
 
     def back_voxel(self, sino, views=None, out=None, accumulate=False):
@@ -218,6 +244,7 @@ class Geometry:
             self._ws[key] = workspace
             while len(self._ws) > 64:
                 self._ws.pop(next(iter(self._ws)))
+        self._scratch(views)
         vp, nv, _keep = _views_arg(views)
         out = np.zeros(max(int(n_iter), 0), dtype=np.float64) if norms else None
         check(self._ctx, _lib.lib().ctrex_sirt_iterate(
@@ -232,6 +259,7 @@ class Geometry:
         """||sino - A vol||_2 (FP64 sum, computed by the library; waits)."""
         self._check_tensor(vol, self.shape, _DT, "vol")
         self._check_tensor(sino, self.sino_shape(views), _DT, "sino")
+        self._scratch(views)
         vp, nv, _keep = _views_arg(views)
         out = ctypes.c_double(0.0)
         check(self._ctx, _lib.lib().ctrex_residual_norm(
@@ -239,6 +267,24 @@ class Geometry:
             ctypes.c_void_p(sino.data_ptr()), _DT[sino.dtype], vp, nv, ctypes.byref(out),
             _stream(self.device)))
         return out.value
+
+    def data_residual(self, vol, b, views=None, scale=1.0, residual=True, sq_sum=True):
+        """Data term of the loss (Eq. (1)'s residual): returns (r, s) with
+        r = scale (A vol - b) in b's storage type (or None) and
+        s = sum (A vol - b)^2 as a 0-d float64 device tensor (or None), both
+        computed by the library's kernels, without a host wait."""
+        self._check_tensor(vol, self.shape, _DT, "vol")
+        self._check_tensor(b, self.sino_shape(views), _DT, "b")
+        r = torch.empty_like(b) if residual else None
+        s = torch.empty((), dtype=torch.float64, device=self.device) if sq_sum else None
+        self._scratch(views)
+        vp, nv, _keep = _views_arg(views)
+        check(self._ctx, _lib.lib().ctrex_data_residual(
+            self._ctx, ctypes.c_void_p(vol.data_ptr()), _DT[vol.dtype],
+            ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(r.data_ptr()) if residual else None,
+            _DT[b.dtype], float(scale), vp, nv,
+            ctypes.c_void_p(s.data_ptr()) if sq_sum else None, _stream(self.device)))
+        return r, s
 
     def os_sirt(self, vol, sino, subsets, n_epochs, alpha=1.0, nonneg=False,
                 gather_dtype=torch.float32, norms=False, voxel_bp=False):
@@ -382,8 +428,37 @@ def total_variation(vol, geom, eps=1e-5):
     return TotalVariation.apply(vol, geom, eps)
 
 
+class DataTerm(torch.autograd.Function):
+    """||A x - b||^2 (Eq. (1)'s data term, summed in FP64) with the gradient
+    2 A^T (A x - b): the forward projection with the residual epilogue, and
+    the exact-transpose backprojector scaled by 2 in the backward.  ``b`` is
+    data (no gradient)."""
+
+    @staticmethod
+    def forward(ctx, vol, b, geom, views=None):
+        r, s = geom.data_residual(vol.contiguous(), b.contiguous(), views)
+        ctx.geom = geom
+        ctx.views = views
+        ctx.save_for_backward(r)
+        return s
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        grad_x = None
+        if ctx.needs_input_grad[0]:
+            (r,) = ctx.saved_tensors
+            grad_x = ctx.geom.back(r, ctx.views, scale=2.0 * float(grad_out))
+        return grad_x, None, None, None
+
+
+def data_term(vol, b, geom, views=None):
+    """Differentiable ||A x - b||^2 through the library's residual and
+    backprojection kernels."""
+    return DataTerm.apply(vol, b, geom, views)
+
+
 def reconstruction_loss(vol, b, geom, lam=1e-3, eps=1e-5, views=None):
-    """||A x - b||^2 + lam TV(x), differentiable through the HIP operators
-    (residual summed in FP64)."""
-    r = project(vol, geom, views) - b
-    return (r.double() ** 2).sum() + lam * total_variation(vol, geom, eps)
+    """||A x - b||^2 + lam TV(x), differentiable through the HIP operators:
+    the data term and its gradient from ``DataTerm``, TV and its gradient
+    from the library's TV kernels."""
+    return data_term(vol, b, geom, views) + lam * total_variation(vol, geom, eps)

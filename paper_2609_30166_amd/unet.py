@@ -53,6 +53,9 @@ LAYERS = (
     ("d1b", "conv", 16, 16),
 )
 _KIND = {name: (kind, cin, cout) for name, kind, cin, cout in LAYERS}
+# resolution level of each layer's weight-gradient input (1 = full resolution;
+# an up-sampling layer reads the coarser level below it)
+_LEVEL = dict(e1a=1, e1b=1, e2a=2, e2b=2, bna=3, bnb=3, up2=3, d2a=2, d2b=2, up1=2, d1a=1, d1b=1)
 
 
 def _wshape(kind, cin, cout):
@@ -130,6 +133,7 @@ class UNet:
         if getattr(self, "_ctx", None) and self._ctx.value:
             _lib.lib().ctrex_destroy(self._ctx)
             self._ctx = ctypes.c_void_p()
+        self._scr = None
 
     def __del__(self):
         try:
@@ -215,7 +219,31 @@ class UNet:
         # inference and training share nothing; keep the most recent of each
         self._bufs = {k: v for k, v in self._bufs.items() if k[1] != train}
         self._bufs[key] = b
+        if train:
+            self._attach_scratch((D, H, W))
         return b
+
+    def _attach_scratch(self, shape):
+        """Attach the device scratch the gradient and loss calls need at this
+        volume shape (the maximum over the layers' needs)."""
+        D, H, W = shape
+        need = 0
+        for name, kind, cin, cout in LAYERS:
+            lv = _LEVEL[name]
+            n = (D >> (lv - 1)) * (H >> (lv - 1)) * (W >> (lv - 1))
+            sz = ctypes.c_size_t(0)
+            check(self._ctx, _lib.lib().ctrex_nn_scratch_bytes(cin, cout, n, ctypes.byref(sz)))
+            need = max(need, int(sz.value))
+        self._grow_scratch(need)
+
+    def _grow_scratch(self, need):
+        """Attach at least ``need`` bytes of device scratch to the context."""
+        if getattr(self, "_scr", None) is None or self._scr.numel() < need:
+            check(self._ctx, _lib.lib().ctrex_set_scratch(self._ctx, None, 0))
+            self._scr = None
+            self._scr = torch.empty(need, dtype=torch.uint8, device=self.device)
+            check(self._ctx, _lib.lib().ctrex_set_scratch(
+                self._ctx, ctypes.c_void_p(self._scr.data_ptr()), need))
 
     @staticmethod
     def check_shape(shape):
@@ -374,6 +402,9 @@ class UNet:
     def mse(self, a, t, grad=None, weight=1.0):
         """weight x mean squared error (FP64 sum), optionally its gradient into ``grad``."""
         loss = ctypes.c_double()
+        sz = ctypes.c_size_t(0)
+        check(self._ctx, _lib.lib().ctrex_nn_scratch_bytes(1, 16, 1, ctypes.byref(sz)))
+        self._grow_scratch(int(sz.value))
         self._call("ctrex_nn_mse", _vp(a), _vp(t), a.numel(), float(weight), ctypes.byref(loss),
                    _vp(grad) if grad is not None else None, self._s())
         return loss.value

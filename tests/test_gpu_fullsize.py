@@ -42,19 +42,49 @@ def full(dev):
     return cfg, x, g
 
 
-def test_full_forward_sampled_projections(full, dev):
+# Projections 0 and 357 put the source near +x / -x (rays mainly along x: the
+# y-fastest gather copy), 180 and 540 near +y / -y (rays mainly along y: the
+# x-fastest copy), 90 and 270 on the diagonals (the copy chosen per detector
+# tile from its central ray, so both are used within one projection).
+FULL_VIEWS = [0, 90, 180, 270, 357, 540]
+
+
+@pytest.fixture(scope="module")
+def full_forward_ref(full):
+    cfg, x, g = full
+    return oracle.forward(cfg.P, cfg.shape, cfg.n_u, cfg.n_v, x.astype(np.float64), cfg.step,
+                          views=FULL_VIEWS)
+
+
+def test_full_forward_sampled_projections(full, full_forward_ref, dev):
     """All 720 projections in one launch (the benchmark's configuration);
-    projections 0 and 357 against the oracle."""
+    six projections covering both gather copies against the oracle, each on
+    its own and together."""
     cfg, x, g = full
     xt = torch.from_numpy(x).to(dev)
     y = g.forward(xt)
-    views = [0, 357]
-    y_ref = oracle.forward(cfg.P, cfg.shape, cfg.n_u, cfg.n_v, x.astype(np.float64), cfg.step,
-                           views=views)
-    assert rel_l2(y[views].cpu().numpy(), y_ref) <= TOL
-    # 16-bit storage of volume and sinogram: error against FP64 bounded by BF16 rounding
-    y16 = g.forward(xt.to(torch.bfloat16), views=views, out_dtype=torch.bfloat16)
-    assert rel_l2(y16.float().cpu().numpy(), y_ref) <= 8e-3
+    got = y[FULL_VIEWS].cpu().numpy()
+    for k, v in enumerate(FULL_VIEWS):
+        assert rel_l2(got[k], full_forward_ref[k]) <= TOL, v
+    assert rel_l2(got, full_forward_ref) <= TOL
+
+
+def test_full_forward_16bit_storage(full, full_forward_ref, dev):
+    """BF16 and FP16 volumes at 512^3 through the 16-bit corner-packed
+    copies (x- and y-fastest): against the oracle on the same rounded volume
+    at 1e-5 with an FP32 sinogram, and against FP64 of the unrounded volume
+    within the storage rounding with a 16-bit sinogram."""
+    cfg, x, g = full
+    xt = torch.from_numpy(x).to(dev)
+    for dt, bound in ((torch.bfloat16, 8e-3), (torch.float16, 2e-3)):
+        x16 = xt.to(dt)
+        y32 = g.forward(x16, views=FULL_VIEWS, out_dtype=torch.float32).cpu().numpy()
+        xr = x16.float().cpu().numpy().astype(np.float64)
+        ref = oracle.forward(cfg.P, cfg.shape, cfg.n_u, cfg.n_v, xr, cfg.step, views=FULL_VIEWS)
+        for k, v in enumerate(FULL_VIEWS):
+            assert rel_l2(y32[k], ref[k]) <= TOL, (dt, v)
+        y16 = g.forward(x16, views=FULL_VIEWS, out_dtype=dt)
+        assert rel_l2(y16.float().cpu().numpy(), full_forward_ref) <= bound, dt
 
 
 def test_full_back_view_subset(full, dev):
@@ -187,7 +217,10 @@ def test_diff_gradient_matches_oracle_on_subset(diff, dev):
         b[views].astype(np.float64)
     want = 2 * oracle.back(cfg.P, cfg.shape, cfg.n_u, cfg.n_v, res, cfg.step, views=views) + \
         1e-3 * oracle.tv_grad(xd, 1e-5)
-    assert rel_l2(xt.grad.cpu().numpy(), want) <= 1e-4
+    # the residual is about 0.2 A x (x0 = 0.8 x_true + noise), so the FP32
+    # projection's error against FP64 (~1e-7 relative) grows about 5-fold in
+    # it: within 1e-5
+    assert rel_l2(xt.grad.cpu().numpy(), want) <= TOL
     assert float(loss) == pytest.approx(float(np.sum(res * res)) + 1e-3 * oracle.tv(xd, 1e-5),
                                         rel=1e-5)
 

@@ -47,8 +47,15 @@ def L():
 def ctx(L):
     c = ctypes.c_void_p()
     assert L.lib().ctrex_create(ctypes.byref(c), 0) == 0
+    # device scratch of the gradient and loss calls, for the largest layer
+    # these tests run (64 -> 64 channels over 8192 voxels)
+    need = ctypes.c_size_t()
+    assert L.lib().ctrex_nn_scratch_bytes(64, 64, 8192, ctypes.byref(need)) == 0
+    scr = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+    assert L.lib().ctrex_set_scratch(c, ctypes.c_void_p(scr.data_ptr()), scr.numel()) == 0
     yield c
     L.lib().ctrex_destroy(c)
+    del scr
 
 
 def _vp(t):
@@ -219,14 +226,12 @@ def test_conv3_weight_gradient_on_slices(L, ctx):
 
 
 # --------------------------------------------------------------- upconv2 ----
-@pytest.mark.parametrize("shape", [(4, 4, 4), (2, 6, 10), (8, 8, 16)])
+@pytest.mark.parametrize("shape", [(4, 4, 4), (4, 4, 12), (8, 8, 16)])
 @pytest.mark.parametrize("cin,cout", UP_PAIRS)
 def test_upconv2_forward_and_gradients(L, ctx, shape, cin, cout):
     from oracle import unet as ou
     r = _rng(6, cin, cout, *shape)
     n = int(np.prod(shape))
-    if n % 64:
-        pytest.skip("voxel count must be a multiple of 64")
     x = torch.tensor(_bf(r.normal(size=shape + (cin,))), requires_grad=True)
     w = torch.tensor(_bf(r.normal(0, 0.2, size=(cin, cout, 8))), requires_grad=True)
     b = torch.tensor(r.normal(size=cout).astype(np.float32).astype(np.float64), requires_grad=True)
@@ -252,6 +257,29 @@ def test_upconv2_forward_and_gradients(L, ctx, shape, cin, cout):
           _vp(dw), _vp(db), None)
     _close(_host(dw).reshape(cin, cout, 8), w.grad.numpy())
     _close(_host(db), b.grad.numpy())
+
+
+def test_upconv2_rejects_voxel_count_not_multiple_of_64(L, ctx):
+    """A 2 x 6 x 10 input (120 voxels) is refused on the host with
+    CTREX_ESHAPE by all three up-sampling calls; the output keeps its fill."""
+    shape, cin, cout = (2, 6, 10), 32, 16
+    n = int(np.prod(shape))
+    xd = torch.zeros(n * cin, dtype=torch.bfloat16, device=DEV)
+    wt = torch.zeros(8 * cin * cout, dtype=torch.bfloat16, device=DEV)
+    bd = torch.zeros(cout, dtype=torch.float32, device=DEV)
+    out = torch.full((8 * n * cout,), 7.0, dtype=torch.float32, device=DEV)
+    lib = L.lib()
+    assert lib.ctrex_nn_upconv2(ctx, _vp(xd), cin, 0, cin, _vp(wt), _vp(bd), _vp(out), cout, 0,
+                                cout, *shape, L.NN_OUT_F32, None) == -2
+    assert b"multiple of 64" in lib.ctrex_last_error(ctx)
+    gd = torch.zeros(8 * n * cout, dtype=torch.bfloat16, device=DEV)
+    assert lib.ctrex_nn_upconv2_dgrad(ctx, _vp(gd), cout, 0, cout, _vp(wt), _vp(xd), cin, 0, cin,
+                                      *shape, 0, None) == -2
+    dw = torch.zeros(cin * cout * 8, dtype=torch.float32, device=DEV)
+    assert lib.ctrex_nn_upconv2_wgrad(ctx, _vp(xd), cin, 0, cin, _vp(gd), cout, 0, cout, *shape,
+                                      _vp(dw), _vp(bd), None) == -2
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all())
 
 
 def test_upconv2_into_concat_slice(L, ctx):

@@ -136,6 +136,39 @@ def test_tv_closed_form_ramp():
     assert oracle.tv(x, eps) == pytest.approx(want, rel=1e-13)
 
 
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_tv_closed_form_ramp_each_axis(axis):
+    """A ramp along one axis (z, y or x): every voxel before the last index of
+    that axis has |grad+ x| = a, the last layer only eps.  A difference taken
+    along the wrong axis, or one axis' difference counted twice, fails."""
+    shape = (4, 5, 6)
+    a, eps = 0.7, 1e-5
+    idx = np.indices(shape)[axis].astype(np.float64)
+    x = a * idx
+    n_axis = shape[axis]
+    layer = int(np.prod(shape)) // n_axis
+    want = (n_axis - 1) * layer * np.sqrt(a * a + eps * eps) + layer * eps
+    assert oracle.tv(x, eps) == pytest.approx(want, rel=1e-13)
+
+
+def test_tv_brute_force_loops():
+    """TV written as an explicit triple loop over voxels with each forward
+    difference taken by index arithmetic, on a random 4x5x6 volume."""
+    rng = np.random.default_rng(21)
+    nz, ny, nx = 4, 5, 6
+    x = rng.normal(size=(nz, ny, nx))
+    eps = 1e-3
+    total = 0.0
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                gx = x[k, j, i + 1] - x[k, j, i] if i + 1 < nx else 0.0
+                gy = x[k, j + 1, i] - x[k, j, i] if j + 1 < ny else 0.0
+                gz = x[k + 1, j, i] - x[k, j, i] if k + 1 < nz else 0.0
+                total += (gx * gx + gy * gy + gz * gz + eps * eps) ** 0.5
+    assert oracle.tv(x, eps) == pytest.approx(total, rel=1e-13)
+
+
 def test_tv_gradient_matches_central_differences():
     rng = np.random.default_rng(4)
     x = rng.normal(size=(5, 6, 7))
