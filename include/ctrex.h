@@ -197,6 +197,26 @@ CTREX_API int ctrex_back_project_scaled(ctrex_ctx *ctx, const void *sino, int32_
                                         const int32_t *views, int32_t n_views, void *stream);
 
 /*
+ * ctrex_back_project without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same operator, arguments, layouts and
+ * errors as ctrex_back_project; it never calls hipMalloc or hipFree and
+ * needs no attached scratch.  Its scratch is a fixed 32 MiB array of the
+ * library on each GPU (held until the process ends): the view list (at most
+ * 262144 entries, else CTREX_ESHAPE before any launch), the max |sino|
+ * cell, and the per-chunk partial volumes, whose number is capped to what
+ * fits (one chunk, and no partial volume, when even two do not), so large
+ * volumes differ from ctrex_back_project only by the rounding of the
+ * fixed-point scale.  With a view list the call waits for `stream` (the
+ * list is copied into the array).  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other threads or
+ * contexts) race and must be serialised by the caller.
+ */
+CTREX_API int ctrex_back_project_noalloc(ctrex_ctx *ctx, const void *sino, int32_t sino_dtype,
+                                         float *vol, int32_t accumulate, const int32_t *views,
+                                         int32_t n_views, void *stream);
+
+/*
  * Sec. 4.1 (backprojection operator), the paper's voxel-driven form:
  * vol (+)= B sino over the listed projections, where for voxel j with centre
  * X_j (V frame, index coordinates centred on the volume) and each sub-view

@@ -60,6 +60,7 @@ def lib():
             "ctrex_back_project": (ctypes.c_int, [vp, vp, i32, vp, i32, ip, i32, vp]),
             "ctrex_back_project_scaled": (ctypes.c_int, [vp, vp, i32, ctypes.c_float, vp, i32, ip,
                                                          i32, vp]),
+            "ctrex_back_project_noalloc": (ctypes.c_int, [vp, vp, i32, vp, i32, ip, i32, vp]),
             "ctrex_scratch_bytes": (ctypes.c_int, [vp, i32, ctypes.POINTER(ctypes.c_size_t)]),
             "ctrex_set_scratch": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
             "ctrex_data_residual": (ctypes.c_int, [vp, vp, i32, vp, vp, i32, ctypes.c_float, ip,

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <limits>
 #include <list>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -305,6 +306,45 @@ CylScratch cyl_scratch(const ctrex_ctx *c) {
     return l;
 }
 
+// ---------------------------------------------- allocation-free backprojection --
+// ctrex_back_project_noalloc keeps its scratch (the view list, the max |r|
+// cell and the per-chunk partial volumes) in the fixed array below instead
+// of the caller's or the library's allocations: one copy per GPU, held until
+// the process ends.  In host code `scratch` names a host-side stand-in, not a
+// device address; kernels are given the address hipGetSymbolAddress returns
+// for the current device (kept in noalloc_ptr).
+constexpr size_t kNoAllocBytes = size_t(32) << 20;
+constexpr size_t kNoAllocViewBytes = size_t(1) << 20;   // up to 262144 projection indices
+constexpr size_t kNoAllocMaxAbs = kNoAllocViewBytes;    // one float, its own 256-byte line
+constexpr size_t kNoAllocSlabs = kNoAllocViewBytes + 256;
+constexpr int kNoAllocDevices = 64;
+
+std::mutex noalloc_mu;
+void *noalloc_ptr[kNoAllocDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+// Look up (once per device, with that device current) the device address of
+// this GPU's copy of `scratch`.
+int noalloc_setup(ctrex_ctx *c) {
+    if (c->device < 0 || c->device >= kNoAllocDevices)
+        return fail(c, CTREX_EDEVICE, "device %d beyond the %d the library supports", c->device,
+                    kNoAllocDevices);
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (noalloc_ptr[c->device]) return CTREX_OK;
+    CTREX_HIP(c, hipSetDevice(c->device));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(c, e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(c, CTREX_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    noalloc_ptr[c->device] = p;
+    return CTREX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -322,6 +362,13 @@ int ctrex_create(ctrex_ctx **out, int device) {
         hipMalloc(&c->d_red, sizeof(double) * 8193) != hipSuccess) {
         if (c->d_count) (void)hipFree(c->d_count);
         if (c->d_scalar) (void)hipFree(c->d_scalar);
+        delete c;
+        return CTREX_EDEVICE;
+    }
+    if (noalloc_setup(c) != CTREX_OK) {
+        (void)hipFree(c->d_count);
+        (void)hipFree(c->d_scalar);
+        (void)hipFree(c->d_red);
         delete c;
         return CTREX_EDEVICE;
     }
@@ -620,6 +667,58 @@ int ctrex_back_project_scaled(ctrex_ctx *c, const void *sino, int32_t sino_dtype
                               int32_t n_views, void *stream) {
     return back_project_common(c, sino, sino_dtype, scale, vol, accumulate, views, n_views,
                                stream);
+}
+
+int ctrex_back_project_noalloc(ctrex_ctx *c, const void *sino, int32_t sino_dtype, float *vol,
+                               int32_t accumulate, const int32_t *views, int32_t n_views,
+                               void *stream) {
+    int st = check_ready(c);
+    if (st != CTREX_OK) return st;
+    if (!vol) return fail(c, CTREX_EINVAL, "vol must be a device pointer");
+    if (!valid_dtype(sino_dtype)) return fail(c, CTREX_EINVAL, "unknown dtype %d", sino_dtype);
+    int32_t nv = c->n_proj;
+    if (views) {
+        if (n_views < 0) return fail(c, CTREX_ESHAPE, "n_views must be >= 0 (got %d)", n_views);
+        if (static_cast<size_t>(n_views) * sizeof(int32_t) > kNoAllocViewBytes)
+            return fail(c, CTREX_ESHAPE, "view list of %d entries exceeds the %zu this call holds",
+                        n_views, kNoAllocViewBytes / sizeof(int32_t));
+        for (int32_t k = 0; k < n_views; ++k)
+            if (views[k] < 0 || views[k] >= c->n_proj)
+                return fail(c, CTREX_ESHAPE, "views[%d] = %d outside [0, %d)", k, views[k],
+                            c->n_proj);
+        nv = n_views;
+    }
+    if ((st = check_blocks(c, nv)) != CTREX_OK) return st;
+    if (nv > 0 && !sino) return fail(c, CTREX_EINVAL, "sino must be a device pointer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t vox = static_cast<size_t>(c->nx) * c->ny * c->nz;
+    if (nv == 0) {
+        if (!accumulate) CTREX_HIP(c, launch_fill_zero(vol, sizeof(float) * vox, s));
+        return CTREX_OK;
+    }
+    if ((st = noalloc_setup(c)) != CTREX_OK) return st;
+    unsigned char *base = static_cast<unsigned char *>(noalloc_ptr[c->device]);
+    const int32_t *dv = nullptr;
+    if (views) {
+        // the list is read from the caller's (pageable) memory during the call
+        CTREX_HIP(c, hipMemcpyAsync(base, views, sizeof(int32_t) * nv, hipMemcpyHostToDevice, s));
+        CTREX_HIP(c, hipStreamSynchronize(s));
+        dv = reinterpret_cast<const int32_t *>(base);
+    }
+    // as many projection chunks (each writing a partial volume) as the array holds
+    const size_t slab_room = kNoAllocBytes - kNoAllocSlabs;
+    const size_t fit = slab_room / (sizeof(float) * vox);
+    const int cap = fit >= 2 ? static_cast<int>(std::min<size_t>(fit, 1u << 20)) : 1;
+    const RayGrid g = make_grid(c, dv, nv);
+    const size_t slabs = back_scratch_bytes(g, cap);
+    if (slabs > slab_room)
+        return fail(c, CTREX_ESHAPE, "partial volumes of %zu bytes exceed the %zu this call holds",
+                    slabs, slab_room);
+    float *rmax = reinterpret_cast<float *>(base + kNoAllocMaxAbs);
+    float *part = slabs ? reinterpret_cast<float *>(base + kNoAllocSlabs) : nullptr;
+    CTREX_HIP(c, launch_back(g, make_warp(c), c->d_P, sino, sino_dtype, vol, accumulate ? 1 : 0,
+                             BP_PLAIN, rmax, part, s, 1.0f, cap));
+    return CTREX_OK;
 }
 
 // Detector sizes the voxel-driven backprojector's bilinear lookups support
