@@ -118,8 +118,8 @@ CTREX_API const char *ctrex_last_error(const ctrex_ctx *ctx);
  * [n_proj][n_sub][3][4].  For every sub-view the library computes, in FP64,
  * the inverse of the left 3x3 block M and the source S = -M^-1 P[:, 3]; it
  * rejects |det M| < 1e-12 ||M||_F^3 (CTREX_ESINGULAR) and sources inside
- * the hull (CTREX_ESOURCE_INSIDE).  Volume sides must be >= 2 and
- * nx*ny*nz < 2^31; step > 0 with fewer than 2^24 steps along the hull
+ * the hull (CTREX_ESOURCE_INSIDE).  Volume sides must be >= 2 and < 2^22
+ * with nx*ny*nz < 2^31; step > 0 with fewer than 2^24 steps along the hull
  * diagonal.  The table is copied to the device
  * synchronously.  Clears any motion field and invalidates cached SIRT weights.
  */

@@ -11,10 +11,11 @@
 // sample.  Here a workgroup owns a brick of the volume (up to 32x15x16
 // voxels) held in LDS for a whole chunk of projections, accumulated as 64-bit
 // fixed point with LDS integer atomics: on gfx950 these sustain about twenty
-// times the lane rate of LDS FP32 atomic adds, the sums are exact (so the
-// result does not depend on the order of the atomics), and a scale bounded
-// from max|r| keeps the rounding of each contribution near 2^-50 of the
-// largest possible sum.  For every
+// times the lane rate of LDS FP32 atomic adds, and the sums are exact (so the
+// result does not depend on the order of the atomics).  A scale bounded from
+// max|r| puts the largest possible contribution at 2^30, so each one is a
+// 32-bit integer (weights formed in FP32, truncated: under 2^-30 of that
+// largest contribution off) while the 64-bit sums cannot overflow.  For every
 // (projection, sub-view) it bounds the detector pixels whose rays can reach
 // the brick (the projection of the brick grown by one voxel and the warp
 // bound), redoes those rays' FP64 set-up, clips their sample range to the
@@ -128,15 +129,16 @@ __device__ __forceinline__ int wave_inclusive_sum(int x) {
     return x;
 }
 
-// Round w * g to the nearest integer (|w g| < 2^51) as a two's-complement
-// 64-bit value: adding 1.5 * 2^52 in the same FMA leaves the rounded integer
-// in the low mantissa bits of the double.  The fixed-point scale is folded
-// into w.
-__device__ __forceinline__ unsigned long long to_fixed(double w, double g) {
-    const double magic = 6755399441055744.0;
-    const double t = fma(w, g, magic);
-    return static_cast<unsigned long long>(__double_as_longlong(t) -
-                                           __double_as_longlong(magic));
+// One contribution as a 64-bit fixed-point integer: c (FP32, the scale
+// folded in, |c| <= 2^30) truncated toward zero to 32 bits, then
+// sign-extended.  Truncation errs by under one unit, 2^-30 of the largest
+// possible contribution.
+__device__ __forceinline__ unsigned long long to_fixed(float c) {
+    return static_cast<unsigned long long>(static_cast<long long>(static_cast<int>(c)));
+}
+
+__device__ __forceinline__ long long shfl64(long long v, int src) {
+    return __shfl(v, src, 64);
 }
 
 template <typename TS, int MODE, bool WARP>
@@ -168,11 +170,11 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
 
     const VolDims d = vol_dims(g);
     const float M = static_cast<float>(w.margin);
-    // samples with an (unwarped) position in [lo, hi] can touch the brick
-    const float lo[3] = {uni(x0 - 1.0f - M), uni(y0 - 1.0f - M), uni(z0 - 1.0f - M)};
-    const float hi[3] = {uni(static_cast<float>(x0 + ex) + M), uni(static_cast<float>(y0 + ey) + M),
-                         uni(static_cast<float>(z0 + ez) + M)};
-    const double lod[3] = {lo[0], lo[1], lo[2]}, hid[3] = {hi[0], hi[1], hi[2]};
+    // samples with an (unwarped) position in [lo, hi] can touch the brick,
+    // for any projection (the warp bound of the whole scan)
+    const double lod[3] = {x0 - 1.0 - M, y0 - 1.0 - M, z0 - 1.0 - M};
+    const double hid[3] = {static_cast<double>(x0 + ex) + M, static_cast<double>(y0 + ey) + M,
+                           static_cast<double>(z0 + ez) + M};
     const double off[3] = {0.5 * (g.nx - 1), 0.5 * (g.ny - 1), 0.5 * (g.nz - 1)};
     // 1 / n_sub and the caller's factor (1 unless scaled; exact when a power of 2)
     const float inv_sub = uni(bg.wscale / static_cast<float>(g.n_sub));
@@ -180,11 +182,13 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
     const int k_end = min(k_first + bg.views_per_chunk, g.n_views);
     const int n_pairs = (k_end - k_first) * g.n_sub;
 
-    // ---- fixed-point scale.  Every contribution to a voxel comes from a
-    // sample of a ray in some pair's pixel box lying in the voxel's corner
-    // cube (side 2); a ray has at most bg.cube_samples samples there and each
-    // contribution is at most step * max|r| / n_sub.  The bound on the sum
-    // picks the scale so that the 64-bit sums never reach 2^51.
+    // ---- fixed-point scale.  Each contribution is at most
+    // cmax = step * max|r| / n_sub (times the caller's factor), and every
+    // contribution to a voxel comes from a sample of a ray in some pair's
+    // pixel box lying in the voxel's corner cube (side 2), at most
+    // bg.cube_samples of them per ray.  The scale 2^kexp puts the largest
+    // contribution at or below 2^30 (so it fits a 32-bit integer) and keeps
+    // the bound on the sums below 2^62.
     double nrays = 0.0;
     for (int q = threadIdx.x; q < n_pairs; q += BP_THREADS) {
         const int k = k_first + q / g.n_sub;
@@ -207,7 +211,9 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
     const double bound = nrays * bg.cube_samples * cmax;
     const bool bad = !(cmax < __builtin_inf());   // NaN or Inf in the input: propagate NaN
     const bool any = uni(static_cast<int>(bound > 0.0 && !bad)) != 0;
-    const int kexp = uni(any ? static_cast<int>(floor(50.0 - log2(bound))) : 0);
+    const int kexp = uni(any ? static_cast<int>(floor(fmin(30.0 - log2(cmax),
+                                                           62.0 - log2(bound))))
+                             : 0);
     const double scale = uni(ldexp(1.0, kexp));
 
     // each wave takes whole (projection, sub-view) pairs, so a pair's pixel
@@ -220,8 +226,18 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
         {
             const int sv_idx = p * g.n_sub + s;
             const SubView &sv = g.tab[sv_idx];
+            // this sub-view's warp moves samples by at most |tau| max|U| on
+            // every axis: its samples within that margin of the brick can
+            // touch it (time-linear fields: half the scan's bound on average)
+            const double mv = WARP ? fabs(sv.tau) * w.umax : 0.0;
+            const float Mp = uni(mv > 0.0 ? static_cast<float>(ceil(mv * (1.0 + 1e-6) + 1e-6)) : 0.0f);
+            const float lo[3] = {uni(x0 - 1.0f - Mp), uni(y0 - 1.0f - Mp), uni(z0 - 1.0f - Mp)};
+            const float hi[3] = {uni(static_cast<float>(x0 + ex) + Mp),
+                                 uni(static_cast<float>(y0 + ey) + Mp),
+                                 uni(static_cast<float>(z0 + ez) + Mp)};
+            const double plo[3] = {lo[0], lo[1], lo[2]}, phi[3] = {hi[0], hi[1], hi[2]};
             int u0 = 0, u1 = g.n_u - 1, v0 = 0, v1 = g.n_v - 1;
-            if (!project_box(Pmat + 12 * static_cast<size_t>(sv_idx), lod, hid, off, g.n_u, g.n_v,
+            if (!project_box(Pmat + 12 * static_cast<size_t>(sv_idx), plo, phi, off, g.n_u, g.n_v,
                              u0, u1, v0, v1)) {
                 u0 = 0;
                 u1 = g.n_u - 1;
@@ -244,9 +260,9 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
                 const int iu = u0 + (blk % bu) * 8 + (lane & 7);
                 // ---- this lane's ray: its samples that can reach the brick
                 int len = 0, ib = 0;
-                float wgt = 0.0f;
+                float wq = 0.0f;   // h r / n_sub in fixed-point units
                 Ray r;
-                r.bx = r.by = r.bz = r.sx = r.sy = r.sz = 0.0;
+                r.qx = r.qy = r.qz = r.tx = r.ty = r.tz = 0;
                 const float rv = (iu > u1 || iv > v1) ? 0.0f
                                  : (MODE == BP_ONES) ? 1.0f
                                                      : ld(sino, (k * g.n_v + iv) * g.n_u + iu);
@@ -275,9 +291,13 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
                         ib = max(static_cast<int>(ceilf(kmin)), 0);
                         const int ie = min(static_cast<int>(floorf(kmax)), r.n - 1);
                         len = max(ie - ib + 1, 0);
-                        wgt = r.h * rv * inv_sub;
+                        wq = static_cast<float>(static_cast<double>(r.h * rv * inv_sub) * scale);
                     }
                 }
+                // position of the ray's first sample in the brick range
+                const long long p0x = r.qx + static_cast<long long>(ib) * r.tx;
+                const long long p0y = r.qy + static_cast<long long>(ib) * r.ty;
+                const long long p0z = r.qz + static_cast<long long>(ib) * r.tz;
                 // ---- exclusive prefix of the segment lengths over the wave
                 const int incl = wave_inclusive_sum(len);
                 const int S = incl - len;
@@ -292,87 +312,82 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
                     const int t = j + st;
                     if (__shfl(S, t, 64) <= start) j = t;
                 }
-                const int off_own = ib - S;   // sample index = off + pos
-                double cbx = __shfl(r.bx, j, 64), cby = __shfl(r.by, j, 64),
-                       cbz = __shfl(r.bz, j, 64), csx = __shfl(r.sx, j, 64),
-                       csy = __shfl(r.sy, j, 64), csz = __shfl(r.sz, j, 64);
-                double cws = static_cast<double>(__shfl(wgt, j, 64)) * scale;
-                int coff = __shfl(off_own, j, 64);
+                // the lane's first ray may be entered mid-way: `start - S_j`
+                // samples after its first sample in the brick range
+                long long ctx = shfl64(r.tx, j), cty = shfl64(r.ty, j), ctz = shfl64(r.tz, j);
+                const long long m = start - __shfl(S, j, 64);
+                long long px = shfl64(p0x, j) + m * ctx, py = shfl64(p0y, j) + m * cty,
+                          pz = shfl64(p0z, j) + m * ctz;
+                float cwq = __shfl(wq, j, 64);
                 int cend = __shfl(incl, j, 64);
-                Ray cr;
-                Anchor an = {0, 0, 0, 0.0f, 0.0f, 0.0f};
-                GridAnchor ga = {0, 0, 0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-                int seg = -1;
                 const int trips = (T + 63) >> 6;
                 int pos = start;
                 for (int it = 0; it < trips; ++it) {
-                    // wave-uniform hand-over to the next ray with samples
+                    // wave-uniform hand-over to the next ray with samples; it is
+                    // entered at its first sample in the brick range
                     const bool need = pos < end && pos == cend;
                     if (__any(need)) {
                         const unsigned long long rest =
                             j < 63 ? (live & (~0ull << (j + 1))) : 0ull;
                         const int jn = need && rest ? __ffsll(static_cast<long long>(rest)) - 1 : j;
                         // lanes without a hand-over read their current ray again
-                        // (the same values), so no second copy of the ray is live
-                        cbx = __shfl(r.bx, jn, 64);
-                        cby = __shfl(r.by, jn, 64);
-                        cbz = __shfl(r.bz, jn, 64);
-                        csx = __shfl(r.sx, jn, 64);
-                        csy = __shfl(r.sy, jn, 64);
-                        csz = __shfl(r.sz, jn, 64);
-                        cws = static_cast<double>(__shfl(wgt, jn, 64)) * scale;
-                        coff = __shfl(off_own, jn, 64);
+                        // (the same values) and keep their position
+                        ctx = shfl64(r.tx, jn);
+                        cty = shfl64(r.ty, jn);
+                        ctz = shfl64(r.tz, jn);
+                        const long long nx0 = shfl64(p0x, jn), ny0 = shfl64(p0y, jn),
+                                        nz0 = shfl64(p0z, jn);
+                        cwq = __shfl(wq, jn, 64);
                         cend = __shfl(incl, jn, 64);
-                        if (need) seg = -1;
+                        if (need) {
+                            px = nx0;
+                            py = ny0;
+                            pz = nz0;
+                        }
                         j = jn;
                     }
                     if (pos >= end) continue;
-                    const int i = coff + pos;
                     ++pos;
-                    const int sg = i & ~(SEG - 1);
-                    if (sg != seg) {
-                        cr.bx = cbx; cr.by = cby; cr.bz = cbz;
-                        cr.sx = csx; cr.sy = csy; cr.sz = csz;
-                        an = anchor_at(cr, sg);
-                        if (WARP) ga = grid_anchor(w, cbx, cby, cbz, csx, csy, csz, sg);
-                        seg = sg;
-                    }
-                    const float jj = static_cast<float>(i - sg);
-                    float cx = fmaf(jj, static_cast<float>(csx), an.ax),
-                          cy = fmaf(jj, static_cast<float>(csy), an.ay),
-                          cz = fmaf(jj, static_cast<float>(csz), an.az);
-                    if (WARP && !warp(w, d, tau, an, ga, jj, cx, cy, cz)) continue;
+                    const long long qx = px, qy = py, qz = pz;
+                    px += ctx;
+                    py += cty;
+                    pz += ctz;
                     int ix, iy, iz;
                     float fx, fy, fz;
-                    corner_idx(d, an, cx, cy, cz, ix, iy, iz, fx, fy, fz);
+                    if (!sample_corner<WARP>(d, w, tau, qx, qy, qz, ix, iy, iz, fx, fy, fz))
+                        continue;
                     const int lx = ix - x0, ly = iy - y0, lz = iz - z0;
-                    const bool z_0 = lz >= 0 && lz < ez, z_1 = lz + 1 >= 0 && lz + 1 < ez;
-                    // no corner in the brick
-                    if (!(lx >= -1 && lx < ex && ly >= -1 && ly < ey && (z_0 || z_1))) continue;
-                    // corner weights in FP64 with the ray weight and the
-                    // fixed-point scale folded in: one FMA per corner below.
-                    // x and y neighbours outside the brick land in the halo;
-                    // a z neighbour outside gets weight zero and a plane
-                    // clamped into the brick (adding an integer zero changes
-                    // no sum), so every lane issues the same eight atomics.
-                    const double gx1 = fx, gx0 = 1.0f - fx;
-                    const double gy1 = fy, gy0 = 1.0f - fy;
-                    const double gz1 = (z_1 ? fz : 0.0f) * cws,
-                                 gz0 = (z_0 ? 1.0f - fz : 0.0f) * cws;
-                    const double w00 = gz0 * gy0, w01 = gz0 * gy1, w10 = gz1 * gy0,
-                                 w11 = gz1 * gy1;
+                    // no corner in the brick: lx, ly outside [-1, e - 1] (the
+                    // halo takes -1 and e - 1's upper neighbour), or lz
+                    // outside [-1, ez - 1]
+                    if (static_cast<uint32_t>(lx + 1) > static_cast<uint32_t>(ex) ||
+                        static_cast<uint32_t>(ly + 1) > static_cast<uint32_t>(ey) ||
+                        static_cast<uint32_t>(lz + 1) > static_cast<uint32_t>(ez))
+                        continue;
+                    const bool z_0 = lz >= 0, z_1 = lz + 1 < ez;
+                    // corner weights in FP32 with the ray weight and the
+                    // fixed-point scale folded in; each contribution becomes a
+                    // 32-bit integer added into the 64-bit cell.  x and y
+                    // neighbours outside the brick land in the halo; a z
+                    // neighbour outside gets weight zero and a plane clamped
+                    // into the brick (adding an integer zero changes no sum),
+                    // so every lane issues the same eight atomics.
+                    const float gx1 = fx, gx0 = 1.0f - fx;
+                    const float gy1 = fy, gy0 = 1.0f - fy;
+                    const float gz1 = (z_1 ? fz : 0.0f) * cwq, gz0 = (z_0 ? 1.0f - fz : 0.0f) * cwq;
+                    const float w00 = gz0 * gy0, w01 = gz0 * gy1, w10 = gz1 * gy0, w11 = gz1 * gy1;
                     const int row = __mul24(ly, LDS_SY) + lx;
                     unsigned long long *const a0 = cell0 + (__mul24(max(lz, 0), LDS_SZ) + row);
                     unsigned long long *const a1 =
                         cell0 + (__mul24(min(lz + 1, ez - 1), LDS_SZ) + row);
-                    atomicAdd(a0, to_fixed(w00, gx0));
-                    atomicAdd(a0 + 1, to_fixed(w00, gx1));
-                    atomicAdd(a0 + LDS_SY, to_fixed(w01, gx0));
-                    atomicAdd(a0 + LDS_SY + 1, to_fixed(w01, gx1));
-                    atomicAdd(a1, to_fixed(w10, gx0));
-                    atomicAdd(a1 + 1, to_fixed(w10, gx1));
-                    atomicAdd(a1 + LDS_SY, to_fixed(w11, gx0));
-                    atomicAdd(a1 + LDS_SY + 1, to_fixed(w11, gx1));
+                    atomicAdd(a0, to_fixed(w00 * gx0));
+                    atomicAdd(a0 + 1, to_fixed(w00 * gx1));
+                    atomicAdd(a0 + LDS_SY, to_fixed(w01 * gx0));
+                    atomicAdd(a0 + LDS_SY + 1, to_fixed(w01 * gx1));
+                    atomicAdd(a1, to_fixed(w10 * gx0));
+                    atomicAdd(a1 + 1, to_fixed(w10 * gx1));
+                    atomicAdd(a1 + LDS_SY, to_fixed(w11 * gx0));
+                    atomicAdd(a1 + LDS_SY + 1, to_fixed(w11 * gx1));
                 }
             }
         }

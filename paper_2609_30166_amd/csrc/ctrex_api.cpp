@@ -144,7 +144,11 @@ WarpGrid make_warp(const ctrex_ctx *c) {
     w.sx = c->d_U ? double(c->gx - 1) / double(c->nx - 1) : 0.0;
     w.sy = c->d_U ? double(c->gy - 1) / double(c->ny - 1) : 0.0;
     w.sz = c->d_U ? double(c->gz - 1) / double(c->nz - 1) : 0.0;
+    w.fsx = static_cast<float>(w.sx);
+    w.fsy = static_cast<float>(w.sy);
+    w.fsz = static_cast<float>(w.sz);
     w.margin = c->d_U ? c->warp_margin : 0;
+    w.umax = c->d_U ? c->warp_umax : 0.0;
     return w;
 }
 
@@ -409,6 +413,8 @@ int ctrex_set_geometry(ctrex_ctx *c, const double *P, int32_t n_proj, int32_t n_
     if (n_proj < 1 || n_sub < 1 || n_u < 1 || n_v < 1)
         return fail(c, CTREX_ESHAPE, "n_proj, n_sub, n_u, n_v must be >= 1");
     if (nx < 2 || ny < 2 || nz < 2) return fail(c, CTREX_ESHAPE, "volume sides must be >= 2");
+    if (nx >= (1 << 22) || ny >= (1 << 22) || nz >= (1 << 22))
+        return fail(c, CTREX_ESHAPE, "volume sides must be < 2^22");
     if (static_cast<long long>(nx) * ny * nz >= (1ll << 31))
         return fail(c, CTREX_ESHAPE, "volume of %lld voxels exceeds 2^31 - 1",
                     static_cast<long long>(nx) * ny * nz);
@@ -537,6 +543,7 @@ int ctrex_set_motion(ctrex_ctx *c, const float *U_dev, int32_t gx, int32_t gy, i
     CTREX_HIP(c, hipMalloc(&c->d_U, sizeof(float4) * nodes));
     CTREX_HIP(c, launch_repack_warp(U_dev, c->d_U, nodes, nullptr));
     c->warp_margin = static_cast<int>(std::ceil(bound * (1.0 + 1e-6) + 1e-6));
+    c->warp_umax = umax;
     for (size_t k = 0; k < c->tab.size(); ++k) c->tab[k].tau = tau[k];
     CTREX_HIP(c, hipMemcpy(c->d_tab, c->tab.data(), sizeof(SubView) * c->tab.size(),
                            hipMemcpyHostToDevice));

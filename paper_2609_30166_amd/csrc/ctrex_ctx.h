@@ -44,6 +44,7 @@ struct ctrex_ctx {
     const float *d_vw = nullptr;   // caller's voxel weights (weighted backprojection)
     int gx = 0, gy = 0, gz = 0;
     int warp_margin = 0;  // ceil(max |tau| * max |U component|)
+    double warp_umax = 0.0;  // max |U component|
     // cached device view lists (most recent first)
     std::list<ctrex::DeviceViewList> lists;
     // small fixed-size device scratch, allocated by ctrex_create

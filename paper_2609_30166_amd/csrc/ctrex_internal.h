@@ -44,7 +44,9 @@ struct WarpGrid {
     const float4 *U;     // repacked [gz][gy][gx] (x, y, z, 0), or nullptr
     int gx, gy, gz;
     double sx, sy, sz;   // index -> grid coordinate scale (g - 1) / (n - 1)
+    float fsx, fsy, fsz; // the same scales in FP32 (used by the sample loops)
     int margin;          // whole voxels bounding |tau * U| on every axis
+    double umax;         // max |U component| (a sub-view moves samples by <= |tau| umax)
 };
 
 

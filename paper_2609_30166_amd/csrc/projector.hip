@@ -9,11 +9,12 @@
 //
 // Per ray (Sec. 4.1, projection operator; Sec. 2.2 geometry):
 //   FP64: direction M^-1 (u, v, 1), slab clip to the voxel-centre hull,
-//         n = ceil(L / step), h = L / n, samples t_in + (i + 1/2) h, and an
-//         anchor (integer voxel + FP32 remainder) every SEG samples;
-//   FP32: sample offsets from the anchor, optional warp
-//         c' = c + tau U(c) (Sec. 3.1, 4.2.1), trilinear lookups, FP32
-//         accumulation; sub-views averaged (Sec. 3.4, 4.2.2).
+//         n = ceil(L / step), h = L / n, samples t_in + (i + 1/2) h, the
+//         first sample and the step rounded to 64-bit fixed point;
+//   integer: sample positions stepped exactly in fixed point;
+//   FP32: fractions, optional warp c' = c + tau U(c) (Sec. 3.1, 4.2.1),
+//         trilinear lookups, FP32 accumulation; sub-views averaged
+//         (Sec. 3.4, 4.2.2).
 // The backprojector (backproject.hip) walks the same samples with the same
 // arithmetic, so it is the transpose of this operator sample by sample.
 
@@ -69,9 +70,28 @@ __device__ __forceinline__ float gather_pk(const void *__restrict__ pk, const Vo
         return gather_p2<TV>(static_cast<const uint2 *>(pk), d, k);
 }
 
+// Value of the sample at fixed-point position (px, py, pz): its trilinear
+// lookup (0 for a warped sample outside the hull; in the ray-length mode, 1
+// inside and 0 outside).  TL: gather from the y-fastest copy; PK: from the
+// corner-packed copy `pk` (y-fastest when TL; element type by TV).
+template <typename TV, int MODE, bool WARP, bool TL, bool PK>
+__device__ __forceinline__ float sample_value(const TV *__restrict__ vol,
+                                              const void *__restrict__ pk, const VolDims &d,
+                                              const WarpGrid &w, float tau, long long px,
+                                              long long py, long long pz) {
+    int ix, iy, iz;
+    Corner k;
+    const bool in = sample_corner<WARP>(d, w, tau, px, py, pz, ix, iy, iz, k.fx, k.fy, k.fz);
+    if (MODE == FP_RECIP_ONES) return in ? 1.0f : 0.0f;
+    k.base = TL ? base_t(d, ix, iy, iz) : base_x(d, ix, iy, iz);
+    const float v = PK   ? gather_pk<TV>(pk, d, k)
+                    : TL ? gather_t(vol, d, k)
+                         : gather(vol, d, k);
+    return in ? v : 0.0f;
+}
+
 // One ray's projection value: the mean over sub-views of the step-weighted
-// trilinear samples.  TL: gather from the y-fastest copy of the volume; PK:
-// from the corner-packed copy `pk` (y-fastest when TL; element type by TV).
+// trilinear samples, two samples per loop iteration (independent gathers).
 template <typename TV, int MODE, bool WARP, bool TL, bool PK>
 __device__ __forceinline__ float march(const RayGrid &g, const WarpGrid &w,
                                        const TV *__restrict__ vol,
@@ -86,62 +106,17 @@ __device__ __forceinline__ float march(const RayGrid &g, const WarpGrid &w,
             continue;
         const float tau = static_cast<float>(sv.tau);
         float acc0 = 0.0f, acc1 = 0.0f;
-        for (int i0 = 0; i0 < r.n; i0 += SEG) {
-            const Anchor an = anchor_at(r, i0);
-            GridAnchor ga;
-            if (WARP) ga = grid_anchor(w, r, i0);
-            const int cnt = min(SEG, r.n - i0);
-            int j = 0;
-            for (; j + 1 < cnt; j += 2) {
-                const float j0 = static_cast<float>(j), j1 = j0 + 1.0f;
-                float ax = fmaf(j0, r.fx, an.ax), ay = fmaf(j0, r.fy, an.ay),
-                      az = fmaf(j0, r.fz, an.az);
-                float bx = fmaf(j1, r.fx, an.ax), by = fmaf(j1, r.fy, an.ay),
-                      bz = fmaf(j1, r.fz, an.az);
-                bool ina = true, inb = true;
-                if (WARP) {
-                    ina = warp(w, d, tau, an, ga, j0, ax, ay, az);
-                    inb = warp(w, d, tau, an, ga, j1, bx, by, bz);
-                }
-                if (MODE == FP_RECIP_ONES) {
-                    acc0 += ina ? 1.0f : 0.0f;
-                    acc1 += inb ? 1.0f : 0.0f;
-                } else {
-                    float va, vb;
-                    if (PK) {
-                        va = gather_pk<TV>(pk, d, TL ? corner_of_t(d, an, ax, ay, az)
-                                                 : corner_of(d, an, ax, ay, az));
-                        vb = gather_pk<TV>(pk, d, TL ? corner_of_t(d, an, bx, by, bz)
-                                                 : corner_of(d, an, bx, by, bz));
-                    } else if (TL) {
-                        va = gather_t(vol, d, corner_of_t(d, an, ax, ay, az));
-                        vb = gather_t(vol, d, corner_of_t(d, an, bx, by, bz));
-                    } else {
-                        va = gather(vol, d, corner_of(d, an, ax, ay, az));
-                        vb = gather(vol, d, corner_of(d, an, bx, by, bz));
-                    }
-                    acc0 += ina ? va : 0.0f;
-                    acc1 += inb ? vb : 0.0f;
-                }
-            }
-            if (j < cnt) {
-                const float j0 = static_cast<float>(j);
-                float ax = fmaf(j0, r.fx, an.ax), ay = fmaf(j0, r.fy, an.ay),
-                      az = fmaf(j0, r.fz, an.az);
-                bool ina = true;
-                if (WARP) ina = warp(w, d, tau, an, ga, j0, ax, ay, az);
-                if (MODE == FP_RECIP_ONES) {
-                    acc0 += ina ? 1.0f : 0.0f;
-                } else {
-                    const float va =
-                        PK ? gather_pk<TV>(pk, d, TL ? corner_of_t(d, an, ax, ay, az)
-                                                 : corner_of(d, an, ax, ay, az))
-                        : TL ? gather_t(vol, d, corner_of_t(d, an, ax, ay, az))
-                             : gather(vol, d, corner_of(d, an, ax, ay, az));
-                    acc0 += ina ? va : 0.0f;
-                }
-            }
+        long long px = r.qx, py = r.qy, pz = r.qz;
+        int i = 0;
+        for (; i + 1 < r.n; i += 2) {
+            acc0 += sample_value<TV, MODE, WARP, TL, PK>(vol, pk, d, w, tau, px, py, pz);
+            acc1 += sample_value<TV, MODE, WARP, TL, PK>(vol, pk, d, w, tau, px + r.tx,
+                                                         py + r.ty, pz + r.tz);
+            px += 2 * r.tx;
+            py += 2 * r.ty;
+            pz += 2 * r.tz;
         }
+        if (i < r.n) acc0 += sample_value<TV, MODE, WARP, TL, PK>(vol, pk, d, w, tau, px, py, pz);
         y = fmaf(r.h, acc0 + acc1, y);
     }
     return y / static_cast<float>(g.n_sub);

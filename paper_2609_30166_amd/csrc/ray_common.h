@@ -26,27 +26,41 @@ __device__ __forceinline__ void st(bf16_t *p, int i, float v) { p[i].bits = f32_
 __device__ __forceinline__ void st(_Float16 *p, int i, float v) { p[i] = static_cast<_Float16>(v); }
 
 // ------------------------------------------------------------- ray set-up --
-// Sample i of a ray sits at b + i * s (index coordinates, FP64).  Positions
-// are never formed in absolute FP32 (its ulp at coordinate 512 is 3e-5):
-// every segment of SEG consecutive samples starts from an FP64 anchor split
-// into an integer voxel and an FP32 remainder in [0, 1), and the samples of
-// the segment are the anchor remainder plus j * s in FP32 (|j| < SEG), which
-// keeps positions within about 1e-6 voxel.  Forward and back projection use
-// the same arithmetic, so their samples agree bit for bit.
-constexpr int SEG = 32;
+// Sample i of a ray sits at b + i s (index coordinates).  The FP64 set-up
+// rounds b and s once to signed 64-bit fixed point with FX = 40 fractional
+// bits; every sample position is then the exact integer q + i t, reached by
+// stepping (q += t) in the forward projector and by one multiply-add or by
+// stepping in the backprojector, so both see the same sample bit for bit.
+// Against FP64 the positions are off by at most 2^-41 (the rounding of q)
+// plus i 2^-41 (that of t): under 1e-8 voxel for 4096 samples and under
+// 1e-5 voxel at the 2^24-sample limit.  The integer voxel is the top word
+// shifted, the fraction its next 32 bits rounded to FP32: no FP64 in the
+// sample loops and no re-anchoring along the ray.
+constexpr int FX = 40;
 
 struct Ray {
-    double bx, by, bz;  // position of sample 0
-    double sx, sy, sz;  // step vector h * d
-    float fx, fy, fz;   // step vector in FP32
-    float h;            // sample weight (path length per sample)
-    int n;              // number of samples
+    double bx, by, bz;      // position of sample 0 (FP64)
+    double sx, sy, sz;      // step vector h * d (FP64)
+    long long qx, qy, qz;   // position of sample 0, fixed point
+    long long tx, ty, tz;   // step vector, fixed point
+    float fx, fy, fz;       // step vector in FP32 (range estimates only)
+    float h;                // sample weight (path length per sample)
+    int n;                  // number of samples
 };
 
-struct Anchor {
-    int ix, iy, iz;     // integer part of the segment's first sample
-    float ax, ay, az;   // remainder in [0, 1)
-};
+__device__ __forceinline__ long long to_fx(double v) {
+    return static_cast<long long>(rint(v * 1099511627776.0));   // v 2^FX, to nearest
+}
+
+// Integer voxel k = floor(p) and fraction f = p - k of a fixed-point
+// coordinate: k from the top word, f from the top 32 fraction bits rounded to
+// FP32 (so f may round up to 1.0, which the corner weights treat like any
+// other fraction: weight 1 on the upper corner).
+__device__ __forceinline__ void fx_split(long long p, int &k, float &f) {
+    const unsigned long long u = static_cast<unsigned long long>(p);
+    k = static_cast<int>(static_cast<uint32_t>(u >> 32)) >> (FX - 32);
+    f = static_cast<float>(static_cast<uint32_t>(u >> (FX - 32))) * 2.3283064365386963e-10f;  // 2^-32
+}
 
 // FP64 clipping of one axis' slab.  Returns false when the ray misses.
 __device__ __forceinline__ bool slab(double s, double d, double hi, double &t0, double &t1) {
@@ -92,27 +106,18 @@ __device__ __forceinline__ bool setup_ray(const SubView &sv, double u, double v,
     r.sx = h * dx;
     r.sy = h * dy;
     r.sz = h * dz;
+    r.qx = to_fx(r.bx);
+    r.qy = to_fx(r.by);
+    r.qz = to_fx(r.bz);
+    r.tx = to_fx(r.sx);
+    r.ty = to_fx(r.sy);
+    r.tz = to_fx(r.sz);
     r.fx = static_cast<float>(r.sx);
     r.fy = static_cast<float>(r.sy);
     r.fz = static_cast<float>(r.sz);
     r.h = static_cast<float>(h);
     r.n = static_cast<int>(nd);
     return true;
-}
-
-// Anchor of the segment whose first sample is i.
-__device__ __forceinline__ Anchor anchor_at(const Ray &r, int i) {
-    const double di = static_cast<double>(i);
-    const double px = fma(di, r.sx, r.bx), py = fma(di, r.sy, r.by), pz = fma(di, r.sz, r.bz);
-    const double fx = floor(px), fy = floor(py), fz = floor(pz);
-    Anchor a;
-    a.ix = static_cast<int>(fx);
-    a.iy = static_cast<int>(fy);
-    a.iz = static_cast<int>(fz);
-    a.ax = static_cast<float>(px - fx);
-    a.ay = static_cast<float>(py - fy);
-    a.az = static_cast<float>(pz - fz);
-    return a;
 }
 
 // ------------------------------------------------------------ trilinear ----
@@ -151,22 +156,24 @@ __device__ __forceinline__ bool axis_inside(int i, float l, int n) {
     return k >= 0 && (k < n - 1 || (k == n - 1 && l == fl));
 }
 
-// Corner of the sample at local offsets (lx, ly, lz) from anchor a.
-__device__ __forceinline__ void corner_idx(const VolDims &d, const Anchor &a, float lx, float ly,
-                                           float lz, int &ix, int &iy, int &iz, float &fx,
-                                           float &fy, float &fz) {
-    axis_corner(a.ix, lx, d.nx, ix, fx);
-    axis_corner(a.iy, ly, d.ny, iy, fy);
-    axis_corner(a.iz, lz, d.nz, iz, fz);
+// The same for a position already split into k + f with f in [0, 1): only
+// the clamps (k < 0 rounds onto the first corner with weight 0 on the next;
+// k > n - 2 is the last face, weight 1 on it).
+__device__ __forceinline__ void axis_clamp(int k, float f, int n, int &kc, float &fc) {
+    kc = k;
+    fc = f;
+    if (k < 0) {
+        kc = 0;
+        fc = 0.0f;
+    }
+    if (k > n - 2) {
+        kc = n - 2;
+        fc = 1.0f;
+    }
 }
 
-__device__ __forceinline__ Corner corner_of(const VolDims &d, const Anchor &a, float lx, float ly,
-                                            float lz) {
-    int ix, iy, iz;
-    Corner k;
-    corner_idx(d, a, lx, ly, lz, ix, iy, iz, k.fx, k.fy, k.fz);
-    k.base = (iz * d.ny + iy) * d.nx + ix;
-    return k;
+__device__ __forceinline__ int base_x(const VolDims &d, int ix, int iy, int iz) {
+    return (iz * d.ny + iy) * d.nx + ix;
 }
 
 // Trilinear blend of the eight corner values (x first, then y, then z).
@@ -210,13 +217,8 @@ __device__ __forceinline__ float gather<float>(const float *__restrict__ vol, co
 // for projections whose rays run mainly along x: a wave's samples then spread
 // over y and z, and with y fastest its neighbouring samples share cache lines
 // again.  The corner values and the blend are exactly those of `gather`.
-__device__ __forceinline__ Corner corner_of_t(const VolDims &d, const Anchor &a, float lx,
-                                              float ly, float lz) {
-    int ix, iy, iz;
-    Corner k;
-    corner_idx(d, a, lx, ly, lz, ix, iy, iz, k.fx, k.fy, k.fz);
-    k.base = (iz * d.nx + ix) * d.ny + iy;
-    return k;
+__device__ __forceinline__ int base_t(const VolDims &d, int ix, int iy, int iz) {
+    return (iz * d.nx + ix) * d.ny + iy;
 }
 
 template <typename TV>
@@ -248,49 +250,20 @@ __device__ __forceinline__ bool x_major(const SubView &sv, double u, double v) {
 }
 
 // ----------------------------------------------------------------- warp ----
-// The displacement grid is anchored like the ray: per segment, the grid
-// coordinate (b + i s) (g - 1) / (n - 1) of its first sample is split in FP64
-// into an integer node and an FP32 remainder, and the samples of the segment
-// add j times the FP32 grid step, so the trilinear weights of U are as exact
-// as the sample positions.
-struct GridAnchor {
-    int ix, iy, iz;      // integer grid node of the segment's first sample
-    float ax, ay, az;    // remainder in [0, 1)
-    float sx, sy, sz;    // grid step per sample
-};
-
-__device__ __forceinline__ GridAnchor grid_anchor(const WarpGrid &w, double bx, double by,
-                                                  double bz, double sx, double sy, double sz,
-                                                  int i) {
-    const double di = static_cast<double>(i);
-    const double px = fma(di, sx, bx) * w.sx, py = fma(di, sy, by) * w.sy,
-                 pz = fma(di, sz, bz) * w.sz;
-    const double fx = floor(px), fy = floor(py), fz = floor(pz);
-    GridAnchor a;
-    a.ix = static_cast<int>(fx);
-    a.iy = static_cast<int>(fy);
-    a.iz = static_cast<int>(fz);
-    a.ax = static_cast<float>(px - fx);
-    a.ay = static_cast<float>(py - fy);
-    a.az = static_cast<float>(pz - fz);
-    a.sx = static_cast<float>(sx * w.sx);
-    a.sy = static_cast<float>(sy * w.sy);
-    a.sz = static_cast<float>(sz * w.sz);
-    return a;
-}
-
-__device__ __forceinline__ GridAnchor grid_anchor(const WarpGrid &w, const Ray &r, int i) {
-    return grid_anchor(w, r.bx, r.by, r.bz, r.sx, r.sy, r.sz, i);
-}
-
-// Displacement at local sample j of the anchored segment (trilinear over the
-// node grid, lookups clamped to the grid).
-__device__ __forceinline__ float3 displacement(const WarpGrid &w, const GridAnchor &ga, float j) {
+// Displacement at the sample k + f (per axis: integer voxel and fraction):
+// the node grid coordinate (k + f) (g - 1) / (n - 1) is formed in FP32 (it
+// is at most g - 1, so its rounding is ~2^-19 of a grid cell) and U is
+// interpolated trilinearly there, lookups clamped to the grid.
+__device__ __forceinline__ float3 displacement(const WarpGrid &w, int kx, float fx, int ky,
+                                               float fy, int kz, float fz) {
+    const float gx = fmaf(fx, w.fsx, static_cast<float>(kx) * w.fsx);
+    const float gy = fmaf(fy, w.fsy, static_cast<float>(ky) * w.fsy);
+    const float gz = fmaf(fz, w.fsz, static_cast<float>(kz) * w.fsz);
     int ix, iy, iz;
-    float fx, fy, fz;
-    axis_corner(ga.ix, fmaf(j, ga.sx, ga.ax), w.gx, ix, fx);
-    axis_corner(ga.iy, fmaf(j, ga.sy, ga.ay), w.gy, iy, fy);
-    axis_corner(ga.iz, fmaf(j, ga.sz, ga.az), w.gz, iz, fz);
+    float ax, ay, az;
+    axis_corner(0, gx, w.gx, ix, ax);
+    axis_corner(0, gy, w.gy, iy, ay);
+    axis_corner(0, gz, w.gz, iz, az);
     const int sy = w.gx, sz = w.gx * w.gy;
     const int b = (iz * w.gy + iy) * w.gx + ix;
     const float4 u000 = w.U[b], u001 = w.U[b + 1], u010 = w.U[b + sy], u011 = w.U[b + sy + 1];
@@ -299,13 +272,13 @@ __device__ __forceinline__ float3 displacement(const WarpGrid &w, const GridAnch
     float3 r;
 #define CTREX_LERP3(c)                                              \
     {                                                               \
-        const float a00 = fmaf(fx, u001.c - u000.c, u000.c);        \
-        const float a01 = fmaf(fx, u011.c - u010.c, u010.c);        \
-        const float a10 = fmaf(fx, u101.c - u100.c, u100.c);        \
-        const float a11 = fmaf(fx, u111.c - u110.c, u110.c);        \
-        const float b0 = fmaf(fy, a01 - a00, a00);                  \
-        const float b1 = fmaf(fy, a11 - a10, a10);                  \
-        r.c = fmaf(fz, b1 - b0, b0);                                \
+        const float a00 = fmaf(ax, u001.c - u000.c, u000.c);        \
+        const float a01 = fmaf(ax, u011.c - u010.c, u010.c);        \
+        const float a10 = fmaf(ax, u101.c - u100.c, u100.c);        \
+        const float a11 = fmaf(ax, u111.c - u110.c, u110.c);        \
+        const float b0 = fmaf(ay, a01 - a00, a00);                  \
+        const float b1 = fmaf(ay, a11 - a10, a10);                  \
+        r.c = fmaf(az, b1 - b0, b0);                                \
     }
     CTREX_LERP3(x)
     CTREX_LERP3(y)
@@ -314,17 +287,40 @@ __device__ __forceinline__ float3 displacement(const WarpGrid &w, const GridAnch
     return r;
 }
 
-// Pull-back warp of local sample j (Sec. 3.1): l += tau U(sample); false if
-// the warped sample leaves the hull.
-__device__ __forceinline__ bool warp(const WarpGrid &w, const VolDims &d, float tau,
-                                     const Anchor &a, const GridAnchor &ga, float j, float &lx,
-                                     float &ly, float &lz) {
-    const float3 u = displacement(w, ga, j);
-    lx = fmaf(tau, u.x, lx);
-    ly = fmaf(tau, u.y, ly);
-    lz = fmaf(tau, u.z, lz);
-    return axis_inside(a.ix, lx, d.nx) && axis_inside(a.iy, ly, d.ny) &&
-           axis_inside(a.iz, lz, d.nz);
+// Lower corner (ix, iy, iz) and fractions of the sample at fixed-point
+// position (px, py, pz), after the pull-back warp c + tau U(c) (Sec. 3.1)
+// when WARP; false if the warped sample leaves the hull.  The corner is
+// always set and clamped into the grid, also for a sample outside (callers
+// may form its address before discarding its value).  The forward and back
+// projectors call this one function, so their corners and weights agree bit
+// for bit.
+template <bool WARP>
+__device__ __forceinline__ bool sample_corner(const VolDims &d, const WarpGrid &w, float tau,
+                                              long long px, long long py, long long pz, int &ix,
+                                              int &iy, int &iz, float &fx, float &fy,
+                                              float &fz) {
+    int kx, ky, kz;
+    float lx, ly, lz;
+    fx_split(px, kx, lx);
+    fx_split(py, ky, ly);
+    fx_split(pz, kz, lz);
+    if (WARP) {
+        const float3 u = displacement(w, kx, lx, ky, ly, kz, lz);
+        lx = fmaf(tau, u.x, lx);
+        ly = fmaf(tau, u.y, ly);
+        lz = fmaf(tau, u.z, lz);
+        const bool in =
+            axis_inside(kx, lx, d.nx) && axis_inside(ky, ly, d.ny) && axis_inside(kz, lz, d.nz);
+        axis_corner(kx, lx, d.nx, ix, fx);
+        axis_corner(ky, ly, d.ny, iy, fy);
+        axis_corner(kz, lz, d.nz, iz, fz);
+        return in;
+    } else {
+        axis_clamp(kx, lx, d.nx, ix, fx);
+        axis_clamp(ky, ly, d.ny, iy, fy);
+        axis_clamp(kz, lz, d.nz, iz, fz);
+    }
+    return true;
 }
 
 // ------------------------------------------------------------- tiling ------
