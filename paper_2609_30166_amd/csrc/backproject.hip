@@ -54,6 +54,24 @@ constexpr int LDS_SZ = LDS_SY * (BRICK_Y + 2);
 constexpr int LDS_CELLS = LDS_SZ * BRICK_Z;
 static_assert(LDS_SZ % 16 == 3, "plane stride");
 
+// Owner-computes bricks (the default form): a brick takes exactly the
+// samples whose lower corner lies in it, so every sample is walked once and
+// issues its eight atomics once, into LDS cells for the brick's voxels plus
+// one halo layer on the high side of each axis (33 x 17 x 17 cells, 76.3 KB;
+// row and plane strides 1 mod 16).  Every brick then adds its cells, halo
+// included, into a 64-bit integer volume with global atomics; integer sums
+// are exact, so neighbours' halos and projection chunks combine in any order
+// and the result stays bitwise reproducible.  All workgroups use one
+// fixed-point scale for that.  The direct form above (a sample walked by every
+// brick it touches, each brick writing only its own voxels) needs no
+// volume-sized buffer and serves the allocation-free entry point.
+constexpr int OWN_X = 32, OWN_Y = 16, OWN_Z = 16;
+constexpr int OWN_SY = OWN_X + 1;
+constexpr int OWN_SZ = OWN_SY * (OWN_Y + 1);
+constexpr int OWN_CELLS = OWN_SZ * (OWN_Z + 1);
+constexpr int MAX_CELLS = OWN_CELLS > LDS_CELLS ? OWN_CELLS : LDS_CELLS;
+static_assert(OWN_SY % 16 == 1 && OWN_SZ % 16 == 1, "owner strides");
+
 struct BrickGrid {
     int bx, by, bz;       // brick size (voxels), at most BRICK_X x BRICK_Y x BRICK_Z
     int nbx, nby, nbz;    // bricks per axis
@@ -63,8 +81,25 @@ struct BrickGrid {
     int accumulate;       // add into vol (else overwrite; needs chunks == 1)
     float wscale;         // every contribution is multiplied by this factor
     double cube_samples;  // max samples of one ray inside a side-2 cube
-    float *partials;      // [chunks][nx*ny*nz] per-chunk results when chunks > 1
+    float *partials;      // direct form: [chunks][nx*ny*nz] per-chunk results when chunks > 1
+    unsigned long long *acc64;  // owner form: the 64-bit integer volume the bricks add into
 };
+
+// Fixed-point exponent of the owner form, the same in every workgroup and in
+// the finishing pass: the largest contribution cmax at or below 2^30, and the
+// sum into any voxel below 2^62 (at most every ray of every listed sub-view
+// passes through the voxel's corner cube, each with at most cube_samples
+// samples there).
+__device__ __forceinline__ int own_kexp(double cmax, const RayGrid &g, double cube_samples) {
+    const double rays = static_cast<double>(g.n_views) * g.n_sub * g.n_u * g.n_v;
+    return static_cast<int>(floor(fmin(30.0 - log2(cmax), 62.0 - log2(rays * cube_samples * cmax))));
+}
+
+// Largest contribution of one sample to one corner: step * max|r| / n_sub
+// times the caller's factor (and a margin for FP32 rounding).
+__device__ __forceinline__ double contribution_bound(const RayGrid &g, double rmax, float wscale) {
+    return rmax * g.step * (1.0 + 1e-5) * fabs(static_cast<double>(wscale)) / g.n_sub;
+}
 
 // Project the 8 corners of an index-space box through the view matrix and
 // return the detector pixel range whose rays can cross the box.  When all
@@ -141,14 +176,14 @@ __device__ __forceinline__ long long shfl64(long long v, int src) {
     return __shfl(v, src, 64);
 }
 
-template <typename TS, int MODE, bool WARP>
+template <typename TS, int MODE, bool WARP, bool OWN>
 __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8))) void bp_brick_kernel(RayGrid g, WarpGrid w,
                                                               const double *__restrict__ Pmat,
                                                               const TS *__restrict__ sino,
                                                               const float *__restrict__ rmax,
                                                               float *__restrict__ vol,
                                                               BrickGrid bg) {
-    __shared__ unsigned long long acc[LDS_CELLS];
+    __shared__ unsigned long long acc[MAX_CELLS];
     __shared__ double red[BP_THREADS / 64];
     // ---- block -> (brick, projection chunk); XCD-aware so that one XCD
     // works on neighbouring bricks
@@ -163,10 +198,11 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
     const int ibz = b / bg.nby;
     const int x0 = ibx * bg.bx, y0 = iby * bg.by, z0 = ibz * bg.bz;
     const int ex = min(bg.bx, g.nx - x0), ey = min(bg.by, g.ny - y0), ez = min(bg.bz, g.nz - z0);
-    const int nlds = LDS_SZ * ez;
+    const int nlds = OWN ? OWN_CELLS : LDS_SZ * ez;
     for (int i = threadIdx.x; i < nlds; i += BP_THREADS) acc[i] = 0ull;
-    // cell (lx, ly, lz) of the brick, lx in [-1, ex], ly in [-1, ey]
-    unsigned long long *const cell0 = acc + LDS_SY + 1;
+    // cell (lx, ly, lz) of the brick: direct form lx in [-1, ex], ly in
+    // [-1, ey]; owner form lx in [0, ex], ly in [0, ey], lz in [0, ez]
+    unsigned long long *const cell0 = OWN ? acc : acc + LDS_SY + 1;
 
     const VolDims d = vol_dims(g);
     const float M = static_cast<float>(w.margin);
@@ -190,7 +226,7 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
     // contribution at or below 2^30 (so it fits a 32-bit integer) and keeps
     // the bound on the sums below 2^62.
     double nrays = 0.0;
-    for (int q = threadIdx.x; q < n_pairs; q += BP_THREADS) {
+    for (int q = threadIdx.x; q < (OWN ? 0 : n_pairs); q += BP_THREADS) {
         const int k = k_first + q / g.n_sub;
         const int p = g.views ? g.views[k] : k;
         const int sv_idx = p * g.n_sub + q % g.n_sub;
@@ -206,14 +242,15 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
     __syncthreads();
     nrays = 0.0;
     for (int i = 0; i < BP_THREADS / 64; ++i) nrays += red[i];
-    const double cmax = ((MODE == BP_ONES) ? 1.0 : static_cast<double>(*rmax)) * g.step *
-                        (1.0 + 1e-5) * fabs(static_cast<double>(bg.wscale)) / g.n_sub;
-    const double bound = nrays * bg.cube_samples * cmax;
+    const double cmax =
+        contribution_bound(g, (MODE == BP_ONES) ? 1.0 : static_cast<double>(*rmax), bg.wscale);
+    const double bound = OWN ? cmax : nrays * bg.cube_samples * cmax;
     const bool bad = !(cmax < __builtin_inf());   // NaN or Inf in the input: propagate NaN
     const bool any = uni(static_cast<int>(bound > 0.0 && !bad)) != 0;
-    const int kexp = uni(any ? static_cast<int>(floor(fmin(30.0 - log2(cmax),
-                                                           62.0 - log2(bound))))
-                             : 0);
+    const int kexp = uni(!any ? 0
+                         : OWN ? own_kexp(cmax, g, bg.cube_samples)
+                               : static_cast<int>(floor(fmin(30.0 - log2(cmax),
+                                                             62.0 - log2(bound)))));
     const double scale = uni(ldexp(1.0, kexp));
 
     // each wave takes whole (projection, sub-view) pairs, so a pair's pixel
@@ -231,7 +268,10 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
             // touch it (time-linear fields: half the scan's bound on average)
             const double mv = WARP ? fabs(sv.tau) * w.umax : 0.0;
             const float Mp = uni(mv > 0.0 ? static_cast<float>(ceil(mv * (1.0 + 1e-6) + 1e-6)) : 0.0f);
-            const float lo[3] = {uni(x0 - 1.0f - Mp), uni(y0 - 1.0f - Mp), uni(z0 - 1.0f - Mp)};
+            // direct form: samples with a corner in the brick, position in
+            // [x0 - 1, x0 + ex]; owner form: lower corner in it, [x0, x0 + ex]
+            const float g0 = OWN ? 0.0f : 1.0f;
+            const float lo[3] = {uni(x0 - g0 - Mp), uni(y0 - g0 - Mp), uni(z0 - g0 - Mp)};
             const float hi[3] = {uni(static_cast<float>(x0 + ex) + Mp),
                                  uni(static_cast<float>(y0 + ey) + Mp),
                                  uni(static_cast<float>(z0 + ez) + Mp)};
@@ -357,6 +397,30 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
                     if (!sample_corner<WARP>(d, w, tau, qx, qy, qz, ix, iy, iz, fx, fy, fz))
                         continue;
                     const int lx = ix - x0, ly = iy - y0, lz = iz - z0;
+                    if (OWN) {
+                        // another brick owns this sample's lower corner
+                        if (static_cast<uint32_t>(lx) >= static_cast<uint32_t>(ex) ||
+                            static_cast<uint32_t>(ly) >= static_cast<uint32_t>(ey) ||
+                            static_cast<uint32_t>(lz) >= static_cast<uint32_t>(ez))
+                            continue;
+                        const float gx1 = fx, gx0 = 1.0f - fx;
+                        const float gy1 = fy, gy0 = 1.0f - fy;
+                        const float gz1 = fz * cwq, gz0 = (1.0f - fz) * cwq;
+                        const float w00 = gz0 * gy0, w01 = gz0 * gy1, w10 = gz1 * gy0,
+                                    w11 = gz1 * gy1;
+                        unsigned long long *const a0 =
+                            cell0 + (__mul24(lz, OWN_SZ) + __mul24(ly, OWN_SY) + lx);
+                        unsigned long long *const a1 = a0 + OWN_SZ;
+                        atomicAdd(a0, to_fixed(w00 * gx0));
+                        atomicAdd(a0 + 1, to_fixed(w00 * gx1));
+                        atomicAdd(a0 + OWN_SY, to_fixed(w01 * gx0));
+                        atomicAdd(a0 + OWN_SY + 1, to_fixed(w01 * gx1));
+                        atomicAdd(a1, to_fixed(w10 * gx0));
+                        atomicAdd(a1 + 1, to_fixed(w10 * gx1));
+                        atomicAdd(a1 + OWN_SY, to_fixed(w11 * gx0));
+                        atomicAdd(a1 + OWN_SY + 1, to_fixed(w11 * gx1));
+                        continue;
+                    }
                     // no corner in the brick: lx, ly outside [-1, e - 1] (the
                     // halo takes -1 and e - 1's upper neighbour), or lz
                     // outside [-1, ez - 1]
@@ -393,6 +457,21 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
         }
     }
     __syncthreads();
+    if (OWN) {
+        // ---- add the brick's cells, halo included, into the integer volume
+        for (int i = threadIdx.x; i < OWN_CELLS; i += BP_THREADS) {
+            const int lz = i / OWN_SZ;
+            const int rem = i - lz * OWN_SZ;
+            const int ly = rem / OWN_SY;
+            const int lx = rem - ly * OWN_SY;
+            const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+            const unsigned long long q = acc[i];
+            if (q != 0ull && lx <= ex && ly <= ey && lz <= ez && gx < g.nx && gy < g.ny &&
+                gz < g.nz)
+                atomicAdd(bg.acc64 + (static_cast<size_t>(gz) * g.ny + gy) * g.nx + gx, q);
+        }
+        return;
+    }
     // ---- write the brick out (x fastest)
     const double inv_scale = ldexp(1.0, -kexp);
     const int nvox = ex * ey * ez;
@@ -427,11 +506,31 @@ __global__ __launch_bounds__(256) void sum_chunks_kernel(const float *__restrict
     }
 }
 
-BrickGrid plan_bricks(const RayGrid &g, int cap_chunks) {
+// Owner form: vol[i] = (vol[i] if accumulate) + acc64[i] 2^-kexp, NaN for a
+// non-finite max |r|, with the exponent every brick used.
+template <int MODE>
+__global__ __launch_bounds__(256) void own_finish_kernel(const unsigned long long *__restrict__ acc64,
+                                                         size_t n, const float *__restrict__ rmax,
+                                                         RayGrid g, double cube_samples,
+                                                         float wscale, int accumulate,
+                                                         float *__restrict__ vol) {
+    const double cmax =
+        contribution_bound(g, MODE == BP_ONES ? 1.0 : static_cast<double>(*rmax), wscale);
+    const bool bad = !(cmax < __builtin_inf());
+    const double inv = (cmax > 0.0 && !bad) ? ldexp(1.0, -own_kexp(cmax, g, cube_samples)) : 0.0;
+    const size_t stride = static_cast<size_t>(gridDim.x) * 256;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) {
+        const float v = bad ? __builtin_nanf("")
+                            : static_cast<float>(static_cast<double>(static_cast<long long>(acc64[i])) * inv);
+        vol[i] = accumulate ? vol[i] + v : v;
+    }
+}
+
+BrickGrid plan_bricks(const RayGrid &g, int cap_chunks, bool own) {
     BrickGrid bg;
-    bg.bx = min(BRICK_X, g.nx);
-    bg.by = min(BRICK_Y, g.ny);
-    bg.bz = min(BRICK_Z, g.nz);
+    bg.bx = min(own ? OWN_X : BRICK_X, g.nx);
+    bg.by = min(own ? OWN_Y : BRICK_Y, g.ny);
+    bg.bz = min(own ? OWN_Z : BRICK_Z, g.nz);
     bg.nbx = (g.nx + bg.bx - 1) / bg.bx;
     bg.nby = (g.ny + bg.by - 1) / bg.by;
     bg.nbz = (g.nz + bg.bz - 1) / bg.bz;
@@ -449,6 +548,7 @@ BrickGrid plan_bricks(const RayGrid &g, int cap_chunks) {
     // chord of at most 2 sqrt(3)
     bg.cube_samples = floor(4.0 * 1.7320508075688772 / g.step) + 1.0;
     bg.partials = nullptr;
+    bg.acc64 = nullptr;
     bg.accumulate = 0;
     bg.wscale = 1.0f;
     return bg;
@@ -456,66 +556,90 @@ BrickGrid plan_bricks(const RayGrid &g, int cap_chunks) {
 
 }  // namespace
 
-size_t back_scratch_bytes(const RayGrid &g, int max_chunks) {
+size_t back_scratch_bytes(const RayGrid &g, int max_chunks, bool direct) {
     if (g.n_views <= 0) return 0;
-    const BrickGrid bg = plan_bricks(g, max_chunks);
-    return bg.chunks > 1 ? sizeof(float) * static_cast<size_t>(bg.chunks) * g.nx * g.ny * g.nz : 0;
+    const size_t nvol = static_cast<size_t>(g.nx) * g.ny * g.nz;
+    if (!direct) return sizeof(unsigned long long) * nvol;
+    const BrickGrid bg = plan_bricks(g, max_chunks, false);
+    return bg.chunks > 1 ? sizeof(float) * static_cast<size_t>(bg.chunks) * nvol : 0;
 }
 
 hipError_t launch_back(const RayGrid &g, const WarpGrid &w, const double *Pmat, const void *sino,
                        int sino_dtype, float *vol, int accumulate, int mode, float *scratch,
-                       float *part, hipStream_t stream, float scale, int max_chunks) {
+                       void *work, hipStream_t stream, float scale, int max_chunks, bool direct) {
     if (g.n_views <= 0) return hipSuccess;
-    BrickGrid bg = plan_bricks(g, max_chunks);
+    BrickGrid bg = plan_bricks(g, direct ? max_chunks : 0, !direct);
     bg.accumulate = accumulate;
     bg.wscale = scale;
-    bg.partials = part;
-    if (bg.chunks > 1 && !part) return hipErrorInvalidValue;
+    const size_t nvol = static_cast<size_t>(g.nx) * g.ny * g.nz;
+    if (direct) {
+        bg.partials = static_cast<float *>(work);
+        if (bg.chunks > 1 && !work) return hipErrorInvalidValue;
+    } else {
+        bg.acc64 = static_cast<unsigned long long *>(work);
+        if (!work) return hipErrorInvalidValue;
+        hipError_t e = launch_fill_zero(work, sizeof(unsigned long long) * nvol, stream);
+        if (e != hipSuccess) return e;
+    }
     const int per = (bg.total + N_XCD - 1) / N_XCD;
     const dim3 grid(static_cast<unsigned>(per * N_XCD)), block(BP_THREADS);
     const size_t shmem = 0;   // the brick is static LDS
     const bool wp = w.U != nullptr;
-    const size_t nvol = static_cast<size_t>(g.nx) * g.ny * g.nz;
-    auto combine = [&]() -> hipError_t {
+    size_t fblocks = (nvol + 255) / 256;
+    if (fblocks > 65536) fblocks = 65536;
+    // after the bricks: the direct form's chunk partials summed in chunk
+    // order, or the owner form's integer volume scaled into vol
+    auto finish = [&](int m) -> hipError_t {
         hipError_t e = hipGetLastError();
-        if (e != hipSuccess || bg.chunks <= 1) return e;
-        size_t blocks = (nvol + 255) / 256;
-        if (blocks > 65536) blocks = 65536;
-        hipLaunchKernelGGL(sum_chunks_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
-                           stream, part, bg.chunks, nvol, accumulate, vol);
+        if (e != hipSuccess) return e;
+        if (!direct) {
+            if (m == BP_ONES)
+                hipLaunchKernelGGL(own_finish_kernel<BP_ONES>, dim3(static_cast<unsigned>(fblocks)),
+                                   dim3(256), 0, stream, bg.acc64, nvol, scratch, g,
+                                   bg.cube_samples, scale, accumulate, vol);
+            else
+                hipLaunchKernelGGL(own_finish_kernel<BP_PLAIN>,
+                                   dim3(static_cast<unsigned>(fblocks)), dim3(256), 0, stream,
+                                   bg.acc64, nvol, scratch, g, bg.cube_samples, scale, accumulate,
+                                   vol);
+            return hipGetLastError();
+        }
+        if (bg.chunks <= 1) return hipSuccess;
+        hipLaunchKernelGGL(sum_chunks_kernel, dim3(static_cast<unsigned>(fblocks)), dim3(256), 0,
+                           stream, bg.partials, bg.chunks, nvol, accumulate, vol);
         return hipGetLastError();
     };
-    if (mode == BP_ONES) {
-        if (wp)
-            hipLaunchKernelGGL((bp_brick_kernel<float, BP_ONES, true>), grid, block, shmem, stream,
-                               g, w, Pmat, nullptr, nullptr, vol, bg);
-        else
-            hipLaunchKernelGGL((bp_brick_kernel<float, BP_ONES, false>), grid, block, shmem,
-                               stream, g, w, Pmat, nullptr, nullptr, vol, bg);
-        return combine();
+#define CTREX_BP_LAUNCH(T, M, SP, RM)                                                           \
+    {                                                                                           \
+        if (direct) {                                                                           \
+            if (wp)                                                                             \
+                hipLaunchKernelGGL((bp_brick_kernel<T, M, true, false>), grid, block, shmem,    \
+                                   stream, g, w, Pmat, SP, RM, vol, bg);                        \
+            else                                                                                \
+                hipLaunchKernelGGL((bp_brick_kernel<T, M, false, false>), grid, block, shmem,   \
+                                   stream, g, w, Pmat, SP, RM, vol, bg);                        \
+        } else {                                                                                \
+            if (wp)                                                                             \
+                hipLaunchKernelGGL((bp_brick_kernel<T, M, true, true>), grid, block, shmem,     \
+                                   stream, g, w, Pmat, SP, RM, vol, bg);                        \
+            else                                                                                \
+                hipLaunchKernelGGL((bp_brick_kernel<T, M, false, true>), grid, block, shmem,    \
+                                   stream, g, w, Pmat, SP, RM, vol, bg);                        \
+        }                                                                                       \
+        return finish(M);                                                                       \
     }
+    if (mode == BP_ONES) CTREX_BP_LAUNCH(float, BP_ONES, nullptr, nullptr)
     // max |r| over the sinogram sets the fixed-point scale
     const size_t n_sino = static_cast<size_t>(g.n_views) * g.n_u * g.n_v;
     hipError_t e = launch_max_abs(sino, sino_dtype, n_sino, scratch, stream);
     if (e != hipSuccess) return e;
-#define CTREX_BP(T)                                                                              \
-    {                                                                                            \
-        const T *sp = static_cast<const T *>(sino);                                              \
-        if (wp)                                                                                  \
-            hipLaunchKernelGGL((bp_brick_kernel<T, BP_PLAIN, true>), grid, block, shmem, stream, \
-                               g, w, Pmat, sp, scratch, vol, bg);                                \
-        else                                                                                     \
-            hipLaunchKernelGGL((bp_brick_kernel<T, BP_PLAIN, false>), grid, block, shmem,        \
-                               stream, g, w, Pmat, sp, scratch, vol, bg);                        \
-        return combine();                                                                        \
-    }
     switch (sino_dtype) {
-        case F32: CTREX_BP(float)
-        case BF16: CTREX_BP(bf16_t)
-        case F16: CTREX_BP(_Float16)
+        case F32: CTREX_BP_LAUNCH(float, BP_PLAIN, static_cast<const float *>(sino), scratch)
+        case BF16: CTREX_BP_LAUNCH(bf16_t, BP_PLAIN, static_cast<const bf16_t *>(sino), scratch)
+        case F16: CTREX_BP_LAUNCH(_Float16, BP_PLAIN, static_cast<const _Float16 *>(sino), scratch)
         default: return hipErrorInvalidValue;
     }
-#undef CTREX_BP
+#undef CTREX_BP_LAUNCH
 }
 
 }  // namespace ctrex

@@ -253,7 +253,7 @@ ProjScratch proj_scratch(const ctrex_ctx *c, int32_t n_views) {
     const size_t vox = static_cast<size_t>(c->nx) * c->ny * c->nz;
     const size_t tiles = static_cast<size_t>((c->n_u + TILE_U - 1) / TILE_U) *
                          ((c->n_v + TILE_V - 1) / TILE_V) * static_cast<size_t>(n_views);
-    const size_t slabs = n_views > 0 ? back_scratch_bytes(make_grid(c, nullptr, n_views)) : 0;
+    const size_t bpw = n_views > 0 ? back_scratch_bytes(make_grid(c, nullptr, n_views)) : 0;
     ProjScratch l;
     size_t off = 0;
     l.z = off;
@@ -261,7 +261,7 @@ ProjScratch proj_scratch(const ctrex_ctx *c, int32_t n_views) {
     l.shadow = off;
     off = align_up(off + 2 * vox);
     l.shared = off;
-    off = align_up(off + std::max(packed_bytes(c, F32), slabs));
+    off = align_up(off + std::max(packed_bytes(c, F32), bpw));
     l.partials = off;
     off = align_up(off + 8 * (tiles + 1));
     l.total = off;
@@ -650,12 +650,13 @@ int back_project_common(ctrex_ctx *c, const void *sino, int32_t sino_dtype, floa
     }
     const RayGrid g = make_grid(c, dv, nv);
     const ProjScratch SL = proj_scratch(c, nv);
-    const size_t slabs = back_scratch_bytes(g);
+    // the backprojector's 64-bit integer volume, in the shared region
+    const size_t work = back_scratch_bytes(g);
     void *scr = nullptr;
-    if (slabs && (st = ctx_scratch(c, SL.shared + slabs, &scr))) return st;
-    float *part = slabs ? reinterpret_cast<float *>(static_cast<char *>(scr) + SL.shared) : nullptr;
+    if ((st = ctx_scratch(c, SL.shared + work, &scr))) return st;
+    void *acc = static_cast<char *>(scr) + SL.shared;
     CTREX_HIP(c, launch_back(g, make_warp(c), c->d_P, sino, sino_dtype, vol, accumulate ? 1 : 0,
-                             BP_PLAIN, c->d_scalar, part, s, scale));
+                             BP_PLAIN, c->d_scalar, acc, s, scale));
     return CTREX_OK;
 }
 
@@ -717,14 +718,15 @@ int ctrex_back_project_noalloc(ctrex_ctx *c, const void *sino, int32_t sino_dtyp
     const size_t fit = slab_room / (sizeof(float) * vox);
     const int cap = fit >= 2 ? static_cast<int>(std::min<size_t>(fit, 1u << 20)) : 1;
     const RayGrid g = make_grid(c, dv, nv);
-    const size_t slabs = back_scratch_bytes(g, cap);
+    const size_t slabs = back_scratch_bytes(g, cap, true);
     if (slabs > slab_room)
         return fail(c, CTREX_ESHAPE, "partial volumes of %zu bytes exceed the %zu this call holds",
                     slabs, slab_room);
     float *rmax = reinterpret_cast<float *>(base + kNoAllocMaxAbs);
     float *part = slabs ? reinterpret_cast<float *>(base + kNoAllocSlabs) : nullptr;
+    // the direct form of the backprojector: no volume-sized buffer
     CTREX_HIP(c, launch_back(g, make_warp(c), c->d_P, sino, sino_dtype, vol, accumulate ? 1 : 0,
-                             BP_PLAIN, rmax, part, s, 1.0f, cap));
+                             BP_PLAIN, rmax, part, s, 1.0f, cap, true));
     return CTREX_OK;
 }
 
@@ -813,12 +815,12 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
     const int gdt = (flags & CTREX_BF16_GATHER) ? BF16 : (flags & CTREX_F16_GATHER) ? F16 : F32;
     const RayGrid g = make_grid(c, dv, nv);
     // scratch: z, the 16-bit shadow, and the gather copies, whose region the
-    // backprojector's partial volumes reuse (the copies are rebuilt after the
+    // backprojector's integer volume reuses (the copies are rebuilt after the
     // update that follows it)
     const ProjScratch SL = proj_scratch(c, nv);
-    const size_t slabs = back_scratch_bytes(g);
+    const size_t work = vbp ? 0 : back_scratch_bytes(g);
     void *scr;
-    if ((st = ctx_scratch(c, SL.shared + std::max(packed_bytes(c, gdt), slabs), &scr)) != CTREX_OK)
+    if ((st = ctx_scratch(c, SL.shared + std::max(packed_bytes(c, gdt), work), &scr)) != CTREX_OK)
         return st;
     char *sc = static_cast<char *>(scr);
     float *z = reinterpret_cast<float *>(sc + SL.z);
@@ -826,7 +828,7 @@ int ctrex_sirt_iterate(ctrex_ctx *c, float *vol, const void *sino, int32_t sino_
     const size_t vox = static_cast<size_t>(c->nx) * c->ny * c->nz;
     const int rdt = sino_dtype;  // the correction image takes the data's storage type
     const WarpGrid w = make_warp(c);
-    float *part = slabs ? reinterpret_cast<float *>(sc + SL.shared) : nullptr;
+    void *part = work ? sc + SL.shared : nullptr;
 
     // R and C for this geometry / motion / subset / workspace, kept between calls.
     auto same_key = [&](const ctrex_ctx::WeightKey &e) {

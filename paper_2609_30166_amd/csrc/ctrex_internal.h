@@ -88,13 +88,16 @@ hipError_t launch_forward(const RayGrid &g, const WarpGrid &w, const void *vol, 
                           hipStream_t stream);
 // vol (+)= scale A^T sino; `Pmat` holds the view matrices [n_proj * n_sub][12]
 // on the device.  accumulate == 0 overwrites vol.  `scratch` is one device
-// float; `part` holds back_scratch_bytes(g, max_chunks) bytes (may be null
-// when that is 0).  max_chunks > 0 caps the number of projection chunks that
-// write separate partial volumes (fewer, larger chunks; 0 = no cap).
+// float (max |sino|); `work` holds back_scratch_bytes(g, max_chunks, direct)
+// bytes: the owner form's 64-bit integer volume, or the direct form's
+// per-chunk partial volumes (may be null when that is 0).  The direct form
+// (direct = true) needs no volume-sized buffer when one projection chunk
+// suffices; max_chunks > 0 caps its chunks (0 = no cap).
 hipError_t launch_back(const RayGrid &g, const WarpGrid &w, const double *Pmat, const void *sino,
                        int sino_dtype, float *vol, int accumulate, int mode, float *scratch,
-                       float *part, hipStream_t stream, float scale = 1.0f, int max_chunks = 0);
-size_t back_scratch_bytes(const RayGrid &g, int max_chunks = 0);
+                       void *work, hipStream_t stream, float scale = 1.0f, int max_chunks = 0,
+                       bool direct = false);
+size_t back_scratch_bytes(const RayGrid &g, int max_chunks = 0, bool direct = false);
 // Where the voxel-driven backprojector's voxel centres sit: the Cartesian
 // grid of the RayGrid (cyl == 0), or the polar grid of the cylindrical domain
 // (cyl != 0: g.nx = n_r rings at (i + 1/2) dr, g.ny = n_phi angles 2 pi j /

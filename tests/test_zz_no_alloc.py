@@ -2,9 +2,14 @@
 ctrex_back_project, through the C ABI (needs an MI355X).
 
 The variant keeps its scratch (view list, max |r| cell, per-chunk partial
-volumes) in the library's fixed per-device array; it must reproduce the
-regular entry point on consecutive calls of different sizes, the array
-keeping the previous call's contents in between.
+volumes) in the library's fixed per-device array and runs the direct form of
+the brick backprojector (each brick writes its own voxels); the regular entry
+point runs the owner form (bricks add into a 64-bit integer volume).  Both
+are the same operator summed in fixed point at different scales, so they
+agree to about 1e-9 relative; the test holds them to 1e-6 (inside the 1e-5
+parity bar) on consecutive calls of different sizes, the array keeping the
+previous call's contents in between, and checks each call's reproducibility
+bit for bit.
 """
 
 import ctypes
@@ -60,12 +65,12 @@ def _case(dev, shape, n_proj, n_u, n_v, sod, seed):
 
 def test_noalloc_matches_back_project_on_consecutive_calls(dev):
     # 1: 64^3 under 60 views (15 projection chunks, each with a partial volume
-    #    in the array): the same chunking as the regular call, so bitwise equal
+    #    in the array)
     P, g, s = _case(dev, (64, 64, 64), 60, 64, 64, 200.0, 1)
     z_ref = g.back(s)
     z = _noalloc(g, s)
     torch.cuda.synchronize()
-    assert torch.equal(z, z_ref)
+    assert rel_l2(z.cpu().numpy(), z_ref.cpu().numpy()) <= 1e-6
     z_or = oracle.back(P, g.shape, 64, 64, s.cpu().numpy().astype(np.float64))
     assert rel_l2(z.cpu().numpy(), z_or) <= 1e-5
     # 2: a smaller input right after it (ragged 17 x 16 x 33 volume, a view
@@ -77,7 +82,7 @@ def test_noalloc_matches_back_project_on_consecutive_calls(dev):
     z2_ref = g2.back(sv, views=views, out=base.clone(), accumulate=True)
     z2 = _noalloc(g2, sv, views=views, out=base.clone(), accumulate=True)
     torch.cuda.synchronize()
-    assert torch.equal(z2, z2_ref)
+    assert rel_l2(z2.cpu().numpy() - 1.0, z2_ref.cpu().numpy() - 1.0) <= 1e-6
     z2_or = 1.0 + oracle.back(P2, g2.shape, 40, 27, sv.cpu().numpy().astype(np.float64),
                               views=views)
     assert rel_l2(z2.cpu().numpy(), z2_or) <= 1e-5
@@ -89,7 +94,7 @@ def test_noalloc_matches_back_project_on_consecutive_calls(dev):
     torch.cuda.synchronize()
     assert rel_l2(z3.cpu().numpy(), z3_ref.cpu().numpy()) <= 1e-6
     # the first case again: the array's leftover contents do not matter
-    assert torch.equal(_noalloc(g, s), z_ref)
+    assert torch.equal(_noalloc(g, s), z)
 
 
 def test_noalloc_rejects_oversized_view_list(dev):
