@@ -14,8 +14,7 @@
 // times the lane rate of LDS FP32 atomic adds, and the sums are exact (so the
 // result does not depend on the order of the atomics).  A scale bounded from
 // max|r| puts the largest possible contribution at 2^30, so each one is a
-// 32-bit integer (weights formed in FP32, truncated: under 2^-30 of that
-// largest contribution off) while the 64-bit sums cannot overflow.  For every
+// 32-bit integer (weights formed in FP32, rounded to the nearest unit) while the 64-bit sums cannot overflow.  For every
 // (projection, sub-view) it bounds the detector pixels whose rays can reach
 // the brick (the projection of the brick grown by one voxel and the warp
 // bound), redoes those rays' FP64 set-up, clips their sample range to the
@@ -95,6 +94,15 @@ __device__ __forceinline__ int own_kexp(double cmax, const RayGrid &g, double cu
     return static_cast<int>(floor(fmin(30.0 - log2(cmax), 62.0 - log2(rays * cube_samples * cmax))));
 }
 
+// A lane merges at most OWN_MERGE_MAX samples into its register sums, and
+// only while the sum of their ray weights |c| (each bounds all eight corner
+// contributions of a sample, the trilinear weights being at most 1) stays at
+// or below OWN_MERGE_LIMIT: the FP32 sums then exceed the exact ones by at
+// most (1024 + 4) 2^-24 of 2^31 < 2^18, inside the 2^19 margin, so a merged
+// corner sum converts to a 32-bit integer.
+constexpr int OWN_MERGE_MAX = 1024;
+constexpr float OWN_MERGE_LIMIT = 2147483648.0f - 524288.0f;   // 2^31 - 2^19
+
 // Largest contribution of one sample to one corner: step * max|r| / n_sub
 // times the caller's factor (and a margin for FP32 rounding).
 __device__ __forceinline__ double contribution_bound(const RayGrid &g, double rmax, float wscale) {
@@ -165,11 +173,11 @@ __device__ __forceinline__ int wave_inclusive_sum(int x) {
 }
 
 // One contribution as a 64-bit fixed-point integer: c (FP32, the scale
-// folded in, |c| <= 2^30) truncated toward zero to 32 bits, then
-// sign-extended.  Truncation errs by under one unit, 2^-30 of the largest
-// possible contribution.
+// folded in, |c| < 2^31) rounded to the nearest integer, then sign-extended.
+// Rounding errs by at most half a unit and without bias, so the error of a
+// voxel's sum grows with the square root of its number of contributions.
 __device__ __forceinline__ unsigned long long to_fixed(float c) {
-    return static_cast<unsigned long long>(static_cast<long long>(static_cast<int>(c)));
+    return static_cast<unsigned long long>(static_cast<long long>(static_cast<int>(rintf(c))));
 }
 
 __device__ __forceinline__ long long shfl64(long long v, int src) {
@@ -253,6 +261,25 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
                                                              62.0 - log2(bound)))));
     const double scale = uni(ldexp(1.0, kexp));
 
+    // owner form: each lane keeps the eight corner sums of the cell its last
+    // samples fell in and adds them to LDS only when the next sample falls in
+    // another cell (consecutive samples 0.5 voxel apart often share one), or
+    // when another sample could take a sum past a 32-bit integer
+    int mcell = -1, mcnt = 0;
+    float msum = 0.0f;
+    float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f, m3 = 0.0f, m4 = 0.0f, m5 = 0.0f, m6 = 0.0f, m7 = 0.0f;
+    auto flush = [&]() {
+        unsigned long long *const f0 = cell0 + mcell;
+        unsigned long long *const f1 = f0 + OWN_SZ;
+        atomicAdd(f0, to_fixed(m0));
+        atomicAdd(f0 + 1, to_fixed(m1));
+        atomicAdd(f0 + OWN_SY, to_fixed(m2));
+        atomicAdd(f0 + OWN_SY + 1, to_fixed(m3));
+        atomicAdd(f1, to_fixed(m4));
+        atomicAdd(f1 + 1, to_fixed(m5));
+        atomicAdd(f1 + OWN_SY, to_fixed(m6));
+        atomicAdd(f1 + OWN_SY + 1, to_fixed(m7));
+    };
     // each wave takes whole (projection, sub-view) pairs, so a pair's pixel
     // box is projected once, by the wave that walks its rays
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -408,17 +435,37 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
                         const float gz1 = fz * cwq, gz0 = (1.0f - fz) * cwq;
                         const float w00 = gz0 * gy0, w01 = gz0 * gy1, w10 = gz1 * gy0,
                                     w11 = gz1 * gy1;
-                        unsigned long long *const a0 =
-                            cell0 + (__mul24(lz, OWN_SZ) + __mul24(ly, OWN_SY) + lx);
-                        unsigned long long *const a1 = a0 + OWN_SZ;
-                        atomicAdd(a0, to_fixed(w00 * gx0));
-                        atomicAdd(a0 + 1, to_fixed(w00 * gx1));
-                        atomicAdd(a0 + OWN_SY, to_fixed(w01 * gx0));
-                        atomicAdd(a0 + OWN_SY + 1, to_fixed(w01 * gx1));
-                        atomicAdd(a1, to_fixed(w10 * gx0));
-                        atomicAdd(a1 + 1, to_fixed(w10 * gx1));
-                        atomicAdd(a1 + OWN_SY, to_fixed(w11 * gx0));
-                        atomicAdd(a1 + OWN_SY + 1, to_fixed(w11 * gx1));
+                        const int cell = __mul24(lz, OWN_SZ) + __mul24(ly, OWN_SY) + lx;
+                        if (WARP) {
+                            // the warp lookup leaves no registers for the
+                            // merge sums: add every sample at once
+                            unsigned long long *const a0 = cell0 + cell;
+                            unsigned long long *const a1 = a0 + OWN_SZ;
+                            atomicAdd(a0, to_fixed(w00 * gx0));
+                            atomicAdd(a0 + 1, to_fixed(w00 * gx1));
+                            atomicAdd(a0 + OWN_SY, to_fixed(w01 * gx0));
+                            atomicAdd(a0 + OWN_SY + 1, to_fixed(w01 * gx1));
+                            atomicAdd(a1, to_fixed(w10 * gx0));
+                            atomicAdd(a1 + 1, to_fixed(w10 * gx1));
+                            atomicAdd(a1 + OWN_SY, to_fixed(w11 * gx0));
+                            atomicAdd(a1 + OWN_SY + 1, to_fixed(w11 * gx1));
+                            continue;
+                        }
+                        const float aw = fabsf(cwq);
+                        const bool same =
+                            cell == mcell && mcnt < OWN_MERGE_MAX && msum + aw <= OWN_MERGE_LIMIT;
+                        if (!same && mcell >= 0) flush();
+                        m0 = same ? m0 + w00 * gx0 : w00 * gx0;
+                        m1 = same ? m1 + w00 * gx1 : w00 * gx1;
+                        m2 = same ? m2 + w01 * gx0 : w01 * gx0;
+                        m3 = same ? m3 + w01 * gx1 : w01 * gx1;
+                        m4 = same ? m4 + w10 * gx0 : w10 * gx0;
+                        m5 = same ? m5 + w10 * gx1 : w10 * gx1;
+                        m6 = same ? m6 + w11 * gx0 : w11 * gx0;
+                        m7 = same ? m7 + w11 * gx1 : w11 * gx1;
+                        msum = same ? msum + aw : aw;
+                        mcnt = same ? mcnt + 1 : 1;
+                        mcell = cell;
                         continue;
                     }
                     // no corner in the brick: lx, ly outside [-1, e - 1] (the
@@ -456,6 +503,7 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
             }
         }
     }
+    if (OWN && !WARP && mcell >= 0) flush();
     __syncthreads();
     if (OWN) {
         // ---- add the brick's cells, halo included, into the integer volume
