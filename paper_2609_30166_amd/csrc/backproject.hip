@@ -30,6 +30,8 @@
 
 #include "ray_common.h"
 
+#include <type_traits>
+
 namespace ctrex {
 namespace {
 
@@ -40,7 +42,7 @@ using namespace dev;
 // 4 waves with no register spills (measured 7% faster at 512^3 x 720).  At the
 // 64-register budget the kernel spills ~160 bytes per lane, all in the ray
 // set-up of each pixel block; the per-sample path reloads nothing.
-constexpr int BP_THREADS = 1024;
+constexpr int BP_THREADS = 768;
 
 // Largest brick, and its LDS layout: rows of BRICK_X + 2 cells (halo on both
 // sides, padded to an odd stride) and planes of BRICK_Y + 2 rows.  64-bit
@@ -94,13 +96,14 @@ __device__ __forceinline__ int own_kexp(double cmax, const RayGrid &g, double cu
     return static_cast<int>(floor(fmin(30.0 - log2(cmax), 62.0 - log2(rays * cube_samples * cmax))));
 }
 
-// A lane merges at most OWN_MERGE_MAX samples into its register sums, and
-// only while the sum of their ray weights |c| (each bounds all eight corner
+// A lane merges at most OWN_MERGE_MAX samples into its register sums (it
+// starts a new run every OWN_MERGE_MAX iterations), and only while the sum of their ray weights |c| (each bounds all eight corner
 // contributions of a sample, the trilinear weights being at most 1) stays at
 // or below OWN_MERGE_LIMIT: the FP32 sums then exceed the exact ones by at
 // most (1024 + 4) 2^-24 of 2^31 < 2^18, inside the 2^19 margin, so a merged
 // corner sum converts to a 32-bit integer.
 constexpr int OWN_MERGE_MAX = 1024;
+static_assert((OWN_MERGE_MAX & (OWN_MERGE_MAX - 1)) == 0, "power of two");
 constexpr float OWN_MERGE_LIMIT = 2147483648.0f - 524288.0f;   // 2^31 - 2^19
 
 // Largest contribution of one sample to one corner: step * max|r| / n_sub
@@ -185,7 +188,7 @@ __device__ __forceinline__ long long shfl64(long long v, int src) {
 }
 
 template <typename TS, int MODE, bool WARP, bool OWN>
-__global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8))) void bp_brick_kernel(RayGrid g, WarpGrid w,
+__global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(6, 6))) void bp_brick_kernel(RayGrid g, WarpGrid w,
                                                               const double *__restrict__ Pmat,
                                                               const TS *__restrict__ sino,
                                                               const float *__restrict__ rmax,
@@ -222,6 +225,9 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
     const double off[3] = {0.5 * (g.nx - 1), 0.5 * (g.ny - 1), 0.5 * (g.nz - 1)};
     // 1 / n_sub and the caller's factor (1 unless scaled; exact when a power of 2)
     const float inv_sub = uni(bg.wscale / static_cast<float>(g.n_sub));
+    // largest side times 2^-22: four times the FP32 rounding error of a
+    // coordinate of a ray's start
+    const float tol = uni(static_cast<float>(max(g.nx, max(g.ny, g.nz))) * 2.38418579e-7f);
     const int k_first = chunk * bg.views_per_chunk;
     const int k_end = min(k_first + bg.views_per_chunk, g.n_views);
     const int n_pairs = (k_end - k_first) * g.n_sub;
@@ -261,25 +267,6 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
                                                              62.0 - log2(bound)))));
     const double scale = uni(ldexp(1.0, kexp));
 
-    // owner form: each lane keeps the eight corner sums of the cell its last
-    // samples fell in and adds them to LDS only when the next sample falls in
-    // another cell (consecutive samples 0.5 voxel apart often share one), or
-    // when another sample could take a sum past a 32-bit integer
-    int mcell = -1, mcnt = 0;
-    float msum = 0.0f;
-    float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f, m3 = 0.0f, m4 = 0.0f, m5 = 0.0f, m6 = 0.0f, m7 = 0.0f;
-    auto flush = [&]() {
-        unsigned long long *const f0 = cell0 + mcell;
-        unsigned long long *const f1 = f0 + OWN_SZ;
-        atomicAdd(f0, to_fixed(m0));
-        atomicAdd(f0 + 1, to_fixed(m1));
-        atomicAdd(f0 + OWN_SY, to_fixed(m2));
-        atomicAdd(f0 + OWN_SY + 1, to_fixed(m3));
-        atomicAdd(f1, to_fixed(m4));
-        atomicAdd(f1 + 1, to_fixed(m5));
-        atomicAdd(f1 + OWN_SY, to_fixed(m6));
-        atomicAdd(f1 + OWN_SY + 1, to_fixed(m7));
-    };
     // each wave takes whole (projection, sub-view) pairs, so a pair's pixel
     // box is projected once, by the wave that walks its rays
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -297,11 +284,16 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
             const float Mp = uni(mv > 0.0 ? static_cast<float>(ceil(mv * (1.0 + 1e-6) + 1e-6)) : 0.0f);
             // direct form: samples with a corner in the brick, position in
             // [x0 - 1, x0 + ex]; owner form: lower corner in it, [x0, x0 + ex]
-            const float g0 = OWN ? 0.0f : 1.0f;
+            // The ray-range estimate below takes the ray's start in FP32,
+            // off by up to 2^-24 of a coordinate: the bounds are widened by
+            // 2^-22 of the largest side (this adds samples that the
+            // exact corner test then rejects; for a ray almost parallel to an
+            // axis the one-sample widening would not cover it)
+            const float g0 = (OWN ? 0.0f : 1.0f) + tol;
             const float lo[3] = {uni(x0 - g0 - Mp), uni(y0 - g0 - Mp), uni(z0 - g0 - Mp)};
-            const float hi[3] = {uni(static_cast<float>(x0 + ex) + Mp),
-                                 uni(static_cast<float>(y0 + ey) + Mp),
-                                 uni(static_cast<float>(z0 + ez) + Mp)};
+            const float hi[3] = {uni(static_cast<float>(x0 + ex) + Mp + tol),
+                                 uni(static_cast<float>(y0 + ey) + Mp + tol),
+                                 uni(static_cast<float>(z0 + ez) + Mp + tol)};
             const double plo[3] = {lo[0], lo[1], lo[2]}, phi[3] = {hi[0], hi[1], hi[2]};
             int u0 = 0, u1 = g.n_u - 1, v0 = 0, v1 = g.n_v - 1;
             if (!project_box(Pmat + 12 * static_cast<size_t>(sv_idx), plo, phi, off, g.n_u, g.n_v,
@@ -335,24 +327,31 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
                                                      : ld(sino, (k * g.n_v + iv) * g.n_u + iu);
                 if (rv != 0.0f && setup_ray(sv, static_cast<double>(iu), static_cast<double>(iv),
                                             g.nx, g.ny, g.nz, g.step, r)) {
-                    // sample indices i with b + i s inside [lo, hi] on every axis
-                    // (FP32 estimate widened by one sample; corners are checked
-                    // exactly below)
+                    // sample indices i with b + i s inside [lo, hi] on every
+                    // axis, in FP32 (corners are checked exactly below).  The
+                    // FP32 start and step put b + i s within 2^-24 (|b| + L) <
+                    // 2.8 2^-24 max side of the fixed-point position of sample
+                    // i (L the ray length, at most sqrt(3) max side), and
+                    // [lo, hi] is widened by tol = 4 2^-24 max side; the index estimate itself is three
+                    // roundings, under 3 2^-24 |t|, inside the margin of
+                    // 1/64 + 2^-20 |t| samples.  An axis the ray does not move
+                    // along (|s| under 1e-30: its samples drift by less than
+                    // tol) only decides whether the ray hits; branch-free.
                     float kmin = 0.0f, kmax = static_cast<float>(r.n - 1);
-                    const float bv[3] = {static_cast<float>(r.bx), static_cast<float>(r.by),
-                                         static_cast<float>(r.bz)};
+                    const float bv[3] = {r.bx, r.by, r.bz};
                     const float sv3[3] = {r.fx, r.fy, r.fz};
                     bool hit = true;
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
-                        if (sv3[q] != 0.0f) {
-                            const float inv = 1.0f / sv3[q];
-                            const float t1 = (lo[q] - bv[q]) * inv, t2 = (hi[q] - bv[q]) * inv;
-                            kmin = fmaxf(kmin, fminf(t1, t2) - 1.0f);
-                            kmax = fminf(kmax, fmaxf(t1, t2) + 1.0f);
-                        } else if (bv[q] < lo[q] || bv[q] > hi[q]) {
-                            hit = false;
-                        }
+                        const bool flat = fabsf(sv3[q]) < 1e-30f;
+                        const float inv = 1.0f / (flat ? 1.0f : sv3[q]);
+                        const float t1 = (lo[q] - bv[q]) * inv, t2 = (hi[q] - bv[q]) * inv;
+                        const float tl = fminf(t1, t2), th = fmaxf(t1, t2);
+                        const float ml = fmaf(fabsf(tl), 9.5367431640625e-7f, 0.015625f);
+                        const float mh = fmaf(fabsf(th), 9.5367431640625e-7f, 0.015625f);
+                        kmin = flat ? kmin : fmaxf(kmin, tl - ml);
+                        kmax = flat ? kmax : fminf(kmax, th + mh);
+                        hit &= !(flat & ((bv[q] < lo[q]) | (bv[q] > hi[q])));
                     }
                     if (hit && kmin <= kmax) {
                         ib = max(static_cast<int>(ceilf(kmin)), 0);
@@ -387,123 +386,177 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8
                           pz = shfl64(p0z, j) + m * ctz;
                 float cwq = __shfl(wq, j, 64);
                 int cend = __shfl(incl, j, 64);
+                // the next ray with samples after each lane's own (itself if none)
+                const unsigned long long later = lane < 63 ? (live & (~0ull << (lane + 1))) : 0ull;
+                const int nxt = later ? __ffsll(static_cast<long long>(later)) - 1 : lane;
                 const int trips = (T + 63) >> 6;
-                int pos = start;
-                for (int it = 0; it < trips; ++it) {
-                    // wave-uniform hand-over to the next ray with samples; it is
-                    // entered at its first sample in the brick range
-                    const bool need = pos < end && pos == cend;
-                    if (__any(need)) {
-                        const unsigned long long rest =
-                            j < 63 ? (live & (~0ull << (j + 1))) : 0ull;
-                        const int jn = need && rest ? __ffsll(static_cast<long long>(rest)) - 1 : j;
-                        // lanes without a hand-over read their current ray again
-                        // (the same values) and keep their position
-                        ctx = shfl64(r.tx, jn);
-                        cty = shfl64(r.ty, jn);
-                        ctz = shfl64(r.tz, jn);
-                        const long long nx0 = shfl64(p0x, jn), ny0 = shfl64(p0y, jn),
-                                        nz0 = shfl64(p0z, jn);
-                        cwq = __shfl(wq, jn, 64);
-                        cend = __shfl(incl, jn, 64);
-                        if (need) {
-                            px = nx0;
-                            py = ny0;
-                            pz = nz0;
+                // the sample walk, with the corner clamps (CLAMP) or without:
+                // in the unwarped owner form a brick that holds neither the
+                // first lower corner 0 nor the last two n - 2, n - 1 on any
+                // axis needs none, since a sample the clamp would move has its
+                // lower corner outside the brick before and after the clamp
+                auto walk = [&](auto clamp_tag) {
+                    constexpr bool CLAMP = decltype(clamp_tag)::value;
+                    // owner form: each lane keeps the eight corner sums of the
+                    // cell its last samples fell in and adds them to LDS only
+                    // when the next sample falls in another cell (consecutive
+                    // samples 0.5 voxel apart often share one), when another
+                    // sample could take a sum past a 32-bit integer, or every
+                    // OWN_MERGE_MAX iterations; the sums are flushed at the end
+                    // of the block, so they hold no registers during the next
+                    // block's ray set-up
+                    int mcell = -1;
+                    float msum = 0.0f;
+                    float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f, m3 = 0.0f;
+                    float m4 = 0.0f, m5 = 0.0f, m6 = 0.0f, m7 = 0.0f;
+                    auto flush = [&]() {
+                        unsigned long long *const f0 = cell0 + mcell;
+                        unsigned long long *const f1 = f0 + OWN_SZ;
+                        atomicAdd(f0, to_fixed(m0));
+                        atomicAdd(f0 + 1, to_fixed(m1));
+                        atomicAdd(f0 + OWN_SY, to_fixed(m2));
+                        atomicAdd(f0 + OWN_SY + 1, to_fixed(m3));
+                        atomicAdd(f1, to_fixed(m4));
+                        atomicAdd(f1 + 1, to_fixed(m5));
+                        atomicAdd(f1 + OWN_SY, to_fixed(m6));
+                        atomicAdd(f1 + OWN_SY + 1, to_fixed(m7));
+                    };
+                    int pos = start;
+                    for (int it = 0; it < trips; ++it) {
+                        // wave-uniform hand-over to the next ray with samples;
+                        // it is entered at its first sample in the brick range
+                        const bool need = pos < end && pos == cend;
+                        if (__any(need)) {
+                            // lanes without a hand-over read their current ray
+                            // again (the same values) and keep their position.
+                            // Every lane reads: a permute that only some lanes
+                            // execute returns 0 from the lanes that skip it
+                            const int jc = __shfl(nxt, j, 64);
+                            const int jn = need ? jc : j;
+                            ctx = shfl64(r.tx, jn);
+                            cty = shfl64(r.ty, jn);
+                            ctz = shfl64(r.tz, jn);
+                            const long long nx0 = shfl64(p0x, jn), ny0 = shfl64(p0y, jn),
+                                            nz0 = shfl64(p0z, jn);
+                            cwq = __shfl(wq, jn, 64);
+                            cend = __shfl(incl, jn, 64);
+                            if (need) {
+                                px = nx0;
+                                py = ny0;
+                                pz = nz0;
+                            }
+                            j = jn;
                         }
-                        j = jn;
-                    }
-                    if (pos >= end) continue;
-                    ++pos;
-                    const long long qx = px, qy = py, qz = pz;
-                    px += ctx;
-                    py += cty;
-                    pz += ctz;
-                    int ix, iy, iz;
-                    float fx, fy, fz;
-                    if (!sample_corner<WARP>(d, w, tau, qx, qy, qz, ix, iy, iz, fx, fy, fz))
-                        continue;
-                    const int lx = ix - x0, ly = iy - y0, lz = iz - z0;
-                    if (OWN) {
-                        // another brick owns this sample's lower corner
-                        if (static_cast<uint32_t>(lx) >= static_cast<uint32_t>(ex) ||
-                            static_cast<uint32_t>(ly) >= static_cast<uint32_t>(ey) ||
-                            static_cast<uint32_t>(lz) >= static_cast<uint32_t>(ez))
+                        if (pos >= end) continue;
+                        ++pos;
+                        const long long qx = px, qy = py, qz = pz;
+                        px += ctx;
+                        py += cty;
+                        pz += ctz;
+                        int ix, iy, iz;
+                        float fx, fy, fz;
+                        if (CLAMP || WARP) {
+                            if (!sample_corner<WARP>(d, w, tau, qx, qy, qz, ix, iy, iz, fx, fy, fz))
+                                continue;
+                        } else {
+                            fx_split(qx, ix, fx);
+                            fx_split(qy, iy, fy);
+                            fx_split(qz, iz, fz);
+                        }
+                        const int lx = ix - x0, ly = iy - y0, lz = iz - z0;
+                        if (OWN) {
+                            // another brick owns this sample's lower corner
+                            if (static_cast<uint32_t>(lx) >= static_cast<uint32_t>(ex) ||
+                                static_cast<uint32_t>(ly) >= static_cast<uint32_t>(ey) ||
+                                static_cast<uint32_t>(lz) >= static_cast<uint32_t>(ez))
+                                continue;
+                            const float gx1 = fx, gx0 = 1.0f - fx;
+                            const float gy1 = fy, gy0 = 1.0f - fy;
+                            const float gz1 = fz * cwq, gz0 = (1.0f - fz) * cwq;
+                            const float w00 = gz0 * gy0, w01 = gz0 * gy1, w10 = gz1 * gy0,
+                                        w11 = gz1 * gy1;
+                            const int cell = __mul24(lz, OWN_SZ) + __mul24(ly, OWN_SY) + lx;
+                            if (WARP) {
+                                // the warp lookup leaves no registers for the
+                                // merge sums: add every sample at once
+                                unsigned long long *const a0 = cell0 + cell;
+                                unsigned long long *const a1 = a0 + OWN_SZ;
+                                atomicAdd(a0, to_fixed(w00 * gx0));
+                                atomicAdd(a0 + 1, to_fixed(w00 * gx1));
+                                atomicAdd(a0 + OWN_SY, to_fixed(w01 * gx0));
+                                atomicAdd(a0 + OWN_SY + 1, to_fixed(w01 * gx1));
+                                atomicAdd(a1, to_fixed(w10 * gx0));
+                                atomicAdd(a1 + 1, to_fixed(w10 * gx1));
+                                atomicAdd(a1 + OWN_SY, to_fixed(w11 * gx0));
+                                atomicAdd(a1 + OWN_SY + 1, to_fixed(w11 * gx1));
+                                continue;
+                            }
+                            const float aw = fabsf(cwq);
+                            const bool fresh = (it & (OWN_MERGE_MAX - 1)) == 0;   // uniform
+                            const bool same =
+                                !fresh && cell == mcell && msum + aw <= OWN_MERGE_LIMIT;
+                            if (!same && mcell >= 0) flush();
+                            const float k0 = same ? m0 : 0.0f, k1 = same ? m1 : 0.0f;
+                            const float k2 = same ? m2 : 0.0f, k3 = same ? m3 : 0.0f;
+                            const float k4 = same ? m4 : 0.0f, k5 = same ? m5 : 0.0f;
+                            const float k6 = same ? m6 : 0.0f, k7 = same ? m7 : 0.0f;
+                            m0 = fmaf(w00, gx0, k0);
+                            m1 = fmaf(w00, gx1, k1);
+                            m2 = fmaf(w01, gx0, k2);
+                            m3 = fmaf(w01, gx1, k3);
+                            m4 = fmaf(w10, gx0, k4);
+                            m5 = fmaf(w10, gx1, k5);
+                            m6 = fmaf(w11, gx0, k6);
+                            m7 = fmaf(w11, gx1, k7);
+                            msum = same ? msum + aw : aw;
+                            mcell = cell;
                             continue;
+                        }
+                        // no corner in the brick: lx, ly outside [-1, e - 1] (the
+                        // halo takes -1 and e - 1's upper neighbour), or lz
+                        // outside [-1, ez - 1]
+                        if (static_cast<uint32_t>(lx + 1) > static_cast<uint32_t>(ex) ||
+                            static_cast<uint32_t>(ly + 1) > static_cast<uint32_t>(ey) ||
+                            static_cast<uint32_t>(lz + 1) > static_cast<uint32_t>(ez))
+                            continue;
+                        const bool z_0 = lz >= 0, z_1 = lz + 1 < ez;
+                        // corner weights in FP32 with the ray weight and the
+                        // fixed-point scale folded in; each contribution becomes a
+                        // 32-bit integer added into the 64-bit cell.  x and y
+                        // neighbours outside the brick land in the halo; a z
+                        // neighbour outside gets weight zero and a plane clamped
+                        // into the brick (adding an integer zero changes no sum),
+                        // so every lane issues the same eight atomics.
                         const float gx1 = fx, gx0 = 1.0f - fx;
                         const float gy1 = fy, gy0 = 1.0f - fy;
-                        const float gz1 = fz * cwq, gz0 = (1.0f - fz) * cwq;
+                        const float gz1 = (z_1 ? fz : 0.0f) * cwq;
+                        const float gz0 = (z_0 ? 1.0f - fz : 0.0f) * cwq;
                         const float w00 = gz0 * gy0, w01 = gz0 * gy1, w10 = gz1 * gy0,
                                     w11 = gz1 * gy1;
-                        const int cell = __mul24(lz, OWN_SZ) + __mul24(ly, OWN_SY) + lx;
-                        if (WARP) {
-                            // the warp lookup leaves no registers for the
-                            // merge sums: add every sample at once
-                            unsigned long long *const a0 = cell0 + cell;
-                            unsigned long long *const a1 = a0 + OWN_SZ;
-                            atomicAdd(a0, to_fixed(w00 * gx0));
-                            atomicAdd(a0 + 1, to_fixed(w00 * gx1));
-                            atomicAdd(a0 + OWN_SY, to_fixed(w01 * gx0));
-                            atomicAdd(a0 + OWN_SY + 1, to_fixed(w01 * gx1));
-                            atomicAdd(a1, to_fixed(w10 * gx0));
-                            atomicAdd(a1 + 1, to_fixed(w10 * gx1));
-                            atomicAdd(a1 + OWN_SY, to_fixed(w11 * gx0));
-                            atomicAdd(a1 + OWN_SY + 1, to_fixed(w11 * gx1));
-                            continue;
-                        }
-                        const float aw = fabsf(cwq);
-                        const bool same =
-                            cell == mcell && mcnt < OWN_MERGE_MAX && msum + aw <= OWN_MERGE_LIMIT;
-                        if (!same && mcell >= 0) flush();
-                        m0 = same ? m0 + w00 * gx0 : w00 * gx0;
-                        m1 = same ? m1 + w00 * gx1 : w00 * gx1;
-                        m2 = same ? m2 + w01 * gx0 : w01 * gx0;
-                        m3 = same ? m3 + w01 * gx1 : w01 * gx1;
-                        m4 = same ? m4 + w10 * gx0 : w10 * gx0;
-                        m5 = same ? m5 + w10 * gx1 : w10 * gx1;
-                        m6 = same ? m6 + w11 * gx0 : w11 * gx0;
-                        m7 = same ? m7 + w11 * gx1 : w11 * gx1;
-                        msum = same ? msum + aw : aw;
-                        mcnt = same ? mcnt + 1 : 1;
-                        mcell = cell;
-                        continue;
+                        const int row = __mul24(ly, LDS_SY) + lx;
+                        unsigned long long *const a0 = cell0 + (__mul24(max(lz, 0), LDS_SZ) + row);
+                        unsigned long long *const a1 =
+                            cell0 + (__mul24(min(lz + 1, ez - 1), LDS_SZ) + row);
+                        atomicAdd(a0, to_fixed(w00 * gx0));
+                        atomicAdd(a0 + 1, to_fixed(w00 * gx1));
+                        atomicAdd(a0 + LDS_SY, to_fixed(w01 * gx0));
+                        atomicAdd(a0 + LDS_SY + 1, to_fixed(w01 * gx1));
+                        atomicAdd(a1, to_fixed(w10 * gx0));
+                        atomicAdd(a1 + 1, to_fixed(w10 * gx1));
+                        atomicAdd(a1 + LDS_SY, to_fixed(w11 * gx0));
+                        atomicAdd(a1 + LDS_SY + 1, to_fixed(w11 * gx1));
                     }
-                    // no corner in the brick: lx, ly outside [-1, e - 1] (the
-                    // halo takes -1 and e - 1's upper neighbour), or lz
-                    // outside [-1, ez - 1]
-                    if (static_cast<uint32_t>(lx + 1) > static_cast<uint32_t>(ex) ||
-                        static_cast<uint32_t>(ly + 1) > static_cast<uint32_t>(ey) ||
-                        static_cast<uint32_t>(lz + 1) > static_cast<uint32_t>(ez))
-                        continue;
-                    const bool z_0 = lz >= 0, z_1 = lz + 1 < ez;
-                    // corner weights in FP32 with the ray weight and the
-                    // fixed-point scale folded in; each contribution becomes a
-                    // 32-bit integer added into the 64-bit cell.  x and y
-                    // neighbours outside the brick land in the halo; a z
-                    // neighbour outside gets weight zero and a plane clamped
-                    // into the brick (adding an integer zero changes no sum),
-                    // so every lane issues the same eight atomics.
-                    const float gx1 = fx, gx0 = 1.0f - fx;
-                    const float gy1 = fy, gy0 = 1.0f - fy;
-                    const float gz1 = (z_1 ? fz : 0.0f) * cwq, gz0 = (z_0 ? 1.0f - fz : 0.0f) * cwq;
-                    const float w00 = gz0 * gy0, w01 = gz0 * gy1, w10 = gz1 * gy0, w11 = gz1 * gy1;
-                    const int row = __mul24(ly, LDS_SY) + lx;
-                    unsigned long long *const a0 = cell0 + (__mul24(max(lz, 0), LDS_SZ) + row);
-                    unsigned long long *const a1 =
-                        cell0 + (__mul24(min(lz + 1, ez - 1), LDS_SZ) + row);
-                    atomicAdd(a0, to_fixed(w00 * gx0));
-                    atomicAdd(a0 + 1, to_fixed(w00 * gx1));
-                    atomicAdd(a0 + LDS_SY, to_fixed(w01 * gx0));
-                    atomicAdd(a0 + LDS_SY + 1, to_fixed(w01 * gx1));
-                    atomicAdd(a1, to_fixed(w10 * gx0));
-                    atomicAdd(a1 + 1, to_fixed(w10 * gx1));
-                    atomicAdd(a1 + LDS_SY, to_fixed(w11 * gx0));
-                    atomicAdd(a1 + LDS_SY + 1, to_fixed(w11 * gx1));
-                }
+                    if (OWN && !WARP && mcell >= 0) flush();
+                };
+                const bool interior = OWN && !WARP && x0 >= 1 && x0 + ex <= g.nx - 2 && y0 >= 1 &&
+                                      y0 + ey <= g.ny - 2 && z0 >= 1 && z0 + ez <= g.nz - 2;
+                if (interior)
+                    walk(std::false_type{});
+                else
+                    walk(std::true_type{});
             }
         }
     }
-    if (OWN && !WARP && mcell >= 0) flush();
     __syncthreads();
     if (OWN) {
         // ---- add the brick's cells, halo included, into the integer volume

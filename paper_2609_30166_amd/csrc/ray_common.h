@@ -39,10 +39,9 @@ __device__ __forceinline__ void st(_Float16 *p, int i, float v) { p[i] = static_
 constexpr int FX = 40;
 
 struct Ray {
-    double bx, by, bz;      // position of sample 0 (FP64)
-    double sx, sy, sz;      // step vector h * d (FP64)
     long long qx, qy, qz;   // position of sample 0, fixed point
     long long tx, ty, tz;   // step vector, fixed point
+    float bx, by, bz;       // position of sample 0 in FP32 (range estimates only)
     float fx, fy, fz;       // step vector in FP32 (range estimates only)
     float h;                // sample weight (path length per sample)
     int n;                  // number of samples
@@ -100,21 +99,22 @@ __device__ __forceinline__ bool setup_ray(const SubView &sv, double u, double v,
     const double nd = ceil(L / step);
     const double h = L / nd;
     const double tb = fma(0.5, h, t0);
-    r.bx = fma(tb, dx, sv.S[0]);
-    r.by = fma(tb, dy, sv.S[1]);
-    r.bz = fma(tb, dz, sv.S[2]);
-    r.sx = h * dx;
-    r.sy = h * dy;
-    r.sz = h * dz;
-    r.qx = to_fx(r.bx);
-    r.qy = to_fx(r.by);
-    r.qz = to_fx(r.bz);
-    r.tx = to_fx(r.sx);
-    r.ty = to_fx(r.sy);
-    r.tz = to_fx(r.sz);
-    r.fx = static_cast<float>(r.sx);
-    r.fy = static_cast<float>(r.sy);
-    r.fz = static_cast<float>(r.sz);
+    const double bx = fma(tb, dx, sv.S[0]);
+    const double by = fma(tb, dy, sv.S[1]);
+    const double bz = fma(tb, dz, sv.S[2]);
+    const double sx = h * dx, sy = h * dy, sz = h * dz;
+    r.qx = to_fx(bx);
+    r.qy = to_fx(by);
+    r.qz = to_fx(bz);
+    r.tx = to_fx(sx);
+    r.ty = to_fx(sy);
+    r.tz = to_fx(sz);
+    r.bx = static_cast<float>(bx);
+    r.by = static_cast<float>(by);
+    r.bz = static_cast<float>(bz);
+    r.fx = static_cast<float>(sx);
+    r.fy = static_cast<float>(sy);
+    r.fz = static_cast<float>(sz);
     r.h = static_cast<float>(h);
     r.n = static_cast<int>(nd);
     return true;
