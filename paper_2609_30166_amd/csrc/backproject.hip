@@ -37,12 +37,16 @@ namespace {
 
 using namespace dev;
 
-// 16 waves per workgroup and two workgroups (two LDS bricks) per CU: 8 waves
-// per SIMD hide the latency of the FP64 set-up and the LDS atomics better than
-// 4 waves with no register spills (measured 7% faster at 512^3 x 720).  At the
-// 64-register budget the kernel spills ~160 bytes per lane, all in the ray
-// set-up of each pixel block; the per-sample path reloads nothing.
-constexpr int BP_THREADS = 768;
+// Launch shape.  Unwarped: 16 waves per workgroup, one workgroup per CU (its
+// LDS brick and its waves' ray tables take 140 KB of the 160), so 4 waves per
+// SIMD at up to 128 registers, with no spills.  The kernel is bound by LDS
+// instructions, each taking about six CU cycles whatever its number of active
+// lanes, so a hand-over reads the next ray from the table (four 16-byte reads
+// by the lanes that hand over) instead of fifteen full-wave permutes.  Warped:
+// the displacement lookups need the latency hiding of 6 waves per SIMD (12
+// waves per workgroup, two per CU, no table), and hand-overs permute.
+template <bool WARP> constexpr int bp_threads() { return WARP ? 768 : 1024; }
+template <bool WARP> constexpr bool bp_table() { return !WARP; }
 
 // Largest brick, and its LDS layout: rows of BRICK_X + 2 cells (halo on both
 // sides, padded to an odd stride) and planes of BRICK_Y + 2 rows.  64-bit
@@ -183,19 +187,42 @@ __device__ __forceinline__ unsigned long long to_fixed(float c) {
     return static_cast<unsigned long long>(static_cast<long long>(static_cast<int>(rintf(c))));
 }
 
-__device__ __forceinline__ long long shfl64(long long v, int src) {
-    return __shfl(v, src, 64);
+// One ray of a wave's 8x8 pixel block, as the lanes that walk its samples
+// need it: position of its first sample in the brick range and its step (both
+// 64-bit fixed point), its weight, the end of its samples in the wave's order
+// and the next ray of the block with samples (64 bytes, four 16-byte reads).
+struct alignas(16) RayRec {
+    long long px, py, pz;
+    long long tx, ty, tz;
+    float wq;
+    int end;
+    int next;
+    int pad;
+};
+static_assert(sizeof(RayRec) == 64, "ray record");
+
+// Orders one wave's LDS writes before its other lanes' reads of them (and
+// those reads before the next writes); no instruction beyond a wait.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <typename TS, int MODE, bool WARP, bool OWN>
-__global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(6, 6))) void bp_brick_kernel(RayGrid g, WarpGrid w,
+__global__ __launch_bounds__(bp_threads<WARP>())
+__attribute__((amdgpu_waves_per_eu(WARP ? 6 : 4, WARP ? 6 : 4))) void bp_brick_kernel(RayGrid g, WarpGrid w,
                                                               const double *__restrict__ Pmat,
                                                               const TS *__restrict__ sino,
                                                               const float *__restrict__ rmax,
                                                               float *__restrict__ vol,
                                                               BrickGrid bg) {
     __shared__ unsigned long long acc[MAX_CELLS];
+    constexpr int BP_THREADS = bp_threads<WARP>();
+    constexpr bool TABLE = bp_table<WARP>();
     __shared__ double red[BP_THREADS / 64];
+    __shared__ RayRec rays[TABLE ? BP_THREADS : 1];
+    RayRec *const tabw = rays + (threadIdx.x & ~63);
     // ---- block -> (brick, projection chunk); XCD-aware so that one XCD
     // works on neighbouring bricks
     const int per = (bg.total + N_XCD - 1) / N_XCD;
@@ -360,16 +387,54 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(6, 6
                         wq = static_cast<float>(static_cast<double>(r.h * rv * inv_sub) * scale);
                     }
                 }
-                // position of the ray's first sample in the brick range
-                const long long p0x = r.qx + static_cast<long long>(ib) * r.tx;
-                const long long p0y = r.qy + static_cast<long long>(ib) * r.ty;
-                const long long p0z = r.qz + static_cast<long long>(ib) * r.tz;
                 // ---- exclusive prefix of the segment lengths over the wave
                 const int incl = wave_inclusive_sum(len);
                 const int S = incl - len;
                 const int T = __builtin_amdgcn_readlane(incl, 63);
                 if (T == 0) continue;   // uniform over the wave
                 const unsigned long long live = __ballot(len > 0);
+                // ---- this lane's ray (position of its first sample in the
+                // brick range, step, weight, end of its samples in the wave's
+                // order, next ray with samples) for the lanes that walk into
+                // it: in the wave's LDS table, or permuted from this lane
+                RayRec mine;
+                {
+                    const unsigned long long later =
+                        lane < 63 ? (live & (~0ull << (lane + 1))) : 0ull;
+                    mine.px = r.qx + static_cast<long long>(ib) * r.tx;
+                    mine.py = r.qy + static_cast<long long>(ib) * r.ty;
+                    mine.pz = r.qz + static_cast<long long>(ib) * r.tz;
+                    mine.tx = r.tx;
+                    mine.ty = r.ty;
+                    mine.tz = r.tz;
+                    mine.wq = wq;
+                    mine.end = incl;
+                    mine.next = later ? __ffsll(static_cast<long long>(later)) - 1 : lane;
+                    mine.pad = 0;
+                }
+                // the record of ray `src` (every lane executes the permutes: a
+                // permute skipped by the source lane returns 0)
+                auto fetch = [&](int src) {
+                    RayRec e;
+                    if (TABLE) {
+                        e = tabw[src];
+                    } else {
+                        e.px = __shfl(mine.px, src, 64);
+                        e.py = __shfl(mine.py, src, 64);
+                        e.pz = __shfl(mine.pz, src, 64);
+                        e.tx = __shfl(mine.tx, src, 64);
+                        e.ty = __shfl(mine.ty, src, 64);
+                        e.tz = __shfl(mine.tz, src, 64);
+                        e.wq = __shfl(mine.wq, src, 64);
+                        e.end = __shfl(mine.end, src, 64);
+                        e.next = __shfl(mine.next, src, 64);
+                    }
+                    return e;
+                };
+                if (TABLE) {
+                    tabw[lane] = mine;
+                    wave_sync();
+                }
                 // ---- lane takes samples [start, end) of the wave's T
                 const int start = (T * lane) >> 6, end = (T * (lane + 1)) >> 6;
                 int j = 0;   // last ray with S_j <= start: it owns sample `start`
@@ -380,15 +445,22 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(6, 6
                 }
                 // the lane's first ray may be entered mid-way: `start - S_j`
                 // samples after its first sample in the brick range
-                long long ctx = shfl64(r.tx, j), cty = shfl64(r.ty, j), ctz = shfl64(r.tz, j);
                 const long long m = start - __shfl(S, j, 64);
-                long long px = shfl64(p0x, j) + m * ctx, py = shfl64(p0y, j) + m * cty,
-                          pz = shfl64(p0z, j) + m * ctz;
-                float cwq = __shfl(wq, j, 64);
-                int cend = __shfl(incl, j, 64);
-                // the next ray with samples after each lane's own (itself if none)
-                const unsigned long long later = lane < 63 ? (live & (~0ull << (lane + 1))) : 0ull;
-                const int nxt = later ? __ffsll(static_cast<long long>(later)) - 1 : lane;
+                long long px, py, pz, ctx, cty, ctz;
+                float cwq;
+                int cend, cnext;
+                {
+                    const RayRec e = fetch(j);
+                    ctx = e.tx;
+                    cty = e.ty;
+                    ctz = e.tz;
+                    px = e.px + m * ctx;
+                    py = e.py + m * cty;
+                    pz = e.pz + m * ctz;
+                    cwq = e.wq;
+                    cend = e.end;
+                    cnext = e.next;
+                }
                 const int trips = (T + 63) >> 6;
                 // the sample walk, with the corner clamps (CLAMP) or without:
                 // in the unwarped owner form a brick that holds neither the
@@ -426,26 +498,22 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(6, 6
                         // wave-uniform hand-over to the next ray with samples;
                         // it is entered at its first sample in the brick range
                         const bool need = pos < end && pos == cend;
-                        if (__any(need)) {
-                            // lanes without a hand-over read their current ray
-                            // again (the same values) and keep their position.
-                            // Every lane reads: a permute that only some lanes
-                            // execute returns 0 from the lanes that skip it
-                            const int jc = __shfl(nxt, j, 64);
-                            const int jn = need ? jc : j;
-                            ctx = shfl64(r.tx, jn);
-                            cty = shfl64(r.ty, jn);
-                            ctz = shfl64(r.tz, jn);
-                            const long long nx0 = shfl64(p0x, jn), ny0 = shfl64(p0y, jn),
-                                            nz0 = shfl64(p0z, jn);
-                            cwq = __shfl(wq, jn, 64);
-                            cend = __shfl(incl, jn, 64);
-                            if (need) {
-                                px = nx0;
-                                py = ny0;
-                                pz = nz0;
-                            }
-                            j = jn;
+                        if (TABLE ? need : __any(need)) {
+                            // with the table only the lanes that hand over
+                            // read; permutes run on every lane, and the others
+                            // keep their ray
+                            const RayRec f = fetch(TABLE ? cnext : (need ? cnext : lane));
+                            const RayRec e = need ? f : RayRec{px, py, pz, ctx, cty, ctz,
+                                                               cwq, cend, cnext, 0};
+                            px = e.px;
+                            py = e.py;
+                            pz = e.pz;
+                            ctx = e.tx;
+                            cty = e.ty;
+                            ctz = e.tz;
+                            cwq = e.wq;
+                            cend = e.end;
+                            cnext = e.next;
                         }
                         if (pos >= end) continue;
                         ++pos;
@@ -477,8 +545,9 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(6, 6
                                         w11 = gz1 * gy1;
                             const int cell = __mul24(lz, OWN_SZ) + __mul24(ly, OWN_SY) + lx;
                             if (WARP) {
-                                // the warp lookup leaves no registers for the
-                                // merge sums: add every sample at once
+                                // warped samples change cells too often for
+                                // the merge to pay (measured 6 % slower):
+                                // add every sample at once
                                 unsigned long long *const a0 = cell0 + cell;
                                 unsigned long long *const a1 = a0 + OWN_SZ;
                                 atomicAdd(a0, to_fixed(w00 * gx0));
@@ -554,6 +623,7 @@ __global__ __launch_bounds__(BP_THREADS) __attribute__((amdgpu_waves_per_eu(6, 6
                     walk(std::false_type{});
                 else
                     walk(std::true_type{});
+                if (TABLE) wave_sync();   // the table is rewritten by the next block
             }
         }
     }
@@ -683,9 +753,10 @@ hipError_t launch_back(const RayGrid &g, const WarpGrid &w, const double *Pmat, 
         if (e != hipSuccess) return e;
     }
     const int per = (bg.total + N_XCD - 1) / N_XCD;
-    const dim3 grid(static_cast<unsigned>(per * N_XCD)), block(BP_THREADS);
-    const size_t shmem = 0;   // the brick is static LDS
     const bool wp = w.U != nullptr;
+    const dim3 grid(static_cast<unsigned>(per * N_XCD));
+    const dim3 block(static_cast<unsigned>(wp ? bp_threads<true>() : bp_threads<false>()));
+    const size_t shmem = 0;   // the brick is static LDS
     size_t fblocks = (nvol + 255) / 256;
     if (fblocks > 65536) fblocks = 65536;
     // after the bricks: the direct form's chunk partials summed in chunk
