@@ -179,6 +179,131 @@ __global__ __launch_bounds__(NT) void conv3_fwd_kernel(const u16 *__restrict__ i
     }
 }
 
+// LDS-tiled form for cin >= 16.  A workgroup computes TY x TZ rows of 16
+// output voxels (x) and first stages their input, grown by one voxel on every
+// side (zeros outside the volume), in LDS: [z][y][8-channel chunk][x], 16
+// bytes per element, so the 16 lanes of an MFMA row group read 256 contiguous
+// bytes.  Each A fragment of the GEMM is then one LDS read instead of a
+// gather through L1/L2 (every input voxel feeds 27 taps); weights come from
+// global memory (the same for every wave, so from the cache).  A wave owns
+// MBW consecutive y rows of one z plane, so every LDS offset but the lane's
+// base is a compile-time constant.
+template <int CIN> struct ConvTile;
+template <> struct ConvTile<16> { static constexpr int TY = 8, TZ = 4; };
+template <> struct ConvTile<32> { static constexpr int TY = 8, TZ = 2; };
+template <> struct ConvTile<64> { static constexpr int TY = 4, TZ = 2; };
+
+template <int CIN, int COUT, bool OUT_F32, bool RELU, bool ACC>
+__global__ __launch_bounds__(NT) void conv3_tile_kernel(const u16 *__restrict__ in, int in_cs,
+                                                        int in_off, const u16 *__restrict__ wt,
+                                                        const float *__restrict__ bias, void *out,
+                                                        int out_cs, int out_off, int D, int H,
+                                                        int W) {
+    constexpr int TY = ConvTile<CIN>::TY, TZ = ConvTile<CIN>::TZ;
+    constexpr int SX = 18, SY = TY + 2, SZ = TZ + 2, NC = CIN / 8;
+    constexpr int NEL = SZ * SY * NC * SX;   // 16-byte elements
+    constexpr int MBW = TY * TZ / (NT / 64);  // rows per wave
+    constexpr int NB = COUT / 16;
+    static_assert(TY % MBW == 0, "a wave's rows lie in one z plane");
+    __shared__ bf16x8 tile[NEL];
+
+    const int ntx = (W + 15) / 16, nty = (H + TY - 1) / TY;
+    int bi = blockIdx.x;
+    const int x0 = (bi % ntx) * 16;
+    bi /= ntx;
+    const int y0 = (bi % nty) * TY, z0 = (bi / nty) * TZ;
+
+    // ---- stage the input (channel chunk fastest in global memory)
+    for (int e = threadIdx.x; e < NEL; e += NT) {
+        const int c = e % NC;
+        int t = e / NC;
+        const int x = t % SX;
+        t /= SX;
+        const int y = t % SY, z = t / SY;
+        const int gx = x0 + x - 1, gy = y0 + y - 1, gz = z0 + z - 1;
+        bf16x8 v = zero8();
+        if (gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D) {
+            const long long q = (static_cast<long long>(gz) * H + gy) * W + gx;
+            v = load8(in + q * in_cs + in_off + 8 * c);
+        }
+        tile[((z * SY + y) * NC + c) * SX + x] = v;
+    }
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    const int row0 = wave * MBW;                 // first row (y + TY z) of this wave
+    const int ym0 = row0 % TY, zm = row0 / TY;
+    // element of (row ym0, plane zm, chunk 0, x = r), tap (0, 0, 0)
+    const int lbase = (((zm + 1) * SY + ym0 + 1) * NC) * SX + r + 1;
+    f32x4 acc[MBW][NB];
+#pragma unroll
+    for (int m = 0; m < MBW; ++m)
+#pragma unroll
+        for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    if constexpr (CIN == 16) {
+        // K steps over pairs of taps: lane groups 0, 1 take tap 2p (channel
+        // chunks 0, 1), groups 2, 3 tap 2p + 1; tap 27 is zero padding
+#pragma unroll
+        for (int p = 0; p < 14; ++p) {
+            const int tap = 2 * p + (g >> 1), c = g & 1;
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const int off = lbase + ((dz * SY + dy) * NC + c) * SX + dx;
+            const bool live = tap < 27;
+            bf16x8 a[MBW], b[NB];
+#pragma unroll
+            for (int m = 0; m < MBW; ++m) a[m] = live ? tile[off + m * NC * SX] : zero8();
+#pragma unroll
+            for (int n = 0; n < NB; ++n)
+                b[n] = live ? load8(wt + (tap * COUT + n * 16 + r) * CIN + 8 * c) : zero8();
+#pragma unroll
+            for (int m = 0; m < MBW; ++m)
+#pragma unroll
+                for (int n = 0; n < NB; ++n) acc[m][n] = mma(a[m], b[n], acc[m][n]);
+        }
+    } else {
+#pragma unroll 3
+        for (int tap = 0; tap < 27; ++tap) {
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+#pragma unroll
+            for (int ks = 0; ks < CIN / 32; ++ks) {
+                const int c = 4 * ks + g;
+                const int off = lbase + ((dz * SY + dy) * NC + c) * SX + dx;
+                bf16x8 a[MBW], b[NB];
+#pragma unroll
+                for (int m = 0; m < MBW; ++m) a[m] = tile[off + m * NC * SX];
+#pragma unroll
+                for (int n = 0; n < NB; ++n)
+                    b[n] = load8(wt + (tap * COUT + n * 16 + r) * CIN + 8 * c);
+#pragma unroll
+                for (int m = 0; m < MBW; ++m)
+#pragma unroll
+                    for (int n = 0; n < NB; ++n) acc[m][n] = mma(a[m], b[n], acc[m][n]);
+            }
+        }
+    }
+    // ---- epilogue: lane (g, r) holds rows 4 g + j (x) of output channel n 16 + r
+    const int gz = z0 + zm;
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+        const int co = n * 16 + r;
+        const float bco = bias ? bias[co] : 0.0f;
+#pragma unroll
+        for (int m = 0; m < MBW; ++m) {
+            const int gy = y0 + ym0 + m;
+            if (gz >= D || gy >= H) continue;
+            const long long vrow = (static_cast<long long>(gz) * H + gy) * W + x0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int x = 4 * g + j;
+                if (x0 + x < W)
+                    store_out<OUT_F32, RELU, ACC>(out, (vrow + x) * out_cs + out_off + co,
+                                                  acc[m][n][j] + bco);
+            }
+        }
+    }
+}
+
 // Weight gradient, cin >= 16: wave = one tap; block = (voxel chunk, 4 taps).
 template <int CIN, int COUT>
 __global__ __launch_bounds__(NT) void conv3_wgrad_kernel(const u16 *__restrict__ in, int in_cs,
@@ -226,6 +351,158 @@ __global__ __launch_bounds__(NT) void conv3_wgrad_kernel(const u16 *__restrict__
         for (int n = 0; n < NBk; ++n)
 #pragma unroll
             for (int j = 0; j < 4; ++j) dst[(m * 16 + 4 * g + j) * CIN + n * 16 + r] = acc[m][n][j];
+}
+
+// Weight gradient for cin, cout in {16, 32} as LDS-tiled GEMMs:
+// dw[tap][co][ci] = sum_v dout[v][co] in[v + tap][ci], M = cout, N = cin,
+// K = 32 voxels of one x row.  A unit is a 32 (x) x 4 (y) column of voxels
+// over a run of z planes.  The workgroup stages, per plane, the output
+// gradient and (in a ring of three) the input planes, each transposed to
+// channel-major rows in LDS, so a lane's eight consecutive K values (voxels of
+// one channel) are one 16-byte read.  Wave w takes the nine taps with
+// dz = w - 1: each input row it reads once, makes the dx = -1, 0, +1
+// fragments from it with 16-bit funnel shifts, and multiplies them with the
+// output-gradient rows y' - dy, so one LDS read feeds about two MFMAs.  The
+// nine taps' sums stay in registers over all the units of the workgroup, which
+// writes them once as its partial (summed over workgroups in a fixed order).
+constexpr int WG_X = 32, WG_Y = 4, WG_IX = 48, WG_IY = WG_Y + 2, WG_THREADS = 192;
+
+__device__ __forceinline__ uint32_t funnel16(uint32_t hi, uint32_t lo) {
+    return __builtin_amdgcn_alignbit(hi, lo, 16);
+}
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(WG_THREADS) void wgrad_tile_kernel(
+    const u16 *__restrict__ in, int in_cs, int in_off, const u16 *__restrict__ dout, int dout_cs,
+    int dout_off, int D, int H, int W, int zseg, int units, float *__restrict__ partial) {
+    constexpr int MBk = COUT / 16, NBk = CIN / 16;
+    // input rows: x' = x + 8 for x in [-8, 40) (the lanes read x in [-2, 34))
+    __shared__ __attribute__((aligned(16))) u16 inT[3][CIN][WG_IY][WG_IX];
+    __shared__ __attribute__((aligned(16))) u16 dT[COUT][WG_Y][WG_X];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    const int dz = wave - 1;
+    const int tx = (W + WG_X - 1) / WG_X, ty = (H + WG_Y - 1) / WG_Y;
+    f32x4 acc[3][3][MBk][NBk];   // [dy + 1][dx + 1]
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int m = 0; m < MBk; ++m)
+#pragma unroll
+                for (int n = 0; n < NBk; ++n) acc[a][b][m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    // input plane zi (zeros outside the volume) into ring slot (zi + 3) % 3
+    auto stage_in = [&](int zi, int x0, int y0) {
+        const int slot = (zi + 3) % 3;
+        constexpr int NCH = CIN / 8, NXS = 36;   // x in [-2, 34)
+        for (int e = threadIdx.x; e < WG_IY * NXS * NCH; e += WG_THREADS) {
+            const int c = e % NCH;
+            const int t = e / NCH;
+            const int xs = t % NXS, iy = t / NXS;
+            const int gx = x0 + xs - 2, gy = y0 - 1 + iy;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (zi >= 0 && zi < D && gx >= 0 && gx < W && gy >= 0 && gy < H) {
+                const long long q = (static_cast<long long>(zi) * H + gy) * W + gx;
+                v = *reinterpret_cast<const uint4 *>(in + q * in_cs + in_off + 8 * c);
+            }
+            const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                inT[slot][8 * c + k][iy][xs + 6] = static_cast<u16>(wv[k >> 1] >> (16 * (k & 1)));
+        }
+    };
+    auto stage_dout = [&](int z, int x0, int y0) {
+        constexpr int NCH = COUT / 8;
+        for (int e = threadIdx.x; e < WG_Y * WG_X * NCH; e += WG_THREADS) {
+            const int c = e % NCH;
+            const int t = e / NCH;
+            const int x = t % WG_X, y = t / WG_X;
+            const int gx = x0 + x, gy = y0 + y;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (gx < W && gy < H) {
+                const long long q = (static_cast<long long>(z) * H + gy) * W + gx;
+                v = *reinterpret_cast<const uint4 *>(dout + q * dout_cs + dout_off + 8 * c);
+            }
+            const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                dT[8 * c + k][y][x] = static_cast<u16>(wv[k >> 1] >> (16 * (k & 1)));
+        }
+    };
+
+    for (int u = blockIdx.x; u < units; u += gridDim.x) {
+        int t = u;
+        const int x0 = (t % tx) * WG_X;
+        t /= tx;
+        const int y0 = (t % ty) * WG_Y;
+        const int za = (t / ty) * zseg;
+        const int zb = za + zseg < D ? za + zseg : D;
+        __syncthreads();   // the previous unit's reads are done
+        stage_in(za - 1, x0, y0);
+        stage_in(za, x0, y0);
+        for (int z = za; z < zb; ++z) {
+            stage_in(z + 1, x0, y0);
+            stage_dout(z, x0, y0);
+            __syncthreads();
+            // this wave's input plane z + dz
+            const int slot = (z + dz + 3) % 3;
+            bf16x8 a[WG_Y][MBk];
+#pragma unroll
+            for (int y = 0; y < WG_Y; ++y)
+#pragma unroll
+                for (int m = 0; m < MBk; ++m)
+                    a[y][m] = *reinterpret_cast<const bf16x8 *>(&dT[m * 16 + r][y][8 * g]);
+#pragma unroll
+            for (int iy = 0; iy < WG_IY; ++iy) {
+                bf16x8 b[3][NBk];
+#pragma unroll
+                for (int n = 0; n < NBk; ++n) {
+                    const u16 *row = &inT[slot][n * 16 + r][iy][0];
+                    // x' = 8 g + 6 .. 8 g + 17: last dword of chunk g, chunk
+                    // g + 1, first dword of chunk g + 2
+                    const uint32_t p3 = *reinterpret_cast<const uint32_t *>(row + 8 * g + 6);
+                    const uint4 c1 = *reinterpret_cast<const uint4 *>(row + 8 * g + 8);
+                    const uint32_t n0 = *reinterpret_cast<const uint32_t *>(row + 8 * g + 16);
+                    const uint4 lm = make_uint4(funnel16(c1.x, p3), funnel16(c1.y, c1.x),
+                                                funnel16(c1.z, c1.y), funnel16(c1.w, c1.z));
+                    const uint4 lp = make_uint4(funnel16(c1.y, c1.x), funnel16(c1.z, c1.y),
+                                                funnel16(c1.w, c1.z), funnel16(n0, c1.w));
+                    b[0][n] = __builtin_bit_cast(bf16x8, lm);
+                    b[1][n] = __builtin_bit_cast(bf16x8, c1);
+                    b[2][n] = __builtin_bit_cast(bf16x8, lp);
+                }
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy) {
+                    const int ry = iy - 1 - dy;   // output-gradient row
+                    if (ry < 0 || ry >= WG_Y) continue;
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                        for (int m = 0; m < MBk; ++m)
+#pragma unroll
+                            for (int n = 0; n < NBk; ++n)
+                                acc[dy + 1][dx][m][n] = mma(a[ry][m], b[dx][n], acc[dy + 1][dx][m][n]);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // partial[block][tap][co][ci]: lane (g, r) holds co = 16 m + 4 g + j, ci = 16 n + r
+    float *dst = partial + static_cast<long long>(blockIdx.x) * 27 * COUT * CIN;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const int tap = (dz + 1) * 9 + a * 3 + b;
+#pragma unroll
+            for (int m = 0; m < MBk; ++m)
+#pragma unroll
+                for (int n = 0; n < NBk; ++n)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        dst[(tap * COUT + m * 16 + 4 * g + j) * CIN + n * 16 + r] = acc[a][b][m][n][j];
+        }
 }
 
 // Weight gradient, cin == 1: N = taps (27 padded to 32), one wave per chunk.
@@ -663,8 +940,17 @@ template <int CI, int CO, bool F32, bool RELU, bool ACC>
 void conv3_go(dim3 grid, dim3 blk, hipStream_t s, const u16 *ip, int in_cs, int in_off,
               const u16 *wp, const float *bias, void *out, int out_cs, int out_off, int D, int H,
               int W) {
-    hipLaunchKernelGGL((conv3_fwd_kernel<CI, CO, F32, RELU, ACC>), grid, blk, 0, s, ip, in_cs,
-                       in_off, wp, bias, out, out_cs, out_off, D, H, W);
+    if constexpr (CI == 1) {
+        hipLaunchKernelGGL((conv3_fwd_kernel<CI, CO, F32, RELU, ACC>), grid, blk, 0, s, ip, in_cs,
+                           in_off, wp, bias, out, out_cs, out_off, D, H, W);
+    } else {
+        constexpr int TY = ConvTile<CI>::TY, TZ = ConvTile<CI>::TZ;
+        const long long tiles = static_cast<long long>((W + 15) / 16) * ((H + TY - 1) / TY) *
+                                ((D + TZ - 1) / TZ);
+        hipLaunchKernelGGL((conv3_tile_kernel<CI, CO, F32, RELU, ACC>),
+                           dim3(static_cast<unsigned>(tiles)), dim3(NT), 0, s, ip, in_cs, in_off,
+                           wp, bias, out, out_cs, out_off, D, H, W);
+    }
 }
 
 template <int CI, int CO>
@@ -731,6 +1017,29 @@ hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin, co
     const int chunks = static_cast<int>((nvox + chunk - 1) / chunk);
     const u16 *ip = static_cast<const u16 *>(in), *dp = static_cast<const u16 *>(dout);
     bool done = false;
+    int parts = chunks;   // partial sums written to scratch
+    if ((cin == 16 || cin == 32) && (cout == 16 || cout == 32)) {
+        // units: 32 x 4 voxel columns over runs of z planes, at most `chunks`
+        // workgroups (each loops over its units), so the scratch is the same
+        const long long tiles = static_cast<long long>((W + WG_X - 1) / WG_X) * ((H + WG_Y - 1) / WG_Y);
+        long long zsegs = chunks / tiles;
+        if (zsegs < 1) zsegs = 1;
+        if (zsegs > D) zsegs = D;
+        const int zseg = static_cast<int>((D + zsegs - 1) / zsegs);
+        const long long units = tiles * ((D + zseg - 1) / zseg);
+        parts = static_cast<int>(units < chunks ? units : chunks);
+#define CTREX_NN_WGT(CI, CO)                                                                      \
+        if (cin == CI && cout == CO)                                                              \
+            hipLaunchKernelGGL((wgrad_tile_kernel<CI, CO>), dim3(parts), dim3(WG_THREADS), 0, s, ip, \
+                               in_cs, in_off, dp, dout_cs, dout_off, D, H, W, zseg,               \
+                               static_cast<int>(units), scratch);
+        CTREX_NN_WGT(16, 16)
+        CTREX_NN_WGT(16, 32)
+        CTREX_NN_WGT(32, 16)
+        CTREX_NN_WGT(32, 32)
+#undef CTREX_NN_WGT
+        done = true;
+    }
     if (cin == 1) {
         if (cout == 16) {
             hipLaunchKernelGGL((conv3_wgrad_c1_kernel<16>), dim3(chunks), dim3(64), 0, s, ip, in_cs,
@@ -744,10 +1053,6 @@ hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin, co
                            in_off, dp, dout_cs, dout_off, D, H, W, chunk, scratch);                  \
         done = true;                                                                                 \
     }
-    CTREX_NN_WG(16, 16)
-    CTREX_NN_WG(16, 32)
-    CTREX_NN_WG(32, 16)
-    CTREX_NN_WG(32, 32)
     CTREX_NN_WG(32, 64)
     CTREX_NN_WG(64, 32)
     CTREX_NN_WG(64, 64)
@@ -756,7 +1061,7 @@ hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin, co
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int n = 27 * cout * cin;
-    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(n)), dim3(NT), 0, s, scratch, chunks, 27,
+    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(n)), dim3(NT), 0, s, scratch, parts, 27,
                        cout, cin, 0, dw);
     return hipGetLastError();
 }

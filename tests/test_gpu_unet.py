@@ -113,7 +113,10 @@ def _pack_up(L, ctx, w):
     return wt, wd
 
 
-SHAPES = [(8, 8, 16), (4, 12, 20)]   # 1024 and 960 voxels: full and ragged workgroups
+# 1024, 960 and 960 voxels (the API takes multiples of 64): full and ragged
+# workgroups; against the tiled convolution's 16 x (8|4) x (4|2) voxel tiles
+# the second is ragged in x (and y for 8), the third in y and z
+SHAPES = [(8, 8, 16), (4, 12, 20), (3, 10, 32)]
 CONV_PAIRS = [(1, 16), (16, 16), (16, 32), (32, 16), (32, 32), (32, 64), (64, 32), (64, 64)]
 UP_PAIRS = [(64, 32), (32, 16)]
 
