@@ -12,7 +12,9 @@
  *    with channel stride `cs` and channel offset `off` sits at
  *    ((z * H + y) * W + x) * cs + off + c.  A stride larger than the channel
  *    count lets a layer read or write a slice of a wider tensor (the skip
- *    concatenations are built in place this way).  Volumes D x H x W need
+ *    concatenations are built in place this way).  Tensors of 16 or more
+ *    channels are read 8 channels at a time (16-byte loads): their stride and
+ *    offset must be multiples of 8 (CTREX_ESHAPE otherwise).  Volumes D x H x W need
  *    D * H * W to be a multiple of 64 and, for the 2x pooling and up-sampling,
  *    even sides.
  *  - Convolution weights are packed BF16 `[taps][cout][cin]` (cin fastest);

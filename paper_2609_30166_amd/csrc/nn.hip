@@ -41,6 +41,15 @@ __device__ __forceinline__ u16 f2bf(float v) {
     return static_cast<u16>(u >> 16);
 }
 
+// Two floats rounded to nearest-even BF16 and packed (first in the low half).
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+    bf16x2 v;
+    v[0] = static_cast<__bf16>(lo);
+    v[1] = static_cast<__bf16>(hi);
+    return __builtin_bit_cast(uint32_t, v);
+}
+
 __device__ __forceinline__ bf16x8 load8(const u16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
 __device__ __forceinline__ bf16x8 zero8() {
     bf16x8 z;
@@ -194,11 +203,12 @@ template <> struct ConvTile<32> { static constexpr int TY = 8, TZ = 2; };
 template <> struct ConvTile<64> { static constexpr int TY = 4, TZ = 2; };
 
 template <int CIN, int COUT, bool OUT_F32, bool RELU, bool ACC>
-__global__ __launch_bounds__(NT) void conv3_tile_kernel(const u16 *__restrict__ in, int in_cs,
+__global__ __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(CIN == 16 && COUT == 16 ? 4 : 1))) void conv3_tile_kernel(const u16 *__restrict__ in, int in_cs,
                                                         int in_off, const u16 *__restrict__ wt,
                                                         const float *__restrict__ bias, void *out,
                                                         int out_cs, int out_off, int D, int H,
-                                                        int W) {
+                                                        int W, int out_vec) {
     constexpr int TY = ConvTile<CIN>::TY, TZ = ConvTile<CIN>::TZ;
     constexpr int SX = 18, SY = TY + 2, SZ = TZ + 2, NC = CIN / 8;
     constexpr int NEL = SZ * SY * NC * SX;   // 16-byte elements
@@ -241,64 +251,88 @@ __global__ __launch_bounds__(NT) void conv3_tile_kernel(const u16 *__restrict__ 
 #pragma unroll
         for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    if constexpr (CIN == 16) {
-        // K steps over pairs of taps: lane groups 0, 1 take tap 2p (channel
-        // chunks 0, 1), groups 2, 3 tap 2p + 1; tap 27 is zero padding
+    // K steps: for 16 channels pairs of taps (lane groups 0, 1 take tap 2p,
+    // channel chunks 0, 1; groups 2, 3 tap 2p + 1; tap 27 is zero padding),
+    // otherwise one tap and 32 channels per step.  The fragments of step
+    // p + 1 are read while the MFMAs of step p run (two register sets; the
+    // scheduling barriers keep the compiler from moving the reads after them).
+    constexpr int KSTEPS = CIN == 16 ? 14 : 27 * (CIN / 32);
+    auto fetch = [&](int p, bf16x8 (&a)[MBW], bf16x8 (&b)[NB]) {
+        const int tap = CIN == 16 ? 2 * p + (g >> 1) : p / (CIN / 32);
+        const int c = CIN == 16 ? (g & 1) : 4 * (p % (CIN / 32)) + g;
+        const bool live = tap < 27;
+        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+        const int off = lbase + ((dz * SY + dy) * NC + c) * SX + dx;
 #pragma unroll
-        for (int p = 0; p < 14; ++p) {
-            const int tap = 2 * p + (g >> 1), c = g & 1;
-            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-            const int off = lbase + ((dz * SY + dy) * NC + c) * SX + dx;
-            const bool live = tap < 27;
-            bf16x8 a[MBW], b[NB];
+        for (int m = 0; m < MBW; ++m) a[m] = live ? tile[off + m * NC * SX] : zero8();
 #pragma unroll
-            for (int m = 0; m < MBW; ++m) a[m] = live ? tile[off + m * NC * SX] : zero8();
+        for (int n = 0; n < NB; ++n)
+            b[n] = live ? load8(wt + (tap * COUT + n * 16 + r) * CIN + 8 * c) : zero8();
+    };
+    auto step = [&](const bf16x8 (&a)[MBW], const bf16x8 (&b)[NB]) {
 #pragma unroll
-            for (int n = 0; n < NB; ++n)
-                b[n] = live ? load8(wt + (tap * COUT + n * 16 + r) * CIN + 8 * c) : zero8();
+        for (int m = 0; m < MBW; ++m)
 #pragma unroll
-            for (int m = 0; m < MBW; ++m)
+            for (int n = 0; n < NB; ++n) acc[m][n] = mma(b[n], a[m], acc[m][n]);
+    };
+    bf16x8 a0[MBW], b0[NB], a1[MBW], b1[NB];
+    fetch(0, a0, b0);
 #pragma unroll
-                for (int n = 0; n < NB; ++n) acc[m][n] = mma(a[m], b[n], acc[m][n]);
-        }
-    } else {
-#pragma unroll 3
-        for (int tap = 0; tap < 27; ++tap) {
-            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-#pragma unroll
-            for (int ks = 0; ks < CIN / 32; ++ks) {
-                const int c = 4 * ks + g;
-                const int off = lbase + ((dz * SY + dy) * NC + c) * SX + dx;
-                bf16x8 a[MBW], b[NB];
-#pragma unroll
-                for (int m = 0; m < MBW; ++m) a[m] = tile[off + m * NC * SX];
-#pragma unroll
-                for (int n = 0; n < NB; ++n)
-                    b[n] = load8(wt + (tap * COUT + n * 16 + r) * CIN + 8 * c);
-#pragma unroll
-                for (int m = 0; m < MBW; ++m)
-#pragma unroll
-                    for (int n = 0; n < NB; ++n) acc[m][n] = mma(a[m], b[n], acc[m][n]);
-            }
-        }
+    for (int p = 0; p < KSTEPS; p += 2) {
+        if (p + 1 < KSTEPS) fetch(p + 1, a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
+        step(a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (p + 2 < KSTEPS) fetch(p + 2, a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (p + 1 < KSTEPS) step(a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
     }
-    // ---- epilogue: lane (g, r) holds rows 4 g + j (x) of output channel n 16 + r
-    const int gz = z0 + zm;
+    // ---- epilogue.  The products were formed as weights x inputs, so lane
+    // (g, r) holds output channels n 16 + 4 g + j (j < 4) of voxel r of each
+    // row: bias, ReLU and rounding four at a time, one 8-byte (BF16) or
+    // 16-byte (FP32) store per lane and block, 512 or 1024 contiguous bytes
+    // per wave (a channel slice at a stride and offset not multiple of 4
+    // stores element by element)
+    const int gz = z0 + zm, gx = x0 + r;
 #pragma unroll
     for (int n = 0; n < NB; ++n) {
-        const int co = n * 16 + r;
-        const float bco = bias ? bias[co] : 0.0f;
+        const int co0 = n * 16 + 4 * g;
+        float bco[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bco[j] = bias ? bias[co0 + j] : 0.0f;
 #pragma unroll
         for (int m = 0; m < MBW; ++m) {
             const int gy = y0 + ym0 + m;
-            if (gz >= D || gy >= H) continue;
-            const long long vrow = (static_cast<long long>(gz) * H + gy) * W + x0;
+            if (gz >= D || gy >= H || gx >= W) continue;
+            const long long o = ((static_cast<long long>(gz) * H + gy) * W + gx) * out_cs + out_off + co0;
+            float v[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int x = 4 * g + j;
-                if (x0 + x < W)
-                    store_out<OUT_F32, RELU, ACC>(out, (vrow + x) * out_cs + out_off + co,
-                                                  acc[m][n][j] + bco);
+                v[j] = acc[m][n][j] + bco[j];
+                if (RELU) v[j] = fmaxf(v[j], 0.0f);
+            }
+            if (!out_vec) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) store_out<OUT_F32, false, ACC>(out, o + j, v[j]);
+            } else if (OUT_F32) {
+                float4 *q = reinterpret_cast<float4 *>(static_cast<float *>(out) + o);
+                float4 w = make_float4(v[0], v[1], v[2], v[3]);
+                if (ACC) {
+                    const float4 p = *q;
+                    w = make_float4(p.x + v[0], p.y + v[1], p.z + v[2], p.w + v[3]);
+                }
+                *q = w;
+            } else {
+                uint2 *q = reinterpret_cast<uint2 *>(static_cast<u16 *>(out) + o);
+                if (ACC) {
+                    const uint2 p = *q;
+                    v[0] += __uint_as_float(p.x << 16);
+                    v[1] += __uint_as_float(p.x & 0xffff0000u);
+                    v[2] += __uint_as_float(p.y << 16);
+                    v[3] += __uint_as_float(p.y & 0xffff0000u);
+                }
+                *q = make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
             }
         }
     }
@@ -562,50 +596,75 @@ __global__ __launch_bounds__(NT) void reduce_wgrad_kernel(const float *__restric
                                                           int chunks, int taps, int cout, int cin,
                                                           int tap_major_out,
                                                           float *__restrict__ dw) {
+    // 32 outputs per block, 8 slices of the chunks each (slice k sums chunks
+    // k, k + 8, ...), slices then added in order: a fixed order in FP64
+    __shared__ double red[NT / 32][32];
     const int n = taps * cout * cin;
-    const int i = blockIdx.x * NT + threadIdx.x;
-    if (i >= n) return;
-    // i enumerates the partial's [tap][co][ci] order
-    double s = 0.0;
-    for (int c = 0; c < chunks; ++c) s += static_cast<double>(partial[static_cast<long long>(c) * n + i]);
+    const int o = threadIdx.x & 31, sl = threadIdx.x >> 5;
+    const int i = blockIdx.x * 32 + o;   // the partial's [tap][co][ci] order
+    double sum = 0.0;
+    if (i < n)
+        for (int c = sl; c < chunks; c += NT / 32)
+            sum += static_cast<double>(partial[static_cast<long long>(c) * n + i]);
+    red[sl][o] = sum;
+    __syncthreads();
+    if (sl != 0 || i >= n) return;
+    double t = 0.0;
+    for (int k = 0; k < NT / 32; ++k) t += red[k][o];
     const int tap = i / (cout * cin);
     const int rem = i - tap * cout * cin;
     const int co = rem / cin, ci = rem - co * cin;
     // conv3: master order [co][ci][tap]; upconv: [ci][co][tap]
-    const int o = tap_major_out ? (ci * cout + co) * taps + tap : (co * cin + ci) * taps + tap;
-    dw[o] = static_cast<float>(s);
+    const int ox = tap_major_out ? (ci * cout + co) * taps + tap : (co * cin + ci) * taps + tap;
+    dw[ox] = static_cast<float>(t);
 }
 
 // Per-channel sums over voxels: partial[block][c].
 __global__ __launch_bounds__(NT) void channel_sum_kernel(const u16 *__restrict__ x, int cs, int off,
                                                          int c, long long nvox,
                                                          double *__restrict__ partial) {
-    // thread t of the block handles channel t % c over voxels strided by NT / c
-    __shared__ double red[NT];
-    const int per = NT / c;   // c divides NT (16, 32, 64)
-    const int ch = threadIdx.x % c, lane_v = threadIdx.x / c;
-    double s = 0.0;
+    // thread t reads 8 channels (8 (t % (c / 8)) ..) of one voxel as one
+    // 16-byte load, over voxels strided by NT / (c / 8); c is 16, 32 or 64
+    __shared__ double red[NT][8];
+    const int cg = c / 8, per = NT / cg;
+    const int grp = threadIdx.x % cg, lane_v = threadIdx.x / cg;
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const long long stride = static_cast<long long>(gridDim.x) * per;
-    for (long long v = static_cast<long long>(blockIdx.x) * per + lane_v; v < nvox; v += stride)
-        s += static_cast<double>(bf2f(x[v * cs + off + ch]));
-    red[threadIdx.x] = s;
+    for (long long v = static_cast<long long>(blockIdx.x) * per + lane_v; v < nvox; v += stride) {
+        const uint4 w = *reinterpret_cast<const uint4 *>(x + v * cs + off + 8 * grp);
+        const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            s[k] += static_cast<double>(bf2f(static_cast<u16>(wv[k >> 1] >> (16 * (k & 1)))));
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) red[threadIdx.x][k] = s[k];
     __syncthreads();
     if (threadIdx.x < c) {
+        const int g8 = threadIdx.x / 8, k = threadIdx.x % 8;
         double t = 0.0;
-        for (int k = 0; k < per; ++k) t += red[k * c + threadIdx.x];
+        for (int l = 0; l < per; ++l) t += red[l * cg + g8][k];
         partial[static_cast<long long>(blockIdx.x) * c + threadIdx.x] = t;
     }
 }
 
 // out[j] = sum_i partial[i * ld + j] for j < cols (FP64, fixed order).
-__global__ __launch_bounds__(64) void reduce_rows_kernel(const double *__restrict__ partial,
+__global__ __launch_bounds__(NT) void reduce_rows_kernel(const double *__restrict__ partial,
                                                          int rows, int cols, int ld,
                                                          float *__restrict__ out) {
-    const int j = blockIdx.x * 64 + threadIdx.x;
-    if (j >= cols) return;
-    double s = 0.0;
-    for (int i = 0; i < rows; ++i) s += partial[static_cast<long long>(i) * ld + j];
-    out[j] = static_cast<float>(s);
+    // 32 columns per block, 8 slices of the rows, added in a fixed order
+    __shared__ double red[NT / 32][32];
+    const int o = threadIdx.x & 31, sl = threadIdx.x >> 5;
+    const int jc = blockIdx.x * 32 + o;
+    double sum = 0.0;
+    if (jc < cols)
+        for (int i = sl; i < rows; i += NT / 32) sum += partial[static_cast<long long>(i) * ld + jc];
+    red[sl][o] = sum;
+    __syncthreads();
+    if (sl != 0 || jc >= cols) return;
+    double t = 0.0;
+    for (int k = 0; k < NT / 32; ++k) t += red[k][o];
+    out[jc] = static_cast<float>(t);
 }
 
 // ------------------------------------------------------ 2x transposed conv --
@@ -947,9 +1006,10 @@ void conv3_go(dim3 grid, dim3 blk, hipStream_t s, const u16 *ip, int in_cs, int 
         constexpr int TY = ConvTile<CI>::TY, TZ = ConvTile<CI>::TZ;
         const long long tiles = static_cast<long long>((W + 15) / 16) * ((H + TY - 1) / TY) *
                                 ((D + TZ - 1) / TZ);
+        const int out_vec = (out_cs % 4 == 0 && out_off % 4 == 0) ? 1 : 0;
         hipLaunchKernelGGL((conv3_tile_kernel<CI, CO, F32, RELU, ACC>),
                            dim3(static_cast<unsigned>(tiles)), dim3(NT), 0, s, ip, in_cs, in_off,
-                           wp, bias, out, out_cs, out_off, D, H, W);
+                           wp, bias, out, out_cs, out_off, D, H, W, out_vec);
     }
 }
 
@@ -1061,7 +1121,7 @@ hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin, co
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int n = 27 * cout * cin;
-    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(n)), dim3(NT), 0, s, scratch, parts, 27,
+    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(n, 32)), dim3(NT), 0, s, scratch, parts, 27,
                        cout, cin, 0, dw);
     return hipGetLastError();
 }
@@ -1070,12 +1130,13 @@ size_t channel_sum_scratch(int c) { return sizeof(double) * 1024 * static_cast<s
 
 hipError_t launch_channel_sum(const void *x, int cs, int off, int c, long long nvox, float *out,
                               double *scratch, hipStream_t s) {
+    if (c % 8 || c < 8 || c > 64) return hipErrorInvalidValue;
     const int blocks = 1024;
     hipLaunchKernelGGL(channel_sum_kernel, dim3(blocks), dim3(NT), 0, s, static_cast<const u16 *>(x),
                        cs, off, c, nvox, scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_rows_kernel, dim3(blocks_for(c, 64)), dim3(64), 0, s, scratch, blocks, c,
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(blocks_for(c, 32)), dim3(NT), 0, s, scratch, blocks, c,
                        c, out);
     return hipGetLastError();
 }
@@ -1154,7 +1215,7 @@ hipError_t launch_upconv2_wgrad(const void *in, int in_cs, int in_off, int cin, 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int n = 8 * cout * cin;
-    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(n)), dim3(NT), 0, s, scratch, chunks, 8,
+    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(n, 32)), dim3(NT), 0, s, scratch, chunks, 8,
                        cout, cin, 1, dw);
     return hipGetLastError();
 }
@@ -1208,8 +1269,8 @@ hipError_t launch_head_bwd(const void *act, int c, const float *h, float scale, 
                        static_cast<u16 *>(dact), n, scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (dh) hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(64), 0, s, scratch, blocks, c, c + 1, dh);
-    if (db) hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(64), 0, s, scratch + c, blocks, 1, c + 1, db);
+    if (dh) hipLaunchKernelGGL(reduce_rows_kernel, dim3(blocks_for(c, 32)), dim3(NT), 0, s, scratch, blocks, c, c + 1, dh);
+    if (db) hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(NT), 0, s, scratch + c, blocks, 1, c + 1, db);
     return hipGetLastError();
 }
 

@@ -130,8 +130,8 @@ int ctrex_nn_conv3_wgrad(ctrex_ctx *c, const void *in, int32_t in_cs, int32_t in
     if (!(cin == 1 || chan_ok(cin)) || !chan_ok(cout) || (cin == 1 && cout != 16))
         return fail(c, CTREX_ESHAPE, "unsupported channels %d -> %d", cin, cout);
     if ((st = check_vol(c, D, H, W, false))) return st;
-    if ((st = check_slice(c, "in", in, in_cs, in_off, cin, false))) return st;
-    if ((st = check_slice(c, "dout", dout, dout_cs, dout_off, cout, false))) return st;
+    if ((st = check_slice(c, "in", in, in_cs, in_off, cin, cin > 1))) return st;
+    if ((st = check_slice(c, "dout", dout, dout_cs, dout_off, cout, true))) return st;
     if (!dw) return fail(c, CTREX_EINVAL, "dw is NULL");
     const long long n = static_cast<long long>(D) * H * W;
     const size_t need = std::max(nn::conv3_wgrad_scratch(cin, cout, n), nn::channel_sum_scratch(cout));
@@ -196,7 +196,7 @@ int ctrex_nn_upconv2_wgrad(ctrex_ctx *c, const void *in, int32_t in_cs, int32_t 
         return fail(c, CTREX_ESHAPE, "unsupported channels %d -> %d", cin, cout);
     if ((st = check_vol(c, D, H, W, false))) return st;
     if ((st = check_slice(c, "in", in, in_cs, in_off, cin, false))) return st;
-    if ((st = check_slice(c, "dout", dout, dout_cs, dout_off, cout, false))) return st;
+    if ((st = check_slice(c, "dout", dout, dout_cs, dout_off, cout, true))) return st;
     if (!dw) return fail(c, CTREX_EINVAL, "dw is NULL");
     const long long n = static_cast<long long>(D) * H * W;
     const size_t need = std::max(nn::upconv2_wgrad_scratch(cin, cout, n), nn::channel_sum_scratch(cout));
