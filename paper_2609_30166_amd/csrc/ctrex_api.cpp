@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <list>
@@ -132,6 +133,7 @@ RayGrid make_grid(const ctrex_ctx *c, const int32_t *dev_views, int32_t n_views)
     g.tiles_v = (c->n_v + TILE_V - 1) / TILE_V;
     const long long total = static_cast<long long>(g.tiles_u) * g.tiles_v * n_views;
     g.total_blocks = static_cast<int>(total);
+    g.tube = c->fp_tube;
     return g;
 }
 
@@ -361,6 +363,8 @@ int ctrex_create(ctrex_ctx **out, int device) {
     if (hipSetDevice(device) != hipSuccess) return CTREX_EDEVICE;
     ctrex_ctx *c = new ctrex_ctx();
     c->device = device;
+    const char *gather = std::getenv("CTREX_FP_GATHER");
+    c->fp_tube = gather && std::strcmp(gather, "lds") == 0;
     if (hipMalloc(&c->d_count, sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&c->d_scalar, 4 * sizeof(float)) != hipSuccess ||
         hipMalloc(&c->d_red, sizeof(double) * 8193) != hipSuccess) {

@@ -21,6 +21,9 @@ struct DeviceViewList {
 
 struct ctrex_ctx {
     int device = 0;
+    // forward projector gather: 0 direct (corner-packed copies), 1 LDS-staged
+    // tubes (CTREX_FP_GATHER=lds at context creation)
+    int fp_tube = 0;
     std::string err;
     // geometry
     bool have_geom = false;

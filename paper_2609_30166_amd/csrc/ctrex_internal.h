@@ -38,6 +38,7 @@ struct RayGrid {
     // detector tiling of the launch
     int tiles_u, tiles_v;
     int total_blocks;    // tiles_u * tiles_v * n_views
+    int tube = 0;        // forward projection of FP32 volumes through LDS-staged tubes
 };
 
 struct WarpGrid {

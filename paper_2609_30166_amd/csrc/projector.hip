@@ -122,19 +122,186 @@ __device__ __forceinline__ float march(const RayGrid &g, const WarpGrid &w,
     return y / static_cast<float>(g.n_sub);
 }
 
-// Occupancy cap.  The FP32 rays gather from the corner-packed copies; at the
-// 5 waves per SIMD their registers allow, more concurrent rays evict each
-// other's patches from L1 and L2.  Measured at 512^3 x 720 x 768^2 (results
-// bitwise identical): 866 ms at 5 waves, 782 ms at 3, 876 ms at 2, 1066 ms at
-// 8.  The warped and 16-bit variants, and the ray-length mode (no gathers),
-// keep the default.
-template <typename TV, int MODE, bool WARP>
-constexpr int fp_max_waves() {
-    return (sizeof(TV) == 4 && !WARP && MODE != FP_RECIP_ONES) ? 3 : 8;
+// ------------------------------------------------ LDS-staged tube gather ----
+// Alternative gather for FP32 volumes without warp.  The 64 rays of a wave (an
+// 8x8 pixel quadrant) are nearly parallel: the wave walks them in slabs of
+// TUBE_S voxels along their common major axis, stages the box of voxels the
+// slab's samples can touch (bounded from each ray's FP32 line with a margin of
+// one voxel, clamped to the volume) in a wave-private LDS region, and every
+// lane takes its own samples of the slab from it.  Positions, corners,
+// trilinear weights and the two accumulators are those of `march`, so the
+// value is bitwise the same; a slab whose box exceeds TUBE_CAP voxels, or a
+// sub-view whose rays do not all advance the same way along one axis, gathers
+// from global memory instead.
+constexpr int TUBE_S = 8;
+constexpr int TUBE_CAP = 2048;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_max_step(float v) {
+    const int o = __builtin_amdgcn_update_dpp(__float_as_int(-__builtin_inff()), __float_as_int(v),
+                                              CTRL, ROWS, 0xf, false);
+    return fmaxf(v, __int_as_float(o));
 }
 
-template <typename TV, typename TS, int MODE, bool WARP>
-__global__ __launch_bounds__(PROJ_THREADS) __attribute__((amdgpu_waves_per_eu(1, fp_max_waves<TV, MODE, WARP>())))
+// Maximum over the wave (lanes without a value pass -inf).
+__device__ __forceinline__ float wave_max_f(float x) {
+    x = dpp_max_step<0x111, 0xf>(x);   // row_shr:1
+    x = dpp_max_step<0x112, 0xf>(x);   // row_shr:2
+    x = dpp_max_step<0x114, 0xf>(x);   // row_shr:4
+    x = dpp_max_step<0x118, 0xf>(x);   // row_shr:8
+    x = dpp_max_step<0x142, 0xa>(x);   // row_bcast:15 -> rows 1, 3
+    x = dpp_max_step<0x143, 0xc>(x);   // row_bcast:31 -> rows 2, 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+template <int MODE>
+__device__ float march_tube(const RayGrid &g, const float *__restrict__ vol, const VolDims &d,
+                            const TileCoord &t, bool active, float *__restrict__ tube) {
+    float y = 0.0f;
+    const int lane = threadIdx.x & 63;
+    const int n3[3] = {d.nx, d.ny, d.nz};
+    for (int s = 0; s < g.n_sub; ++s) {
+        const SubView &sv = g.tab[t.p * g.n_sub + s];
+        Ray r;
+        const bool ok = active && setup_ray(sv, static_cast<double>(t.iu),
+                                            static_cast<double>(t.iv), g.nx, g.ny, g.nz, g.step, r);
+        const unsigned long long okm = __ballot(ok);
+        if (!okm) continue;   // uniform
+        // common major axis and direction, from the first ray; every ray must
+        // advance strictly the same way along it
+        const int f = __builtin_ctzll(okm);
+        const float sx = __shfl(r.fx, f, 64), sy = __shfl(r.fy, f, 64), sz = __shfl(r.fz, f, 64);
+        const int ma = (fabsf(sx) >= fabsf(sy) && fabsf(sx) >= fabsf(sz)) ? 0
+                       : (fabsf(sy) >= fabsf(sz) ? 1 : 2);
+        const long long ta = ma == 0 ? r.tx : (ma == 1 ? r.ty : r.tz);
+        const bool up = (ma == 0 ? sx : (ma == 1 ? sy : sz)) > 0.0f;
+        const bool same = __all(!ok || (up ? ta > 0 : ta < 0));
+        float acc0 = 0.0f, acc1 = 0.0f;
+        long long px = r.qx, py = r.qy, pz = r.qz;
+        const int n = ok ? r.n : 0;
+        int i = 0;
+        auto major_of = [&](long long qx, long long qy, long long qz) {
+            int k;
+            float fr;
+            fx_split(ma == 0 ? qx : (ma == 1 ? qy : qz), k, fr);
+            return k;
+        };
+        auto sample_at = [&](const float *src, int x0, int y0, int z0, int lx, int ly, int lz,
+                             bool lds) {
+            int ix, iy, iz;
+            Corner k;
+            sample_corner<false>(d, WarpGrid{}, 0.0f, px, py, pz, ix, iy, iz, k.fx, k.fy, k.fz);
+            // a corner outside the staged box (never, if the bound holds)
+            // falls back to the global gather
+            lds = lds && static_cast<unsigned>(ix - x0) < static_cast<unsigned>(lx - 1) &&
+                  static_cast<unsigned>(iy - y0) < static_cast<unsigned>(ly - 1) &&
+                  static_cast<unsigned>(iz - z0) < static_cast<unsigned>(lz - 1);
+            float v;
+            if (lds) {
+                const int lxy = lx * ly;
+                const int b = ((iz - z0) * ly + (iy - y0)) * lx + (ix - x0);
+                v = blend(k, src[b], src[b + 1], src[b + lx], src[b + lx + 1], src[b + lxy],
+                          src[b + lxy + 1], src[b + lxy + lx], src[b + lxy + lx + 1]);
+            } else {
+                k.base = base_x(d, ix, iy, iz);
+                v = gather(vol, d, k);
+            }
+            if (i & 1)
+                acc1 += v;
+            else
+                acc0 += v;
+            px += r.tx;
+            py += r.ty;
+            pz += r.tz;
+            ++i;
+        };
+        if (!same) {
+            while (i < n) sample_at(nullptr, 0, 0, 0, 2, 2, 2, false);
+        } else {
+            // major-axis index range of the wave's samples
+            const int k_first = n > 0 ? major_of(px, py, pz) : 0;
+            const long long lx_ = px + static_cast<long long>(n - 1) * r.tx,
+                            ly_ = py + static_cast<long long>(n - 1) * r.ty,
+                            lz_ = pz + static_cast<long long>(n - 1) * r.tz;
+            const int k_last = n > 0 ? major_of(lx_, ly_, lz_) : 0;
+            const float lo_all = n > 0 ? static_cast<float>(up ? k_first : k_last) : __builtin_inff();
+            const float hi_all = n > 0 ? static_cast<float>(up ? k_last : k_first) : -__builtin_inff();
+            const int kmin = static_cast<int>(-wave_max_f(-lo_all));
+            const int kmax = static_cast<int>(wave_max_f(hi_all));
+            // the ray's FP32 line: minor coordinates as functions of the major one
+            const float b3[3] = {r.bx, r.by, r.bz}, f3[3] = {r.fx, r.fy, r.fz};
+            const int mb = ma == 0 ? 1 : 0, mc = ma == 2 ? 1 : 2;
+            const float ia = ok ? 1.0f / f3[ma] : 0.0f;
+            const float nslab = static_cast<float>((kmax - kmin) / TUBE_S + 1);
+            for (int j = 0; j < static_cast<int>(nslab); ++j) {
+                // slab [sl, sh] of major indices, in the rays' direction
+                const int sl = up ? kmin + j * TUBE_S : kmax - (j + 1) * TUBE_S + 1;
+                const int sh = sl + TUBE_S - 1;
+                int lo3[3], hi3[3];
+                lo3[ma] = max(0, min(sl, n3[ma] - 2));
+                hi3[ma] = min(n3[ma] - 1, sh + 1);
+                float mlo[2], mhi[2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int ax = q == 0 ? mb : mc;
+                    const float slope = f3[ax] * ia;
+                    const float m1 = b3[ax] + (static_cast<float>(sl) - b3[ma]) * slope;
+                    const float m2 = b3[ax] + (static_cast<float>(sh + 1) - b3[ma]) * slope;
+                    mlo[q] = ok ? fminf(m1, m2) : __builtin_inff();
+                    mhi[q] = ok ? fmaxf(m1, m2) : -__builtin_inff();
+                }
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int ax = q == 0 ? mb : mc;
+                    const float a = -wave_max_f(-mlo[q]), b = wave_max_f(mhi[q]);
+                    lo3[ax] = max(0, min(n3[ax] - 1, static_cast<int>(floorf(a)) - 1));
+                    hi3[ax] = max(0, min(n3[ax] - 1, static_cast<int>(floorf(b)) + 2));
+                }
+                const int lx = hi3[0] - lo3[0] + 1, ly = hi3[1] - lo3[1] + 1,
+                          lz = hi3[2] - lo3[2] + 1;
+                const int lxy = lx * ly, nbox = lxy * lz;
+                const bool fits = nbox <= TUBE_CAP;   // uniform
+                if (fits) {
+                    for (int e = lane; e < nbox; e += 64) {
+                        const int zz = e / lxy, rem = e - zz * lxy;
+                        const int yy = rem / lx, xx = rem - yy * lx;
+                        tube[e] = vol[((lo3[2] + zz) * d.ny + lo3[1] + yy) * d.nx + lo3[0] + xx];
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+                // this lane's samples whose major index lies in the slab
+                while (i < n) {
+                    const int k = major_of(px, py, pz);
+                    if (k < sl || k > sh) break;
+                    sample_at(tube, lo3[0], lo3[1], lo3[2], lx, ly, lz, fits);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            // samples beyond the slabs (none unless the index estimate erred)
+            while (i < n) sample_at(nullptr, 0, 0, 0, 2, 2, 2, false);
+        }
+        if (ok) y = fmaf(r.h, acc0 + acc1, y);
+    }
+    return y / static_cast<float>(g.n_sub);
+}
+
+// Occupancy caps.  The rays gather from the corner-packed copies; with more
+// concurrent rays than the caches hold their patches evict each other.
+// Measured at 512^3 x 720 x 768^2 (results bitwise identical): FP32 866 ms at
+// 5 waves per SIMD, 782 ms at 3, 876 ms at 2, 1066 ms at 8; 16-bit 823 ms at
+// 8, 765 at 6, 711 at 5, 674 at 4, 689 at 3, 808 at 2.  The warped variants
+// and the ray-length mode (no gathers) keep the default.
+template <typename TV, int MODE, bool WARP>
+constexpr int fp_max_waves() {
+    return (WARP || MODE == FP_RECIP_ONES) ? 8 : (sizeof(TV) == 4 ? 3 : 4);
+}
+
+template <typename TV, typename TS, int MODE, bool WARP, bool TUBE = false>
+__global__ __launch_bounds__(PROJ_THREADS) __attribute__((amdgpu_waves_per_eu(1, TUBE ? 8 : fp_max_waves<TV, MODE, WARP>())))
 void fp_kernel(RayGrid g, WarpGrid w,
                                                           const TV *__restrict__ vol,
                                                           TS *__restrict__ out, FpExtra ex) {
@@ -142,6 +309,25 @@ void fp_kernel(RayGrid g, WarpGrid w,
     if (!t.valid) return;  // uniform over the block
     const VolDims d = vol_dims(g);
     const bool active = t.iu < g.n_u && t.iv < g.n_v;
+    if constexpr (TUBE) {
+        __shared__ float tube[PROJ_THREADS / 64][TUBE_CAP];
+        const float y = march_tube<MODE>(g, reinterpret_cast<const float *>(vol), d, t, active,
+                                         tube[threadIdx.x >> 6]);
+        const int pix = (t.k * g.n_v + t.iv) * g.n_u + t.iu;
+        if (MODE == FP_PLAIN) {
+            if (active) st(out, pix, y);
+        } else {
+            double e2 = 0.0;
+            if (active) {
+                const float bval = ld(static_cast<const TS *>(ex.b), pix);
+                const float res = bval - y;
+                e2 = static_cast<double>(res) * static_cast<double>(res);
+                if (MODE == FP_CORRECT) st(out, pix, (ex.R ? ex.R[pix] : ex.rscale) * res);
+            }
+            block_sum_store(e2, ex.partials + t.lidx);
+        }
+        return;
+    }
     // projections whose rays run mainly along x read the y-fastest copy
     const TV *vt = static_cast<const TV *>(ex.vol_t);
     const double uc = static_cast<double>((t.iu & ~(TILE_U - 1)) + TILE_U / 2);
@@ -202,6 +388,20 @@ inline dim3 proj_grid(const RayGrid &g) {
     return dim3(static_cast<unsigned>(per * N_XCD));
 }
 
+// FP32 volumes without warp may take the LDS-staged tube gather.
+template <typename TV, typename TS, int M, bool W>
+void fp_launch(dim3 grid, dim3 block, hipStream_t s, const RayGrid &g, const WarpGrid &w,
+               const TV *v, TS *o, const FpExtra &ex) {
+    if constexpr (!W && sizeof(TV) == 4) {
+        if (g.tube) {
+            hipLaunchKernelGGL((fp_kernel<TV, TS, M, false, true>), grid, block, 0, s, g, w, v, o,
+                               ex);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((fp_kernel<TV, TS, M, W>), grid, block, 0, s, g, w, v, o, ex);
+}
+
 template <typename TV, typename TS>
 hipError_t fp_dispatch_mode(const RayGrid &g, const WarpGrid &w, const void *vol, void *out,
                             int mode, const FpExtra &ex, hipStream_t s) {
@@ -209,7 +409,7 @@ hipError_t fp_dispatch_mode(const RayGrid &g, const WarpGrid &w, const void *vol
     const TV *v = static_cast<const TV *>(vol);
     TS *o = static_cast<TS *>(out);
     const bool wp = w.U != nullptr;
-#define CTREX_FP(M, W) hipLaunchKernelGGL((fp_kernel<TV, TS, M, W>), grid, block, 0, s, g, w, v, o, ex)
+#define CTREX_FP(M, W) fp_launch<TV, TS, M, W>(grid, block, s, g, w, v, o, ex)
     if (mode == FP_PLAIN) {
         if (wp) CTREX_FP(FP_PLAIN, true); else CTREX_FP(FP_PLAIN, false);
     } else if (mode == FP_CORRECT) {

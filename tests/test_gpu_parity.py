@@ -125,6 +125,39 @@ def test_ragged_tiles_and_odd_volumes(dev, n_u, n_v, shape):
     assert rel_l2(z, z_ref) <= TOL
 
 
+def test_tube_gather_is_bitwise_the_direct_gather(tiny, dev, monkeypatch):
+    """The LDS-staged tube gather (CTREX_FP_GATHER=lds, read when the context
+    is created) walks the same samples with the same arithmetic as the direct
+    gather: bitwise equal forward projections, plain and in the SIRT modes,
+    and the oracle's at 1e-5; also on a ragged volume and detector."""
+    from paper_2609_30166_amd import Geometry
+
+    cfg, x, g, y_ref, _ = tiny
+    xt = torch.from_numpy(x).to(dev)
+    monkeypatch.setenv("CTREX_FP_GATHER", "lds")
+    gt = Geometry(cfg.P, cfg.n_u, cfg.n_v, cfg.shape, cfg.step, device=dev)
+    monkeypatch.delenv("CTREX_FP_GATHER")
+    y1 = g.forward(xt)
+    y2 = gt.forward(xt)
+    assert torch.equal(y1, y2)
+    assert rel_l2(y2.cpu().numpy(), y_ref) <= TOL
+    b = torch.from_numpy(y_ref.astype(np.float32)).to(dev) * 1.01
+    v1 = torch.zeros_like(xt)
+    v2 = torch.zeros_like(xt)
+    n1 = g.sirt(v1, b, 2)
+    n2 = gt.sirt(v2, b, 2)
+    assert torch.equal(v1, v2)
+    np.testing.assert_array_equal(np.asarray(n1), np.asarray(n2))
+    shape = (21, 26, 30)
+    P = synth.circular_cone(7, 37, 23, 60.0, 110.0, 0.9, arc=4.0, det_offset_u=1.3)
+    xr = np.random.default_rng(3).uniform(0, 1, shape).astype(np.float32)
+    monkeypatch.setenv("CTREX_FP_GATHER", "lds")
+    gr = Geometry(P, 37, 23, shape, 0.5, device=dev)
+    monkeypatch.delenv("CTREX_FP_GATHER")
+    yr = gr.forward(torch.from_numpy(xr).to(dev)).cpu().numpy()
+    assert rel_l2(yr, oracle.forward(P, shape, 37, 23, xr.astype(np.float64))) <= TOL
+
+
 def test_interior_bricks_match_oracle(dev):
     """A volume large enough that some 32 x 16 x 16 backprojection bricks
     touch no face (x0 >= 1 and x0 + e <= n - 2 on every axis): these walk
