@@ -196,21 +196,28 @@ __global__ __launch_bounds__(NT) void conv3_fwd_kernel(const u16 *__restrict__ i
 // gather through L1/L2 (every input voxel feeds 27 taps); weights come from
 // global memory (the same for every wave, so from the cache).  A wave owns
 // MBW consecutive y rows of one z plane, so every LDS offset but the lane's
-// base is a compile-time constant.
+// base is a compile-time constant.  More than 32 input channels are staged
+// and contracted 32 at a time (the tile keeps the 32-channel shape and LDS
+// size: 64 channels at once would need a 4 x 2 tile, three times as many
+// halo voxels per output, and half the workgroups per CU).  Occupancy hints:
+// 16 -> 16 runs 4 waves per SIMD in 128 registers; 32 or 64 inputs with at
+// most 32 outputs run 3 (the LDS tile admits three workgroups per CU); the
+// rest take what their accumulators leave (3 would spill 16 -> 32).
 template <int CIN> struct ConvTile;
 template <> struct ConvTile<16> { static constexpr int TY = 8, TZ = 4; };
 template <> struct ConvTile<32> { static constexpr int TY = 8, TZ = 2; };
-template <> struct ConvTile<64> { static constexpr int TY = 4, TZ = 2; };
+template <> struct ConvTile<64> { static constexpr int TY = 8, TZ = 2; };
 
 template <int CIN, int COUT, bool OUT_F32, bool RELU, bool ACC>
-__global__ __launch_bounds__(NT)
-__attribute__((amdgpu_waves_per_eu(CIN == 16 && COUT == 16 ? 4 : 1))) void conv3_tile_kernel(const u16 *__restrict__ in, int in_cs,
-                                                        int in_off, const u16 *__restrict__ wt,
-                                                        const float *__restrict__ bias, void *out,
-                                                        int out_cs, int out_off, int D, int H,
-                                                        int W, int out_vec) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
+    CIN == 16 ? (COUT == 16 ? 4 : 1) : (COUT <= 32 ? 3 : 1)))) void
+conv3_tile_kernel(const u16 *__restrict__ in, int in_cs, int in_off, const u16 *__restrict__ wt,
+                  const float *__restrict__ bias, void *out, int out_cs, int out_off, int D, int H,
+                  int W, int out_vec) {
     constexpr int TY = ConvTile<CIN>::TY, TZ = ConvTile<CIN>::TZ;
-    constexpr int SX = 18, SY = TY + 2, SZ = TZ + 2, NC = CIN / 8;
+    constexpr int CST = CIN < 32 ? CIN : 32;  // channels staged at a time
+    constexpr int NH = CIN / CST;             // staging passes
+    constexpr int SX = 18, SY = TY + 2, SZ = TZ + 2, NC = CST / 8;
     constexpr int NEL = SZ * SY * NC * SX;   // 16-byte elements
     constexpr int MBW = TY * TZ / (NT / 64);  // rows per wave
     constexpr int NB = COUT / 16;
@@ -223,23 +230,6 @@ __attribute__((amdgpu_waves_per_eu(CIN == 16 && COUT == 16 ? 4 : 1))) void conv3
     bi /= ntx;
     const int y0 = (bi % nty) * TY, z0 = (bi / nty) * TZ;
 
-    // ---- stage the input (channel chunk fastest in global memory)
-    for (int e = threadIdx.x; e < NEL; e += NT) {
-        const int c = e % NC;
-        int t = e / NC;
-        const int x = t % SX;
-        t /= SX;
-        const int y = t % SY, z = t / SY;
-        const int gx = x0 + x - 1, gy = y0 + y - 1, gz = z0 + z - 1;
-        bf16x8 v = zero8();
-        if (gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D) {
-            const long long q = (static_cast<long long>(gz) * H + gy) * W + gx;
-            v = load8(in + q * in_cs + in_off + 8 * c);
-        }
-        tile[((z * SY + y) * NC + c) * SX + x] = v;
-    }
-    __syncthreads();
-
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
     const int row0 = wave * MBW;                 // first row (y + TY z) of this wave
     const int ym0 = row0 % TY, zm = row0 / TY;
@@ -251,42 +241,84 @@ __attribute__((amdgpu_waves_per_eu(CIN == 16 && COUT == 16 ? 4 : 1))) void conv3
 #pragma unroll
         for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    // K steps: for 16 channels pairs of taps (lane groups 0, 1 take tap 2p,
-    // channel chunks 0, 1; groups 2, 3 tap 2p + 1; tap 27 is zero padding),
-    // otherwise one tap and 32 channels per step.  The fragments of step
-    // p + 1 are read while the MFMAs of step p run (two register sets; the
-    // scheduling barriers keep the compiler from moving the reads after them).
-    constexpr int KSTEPS = CIN == 16 ? 14 : 27 * (CIN / 32);
-    auto fetch = [&](int p, bf16x8 (&a)[MBW], bf16x8 (&b)[NB]) {
-        const int tap = CIN == 16 ? 2 * p + (g >> 1) : p / (CIN / 32);
-        const int c = CIN == 16 ? (g & 1) : 4 * (p % (CIN / 32)) + g;
-        const bool live = tap < 27;
-        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-        const int off = lbase + ((dz * SY + dy) * NC + c) * SX + dx;
+#pragma unroll 1
+    for (int h = 0; h < NH; ++h) {
+        if (h > 0) __syncthreads();   // every wave is done with the previous half
+        // ---- stage the input (channel chunk fastest in global memory).  Element
+        // e = (row (z, y)) ROWLEN + col, col = x NC + c; the thread stride NT moves
+        // col by NT % ROWLEN and the row by NT / ROWLEN, so (y, z, col) are
+        // stepped with adds and one wrap each instead of divisions.
+        {
+            constexpr int ROWLEN = SX * NC, DCOL = NT % ROWLEN, DROW = NT / ROWLEN;
+            static_assert(DROW < SY, "one y wrap per step");
+            int col = threadIdx.x % ROWLEN, row = threadIdx.x / ROWLEN;
+            int y = row % SY, z = row / SY;
+            for (int e = threadIdx.x; e < NEL; e += NT) {
+                const int c = col % NC, x = col / NC;   // NC is a power of 2
+                const int gx = x0 + x - 1, gy = y0 + y - 1, gz = z0 + z - 1;
+                bf16x8 v = zero8();
+                if (gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D) {
+                    const long long q = (static_cast<long long>(gz) * H + gy) * W + gx;
+                    v = load8(in + q * in_cs + in_off + h * CST + 8 * c);
+                }
+                tile[((z * SY + y) * NC + c) * SX + x] = v;
+                col += DCOL;
+                int dy = DROW;
+                if (col >= ROWLEN) {
+                    col -= ROWLEN;
+                    ++dy;
+                }
+                y += dy;
+                if (y >= SY) {
+                    y -= SY;
+                    ++z;
+                }
+            }
+        }
+        __syncthreads();
+
+        // K steps: for 16 channels pairs of taps (lane groups 0, 1 take tap 2p,
+        // channel chunks 0, 1; groups 2, 3 tap 2p + 1; tap 27 is zero padding),
+        // otherwise one tap and 32 channels per step.  The fragments of step
+        // p + 1 are read while the MFMAs of step p run (two register sets; the
+        // scheduling barriers keep the compiler from moving the reads after them).
+        constexpr int KSTEPS = CIN == 16 ? 14 : 27;
+        // this half's weights; the empty asm makes the pointer opaque, so
+        // the 27 per-tap addresses are formed inside the loop over halves
+        // instead of being hoisted out of it and held in registers
+        const u16 *wh = wt + h * CST;
+        if (NH > 1) asm volatile("" : "+v"(wh));
+        auto fetch = [&](int p, bf16x8 (&a)[MBW], bf16x8 (&b)[NB]) {
+            const int tap = CIN == 16 ? 2 * p + (g >> 1) : p;
+            const int c = CIN == 16 ? (g & 1) : g;
+            const bool live = tap < 27;
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const int off = lbase + ((dz * SY + dy) * NC + c) * SX + dx;
 #pragma unroll
-        for (int m = 0; m < MBW; ++m) a[m] = live ? tile[off + m * NC * SX] : zero8();
+            for (int m = 0; m < MBW; ++m) a[m] = live ? tile[off + m * NC * SX] : zero8();
 #pragma unroll
-        for (int n = 0; n < NB; ++n)
-            b[n] = live ? load8(wt + (tap * COUT + n * 16 + r) * CIN + 8 * c) : zero8();
-    };
-    auto step = [&](const bf16x8 (&a)[MBW], const bf16x8 (&b)[NB]) {
+            for (int n = 0; n < NB; ++n)
+                b[n] = live ? load8(wh + (tap * COUT + n * 16 + r) * CIN + 8 * c) : zero8();
+        };
+        auto step = [&](const bf16x8 (&a)[MBW], const bf16x8 (&b)[NB]) {
 #pragma unroll
-        for (int m = 0; m < MBW; ++m)
+            for (int m = 0; m < MBW; ++m)
 #pragma unroll
-            for (int n = 0; n < NB; ++n) acc[m][n] = mma(b[n], a[m], acc[m][n]);
-    };
-    bf16x8 a0[MBW], b0[NB], a1[MBW], b1[NB];
-    fetch(0, a0, b0);
+                for (int n = 0; n < NB; ++n) acc[m][n] = mma(b[n], a[m], acc[m][n]);
+        };
+        bf16x8 a0[MBW], b0[NB], a1[MBW], b1[NB];
+        fetch(0, a0, b0);
 #pragma unroll
-    for (int p = 0; p < KSTEPS; p += 2) {
-        if (p + 1 < KSTEPS) fetch(p + 1, a1, b1);
-        __builtin_amdgcn_sched_barrier(0);
-        step(a0, b0);
-        __builtin_amdgcn_sched_barrier(0);
-        if (p + 2 < KSTEPS) fetch(p + 2, a0, b0);
-        __builtin_amdgcn_sched_barrier(0);
-        if (p + 1 < KSTEPS) step(a1, b1);
-        __builtin_amdgcn_sched_barrier(0);
+        for (int p = 0; p < KSTEPS; p += 2) {
+            if (p + 1 < KSTEPS) fetch(p + 1, a1, b1);
+            __builtin_amdgcn_sched_barrier(0);
+            step(a0, b0);
+            __builtin_amdgcn_sched_barrier(0);
+            if (p + 2 < KSTEPS) fetch(p + 2, a0, b0);
+            __builtin_amdgcn_sched_barrier(0);
+            if (p + 1 < KSTEPS) step(a1, b1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
     // ---- epilogue.  The products were formed as weights x inputs, so lane
     // (g, r) holds output channels n 16 + 4 g + j (j < 4) of voxel r of each
