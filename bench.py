@@ -25,8 +25,11 @@ projector: position, corner indices and fractions, trilinear weights or
 blend, accumulation) x samples per launch / launch time, against 256 CUs x 4
 SIMDs x 32 lanes per clock x 2.4 GHz = 78.6e12 lane operations per second
 (the fp32 vector peak of 157.3 TFLOP/s counts an FMA as two).  The
-backprojector's 8 LDS 64-bit atomics per sample are also set against the LDS
-roof (128 bytes per clock per CU: 16 such lane operations).  HBM traffic and
+backprojector's 8 algorithmic LDS 64-bit atomics per sample (before the
+register merge of same-cell samples) are also set against the LDS roof (128
+bytes per clock per CU: 16 such lane operations); the issue counters of the
+committed summary give its measured LDS and VALU rates and the fraction of
+cycles lost to LDS bank conflicts, the kernel's actual limit.  HBM traffic and
 the L2 hit rate per kernel are read from the committed counter summary
 (rocprofv3 --pmc passes: FETCH_SIZE, WRITE_SIZE scaled by the same counters
 of a plain copy kernel of known size, ``--copy-calibrate``; TCC_HIT_sum and
@@ -36,6 +39,10 @@ voxel reads or accumulations) is reported beside it as the fraction of the
 achievable HBM bandwidth (a stream copy timed in the same run), the figure
 the 60% target is stated in.
 
+The ``unet`` object times the correction network alone (forward pass and one
+Adam training step on a 256^3 volume) with its FLOP rate against the BF16
+dense MFMA peak of 2.5 PFLOP/s.
+
 The ``voxel_bp`` object repeats the SIRT run with the paper's voxel-driven
 backprojector in place of the exact transpose (speed, and residual and PSNR
 after the same number of iterations); the ``cylinder`` object runs SIRT on the
@@ -44,6 +51,7 @@ same scan.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|bf16]
                        [--copy-calibrate] [--no-learned] [--no-voxel-bp] [--no-cylinder]
+                       [--no-bf16] [--no-helical] [--no-autograd] [--no-unet]
 """
 
 from __future__ import annotations
@@ -63,7 +71,8 @@ METRIC = "FP+BP Gsamples/s @512³×720 proj; time-to-PSNR learned vs plain SIRT"
 HBM_PEAK_GBS = 8000.0
 GATHER_BYTES = {"f32": 32, "bf16": 16}   # 8 voxel reads per sample
 # plain-ALU issue roof: 256 CUs x 4 SIMDs x 32 lanes per clock x 2.4 GHz
-ALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
+CLOCK_HZ = 2.4e9
+ALU_PEAK_TOPS = 256 * 4 * 32 * CLOCK_HZ / 1e12
 # LDS roof for 64-bit atomics: 128 bytes per clock per CU = 16 lane operations
 LDS_ATOMIC_PEAK_TOPS = 256 * 16 * 2.4e9 / 1e12
 # algorithmic VALU lane operations per sample (position 3 FMA; floor, convert
@@ -306,6 +315,63 @@ def time_to_psnr(dev):
                 "reaches_sirt_psnr": bool(lit["psnr_learned"] >= lit["psnr_sirt"])},
             "workload": "256^3, 180 projections of 384x384, Poisson I0=1e4, seeded held-out "
                         "phantom; inference only"}
+
+
+def unet_flops(n):
+    """Multiply-add FLOPs (2 per MAC) of one U-Net forward pass on an n^3
+    volume: 3x3x3 convolutions 54 cin cout per output voxel, 2x2x2 stride-2
+    up-sampling 2 cin cout per output voxel, the 16-channel head 32 per voxel."""
+    from paper_2609_30166_amd.unet import LAYERS
+
+    level = dict(e1a=1, e1b=1, e2a=2, e2b=2, bna=3, bnb=3, up2=2, d2a=2, d2b=2, up1=1,
+                 d1a=1, d1b=1)   # level of each layer's output
+    total = 32.0 * n ** 3
+    for name, kind, cin, cout in LAYERS:
+        vox = n ** 3 / 8 ** (level[name] - 1)
+        total += (54.0 if kind == "conv" else 2.0) * cin * cout * vox
+    return total
+
+
+def unet_run(dev, args, n=256, reps=5):
+    """The correction U-Net alone on a 256^3 volume (He-normal weights from a
+    seed, uniform synthetic input): forward pass and one training step
+    (forward, MSE, backward, Adam), mean of ``reps`` after one warm-up, timed
+    with HIP events on the library's launch stream."""
+    import torch
+
+    from paper_2609_30166_amd.unet import UNet
+
+    net = UNet(device=dev, seed=1)
+    gen = torch.Generator(device="cpu").manual_seed(3)
+    x = torch.rand((n, n, n), generator=gen).to(dev)
+    t = x + 0.01 * torch.rand((n, n, n), generator=gen).to(dev)
+    s = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = torch.empty_like(x)
+    fwd_ms = timed(lambda: net.forward(x, out=out))
+    step_ms = timed(lambda: net.train_step(x, t))
+    f = unet_flops(n)
+    peak = 2.5e15
+    del net, x, t, out
+    return {"workload": "U-Net 16/32/64 channels, 3 levels, BF16 activations, FP32 "
+                        "accumulation, %d^3 volume, batch 1" % n,
+            "forward_ms": fwd_ms, "train_step_ms": step_ms,
+            "forward_gflop": f / 1e9,
+            "forward_tflops": f / (fwd_ms * 1e-3) / 1e12,
+            "forward_frac_of_bf16_peak": f / (fwd_ms * 1e-3) / peak,
+            "train_step_tflops_est": 3.0 * f / (step_ms * 1e-3) / 1e12,
+            "note": "training step counted as 3x the forward FLOPs (data and weight "
+                    "gradients); per-kernel rates are in the committed kernel trace"}
 
 
 def bf16_run(g, xt, b32, vol32, y_or, views, args):
@@ -570,6 +636,8 @@ def main():
                     help="skip the helical / sub-view / warp configuration")
     ap.add_argument("--no-autograd", action="store_true",
                     help="skip the differentiable-loss configuration")
+    ap.add_argument("--no-unet", action="store_true",
+                    help="skip the U-Net forward / training-step timing")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -638,6 +706,16 @@ def main():
             lds = 8 * n_s / (ms * 1e-3) / 1e12
             row["lds_atomic_tops"] = lds
             row["lds_atomic_frac"] = lds / LDS_ATOMIC_PEAK_TOPS
+        rec = counter_record(name, args.dtype)
+        if rec is not None and "sq_insts_valu" in rec:
+            # issue counters per launch (summed over the chip) against this
+            # run's launch time: VALU wave-instructions per CU per clock, LDS
+            # wave-instructions per CU per clock, bank-conflict cycles as a
+            # fraction of every CU's cycles
+            cu_clk = 256 * ms * 1e-3 * CLOCK_HZ
+            row["counters"] = {"valu_per_cu_clock": rec["sq_insts_valu"] / cu_clk,
+                               "lds_per_cu_clock": rec["sq_insts_lds"] / cu_clk,
+                               "lds_bank_conflict_frac": rec["sq_lds_bank_conflict"] / cu_clk}
         return row
 
     kernels = {"fp_kernel": kernel_row("fp_kernel", fp_ms),
@@ -678,6 +756,7 @@ def main():
                      "(fp32 vector 157.3 TFLOP/s counting an FMA as 2)" % (ALU_OPS[dom], n_s),
             "l2_hit_rate": d["l2_hit_rate"],
             "hbm_GBps": d["hbm_GBps"],
+            "counters": d.get("counters"),
         },
         "kernels": kernels,
         "gather_equivalent": {
@@ -722,6 +801,10 @@ def main():
     if not args.no_autograd:
         _log("differentiable loss ...")
         out["autograd"] = autograd_run(dev, args)
+        torch.cuda.empty_cache()
+    if not args.no_unet:
+        _log("U-Net forward and training step ...")
+        out["unet"] = unet_run(dev, args)
         torch.cuda.empty_cache()
     if not args.no_learned:
         _log("learned pipeline vs SIRT-50 ...")
