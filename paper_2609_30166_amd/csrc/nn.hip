@@ -370,56 +370,8 @@ conv3_tile_kernel(const u16 *__restrict__ in, int in_cs, int in_off, const u16 *
     }
 }
 
-// Weight gradient, cin >= 16: wave = one tap; block = (voxel chunk, 4 taps).
-template <int CIN, int COUT>
-__global__ __launch_bounds__(NT) void conv3_wgrad_kernel(const u16 *__restrict__ in, int in_cs,
-                                                         int in_off, const u16 *__restrict__ dout,
-                                                         int dout_cs, int dout_off, int D, int H,
-                                                         int W, long long chunk,
-                                                         float *__restrict__ partial) {
-    constexpr int MBk = COUT / 16, NBk = CIN / 16;
-    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
-    const int tap = blockIdx.y * (NT / 64) + (threadIdx.x >> 6);
-    if (tap >= 27) return;
-    const long long nvox = static_cast<long long>(D) * H * W;
-    const long long v0 = static_cast<long long>(blockIdx.x) * chunk;
-    const long long v1 = v0 + chunk < nvox ? v0 + chunk : nvox;
-    f32x4 acc[MBk][NBk];
-#pragma unroll
-    for (int m = 0; m < MBk; ++m)
-#pragma unroll
-        for (int n = 0; n < NBk; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (long long vk = v0; vk < v1; vk += 32) {
-        bf16x8 a[MBk], b[NBk];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const long long v = vk + 8 * g + e;
-            const bool ok = v < v1;
-            const long long q = ok ? nbr(decode(v, H, W), tap, D, H, W) : -1;
-#pragma unroll
-            for (int m = 0; m < MBk; ++m)
-                a[m][e] = ok ? as_bf(dout[v * dout_cs + dout_off + m * 16 + r])
-                             : static_cast<__bf16>(0.0f);
-#pragma unroll
-            for (int n = 0; n < NBk; ++n)
-                b[n][e] = q >= 0 ? as_bf(in[q * in_cs + in_off + n * 16 + r])
-                                 : static_cast<__bf16>(0.0f);
-        }
-#pragma unroll
-        for (int m = 0; m < MBk; ++m)
-#pragma unroll
-            for (int n = 0; n < NBk; ++n) acc[m][n] = mma(a[m], b[n], acc[m][n]);
-    }
-    float *dst = partial + (static_cast<long long>(blockIdx.x) * 27 + tap) * COUT * CIN;
-#pragma unroll
-    for (int m = 0; m < MBk; ++m)
-#pragma unroll
-        for (int n = 0; n < NBk; ++n)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) dst[(m * 16 + 4 * g + j) * CIN + n * 16 + r] = acc[m][n][j];
-}
-
-// Weight gradient for cin, cout in {16, 32} as LDS-tiled GEMMs:
+// Weight gradient for cin, cout in {16, 32} as LDS-tiled GEMMs (wider layers
+// run it per 32-channel block):
 // dw[tap][co][ci] = sum_v dout[v][co] in[v + tap][ci], M = cout, N = cin,
 // K = 32 voxels of one x row.  A unit is a 32 (x) x 4 (y) column of voxels
 // over a run of z planes.  The workgroup stages, per plane, the output
@@ -624,14 +576,18 @@ __global__ __launch_bounds__(64) void conv3_wgrad_c1_kernel(const u16 *__restric
 }
 
 // dw[co][ci][tap] = sum over chunks of partial[c][tap][co][ci] (FP64, fixed order).
+// The partials hold a (cout_b x cin_b) block of the gradient, output
+// channels co0 + [0, cout_b), input channels ci0 + [0, cin_b), of a layer
+// with cout x cin channels.
 __global__ __launch_bounds__(NT) void reduce_wgrad_kernel(const float *__restrict__ partial,
-                                                          int chunks, int taps, int cout, int cin,
-                                                          int tap_major_out,
+                                                          int chunks, int taps, int cout_b,
+                                                          int cin_b, int co0, int ci0, int cout,
+                                                          int cin, int tap_major_out,
                                                           float *__restrict__ dw) {
     // 32 outputs per block, 8 slices of the chunks each (slice k sums chunks
     // k, k + 8, ...), slices then added in order: a fixed order in FP64
     __shared__ double red[NT / 32][32];
-    const int n = taps * cout * cin;
+    const int n = taps * cout_b * cin_b;
     const int o = threadIdx.x & 31, sl = threadIdx.x >> 5;
     const int i = blockIdx.x * 32 + o;   // the partial's [tap][co][ci] order
     double sum = 0.0;
@@ -643,9 +599,9 @@ __global__ __launch_bounds__(NT) void reduce_wgrad_kernel(const float *__restric
     if (sl != 0 || i >= n) return;
     double t = 0.0;
     for (int k = 0; k < NT / 32; ++k) t += red[k][o];
-    const int tap = i / (cout * cin);
-    const int rem = i - tap * cout * cin;
-    const int co = rem / cin, ci = rem - co * cin;
+    const int tap = i / (cout_b * cin_b);
+    const int rem = i - tap * cout_b * cin_b;
+    const int co = co0 + rem / cin_b, ci = ci0 + rem % cin_b;
     // conv3: master order [co][ci][tap]; upconv: [ci][co][tap]
     const int ox = tap_major_out ? (ci * cout + co) * taps + tap : (co * cin + ci) * taps + tap;
     dw[ox] = static_cast<float>(t);
@@ -903,6 +859,29 @@ __global__ __launch_bounds__(NT) void relu_bwd_kernel(const u16 *__restrict__ y,
     if (!(bf2f(y[idx]) > 0.0f)) gr[idx] = 0;
 }
 
+// The same, 8 channels (16 bytes) per thread: channel slices at strides and
+// offsets that are multiples of 8 (every U-Net activation).
+__global__ __launch_bounds__(NT) void relu_bwd8_kernel(const u16 *__restrict__ y, u16 *__restrict__ gr,
+                                                       int cs, int off, int c8, long long n8) {
+    const long long i = static_cast<long long>(blockIdx.x) * NT + threadIdx.x;
+    if (i >= n8) return;
+    const long long v = i / c8;
+    const long long idx = v * cs + off + 8 * (i - v * c8);
+    const uint4 a = *reinterpret_cast<const uint4 *>(y + idx);
+    uint4 *gp = reinterpret_cast<uint4 *>(gr + idx);
+    uint4 q = *gp;
+    // a BF16 value h is > 0 when its sign bit is clear and its magnitude bits
+    // lie in (0, 0x7f80] (+0 and NaN are not; +inf is), as in the scalar form
+    auto pos = [](uint32_t h) { return (h & 0x8000u) == 0 && h != 0 && h <= 0x7f80u; };
+    auto keep = [&](uint32_t w, uint32_t g) {
+        const uint32_t lo = pos(w & 0xffffu) ? 0xffffu : 0u;
+        const uint32_t hi = pos(w >> 16) ? 0xffff0000u : 0u;
+        return g & (lo | hi);
+    };
+    q = make_uint4(keep(a.x, q.x), keep(a.y, q.y), keep(a.z, q.z), keep(a.w, q.w));
+    *gp = q;
+}
+
 // out = x + m scale (b + sum_k h_k act_k), m = mask[v] (1 without a mask)
 __global__ __launch_bounds__(NT) void head_kernel(const u16 *__restrict__ act, int c,
                                                   const float *__restrict__ h, const float *__restrict__ b,
@@ -1108,54 +1087,55 @@ hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin, co
     const long long chunk = wgrad_chunk(nvox);
     const int chunks = static_cast<int>((nvox + chunk - 1) / chunk);
     const u16 *ip = static_cast<const u16 *>(in), *dp = static_cast<const u16 *>(dout);
-    bool done = false;
-    int parts = chunks;   // partial sums written to scratch
-    if ((cin == 16 || cin == 32) && (cout == 16 || cout == 32)) {
-        // units: 32 x 4 voxel columns over runs of z planes, at most `chunks`
-        // workgroups (each loops over its units), so the scratch is the same
-        const long long tiles = static_cast<long long>((W + WG_X - 1) / WG_X) * ((H + WG_Y - 1) / WG_Y);
-        long long zsegs = chunks / tiles;
-        if (zsegs < 1) zsegs = 1;
-        if (zsegs > D) zsegs = D;
-        const int zseg = static_cast<int>((D + zsegs - 1) / zsegs);
-        const long long units = tiles * ((D + zseg - 1) / zseg);
-        parts = static_cast<int>(units < chunks ? units : chunks);
-#define CTREX_NN_WGT(CI, CO)                                                                      \
-        if (cin == CI && cout == CO)                                                              \
-            hipLaunchKernelGGL((wgrad_tile_kernel<CI, CO>), dim3(parts), dim3(WG_THREADS), 0, s, ip, \
-                               in_cs, in_off, dp, dout_cs, dout_off, D, H, W, zseg,               \
-                               static_cast<int>(units), scratch);
-        CTREX_NN_WGT(16, 16)
-        CTREX_NN_WGT(16, 32)
-        CTREX_NN_WGT(32, 16)
-        CTREX_NN_WGT(32, 32)
-#undef CTREX_NN_WGT
-        done = true;
-    }
     if (cin == 1) {
-        if (cout == 16) {
-            hipLaunchKernelGGL((conv3_wgrad_c1_kernel<16>), dim3(chunks), dim3(64), 0, s, ip, in_cs,
-                               in_off, dp, dout_cs, dout_off, D, H, W, chunk, scratch);
-            done = true;
+        if (cout != 16) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((conv3_wgrad_c1_kernel<16>), dim3(chunks), dim3(64), 0, s, ip, in_cs,
+                           in_off, dp, dout_cs, dout_off, D, H, W, chunk, scratch);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int n = 27 * cout;
+        hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(n, 32)), dim3(NT), 0, s, scratch,
+                           chunks, 27, cout, 1, 0, 0, cout, 1, 0, dw);
+        return hipGetLastError();
+    }
+    if ((cin != 16 && cin != 32 && cin != 64) || (cout != 16 && cout != 32 && cout != 64))
+        return hipErrorInvalidValue;
+    // Units: 32 x 4 voxel columns over runs of z planes, at most `chunks`
+    // workgroups (each loops over its units).  64 channels are split into
+    // 32-channel blocks, each a tiled GEMM of its own writing its partials
+    // after the previous block's; the scratch (chunks x 27 x cin x cout
+    // floats) holds them all.
+    const long long tiles = static_cast<long long>((W + WG_X - 1) / WG_X) * ((H + WG_Y - 1) / WG_Y);
+    long long zsegs = chunks / tiles;
+    if (zsegs < 1) zsegs = 1;
+    if (zsegs > D) zsegs = D;
+    const int zseg = static_cast<int>((D + zsegs - 1) / zsegs);
+    const long long units = tiles * ((D + zseg - 1) / zseg);
+    const int parts = static_cast<int>(units < chunks ? units : chunks);
+    const int cib = cin < 32 ? cin : 32, cob = cout < 32 ? cout : 32;
+    float *part = scratch;
+    for (int co0 = 0; co0 < cout; co0 += cob)
+        for (int ci0 = 0; ci0 < cin; ci0 += cib) {
+#define CTREX_NN_WGT(CI, CO)                                                                      \
+            if (cib == CI && cob == CO)                                                           \
+                hipLaunchKernelGGL((wgrad_tile_kernel<CI, CO>), dim3(parts), dim3(WG_THREADS), 0, \
+                                   s, ip, in_cs, in_off + ci0, dp, dout_cs, dout_off + co0, D, H, \
+                                   W, zseg, static_cast<int>(units), part);
+            CTREX_NN_WGT(16, 16)
+            CTREX_NN_WGT(16, 32)
+            CTREX_NN_WGT(32, 16)
+            CTREX_NN_WGT(32, 32)
+#undef CTREX_NN_WGT
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            const int n = 27 * cob * cib;
+            hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(n, 32)), dim3(NT), 0, s, part,
+                               parts, 27, cob, cib, co0, ci0, cout, cin, 0, dw);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            part += static_cast<long long>(parts) * n;
         }
-    }
-#define CTREX_NN_WG(CI, CO)                                                                         \
-    if (!done && cin == CI && cout == CO) {                                                          \
-        hipLaunchKernelGGL((conv3_wgrad_kernel<CI, CO>), dim3(chunks, 7), dim3(NT), 0, s, ip, in_cs, \
-                           in_off, dp, dout_cs, dout_off, D, H, W, chunk, scratch);                  \
-        done = true;                                                                                 \
-    }
-    CTREX_NN_WG(32, 64)
-    CTREX_NN_WG(64, 32)
-    CTREX_NN_WG(64, 64)
-#undef CTREX_NN_WG
-    if (!done) return hipErrorInvalidValue;
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int n = 27 * cout * cin;
-    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(n, 32)), dim3(NT), 0, s, scratch, parts, 27,
-                       cout, cin, 0, dw);
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 size_t channel_sum_scratch(int c) { return sizeof(double) * 1024 * static_cast<size_t>(c); }
@@ -1248,7 +1228,7 @@ hipError_t launch_upconv2_wgrad(const void *in, int in_cs, int in_off, int cin, 
     if (e != hipSuccess) return e;
     const int n = 8 * cout * cin;
     hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(n, 32)), dim3(NT), 0, s, scratch, chunks, 8,
-                       cout, cin, 1, dw);
+                       cout, cin, 0, 0, cout, cin, 1, dw);
     return hipGetLastError();
 }
 
@@ -1271,6 +1251,14 @@ hipError_t launch_maxpool2_bwd(const void *in, int in_cs, int in_off, int c, con
 
 hipError_t launch_relu_bwd(const void *y, void *g, int cs, int off, int c, long long nvox,
                            hipStream_t s) {
+    const bool vec = cs % 8 == 0 && off % 8 == 0 && c % 8 == 0 &&
+                     (reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(g)) % 16 == 0;
+    if (vec) {
+        const long long n8 = nvox * (c / 8);
+        hipLaunchKernelGGL(relu_bwd8_kernel, dim3(blocks_for(n8)), dim3(NT), 0, s,
+                           static_cast<const u16 *>(y), static_cast<u16 *>(g), cs, off, c / 8, n8);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(relu_bwd_kernel, dim3(blocks_for(nvox * c)), dim3(NT), 0, s,
                        static_cast<const u16 *>(y), static_cast<u16 *>(g), cs, off, c, nvox);
     return hipGetLastError();

@@ -211,19 +211,24 @@ def test_conv3_weight_gradient(L, ctx, shape, cin, cout):
     _close(_host(db), b.grad.numpy())
 
 
-def test_conv3_weight_gradient_on_slices(L, ctx):
+@pytest.mark.parametrize("cin,cout,xs,xo,gs,go", [(32, 16, 64, 32, 32, 16),
+                                                   (64, 32, 96, 32, 64, 32),
+                                                   (64, 64, 72, 8, 80, 16)])
+def test_conv3_weight_gradient_on_slices(L, ctx, cin, cout, xs, xo, gs, go):
+    """Channel slices of wider tensors (64-channel layers run per 32-channel
+    block, each at its own offset into the slice)."""
     from oracle import unet as ou
-    shape, cin, cout = (8, 8, 8), 32, 16
+    shape = (8, 8, 8)
     n = 512
     r = _rng(5)
-    xw = _bf(r.normal(size=(n, 64)))
-    gw = _bf(r.normal(size=(n, 32)))
-    x, g = xw[:, 32:64].reshape(shape + (cin,)), gw[:, 16:32].reshape(shape + (cout,))
+    xw = _bf(r.normal(size=(n, xs)))
+    gw = _bf(r.normal(size=(n, gs)))
+    x, g = xw[:, xo:xo + cin].reshape(shape + (cin,)), gw[:, go:go + cout].reshape(shape + (cout,))
     w = torch.zeros((cout, cin, 27), dtype=torch.float64, requires_grad=True)
     (ou.conv3(torch.tensor(x), w) * torch.tensor(g)).sum().backward()
     xd, gd = _dev_bf(xw), _dev_bf(gw)
     dw = torch.empty(cout * cin * 27, dtype=torch.float32, device=DEV)
-    _call(L, ctx, "ctrex_nn_conv3_wgrad", _vp(xd), 64, 32, cin, _vp(gd), 32, 16, cout, *shape,
+    _call(L, ctx, "ctrex_nn_conv3_wgrad", _vp(xd), xs, xo, cin, _vp(gd), gs, go, cout, *shape,
           _vp(dw), None, None)
     _close(_host(dw).reshape(cout, cin, 27), w.grad.numpy())
 
@@ -328,16 +333,26 @@ def test_maxpool_and_backward_bit_exact(L, ctx):
     assert np.all(got[:, :off] == 0) and np.all(got[:, off + c:] == 0)
 
 
-def test_relu_backward_bit_exact(L, ctx):
-    n, cs, off, c = 960, 48, 16, 32
+@pytest.mark.parametrize("cs,off,c", [(48, 16, 32), (20, 3, 12)])
+def test_relu_backward_bit_exact(L, ctx, cs, off, c):
+    """g is zeroed wherever y > 0 fails (8-channel vector form for aligned
+    slices, element form otherwise); special values included: +-0, +-inf,
+    NaN, subnormals."""
+    n = 960
     r = _rng(9)
-    y = _bf(np.maximum(r.normal(size=(n, cs)), 0))
+    y = np.maximum(r.normal(size=(n, cs)), 0)
+    y[r.random(size=y.shape) < 0.2] *= -1.0
+    flat = y.reshape(-1)
+    for k, v in enumerate([-0.0, 0.0, np.inf, -np.inf, np.nan, 1e-39, -1e-39]):
+        flat[k * 37 + 5::997] = v
+    y = _bf(y)
     g = _bf(r.normal(size=(n, cs)))
     yd, gd = _dev_bf(y), _dev_bf(g)
     _call(L, ctx, "ctrex_nn_relu_backward", _vp(yd), _vp(gd), cs, off, c, n, None)
     ref = g.copy()
     sl = ref[:, off:off + c]
-    sl[y[:, off:off + c] <= 0] = 0
+    with np.errstate(invalid="ignore"):
+        sl[~(y[:, off:off + c] > 0)] = 0
     np.testing.assert_array_equal(_host(gd), ref)
 
 
