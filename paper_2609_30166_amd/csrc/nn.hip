@@ -95,96 +95,88 @@ __device__ __forceinline__ void store_out(void *out, long long idx, float val) {
     }
 }
 
+// Four consecutive channels of one voxel (lane layout of an MFMA product
+// formed as weights x inputs): bias added by the caller, then ReLU, rounding
+// and one 8-byte (BF16) or 16-byte (FP32) store; `vec` false (a channel slice
+// at a stride or offset not a multiple of 4) stores element by element.
+template <bool OUT_F32, bool RELU, bool ACC>
+__device__ __forceinline__ void store4(void *out, long long o, float (&v)[4], bool vec) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (RELU) v[j] = fmaxf(v[j], 0.0f);
+    if (!vec) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) store_out<OUT_F32, false, ACC>(out, o + j, v[j]);
+    } else if (OUT_F32) {
+        float4 *q = reinterpret_cast<float4 *>(static_cast<float *>(out) + o);
+        float4 w = make_float4(v[0], v[1], v[2], v[3]);
+        if (ACC) {
+            const float4 p = *q;
+            w = make_float4(p.x + v[0], p.y + v[1], p.z + v[2], p.w + v[3]);
+        }
+        *q = w;
+    } else {
+        uint2 *q = reinterpret_cast<uint2 *>(static_cast<u16 *>(out) + o);
+        if (ACC) {
+            const uint2 p = *q;
+            v[0] += __uint_as_float(p.x << 16);
+            v[1] += __uint_as_float(p.x & 0xffff0000u);
+            v[2] += __uint_as_float(p.y << 16);
+            v[3] += __uint_as_float(p.y & 0xffff0000u);
+        }
+        *q = make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
+    }
+}
+
 // ------------------------------------------------------------ conv 3x3x3 ----
-template <int CIN, int COUT, bool OUT_F32, bool RELU, bool ACC>
-__global__ __launch_bounds__(NT) void conv3_fwd_kernel(const u16 *__restrict__ in, int in_cs,
-                                                       int in_off, const u16 *__restrict__ wt,
-                                                       const float *__restrict__ bias, void *out,
-                                                       int out_cs, int out_off, int D, int H, int W) {
+// One input channel: K = the 27 taps (padded to 32) of one voxel, one K step.
+// A wave takes 64 consecutive voxels; the products are formed as weights x
+// inputs, so lane (g, r) ends with output channels n 16 + 4 g + j (j < 4) of
+// voxel m 16 + r, stored four at a time.
+template <int COUT, bool OUT_F32, bool RELU, bool ACC>
+__global__ __launch_bounds__(NT) void conv3_c1_kernel(const u16 *__restrict__ in, int in_cs,
+                                                      int in_off, const u16 *__restrict__ wt,
+                                                      const float *__restrict__ bias, void *out,
+                                                      int out_cs, int out_off, int D, int H, int W,
+                                                      int out_vec) {
     constexpr int NB = COUT / 16;
     const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
     const long long nvox = static_cast<long long>(D) * H * W;
     const long long base = (static_cast<long long>(blockIdx.x) * (NT / 64) + (threadIdx.x >> 6)) * 64;
-    if (base >= nvox) return;   // whole wave
+    if (base >= nvox) return;   // whole wave (the voxel count is a multiple of 64)
     Vox pa[MB];
 #pragma unroll
     for (int m = 0; m < MB; ++m) pa[m] = decode(base + m * 16 + r, H, W);
-    f32x4 acc[MB][NB];
+    // k = 8 g + e is the tap
+    bf16x8 a[MB], b[NB];
 #pragma unroll
-    for (int m = 0; m < MB; ++m)
+    for (int e = 0; e < 8; ++e) {
+        const int tap = 8 * g + e;
 #pragma unroll
-        for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-
-    if constexpr (CIN == 1) {
-        // one K step: k = 8 g + e is the tap
-        bf16x8 a[MB], b[NB];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int tap = 8 * g + e;
-#pragma unroll
-            for (int m = 0; m < MB; ++m) {
-                const long long q = tap < 27 ? nbr(pa[m], tap, D, H, W) : -1;
-                a[m][e] = q >= 0 ? as_bf(in[q * in_cs + in_off]) : static_cast<__bf16>(0.0f);
-            }
-#pragma unroll
-            for (int n = 0; n < NB; ++n)
-                b[n][e] = tap < 27 ? as_bf(wt[tap * COUT + n * 16 + r]) : static_cast<__bf16>(0.0f);
+        for (int m = 0; m < MB; ++m) {
+            const long long q = tap < 27 ? nbr(pa[m], tap, D, H, W) : -1;
+            a[m][e] = q >= 0 ? as_bf(in[q * in_cs + in_off]) : static_cast<__bf16>(0.0f);
         }
 #pragma unroll
-        for (int m = 0; m < MB; ++m)
-#pragma unroll
-            for (int n = 0; n < NB; ++n) acc[m][n] = mma(a[m], b[n], acc[m][n]);
-    } else if constexpr (CIN == 16) {
-        // K steps over pairs of taps: lanes g = 0, 1 take tap 2p, g = 2, 3 tap 2p + 1
-        for (int p = 0; p < 14; ++p) {
-            const int tap = 2 * p + (g >> 1);
-            const int ch = 8 * (g & 1);
-            bf16x8 a[MB], b[NB];
-#pragma unroll
-            for (int m = 0; m < MB; ++m) {
-                const long long q = tap < 27 ? nbr(pa[m], tap, D, H, W) : -1;
-                a[m] = q >= 0 ? load8(in + q * in_cs + in_off + ch) : zero8();
-            }
-#pragma unroll
-            for (int n = 0; n < NB; ++n)
-                b[n] = tap < 27 ? load8(wt + (tap * COUT + n * 16 + r) * CIN + ch) : zero8();
-#pragma unroll
-            for (int m = 0; m < MB; ++m)
-#pragma unroll
-                for (int n = 0; n < NB; ++n) acc[m][n] = mma(a[m], b[n], acc[m][n]);
-        }
-    } else {
-        for (int tap = 0; tap < 27; ++tap) {
-            long long q[MB];
-#pragma unroll
-            for (int m = 0; m < MB; ++m) q[m] = nbr(pa[m], tap, D, H, W);
-#pragma unroll
-            for (int ks = 0; ks < CIN / 32; ++ks) {
-                const int ch = ks * 32 + 8 * g;
-                bf16x8 a[MB], b[NB];
-#pragma unroll
-                for (int m = 0; m < MB; ++m)
-                    a[m] = q[m] >= 0 ? load8(in + q[m] * in_cs + in_off + ch) : zero8();
-#pragma unroll
-                for (int n = 0; n < NB; ++n) b[n] = load8(wt + (tap * COUT + n * 16 + r) * CIN + ch);
-#pragma unroll
-                for (int m = 0; m < MB; ++m)
-#pragma unroll
-                    for (int n = 0; n < NB; ++n) acc[m][n] = mma(a[m], b[n], acc[m][n]);
-            }
-        }
+        for (int n = 0; n < NB; ++n)
+            b[n][e] = tap < 27 ? as_bf(wt[tap * COUT + n * 16 + r]) : static_cast<__bf16>(0.0f);
     }
+    const f32x4 zero = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int n = 0; n < NB; ++n) {
-        const int co = n * 16 + r;
-        const float bco = bias ? bias[co] : 0.0f;
+        const int co0 = n * 16 + 4 * g;
+        float bco[4];
 #pragma unroll
-        for (int m = 0; m < MB; ++m)
+        for (int j = 0; j < 4; ++j) bco[j] = bias ? bias[co0 + j] : 0.0f;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const long long v = base + m * 16 + 4 * g + j;
-                store_out<OUT_F32, RELU, ACC>(out, v * out_cs + out_off + co, acc[m][n][j] + bco);
-            }
+        for (int m = 0; m < MB; ++m) {
+            const f32x4 acc = mma(b[n], a[m], zero);
+            float v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = acc[j] + bco[j];
+            store4<OUT_F32, RELU, ACC>(out, (base + m * 16 + r) * out_cs + out_off + co0, v,
+                                       out_vec != 0);
+        }
     }
 }
 
@@ -340,32 +332,8 @@ conv3_tile_kernel(const u16 *__restrict__ in, int in_cs, int in_off, const u16 *
             const long long o = ((static_cast<long long>(gz) * H + gy) * W + gx) * out_cs + out_off + co0;
             float v[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                v[j] = acc[m][n][j] + bco[j];
-                if (RELU) v[j] = fmaxf(v[j], 0.0f);
-            }
-            if (!out_vec) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) store_out<OUT_F32, false, ACC>(out, o + j, v[j]);
-            } else if (OUT_F32) {
-                float4 *q = reinterpret_cast<float4 *>(static_cast<float *>(out) + o);
-                float4 w = make_float4(v[0], v[1], v[2], v[3]);
-                if (ACC) {
-                    const float4 p = *q;
-                    w = make_float4(p.x + v[0], p.y + v[1], p.z + v[2], p.w + v[3]);
-                }
-                *q = w;
-            } else {
-                uint2 *q = reinterpret_cast<uint2 *>(static_cast<u16 *>(out) + o);
-                if (ACC) {
-                    const uint2 p = *q;
-                    v[0] += __uint_as_float(p.x << 16);
-                    v[1] += __uint_as_float(p.x & 0xffff0000u);
-                    v[2] += __uint_as_float(p.y << 16);
-                    v[3] += __uint_as_float(p.y & 0xffff0000u);
-                }
-                *q = make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
-            }
+            for (int j = 0; j < 4; ++j) v[j] = acc[m][n][j] + bco[j];
+            store4<OUT_F32, RELU, ACC>(out, o, v, out_vec != 0);
         }
     }
 }
@@ -656,52 +624,57 @@ __global__ __launch_bounds__(NT) void reduce_rows_kernel(const double *__restric
 }
 
 // ------------------------------------------------------ 2x transposed conv --
+// out[2i + a][co] = bias[co] + sum_ci in[i][ci] wt[a][co][ci] for the 8
+// sub-positions a.  A wave takes 64 consecutive input voxels, reads their
+// channels once, and for each sub-position forms the products as weights x
+// inputs, so lane (g, r) holds output channels n 16 + 4 g + j of input voxel
+// m 16 + r's child a, stored four at a time.
 template <int CIN, int COUT, bool OUT_F32, bool ACC>
 __global__ __launch_bounds__(NT) void upconv2_fwd_kernel(const u16 *__restrict__ in, int in_cs,
                                                          int in_off, const u16 *__restrict__ wt,
                                                          const float *__restrict__ bias, void *out,
                                                          int out_cs, int out_off, int D, int H,
-                                                         int W) {
-    constexpr int NB = COUT / 16;
+                                                         int W, int out_vec) {
+    constexpr int NB = COUT / 16, KS = CIN / 32;
     const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
     const long long nvox = static_cast<long long>(D) * H * W;
     const long long base = (static_cast<long long>(blockIdx.x) * (NT / 64) + (threadIdx.x >> 6)) * 64;
     if (base >= nvox) return;
     const int H2 = 2 * H, W2 = 2 * W;
+    bf16x8 av[KS][MB];
+    long long child0[MB];   // output index of child (0, 0, 0) of voxel m 16 + r
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+        const Vox p = decode(base + m * 16 + r, H, W);
+        child0[m] = ((static_cast<long long>(2 * p.z) * H2) + 2 * p.y) * W2 + 2 * p.x;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            av[ks][m] = load8(in + (base + m * 16 + r) * in_cs + in_off + ks * 32 + 8 * g);
+    }
+    const f32x4 zero = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     for (int a = 0; a < 8; ++a) {
-        f32x4 acc[MB][NB];
-#pragma unroll
-        for (int m = 0; m < MB; ++m)
-#pragma unroll
-            for (int n = 0; n < NB; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int ks = 0; ks < CIN / 32; ++ks) {
-            const int ch = ks * 32 + 8 * g;
-            bf16x8 av[MB], bv[NB];
-#pragma unroll
-            for (int m = 0; m < MB; ++m) av[m] = load8(in + (base + m * 16 + r) * in_cs + in_off + ch);
-#pragma unroll
-            for (int n = 0; n < NB; ++n) bv[n] = load8(wt + (a * COUT + n * 16 + r) * CIN + ch);
-#pragma unroll
-            for (int m = 0; m < MB; ++m)
-#pragma unroll
-                for (int n = 0; n < NB; ++n) acc[m][n] = mma(av[m], bv[n], acc[m][n]);
-        }
-        const int az = a >> 2, ay = (a >> 1) & 1, ax = a & 1;
+        const long long da = ((static_cast<long long>(a >> 2) * H2) + ((a >> 1) & 1)) * W2 + (a & 1);
 #pragma unroll
         for (int n = 0; n < NB; ++n) {
-            const int co = n * 16 + r;
-            const float bco = bias ? bias[co] : 0.0f;
+            bf16x8 bv[KS];
 #pragma unroll
-            for (int m = 0; m < MB; ++m)
+            for (int ks = 0; ks < KS; ++ks)
+                bv[ks] = load8(wt + (a * COUT + n * 16 + r) * CIN + ks * 32 + 8 * g);
+            const int co0 = n * 16 + 4 * g;
+            float bco[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const Vox p = decode(base + m * 16 + 4 * g + j, H, W);
-                    const long long o =
-                        ((static_cast<long long>(2 * p.z + az) * H2) + (2 * p.y + ay)) * W2 +
-                        (2 * p.x + ax);
-                    store_out<OUT_F32, false, ACC>(out, o * out_cs + out_off + co, acc[m][n][j] + bco);
-                }
+            for (int j = 0; j < 4; ++j) bco[j] = bias ? bias[co0 + j] : 0.0f;
+#pragma unroll
+            for (int m = 0; m < MB; ++m) {
+                f32x4 acc = zero;
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) acc = mma(bv[ks], av[ks][m], acc);
+                float v[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[j] = acc[j] + bco[j];
+                store4<OUT_F32, false, ACC>(out, (child0[m] + da) * out_cs + out_off + co0, v,
+                                            out_vec != 0);
+            }
         }
     }
 }
@@ -896,6 +869,33 @@ __global__ __launch_bounds__(NT) void head_kernel(const u16 *__restrict__ act, i
     out[v] = fmaf(sc, s, x[v]);
 }
 
+// The same for C channels (a multiple of 8) read 8 at a time, same order of
+// operations (so the same result).
+template <int C>
+__global__ __launch_bounds__(NT) void head_vec_kernel(const u16 *__restrict__ act,
+                                                      const float *__restrict__ h,
+                                                      const float *__restrict__ b,
+                                                      const float *__restrict__ x, float scale,
+                                                      const float *__restrict__ mask,
+                                                      float *__restrict__ out, long long n) {
+    const long long v = static_cast<long long>(blockIdx.x) * NT + threadIdx.x;
+    if (v >= n) return;
+    const uint4 *ap = reinterpret_cast<const uint4 *>(act + v * C);
+    float s = b[0];
+#pragma unroll
+    for (int q = 0; q < C / 8; ++q) {
+        const uint4 a = ap[q];
+        const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t bits = k & 1 ? w[k >> 1] & 0xffff0000u : w[k >> 1] << 16;
+            s = fmaf(h[8 * q + k], __uint_as_float(bits), s);
+        }
+    }
+    const float sc = mask ? scale * mask[v] : scale;
+    out[v] = fmaf(sc, s, x[v]);
+}
+
 // xb = BF16(scale x)
 __global__ __launch_bounds__(NT) void scale_bf16_kernel(const float *__restrict__ x, float scale,
                                                         u16 *__restrict__ xb, long long n) {
@@ -904,7 +904,7 @@ __global__ __launch_bounds__(NT) void scale_bf16_kernel(const float *__restrict_
 }
 
 // With d = mask scale dout: dact = d h; per-block partial sums of d act[:, k] (k < C) and d.
-template <int C>
+template <int C, bool VEC>
 __global__ __launch_bounds__(NT) void head_bwd_kernel(const u16 *__restrict__ act,
                                                       const float *__restrict__ h, float scale,
                                                       const float *__restrict__ mask,
@@ -916,12 +916,34 @@ __global__ __launch_bounds__(NT) void head_bwd_kernel(const u16 *__restrict__ ac
 #pragma unroll
     for (int k = 0; k <= C; ++k) acc[k] = 0.0;
     const long long stride = static_cast<long long>(gridDim.x) * NT;
+    static_assert(C % 8 == 0, "8 channels per 16-byte access");
     for (long long v = static_cast<long long>(blockIdx.x) * NT + threadIdx.x; v < n; v += stride) {
         const float d = (mask ? scale * mask[v] : scale) * dout[v];
+        if constexpr (!VEC) {   // act or dact not 16-byte aligned
 #pragma unroll
-        for (int k = 0; k < C; ++k) {
-            acc[k] += static_cast<double>(d) * bf2f(act[v * C + k]);
-            dact[v * C + k] = f2bf(d * h[k]);
+            for (int k = 0; k < C; ++k) {
+                acc[k] += static_cast<double>(d) * bf2f(act[v * C + k]);
+                dact[v * C + k] = f2bf(d * h[k]);
+            }
+            acc[C] += d;
+            continue;
+        }
+        const uint4 *ap = reinterpret_cast<const uint4 *>(act + v * C);
+        uint4 *dp = reinterpret_cast<uint4 *>(dact + v * C);
+#pragma unroll
+        for (int q = 0; q < C / 8; ++q) {
+            const uint4 a = ap[q];
+            const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+            uint32_t o[4];
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) {
+                const int k = 8 * q + 2 * k2;
+                acc[k] += static_cast<double>(d) * __uint_as_float(w[k2] << 16);
+                acc[k + 1] += static_cast<double>(d) * __uint_as_float(w[k2] & 0xffff0000u);
+                o[k2] = static_cast<uint32_t>(f2bf(d * h[k])) |
+                        (static_cast<uint32_t>(f2bf(d * h[k + 1])) << 16);
+            }
+            dp[q] = make_uint4(o[0], o[1], o[2], o[3]);
         }
         acc[C] += d;
     }
@@ -1010,14 +1032,16 @@ template <int CI, int CO, bool F32, bool RELU, bool ACC>
 void conv3_go(dim3 grid, dim3 blk, hipStream_t s, const u16 *ip, int in_cs, int in_off,
               const u16 *wp, const float *bias, void *out, int out_cs, int out_off, int D, int H,
               int W) {
+    // four channels per store: 4-aligned channel slice of a 16-byte aligned tensor
+    const int out_vec = (out_cs % 4 == 0 && out_off % 4 == 0 &&
+                         reinterpret_cast<uintptr_t>(out) % 16 == 0) ? 1 : 0;
     if constexpr (CI == 1) {
-        hipLaunchKernelGGL((conv3_fwd_kernel<CI, CO, F32, RELU, ACC>), grid, blk, 0, s, ip, in_cs,
-                           in_off, wp, bias, out, out_cs, out_off, D, H, W);
+        hipLaunchKernelGGL((conv3_c1_kernel<CO, F32, RELU, ACC>), grid, blk, 0, s, ip, in_cs,
+                           in_off, wp, bias, out, out_cs, out_off, D, H, W, out_vec);
     } else {
         constexpr int TY = ConvTile<CI>::TY, TZ = ConvTile<CI>::TZ;
         const long long tiles = static_cast<long long>((W + 15) / 16) * ((H + TY - 1) / TY) *
                                 ((D + TZ - 1) / TZ);
-        const int out_vec = (out_cs % 4 == 0 && out_off % 4 == 0) ? 1 : 0;
         hipLaunchKernelGGL((conv3_tile_kernel<CI, CO, F32, RELU, ACC>),
                            dim3(static_cast<unsigned>(tiles)), dim3(NT), 0, s, ip, in_cs, in_off,
                            wp, bias, out, out_cs, out_off, D, H, W, out_vec);
@@ -1159,22 +1183,28 @@ hipError_t launch_upconv2(const void *in, int in_cs, int in_off, int cin, const 
     const long long nvox = static_cast<long long>(D) * H * W;
     const dim3 grid(blocks_for(nvox, NT)), blk(NT);
     const u16 *ip = static_cast<const u16 *>(in), *wp = static_cast<const u16 *>(wt);
-#define CTREX_NN_UP(CI, CO)                                                                           \
-    if (cin == CI && cout == CO) {                                                                    \
-        if (out_f32) {                                                                                \
-            if (acc) { hipLaunchKernelGGL((upconv2_fwd_kernel<CI, CO, true, true>), grid, blk, 0, s, ip, in_cs, in_off, wp, bias, out, out_cs, out_off, D, H, W); } \
-                else { hipLaunchKernelGGL((upconv2_fwd_kernel<CI, CO, true, false>), grid, blk, 0, s, ip, in_cs, in_off, wp, bias, out, out_cs, out_off, D, H, W); } \
-        } else {                                                                                      \
-            if (acc) { hipLaunchKernelGGL((upconv2_fwd_kernel<CI, CO, false, true>), grid, blk, 0, s, ip, in_cs, in_off, wp, bias, out, out_cs, out_off, D, H, W); } \
-                else { hipLaunchKernelGGL((upconv2_fwd_kernel<CI, CO, false, false>), grid, blk, 0, s, ip, in_cs, in_off, wp, bias, out, out_cs, out_off, D, H, W); } \
-        }                                                                                             \
-        return hipGetLastError();                                                                     \
+    const int ov = (out_cs % 4 == 0 && out_off % 4 == 0 &&
+                    reinterpret_cast<uintptr_t>(out) % 16 == 0) ? 1 : 0;
+#define CTREX_NN_UP_GO(CI, CO, F, A)                                                              \
+    hipLaunchKernelGGL((upconv2_fwd_kernel<CI, CO, F, A>), grid, blk, 0, s, ip, in_cs, in_off, wp, \
+                       bias, out, out_cs, out_off, D, H, W, ov)
+#define CTREX_NN_UP(CI, CO)                                                                       \
+    if (cin == CI && cout == CO) {                                                                \
+        if (out_f32) {                                                                            \
+            if (acc) CTREX_NN_UP_GO(CI, CO, true, true);                                          \
+            else CTREX_NN_UP_GO(CI, CO, true, false);                                             \
+        } else {                                                                                  \
+            if (acc) CTREX_NN_UP_GO(CI, CO, false, true);                                         \
+            else CTREX_NN_UP_GO(CI, CO, false, false);                                            \
+        }                                                                                         \
+        return hipGetLastError();                                                                 \
     }
     CTREX_NN_UP(64, 32)
     CTREX_NN_UP(32, 16)
     CTREX_NN_UP(32, 32)
     CTREX_NN_UP(64, 64)
 #undef CTREX_NN_UP
+#undef CTREX_NN_UP_GO
     return hipErrorInvalidValue;
 }
 
@@ -1266,8 +1296,12 @@ hipError_t launch_relu_bwd(const void *y, void *g, int cs, int off, int c, long 
 
 hipError_t launch_head(const void *act, int c, const float *h, const float *b, const float *x,
                        float scale, const float *mask, float *out, long long n, hipStream_t s) {
-    hipLaunchKernelGGL(head_kernel, dim3(blocks_for(n)), dim3(NT), 0, s, static_cast<const u16 *>(act),
-                       c, h, b, x, scale, mask, out, n);
+    if (c == 16 && reinterpret_cast<uintptr_t>(act) % 16 == 0)
+        hipLaunchKernelGGL((head_vec_kernel<16>), dim3(blocks_for(n)), dim3(NT), 0, s,
+                           static_cast<const u16 *>(act), h, b, x, scale, mask, out, n);
+    else
+        hipLaunchKernelGGL(head_kernel, dim3(blocks_for(n)), dim3(NT), 0, s,
+                           static_cast<const u16 *>(act), c, h, b, x, scale, mask, out, n);
     return hipGetLastError();
 }
 
@@ -1277,16 +1311,25 @@ hipError_t launch_scale_bf16(const float *x, float scale, void *xb, long long n,
     return hipGetLastError();
 }
 
-size_t head_bwd_scratch(int c) { return sizeof(double) * 512 * static_cast<size_t>(c + 1); }
+constexpr int kHeadBwdBlocks = 2048;
+
+size_t head_bwd_scratch(int c) {
+    return sizeof(double) * kHeadBwdBlocks * static_cast<size_t>(c + 1);
+}
 
 hipError_t launch_head_bwd(const void *act, int c, const float *h, float scale, const float *mask,
                            const float *dout, void *dact, float *dh, float *db, long long n,
                            double *scratch, hipStream_t s) {
-    const int blocks = 512;
+    const int blocks = kHeadBwdBlocks;
     if (c != 16) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((head_bwd_kernel<16>), dim3(blocks), dim3(NT), 0, s,
-                       static_cast<const u16 *>(act), h, scale, mask, dout,
-                       static_cast<u16 *>(dact), n, scratch);
+    if ((reinterpret_cast<uintptr_t>(act) | reinterpret_cast<uintptr_t>(dact)) % 16 == 0)
+        hipLaunchKernelGGL((head_bwd_kernel<16, true>), dim3(blocks), dim3(NT), 0, s,
+                           static_cast<const u16 *>(act), h, scale, mask, dout,
+                           static_cast<u16 *>(dact), n, scratch);
+    else
+        hipLaunchKernelGGL((head_bwd_kernel<16, false>), dim3(blocks), dim3(NT), 0, s,
+                           static_cast<const u16 *>(act), h, scale, mask, dout,
+                           static_cast<u16 *>(dact), n, scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (dh) hipLaunchKernelGGL(reduce_rows_kernel, dim3(blocks_for(c, 32)), dim3(NT), 0, s, scratch, blocks, c, c + 1, dh);

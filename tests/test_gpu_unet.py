@@ -143,10 +143,12 @@ def test_conv3_forward_f32(L, ctx, shape, cin, cout):
     _close(_host(out).reshape(ref.shape), ref)
 
 
-@pytest.mark.parametrize("cin,cout", [(16, 32), (32, 16), (64, 64)])
-def test_conv3_slices_relu_accumulate_bf16(L, ctx, cin, cout):
+@pytest.mark.parametrize("cin,cout,off_out", [(16, 32, 16), (32, 16, 16), (64, 64, 16),
+                                              (1, 16, 16), (1, 16, 6), (32, 16, 6)])
+def test_conv3_slices_relu_accumulate_bf16(L, ctx, cin, cout, off_out):
     """Input read from a channel slice of a wider tensor, output accumulated
-    (after ReLU) into a slice of another, BF16 storage."""
+    (after ReLU) into a slice of another, BF16 storage (an output offset not
+    a multiple of 4 takes the element-by-element stores)."""
     from oracle import unet as ou
     shape = (4, 8, 8)
     n = int(np.prod(shape))
@@ -155,7 +157,7 @@ def test_conv3_slices_relu_accumulate_bf16(L, ctx, cin, cout):
     xw = _bf(r.normal(size=(n, wide_in)))
     w = r.normal(0, 0.1, size=(cout, cin, 27))
     b = r.normal(size=cout).astype(np.float32).astype(np.float64)
-    wide_out, off_out = cout + 32, 16
+    wide_out = cout + 32
     prev = _bf(r.normal(size=(n, wide_out)))
     wt, _ = _pack_conv(L, ctx, w)
     xd, bd, od = _dev_bf(xw), _dev_f(b), _dev_bf(prev)
@@ -309,6 +311,34 @@ def test_upconv2_into_concat_slice(L, ctx):
     assert np.all(np.abs(got[:, :16] - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-7)
 
 
+@pytest.mark.parametrize("cin,cout", UP_PAIRS)
+def test_upconv2_accumulate_unaligned_slice(L, ctx, cin, cout):
+    """Accumulation into a channel slice at offset 6 (element-by-element
+    stores): untouched channels bit-exact, written ones one rounding of
+    prev + y."""
+    from oracle import unet as ou
+    shape = (4, 4, 8)
+    r = _rng(8, cin, cout)
+    x = _bf(r.normal(size=shape + (cin,)))
+    w = _bf(r.normal(0, 0.2, size=(cin, cout, 8)))
+    b = r.normal(size=cout).astype(np.float32).astype(np.float64)
+    wt, _ = _pack_up(L, ctx, w)
+    n_out = 8 * int(np.prod(shape))
+    wide, off = cout + 10, 6
+    prev = _bf(r.normal(size=(n_out, wide)))
+    od, xd, bd = _dev_bf(prev), _dev_bf(x), _dev_f(b)
+    _call(L, ctx, "ctrex_nn_upconv2", _vp(xd), cin, 0, cin, _vp(wt), _vp(bd), _vp(od), wide, off,
+          cout, *shape, L.NN_ACCUMULATE, None)
+    got = _host(od)
+    y = ou.upconv2(torch.tensor(x), torch.tensor(w), torch.tensor(b)).numpy().reshape(n_out, cout)
+    np.testing.assert_array_equal(got[:, :off], prev[:, :off])
+    np.testing.assert_array_equal(got[:, off + cout:], prev[:, off + cout:])
+    old = prev[:, off:off + cout]
+    exact = old + y
+    d = np.abs(got[:, off:off + cout] - exact)
+    assert np.all(d <= 2.0 ** -8 * np.abs(exact) + 1e-5 * (np.abs(old) + np.abs(y)))
+
+
 # --------------------------------------------------------- elementwise ops --
 def test_maxpool_and_backward_bit_exact(L, ctx):
     from oracle import unet as ou
@@ -356,7 +386,10 @@ def test_relu_backward_bit_exact(L, ctx, cs, off, c):
     np.testing.assert_array_equal(_host(gd), ref)
 
 
-def test_head_forward_backward(L, ctx):
+@pytest.mark.parametrize("misaligned", [False, True])
+def test_head_forward_backward(L, ctx, misaligned):
+    """16-byte channel accesses for aligned activations, element accesses when
+    `act` / `dact` start 2 bytes past an aligned address."""
     n = 4096
     r = _rng(10)
     act = _bf(np.maximum(r.normal(size=(n, 16)), 0))
@@ -364,7 +397,10 @@ def test_head_forward_backward(L, ctx):
     bb = np.array([0.25])
     x = r.normal(size=n).astype(np.float32).astype(np.float64)
     dout = r.normal(size=n).astype(np.float32).astype(np.float64)
-    ad, hd, bd, xd, dd = _dev_bf(act), _dev_f(h), _dev_f(bb), _dev_f(x), _dev_f(dout)
+    sh = 1 if misaligned else 0
+    ad_buf = _dev_bf(np.concatenate([np.zeros(sh), act.reshape(-1)]))
+    ad = ad_buf[sh:]
+    hd, bd, xd, dd = _dev_f(h), _dev_f(bb), _dev_f(x), _dev_f(dout)
     out = torch.empty(n, dtype=torch.float32, device=DEV)
     m = (r.uniform(size=n) < 0.7).astype(np.float64)
     md = _dev_f(m)
@@ -374,7 +410,7 @@ def test_head_forward_backward(L, ctx):
         _call(L, ctx, "ctrex_nn_head", _vp(ad), 16, _vp(hd), _vp(bd), _vp(xd), s, mp, _vp(out),
               n, None)
         _close(_host(out), x + w * (bb[0] + act @ h), rel=1e-6)
-        dact = torch.empty(n * 16, dtype=torch.bfloat16, device=DEV)
+        dact = torch.empty(n * 16 + sh, dtype=torch.bfloat16, device=DEV)[sh:]
         dh = torch.empty(16, dtype=torch.float32, device=DEV)
         db = torch.empty(1, dtype=torch.float32, device=DEV)
         _call(L, ctx, "ctrex_nn_head_backward", _vp(ad), 16, _vp(hd), s, mp, _vp(dd), _vp(dact),
