@@ -294,7 +294,10 @@ __device__ float march_tube(const RayGrid &g, const float *__restrict__ vol, con
 // Measured at 512^3 x 720 x 768^2 (results bitwise identical): FP32 866 ms at
 // 5 waves per SIMD, 782 ms at 3, 876 ms at 2, 1066 ms at 8; 16-bit 823 ms at
 // 8, 765 at 6, 711 at 5, 674 at 4, 689 at 3, 808 at 2.  The warped variants
-// and the ray-length mode (no gathers) keep the default.
+// keep the default: their 111 registers already limit them to 4 waves, and
+// capping them lower was slower (helical 256^3, 1200 x 4 sub-views of
+// 512 x 256, 32^3 warp: 700 ms at 4, 714 at 3, 777 at 2).  The ray-length
+// mode (no gathers) keeps the default too.
 template <typename TV, int MODE, bool WARP>
 constexpr int fp_max_waves() {
     return (WARP || MODE == FP_RECIP_ONES) ? 8 : (sizeof(TV) == 4 ? 3 : 4);
