@@ -239,77 +239,146 @@ conv3_tile_kernel(const u16 *__restrict__ in, int in_cs, int in_off, const u16 *
         // ---- stage the input (channel chunk fastest in global memory).  Element
         // e = (row (z, y)) ROWLEN + col, col = x NC + c; the thread stride NT moves
         // col by NT % ROWLEN and the row by NT / ROWLEN, so (y, z, col) are
-        // stepped with adds and one wrap each instead of divisions.
+        // stepped with adds and one wrap each instead of divisions.  A batch
+        // of a thread's loads is issued before its LDS writes, so their
+        // latencies overlap instead of adding up (a load-then-write loop
+        // waited for each load in turn).
         {
             constexpr int ROWLEN = SX * NC, DCOL = NT % ROWLEN, DROW = NT / ROWLEN;
+            constexpr int ITER = (NEL + NT - 1) / NT;
+            constexpr int STAGE_BATCH = 6;   // loads in flight per thread
             static_assert(DROW < SY, "one y wrap per step");
             int col = threadIdx.x % ROWLEN, row = threadIdx.x / ROWLEN;
             int y = row % SY, z = row / SY;
-            for (int e = threadIdx.x; e < NEL; e += NT) {
-                const int c = col % NC, x = col / NC;   // NC is a power of 2
-                const int gx = x0 + x - 1, gy = y0 + y - 1, gz = z0 + z - 1;
-                bf16x8 v = zero8();
-                if (gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D) {
-                    const long long q = (static_cast<long long>(gz) * H + gy) * W + gx;
-                    v = load8(in + q * in_cs + in_off + h * CST + 8 * c);
+#pragma unroll
+            for (int k0 = 0; k0 < ITER; k0 += STAGE_BATCH) {
+                bf16x8 v[STAGE_BATCH];
+                int dst[STAGE_BATCH];
+#pragma unroll
+                for (int j = 0; j < STAGE_BATCH; ++j) {
+                    const int k = k0 + j;
+                    const int c = col % NC, x = col / NC;   // NC is a power of 2
+                    const int gx = x0 + x - 1, gy = y0 + y - 1, gz = z0 + z - 1;
+                    const bool in_tile = k < ITER && threadIdx.x + k * NT < NEL;
+                    dst[j] = in_tile ? ((z * SY + y) * NC + c) * SX + x : -1;
+                    v[j] = zero8();
+                    if (in_tile && gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D) {
+                        const long long q = (static_cast<long long>(gz) * H + gy) * W + gx;
+                        v[j] = load8(in + q * in_cs + in_off + h * CST + 8 * c);
+                    }
+                    col += DCOL;
+                    int dy = DROW;
+                    if (col >= ROWLEN) {
+                        col -= ROWLEN;
+                        ++dy;
+                    }
+                    y += dy;
+                    if (y >= SY) {
+                        y -= SY;
+                        ++z;
+                    }
                 }
-                tile[((z * SY + y) * NC + c) * SX + x] = v;
-                col += DCOL;
-                int dy = DROW;
-                if (col >= ROWLEN) {
-                    col -= ROWLEN;
-                    ++dy;
-                }
-                y += dy;
-                if (y >= SY) {
-                    y -= SY;
-                    ++z;
-                }
+#pragma unroll
+                for (int j = 0; j < STAGE_BATCH; ++j)
+                    if (dst[j] >= 0) tile[dst[j]] = v[j];
             }
         }
         __syncthreads();
 
-        // K steps: for 16 channels pairs of taps (lane groups 0, 1 take tap 2p,
-        // channel chunks 0, 1; groups 2, 3 tap 2p + 1; tap 27 is zero padding),
-        // otherwise one tap and 32 channels per step.  The fragments of step
-        // p + 1 are read while the MFMAs of step p run (two register sets; the
-        // scheduling barriers keep the compiler from moving the reads after them).
-        constexpr int KSTEPS = CIN == 16 ? 14 : 27;
         // this half's weights; the empty asm makes the pointer opaque, so
         // the 27 per-tap addresses are formed inside the loop over halves
         // instead of being hoisted out of it and held in registers
         const u16 *wh = wt + h * CST;
         if (NH > 1) asm volatile("" : "+v"(wh));
-        auto fetch = [&](int p, bf16x8 (&a)[MBW], bf16x8 (&b)[NB]) {
-            const int tap = CIN == 16 ? 2 * p + (g >> 1) : p;
-            const int c = CIN == 16 ? (g & 1) : g;
-            const bool live = tap < 27;
-            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-            const int off = lbase + ((dz * SY + dy) * NC + c) * SX + dx;
+        if constexpr (CIN == 16 || NB > 2) {
+            // K steps: for 16 channels pairs of taps (lane groups 0, 1 take tap 2p,
+            // channel chunks 0, 1; groups 2, 3 tap 2p + 1; tap 27 is zero padding),
+            // otherwise one tap and 32 channels per step.  The fragments of step
+            // p + 1 are read while the MFMAs of step p run (two register sets; the
+            // scheduling barriers keep the compiler from moving the reads after them).
+            constexpr int KSTEPS = CIN == 16 ? 14 : 27;
+            auto fetch = [&](int p, bf16x8 (&a)[MBW], bf16x8 (&b)[NB]) {
+                const int tap = CIN == 16 ? 2 * p + (g >> 1) : p;
+                const int c = CIN == 16 ? (g & 1) : g;
+                const bool live = tap < 27;
+                const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+                const int off = lbase + ((dz * SY + dy) * NC + c) * SX + dx;
 #pragma unroll
-            for (int m = 0; m < MBW; ++m) a[m] = live ? tile[off + m * NC * SX] : zero8();
+                for (int m = 0; m < MBW; ++m) a[m] = live ? tile[off + m * NC * SX] : zero8();
 #pragma unroll
-            for (int n = 0; n < NB; ++n)
-                b[n] = live ? load8(wh + (tap * COUT + n * 16 + r) * CIN + 8 * c) : zero8();
-        };
-        auto step = [&](const bf16x8 (&a)[MBW], const bf16x8 (&b)[NB]) {
+                for (int n = 0; n < NB; ++n)
+                    b[n] = live ? load8(wh + (tap * COUT + n * 16 + r) * CIN + 8 * c) : zero8();
+            };
+            auto step = [&](const bf16x8 (&a)[MBW], const bf16x8 (&b)[NB]) {
 #pragma unroll
-            for (int m = 0; m < MBW; ++m)
+                for (int m = 0; m < MBW; ++m)
 #pragma unroll
-                for (int n = 0; n < NB; ++n) acc[m][n] = mma(b[n], a[m], acc[m][n]);
-        };
-        bf16x8 a0[MBW], b0[NB], a1[MBW], b1[NB];
-        fetch(0, a0, b0);
+                    for (int n = 0; n < NB; ++n) acc[m][n] = mma(b[n], a[m], acc[m][n]);
+            };
+            bf16x8 a0[MBW], b0[NB], a1[MBW], b1[NB];
+            fetch(0, a0, b0);
 #pragma unroll
-        for (int p = 0; p < KSTEPS; p += 2) {
-            if (p + 1 < KSTEPS) fetch(p + 1, a1, b1);
-            __builtin_amdgcn_sched_barrier(0);
-            step(a0, b0);
-            __builtin_amdgcn_sched_barrier(0);
-            if (p + 2 < KSTEPS) fetch(p + 2, a0, b0);
-            __builtin_amdgcn_sched_barrier(0);
-            if (p + 1 < KSTEPS) step(a1, b1);
-            __builtin_amdgcn_sched_barrier(0);
+            for (int p = 0; p < KSTEPS; p += 2) {
+                if (p + 1 < KSTEPS) fetch(p + 1, a1, b1);
+                __builtin_amdgcn_sched_barrier(0);
+                step(a0, b0);
+                __builtin_amdgcn_sched_barrier(0);
+                if (p + 2 < KSTEPS) fetch(p + 2, a0, b0);
+                __builtin_amdgcn_sched_barrier(0);
+                if (p + 1 < KSTEPS) step(a1, b1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+            // One tap and 32 channels per K step, blocked over dy: for each
+            // (dz, dx) the wave reads each input row of its span (rows
+            // ym0 - 1 .. ym0 + MBW) once and multiplies it with the weights
+            // of the three dy taps of the output rows it neighbours, so one
+            // LDS read feeds up to three MFMA blocks instead of one.  The
+            // next row's fragment (and, at the first row of a (dz, dx), the
+            // next pair's weights) is read while the current MFMAs run.
+            constexpr int NR = MBW + 2, NS = 9 * NR;
+            static_assert(NR % 2 == 0, "rows are taken in pairs");
+            auto fetch_b = [&](int q, bf16x8 (&b)[3][NB]) {
+                const int dz = q / 3 - 1, dx = q % 3 - 1;
+#pragma unroll
+                for (int dyi = 0; dyi < 3; ++dyi) {
+                    const int tap = (dz + 1) * 9 + dyi * 3 + dx + 1;
+#pragma unroll
+                    for (int n = 0; n < NB; ++n)
+                        b[dyi][n] = load8(wh + (tap * COUT + n * 16 + r) * CIN + 8 * g);
+                }
+            };
+            auto fetch_a = [&](int st) {
+                const int q = st / NR, ri = st % NR - 1;
+                const int dz = q / 3 - 1, dx = q % 3 - 1;
+                return tile[lbase + ((dz * SY + ri) * NC + g) * SX + dx];
+            };
+            auto rows = [&](int st, const bf16x8 &a, const bf16x8 (&b)[3][NB]) {
+                const int ri = st % NR - 1;
+#pragma unroll
+                for (int dyi = 0; dyi < 3; ++dyi) {
+                    const int m = ri - (dyi - 1);   // output row fed with tap dy = dyi - 1
+                    if (m < 0 || m >= MBW) continue;
+#pragma unroll
+                    for (int n = 0; n < NB; ++n) acc[m][n] = mma(b[dyi][n], a, acc[m][n]);
+                }
+            };
+            bf16x8 bq[2][3][NB];
+            fetch_b(0, bq[0]);
+            bf16x8 a0 = fetch_a(0), a1;
+#pragma unroll
+            for (int st = 0; st < NS; st += 2) {
+                const int q = st / NR;
+                if (st % NR == 0 && q + 1 < 9) fetch_b(q + 1, bq[(q + 1) & 1]);
+                a1 = fetch_a(st + 1);
+                __builtin_amdgcn_sched_barrier(0);
+                rows(st, a0, bq[q & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+                if (st + 2 < NS) a0 = fetch_a(st + 2);
+                __builtin_amdgcn_sched_barrier(0);
+                rows(st + 1, a1, bq[((st + 1) / NR) & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
     }
     // ---- epilogue.  The products were formed as weights x inputs, so lane
@@ -378,43 +447,77 @@ __global__ __launch_bounds__(WG_THREADS) void wgrad_tile_kernel(
 #pragma unroll
                 for (int n = 0; n < NBk; ++n) acc[a][b][m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
+    // Staging is split into loads (all of a thread's elements of one plane
+    // in flight at once) and LDS writes, so the load latencies overlap
+    // instead of adding up.
     // input plane zi (zeros outside the volume) into ring slot (zi + 3) % 3
-    auto stage_in = [&](int zi, int x0, int y0) {
-        const int slot = (zi + 3) % 3;
-        constexpr int NCH = CIN / 8, NXS = 36;   // x in [-2, 34)
-        for (int e = threadIdx.x; e < WG_IY * NXS * NCH; e += WG_THREADS) {
-            const int c = e % NCH;
-            const int t = e / NCH;
+    constexpr int NCH_I = CIN / 8, NXS = 36;   // x in [-2, 34)
+    constexpr int NEL_I = WG_IY * NXS * NCH_I, IT_I = (NEL_I + WG_THREADS - 1) / WG_THREADS;
+    constexpr int NCH_D = COUT / 8;
+    constexpr int NEL_D = WG_Y * WG_X * NCH_D, IT_D = (NEL_D + WG_THREADS - 1) / WG_THREADS;
+    auto load_in = [&](int zi, int x0, int y0, uint4 (&v)[IT_I]) {
+#pragma unroll
+        for (int k = 0; k < IT_I; ++k) {
+            const int e = threadIdx.x + k * WG_THREADS;
+            const int c = e % NCH_I;
+            const int t = e / NCH_I;
             const int xs = t % NXS, iy = t / NXS;
             const int gx = x0 + xs - 2, gy = y0 - 1 + iy;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (zi >= 0 && zi < D && gx >= 0 && gx < W && gy >= 0 && gy < H) {
+            v[k] = make_uint4(0u, 0u, 0u, 0u);
+            if (e < NEL_I && zi >= 0 && zi < D && gx >= 0 && gx < W && gy >= 0 && gy < H) {
                 const long long q = (static_cast<long long>(zi) * H + gy) * W + gx;
-                v = *reinterpret_cast<const uint4 *>(in + q * in_cs + in_off + 8 * c);
+                v[k] = *reinterpret_cast<const uint4 *>(in + q * in_cs + in_off + 8 * c);
             }
-            const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                inT[slot][8 * c + k][iy][xs + 6] = static_cast<u16>(wv[k >> 1] >> (16 * (k & 1)));
         }
     };
-    auto stage_dout = [&](int z, int x0, int y0) {
-        constexpr int NCH = COUT / 8;
-        for (int e = threadIdx.x; e < WG_Y * WG_X * NCH; e += WG_THREADS) {
-            const int c = e % NCH;
-            const int t = e / NCH;
+    auto store_in = [&](int zi, const uint4 (&v)[IT_I]) {
+        const int slot = (zi + 3) % 3;
+#pragma unroll
+        for (int k = 0; k < IT_I; ++k) {
+            const int e = threadIdx.x + k * WG_THREADS;
+            if (e >= NEL_I) continue;
+            const int c = e % NCH_I;
+            const int t = e / NCH_I;
+            const int xs = t % NXS, iy = t / NXS;
+            const uint32_t wv[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                inT[slot][8 * c + j][iy][xs + 6] = static_cast<u16>(wv[j >> 1] >> (16 * (j & 1)));
+        }
+    };
+    auto load_dout = [&](int z, int x0, int y0, uint4 (&v)[IT_D]) {
+#pragma unroll
+        for (int k = 0; k < IT_D; ++k) {
+            const int e = threadIdx.x + k * WG_THREADS;
+            const int c = e % NCH_D;
+            const int t = e / NCH_D;
             const int x = t % WG_X, y = t / WG_X;
             const int gx = x0 + x, gy = y0 + y;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (gx < W && gy < H) {
+            v[k] = make_uint4(0u, 0u, 0u, 0u);
+            if (e < NEL_D && gx < W && gy < H) {
                 const long long q = (static_cast<long long>(z) * H + gy) * W + gx;
-                v = *reinterpret_cast<const uint4 *>(dout + q * dout_cs + dout_off + 8 * c);
+                v[k] = *reinterpret_cast<const uint4 *>(dout + q * dout_cs + dout_off + 8 * c);
             }
-            const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                dT[8 * c + k][y][x] = static_cast<u16>(wv[k >> 1] >> (16 * (k & 1)));
         }
+    };
+    auto store_dout = [&](const uint4 (&v)[IT_D]) {
+#pragma unroll
+        for (int k = 0; k < IT_D; ++k) {
+            const int e = threadIdx.x + k * WG_THREADS;
+            if (e >= NEL_D) continue;
+            const int c = e % NCH_D;
+            const int t = e / NCH_D;
+            const int x = t % WG_X, y = t / WG_X;
+            const uint32_t wv[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                dT[8 * c + j][y][x] = static_cast<u16>(wv[j >> 1] >> (16 * (j & 1)));
+        }
+    };
+    auto stage_in = [&](int zi, int x0, int y0) {
+        uint4 v[IT_I];
+        load_in(zi, x0, y0, v);
+        store_in(zi, v);
     };
 
     for (int u = blockIdx.x; u < units; u += gridDim.x) {
@@ -428,8 +531,13 @@ __global__ __launch_bounds__(WG_THREADS) void wgrad_tile_kernel(
         stage_in(za - 1, x0, y0);
         stage_in(za, x0, y0);
         for (int z = za; z < zb; ++z) {
-            stage_in(z + 1, x0, y0);
-            stage_dout(z, x0, y0);
+            {
+                uint4 vi[IT_I], vd[IT_D];
+                load_in(z + 1, x0, y0, vi);
+                load_dout(z, x0, y0, vd);
+                store_in(z + 1, vi);
+                store_dout(vd);
+            }
             __syncthreads();
             // this wave's input plane z + dz
             const int slot = (z + dz + 3) % 3;
