@@ -654,33 +654,50 @@ __global__ __launch_bounds__(64) void conv3_wgrad_c1_kernel(const u16 *__restric
 // dw[co][ci][tap] = sum over chunks of partial[c][tap][co][ci] (FP64, fixed order).
 // The partials hold a (cout_b x cin_b) block of the gradient, output
 // channels co0 + [0, cout_b), input channels ci0 + [0, cin_b), of a layer
-// with cout x cin channels.
+// with cout x cin channels.  OUTB outputs per block, NT / OUTB slices of the
+// chunks each (slice k sums chunks k, k + NT / OUTB, ...), the slices then
+// added in order: a fixed order in FP64.  Few outputs over many chunks take
+// OUTB = 8 (more slices, more blocks), the others 32.
+template <int OUTB>
 __global__ __launch_bounds__(NT) void reduce_wgrad_kernel(const float *__restrict__ partial,
                                                           int chunks, int taps, int cout_b,
                                                           int cin_b, int co0, int ci0, int cout,
                                                           int cin, int tap_major_out,
                                                           float *__restrict__ dw) {
-    // 32 outputs per block, 8 slices of the chunks each (slice k sums chunks
-    // k, k + 8, ...), slices then added in order: a fixed order in FP64
-    __shared__ double red[NT / 32][32];
+    constexpr int SL = NT / OUTB;
+    __shared__ double red[SL][OUTB];
     const int n = taps * cout_b * cin_b;
-    const int o = threadIdx.x & 31, sl = threadIdx.x >> 5;
-    const int i = blockIdx.x * 32 + o;   // the partial's [tap][co][ci] order
+    const int o = threadIdx.x % OUTB, sl = threadIdx.x / OUTB;
+    const int i = blockIdx.x * OUTB + o;   // the partial's [tap][co][ci] order
     double sum = 0.0;
     if (i < n)
-        for (int c = sl; c < chunks; c += NT / 32)
+        for (int c = sl; c < chunks; c += SL)
             sum += static_cast<double>(partial[static_cast<long long>(c) * n + i]);
     red[sl][o] = sum;
     __syncthreads();
     if (sl != 0 || i >= n) return;
     double t = 0.0;
-    for (int k = 0; k < NT / 32; ++k) t += red[k][o];
+    for (int k = 0; k < SL; ++k) t += red[k][o];
     const int tap = i / (cout_b * cin_b);
     const int rem = i - tap * cout_b * cin_b;
     const int co = co0 + rem / cin_b, ci = ci0 + rem % cin_b;
     // conv3: master order [co][ci][tap]; upconv: [ci][co][tap]
     const int ox = tap_major_out ? (ci * cout + co) * taps + tap : (co * cin + ci) * taps + tap;
     dw[ox] = static_cast<float>(t);
+}
+
+// Sum the chunks' partials of one gradient block into dw (see above).
+hipError_t launch_reduce_wgrad(const float *partial, int chunks, int taps, int cout_b, int cin_b,
+                               int co0, int ci0, int cout, int cin, int tap_major_out, float *dw,
+                               hipStream_t s) {
+    const int n = taps * cout_b * cin_b;
+    if (n < 4096 && chunks >= 1024)
+        hipLaunchKernelGGL(reduce_wgrad_kernel<8>, dim3((n + 7) / 8), dim3(NT), 0, s, partial,
+                           chunks, taps, cout_b, cin_b, co0, ci0, cout, cin, tap_major_out, dw);
+    else
+        hipLaunchKernelGGL(reduce_wgrad_kernel<32>, dim3((n + 31) / 32), dim3(NT), 0, s, partial,
+                           chunks, taps, cout_b, cin_b, co0, ci0, cout, cin, tap_major_out, dw);
+    return hipGetLastError();
 }
 
 // Per-channel sums over voxels: partial[block][c].
@@ -1207,8 +1224,19 @@ long long wgrad_chunk(long long nvox) {
     return chunk < 512 ? 512 : chunk;
 }
 
+// One input channel: one wave per chunk gathers its 27 taps per voxel, so
+// many small chunks (about 8192, at least 512 voxels each) keep enough waves
+// in flight to hide the gathers' latency; the partials stay small (27 cout
+// floats per chunk).
+long long wgrad_c1_chunk(long long nvox) {
+    long long chunk = (nvox + 8191) / 8192;
+    chunk = (chunk + 31) / 32 * 32;
+    return chunk < 512 ? 512 : chunk;
+}
+
 size_t conv3_wgrad_scratch(int cin, int cout, long long nvox) {
-    const long long chunks = (nvox + wgrad_chunk(nvox) - 1) / wgrad_chunk(nvox);
+    const long long ch = cin == 1 ? wgrad_c1_chunk(nvox) : wgrad_chunk(nvox);
+    const long long chunks = (nvox + ch - 1) / ch;
     return sizeof(float) * static_cast<size_t>(chunks) * 27 * cin * cout;
 }
 
@@ -1221,14 +1249,13 @@ hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin, co
     const u16 *ip = static_cast<const u16 *>(in), *dp = static_cast<const u16 *>(dout);
     if (cin == 1) {
         if (cout != 16) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((conv3_wgrad_c1_kernel<16>), dim3(chunks), dim3(64), 0, s, ip, in_cs,
-                           in_off, dp, dout_cs, dout_off, D, H, W, chunk, scratch);
+        const long long c1 = wgrad_c1_chunk(nvox);
+        const int n1 = static_cast<int>((nvox + c1 - 1) / c1);
+        hipLaunchKernelGGL((conv3_wgrad_c1_kernel<16>), dim3(n1), dim3(64), 0, s, ip, in_cs,
+                           in_off, dp, dout_cs, dout_off, D, H, W, c1, scratch);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        const int n = 27 * cout;
-        hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(n, 32)), dim3(NT), 0, s, scratch,
-                           chunks, 27, cout, 1, 0, 0, cout, 1, 0, dw);
-        return hipGetLastError();
+        return launch_reduce_wgrad(scratch, n1, 27, cout, 1, 0, 0, cout, 1, 0, dw, s);
     }
     if ((cin != 16 && cin != 32 && cin != 64) || (cout != 16 && cout != 32 && cout != 64))
         return hipErrorInvalidValue;
@@ -1261,9 +1288,7 @@ hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin, co
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             const int n = 27 * cob * cib;
-            hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(n, 32)), dim3(NT), 0, s, part,
-                               parts, 27, cob, cib, co0, ci0, cout, cin, 0, dw);
-            e = hipGetLastError();
+            e = launch_reduce_wgrad(part, parts, 27, cob, cib, co0, ci0, cout, cin, 0, dw, s);
             if (e != hipSuccess) return e;
             part += static_cast<long long>(parts) * n;
         }
@@ -1364,10 +1389,7 @@ hipError_t launch_upconv2_wgrad(const void *in, int in_cs, int in_off, int cin, 
     if (!done) return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int n = 8 * cout * cin;
-    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(n, 32)), dim3(NT), 0, s, scratch, chunks, 8,
-                       cout, cin, 0, 0, cout, cin, 1, dw);
-    return hipGetLastError();
+    return launch_reduce_wgrad(scratch, chunks, 8, cout, cin, 0, 0, cout, cin, 1, dw, s);
 }
 
 hipError_t launch_maxpool2(const void *in, int in_cs, int in_off, int c, void *out, int D, int H,
