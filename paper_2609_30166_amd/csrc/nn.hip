@@ -722,7 +722,7 @@ __global__ __launch_bounds__(NT) void channel_sum_kernel(const u16 *__restrict__
 #pragma unroll
     for (int k = 0; k < 8; ++k) red[threadIdx.x][k] = s[k];
     __syncthreads();
-    if (threadIdx.x < c) {
+    if (static_cast<int>(threadIdx.x) < c) {
         const int g8 = threadIdx.x / 8, k = threadIdx.x % 8;
         double t = 0.0;
         for (int l = 0; l < per; ++l) t += red[l * cg + g8][k];
