@@ -715,7 +715,15 @@ def main():
             cu_clk = 256 * ms * 1e-3 * CLOCK_HZ
             row["counters"] = {"valu_per_cu_clock": rec["sq_insts_valu"] / cu_clk,
                                "lds_per_cu_clock": rec["sq_insts_lds"] / cu_clk,
-                               "lds_bank_conflict_frac": rec["sq_lds_bank_conflict"] / cu_clk}
+                               "lds_bank_conflict_frac": rec["sq_lds_bank_conflict"] / cu_clk,
+                               # LDS pipe: 4 clocks per wave instruction (64 lanes x 8 B
+                               # at 128 B per clock) plus the bank-conflict clocks
+                               "lds_busy_est": (4 * rec["sq_insts_lds"] +
+                                                rec["sq_lds_bank_conflict"]) / cu_clk}
+            if "ta_busy_sum" in rec:
+                # texture addresser (one per CU): busy, and stalled waiting on the L1
+                row["counters"]["ta_busy"] = rec["ta_busy_sum"] / cu_clk
+                row["counters"]["ta_stalled_by_l1"] = rec["ta_addr_stalled_by_tc_sum"] / cu_clk
         return row
 
     kernels = {"fp_kernel": kernel_row("fp_kernel", fp_ms),
