@@ -28,8 +28,11 @@ SIMDs x 32 lanes per clock x 2.4 GHz = 78.6e12 lane operations per second
 backprojector's 8 algorithmic LDS 64-bit atomics per sample (before the
 register merge of same-cell samples) are also set against the LDS roof (128
 bytes per clock per CU: 16 such lane operations); the issue counters of the
-committed summary give its measured LDS and VALU rates and the fraction of
-cycles lost to LDS bank conflicts, the kernel's actual limit.  HBM traffic and
+committed summary give its measured LDS and VALU rates, the fraction of
+cycles lost to LDS bank conflicts and an LDS-pipe estimate (4 clocks per LDS
+wave-instruction plus the conflict clocks), the kernel's actual limit; for the
+forward projector they give the texture addresser's busy and L1-stalled
+fractions, its limit.  HBM traffic and
 the L2 hit rate per kernel are read from the committed counter summary
 (rocprofv3 --pmc passes: FETCH_SIZE, WRITE_SIZE scaled by the same counters
 of a plain copy kernel of known size, ``--copy-calibrate``; TCC_HIT_sum and
