@@ -93,9 +93,9 @@ CTREX_API int ctrex_create(ctrex_ctx **out, int device);
  * set) need for view lists of up to n_views entries (n_views <= 0: n_proj):
  * the correction volume (4 bytes per voxel), a 16-bit shadow (2), the
  * copies of the volume the rays gather from (32 for FP32, 16 for 16-bit;
- * the backprojector's per-chunk partial volumes reuse that region) and the
- * residual partials (8 per 16x16 detector tile per view).  CTREX_ESTATE
- * without a geometry.
+ * the backprojector's 64-bit integer sums, 8 per voxel, reuse that region)
+ * and the residual partials (8 per 16x16 detector tile per view).
+ * CTREX_ESTATE without a geometry.
  * ctrex_set_scratch attaches `bytes` of device memory at `dev` (NULL, 0
  * detaches).  The library keeps the pointer: the memory must stay allocated
  * and must not be written by the caller while calls that use it may run.
@@ -178,9 +178,9 @@ CTREX_API int ctrex_forward_project(ctrex_ctx *ctx, const void *vol, int32_t vol
  * (also for an empty view list, where `sino` may be NULL).
  * Contributions are summed as 64-bit fixed-point integers (scale chosen from
  * max |sino| so no sum overflows), so the result is bitwise reproducible
- * from run to run.  A context cell holds max |sino|; when the projections
- * are split into several chunks (small volumes), the attached scratch holds
- * one float32 partial volume per chunk (summed in a fixed order).
+ * from run to run.  A context cell holds max |sino|; the integer sums are
+ * kept in the attached scratch (8 bytes per voxel, in the region of the
+ * forward projector's gather copies) and scaled into `vol` at the end.
  */
 CTREX_API int ctrex_back_project(ctrex_ctx *ctx, const void *sino, int32_t sino_dtype, float *vol,
                        int32_t accumulate, const int32_t *views, int32_t n_views,
