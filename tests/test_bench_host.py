@@ -63,3 +63,35 @@ def test_source_hash_covers_every_listed_file(monkeypatch):
 
     monkeypatch.setattr("builtins.open", fake_open)
     assert bench.source_hash("bp_brick_kernel") != h0
+
+
+def test_unet_flop_count_matches_torch_flop_counter():
+    """The FLOPs behind the reported U-Net rate, counted independently: torch's
+    flop counter over the same network written with plain torch operators
+    (3x3x3 same-padded convolutions, 2x2x2 stride-2 transposed convolutions,
+    a 1x1x1 head; pooling and concatenation cost no FLOPs)."""
+    import torch
+    import torch.nn.functional as F
+    from torch.utils.flop_counter import FlopCounterMode
+
+    from paper_2609_30166_amd.unet import LAYERS
+
+    n = 8
+    w = {name: torch.rand(cout, cin, 3, 3, 3) if kind == "conv" else torch.rand(cin, cout, 2, 2, 2)
+         for name, kind, cin, cout in LAYERS}
+
+    def conv(name, t):
+        return F.relu(F.conv3d(t, w[name], padding=1))
+
+    def up(name, t):
+        return F.conv_transpose3d(t, w[name], stride=2)
+
+    x = torch.rand(1, 1, n, n, n)
+    with FlopCounterMode(display=False) as fc:
+        e1 = conv("e1b", conv("e1a", x))
+        e2 = conv("e2b", conv("e2a", F.max_pool3d(e1, 2)))
+        b = conv("bnb", conv("bna", F.max_pool3d(e2, 2)))
+        d2 = conv("d2b", conv("d2a", torch.cat([up("up2", b), e2], 1)))
+        d1 = conv("d1b", conv("d1a", torch.cat([up("up1", d2), e1], 1)))
+        F.conv3d(d1, torch.rand(1, 16, 1, 1, 1))
+    assert fc.get_total_flops() == bench.unet_flops(n)
