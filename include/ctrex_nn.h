@@ -11,8 +11,11 @@
  *  - Activations are BF16, channels-last: element (z, y, x, c) of a tensor
  *    with channel stride `cs` and channel offset `off` sits at
  *    ((z * H + y) * W + x) * cs + off + c.  A stride larger than the channel
- *    count lets a layer read or write a slice of a wider tensor (the skip
- *    concatenations are built in place this way).  Tensors of 16 or more
+ *    count lets a layer read or write a slice of a wider tensor.  The
+ *    decoder's skip concatenations are never stored: ctrex_nn_conv3_cat
+ *    reads the two tensors and writes the two gradients directly (a stored
+ *    concatenation costs its producers half-record writes, which the memory
+ *    system turns into read-modify-writes).  Tensors of 16 or more
  *    channels are read 8 channels at a time (16-byte loads): their stride and
  *    offset must be multiples of 8 (CTREX_ESHAPE otherwise).  Volumes D x H x W need
  *    D * H * W to be a multiple of 64 and, for the 2x pooling and up-sampling,
@@ -83,6 +86,40 @@ CTREX_API int ctrex_nn_conv3_wgrad(ctrex_ctx *ctx, const void *in, int32_t in_cs
                                    int32_t cin, const void *dout, int32_t dout_cs,
                                    int32_t dout_off, int32_t cout, int32_t D, int32_t H, int32_t W,
                                    float *dw, float *dbias, void *stream);
+
+/*
+ * ctrex_nn_conv3 over the channel concatenation of two tensors, written to
+ * two tensors: the U-Net decoder's convolution of [up-sampled features |
+ * skip features] and, with the dgrad packing, its data gradient split back
+ * into the two parts.  Input channels [0, ca) are in_a's channels a_off ..
+ * a_off + ca - 1 (stride a_cs), input channels [ca, ca + cb) in_b's channels
+ * b_off .. (stride b_cs); output channels [0, oa) go to out_a (stride oa_cs,
+ * offset oa_off), [oa, oa + ob) to out_b.  cb = 0 ignores in_b, ob = 0
+ * ignores out_b (then this is ctrex_nn_conv3).  A two-tensor input (cb > 0)
+ * is supported for (ca + cb, oa + ob) = (32, 16) or (64, 32) with ca a
+ * multiple of 8; a two-tensor output (ob > 0) needs cin >= 16 and oa a
+ * multiple of 16; other shapes as ctrex_nn_conv3, CTREX_ESHAPE otherwise.
+ * Same flags, packing, arithmetic and status behaviour as ctrex_nn_conv3.
+ */
+CTREX_API int ctrex_nn_conv3_cat(ctrex_ctx *ctx, const void *in_a, int32_t a_cs, int32_t a_off,
+                                 int32_t ca, const void *in_b, int32_t b_cs, int32_t b_off,
+                                 int32_t cb, const void *wt, const float *bias, void *out_a,
+                                 int32_t oa_cs, int32_t oa_off, int32_t oa, void *out_b,
+                                 int32_t ob_cs, int32_t ob_off, int32_t ob, int32_t D, int32_t H,
+                                 int32_t W, uint32_t flags, void *stream);
+
+/*
+ * ctrex_nn_conv3_wgrad with the input the channel concatenation of in_a
+ * (ca channels) and in_b (cb channels, 0 = none), both in {16, 32, 64} with
+ * ca + cb <= 64: dw[co][ci][tap] over ci < ca + cb in concatenation order.
+ * Scratch, determinism and statuses as ctrex_nn_conv3_wgrad.
+ */
+CTREX_API int ctrex_nn_conv3_wgrad_cat(ctrex_ctx *ctx, const void *in_a, int32_t a_cs,
+                                       int32_t a_off, int32_t ca, const void *in_b, int32_t b_cs,
+                                       int32_t b_off, int32_t cb, const void *dout,
+                                       int32_t dout_cs, int32_t dout_off, int32_t cout, int32_t D,
+                                       int32_t H, int32_t W, float *dw, float *dbias,
+                                       void *stream);
 
 /*
  * 2x2x2 stride-2 transposed convolution (up-sampling): the input is

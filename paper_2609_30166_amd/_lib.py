@@ -95,6 +95,12 @@ def lib():
                                               i32, i32, i32, u32, vp]),
             "ctrex_nn_conv3_wgrad": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, i32, i32, i32,
                                                     i32, i32, i32, vp, vp, vp]),
+            "ctrex_nn_conv3_cat": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, i32, i32, i32, vp,
+                                                  vp, vp, i32, i32, i32, vp, i32, i32, i32, i32,
+                                                  i32, i32, u32, vp]),
+            "ctrex_nn_conv3_wgrad_cat": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, i32, i32, i32,
+                                                        vp, i32, i32, i32, i32, i32, i32, vp, vp,
+                                                        vp]),
             "ctrex_nn_upconv2": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, vp, vp, i32, i32, i32,
                                                 i32, i32, i32, u32, vp]),
             "ctrex_nn_upconv2_dgrad": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, vp, i32, i32,

@@ -201,12 +201,24 @@ template <int CIN, int COUT> struct ConvTile {
     static constexpr int TY = 8, TZ = CIN == 16 && COUT == 16 ? 4 : 2;
 };
 
-template <int CIN, int COUT, bool OUT_F32, bool RELU, bool ACC>
+// Second input and output of a convolution over a channel concatenation: input
+// channels k >= ksplit are channel k - ksplit of in2 (only read where the
+// kernel's CAT parameter is set), output channels co >= nsplit go to channel
+// co - nsplit of out2 (nsplit a multiple of 16).  A plain convolution passes
+// ksplit = cin, nsplit = cout.
+struct CatArgs {
+    const u16 *in2;
+    int in2_cs, in2_off, ksplit;
+    void *out2;
+    int out2_cs, out2_off, nsplit;
+};
+
+template <int CIN, int COUT, bool OUT_F32, bool RELU, bool ACC, bool CAT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
     CIN == 16 ? (COUT == 16 ? 4 : 1) : (COUT <= 32 ? 3 : 1)))) void
 conv3_tile_kernel(const u16 *__restrict__ in, int in_cs, int in_off, const u16 *__restrict__ wt,
                   const float *__restrict__ bias, void *out, int out_cs, int out_off, int D, int H,
-                  int W, int out_vec) {
+                  int W, int out_vec, CatArgs cat) {
     constexpr int TY = ConvTile<CIN, COUT>::TY, TZ = ConvTile<CIN, COUT>::TZ;
     constexpr int CST = CIN < 32 ? CIN : 32;  // channels staged at a time
     constexpr int NH = CIN / CST;             // staging passes
@@ -265,7 +277,15 @@ conv3_tile_kernel(const u16 *__restrict__ in, int in_cs, int in_off, const u16 *
                     v[j] = zero8();
                     if (in_tile && gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D) {
                         const long long q = (static_cast<long long>(gz) * H + gy) * W + gx;
-                        v[j] = load8(in + q * in_cs + in_off + h * CST + 8 * c);
+                        const int k = h * CST + 8 * c;   // first input channel of the chunk
+                        const u16 *src = in;
+                        int scs = in_cs, sch = in_off + k;
+                        if (CAT && k >= cat.ksplit) {
+                            src = cat.in2;
+                            scs = cat.in2_cs;
+                            sch = cat.in2_off + k - cat.ksplit;
+                        }
+                        v[j] = load8(src + q * scs + sch);
                     }
                     col += DCOL;
                     int dy = DROW;
@@ -395,15 +415,20 @@ conv3_tile_kernel(const u16 *__restrict__ in, int in_cs, int in_off, const u16 *
         float bco[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) bco[j] = bias ? bias[co0 + j] : 0.0f;
+        // the block's destination (the same for the whole workgroup)
+        const bool second = n * 16 >= cat.nsplit;
+        void *dst = second ? cat.out2 : out;
+        const int dcs = second ? cat.out2_cs : out_cs;
+        const int dch = second ? cat.out2_off + co0 - cat.nsplit : out_off + co0;
 #pragma unroll
         for (int m = 0; m < MBW; ++m) {
             const int gy = y0 + ym0 + m;
             if (gz >= D || gy >= H || gx >= W) continue;
-            const long long o = ((static_cast<long long>(gz) * H + gy) * W + gx) * out_cs + out_off + co0;
+            const long long o = ((static_cast<long long>(gz) * H + gy) * W + gx) * dcs + dch;
             float v[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) v[j] = acc[m][n][j] + bco[j];
-            store4<OUT_F32, RELU, ACC>(out, o, v, out_vec != 0);
+            store4<OUT_F32, RELU, ACC>(dst, o, v, out_vec != 0);
         }
     }
 }
@@ -1154,59 +1179,97 @@ inline unsigned blocks_for(long long n, int per = NT) {
 }  // namespace
 
 // ---------------------------------------------------------------- launchers --
+// The tiled convolution over a two-tensor concatenation is built for the
+// decoder shapes only (the up-sampled features and the skip features, equal
+// halves of the input).
+template <int CI, int CO> constexpr bool cat_shape() {
+    return (CI == 32 && CO == 16) || (CI == 64 && CO == 32);
+}
+
+inline bool vec_ok(const void *p, int cs, int off) {
+    return cs % 4 == 0 && off % 4 == 0 && reinterpret_cast<uintptr_t>(p) % 16 == 0;
+}
+
 template <int CI, int CO, bool F32, bool RELU, bool ACC>
-void conv3_go(dim3 grid, dim3 blk, hipStream_t s, const u16 *ip, int in_cs, int in_off,
-              const u16 *wp, const float *bias, void *out, int out_cs, int out_off, int D, int H,
-              int W) {
-    // four channels per store: 4-aligned channel slice of a 16-byte aligned tensor
-    const int out_vec = (out_cs % 4 == 0 && out_off % 4 == 0 &&
-                         reinterpret_cast<uintptr_t>(out) % 16 == 0) ? 1 : 0;
+hipError_t conv3_go(hipStream_t s, const u16 *ip, int in_cs, int in_off, const u16 *wp,
+                    const float *bias, void *out, int out_cs, int out_off, int D, int H, int W,
+                    const CatArgs &cat) {
+    // four channels per store: 4-aligned channel slices of 16-byte aligned tensors
+    const int out_vec = vec_ok(out, out_cs, out_off) && vec_ok(cat.out2, cat.out2_cs, cat.out2_off);
+    const bool two_in = cat.ksplit < CI;
     if constexpr (CI == 1) {
-        hipLaunchKernelGGL((conv3_c1_kernel<CO, F32, RELU, ACC>), grid, blk, 0, s, ip, in_cs,
-                           in_off, wp, bias, out, out_cs, out_off, D, H, W, out_vec);
+        if (two_in || cat.nsplit < CO) return hipErrorInvalidValue;
+        const long long nvox = static_cast<long long>(D) * H * W;
+        hipLaunchKernelGGL((conv3_c1_kernel<CO, F32, RELU, ACC>), dim3(blocks_for(nvox, NT)),
+                           dim3(NT), 0, s, ip, in_cs, in_off, wp, bias, out, out_cs, out_off, D, H,
+                           W, out_vec);
     } else {
         constexpr int TY = ConvTile<CI, CO>::TY, TZ = ConvTile<CI, CO>::TZ;
         const long long tiles = static_cast<long long>((W + 15) / 16) * ((H + TY - 1) / TY) *
                                 ((D + TZ - 1) / TZ);
-        hipLaunchKernelGGL((conv3_tile_kernel<CI, CO, F32, RELU, ACC>),
-                           dim3(static_cast<unsigned>(tiles)), dim3(NT), 0, s, ip, in_cs, in_off,
-                           wp, bias, out, out_cs, out_off, D, H, W, out_vec);
+        const dim3 grid(static_cast<unsigned>(tiles));
+        if (two_in) {
+            if constexpr (cat_shape<CI, CO>())
+                hipLaunchKernelGGL((conv3_tile_kernel<CI, CO, F32, RELU, ACC, true>), grid,
+                                   dim3(NT), 0, s, ip, in_cs, in_off, wp, bias, out, out_cs,
+                                   out_off, D, H, W, out_vec, cat);
+            else
+                return hipErrorInvalidValue;
+        } else {
+            hipLaunchKernelGGL((conv3_tile_kernel<CI, CO, F32, RELU, ACC, false>), grid, dim3(NT),
+                               0, s, ip, in_cs, in_off, wp, bias, out, out_cs, out_off, D, H, W,
+                               out_vec, cat);
+        }
     }
+    return hipGetLastError();
 }
 
 template <int CI, int CO>
-void conv3_pick(bool relu, bool acc, bool f32, dim3 grid, dim3 blk, hipStream_t s, const u16 *ip,
-                int in_cs, int in_off, const u16 *wp, const float *bias, void *out, int out_cs,
-                int out_off, int D, int H, int W) {
+hipError_t conv3_pick(bool relu, bool acc, bool f32, hipStream_t s, const u16 *ip, int in_cs,
+                      int in_off, const u16 *wp, const float *bias, void *out, int out_cs,
+                      int out_off, int D, int H, int W, const CatArgs &cat) {
     const int k = (f32 ? 4 : 0) | (relu ? 2 : 0) | (acc ? 1 : 0);
-#define GO(F, R, A) conv3_go<CI, CO, F, R, A>(grid, blk, s, ip, in_cs, in_off, wp, bias, out, out_cs, out_off, D, H, W)
+#define GO(F, R, A) \
+    return conv3_go<CI, CO, F, R, A>(s, ip, in_cs, in_off, wp, bias, out, out_cs, out_off, D, H, W, cat)
     switch (k) {
-        case 0: GO(false, false, false); break;
-        case 1: GO(false, false, true); break;
-        case 2: GO(false, true, false); break;
-        case 3: GO(false, true, true); break;
-        case 4: GO(true, false, false); break;
-        case 5: GO(true, false, true); break;
-        case 6: GO(true, true, false); break;
-        default: GO(true, true, true); break;
+        case 0: GO(false, false, false);
+        case 1: GO(false, false, true);
+        case 2: GO(false, true, false);
+        case 3: GO(false, true, true);
+        case 4: GO(true, false, false);
+        case 5: GO(true, false, true);
+        case 6: GO(true, true, false);
+        default: GO(true, true, true);
     }
 #undef GO
 }
 
-hipError_t launch_conv3(const void *in, int in_cs, int in_off, int cin, const void *wt,
-                        const float *bias, void *out, int out_cs, int out_off, int cout, int D,
-                        int H, int W, bool relu, bool acc, bool out_f32, hipStream_t s) {
-    const long long nvox = static_cast<long long>(D) * H * W;
-    const dim3 grid(blocks_for(nvox, NT)), blk(NT);
+hipError_t launch_conv3(const void *in, int in_cs, int in_off, int cin_a, const void *in2,
+                        int in2_cs, int in2_off, int cin_b, const void *wt, const float *bias,
+                        void *out, int out_cs, int out_off, int cout_a, void *out2, int out2_cs,
+                        int out2_off, int cout_b, int D, int H, int W, bool relu, bool acc,
+                        bool out_f32, hipStream_t s) {
+    const int cin = cin_a + cin_b, cout = cout_a + cout_b;
     const u16 *ip = static_cast<const u16 *>(in);
     const u16 *wp = static_cast<const u16 *>(wt);
+    CatArgs cat;
+    cat.in2 = cin_b > 0 ? static_cast<const u16 *>(in2) : ip;
+    cat.in2_cs = cin_b > 0 ? in2_cs : in_cs;
+    cat.in2_off = cin_b > 0 ? in2_off : in_off + cin_a;
+    cat.ksplit = cin_a;
+    cat.out2 = cout_b > 0 ? out2 : out;
+    cat.out2_cs = cout_b > 0 ? out2_cs : out_cs;
+    cat.out2_off = cout_b > 0 ? out2_off : out_off + cout_a;
+    cat.nsplit = cout_a;
+    if (cin_a <= 0 || cout_a <= 0 || cout_a % 16 != 0 || (cin_b > 0 && cin_a % 8 != 0))
+        return hipErrorInvalidValue;
 #define CASE(CI, CO)                                                                             \
-    if (cin == CI && cout == CO) {                                                               \
-        conv3_pick<CI, CO>(relu, acc, out_f32, grid, blk, s, ip, in_cs, in_off, wp, bias, out,   \
-                           out_cs, out_off, D, H, W);                                            \
-        return hipGetLastError();                                                                \
-    }
-    CASE(1, 16)
+    if (cin == CI && cout == CO)                                                                 \
+        return conv3_pick<CI, CO>(relu, acc, out_f32, s, ip, in_cs, in_off, wp, bias, out, out_cs, \
+                                  out_off, D, H, W, cat);
+    if (cin == 1 && cout == 16)
+        return conv3_pick<1, 16>(relu, acc, out_f32, s, ip, in_cs, in_off, wp, bias, out, out_cs,
+                                 out_off, D, H, W, cat);
     CASE(16, 16)
     CASE(16, 32)
     CASE(32, 16)
@@ -1241,15 +1304,17 @@ size_t conv3_wgrad_scratch(int cin, int cout, long long nvox) {
     return sizeof(float) * static_cast<size_t>(chunks) * 27 * cin * cout;
 }
 
-hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin, const void *dout,
-                              int dout_cs, int dout_off, int cout, int D, int H, int W, float *dw,
+hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin_a, const void *in2,
+                              int in2_cs, int in2_off, int cin_b, const void *dout, int dout_cs,
+                              int dout_off, int cout, int D, int H, int W, float *dw,
                               float *scratch, hipStream_t s) {
+    const int cin = cin_a + cin_b;
     const long long nvox = static_cast<long long>(D) * H * W;
     const long long chunk = wgrad_chunk(nvox);
     const int chunks = static_cast<int>((nvox + chunk - 1) / chunk);
     const u16 *ip = static_cast<const u16 *>(in), *dp = static_cast<const u16 *>(dout);
     if (cin == 1) {
-        if (cout != 16) return hipErrorInvalidValue;
+        if (cout != 16 || cin_b != 0) return hipErrorInvalidValue;
         const long long c1 = wgrad_c1_chunk(nvox);
         const int n1 = static_cast<int>((nvox + c1 - 1) / c1);
         hipLaunchKernelGGL((conv3_wgrad_c1_kernel<16>), dim3(n1), dim3(64), 0, s, ip, in_cs,
@@ -1258,13 +1323,15 @@ hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin, co
         if (e != hipSuccess) return e;
         return launch_reduce_wgrad(scratch, n1, 27, cout, 1, 0, 0, cout, 1, 0, dw, s);
     }
-    if ((cin != 16 && cin != 32 && cin != 64) || (cout != 16 && cout != 32 && cout != 64))
+    const auto chan_ok = [](int c) { return c == 16 || c == 32 || c == 64; };
+    if (!chan_ok(cin_a) || (cin_b != 0 && !chan_ok(cin_b)) || cin > 64 || !chan_ok(cout))
         return hipErrorInvalidValue;
     // Units: 32 x 4 voxel columns over runs of z planes, at most `chunks`
-    // workgroups (each loops over its units).  64 channels are split into
-    // 32-channel blocks, each a tiled GEMM of its own writing its partials
-    // after the previous block's; the scratch (chunks x 27 x cin x cout
-    // floats) holds them all.
+    // workgroups (each loops over its units).  The input channels (of one
+    // tensor or of a two-tensor concatenation) and 64 output channels are
+    // split into blocks of at most 32, each a tiled GEMM of its own writing
+    // its partials after the previous block's; the scratch (chunks x 27 x cin
+    // x cout floats) holds them all.
     const long long tiles = static_cast<long long>((W + WG_X - 1) / WG_X) * ((H + WG_Y - 1) / WG_Y);
     long long zsegs = chunks / tiles;
     if (zsegs < 1) zsegs = 1;
@@ -1272,26 +1339,36 @@ hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin, co
     const int zseg = static_cast<int>((D + zsegs - 1) / zsegs);
     const long long units = tiles * ((D + zseg - 1) / zseg);
     const int parts = static_cast<int>(units < chunks ? units : chunks);
-    const int cib = cin < 32 ? cin : 32, cob = cout < 32 ? cout : 32;
+    const int cob = cout < 32 ? cout : 32;
+    struct Source {
+        const u16 *p;
+        int cs, off, c, ci0;
+    };
+    const Source src[2] = {{ip, in_cs, in_off, cin_a, 0},
+                           {static_cast<const u16 *>(in2), in2_cs, in2_off, cin_b, cin_a}};
     float *part = scratch;
     for (int co0 = 0; co0 < cout; co0 += cob)
-        for (int ci0 = 0; ci0 < cin; ci0 += cib) {
+        for (const Source &sc : src) {
+            const int cib = sc.c < 32 ? sc.c : 32;
+            for (int l = 0; l < sc.c; l += cib) {
 #define CTREX_NN_WGT(CI, CO)                                                                      \
-            if (cib == CI && cob == CO)                                                           \
-                hipLaunchKernelGGL((wgrad_tile_kernel<CI, CO>), dim3(parts), dim3(WG_THREADS), 0, \
-                                   s, ip, in_cs, in_off + ci0, dp, dout_cs, dout_off + co0, D, H, \
-                                   W, zseg, static_cast<int>(units), part);
-            CTREX_NN_WGT(16, 16)
-            CTREX_NN_WGT(16, 32)
-            CTREX_NN_WGT(32, 16)
-            CTREX_NN_WGT(32, 32)
+                if (cib == CI && cob == CO)                                                       \
+                    hipLaunchKernelGGL((wgrad_tile_kernel<CI, CO>), dim3(parts),                  \
+                                       dim3(WG_THREADS), 0, s, sc.p, sc.cs, sc.off + l, dp,       \
+                                       dout_cs, dout_off + co0, D, H, W, zseg,                    \
+                                       static_cast<int>(units), part);
+                CTREX_NN_WGT(16, 16)
+                CTREX_NN_WGT(16, 32)
+                CTREX_NN_WGT(32, 16)
+                CTREX_NN_WGT(32, 32)
 #undef CTREX_NN_WGT
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-            const int n = 27 * cob * cib;
-            e = launch_reduce_wgrad(part, parts, 27, cob, cib, co0, ci0, cout, cin, 0, dw, s);
-            if (e != hipSuccess) return e;
-            part += static_cast<long long>(parts) * n;
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+                e = launch_reduce_wgrad(part, parts, 27, cob, cib, co0, sc.ci0 + l, cout, cin, 0,
+                                        dw, s);
+                if (e != hipSuccess) return e;
+                part += static_cast<long long>(parts) * 27 * cob * cib;
+            }
         }
     return hipSuccess;
 }

@@ -11,12 +11,15 @@
 
 namespace ctrex {
 namespace nn {
-hipError_t launch_conv3(const void *in, int in_cs, int in_off, int cin, const void *wt,
-                        const float *bias, void *out, int out_cs, int out_off, int cout, int D,
-                        int H, int W, bool relu, bool acc, bool out_f32, hipStream_t s);
+hipError_t launch_conv3(const void *in, int in_cs, int in_off, int cin_a, const void *in2,
+                        int in2_cs, int in2_off, int cin_b, const void *wt, const float *bias,
+                        void *out, int out_cs, int out_off, int cout_a, void *out2, int out2_cs,
+                        int out2_off, int cout_b, int D, int H, int W, bool relu, bool acc,
+                        bool out_f32, hipStream_t s);
 size_t conv3_wgrad_scratch(int cin, int cout, long long nvox);
-hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin, const void *dout,
-                              int dout_cs, int dout_off, int cout, int D, int H, int W, float *dw,
+hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin_a, const void *in2,
+                              int in2_cs, int in2_off, int cin_b, const void *dout, int dout_cs,
+                              int dout_off, int cout, int D, int H, int W, float *dw,
                               float *scratch, hipStream_t s);
 size_t channel_sum_scratch(int c);
 hipError_t launch_channel_sum(const void *x, int cs, int off, int c, long long nvox, float *out,
@@ -104,8 +107,40 @@ int ctrex_nn_conv3(ctrex_ctx *c, const void *in, int32_t in_cs, int32_t in_off, 
     if ((st = check_slice(c, "in", in, in_cs, in_off, cin, cin > 1))) return st;
     if ((st = check_slice(c, "out", out, out_cs, out_off, cout, false))) return st;
     if (!wt) return fail(c, CTREX_EINVAL, "wt is NULL");
-    CTREX_HIP(c, nn::launch_conv3(in, in_cs, in_off, cin, wt, bias, out, out_cs, out_off, cout, D,
-                                  H, W, flags & CTREX_NN_RELU, flags & CTREX_NN_ACCUMULATE,
+    CTREX_HIP(c, nn::launch_conv3(in, in_cs, in_off, cin, nullptr, 0, 0, 0, wt, bias, out, out_cs,
+                                  out_off, cout, nullptr, 0, 0, 0, D, H, W, flags & CTREX_NN_RELU,
+                                  flags & CTREX_NN_ACCUMULATE, flags & CTREX_NN_OUT_F32,
+                                  static_cast<hipStream_t>(stream)));
+    return CTREX_OK;
+}
+
+int ctrex_nn_conv3_cat(ctrex_ctx *c, const void *in_a, int32_t a_cs, int32_t a_off, int32_t ca,
+                       const void *in_b, int32_t b_cs, int32_t b_off, int32_t cb, const void *wt,
+                       const float *bias, void *out_a, int32_t oa_cs, int32_t oa_off, int32_t oa,
+                       void *out_b, int32_t ob_cs, int32_t ob_off, int32_t ob, int32_t D,
+                       int32_t H, int32_t W, uint32_t flags, void *stream) {
+    int st = begin(c);
+    if (st) return st;
+    const int cin = ca + cb, cout = oa + ob;
+    if (ca < 1 || cb < 0 || oa < 1 || ob < 0 || !(cin == 1 || chan_ok(cin)) || !chan_ok(cout))
+        return fail(c, CTREX_ESHAPE, "unsupported channels %d + %d -> %d + %d", ca, cb, oa, ob);
+    if (cb > 0 && !((cin == 32 && cout == 16) || (cin == 64 && cout == 32)) )
+        return fail(c, CTREX_ESHAPE, "a two-tensor input needs 32 -> 16 or 64 -> 32 channels");
+    if (cb > 0 && ca % 8)
+        return fail(c, CTREX_ESHAPE, "the first input's channel count must be a multiple of 8");
+    if (ob > 0 && (oa % 16 || cin == 1))
+        return fail(c, CTREX_ESHAPE, "a two-tensor output needs cin >= 16 and oa a multiple of 16");
+    if (flags & ~(CTREX_NN_RELU | CTREX_NN_ACCUMULATE | CTREX_NN_OUT_F32))
+        return fail(c, CTREX_EINVAL, "unknown flags");
+    if ((st = check_vol(c, D, H, W, false))) return st;
+    if ((st = check_slice(c, "in_a", in_a, a_cs, a_off, ca, cin > 1))) return st;
+    if (cb > 0 && (st = check_slice(c, "in_b", in_b, b_cs, b_off, cb, true))) return st;
+    if ((st = check_slice(c, "out_a", out_a, oa_cs, oa_off, oa, false))) return st;
+    if (ob > 0 && (st = check_slice(c, "out_b", out_b, ob_cs, ob_off, ob, false))) return st;
+    if (!wt) return fail(c, CTREX_EINVAL, "wt is NULL");
+    CTREX_HIP(c, nn::launch_conv3(in_a, a_cs, a_off, ca, in_b, b_cs, b_off, cb, wt, bias, out_a,
+                                  oa_cs, oa_off, oa, out_b, ob_cs, ob_off, ob, D, H, W,
+                                  flags & CTREX_NN_RELU, flags & CTREX_NN_ACCUMULATE,
                                   flags & CTREX_NN_OUT_F32, static_cast<hipStream_t>(stream)));
     return CTREX_OK;
 }
@@ -138,8 +173,36 @@ int ctrex_nn_conv3_wgrad(ctrex_ctx *c, const void *in, int32_t in_cs, int32_t in
     void *scr;
     if ((st = ctx_scratch(c, need, &scr))) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    CTREX_HIP(c, nn::launch_conv3_wgrad(in, in_cs, in_off, cin, dout, dout_cs, dout_off, cout, D, H,
-                                        W, dw, static_cast<float *>(scr), s));
+    CTREX_HIP(c, nn::launch_conv3_wgrad(in, in_cs, in_off, cin, nullptr, 0, 0, 0, dout, dout_cs,
+                                        dout_off, cout, D, H, W, dw, static_cast<float *>(scr), s));
+    if (dbias)
+        CTREX_HIP(c, nn::launch_channel_sum(dout, dout_cs, dout_off, cout, n, dbias,
+                                            static_cast<double *>(scr), s));
+    return CTREX_OK;
+}
+
+int ctrex_nn_conv3_wgrad_cat(ctrex_ctx *c, const void *in_a, int32_t a_cs, int32_t a_off,
+                             int32_t ca, const void *in_b, int32_t b_cs, int32_t b_off, int32_t cb,
+                             const void *dout, int32_t dout_cs, int32_t dout_off, int32_t cout,
+                             int32_t D, int32_t H, int32_t W, float *dw, float *dbias,
+                             void *stream) {
+    int st = begin(c);
+    if (st) return st;
+    const int cin = ca + cb;
+    if (!chan_ok(ca) || !(cb == 0 || chan_ok(cb)) || cin > 64 || !chan_ok(cout))
+        return fail(c, CTREX_ESHAPE, "unsupported channels %d + %d -> %d", ca, cb, cout);
+    if ((st = check_vol(c, D, H, W, false))) return st;
+    if ((st = check_slice(c, "in_a", in_a, a_cs, a_off, ca, true))) return st;
+    if (cb > 0 && (st = check_slice(c, "in_b", in_b, b_cs, b_off, cb, true))) return st;
+    if ((st = check_slice(c, "dout", dout, dout_cs, dout_off, cout, true))) return st;
+    if (!dw) return fail(c, CTREX_EINVAL, "dw is NULL");
+    const long long n = static_cast<long long>(D) * H * W;
+    const size_t need = std::max(nn::conv3_wgrad_scratch(cin, cout, n), nn::channel_sum_scratch(cout));
+    void *scr;
+    if ((st = ctx_scratch(c, need, &scr))) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    CTREX_HIP(c, nn::launch_conv3_wgrad(in_a, a_cs, a_off, ca, in_b, b_cs, b_off, cb, dout, dout_cs,
+                                        dout_off, cout, D, H, W, dw, static_cast<float *>(scr), s));
     if (dbias)
         CTREX_HIP(c, nn::launch_channel_sum(dout, dout_cs, dout_off, cout, n, dbias,
                                             static_cast<double *>(scr), s));

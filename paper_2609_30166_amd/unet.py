@@ -208,12 +208,14 @@ class UNet:
         def t(n, c):
             return torch.empty(n * c, dtype=torch.bfloat16, device=self.device)
 
-        b = dict(xb=t(n1, 1), a1=t(n1, 16), cat1=t(n1, 32), a5=t(n1, 16), d1=t(n1, 16),
-                 p1=t(n2, 16), a2=t(n2, 32), cat2=t(n2, 64), a4=t(n2, 32), d2=t(n2, 32),
-                 p2=t(n3, 32), a3=t(n3, 64), b3=t(n3, 64))
+        # the skip concatenations [u | e] are never stored: the decoder's first
+        # convolution reads u and e, and its data gradient writes gu and ge
+        b = dict(xb=t(n1, 1), a1=t(n1, 16), e1=t(n1, 16), u1=t(n1, 16), a5=t(n1, 16),
+                 d1=t(n1, 16), p1=t(n2, 16), a2=t(n2, 32), e2=t(n2, 32), u2=t(n2, 32),
+                 a4=t(n2, 32), d2=t(n2, 32), p2=t(n3, 32), a3=t(n3, 64), b3=t(n3, 64))
         if train:
-            b.update(g1a=t(n1, 16), g1b=t(n1, 16), gcat1=t(n1, 32),
-                     g2a=t(n2, 32), g2b=t(n2, 32), gcat2=t(n2, 64), gp1=t(n2, 16),
+            b.update(g1a=t(n1, 16), g1b=t(n1, 16), gu1=t(n1, 16), ge1=t(n1, 16),
+                     g2a=t(n2, 32), g2b=t(n2, 32), gu2=t(n2, 32), ge2=t(n2, 32), gp1=t(n2, 16),
                      g3a=t(n3, 64), g3b=t(n3, 64), gp2=t(n3, 32),
                      dout=torch.empty(n1, dtype=torch.float32, device=self.device))
         # inference and training share nothing; keep the most recent of each
@@ -262,6 +264,15 @@ class UNet:
                    _vp(self.p(name + ".b")), _vp(dst), d_cs, d_off, cout, D, H, W,
                    _lib.NN_RELU if relu else 0, self._s())
 
+    def _conv_cat(self, name, ua, ea, dst, dims):
+        """Decoder convolution of the concatenation [ua | ea] (equal halves)."""
+        kind, cin, cout = _KIND[name]
+        D, H, W = dims
+        h = cin // 2
+        self._call("ctrex_nn_conv3_cat", _vp(ua), h, 0, h, _vp(ea), h, 0, h,
+                   _vp(self._wt[name]), _vp(self.p(name + ".b")), _vp(dst), cout, 0, cout, None,
+                   0, 0, 0, D, H, W, _lib.NN_RELU, self._s())
+
     def _up(self, name, src, dst, d_cs, d_off, dims):
         kind, cin, cout = _KIND[name]
         D, H, W = dims
@@ -286,18 +297,18 @@ class UNet:
         n1 = D * H * W
         self._call("ctrex_nn_input", _vp(x), self.scale, _vp(b["xb"]), n1, self._s())
         self._conv("e1a", b["xb"], 1, 0, b["a1"], 16, 0, l1)
-        self._conv("e1b", b["a1"], 16, 0, b["cat1"], 32, 16, l1)
-        self._pool(b["cat1"], 32, 16, 16, b["p1"], l1)
+        self._conv("e1b", b["a1"], 16, 0, b["e1"], 16, 0, l1)
+        self._pool(b["e1"], 16, 0, 16, b["p1"], l1)
         self._conv("e2a", b["p1"], 16, 0, b["a2"], 32, 0, l2)
-        self._conv("e2b", b["a2"], 32, 0, b["cat2"], 64, 32, l2)
-        self._pool(b["cat2"], 64, 32, 32, b["p2"], l2)
+        self._conv("e2b", b["a2"], 32, 0, b["e2"], 32, 0, l2)
+        self._pool(b["e2"], 32, 0, 32, b["p2"], l2)
         self._conv("bna", b["p2"], 32, 0, b["a3"], 64, 0, l3)
         self._conv("bnb", b["a3"], 64, 0, b["b3"], 64, 0, l3)
-        self._up("up2", b["b3"], b["cat2"], 64, 0, l3)
-        self._conv("d2a", b["cat2"], 64, 0, b["a4"], 32, 0, l2)
+        self._up("up2", b["b3"], b["u2"], 32, 0, l3)
+        self._conv_cat("d2a", b["u2"], b["e2"], b["a4"], l2)
         self._conv("d2b", b["a4"], 32, 0, b["d2"], 32, 0, l2)
-        self._up("up1", b["d2"], b["cat1"], 32, 0, l2)
-        self._conv("d1a", b["cat1"], 32, 0, b["a5"], 16, 0, l1)
+        self._up("up1", b["d2"], b["u1"], 16, 0, l2)
+        self._conv_cat("d1a", b["u1"], b["e1"], b["a5"], l1)
         self._conv("d1b", b["a5"], 16, 0, b["d1"], 16, 0, l1)
         if out is None:
             out = torch.empty_like(x)
@@ -314,9 +325,9 @@ class UNet:
         D, H, W = x.shape
         b = self._buffers((D, H, W), False)
         dims = {1: (D, H, W), 2: (D // 2, H // 2, W // 2), 3: (D // 4, H // 4, W // 4)}
-        lay = dict(xb=(1, 1), a1=(1, 16), cat1=(1, 32), a5=(1, 16), d1=(1, 16), p1=(2, 16),
-                   a2=(2, 32), cat2=(2, 64), a4=(2, 32), d2=(2, 32), p2=(3, 32), a3=(3, 64),
-                   b3=(3, 64))
+        lay = dict(xb=(1, 1), a1=(1, 16), e1=(1, 16), u1=(1, 16), a5=(1, 16), d1=(1, 16),
+                   p1=(2, 16), a2=(2, 32), e2=(2, 32), u2=(2, 32), a4=(2, 32), d2=(2, 32),
+                   p2=(3, 32), a3=(3, 64), b3=(3, 64))
         return {k: b[k].view(*dims[lv], c) for k, (lv, c) in lay.items()}
 
     # ------------------------------------------------------------- backward
@@ -329,6 +340,24 @@ class UNet:
         fn = "ctrex_nn_conv3_wgrad" if kind == "conv" else "ctrex_nn_upconv2_wgrad"
         self._call(fn, _vp(src), s_cs, s_off, cin, _vp(dout), d_cs, d_off, cout, D, H, W,
                    _vp(self.p(name + ".w", self.grad)), _vp(self.p(name + ".b", self.grad)),
+                   self._s())
+
+    def _wgrad_cat(self, name, ua, ea, dout, d_cs, dims):
+        kind, cin, cout = _KIND[name]
+        D, H, W = dims
+        h = cin // 2
+        self._call("ctrex_nn_conv3_wgrad_cat", _vp(ua), h, 0, h, _vp(ea), h, 0, h, _vp(dout),
+                   d_cs, 0, cout, D, H, W, _vp(self.p(name + ".w", self.grad)),
+                   _vp(self.p(name + ".b", self.grad)), self._s())
+
+    def _dgrad_cat(self, name, dout, d_cs, gu, ge, dims):
+        """Data gradient of a decoder convolution, split into the gradients of
+        its two inputs (the up-sampled and the skip features)."""
+        kind, cin, cout = _KIND[name]
+        D, H, W = dims
+        h = cin // 2
+        self._call("ctrex_nn_conv3_cat", _vp(dout), d_cs, 0, cout, None, 0, 0, 0,
+                   _vp(self._wd[name]), None, _vp(gu), h, 0, h, _vp(ge), h, 0, h, D, H, W, 0,
                    self._s())
 
     def _dgrad(self, name, dout, d_cs, d_off, dst, o_cs, o_off, dims):
@@ -357,21 +386,21 @@ class UNet:
         self._wgrad("d1b", b["a5"], 16, 0, b["g1a"], 16, 0, l1)
         self._dgrad("d1b", b["g1a"], 16, 0, b["g1b"], 16, 0, l1)
         self._relu_bwd(b["a5"], b["g1b"], 16, 0, 16, n1)
-        self._wgrad("d1a", b["cat1"], 32, 0, b["g1b"], 16, 0, l1)
-        self._dgrad("d1a", b["g1b"], 16, 0, b["gcat1"], 32, 0, l1)
+        self._wgrad_cat("d1a", b["u1"], b["e1"], b["g1b"], 16, l1)
+        self._dgrad_cat("d1a", b["g1b"], 16, b["gu1"], b["ge1"], l1)
         # up-sampling 1 and decoder level 2
-        self._wgrad("up1", b["d2"], 32, 0, b["gcat1"], 32, 0, l2)
-        self._call("ctrex_nn_upconv2_dgrad", _vp(b["gcat1"]), 32, 0, 16, _vp(self._wd["up1"]),
+        self._wgrad("up1", b["d2"], 32, 0, b["gu1"], 16, 0, l2)
+        self._call("ctrex_nn_upconv2_dgrad", _vp(b["gu1"]), 16, 0, 16, _vp(self._wd["up1"]),
                    _vp(b["g2a"]), 32, 0, 32, l2[0], l2[1], l2[2], 0, self._s())
         self._relu_bwd(b["d2"], b["g2a"], 32, 0, 32, n2)
         self._wgrad("d2b", b["a4"], 32, 0, b["g2a"], 32, 0, l2)
         self._dgrad("d2b", b["g2a"], 32, 0, b["g2b"], 32, 0, l2)
         self._relu_bwd(b["a4"], b["g2b"], 32, 0, 32, n2)
-        self._wgrad("d2a", b["cat2"], 64, 0, b["g2b"], 32, 0, l2)
-        self._dgrad("d2a", b["g2b"], 32, 0, b["gcat2"], 64, 0, l2)
+        self._wgrad_cat("d2a", b["u2"], b["e2"], b["g2b"], 32, l2)
+        self._dgrad_cat("d2a", b["g2b"], 32, b["gu2"], b["ge2"], l2)
         # up-sampling 2 and the bottom level
-        self._wgrad("up2", b["b3"], 64, 0, b["gcat2"], 64, 0, l3)
-        self._call("ctrex_nn_upconv2_dgrad", _vp(b["gcat2"]), 64, 0, 32, _vp(self._wd["up2"]),
+        self._wgrad("up2", b["b3"], 64, 0, b["gu2"], 32, 0, l3)
+        self._call("ctrex_nn_upconv2_dgrad", _vp(b["gu2"]), 32, 0, 32, _vp(self._wd["up2"]),
                    _vp(b["g3a"]), 64, 0, 64, l3[0], l3[1], l3[2], 0, self._s())
         self._relu_bwd(b["b3"], b["g3a"], 64, 0, 64, n3)
         self._wgrad("bnb", b["a3"], 64, 0, b["g3a"], 64, 0, l3)
@@ -380,20 +409,20 @@ class UNet:
         self._wgrad("bna", b["p2"], 32, 0, b["g3b"], 64, 0, l3)
         self._dgrad("bna", b["g3b"], 64, 0, b["gp2"], 32, 0, l3)
         # encoder level 2: pooled gradient joins the skip gradient in place
-        self._call("ctrex_nn_maxpool2_backward", _vp(b["cat2"]), 64, 32, 32, _vp(b["gp2"]),
-                   _vp(b["gcat2"]), l2[0], l2[1], l2[2], self._s())
-        self._relu_bwd(b["cat2"], b["gcat2"], 64, 32, 32, n2)
-        self._wgrad("e2b", b["a2"], 32, 0, b["gcat2"], 64, 32, l2)
-        self._dgrad("e2b", b["gcat2"], 64, 32, b["g2a"], 32, 0, l2)
+        self._call("ctrex_nn_maxpool2_backward", _vp(b["e2"]), 32, 0, 32, _vp(b["gp2"]),
+                   _vp(b["ge2"]), l2[0], l2[1], l2[2], self._s())
+        self._relu_bwd(b["e2"], b["ge2"], 32, 0, 32, n2)
+        self._wgrad("e2b", b["a2"], 32, 0, b["ge2"], 32, 0, l2)
+        self._dgrad("e2b", b["ge2"], 32, 0, b["g2a"], 32, 0, l2)
         self._relu_bwd(b["a2"], b["g2a"], 32, 0, 32, n2)
         self._wgrad("e2a", b["p1"], 16, 0, b["g2a"], 32, 0, l2)
         self._dgrad("e2a", b["g2a"], 32, 0, b["gp1"], 16, 0, l2)
         # encoder level 1
-        self._call("ctrex_nn_maxpool2_backward", _vp(b["cat1"]), 32, 16, 16, _vp(b["gp1"]),
-                   _vp(b["gcat1"]), l1[0], l1[1], l1[2], self._s())
-        self._relu_bwd(b["cat1"], b["gcat1"], 32, 16, 16, n1)
-        self._wgrad("e1b", b["a1"], 16, 0, b["gcat1"], 32, 16, l1)
-        self._dgrad("e1b", b["gcat1"], 32, 16, b["g1a"], 16, 0, l1)
+        self._call("ctrex_nn_maxpool2_backward", _vp(b["e1"]), 16, 0, 16, _vp(b["gp1"]),
+                   _vp(b["ge1"]), l1[0], l1[1], l1[2], self._s())
+        self._relu_bwd(b["e1"], b["ge1"], 16, 0, 16, n1)
+        self._wgrad("e1b", b["a1"], 16, 0, b["ge1"], 16, 0, l1)
+        self._dgrad("e1b", b["ge1"], 16, 0, b["g1a"], 16, 0, l1)
         self._relu_bwd(b["a1"], b["g1a"], 16, 0, 16, n1)
         self._wgrad("e1a", b["xb"], 1, 0, b["g1a"], 16, 0, l1)
         return self.grad

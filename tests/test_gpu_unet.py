@@ -235,6 +235,104 @@ def test_conv3_weight_gradient_on_slices(L, ctx, cin, cout, xs, xo, gs, go):
     _close(_host(dw).reshape(cout, cin, 27), w.grad.numpy())
 
 
+# ------------------------------------------- convolution over a concatenation --
+@pytest.mark.parametrize("shape", [(4, 8, 8), (4, 6, 24), (2, 16, 40)])
+@pytest.mark.parametrize("cin,cout", [(32, 16), (64, 32)])
+def test_conv3_cat_two_inputs(L, ctx, shape, cin, cout):
+    """A decoder convolution reading [a | b] from two tensors equals the
+    convolution of the stored concatenation (the oracle), here with both
+    inputs slices of wider tensors and the output a slice of another."""
+    from oracle import unet as ou
+    n = int(np.prod(shape))
+    h = cin // 2
+    r = _rng(41, cin, *shape)
+    aw = _bf(r.normal(size=(n, h + 8)))
+    bw = _bf(r.normal(size=(n, h + 16)))
+    xa, xb = aw[:, 8:8 + h], bw[:, 16:16 + h]
+    w = r.normal(0, 0.1, size=(cout, cin, 27))
+    b = r.normal(size=cout).astype(np.float32).astype(np.float64)
+    wt, _ = _pack_conv(L, ctx, w)
+    out = torch.zeros(n * (cout + 4), dtype=torch.float32, device=DEV)
+    ad, bd_, biasd = _dev_bf(aw), _dev_bf(bw), _dev_f(b)
+    _call(L, ctx, "ctrex_nn_conv3_cat", _vp(ad), h + 8, 8, h, _vp(bd_), h + 16, 16, h, _vp(wt),
+          _vp(biasd), _vp(out), cout + 4, 4, cout, None, 0, 0, 0, *shape,
+          L.NN_RELU | L.NN_OUT_F32, None)
+    x = np.concatenate([xa, xb], axis=1).reshape(shape + (cin,))
+    ref = np.maximum(ou.conv3(torch.tensor(x), torch.tensor(_bf(w)), torch.tensor(b)).numpy(), 0)
+    got = _host(out).reshape(n, cout + 4)
+    assert np.all(got[:, :4] == 0)   # channels before the slice untouched
+    _close(got[:, 4:].reshape(shape + (cout,)), ref)
+
+
+@pytest.mark.parametrize("cin,cout", [(16, 32), (32, 64)])
+def test_conv3_cat_two_outputs_data_gradient(L, ctx, cin, cout):
+    """The data gradient of a decoder convolution (cin = the concatenation's
+    width) written as its two halves into two tensors."""
+    from oracle import unet as ou
+    shape = (4, 12, 20)
+    n = int(np.prod(shape))
+    r = _rng(42, cin, cout)
+    x = torch.tensor(_bf(r.normal(size=shape + (cout,))), requires_grad=True)
+    w = _bf(r.normal(0, 0.1, size=(cin, cout, 27)))   # forward: cout -> cin channels
+    g = _bf(r.normal(size=shape + (cin,)))
+    (ou.conv3(x, torch.tensor(w)) * torch.tensor(g)).sum().backward()
+    _, wd = _pack_conv(L, ctx, w)
+    gd = _dev_bf(g)
+    h = cout // 2
+    ga = torch.empty(n * h, dtype=torch.float32, device=DEV)
+    gb = torch.full((n * (h + 8),), 5.0, dtype=torch.float32, device=DEV)
+    _call(L, ctx, "ctrex_nn_conv3_cat", _vp(gd), cin, 0, cin, None, 0, 0, 0, _vp(wd), None,
+          _vp(ga), h, 0, h, _vp(gb), h + 8, 8, h, *shape, L.NN_OUT_F32, None)
+    ref = x.grad.numpy().reshape(n, cout)
+    _close(_host(ga).reshape(n, h), ref[:, :h])
+    got_b = _host(gb).reshape(n, h + 8)
+    assert np.all(got_b[:, :8] == 5.0)   # channels before the slice untouched
+    _close(got_b[:, 8:], ref[:, h:])
+
+
+@pytest.mark.parametrize("ca,cout", [(16, 16), (32, 32)])
+def test_conv3_wgrad_cat(L, ctx, ca, cout):
+    """Weight and bias gradients of a convolution over [a | b] from the two
+    tensors equal those over the stored concatenation."""
+    from oracle import unet as ou
+    shape = (8, 8, 16)
+    n = int(np.prod(shape))
+    r = _rng(43, ca, cout)
+    xa, xb = _bf(r.normal(size=(n, ca))), _bf(r.normal(size=(n, ca + 8)))
+    g = _bf(r.normal(size=shape + (cout,)))
+    x = np.concatenate([xa, xb[:, 8:]], axis=1).reshape(shape + (2 * ca,))
+    w = torch.zeros((cout, 2 * ca, 27), dtype=torch.float64, requires_grad=True)
+    b = torch.zeros(cout, dtype=torch.float64, requires_grad=True)
+    (ou.conv3(torch.tensor(x), w, b) * torch.tensor(g)).sum().backward()
+    ad, bd_, gd = _dev_bf(xa), _dev_bf(xb), _dev_bf(g)
+    dw = torch.empty(cout * 2 * ca * 27, dtype=torch.float32, device=DEV)
+    db = torch.empty(cout, dtype=torch.float32, device=DEV)
+    _call(L, ctx, "ctrex_nn_conv3_wgrad_cat", _vp(ad), ca, 0, ca, _vp(bd_), ca + 8, 8, ca,
+          _vp(gd), cout, 0, cout, *shape, _vp(dw), _vp(db), None)
+    _close(_host(dw).reshape(cout, 2 * ca, 27), w.grad.numpy())
+    _close(_host(db), b.grad.numpy())
+
+
+def test_conv3_cat_rejects_unsupported_splits(L, ctx):
+    """Shapes outside the two-tensor forms return CTREX_ESHAPE before any launch."""
+    n = 64
+    a = torch.zeros(n * 64, dtype=torch.bfloat16, device=DEV)
+    o = torch.zeros(n * 64, dtype=torch.bfloat16, device=DEV)
+    wt = torch.zeros(27 * 64 * 64, dtype=torch.bfloat16, device=DEV)
+    bad = [
+        # two inputs for a shape other than 32 -> 16 / 64 -> 32
+        (16, 16, 32, 0),
+        # first input not a multiple of 8
+        (12, 20, 16, 0),
+        # output split not at a multiple of 16
+        (32, 0, 8, 8),
+    ]
+    for ca, cb, oa, ob in bad:
+        rc = L.lib().ctrex_nn_conv3_cat(ctx, _vp(a), 64, 0, ca, _vp(a), 64, 0, cb, _vp(wt), None,
+                                        _vp(o), 64, 0, oa, _vp(o), 64, 0, ob, 4, 4, 4, 0, None)
+        assert rc == -2, (ca, cb, oa, ob)   # CTREX_ESHAPE
+
+
 # --------------------------------------------------------------- upconv2 ----
 @pytest.mark.parametrize("shape", [(4, 4, 4), (4, 4, 12), (8, 8, 16)])
 @pytest.mark.parametrize("cin,cout", UP_PAIRS)
@@ -535,8 +633,10 @@ def test_network_forward_matches_oracle(shape, scale):
     for k_gpu, k_or in (("a1", "a1"), ("p2", "p2"), ("b3", "b3"), ("d1", "d1")):
         g, r = _host(acts[k_gpu]), tens[k_or].numpy()
         assert np.linalg.norm(g - r) <= 1e-2 * np.linalg.norm(r), k_gpu
-    cat1 = _host(acts["cat1"])
-    np.testing.assert_allclose(cat1[..., 16:], tens["e1"].numpy(), rtol=2e-2, atol=1e-2)
+    # the two halves of each skip concatenation, stored apart
+    for k in ("e1", "u1", "e2", "u2"):
+        np.testing.assert_allclose(_host(acts[k]), tens[k].numpy(), rtol=2e-2, atol=1e-2,
+                                   err_msg=k)
 
 
 @pytest.mark.parametrize("scale", [1.0, 256.0])
