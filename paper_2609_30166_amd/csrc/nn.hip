@@ -32,6 +32,7 @@ typedef uint16_t u16;
 
 constexpr int NT = 256;   // threads per workgroup (4 waves)
 constexpr int MB = 4;     // 16-voxel M blocks per wave (64 voxels)
+constexpr int C1_TY = 8, C1_TZ = 4;   // output rows (y) and planes (z) of a one-channel tile
 
 __device__ __forceinline__ float bf2f(u16 v) { return __uint_as_float(static_cast<uint32_t>(v) << 16); }
 __device__ __forceinline__ u16 f2bf(float v) {
@@ -67,8 +68,18 @@ struct Vox {
     int z, y, x;
 };
 
+// (z, y, x) of voxel v; below 2^32 voxels in 32-bit arithmetic (a 32-bit
+// division by a register costs a fraction of a 64-bit one).
 __device__ __forceinline__ Vox decode(long long v, int H, int W) {
     Vox r;
+    if (static_cast<unsigned long long>(v) <= 0xffffffffull) {
+        const uint32_t u = static_cast<uint32_t>(v), t = u / static_cast<uint32_t>(W);
+        r.x = static_cast<int>(u - t * static_cast<uint32_t>(W));
+        const uint32_t zq = t / static_cast<uint32_t>(H);
+        r.y = static_cast<int>(t - zq * static_cast<uint32_t>(H));
+        r.z = static_cast<int>(zq);
+        return r;
+    }
     r.x = static_cast<int>(v % W);
     const long long t = v / W;
     r.y = static_cast<int>(t % H);
@@ -129,53 +140,90 @@ __device__ __forceinline__ void store4(void *out, long long o, float (&v)[4], bo
 }
 
 // ------------------------------------------------------------ conv 3x3x3 ----
-// One input channel: K = the 27 taps (padded to 32) of one voxel, one K step.
-// A wave takes 64 consecutive voxels; the products are formed as weights x
-// inputs, so lane (g, r) ends with output channels n 16 + 4 g + j (j < 4) of
-// voxel m 16 + r, stored four at a time.
+// One input channel: K = the 27 taps (padded to 32) of one voxel, one K step,
+// LDS-tiled: a workgroup stages the 18 x 10 x 6 input
+// block around its 16 x 8 x 4 output voxels once (zeros outside the volume),
+// and each lane then reads its eight taps of a voxel from LDS at addresses
+// fixed for the whole kernel (the rows of a wave differ by a constant),
+// instead of gathering the 27 neighbours of every voxel from global memory
+// with 64-bit index arithmetic.  Lane (g, r) takes taps 8 g .. 8 g + 7 of
+// voxel r of each row; taps 27 .. 31 read a block of zeros.  Wave w owns z
+// plane w of the tile (8 rows of 16 voxels).
 template <int COUT, bool OUT_F32, bool RELU, bool ACC>
-__global__ __launch_bounds__(NT) void conv3_c1_kernel(const u16 *__restrict__ in, int in_cs,
-                                                      int in_off, const u16 *__restrict__ wt,
-                                                      const float *__restrict__ bias, void *out,
-                                                      int out_cs, int out_off, int D, int H, int W,
-                                                      int out_vec) {
+__global__ __launch_bounds__(NT) void conv3_c1_tile_kernel(const u16 *__restrict__ in, int in_cs,
+                                                           int in_off, const u16 *__restrict__ wt,
+                                                           const float *__restrict__ bias,
+                                                           void *out, int out_cs, int out_off,
+                                                           int D, int H, int W, int out_vec) {
+    constexpr int TY = C1_TY, TZ = C1_TZ, SX = 18, SY = TY + 2, SZ = TZ + 2;
+    constexpr int NEL = SX * SY * SZ;         // staged input values
+    constexpr int MBW = TY * TZ / (NT / 64);  // rows per wave
+    constexpr int NZ = MBW * SX;              // zero block after the tile
     constexpr int NB = COUT / 16;
-    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
-    const long long nvox = static_cast<long long>(D) * H * W;
-    const long long base = (static_cast<long long>(blockIdx.x) * (NT / 64) + (threadIdx.x >> 6)) * 64;
-    if (base >= nvox) return;   // whole wave (the voxel count is a multiple of 64)
-    Vox pa[MB];
+    static_assert(MBW == TY, "a wave owns one z plane of the tile");
+    __shared__ u16 tile[NEL + NZ];
+
+    const int ntx = (W + 15) / 16, nty = (H + TY - 1) / TY;
+    int bi = blockIdx.x;
+    const int x0 = (bi % ntx) * 16;
+    bi /= ntx;
+    const int y0 = (bi % nty) * TY, z0 = (bi / nty) * TZ;
+
+    // ---- stage: every load of the thread in flight before the LDS writes
+    constexpr int ITER = (NEL + NZ + NT - 1) / NT;
+    u16 v[ITER];
 #pragma unroll
-    for (int m = 0; m < MB; ++m) pa[m] = decode(base + m * 16 + r, H, W);
-    // k = 8 g + e is the tap
-    bf16x8 a[MB], b[NB];
+    for (int k = 0; k < ITER; ++k) {
+        const int i = threadIdx.x + k * NT;
+        const int x = i % SX, y = (i / SX) % SY, z = i / (SX * SY);
+        const int gx = x0 + x - 1, gy = y0 + y - 1, gz = z0 + z - 1;
+        v[k] = 0;
+        if (i < NEL && gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D)
+            v[k] = in[((static_cast<long long>(gz) * H + gy) * W + gx) * in_cs + in_off];
+    }
+#pragma unroll
+    for (int k = 0; k < ITER; ++k) {
+        const int i = threadIdx.x + k * NT;
+        if (i < NEL + NZ) tile[i] = v[k];
+    }
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    int addr[8];   // this lane's eight taps of row 0
+    bf16x8 b[NB];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int tap = 8 * g + e;
-#pragma unroll
-        for (int m = 0; m < MB; ++m) {
-            const long long q = tap < 27 ? nbr(pa[m], tap, D, H, W) : -1;
-            a[m][e] = q >= 0 ? as_bf(in[q * in_cs + in_off]) : static_cast<__bf16>(0.0f);
-        }
+        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+        addr[e] = tap < 27 ? ((wave + 1 + dz) * SY + 1 + dy) * SX + r + 1 + dx : NEL + r;
 #pragma unroll
         for (int n = 0; n < NB; ++n)
             b[n][e] = tap < 27 ? as_bf(wt[tap * COUT + n * 16 + r]) : static_cast<__bf16>(0.0f);
     }
+    float bco[NB][4];
+#pragma unroll
+    for (int n = 0; n < NB; ++n)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bco[n][j] = bias ? bias[n * 16 + 4 * g + j] : 0.0f;
+    __syncthreads();
+
     const f32x4 zero = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int gz = z0 + wave, gx = x0 + r;
 #pragma unroll
-    for (int n = 0; n < NB; ++n) {
-        const int co0 = n * 16 + 4 * g;
-        float bco[4];
+    for (int m = 0; m < MBW; ++m) {
+        bf16x8 a;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bco[j] = bias ? bias[co0 + j] : 0.0f;
+        for (int e = 0; e < 8; ++e) a[e] = as_bf(tile[addr[e] + m * SX]);
+        const int gy = y0 + m;
 #pragma unroll
-        for (int m = 0; m < MB; ++m) {
-            const f32x4 acc = mma(b[n], a[m], zero);
-            float v[4];
+        for (int n = 0; n < NB; ++n) {
+            const f32x4 acc = mma(b[n], a, zero);
+            if (gz >= D || gy >= H || gx >= W) continue;
+            float o[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) v[j] = acc[j] + bco[j];
-            store4<OUT_F32, RELU, ACC>(out, (base + m * 16 + r) * out_cs + out_off + co0, v,
-                                       out_vec != 0);
+            for (int j = 0; j < 4; ++j) o[j] = acc[j] + bco[n][j];
+            store4<OUT_F32, RELU, ACC>(
+                out, ((static_cast<long long>(gz) * H + gy) * W + gx) * out_cs + out_off + n * 16 + 4 * g,
+                o, out_vec != 0);
         }
     }
 }
@@ -1199,10 +1247,11 @@ hipError_t conv3_go(hipStream_t s, const u16 *ip, int in_cs, int in_off, const u
     const bool two_in = cat.ksplit < CI;
     if constexpr (CI == 1) {
         if (two_in || cat.nsplit < CO) return hipErrorInvalidValue;
-        const long long nvox = static_cast<long long>(D) * H * W;
-        hipLaunchKernelGGL((conv3_c1_kernel<CO, F32, RELU, ACC>), dim3(blocks_for(nvox, NT)),
-                           dim3(NT), 0, s, ip, in_cs, in_off, wp, bias, out, out_cs, out_off, D, H,
-                           W, out_vec);
+        const long long tiles = static_cast<long long>((W + 15) / 16) * ((H + C1_TY - 1) / C1_TY) *
+                                ((D + C1_TZ - 1) / C1_TZ);
+        hipLaunchKernelGGL((conv3_c1_tile_kernel<CO, F32, RELU, ACC>),
+                           dim3(static_cast<unsigned>(tiles)), dim3(NT), 0, s, ip, in_cs, in_off,
+                           wp, bias, out, out_cs, out_off, D, H, W, out_vec);
     } else {
         constexpr int TY = ConvTile<CI, CO>::TY, TZ = ConvTile<CI, CO>::TZ;
         const long long tiles = static_cast<long long>((W + 15) / 16) * ((H + TY - 1) / TY) *
