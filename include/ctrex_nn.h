@@ -95,18 +95,25 @@ CTREX_API int ctrex_nn_conv3_wgrad(ctrex_ctx *ctx, const void *in, int32_t in_cs
  * a_off + ca - 1 (stride a_cs), input channels [ca, ca + cb) in_b's channels
  * b_off .. (stride b_cs); output channels [0, oa) go to out_a (stride oa_cs,
  * offset oa_off), [oa, oa + ob) to out_b.  cb = 0 ignores in_b, ob = 0
- * ignores out_b (then this is ctrex_nn_conv3).  A two-tensor input (cb > 0)
+ * ignores out_b (then this is ctrex_nn_conv3).  `gate` (NULL = none; channel
+ * stride g_cs and offset g_off, multiples of 8) zeroes output channel co of
+ * voxel v where gate[v][g_off + co] <= 0 (or NaN), before the activation and
+ * accumulation: with gate = the forward ReLU output, a data-gradient
+ * convolution writes the gradient at that layer's pre-activation (the ReLU
+ * backward folded in).  A two-tensor input (cb > 0)
  * is supported for (ca + cb, oa + ob) = (32, 16) or (64, 32) with ca a
  * multiple of 8; a two-tensor output (ob > 0) needs cin >= 16 and oa a
- * multiple of 16; other shapes as ctrex_nn_conv3, CTREX_ESHAPE otherwise.
+ * multiple of 16; a gate needs cin >= 16; other shapes as ctrex_nn_conv3,
+ * CTREX_ESHAPE otherwise.
  * Same flags, packing, arithmetic and status behaviour as ctrex_nn_conv3.
  */
 CTREX_API int ctrex_nn_conv3_cat(ctrex_ctx *ctx, const void *in_a, int32_t a_cs, int32_t a_off,
                                  int32_t ca, const void *in_b, int32_t b_cs, int32_t b_off,
                                  int32_t cb, const void *wt, const float *bias, void *out_a,
                                  int32_t oa_cs, int32_t oa_off, int32_t oa, void *out_b,
-                                 int32_t ob_cs, int32_t ob_off, int32_t ob, int32_t D, int32_t H,
-                                 int32_t W, uint32_t flags, void *stream);
+                                 int32_t ob_cs, int32_t ob_off, int32_t ob, const void *gate,
+                                 int32_t g_cs, int32_t g_off, int32_t D, int32_t H, int32_t W,
+                                 uint32_t flags, void *stream);
 
 /*
  * ctrex_nn_conv3_wgrad with the input the channel concatenation of in_a
@@ -163,6 +170,15 @@ CTREX_API int ctrex_nn_maxpool2_backward(ctrex_ctx *ctx, const void *in, int32_t
                                          int32_t in_off, int32_t c, const void *dout, void *din,
                                          int32_t D, int32_t H, int32_t W, void *stream);
 
+/* ctrex_nn_maxpool2_backward followed by ctrex_nn_relu_backward with y = in
+ * over the whole slice, in one pass (`in` is a ReLU output): din[v][c] = 0
+ * where in[v][c] <= 0 (or NaN), otherwise din plus the pooled gradient as
+ * above.  Only the window maxima's din is read. */
+CTREX_API int ctrex_nn_maxpool2_relu_backward(ctrex_ctx *ctx, const void *in, int32_t in_cs,
+                                              int32_t in_off, int32_t c, const void *dout,
+                                              void *din, int32_t D, int32_t H, int32_t W,
+                                              void *stream);
+
 /* ReLU backward in place: g[v][c] = 0 where y[v][c] <= 0 (y, g share the
  * channel stride/offset layout; n_vox voxels of c channels). */
 CTREX_API int ctrex_nn_relu_backward(ctrex_ctx *ctx, const void *y, void *g, int32_t cs,
@@ -189,6 +205,14 @@ CTREX_API int ctrex_nn_head_backward(ctrex_ctx *ctx, const void *act, int32_t c,
                                      float out_scale, const float *mask, const float *dout,
                                      void *dact, float *dh, float *db, int64_t n_vox,
                                      void *stream);
+
+/* ctrex_nn_head_backward with dact also multiplied by the ReLU derivative at
+ * act (dact = 0 where act <= 0 or NaN): the gradient at the pre-activation of
+ * the layer whose ReLU output the head reads, in one pass. */
+CTREX_API int ctrex_nn_head_relu_backward(ctrex_ctx *ctx, const void *act, int32_t c,
+                                          const float *h, float out_scale, const float *mask,
+                                          const float *dout, void *dact, float *dh, float *db,
+                                          int64_t n_vox, void *stream);
 
 /* Weighted mean squared error over n values: *loss (host, optional; waits)
  * = weight sum (a - t)^2 / n with the sum in FP64, grad (optional) =

@@ -96,8 +96,8 @@ def lib():
             "ctrex_nn_conv3_wgrad": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, i32, i32, i32,
                                                     i32, i32, i32, vp, vp, vp]),
             "ctrex_nn_conv3_cat": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, i32, i32, i32, vp,
-                                                  vp, vp, i32, i32, i32, vp, i32, i32, i32, i32,
-                                                  i32, i32, u32, vp]),
+                                                  vp, vp, i32, i32, i32, vp, i32, i32, i32, vp,
+                                                  i32, i32, i32, i32, i32, u32, vp]),
             "ctrex_nn_conv3_wgrad_cat": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, i32, i32, i32,
                                                         vp, i32, i32, i32, i32, i32, i32, vp, vp,
                                                         vp]),
@@ -110,6 +110,8 @@ def lib():
             "ctrex_nn_maxpool2": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, i32, i32, i32, vp]),
             "ctrex_nn_maxpool2_backward": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, vp, i32, i32,
                                                           i32, vp]),
+            "ctrex_nn_maxpool2_relu_backward": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, vp, i32,
+                                                               i32, i32, vp]),
             "ctrex_nn_relu_backward": (ctypes.c_int, [vp, vp, vp, i32, i32, i32, ctypes.c_int64,
                                                       vp]),
             "ctrex_nn_input": (ctypes.c_int, [vp, vp, ctypes.c_float, vp, ctypes.c_int64, vp]),
@@ -117,6 +119,8 @@ def lib():
                                              ctypes.c_int64, vp]),
             "ctrex_nn_head_backward": (ctypes.c_int, [vp, vp, i32, vp, ctypes.c_float, vp, vp, vp,
                                                       vp, vp, ctypes.c_int64, vp]),
+            "ctrex_nn_head_relu_backward": (ctypes.c_int, [vp, vp, i32, vp, ctypes.c_float, vp,
+                                                           vp, vp, vp, vp, ctypes.c_int64, vp]),
             "ctrex_nn_mse": (ctypes.c_int, [vp, vp, vp, ctypes.c_int64, ctypes.c_float, dp, vp,
                                             vp]),
             "ctrex_nn_adam": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float,

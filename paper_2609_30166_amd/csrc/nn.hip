@@ -241,8 +241,10 @@ __global__ __launch_bounds__(NT) void conv3_c1_tile_kernel(const u16 *__restrict
 // size: 64 channels at once would need a 4 x 2 tile, three times as many
 // halo voxels per output, and half the workgroups per CU).  Occupancy hints:
 // 16 -> 16 runs 4 waves per SIMD in 128 registers; 32 or 64 inputs with at
-// most 32 outputs run 3 (the LDS tile admits three workgroups per CU); the
-// rest take what their accumulators leave.  Tiles: 8 x 4 rows for 16 -> 16,
+// most 32 outputs run 3 (the LDS tile admits three workgroups per CU); 64
+// outputs with 32 or 64 inputs run 2 (without the hint the 64 -> 64 tile's
+// two epilogue forms took just over 256 registers, one wave per SIMD); 16 ->
+// 32 takes what its accumulators leave.  Tiles: 8 x 4 rows for 16 -> 16,
 // 8 x 2 otherwise (16 -> 32 measured 0.83 -> 0.70 ms as a data gradient at
 // 256^3 with 8 x 2, 16 -> 16 0.46 -> 0.49 ms, so each keeps its faster shape).
 template <int CIN, int COUT> struct ConvTile {
@@ -253,17 +255,22 @@ template <int CIN, int COUT> struct ConvTile {
 // channels k >= ksplit are channel k - ksplit of in2 (only read where the
 // kernel's CAT parameter is set), output channels co >= nsplit go to channel
 // co - nsplit of out2 (nsplit a multiple of 16).  A plain convolution passes
-// ksplit = cin, nsplit = cout.
+// ksplit = cin, nsplit = cout.  With `gate` set, output channel co of a voxel
+// is zeroed where gate[voxel][gate_off + co] <= 0 (or NaN), before the
+// activation and accumulation: the ReLU derivative at the forward activation
+// whose gradient a data-gradient convolution produces.
 struct CatArgs {
     const u16 *in2;
     int in2_cs, in2_off, ksplit;
     void *out2;
     int out2_cs, out2_off, nsplit;
+    const u16 *gate;
+    int gate_cs, gate_off;
 };
 
 template <int CIN, int COUT, bool OUT_F32, bool RELU, bool ACC, bool CAT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
-    CIN == 16 ? (COUT == 16 ? 4 : 1) : (COUT <= 32 ? 3 : 1)))) void
+    CIN == 16 ? (COUT == 16 ? 4 : 1) : (COUT <= 32 ? 3 : 2)))) void
 conv3_tile_kernel(const u16 *__restrict__ in, int in_cs, int in_off, const u16 *__restrict__ wt,
                   const float *__restrict__ bias, void *out, int out_cs, int out_off, int D, int H,
                   int W, int out_vec, CatArgs cat) {
@@ -468,15 +475,50 @@ conv3_tile_kernel(const u16 *__restrict__ in, int in_cs, int in_off, const u16 *
         void *dst = second ? cat.out2 : out;
         const int dcs = second ? cat.out2_cs : out_cs;
         const int dch = second ? cat.out2_off + co0 - cat.nsplit : out_off + co0;
+        if (!cat.gate) {
 #pragma unroll
-        for (int m = 0; m < MBW; ++m) {
-            const int gy = y0 + ym0 + m;
-            if (gz >= D || gy >= H || gx >= W) continue;
-            const long long o = ((static_cast<long long>(gz) * H + gy) * W + gx) * dcs + dch;
-            float v[4];
+            for (int m = 0; m < MBW; ++m) {
+                const int gy = y0 + ym0 + m;
+                if (gz >= D || gy >= H || gx >= W) continue;
+                const long long vox = (static_cast<long long>(gz) * H + gy) * W + gx;
+                float v[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) v[j] = acc[m][n][j] + bco[j];
-            store4<OUT_F32, RELU, ACC>(dst, o, v, out_vec != 0);
+                for (int j = 0; j < 4; ++j) v[j] = acc[m][n][j] + bco[j];
+                store4<OUT_F32, RELU, ACC>(dst, vox * dcs + dch, v, out_vec != 0);
+            }
+            continue;
+        }
+        // the gate's 4 channels of each row (one 8-byte load: stride and
+        // offset are multiples of 8); with at most 32 outputs those of all
+        // rows of the block are loaded together, so their latencies overlap
+        // (the 64-output tiles have no registers to spare for them)
+        constexpr int GB = NB <= 2 ? MBW : 1;   // rows per batch of gate loads
+#pragma unroll
+        for (int m0 = 0; m0 < MBW; m0 += GB) {
+            uint2 gv[GB];
+#pragma unroll
+            for (int k = 0; k < GB; ++k) {
+                const int gy = y0 + ym0 + m0 + k;
+                gv[k] = make_uint2(0u, 0u);
+                if (gz < D && gy < H && gx < W)
+                    gv[k] = *reinterpret_cast<const uint2 *>(
+                        cat.gate + ((static_cast<long long>(gz) * H + gy) * W + gx) * cat.gate_cs +
+                        cat.gate_off + co0);
+            }
+#pragma unroll
+            for (int k = 0; k < GB; ++k) {
+                const int m = m0 + k, gy = y0 + ym0 + m;
+                if (gz >= D || gy >= H || gx >= W) continue;
+                const long long vox = (static_cast<long long>(gz) * H + gy) * W + gx;
+                float v[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[j] = acc[m][n][j] + bco[j];
+                if (!(__uint_as_float(gv[k].x << 16) > 0.0f)) v[0] = 0.0f;
+                if (!(__uint_as_float(gv[k].x & 0xffff0000u) > 0.0f)) v[1] = 0.0f;
+                if (!(__uint_as_float(gv[k].y << 16) > 0.0f)) v[2] = 0.0f;
+                if (!(__uint_as_float(gv[k].y & 0xffff0000u) > 0.0f)) v[3] = 0.0f;
+                store4<OUT_F32, RELU, ACC>(dst, vox * dcs + dch, v, out_vec != 0);
+            }
         }
     }
 }
@@ -998,6 +1040,10 @@ __global__ __launch_bounds__(NT) void maxpool2_kernel(const u16 *__restrict__ in
     out[i] = f2bf(m);
 }
 
+// RELU: then the ReLU derivative at in, over every input element: din is
+// zeroed where in <= 0 (or NaN) and left as it is elsewhere, so only the
+// arg-max element's din is read.
+template <bool RELU>
 __global__ __launch_bounds__(NT) void maxpool2_bwd_kernel(const u16 *__restrict__ in, int in_cs,
                                                           int in_off, int c,
                                                           const u16 *__restrict__ dout,
@@ -1010,17 +1056,29 @@ __global__ __launch_bounds__(NT) void maxpool2_bwd_kernel(const u16 *__restrict_
     const Vox p = decode(i / c, Ho, Wo);
     float m = -__builtin_inff();
     long long best = -1;
+    bool pos[8];
+#pragma unroll
     for (int a = 0; a < 8; ++a) {
         const long long q = (static_cast<long long>(2 * p.z + (a >> 2)) * H + 2 * p.y + ((a >> 1) & 1)) * W +
                             2 * p.x + (a & 1);
         const float v = bf2f(in[q * in_cs + in_off + ch]);
+        pos[a] = v > 0.0f;
         if (v > m || best < 0) {
             m = v;
             best = q;
         }
     }
     u16 *o = din + best * in_cs + in_off + ch;
-    *o = f2bf(bf2f(*o) + bf2f(dout[i]));
+    if (!RELU || m > 0.0f) *o = f2bf(bf2f(*o) + bf2f(dout[i]));
+    if (RELU) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            if (pos[a]) continue;
+            const long long q = (static_cast<long long>(2 * p.z + (a >> 2)) * H + 2 * p.y + ((a >> 1) & 1)) * W +
+                                2 * p.x + (a & 1);
+            din[q * in_cs + in_off + ch] = 0;
+        }
+    }
 }
 
 __global__ __launch_bounds__(NT) void relu_bwd_kernel(const u16 *__restrict__ y, u16 *__restrict__ gr,
@@ -1102,8 +1160,10 @@ __global__ __launch_bounds__(NT) void scale_bf16_kernel(const float *__restrict_
     if (i < n) xb[i] = f2bf(scale * x[i]);
 }
 
-// With d = mask scale dout: dact = d h; per-block partial sums of d act[:, k] (k < C) and d.
-template <int C, bool VEC>
+// With d = mask scale dout: dact = d h (RELU: zero where act <= 0, the
+// gradient at the pre-activation); per-block partial sums of d act[:, k]
+// (k < C) and d.
+template <int C, bool VEC, bool RELU>
 __global__ __launch_bounds__(NT) void head_bwd_kernel(const u16 *__restrict__ act,
                                                       const float *__restrict__ h, float scale,
                                                       const float *__restrict__ mask,
@@ -1121,8 +1181,9 @@ __global__ __launch_bounds__(NT) void head_bwd_kernel(const u16 *__restrict__ ac
         if constexpr (!VEC) {   // act or dact not 16-byte aligned
 #pragma unroll
             for (int k = 0; k < C; ++k) {
-                acc[k] += static_cast<double>(d) * bf2f(act[v * C + k]);
-                dact[v * C + k] = f2bf(d * h[k]);
+                const float a = bf2f(act[v * C + k]);
+                acc[k] += static_cast<double>(d) * a;
+                dact[v * C + k] = RELU && !(a > 0.0f) ? 0 : f2bf(d * h[k]);
             }
             acc[C] += d;
             continue;
@@ -1137,10 +1198,13 @@ __global__ __launch_bounds__(NT) void head_bwd_kernel(const u16 *__restrict__ ac
 #pragma unroll
             for (int k2 = 0; k2 < 4; ++k2) {
                 const int k = 8 * q + 2 * k2;
-                acc[k] += static_cast<double>(d) * __uint_as_float(w[k2] << 16);
-                acc[k + 1] += static_cast<double>(d) * __uint_as_float(w[k2] & 0xffff0000u);
-                o[k2] = static_cast<uint32_t>(f2bf(d * h[k])) |
-                        (static_cast<uint32_t>(f2bf(d * h[k + 1])) << 16);
+                const float a0 = __uint_as_float(w[k2] << 16);
+                const float a1 = __uint_as_float(w[k2] & 0xffff0000u);
+                acc[k] += static_cast<double>(d) * a0;
+                acc[k + 1] += static_cast<double>(d) * a1;
+                const uint32_t lo = RELU && !(a0 > 0.0f) ? 0u : f2bf(d * h[k]);
+                const uint32_t hi = RELU && !(a1 > 0.0f) ? 0u : f2bf(d * h[k + 1]);
+                o[k2] = lo | (hi << 16);
             }
             dp[q] = make_uint4(o[0], o[1], o[2], o[3]);
         }
@@ -1296,8 +1360,8 @@ hipError_t conv3_pick(bool relu, bool acc, bool f32, hipStream_t s, const u16 *i
 hipError_t launch_conv3(const void *in, int in_cs, int in_off, int cin_a, const void *in2,
                         int in2_cs, int in2_off, int cin_b, const void *wt, const float *bias,
                         void *out, int out_cs, int out_off, int cout_a, void *out2, int out2_cs,
-                        int out2_off, int cout_b, int D, int H, int W, bool relu, bool acc,
-                        bool out_f32, hipStream_t s) {
+                        int out2_off, int cout_b, const void *gate, int gate_cs, int gate_off,
+                        int D, int H, int W, bool relu, bool acc, bool out_f32, hipStream_t s) {
     const int cin = cin_a + cin_b, cout = cout_a + cout_b;
     const u16 *ip = static_cast<const u16 *>(in);
     const u16 *wp = static_cast<const u16 *>(wt);
@@ -1310,6 +1374,10 @@ hipError_t launch_conv3(const void *in, int in_cs, int in_off, int cin_a, const 
     cat.out2_cs = cout_b > 0 ? out2_cs : out_cs;
     cat.out2_off = cout_b > 0 ? out2_off : out_off + cout_a;
     cat.nsplit = cout_a;
+    cat.gate = static_cast<const u16 *>(gate);
+    cat.gate_cs = gate_cs;
+    cat.gate_off = gate_off;
+    if (gate && cin == 1) return hipErrorInvalidValue;
     if (cin_a <= 0 || cout_a <= 0 || cout_a % 16 != 0 || (cin_b > 0 && cin_a % 8 != 0))
         return hipErrorInvalidValue;
 #define CASE(CI, CO)                                                                             \
@@ -1528,11 +1596,16 @@ hipError_t launch_maxpool2(const void *in, int in_cs, int in_off, int c, void *o
 }
 
 hipError_t launch_maxpool2_bwd(const void *in, int in_cs, int in_off, int c, const void *dout,
-                               void *din, int D, int H, int W, hipStream_t s) {
+                               void *din, int D, int H, int W, bool relu, hipStream_t s) {
     const long long n = static_cast<long long>(D / 2) * (H / 2) * (W / 2) * c;
-    hipLaunchKernelGGL(maxpool2_bwd_kernel, dim3(blocks_for(n)), dim3(NT), 0, s,
-                       static_cast<const u16 *>(in), in_cs, in_off, c, static_cast<const u16 *>(dout),
-                       static_cast<u16 *>(din), D, H, W);
+    if (relu)
+        hipLaunchKernelGGL(maxpool2_bwd_kernel<true>, dim3(blocks_for(n)), dim3(NT), 0, s,
+                           static_cast<const u16 *>(in), in_cs, in_off, c,
+                           static_cast<const u16 *>(dout), static_cast<u16 *>(din), D, H, W);
+    else
+        hipLaunchKernelGGL(maxpool2_bwd_kernel<false>, dim3(blocks_for(n)), dim3(NT), 0, s,
+                           static_cast<const u16 *>(in), in_cs, in_off, c,
+                           static_cast<const u16 *>(dout), static_cast<u16 *>(din), D, H, W);
     return hipGetLastError();
 }
 
@@ -1576,17 +1649,22 @@ size_t head_bwd_scratch(int c) {
 
 hipError_t launch_head_bwd(const void *act, int c, const float *h, float scale, const float *mask,
                            const float *dout, void *dact, float *dh, float *db, long long n,
-                           double *scratch, hipStream_t s) {
+                           bool relu, double *scratch, hipStream_t s) {
     const int blocks = kHeadBwdBlocks;
     if (c != 16) return hipErrorInvalidValue;
-    if ((reinterpret_cast<uintptr_t>(act) | reinterpret_cast<uintptr_t>(dact)) % 16 == 0)
-        hipLaunchKernelGGL((head_bwd_kernel<16, true>), dim3(blocks), dim3(NT), 0, s,
-                           static_cast<const u16 *>(act), h, scale, mask, dout,
-                           static_cast<u16 *>(dact), n, scratch);
-    else
-        hipLaunchKernelGGL((head_bwd_kernel<16, false>), dim3(blocks), dim3(NT), 0, s,
-                           static_cast<const u16 *>(act), h, scale, mask, dout,
-                           static_cast<u16 *>(dact), n, scratch);
+    const bool vec = (reinterpret_cast<uintptr_t>(act) | reinterpret_cast<uintptr_t>(dact)) % 16 == 0;
+#define CTREX_NN_HB(V, R)                                                                          \
+    hipLaunchKernelGGL((head_bwd_kernel<16, V, R>), dim3(blocks), dim3(NT), 0, s,                  \
+                       static_cast<const u16 *>(act), h, scale, mask, dout,                        \
+                       static_cast<u16 *>(dact), n, scratch)
+    if (vec) {
+        if (relu) CTREX_NN_HB(true, true);
+        else CTREX_NN_HB(true, false);
+    } else {
+        if (relu) CTREX_NN_HB(false, true);
+        else CTREX_NN_HB(false, false);
+    }
+#undef CTREX_NN_HB
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (dh) hipLaunchKernelGGL(reduce_rows_kernel, dim3(blocks_for(c, 32)), dim3(NT), 0, s, scratch, blocks, c, c + 1, dh);

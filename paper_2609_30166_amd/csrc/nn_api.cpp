@@ -14,8 +14,8 @@ namespace nn {
 hipError_t launch_conv3(const void *in, int in_cs, int in_off, int cin_a, const void *in2,
                         int in2_cs, int in2_off, int cin_b, const void *wt, const float *bias,
                         void *out, int out_cs, int out_off, int cout_a, void *out2, int out2_cs,
-                        int out2_off, int cout_b, int D, int H, int W, bool relu, bool acc,
-                        bool out_f32, hipStream_t s);
+                        int out2_off, int cout_b, const void *gate, int gate_cs, int gate_off,
+                        int D, int H, int W, bool relu, bool acc, bool out_f32, hipStream_t s);
 size_t conv3_wgrad_scratch(int cin, int cout, long long nvox);
 hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin_a, const void *in2,
                               int in2_cs, int in2_off, int cin_b, const void *dout, int dout_cs,
@@ -37,7 +37,7 @@ hipError_t launch_upconv2_wgrad(const void *in, int in_cs, int in_off, int cin, 
 hipError_t launch_maxpool2(const void *in, int in_cs, int in_off, int c, void *out, int D, int H,
                            int W, hipStream_t s);
 hipError_t launch_maxpool2_bwd(const void *in, int in_cs, int in_off, int c, const void *dout,
-                               void *din, int D, int H, int W, hipStream_t s);
+                               void *din, int D, int H, int W, bool relu, hipStream_t s);
 hipError_t launch_relu_bwd(const void *y, void *g, int cs, int off, int c, long long nvox,
                            hipStream_t s);
 hipError_t launch_head(const void *act, int c, const float *h, const float *b, const float *x,
@@ -46,7 +46,7 @@ hipError_t launch_scale_bf16(const float *x, float scale, void *xb, long long n,
 size_t head_bwd_scratch(int c);
 hipError_t launch_head_bwd(const void *act, int c, const float *h, float scale, const float *mask,
                            const float *dout, void *dact, float *dh, float *db, long long n,
-                           double *scratch, hipStream_t s);
+                           bool relu, double *scratch, hipStream_t s);
 hipError_t launch_mse(const float *a, const float *t, long long n, float weight, float *grad,
                       double *partial, int blocks, hipStream_t s);
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, long long n, float lr, float b1,
@@ -90,6 +90,35 @@ int begin(ctrex_ctx *c) {
     return CTREX_OK;
 }
 
+int maxpool2_backward(ctrex_ctx *c, const void *in, int32_t in_cs, int32_t in_off, int32_t ch,
+                      const void *dout, void *din, int32_t D, int32_t H, int32_t W, bool relu,
+                      void *stream) {
+    int st = begin(c);
+    if (st) return st;
+    if (ch < 1) return fail(c, CTREX_ESHAPE, "c must be >= 1");
+    if (D < 2 || H < 2 || W < 2 || D % 2 || H % 2 || W % 2)
+        return fail(c, CTREX_ESHAPE, "pooling needs even sides >= 2");
+    if ((st = check_slice(c, "in", in, in_cs, in_off, ch, false))) return st;
+    if (!dout || !din) return fail(c, CTREX_EINVAL, "dout and din must be device pointers");
+    CTREX_HIP(c, nn::launch_maxpool2_bwd(in, in_cs, in_off, ch, dout, din, D, H, W, relu,
+                                         static_cast<hipStream_t>(stream)));
+    return CTREX_OK;
+}
+
+int head_backward(ctrex_ctx *c, const void *act, int32_t ch, const float *h, float out_scale,
+                  const float *mask, const float *dout, void *dact, float *dh, float *db,
+                  int64_t n_vox, bool relu, void *stream) {
+    int st = begin(c);
+    if (st) return st;
+    if (!act || !h || !dout || !dact) return fail(c, CTREX_EINVAL, "NULL pointer");
+    if (ch != 16 || n_vox < 1) return fail(c, CTREX_ESHAPE, "the head takes 16 channels");
+    if (!std::isfinite(out_scale)) return fail(c, CTREX_EINVAL, "out_scale must be finite");
+    void *scr;
+    if ((st = ctx_scratch(c, nn::head_bwd_scratch(ch), &scr))) return st;
+    CTREX_HIP(c, nn::launch_head_bwd(act, ch, h, out_scale, mask, dout, dact, dh, db, n_vox, relu,
+                                     static_cast<double *>(scr), static_cast<hipStream_t>(stream)));
+    return CTREX_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -108,17 +137,18 @@ int ctrex_nn_conv3(ctrex_ctx *c, const void *in, int32_t in_cs, int32_t in_off, 
     if ((st = check_slice(c, "out", out, out_cs, out_off, cout, false))) return st;
     if (!wt) return fail(c, CTREX_EINVAL, "wt is NULL");
     CTREX_HIP(c, nn::launch_conv3(in, in_cs, in_off, cin, nullptr, 0, 0, 0, wt, bias, out, out_cs,
-                                  out_off, cout, nullptr, 0, 0, 0, D, H, W, flags & CTREX_NN_RELU,
-                                  flags & CTREX_NN_ACCUMULATE, flags & CTREX_NN_OUT_F32,
-                                  static_cast<hipStream_t>(stream)));
+                                  out_off, cout, nullptr, 0, 0, 0, nullptr, 0, 0, D, H, W,
+                                  flags & CTREX_NN_RELU, flags & CTREX_NN_ACCUMULATE,
+                                  flags & CTREX_NN_OUT_F32, static_cast<hipStream_t>(stream)));
     return CTREX_OK;
 }
 
 int ctrex_nn_conv3_cat(ctrex_ctx *c, const void *in_a, int32_t a_cs, int32_t a_off, int32_t ca,
                        const void *in_b, int32_t b_cs, int32_t b_off, int32_t cb, const void *wt,
                        const float *bias, void *out_a, int32_t oa_cs, int32_t oa_off, int32_t oa,
-                       void *out_b, int32_t ob_cs, int32_t ob_off, int32_t ob, int32_t D,
-                       int32_t H, int32_t W, uint32_t flags, void *stream) {
+                       void *out_b, int32_t ob_cs, int32_t ob_off, int32_t ob, const void *gate,
+                       int32_t g_cs, int32_t g_off, int32_t D, int32_t H, int32_t W,
+                       uint32_t flags, void *stream) {
     int st = begin(c);
     if (st) return st;
     const int cin = ca + cb, cout = oa + ob;
@@ -137,9 +167,12 @@ int ctrex_nn_conv3_cat(ctrex_ctx *c, const void *in_a, int32_t a_cs, int32_t a_o
     if (cb > 0 && (st = check_slice(c, "in_b", in_b, b_cs, b_off, cb, true))) return st;
     if ((st = check_slice(c, "out_a", out_a, oa_cs, oa_off, oa, false))) return st;
     if (ob > 0 && (st = check_slice(c, "out_b", out_b, ob_cs, ob_off, ob, false))) return st;
+    if (gate && cin == 1) return fail(c, CTREX_ESHAPE, "a gate needs cin >= 16");
+    if (gate && (st = check_slice(c, "gate", gate, g_cs, g_off, cout, true))) return st;
     if (!wt) return fail(c, CTREX_EINVAL, "wt is NULL");
     CTREX_HIP(c, nn::launch_conv3(in_a, a_cs, a_off, ca, in_b, b_cs, b_off, cb, wt, bias, out_a,
-                                  oa_cs, oa_off, oa, out_b, ob_cs, ob_off, ob, D, H, W,
+                                  oa_cs, oa_off, oa, out_b, ob_cs, ob_off, ob, gate, g_cs, g_off,
+                                  D, H, W,
                                   flags & CTREX_NN_RELU, flags & CTREX_NN_ACCUMULATE,
                                   flags & CTREX_NN_OUT_F32, static_cast<hipStream_t>(stream)));
     return CTREX_OK;
@@ -290,16 +323,13 @@ int ctrex_nn_maxpool2(ctrex_ctx *c, const void *in, int32_t in_cs, int32_t in_of
 int ctrex_nn_maxpool2_backward(ctrex_ctx *c, const void *in, int32_t in_cs, int32_t in_off,
                                int32_t ch, const void *dout, void *din, int32_t D, int32_t H,
                                int32_t W, void *stream) {
-    int st = begin(c);
-    if (st) return st;
-    if (ch < 1) return fail(c, CTREX_ESHAPE, "c must be >= 1");
-    if (D < 2 || H < 2 || W < 2 || D % 2 || H % 2 || W % 2)
-        return fail(c, CTREX_ESHAPE, "pooling needs even sides >= 2");
-    if ((st = check_slice(c, "in", in, in_cs, in_off, ch, false))) return st;
-    if (!dout || !din) return fail(c, CTREX_EINVAL, "dout and din must be device pointers");
-    CTREX_HIP(c, nn::launch_maxpool2_bwd(in, in_cs, in_off, ch, dout, din, D, H, W,
-                                         static_cast<hipStream_t>(stream)));
-    return CTREX_OK;
+    return maxpool2_backward(c, in, in_cs, in_off, ch, dout, din, D, H, W, false, stream);
+}
+
+int ctrex_nn_maxpool2_relu_backward(ctrex_ctx *c, const void *in, int32_t in_cs, int32_t in_off,
+                                    int32_t ch, const void *dout, void *din, int32_t D, int32_t H,
+                                    int32_t W, void *stream) {
+    return maxpool2_backward(c, in, in_cs, in_off, ch, dout, din, D, H, W, true, stream);
 }
 
 int ctrex_nn_relu_backward(ctrex_ctx *c, const void *y, void *g, int32_t cs, int32_t off,
@@ -343,16 +373,13 @@ int ctrex_nn_head(ctrex_ctx *c, const void *act, int32_t ch, const float *h, con
 int ctrex_nn_head_backward(ctrex_ctx *c, const void *act, int32_t ch, const float *h,
                            float out_scale, const float *mask, const float *dout, void *dact,
                            float *dh, float *db, int64_t n_vox, void *stream) {
-    int st = begin(c);
-    if (st) return st;
-    if (!act || !h || !dout || !dact) return fail(c, CTREX_EINVAL, "NULL pointer");
-    if (ch != 16 || n_vox < 1) return fail(c, CTREX_ESHAPE, "the head takes 16 channels");
-    if (!std::isfinite(out_scale)) return fail(c, CTREX_EINVAL, "out_scale must be finite");
-    void *scr;
-    if ((st = ctx_scratch(c, nn::head_bwd_scratch(ch), &scr))) return st;
-    CTREX_HIP(c, nn::launch_head_bwd(act, ch, h, out_scale, mask, dout, dact, dh, db, n_vox,
-                                     static_cast<double *>(scr), static_cast<hipStream_t>(stream)));
-    return CTREX_OK;
+    return head_backward(c, act, ch, h, out_scale, mask, dout, dact, dh, db, n_vox, false, stream);
+}
+
+int ctrex_nn_head_relu_backward(ctrex_ctx *c, const void *act, int32_t ch, const float *h,
+                                float out_scale, const float *mask, const float *dout, void *dact,
+                                float *dh, float *db, int64_t n_vox, void *stream) {
+    return head_backward(c, act, ch, h, out_scale, mask, dout, dact, dh, db, n_vox, true, stream);
 }
 
 int ctrex_nn_mse(ctrex_ctx *c, const float *a, const float *t, int64_t n, float weight,

@@ -271,7 +271,7 @@ class UNet:
         h = cin // 2
         self._call("ctrex_nn_conv3_cat", _vp(ua), h, 0, h, _vp(ea), h, 0, h,
                    _vp(self._wt[name]), _vp(self.p(name + ".b")), _vp(dst), cout, 0, cout, None,
-                   0, 0, 0, D, H, W, _lib.NN_RELU, self._s())
+                   0, 0, 0, None, 0, 0, D, H, W, _lib.NN_RELU, self._s())
 
     def _up(self, name, src, dst, d_cs, d_off, dims):
         kind, cin, cout = _KIND[name]
@@ -357,16 +357,24 @@ class UNet:
         D, H, W = dims
         h = cin // 2
         self._call("ctrex_nn_conv3_cat", _vp(dout), d_cs, 0, cout, None, 0, 0, 0,
-                   _vp(self._wd[name]), None, _vp(gu), h, 0, h, _vp(ge), h, 0, h, D, H, W, 0,
-                   self._s())
+                   _vp(self._wd[name]), None, _vp(gu), h, 0, h, _vp(ge), h, 0, h, None, 0, 0, D, H,
+                   W, 0, self._s())
 
-    def _dgrad(self, name, dout, d_cs, d_off, dst, o_cs, o_off, dims):
+    def _dgrad(self, name, dout, d_cs, d_off, dst, o_cs, o_off, dims, relu_of=None):
         """Data gradient of a convolution: the convolution with the mirrored,
-        transposed packing (cin and cout swap roles)."""
+        transposed packing (cin and cout swap roles).  ``relu_of``: the ReLU
+        output (channels-last, cin channels) that the layer's input is; its
+        derivative is applied in the same pass, giving the gradient at the
+        producing layer's pre-activation."""
         kind, cin, cout = _KIND[name]
         D, H, W = dims
-        self._call("ctrex_nn_conv3", _vp(dout), d_cs, d_off, cout, _vp(self._wd[name]), None,
-                   _vp(dst), o_cs, o_off, cin, D, H, W, 0, self._s())
+        if relu_of is None:
+            self._call("ctrex_nn_conv3", _vp(dout), d_cs, d_off, cout, _vp(self._wd[name]), None,
+                       _vp(dst), o_cs, o_off, cin, D, H, W, 0, self._s())
+            return
+        self._call("ctrex_nn_conv3_cat", _vp(dout), d_cs, d_off, cout, None, 0, 0, 0,
+                   _vp(self._wd[name]), None, _vp(dst), o_cs, o_off, cin, None, 0, 0, 0,
+                   _vp(relu_of), cin, 0, D, H, W, 0, self._s())
 
     def backward(self, dout):
         """Gradients of every parameter given d loss / d out (float32 [D][H][W]);
@@ -378,14 +386,13 @@ class UNet:
         n2, n3 = n1 // 8, n1 // 64
         g = self.grad
         # head and decoder level 1
-        self._call("ctrex_nn_head_backward", _vp(b["d1"]), 16, _vp(self.p("head.w")),
+        # each ReLU's derivative is applied by the call producing its gradient
+        self._call("ctrex_nn_head_relu_backward", _vp(b["d1"]), 16, _vp(self.p("head.w")),
                    1.0 / self.scale, _vp(mask) if mask is not None else None, _vp(dout),
                    _vp(b["g1a"]), _vp(self.p("head.w", g)), _vp(self.p("head.b", g)), n1,
                    self._s())
-        self._relu_bwd(b["d1"], b["g1a"], 16, 0, 16, n1)
         self._wgrad("d1b", b["a5"], 16, 0, b["g1a"], 16, 0, l1)
-        self._dgrad("d1b", b["g1a"], 16, 0, b["g1b"], 16, 0, l1)
-        self._relu_bwd(b["a5"], b["g1b"], 16, 0, 16, n1)
+        self._dgrad("d1b", b["g1a"], 16, 0, b["g1b"], 16, 0, l1, relu_of=b["a5"])
         self._wgrad_cat("d1a", b["u1"], b["e1"], b["g1b"], 16, l1)
         self._dgrad_cat("d1a", b["g1b"], 16, b["gu1"], b["ge1"], l1)
         # up-sampling 1 and decoder level 2
@@ -394,8 +401,7 @@ class UNet:
                    _vp(b["g2a"]), 32, 0, 32, l2[0], l2[1], l2[2], 0, self._s())
         self._relu_bwd(b["d2"], b["g2a"], 32, 0, 32, n2)
         self._wgrad("d2b", b["a4"], 32, 0, b["g2a"], 32, 0, l2)
-        self._dgrad("d2b", b["g2a"], 32, 0, b["g2b"], 32, 0, l2)
-        self._relu_bwd(b["a4"], b["g2b"], 32, 0, 32, n2)
+        self._dgrad("d2b", b["g2a"], 32, 0, b["g2b"], 32, 0, l2, relu_of=b["a4"])
         self._wgrad_cat("d2a", b["u2"], b["e2"], b["g2b"], 32, l2)
         self._dgrad_cat("d2a", b["g2b"], 32, b["gu2"], b["ge2"], l2)
         # up-sampling 2 and the bottom level
@@ -404,26 +410,21 @@ class UNet:
                    _vp(b["g3a"]), 64, 0, 64, l3[0], l3[1], l3[2], 0, self._s())
         self._relu_bwd(b["b3"], b["g3a"], 64, 0, 64, n3)
         self._wgrad("bnb", b["a3"], 64, 0, b["g3a"], 64, 0, l3)
-        self._dgrad("bnb", b["g3a"], 64, 0, b["g3b"], 64, 0, l3)
-        self._relu_bwd(b["a3"], b["g3b"], 64, 0, 64, n3)
+        self._dgrad("bnb", b["g3a"], 64, 0, b["g3b"], 64, 0, l3, relu_of=b["a3"])
         self._wgrad("bna", b["p2"], 32, 0, b["g3b"], 64, 0, l3)
         self._dgrad("bna", b["g3b"], 64, 0, b["gp2"], 32, 0, l3)
         # encoder level 2: pooled gradient joins the skip gradient in place
-        self._call("ctrex_nn_maxpool2_backward", _vp(b["e2"]), 32, 0, 32, _vp(b["gp2"]),
+        self._call("ctrex_nn_maxpool2_relu_backward", _vp(b["e2"]), 32, 0, 32, _vp(b["gp2"]),
                    _vp(b["ge2"]), l2[0], l2[1], l2[2], self._s())
-        self._relu_bwd(b["e2"], b["ge2"], 32, 0, 32, n2)
         self._wgrad("e2b", b["a2"], 32, 0, b["ge2"], 32, 0, l2)
-        self._dgrad("e2b", b["ge2"], 32, 0, b["g2a"], 32, 0, l2)
-        self._relu_bwd(b["a2"], b["g2a"], 32, 0, 32, n2)
+        self._dgrad("e2b", b["ge2"], 32, 0, b["g2a"], 32, 0, l2, relu_of=b["a2"])
         self._wgrad("e2a", b["p1"], 16, 0, b["g2a"], 32, 0, l2)
         self._dgrad("e2a", b["g2a"], 32, 0, b["gp1"], 16, 0, l2)
         # encoder level 1
-        self._call("ctrex_nn_maxpool2_backward", _vp(b["e1"]), 16, 0, 16, _vp(b["gp1"]),
+        self._call("ctrex_nn_maxpool2_relu_backward", _vp(b["e1"]), 16, 0, 16, _vp(b["gp1"]),
                    _vp(b["ge1"]), l1[0], l1[1], l1[2], self._s())
-        self._relu_bwd(b["e1"], b["ge1"], 16, 0, 16, n1)
         self._wgrad("e1b", b["a1"], 16, 0, b["ge1"], 16, 0, l1)
-        self._dgrad("e1b", b["ge1"], 16, 0, b["g1a"], 16, 0, l1)
-        self._relu_bwd(b["a1"], b["g1a"], 16, 0, 16, n1)
+        self._dgrad("e1b", b["ge1"], 16, 0, b["g1a"], 16, 0, l1, relu_of=b["a1"])
         self._wgrad("e1a", b["xb"], 1, 0, b["g1a"], 16, 0, l1)
         return self.grad
 

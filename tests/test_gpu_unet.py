@@ -255,7 +255,7 @@ def test_conv3_cat_two_inputs(L, ctx, shape, cin, cout):
     out = torch.zeros(n * (cout + 4), dtype=torch.float32, device=DEV)
     ad, bd_, biasd = _dev_bf(aw), _dev_bf(bw), _dev_f(b)
     _call(L, ctx, "ctrex_nn_conv3_cat", _vp(ad), h + 8, 8, h, _vp(bd_), h + 16, 16, h, _vp(wt),
-          _vp(biasd), _vp(out), cout + 4, 4, cout, None, 0, 0, 0, *shape,
+          _vp(biasd), _vp(out), cout + 4, 4, cout, None, 0, 0, 0, None, 0, 0, *shape,
           L.NN_RELU | L.NN_OUT_F32, None)
     x = np.concatenate([xa, xb], axis=1).reshape(shape + (cin,))
     ref = np.maximum(ou.conv3(torch.tensor(x), torch.tensor(_bf(w)), torch.tensor(b)).numpy(), 0)
@@ -282,7 +282,7 @@ def test_conv3_cat_two_outputs_data_gradient(L, ctx, cin, cout):
     ga = torch.empty(n * h, dtype=torch.float32, device=DEV)
     gb = torch.full((n * (h + 8),), 5.0, dtype=torch.float32, device=DEV)
     _call(L, ctx, "ctrex_nn_conv3_cat", _vp(gd), cin, 0, cin, None, 0, 0, 0, _vp(wd), None,
-          _vp(ga), h, 0, h, _vp(gb), h + 8, 8, h, *shape, L.NN_OUT_F32, None)
+          _vp(ga), h, 0, h, _vp(gb), h + 8, 8, h, None, 0, 0, *shape, L.NN_OUT_F32, None)
     ref = x.grad.numpy().reshape(n, cout)
     _close(_host(ga).reshape(n, h), ref[:, :h])
     got_b = _host(gb).reshape(n, h + 8)
@@ -329,8 +329,105 @@ def test_conv3_cat_rejects_unsupported_splits(L, ctx):
     ]
     for ca, cb, oa, ob in bad:
         rc = L.lib().ctrex_nn_conv3_cat(ctx, _vp(a), 64, 0, ca, _vp(a), 64, 0, cb, _vp(wt), None,
-                                        _vp(o), 64, 0, oa, _vp(o), 64, 0, ob, 4, 4, 4, 0, None)
+                                        _vp(o), 64, 0, oa, _vp(o), 64, 0, ob, None, 0, 0, 4, 4, 4,
+                                        0, None)
         assert rc == -2, (ca, cb, oa, ob)   # CTREX_ESHAPE
+    # a gate at a channel offset that is not a multiple of 8
+    rc = L.lib().ctrex_nn_conv3_cat(ctx, _vp(a), 16, 0, 16, None, 0, 0, 0, _vp(wt), None, _vp(o),
+                                    16, 0, 16, None, 0, 0, 0, _vp(a), 20, 4, 4, 4, 4, 0, None)
+    assert rc == -2
+
+
+def _special_relu_out(r, n, c):
+    """A ReLU-output-like tensor with negative values, +-0, +-inf, NaN and
+    subnormals mixed in (the gate's "<= 0 or NaN" cases)."""
+    y = np.maximum(r.normal(size=(n, c)), 0)
+    y[r.random(size=y.shape) < 0.2] *= -1.0
+    flat = y.reshape(-1)
+    for k, v in enumerate([-0.0, 0.0, np.inf, -np.inf, np.nan, 1e-39, -1e-39]):
+        flat[k * 37 + 5::997] = v
+    return _bf(y)
+
+
+@pytest.mark.parametrize("cin,cout,split", [(16, 16, 0), (32, 32, 0), (64, 64, 0), (16, 32, 16)])
+def test_conv3_gate_is_relu_backward_of_the_output(L, ctx, cin, cout, split):
+    """A gated data-gradient convolution equals the ungated one followed by
+    the ReLU backward at the gate, bit for bit (also with the output split
+    over two tensors)."""
+    shape = (4, 8, 24)
+    n = int(np.prod(shape))
+    r = _rng(44, cin, cout)
+    x = _bf(r.normal(size=(n, cin)))
+    w = r.normal(0, 0.1, size=(cout, cin, 27))
+    wt, _ = _pack_conv(L, ctx, w)
+    gate = _special_relu_out(r, n, cout + 8)       # read at channel offset 8
+    xd, gd = _dev_bf(x), _dev_bf(gate)
+    plain = torch.empty(n * cout, dtype=torch.bfloat16, device=DEV)
+    _call(L, ctx, "ctrex_nn_conv3", _vp(xd), cin, 0, cin, _vp(wt), None, _vp(plain), cout, 0,
+          cout, *shape, 0, None)
+    ref = _host(plain).reshape(n, cout)
+    with np.errstate(invalid="ignore"):
+        ref[~(gate[:, 8:] > 0)] = 0
+    oa = split or cout
+    ga = torch.empty(n * oa, dtype=torch.bfloat16, device=DEV)
+    gb = torch.empty(n * max(cout - oa, 1), dtype=torch.bfloat16, device=DEV)
+    _call(L, ctx, "ctrex_nn_conv3_cat", _vp(xd), cin, 0, cin, None, 0, 0, 0, _vp(wt), None,
+          _vp(ga), oa, 0, oa, _vp(gb) if split else None, cout - oa, 0, cout - oa, _vp(gd),
+          cout + 8, 8, *shape, 0, None)
+    got = _host(ga).reshape(n, oa)
+    if split:
+        got = np.concatenate([got, _host(gb).reshape(n, cout - oa)], axis=1)
+    np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("cs,off,c", [(16, 0, 16), (48, 16, 32)])
+def test_maxpool2_relu_backward_is_the_two_calls(L, ctx, cs, off, c):
+    """The fused pooling + ReLU backward equals ctrex_nn_maxpool2_backward
+    followed by ctrex_nn_relu_backward bit for bit: ties inside windows,
+    windows whose maximum is <= 0, special values, a prefilled din."""
+    shape = (4, 8, 12)
+    n = int(np.prod(shape))
+    r = _rng(45, c)
+    x = _special_relu_out(r, n, cs)
+    x[::7] = np.round(x[::7] * 4) / 4                 # ties
+    x[: n // 2] = -np.abs(x[: n // 2])                 # z planes 0, 1: windows at or below zero
+    g0 = _bf(r.normal(size=(n, cs)))
+    d = _bf(r.normal(size=(n // 8, c)))
+    xd, dd = _dev_bf(x), _dev_bf(d)
+    two, fused = _dev_bf(g0), _dev_bf(g0)
+    _call(L, ctx, "ctrex_nn_maxpool2_backward", _vp(xd), cs, off, c, _vp(dd), _vp(two), *shape,
+          None)
+    _call(L, ctx, "ctrex_nn_relu_backward", _vp(xd), _vp(two), cs, off, c, n, None)
+    _call(L, ctx, "ctrex_nn_maxpool2_relu_backward", _vp(xd), cs, off, c, _vp(dd), _vp(fused),
+          *shape, None)
+    np.testing.assert_array_equal(_host(fused), _host(two))
+
+
+@pytest.mark.parametrize("misaligned", [False, True])
+def test_head_relu_backward_is_head_backward_then_relu(L, ctx, misaligned):
+    n = 4096
+    r = _rng(46)
+    act = _special_relu_out(r, n, 16)
+    act[~np.isfinite(act)] = 0.0   # the parameter gradients need finite activations
+    h = r.normal(size=16).astype(np.float32).astype(np.float64)
+    dout = r.normal(size=n).astype(np.float32).astype(np.float64)
+    sh = 1 if misaligned else 0
+    ad = _dev_bf(np.concatenate([np.zeros(sh), act.reshape(-1)]))[sh:]
+    hd, dd = _dev_f(h), _dev_f(dout)
+    outs = []
+    for fn in ("ctrex_nn_head_backward", "ctrex_nn_head_relu_backward"):
+        dact = torch.empty(n * 16 + sh, dtype=torch.bfloat16, device=DEV)[sh:]
+        dh = torch.empty(16, dtype=torch.float32, device=DEV)
+        db = torch.empty(1, dtype=torch.float32, device=DEV)
+        _call(L, ctx, fn, _vp(ad), 16, _vp(hd), 0.5, None, _vp(dd), _vp(dact), _vp(dh), _vp(db), n,
+              None)
+        outs.append((_host(dact).reshape(n, 16), _host(dh), _host(db)))
+    (d0, h0, b0), (d1, h1, b1) = outs
+    ref = d0.copy()
+    ref[~(act > 0)] = 0
+    np.testing.assert_array_equal(d1, ref)
+    np.testing.assert_array_equal(h1, h0)
+    np.testing.assert_array_equal(b1, b0)
 
 
 # --------------------------------------------------------------- upconv2 ----
