@@ -97,7 +97,8 @@ CTREX_API int ctrex_create(ctrex_ctx **out, int device);
  * and the residual partials (8 per 16x16 detector tile per view).
  * CTREX_ESTATE without a geometry.
  * ctrex_set_scratch attaches `bytes` of device memory at `dev` (NULL, 0
- * detaches).  The library keeps the pointer: the memory must stay allocated
+ * detaches; `dev` 256-byte aligned, as hipMalloc returns it, CTREX_EINVAL
+ * otherwise).  The library keeps the pointer: the memory must stay allocated
  * and must not be written by the caller while calls that use it may run.
  * Calls that need more scratch than is attached return CTREX_EWORKSPACE
  * before launching anything; the library never allocates it itself.  The

@@ -1035,6 +1035,8 @@ int ctrex_scratch_bytes(const ctrex_ctx *c, int32_t n_views, size_t *bytes) {
 int ctrex_set_scratch(ctrex_ctx *c, void *dev, size_t bytes) {
     if (!c) return CTREX_EINVAL;
     if (!dev && bytes) return fail(c, CTREX_EINVAL, "NULL scratch with a non-zero size");
+    if (reinterpret_cast<uintptr_t>(dev) % 256 != 0)
+        return fail(c, CTREX_EINVAL, "scratch must be 256-byte aligned");
     c->user_scratch = bytes ? dev : nullptr;
     c->user_scratch_bytes = dev ? bytes : 0;
     return CTREX_OK;

@@ -770,28 +770,41 @@ __global__ __launch_bounds__(64) void conv3_wgrad_c1_kernel(const u16 *__restric
 // dw[co][ci][tap] = sum over chunks of partial[c][tap][co][ci] (FP64, fixed order).
 // The partials hold a (cout_b x cin_b) block of the gradient, output
 // channels co0 + [0, cout_b), input channels ci0 + [0, cin_b), of a layer
-// with cout x cin channels.  OUTB outputs per block, NT / OUTB slices of the
-// chunks each (slice k sums chunks k, k + NT / OUTB, ...), the slices then
-// added in order: a fixed order in FP64.  Few outputs over many chunks take
-// OUTB = 8 (more slices, more blocks), the others 32.
+// with cout x cin channels.  A block takes OUTB consecutive outputs; its
+// threads read them as 16-byte groups of four, OUTB / 4 threads per chunk row
+// and NT / (OUTB / 4) slices of the chunks (slice k sums chunks k, k + SL,
+// ...; eight rows' loads in flight per thread), then the slices are added in
+// order: a fixed order in FP64.  The output count is a multiple of 4 (cout_b
+// is a multiple of 16).  Few outputs over many chunks take OUTB = 4 (more
+// slices, more blocks), the others 32 (128 contiguous bytes per chunk row).
 template <int OUTB>
 __global__ __launch_bounds__(NT) void reduce_wgrad_kernel(const float *__restrict__ partial,
                                                           int chunks, int taps, int cout_b,
                                                           int cin_b, int co0, int ci0, int cout,
                                                           int cin, int tap_major_out,
                                                           float *__restrict__ dw) {
-    constexpr int SL = NT / OUTB;
+    constexpr int TPO = OUTB / 4, SL = NT / TPO;
     __shared__ double red[SL][OUTB];
     const int n = taps * cout_b * cin_b;
-    const int o = threadIdx.x % OUTB, sl = threadIdx.x / OUTB;
-    const int i = blockIdx.x * OUTB + o;   // the partial's [tap][co][ci] order
-    double sum = 0.0;
-    if (i < n)
-        for (int c = sl; c < chunks; c += SL)
-            sum += static_cast<double>(partial[static_cast<long long>(c) * n + i]);
-    red[sl][o] = sum;
+    const int q = threadIdx.x % TPO, sl = threadIdx.x / TPO;
+    const int i0 = blockIdx.x * OUTB + 4 * q;   // the partial's [tap][co][ci] order
+    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i0 < n) {
+        const float *p = partial + i0;
+#pragma unroll 8
+        for (int c = sl; c < chunks; c += SL) {
+            const float4 v = *reinterpret_cast<const float4 *>(p + static_cast<long long>(c) * n);
+            sum[0] += static_cast<double>(v.x);
+            sum[1] += static_cast<double>(v.y);
+            sum[2] += static_cast<double>(v.z);
+            sum[3] += static_cast<double>(v.w);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[sl][4 * q + j] = sum[j];
     __syncthreads();
-    if (sl != 0 || i >= n) return;
+    const int o = threadIdx.x, i = blockIdx.x * OUTB + o;
+    if (o >= OUTB || i >= n) return;
     double t = 0.0;
     for (int k = 0; k < SL; ++k) t += red[k][o];
     const int tap = i / (cout_b * cin_b);
@@ -807,8 +820,9 @@ hipError_t launch_reduce_wgrad(const float *partial, int chunks, int taps, int c
                                int co0, int ci0, int cout, int cin, int tap_major_out, float *dw,
                                hipStream_t s) {
     const int n = taps * cout_b * cin_b;
-    if (n < 4096 && chunks >= 1024)
-        hipLaunchKernelGGL(reduce_wgrad_kernel<8>, dim3((n + 7) / 8), dim3(NT), 0, s, partial,
+    if (n % 4 != 0 || reinterpret_cast<uintptr_t>(partial) % 16 != 0) return hipErrorInvalidValue;
+    if (n / 32 < 128)
+        hipLaunchKernelGGL(reduce_wgrad_kernel<4>, dim3((n + 3) / 4), dim3(NT), 0, s, partial,
                            chunks, taps, cout_b, cin_b, co0, ci0, cout, cin, tap_major_out, dw);
     else
         hipLaunchKernelGGL(reduce_wgrad_kernel<32>, dim3((n + 31) / 32), dim3(NT), 0, s, partial,
@@ -846,21 +860,28 @@ __global__ __launch_bounds__(NT) void channel_sum_kernel(const u16 *__restrict__
 }
 
 // out[j] = sum_i partial[i * ld + j] for j < cols (FP64, fixed order).
-__global__ __launch_bounds__(NT) void reduce_rows_kernel(const double *__restrict__ partial,
-                                                         int rows, int cols, int ld,
-                                                         float *__restrict__ out) {
-    // 32 columns per block, 8 slices of the rows, added in a fixed order
-    __shared__ double red[NT / 32][32];
+constexpr int RR_THREADS = 1024;   // threads of a row-reduction block
+
+__global__ __launch_bounds__(RR_THREADS) void reduce_rows_kernel(const double *__restrict__ partial,
+                                                                 int rows, int cols, int ld,
+                                                                 float *__restrict__ out) {
+    // 32 columns per block, 32 slices of the rows (eight rows' loads in
+    // flight per thread: the sums are short, so latency, not bandwidth,
+    // bounds them), the slices added in a fixed order
+    constexpr int SL = RR_THREADS / 32;
+    __shared__ double red[SL][32];
     const int o = threadIdx.x & 31, sl = threadIdx.x >> 5;
     const int jc = blockIdx.x * 32 + o;
     double sum = 0.0;
-    if (jc < cols)
-        for (int i = sl; i < rows; i += NT / 32) sum += partial[static_cast<long long>(i) * ld + jc];
+    if (jc < cols) {
+#pragma unroll 8
+        for (int i = sl; i < rows; i += SL) sum += partial[static_cast<long long>(i) * ld + jc];
+    }
     red[sl][o] = sum;
     __syncthreads();
     if (sl != 0 || jc >= cols) return;
     double t = 0.0;
-    for (int k = 0; k < NT / 32; ++k) t += red[k][o];
+    for (int k = 0; k < SL; ++k) t += red[k][o];
     out[jc] = static_cast<float>(t);
 }
 
@@ -1500,8 +1521,8 @@ hipError_t launch_channel_sum(const void *x, int cs, int off, int c, long long n
                        cs, off, c, nvox, scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_rows_kernel, dim3(blocks_for(c, 32)), dim3(NT), 0, s, scratch, blocks, c,
-                       c, out);
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(blocks_for(c, 32)), dim3(RR_THREADS), 0, s,
+                       scratch, blocks, c, c, out);
     return hipGetLastError();
 }
 
@@ -1667,8 +1688,12 @@ hipError_t launch_head_bwd(const void *act, int c, const float *h, float scale, 
 #undef CTREX_NN_HB
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (dh) hipLaunchKernelGGL(reduce_rows_kernel, dim3(blocks_for(c, 32)), dim3(NT), 0, s, scratch, blocks, c, c + 1, dh);
-    if (db) hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(NT), 0, s, scratch + c, blocks, 1, c + 1, db);
+    if (dh)
+        hipLaunchKernelGGL(reduce_rows_kernel, dim3(blocks_for(c, 32)), dim3(RR_THREADS), 0, s,
+                           scratch, blocks, c, c + 1, dh);
+    if (db)
+        hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(RR_THREADS), 0, s, scratch + c,
+                           blocks, 1, c + 1, db);
     return hipGetLastError();
 }
 

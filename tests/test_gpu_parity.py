@@ -371,6 +371,9 @@ def test_calls_need_attached_scratch(tiny, dev):
     torch.cuda.synchronize()
     assert rel_l2(y.cpu().numpy(), g.forward(xt).cpu().numpy()) == 0.0
     assert L.ctrex_set_scratch(ctx, None, 5) == -1
+    # a pointer off the 256-byte alignment is refused (its 16-byte partial
+    # sums would be misaligned)
+    assert L.ctrex_set_scratch(ctx, ctypes.c_void_p(scr.data_ptr() + 8), scr.numel() - 8) == -1
     assert L.ctrex_set_scratch(ctx, None, 0) == 0
     L.ctrex_destroy(ctx)
 
