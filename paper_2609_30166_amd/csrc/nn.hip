@@ -87,13 +87,6 @@ __device__ __forceinline__ Vox decode(long long v, int H, int W) {
     return r;
 }
 
-// Neighbour (voxel + tap offset) index or -1 outside the volume.
-__device__ __forceinline__ long long nbr(const Vox &p, int tap, int D, int H, int W) {
-    const int z = p.z + tap / 9 - 1, y = p.y + (tap / 3) % 3 - 1, x = p.x + tap % 3 - 1;
-    if (z < 0 || z >= D || y < 0 || y >= H || x < 0 || x >= W) return -1;
-    return (static_cast<long long>(z) * H + y) * W + x;
-}
-
 template <bool OUT_F32, bool RELU, bool ACC>
 __device__ __forceinline__ void store_out(void *out, long long idx, float val) {
     if (RELU) val = fmaxf(val, 0.0f);
@@ -715,47 +708,93 @@ __global__ __launch_bounds__(WG_THREADS) void wgrad_tile_kernel(
         }
 }
 
-// Weight gradient, cin == 1: N = taps (27 padded to 32), one wave per chunk.
+// Weight gradient, cin == 1, LDS-tiled on the forward kernel's 16 x 8 x 4
+// tiles: M = cout, N = taps (27 padded to 32, two blocks), K = 32 voxels (two
+// rows of a tile plane).  A workgroup takes a run of consecutive tiles; for
+// each it stages the 18 x 10 x 6 input block in LDS (zeros outside the
+// volume), and wave w takes plane w: per K step a lane reads 8 output-gradient
+// values of its channel (voxels x = 8 (g & 1) + e of row 2 s + (g >> 1)) and
+// its tap's 8 inputs from LDS.  Voxels outside the volume contribute zero on
+// both sides; taps 27 .. 31 read tap 13's inputs and are not stored.  The four
+// waves' sums are added in order and written as the workgroup's partial
+// [27][cout].
 template <int COUT>
-__global__ __launch_bounds__(64) void conv3_wgrad_c1_kernel(const u16 *__restrict__ in, int in_cs,
-                                                            int in_off,
-                                                            const u16 *__restrict__ dout,
-                                                            int dout_cs, int dout_off, int D, int H,
-                                                            int W, long long chunk,
-                                                            float *__restrict__ partial) {
-    constexpr int MBk = COUT / 16;
-    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
-    const long long nvox = static_cast<long long>(D) * H * W;
-    const long long v0 = static_cast<long long>(blockIdx.x) * chunk;
-    const long long v1 = v0 + chunk < nvox ? v0 + chunk : nvox;
+__global__ __launch_bounds__(NT) void conv3_wgrad_c1_tile_kernel(
+    const u16 *__restrict__ in, int in_cs, int in_off, const u16 *__restrict__ dout, int dout_cs,
+    int dout_off, int D, int H, int W, int tiles_per_wg, float *__restrict__ partial) {
+    constexpr int TY = C1_TY, TZ = C1_TZ, SX = 18, SY = TY + 2, SZ = TZ + 2;
+    constexpr int NEL = SX * SY * SZ;
+    constexpr int MBk = COUT / 16, NOUT = 27 * COUT;
+    static_assert(TZ == NT / 64, "a wave owns one z plane of the tile");
+    static_assert(TY % 2 == 0, "K steps take two rows");
+    __shared__ u16 tile[NEL];
+    __shared__ float red[NT / 64][NOUT];
+
+    const int ntx = (W + 15) / 16, nty = (H + TY - 1) / TY, ntz = (D + TZ - 1) / TZ;
+    const long long ntiles = static_cast<long long>(ntx) * nty * ntz;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    const int xs = 8 * (g & 1), rs = g >> 1;   // the lane's 8 voxels: x = xs + e of row 2 s + rs
+    int boff[2];                                // LDS element of tap n 16 + r, voxel (xs, row 0)
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+        int tap = n * 16 + r;
+        if (tap >= 27) tap = 13;
+        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+        boff[n] = ((wave + 1 + dz) * SY + 1 + dy) * SX + xs + 1 + dx;
+    }
     f32x4 acc[MBk][2];
 #pragma unroll
     for (int m = 0; m < MBk; ++m) acc[m][0] = acc[m][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (long long vk = v0; vk < v1; vk += 32) {
-        bf16x8 a[MBk], b[2];
+
+    const long long t0 = static_cast<long long>(blockIdx.x) * tiles_per_wg;
+    const long long t1 = t0 + tiles_per_wg < ntiles ? t0 + tiles_per_wg : ntiles;
+    for (long long t = t0; t < t1; ++t) {
+        const int x0 = static_cast<int>(t % ntx) * 16;
+        const long long tq = t / ntx;
+        const int y0 = static_cast<int>(tq % nty) * TY, z0 = static_cast<int>(tq / nty) * TZ;
+        __syncthreads();   // the previous tile's LDS reads are done
+        constexpr int ITER = (NEL + NT - 1) / NT;
+        u16 v[ITER];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const long long v = vk + 8 * g + e;
-            const bool ok = v < v1;
-            const Vox p = decode(ok ? v : 0, H, W);
-#pragma unroll
-            for (int m = 0; m < MBk; ++m)
-                a[m][e] = ok ? as_bf(dout[v * dout_cs + dout_off + m * 16 + r])
-                             : static_cast<__bf16>(0.0f);
-#pragma unroll
-            for (int n = 0; n < 2; ++n) {
-                const int tap = n * 16 + r;
-                const long long q = ok && tap < 27 ? nbr(p, tap, D, H, W) : -1;
-                b[n][e] = q >= 0 ? as_bf(in[q * in_cs + in_off]) : static_cast<__bf16>(0.0f);
-            }
+        for (int k = 0; k < ITER; ++k) {
+            const int i = threadIdx.x + k * NT;
+            const int x = i % SX, y = (i / SX) % SY, z = i / (SX * SY);
+            const int gx = x0 + x - 1, gy = y0 + y - 1, gz = z0 + z - 1;
+            v[k] = 0;
+            if (i < NEL && gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D)
+                v[k] = in[((static_cast<long long>(gz) * H + gy) * W + gx) * in_cs + in_off];
         }
 #pragma unroll
-        for (int m = 0; m < MBk; ++m)
+        for (int k = 0; k < ITER; ++k) {
+            const int i = threadIdx.x + k * NT;
+            if (i < NEL) tile[i] = v[k];
+        }
+        __syncthreads();
+        const int gz = z0 + wave;
 #pragma unroll
-            for (int n = 0; n < 2; ++n) acc[m][n] = mma(a[m], b[n], acc[m][n]);
+        for (int st = 0; st < TY / 2; ++st) {
+            const int row = 2 * st + rs, gy = y0 + row;
+            bf16x8 a[MBk], b[2];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int gx = x0 + xs + e;
+                const bool ok = gz < D && gy < H && gx < W;
+                const long long vox = ok ? (static_cast<long long>(gz) * H + gy) * W + gx : 0;
+#pragma unroll
+                for (int m = 0; m < MBk; ++m)
+                    a[m][e] = ok ? as_bf(dout[vox * dout_cs + dout_off + m * 16 + r])
+                                 : static_cast<__bf16>(0.0f);
+#pragma unroll
+                for (int n = 0; n < 2; ++n)
+                    b[n][e] = ok ? as_bf(tile[boff[n] + row * SX + e]) : static_cast<__bf16>(0.0f);
+            }
+#pragma unroll
+            for (int m = 0; m < MBk; ++m)
+#pragma unroll
+                for (int n = 0; n < 2; ++n) acc[m][n] = mma(a[m], b[n], acc[m][n]);
+        }
     }
-    // partial layout [chunk][27][COUT][1]
-    float *dst = partial + static_cast<long long>(blockIdx.x) * 27 * COUT;
+    // lane (g, r) holds co = m 16 + 4 g + j, tap = n 16 + r
 #pragma unroll
     for (int m = 0; m < MBk; ++m)
 #pragma unroll
@@ -763,8 +802,16 @@ __global__ __launch_bounds__(64) void conv3_wgrad_c1_kernel(const u16 *__restric
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int tap = n * 16 + r;
-                if (tap < 27) dst[tap * COUT + m * 16 + 4 * g + j] = acc[m][n][j];
+                if (tap < 27) red[wave][tap * COUT + m * 16 + 4 * g + j] = acc[m][n][j];
             }
+    __syncthreads();
+    float *dst = partial + static_cast<long long>(blockIdx.x) * NOUT;
+    for (int i = threadIdx.x; i < NOUT; i += NT) {
+        float sum = red[0][i];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) sum += red[w][i];
+        dst[i] = sum;
+    }
 }
 
 // dw[co][ci][tap] = sum over chunks of partial[c][tap][co][ci] (FP64, fixed order).
@@ -1426,10 +1473,9 @@ long long wgrad_chunk(long long nvox) {
     return chunk < 512 ? 512 : chunk;
 }
 
-// One input channel: one wave per chunk gathers its 27 taps per voxel, so
-// many small chunks (about 8192, at least 512 voxels each) keep enough waves
-// in flight to hide the gathers' latency; the partials stay small (27 cout
-// floats per chunk).
+// One input channel: at most about 8192 partials (chunks of at least 512
+// voxels), each the sum of one workgroup's run of tiles; they stay small (27
+// cout floats each).
 long long wgrad_c1_chunk(long long nvox) {
     long long chunk = (nvox + 8191) / 8192;
     chunk = (chunk + 31) / 32 * 32;
@@ -1453,13 +1499,18 @@ hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin_a, 
     const u16 *ip = static_cast<const u16 *>(in), *dp = static_cast<const u16 *>(dout);
     if (cin == 1) {
         if (cout != 16 || cin_b != 0) return hipErrorInvalidValue;
+        // at most as many workgroups (partials) as the scratch sizing assumes
         const long long c1 = wgrad_c1_chunk(nvox);
-        const int n1 = static_cast<int>((nvox + c1 - 1) / c1);
-        hipLaunchKernelGGL((conv3_wgrad_c1_kernel<16>), dim3(n1), dim3(64), 0, s, ip, in_cs,
-                           in_off, dp, dout_cs, dout_off, D, H, W, c1, scratch);
+        const long long n1 = (nvox + c1 - 1) / c1;
+        const long long ntiles = static_cast<long long>((W + 15) / 16) * ((H + C1_TY - 1) / C1_TY) *
+                                 ((D + C1_TZ - 1) / C1_TZ);
+        const long long per = (ntiles + n1 - 1) / n1;
+        const int wgs = static_cast<int>((ntiles + per - 1) / per);
+        hipLaunchKernelGGL((conv3_wgrad_c1_tile_kernel<16>), dim3(wgs), dim3(NT), 0, s, ip, in_cs,
+                           in_off, dp, dout_cs, dout_off, D, H, W, static_cast<int>(per), scratch);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        return launch_reduce_wgrad(scratch, n1, 27, cout, 1, 0, 0, cout, 1, 0, dw, s);
+        return launch_reduce_wgrad(scratch, wgs, 27, cout, 1, 0, 0, cout, 1, 0, dw, s);
     }
     const auto chan_ok = [](int c) { return c == 16 || c == 32 || c == 64; };
     if (!chan_ok(cin_a) || (cin_b != 0 && !chan_ok(cin_b)) || cin > 64 || !chan_ok(cout))
