@@ -1108,6 +1108,40 @@ __global__ __launch_bounds__(NT) void maxpool2_kernel(const u16 *__restrict__ in
     out[i] = f2bf(m);
 }
 
+// The same, 8 channels per thread (16-byte loads and store): channel counts,
+// strides and offsets multiples of 8, 16-byte aligned tensors.  Each channel
+// takes the same fmaxf sequence as above, so the results are identical.
+__global__ __launch_bounds__(NT) void maxpool2_vec8_kernel(const u16 *__restrict__ in, int in_cs,
+                                                           int in_off, int c8,
+                                                           u16 *__restrict__ out, int D, int H,
+                                                           int W) {
+    const int Do = D / 2, Ho = H / 2, Wo = W / 2;
+    const long long n = static_cast<long long>(Do) * Ho * Wo * c8;
+    const long long i = static_cast<long long>(blockIdx.x) * NT + threadIdx.x;
+    if (i >= n) return;
+    const long long pv = i / c8;
+    const int ch = 8 * static_cast<int>(i - pv * c8);
+    const Vox p = decode(pv, Ho, Wo);
+    float m[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) m[j] = -__builtin_inff();
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        const long long q = (static_cast<long long>(2 * p.z + (a >> 2)) * H + 2 * p.y + ((a >> 1) & 1)) * W +
+                            2 * p.x + (a & 1);
+        const uint4 v = *reinterpret_cast<const uint4 *>(in + q * in_cs + in_off + ch);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            m[j] = fmaxf(m[j], __uint_as_float(j & 1 ? w[j >> 1] & 0xffff0000u : w[j >> 1] << 16));
+    }
+    uint32_t o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        o[k] = static_cast<uint32_t>(f2bf(m[2 * k])) | (static_cast<uint32_t>(f2bf(m[2 * k + 1])) << 16);
+    *reinterpret_cast<uint4 *>(out + pv * (8 * c8) + ch) = make_uint4(o[0], o[1], o[2], o[3]);
+}
+
 // RELU: then the ReLU derivative at in, over every input element: din is
 // zeroed where in <= 0 (or NaN) and left as it is elsewhere, so only the
 // arg-max element's din is read.
@@ -1662,6 +1696,13 @@ hipError_t launch_upconv2_wgrad(const void *in, int in_cs, int in_off, int cin, 
 hipError_t launch_maxpool2(const void *in, int in_cs, int in_off, int c, void *out, int D, int H,
                            int W, hipStream_t s) {
     const long long n = static_cast<long long>(D / 2) * (H / 2) * (W / 2) * c;
+    if (c % 8 == 0 && in_cs % 8 == 0 && in_off % 8 == 0 &&
+        (reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) % 16 == 0) {
+        hipLaunchKernelGGL(maxpool2_vec8_kernel, dim3(blocks_for(n / 8)), dim3(NT), 0, s,
+                           static_cast<const u16 *>(in), in_cs, in_off, c / 8,
+                           static_cast<u16 *>(out), D, H, W);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(maxpool2_kernel, dim3(blocks_for(n)), dim3(NT), 0, s,
                        static_cast<const u16 *>(in), in_cs, in_off, c, static_cast<u16 *>(out), D, H, W);
     return hipGetLastError();

@@ -380,7 +380,7 @@ def test_conv3_gate_is_relu_backward_of_the_output(L, ctx, cin, cout, split):
     np.testing.assert_array_equal(got, ref)
 
 
-@pytest.mark.parametrize("cs,off,c", [(16, 0, 16), (48, 16, 32)])
+@pytest.mark.parametrize("cs,off,c", [(16, 0, 16), (48, 16, 32), (20, 4, 12)])
 def test_maxpool2_relu_backward_is_the_two_calls(L, ctx, cs, off, c):
     """The fused pooling + ReLU backward equals ctrex_nn_maxpool2_backward
     followed by ctrex_nn_relu_backward bit for bit: ties inside windows,
@@ -535,9 +535,11 @@ def test_upconv2_accumulate_unaligned_slice(L, ctx, cin, cout):
 
 
 # --------------------------------------------------------- elementwise ops --
-def test_maxpool_and_backward_bit_exact(L, ctx):
+@pytest.mark.parametrize("cs,off,c", [(32, 16, 16), (20, 4, 12)])
+def test_maxpool_and_backward_bit_exact(L, ctx, cs, off, c):
+    """8-channel vector pooling for aligned slices, element pooling otherwise."""
     from oracle import unet as ou
-    shape, c, cs, off = (4, 8, 12), 16, 32, 16
+    shape = (4, 8, 12)
     n = int(np.prod(shape))
     r = _rng(8)
     xw = _bf(np.round(r.normal(size=(n, cs)) * 4) / 4)   # ties inside windows
