@@ -529,16 +529,23 @@ conv3_tile_kernel(const u16 *__restrict__ in, int in_cs, int in_off, const u16 *
 // output-gradient rows y' - dy, so one LDS read feeds about two MFMAs.  The
 // nine taps' sums stay in registers over all the units of the workgroup, which
 // writes them once as its partial (summed over workgroups in a fixed order).
+// With bias_part set, the workgroup also sums the output gradient per channel
+// (the bias gradient) as it stages it: each thread always stages the same 8
+// channels, keeps FP64 sums, and the threads' sums are added in a fixed order
+// into bias_part[block][bias_off + co] (row stride bias_ld).
 constexpr int WG_X = 32, WG_Y = 4, WG_IX = 48, WG_IY = WG_Y + 2, WG_THREADS = 192;
 
 __device__ __forceinline__ uint32_t funnel16(uint32_t hi, uint32_t lo) {
     return __builtin_amdgcn_alignbit(hi, lo, 16);
 }
 
+// (16 -> 16 keeps four waves per SIMD with the bias sums: 126 registers)
 template <int CIN, int COUT>
-__global__ __launch_bounds__(WG_THREADS) void wgrad_tile_kernel(
+__global__ __launch_bounds__(WG_THREADS) __attribute__((amdgpu_waves_per_eu(
+    CIN == 16 && COUT == 16 ? 4 : 1))) void wgrad_tile_kernel(
     const u16 *__restrict__ in, int in_cs, int in_off, const u16 *__restrict__ dout, int dout_cs,
-    int dout_off, int D, int H, int W, int zseg, int units, float *__restrict__ partial) {
+    int dout_off, int D, int H, int W, int zseg, int units, float *__restrict__ partial,
+    double *__restrict__ bias_part, int bias_ld, int bias_off) {
     constexpr int MBk = COUT / 16, NBk = CIN / 16;
     // input rows: x' = x + 8 for x in [-8, 40) (the lanes read x in [-2, 34))
     __shared__ __attribute__((aligned(16))) u16 inT[3][CIN][WG_IY][WG_IX];
@@ -564,6 +571,8 @@ __global__ __launch_bounds__(WG_THREADS) void wgrad_tile_kernel(
     constexpr int NEL_I = WG_IY * NXS * NCH_I, IT_I = (NEL_I + WG_THREADS - 1) / WG_THREADS;
     constexpr int NCH_D = COUT / 8;
     constexpr int NEL_D = WG_Y * WG_X * NCH_D, IT_D = (NEL_D + WG_THREADS - 1) / WG_THREADS;
+    static_assert(WG_THREADS % NCH_D == 0, "a thread stages the same 8 channels throughout");
+    double bsum[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     auto load_in = [&](int zi, int x0, int y0, uint4 (&v)[IT_I]) {
 #pragma unroll
         for (int k = 0; k < IT_I; ++k) {
@@ -646,6 +655,17 @@ __global__ __launch_bounds__(WG_THREADS) void wgrad_tile_kernel(
                 load_dout(z, x0, y0, vd);
                 store_in(z + 1, vi);
                 store_dout(vd);
+                if (bias_part) {   // zeros outside the volume
+#pragma unroll
+                    for (int k = 0; k < IT_D; ++k) {
+                        if (threadIdx.x + k * WG_THREADS >= NEL_D) continue;
+                        const uint32_t wv[4] = {vd[k].x, vd[k].y, vd[k].z, vd[k].w};
+#pragma unroll
+                        for (int j = 0; j < 8; ++j)
+                            bsum[j] += static_cast<double>(__uint_as_float(
+                                j & 1 ? wv[j >> 1] & 0xffff0000u : wv[j >> 1] << 16));
+                    }
+                }
             }
             __syncthreads();
             // this wave's input plane z + dz
@@ -706,6 +726,22 @@ __global__ __launch_bounds__(WG_THREADS) void wgrad_tile_kernel(
                     for (int j = 0; j < 4; ++j)
                         dst[(tap * COUT + m * 16 + 4 * g + j) * CIN + n * 16 + r] = acc[a][b][m][n][j];
         }
+    if (bias_part) {
+        // the staging buffers are free: the threads' sums through LDS, added
+        // in thread order per channel
+        double *red = reinterpret_cast<double *>(&inT[0][0][0][0]);
+        static_assert(sizeof(inT) >= sizeof(double) * 8 * WG_THREADS, "room for the sums");
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 8; ++j) red[threadIdx.x * 8 + j] = bsum[j];
+        __syncthreads();
+        if (static_cast<int>(threadIdx.x) < COUT) {
+            const int c = threadIdx.x / 8, j = threadIdx.x % 8;
+            double t = 0.0;
+            for (int u = c; u < WG_THREADS; u += NCH_D) t += red[u * 8 + j];
+            bias_part[static_cast<long long>(blockIdx.x) * bias_ld + bias_off + threadIdx.x] = t;
+        }
+    }
 }
 
 // Weight gradient, cin == 1, LDS-tiled on the forward kernel's 16 x 8 x 4
@@ -1516,23 +1552,31 @@ long long wgrad_c1_chunk(long long nvox) {
     return chunk < 512 ? 512 : chunk;
 }
 
+// Bytes of the weight partials, rounded up to 256 (the bias partials follow).
+size_t wgrad_partial_bytes(long long chunks, int cin, int cout) {
+    const size_t b = sizeof(float) * static_cast<size_t>(chunks) * 27 * cin * cout;
+    return (b + 255) / 256 * 256;
+}
+
 size_t conv3_wgrad_scratch(int cin, int cout, long long nvox) {
     const long long ch = cin == 1 ? wgrad_c1_chunk(nvox) : wgrad_chunk(nvox);
     const long long chunks = (nvox + ch - 1) / ch;
-    return sizeof(float) * static_cast<size_t>(chunks) * 27 * cin * cout;
+    // cin > 1: FP64 bias partials [chunks][cout] after the weight partials
+    return wgrad_partial_bytes(chunks, cin, cout) +
+           (cin > 1 ? sizeof(double) * static_cast<size_t>(chunks) * cout : 0);
 }
 
 hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin_a, const void *in2,
                               int in2_cs, int in2_off, int cin_b, const void *dout, int dout_cs,
                               int dout_off, int cout, int D, int H, int W, float *dw,
-                              float *scratch, hipStream_t s) {
+                              float *dbias, float *scratch, hipStream_t s) {
     const int cin = cin_a + cin_b;
     const long long nvox = static_cast<long long>(D) * H * W;
     const long long chunk = wgrad_chunk(nvox);
     const int chunks = static_cast<int>((nvox + chunk - 1) / chunk);
     const u16 *ip = static_cast<const u16 *>(in), *dp = static_cast<const u16 *>(dout);
     if (cin == 1) {
-        if (cout != 16 || cin_b != 0) return hipErrorInvalidValue;
+        if (cout != 16 || cin_b != 0 || dbias) return hipErrorInvalidValue;
         // at most as many workgroups (partials) as the scratch sizing assumes
         const long long c1 = wgrad_c1_chunk(nvox);
         const long long n1 = (nvox + c1 - 1) / c1;
@@ -1570,16 +1614,21 @@ hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin_a, 
     const Source src[2] = {{ip, in_cs, in_off, cin_a, 0},
                            {static_cast<const u16 *>(in2), in2_cs, in2_off, cin_b, cin_a}};
     float *part = scratch;
+    // bias partials [parts][cout] (FP64) after all weight partials; the first
+    // input block of each output block sums its output gradient
+    double *bpart = reinterpret_cast<double *>(reinterpret_cast<char *>(scratch) +
+                                               wgrad_partial_bytes(parts, cin, cout));
     for (int co0 = 0; co0 < cout; co0 += cob)
         for (const Source &sc : src) {
             const int cib = sc.c < 32 ? sc.c : 32;
             for (int l = 0; l < sc.c; l += cib) {
+                double *bp = dbias && &sc == &src[0] && l == 0 ? bpart : nullptr;
 #define CTREX_NN_WGT(CI, CO)                                                                      \
                 if (cib == CI && cob == CO)                                                       \
                     hipLaunchKernelGGL((wgrad_tile_kernel<CI, CO>), dim3(parts),                  \
                                        dim3(WG_THREADS), 0, s, sc.p, sc.cs, sc.off + l, dp,       \
                                        dout_cs, dout_off + co0, D, H, W, zseg,                    \
-                                       static_cast<int>(units), part);
+                                       static_cast<int>(units), part, bp, cout, co0);
                 CTREX_NN_WGT(16, 16)
                 CTREX_NN_WGT(16, 32)
                 CTREX_NN_WGT(32, 16)
@@ -1593,7 +1642,10 @@ hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin_a, 
                 part += static_cast<long long>(parts) * 27 * cob * cib;
             }
         }
-    return hipSuccess;
+    if (dbias)
+        hipLaunchKernelGGL(reduce_rows_kernel, dim3(blocks_for(cout, 32)), dim3(RR_THREADS), 0, s,
+                           bpart, parts, cout, cout, dbias);
+    return hipGetLastError();
 }
 
 size_t channel_sum_scratch(int c) { return sizeof(double) * 1024 * static_cast<size_t>(c); }

@@ -20,7 +20,7 @@ size_t conv3_wgrad_scratch(int cin, int cout, long long nvox);
 hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin_a, const void *in2,
                               int in2_cs, int in2_off, int cin_b, const void *dout, int dout_cs,
                               int dout_off, int cout, int D, int H, int W, float *dw,
-                              float *scratch, hipStream_t s);
+                              float *dbias, float *scratch, hipStream_t s);
 size_t channel_sum_scratch(int c);
 hipError_t launch_channel_sum(const void *x, int cs, int off, int c, long long nvox, float *out,
                               double *scratch, hipStream_t s);
@@ -206,9 +206,11 @@ int ctrex_nn_conv3_wgrad(ctrex_ctx *c, const void *in, int32_t in_cs, int32_t in
     void *scr;
     if ((st = ctx_scratch(c, need, &scr))) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // the tiled weight gradient sums the bias gradient as it stages dout
     CTREX_HIP(c, nn::launch_conv3_wgrad(in, in_cs, in_off, cin, nullptr, 0, 0, 0, dout, dout_cs,
-                                        dout_off, cout, D, H, W, dw, static_cast<float *>(scr), s));
-    if (dbias)
+                                        dout_off, cout, D, H, W, dw, cin > 1 ? dbias : nullptr,
+                                        static_cast<float *>(scr), s));
+    if (dbias && cin == 1)
         CTREX_HIP(c, nn::launch_channel_sum(dout, dout_cs, dout_off, cout, n, dbias,
                                             static_cast<double *>(scr), s));
     return CTREX_OK;
@@ -235,10 +237,8 @@ int ctrex_nn_conv3_wgrad_cat(ctrex_ctx *c, const void *in_a, int32_t a_cs, int32
     if ((st = ctx_scratch(c, need, &scr))) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     CTREX_HIP(c, nn::launch_conv3_wgrad(in_a, a_cs, a_off, ca, in_b, b_cs, b_off, cb, dout, dout_cs,
-                                        dout_off, cout, D, H, W, dw, static_cast<float *>(scr), s));
-    if (dbias)
-        CTREX_HIP(c, nn::launch_channel_sum(dout, dout_cs, dout_off, cout, n, dbias,
-                                            static_cast<double *>(scr), s));
+                                        dout_off, cout, D, H, W, dw, dbias,
+                                        static_cast<float *>(scr), s));
     return CTREX_OK;
 }
 
