@@ -1314,7 +1314,12 @@ __global__ __launch_bounds__(NT) void head_bwd_kernel(const u16 *__restrict__ ac
     for (int k = 0; k <= C; ++k) acc[k] = 0.0;
     const long long stride = static_cast<long long>(gridDim.x) * NT;
     static_assert(C % 8 == 0, "8 channels per 16-byte access");
-    for (long long v = static_cast<long long>(blockIdx.x) * NT + threadIdx.x; v < n; v += stride) {
+    // a counted loop (unrolled by 4), so several voxels' loads are in flight
+    const long long v0 = static_cast<long long>(blockIdx.x) * NT + threadIdx.x;
+    const int iters = v0 < n ? static_cast<int>((n - v0 + stride - 1) / stride) : 0;
+#pragma unroll 4
+    for (int it = 0; it < iters; ++it) {
+        const long long v = v0 + it * stride;
         const float d = (mask ? scale * mask[v] : scale) * dout[v];
         if constexpr (!VEC) {   // act or dact not 16-byte aligned
 #pragma unroll
