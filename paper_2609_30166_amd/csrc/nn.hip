@@ -547,6 +547,10 @@ __global__ __launch_bounds__(WG_THREADS) __attribute__((amdgpu_waves_per_eu(
     int dout_off, int D, int H, int W, int zseg, int units, float *__restrict__ partial,
     double *__restrict__ bias_part, int bias_ld, int bias_off) {
     constexpr int MBk = COUT / 16, NBk = CIN / 16;
+    // the next plane is loaded during this plane's MFMAs, where the extra
+    // registers cost no occupancy (all but 16 -> 16, which keeps four waves
+    // per SIMD in 128 registers without it)
+    constexpr bool PIPE = !(CIN == 16 && COUT == 16);
     // input rows: x' = x + 8 for x in [-8, 40) (the lanes read x in [-2, 34))
     __shared__ __attribute__((aligned(16))) u16 inT[3][CIN][WG_IY][WG_IX];
     __shared__ __attribute__((aligned(16))) u16 dT[COUT][WG_Y][WG_X];
@@ -645,27 +649,43 @@ __global__ __launch_bounds__(WG_THREADS) __attribute__((amdgpu_waves_per_eu(
         const int y0 = (t % ty) * WG_Y;
         const int za = (t / ty) * zseg;
         const int zb = za + zseg < D ? za + zseg : D;
+        auto add_bias = [&](const uint4 (&vd)[IT_D]) {
+            if (!bias_part) return;   // zeros outside the volume
+#pragma unroll
+            for (int k = 0; k < IT_D; ++k) {
+                if (threadIdx.x + k * WG_THREADS >= NEL_D) continue;
+                const uint32_t wv[4] = {vd[k].x, vd[k].y, vd[k].z, vd[k].w};
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    bsum[j] += static_cast<double>(
+                        __uint_as_float(j & 1 ? wv[j >> 1] & 0xffff0000u : wv[j >> 1] << 16));
+            }
+        };
         __syncthreads();   // the previous unit's reads are done
         stage_in(za - 1, x0, y0);
         stage_in(za, x0, y0);
+        if constexpr (PIPE) {   // plane za + 1 and the output gradient of za
+            uint4 vi[IT_I], vd[IT_D];
+            load_in(za + 1, x0, y0, vi);
+            load_dout(za, x0, y0, vd);
+            store_in(za + 1, vi);
+            store_dout(vd);
+            add_bias(vd);
+        }
         for (int z = za; z < zb; ++z) {
-            {
-                uint4 vi[IT_I], vd[IT_D];
+            uint4 vi[IT_I], vd[IT_D];
+            if constexpr (!PIPE) {
                 load_in(z + 1, x0, y0, vi);
                 load_dout(z, x0, y0, vd);
                 store_in(z + 1, vi);
                 store_dout(vd);
-                if (bias_part) {   // zeros outside the volume
-#pragma unroll
-                    for (int k = 0; k < IT_D; ++k) {
-                        if (threadIdx.x + k * WG_THREADS >= NEL_D) continue;
-                        const uint32_t wv[4] = {vd[k].x, vd[k].y, vd[k].z, vd[k].w};
-#pragma unroll
-                        for (int j = 0; j < 8; ++j)
-                            bsum[j] += static_cast<double>(__uint_as_float(
-                                j & 1 ? wv[j >> 1] & 0xffff0000u : wv[j >> 1] << 16));
-                    }
-                }
+                add_bias(vd);
+            } else if (z + 1 < zb) {
+                // the next plane's loads stay in flight while this plane's
+                // MFMAs run; they go to LDS after the barrier below, into the
+                // ring slot of plane z - 1
+                load_in(z + 2, x0, y0, vi);
+                load_dout(z + 1, x0, y0, vd);
             }
             __syncthreads();
             // this wave's input plane z + dz
@@ -709,6 +729,13 @@ __global__ __launch_bounds__(WG_THREADS) __attribute__((amdgpu_waves_per_eu(
                 }
             }
             __syncthreads();
+            if constexpr (PIPE) {
+                if (z + 1 < zb) {
+                    store_in(z + 2, vi);
+                    store_dout(vd);
+                    add_bias(vd);
+                }
+            }
         }
     }
     // partial[block][tap][co][ci]: lane (g, r) holds co = 16 m + 4 g + j, ci = 16 n + r
