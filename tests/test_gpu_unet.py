@@ -213,6 +213,27 @@ def test_conv3_weight_gradient(L, ctx, shape, cin, cout):
     _close(_host(db), b.grad.numpy())
 
 
+@pytest.mark.parametrize("shape", [(8, 8, 17), (12, 16, 17), (2, 18, 16), (4, 4, 36)])
+def test_conv3_weight_gradient_one_channel_tile_runs(L, ctx, shape):
+    """The one-channel weight gradient with workgroups that each take a run of
+    2 tiles of 16 x 8 x 4 voxels (ragged sides make the tile count exceed the
+    partial count; for 2 x 18 x 16 and 4 x 4 x 36 the last run is one tile)."""
+    from oracle import unet as ou
+    r = _rng(47, *shape)
+    x = _bf(r.normal(size=shape + (1,)))
+    g = _bf(r.normal(size=shape + (16,)))
+    w = torch.zeros((16, 1, 27), dtype=torch.float64, requires_grad=True)
+    b = torch.zeros(16, dtype=torch.float64, requires_grad=True)
+    (ou.conv3(torch.tensor(x), w, b) * torch.tensor(g)).sum().backward()
+    xd, gd = _dev_bf(x), _dev_bf(g)
+    dw = torch.empty(16 * 27, dtype=torch.float32, device=DEV)
+    db = torch.empty(16, dtype=torch.float32, device=DEV)
+    _call(L, ctx, "ctrex_nn_conv3_wgrad", _vp(xd), 1, 0, 1, _vp(gd), 16, 0, 16, *shape, _vp(dw),
+          _vp(db), None)
+    _close(_host(dw).reshape(16, 1, 27), w.grad.numpy())
+    _close(_host(db), b.grad.numpy())
+
+
 @pytest.mark.parametrize("cin,cout,xs,xo,gs,go", [(32, 16, 64, 32, 32, 16),
                                                    (64, 32, 96, 32, 64, 32),
                                                    (64, 64, 72, 8, 80, 16)])
