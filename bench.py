@@ -337,9 +337,10 @@ def unet_flops(n):
 
 def unet_run(dev, args, n=256, reps=5):
     """The correction U-Net alone on a 256^3 volume (He-normal weights from a
-    seed, uniform synthetic input): forward pass and one training step
-    (forward, MSE, backward, Adam), mean of ``reps`` after one warm-up, timed
-    with HIP events on the library's launch stream."""
+    seed, uniform synthetic input): forward pass (launched kernel by kernel,
+    and as replays of its captured HIP graph) and one training step (forward,
+    MSE, backward, Adam), mean of ``reps`` after one warm-up, timed with HIP
+    events on the library's launch stream."""
     import torch
 
     from paper_2609_30166_amd.unet import UNet
@@ -362,13 +363,16 @@ def unet_run(dev, args, n=256, reps=5):
 
     out = torch.empty_like(x)
     fwd_ms = timed(lambda: net.forward(x, out=out))
+    graph = net.capture_forward(x, out)
+    graph_ms = timed(graph.replay)
+    del graph
     step_ms = timed(lambda: net.train_step(x, t))
     f = unet_flops(n)
     peak = 2.5e15
     del net, x, t, out
     return {"workload": "U-Net 16/32/64 channels, 3 levels, BF16 activations, FP32 "
                         "accumulation, %d^3 volume, batch 1" % n,
-            "forward_ms": fwd_ms, "train_step_ms": step_ms,
+            "forward_ms": fwd_ms, "forward_graph_ms": graph_ms, "train_step_ms": step_ms,
             "forward_gflop": f / 1e9,
             "forward_tflops": f / (fwd_ms * 1e-3) / 1e12,
             "forward_frac_of_bf16_peak": f / (fwd_ms * 1e-3) / peak,

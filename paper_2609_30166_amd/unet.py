@@ -183,12 +183,17 @@ class UNet:
         self._pack()
 
     def _pack(self):
-        """BF16 packings of every layer: forward and data-gradient layouts."""
-        self._wt, self._wd = {}, {}
+        """BF16 packings of every layer: forward and data-gradient layouts,
+        rewritten in place after the first call (a captured forward graph
+        reads them at fixed addresses)."""
+        if not getattr(self, "_wt", None):
+            self._wt, self._wd = {}, {}
         for name, kind, cin, cout in LAYERS:
             taps = 27 if kind == "conv" else 8
-            wt = torch.empty(taps * cin * cout, dtype=torch.bfloat16, device=self.device)
-            wd = torch.empty_like(wt)
+            wt, wd = self._wt.get(name), self._wd.get(name)
+            if wt is None:
+                wt = torch.empty(taps * cin * cout, dtype=torch.bfloat16, device=self.device)
+                wd = torch.empty_like(wt)
             w = self.p(name + ".w")
             if kind == "conv":
                 self._call("ctrex_nn_pack_conv3", _vp(w), cout, cin, _vp(wt), _vp(wd), self._s())
@@ -330,6 +335,22 @@ class UNet:
                    p2=(3, 32), a3=(3, 64), b3=(3, 64))
         return {k: b[k].view(*dims[lv], c) for k, (lv, c) in lay.items()}
 
+    def capture_forward(self, x, out, mask=None):
+        """The inference forward pass on ``x`` into ``out`` (and ``mask``), at
+        their present addresses, captured once as a HIP graph: the returned
+        object's ``replay()`` launches all of its kernels with one call on the
+        current stream, without the host round trip per kernel.  Replays read
+        the current parameters (biases in place, packed weights rewritten in
+        place by every optimizer step) and the present contents of ``x`` and
+        ``mask``; a change of the input scale needs a new capture."""
+        self.forward(x, out=out, mask=mask)   # buffers and packings exist
+        torch.cuda.synchronize(self.device)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.forward(x, out=out, mask=mask)
+        return _ForwardGraph(self, g, (x, out, mask, self._buffers(tuple(x.shape), False),
+                                       dict(self._wt)))
+
     # ------------------------------------------------------------- backward
     def _relu_bwd(self, y, g, cs, off, c, n):
         self._call("ctrex_nn_relu_backward", _vp(y), _vp(g), cs, off, c, n, self._s())
@@ -454,3 +475,16 @@ class UNet:
         self.backward(b["dout"].view_as(x))
         self.adam(lr)
         return loss
+
+
+class _ForwardGraph:
+    """A captured U-Net forward pass (see UNet.capture_forward); it keeps the
+    tensors the graph reads and writes alive."""
+
+    def __init__(self, net, graph, keep):
+        self._net, self._graph, self._keep, self._scale = net, graph, keep, net.scale
+
+    def replay(self):
+        if self._net.scale != self._scale:
+            raise RuntimeError("the input scale changed since the capture; capture again")
+        self._graph.replay()

@@ -834,3 +834,33 @@ def test_network_full_size_sampled_against_oracle():
     ref_b = ref[blk, blk, blk]
     xb = crop.numpy()[blk, blk, blk]
     _net_close(got_b - xb, ref_b - xb)
+
+
+def test_captured_forward_replays_match_eager():
+    """The forward pass captured as one HIP graph: every replay equals the
+    eager pass bit for bit, with eager passes (on the same intermediate
+    buffers) between the replays, after new input contents, and after an
+    optimizer step (the packed weights are rewritten in place)."""
+    _skip()
+    shape = (16, 16, 32)
+    net = _rand_net(6)
+    r = _rng(48)
+    x = _dev_f(r.uniform(0, 1, size=shape).astype(np.float32))
+    out = torch.empty_like(x)
+    graph = net.capture_forward(x, out)
+    for _ in range(3):
+        out.fill_(-1.0)
+        graph.replay()
+        got = _host(out)
+        np.testing.assert_array_equal(got, _host(net.forward(x)))
+    x.copy_(_dev_f(r.uniform(0, 1, size=shape).astype(np.float32)))
+    graph.replay()
+    got = _host(out)
+    np.testing.assert_array_equal(got, _host(net.forward(x)))
+    t = x + 0.05
+    net.train_step(x, t)
+    graph.replay()
+    got = _host(out)
+    ref = _host(net.forward(x))
+    np.testing.assert_array_equal(got, ref)
+    assert not np.array_equal(got, _host(x))   # the correction is not empty
