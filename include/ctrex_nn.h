@@ -129,6 +129,21 @@ CTREX_API int ctrex_nn_conv3_wgrad_cat(ctrex_ctx *ctx, const void *in_a, int32_t
                                        void *stream);
 
 /*
+ * The last decoder convolution with the head folded in: a = BF16(ReLU(bias +
+ * conv3x3x3(in, w))) for 16 -> 16 channels (packing as ctrex_nn_conv3), then
+ * out[v] = x[v] + m[v] out_scale (hb[0] + sum_c h[c] a[v][c]) as
+ * ctrex_nn_head computes it (the 16 products are summed in another order, so
+ * results may differ from the two calls in the last bits).  `act` (BF16,
+ * channel stride act_cs, offset act_off; NULL = not stored) receives a, which
+ * only training needs; `mask` as in ctrex_nn_head.
+ */
+CTREX_API int ctrex_nn_conv3_head(ctrex_ctx *ctx, const void *in, int32_t in_cs, int32_t in_off,
+                                  const void *wt, const float *bias, void *act, int32_t act_cs,
+                                  int32_t act_off, const float *h, const float *hb,
+                                  const float *x, float out_scale, const float *mask, float *out,
+                                  int32_t D, int32_t H, int32_t W, void *stream);
+
+/*
  * 2x2x2 stride-2 transposed convolution (up-sampling): the input is
  * D x H x W, the output 2D x 2H x 2W; out[2i + a][co] = bias[co] +
  * sum_ci in[i][ci] w[a][co][ci], `wt` packed BF16 [8][cout][cin].

@@ -98,6 +98,9 @@ def lib():
             "ctrex_nn_conv3_cat": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, i32, i32, i32, vp,
                                                   vp, vp, i32, i32, i32, vp, i32, i32, i32, vp,
                                                   i32, i32, i32, i32, i32, u32, vp]),
+            "ctrex_nn_conv3_head": (ctypes.c_int, [vp, vp, i32, i32, vp, vp, vp, i32, i32, vp, vp,
+                                                   vp, ctypes.c_float, vp, vp, i32, i32, i32,
+                                                   vp]),
             "ctrex_nn_conv3_wgrad_cat": (ctypes.c_int, [vp, vp, i32, i32, i32, vp, i32, i32, i32,
                                                         vp, i32, i32, i32, i32, i32, i32, vp, vp,
                                                         vp]),

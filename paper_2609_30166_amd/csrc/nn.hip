@@ -261,12 +261,23 @@ struct CatArgs {
     int gate_cs, gate_off;
 };
 
+// The 1x1x1 head folded into a 16-output ReLU convolution (BF16 output, no
+// accumulate, one input tensor): with `out` set, out[v] = x[v] + s_v (b +
+// sum_c h[c] a[v][c]), a = the BF16-rounded activations and s_v = scale
+// (times mask[v] if given); the activations are stored only if write_act.
+struct HeadArgs {
+    const float *h, *b, *x, *mask;
+    float scale;
+    float *out;
+    int write_act;
+};
+
 template <int CIN, int COUT, bool OUT_F32, bool RELU, bool ACC, bool CAT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
     CIN == 16 ? (COUT == 16 ? 4 : 1) : (COUT <= 32 ? 3 : 2)))) void
 conv3_tile_kernel(const u16 *__restrict__ in, int in_cs, int in_off, const u16 *__restrict__ wt,
                   const float *__restrict__ bias, void *out, int out_cs, int out_off, int D, int H,
-                  int W, int out_vec, CatArgs cat) {
+                  int W, int out_vec, CatArgs cat, HeadArgs head) {
     constexpr int TY = ConvTile<CIN, COUT>::TY, TZ = ConvTile<CIN, COUT>::TZ;
     constexpr int CST = CIN < 32 ? CIN : 32;  // channels staged at a time
     constexpr int NH = CIN / CST;             // staging passes
@@ -457,6 +468,57 @@ conv3_tile_kernel(const u16 *__restrict__ in, int in_cs, int in_off, const u16 *
     // per wave (a channel slice at a stride and offset not multiple of 4
     // stores element by element)
     const int gz = z0 + zm, gx = x0 + r;
+    if constexpr (COUT == 16 && RELU && !ACC && !OUT_F32 && !CAT) {
+        if (head.out) {
+            // lane (g, r): channels 4 g .. 4 g + 3 of voxel r of each row; the
+            // four lane groups' partial dot products are added in a fixed
+            // order across lanes (xor 16, then xor 32)
+            float hh[4], bco[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                hh[j] = head.h[4 * g + j];
+                bco[j] = bias ? bias[4 * g + j] : 0.0f;
+            }
+            const float hb = head.b[0];
+            // lane group g reads x and the mask of rows 2 g, 2 g + 1 (all rows'
+            // loads in flight before the stores)
+            static_assert(MBW <= 8, "four lane groups, two rows each");
+            float xv[2], sv[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int m = (2 * g + k) % MBW, gy = y0 + ym0 + m;
+                xv[k] = 0.0f;
+                sv[k] = head.scale;
+                if (2 * g + k < MBW && gz < D && gy < H && gx < W) {
+                    const long long vox = (static_cast<long long>(gz) * H + gy) * W + gx;
+                    xv[k] = head.x[vox];
+                    if (head.mask) sv[k] = head.scale * head.mask[vox];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < MBW; ++m) {
+                const int gy = y0 + ym0 + m;
+                float a[4], p = 0.0f;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    a[j] = bf2f(f2bf(fmaxf(acc[m][0][j] + bco[j], 0.0f)));
+                    p = fmaf(hh[j], a[j], p);
+                }
+                p += __shfl_xor(p, 16, 64);
+                p += __shfl_xor(p, 32, 64);
+                if (gz >= D || gy >= H || gx >= W) continue;
+                const long long vox = (static_cast<long long>(gz) * H + gy) * W + gx;
+                if (g == (m >> 1)) {   // the lane group that loaded this row's x
+                    const int k = m & 1;
+                    head.out[vox] = fmaf(sv[k], hb + p, xv[k]);
+                }
+                if (head.write_act)
+                    store4<false, false, false>(out, vox * out_cs + out_off + 4 * g, a,
+                                                out_vec != 0);
+            }
+            return;
+        }
+    }
 #pragma unroll
     for (int n = 0; n < NB; ++n) {
         const int co0 = n * 16 + 4 * g;
@@ -1475,7 +1537,7 @@ inline bool vec_ok(const void *p, int cs, int off) {
 template <int CI, int CO, bool F32, bool RELU, bool ACC>
 hipError_t conv3_go(hipStream_t s, const u16 *ip, int in_cs, int in_off, const u16 *wp,
                     const float *bias, void *out, int out_cs, int out_off, int D, int H, int W,
-                    const CatArgs &cat) {
+                    const CatArgs &cat, const HeadArgs &head) {
     // four channels per store: 4-aligned channel slices of 16-byte aligned tensors
     const int out_vec = vec_ok(out, out_cs, out_off) && vec_ok(cat.out2, cat.out2_cs, cat.out2_off);
     const bool two_in = cat.ksplit < CI;
@@ -1495,13 +1557,13 @@ hipError_t conv3_go(hipStream_t s, const u16 *ip, int in_cs, int in_off, const u
             if constexpr (cat_shape<CI, CO>())
                 hipLaunchKernelGGL((conv3_tile_kernel<CI, CO, F32, RELU, ACC, true>), grid,
                                    dim3(NT), 0, s, ip, in_cs, in_off, wp, bias, out, out_cs,
-                                   out_off, D, H, W, out_vec, cat);
+                                   out_off, D, H, W, out_vec, cat, head);
             else
                 return hipErrorInvalidValue;
         } else {
             hipLaunchKernelGGL((conv3_tile_kernel<CI, CO, F32, RELU, ACC, false>), grid, dim3(NT),
                                0, s, ip, in_cs, in_off, wp, bias, out, out_cs, out_off, D, H, W,
-                               out_vec, cat);
+                               out_vec, cat, head);
         }
     }
     return hipGetLastError();
@@ -1512,8 +1574,10 @@ hipError_t conv3_pick(bool relu, bool acc, bool f32, hipStream_t s, const u16 *i
                       int in_off, const u16 *wp, const float *bias, void *out, int out_cs,
                       int out_off, int D, int H, int W, const CatArgs &cat) {
     const int k = (f32 ? 4 : 0) | (relu ? 2 : 0) | (acc ? 1 : 0);
+    const HeadArgs head{};   // no head
 #define GO(F, R, A) \
-    return conv3_go<CI, CO, F, R, A>(s, ip, in_cs, in_off, wp, bias, out, out_cs, out_off, D, H, W, cat)
+    return conv3_go<CI, CO, F, R, A>(s, ip, in_cs, in_off, wp, bias, out, out_cs, out_off, D, H, W, \
+                                     cat, head)
     switch (k) {
         case 0: GO(false, false, false);
         case 1: GO(false, false, true);
@@ -1566,6 +1630,32 @@ hipError_t launch_conv3(const void *in, int in_cs, int in_off, int cin_a, const 
     CASE(64, 64)
 #undef CASE
     return hipErrorInvalidValue;
+}
+
+// A 16 -> 16 ReLU convolution with the head folded in (see HeadArgs); `act`
+// (BF16, channel stride act_cs, offset act_off) receives the activations when
+// not NULL.
+hipError_t launch_conv3_head(const void *in, int in_cs, int in_off, const void *wt,
+                             const float *bias, void *act, int act_cs, int act_off, const float *h,
+                             const float *hb, const float *x, float scale, const float *mask,
+                             float *out, int D, int H, int W, hipStream_t s) {
+    CatArgs cat{};
+    cat.ksplit = 16;   // one input tensor
+    cat.nsplit = 16;   // one output tensor
+    cat.out2 = act;
+    cat.out2_cs = act_cs;
+    cat.out2_off = act_off;
+    HeadArgs head;
+    head.h = h;
+    head.b = hb;
+    head.x = x;
+    head.mask = mask;
+    head.scale = scale;
+    head.out = out;
+    head.write_act = act != nullptr;
+    return conv3_go<16, 16, false, true, false>(s, static_cast<const u16 *>(in), in_cs, in_off,
+                                                static_cast<const u16 *>(wt), bias, act, act_cs,
+                                                act_off, D, H, W, cat, head);
 }
 
 long long wgrad_chunk(long long nvox) {

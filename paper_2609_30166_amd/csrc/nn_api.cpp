@@ -16,6 +16,10 @@ hipError_t launch_conv3(const void *in, int in_cs, int in_off, int cin_a, const 
                         void *out, int out_cs, int out_off, int cout_a, void *out2, int out2_cs,
                         int out2_off, int cout_b, const void *gate, int gate_cs, int gate_off,
                         int D, int H, int W, bool relu, bool acc, bool out_f32, hipStream_t s);
+hipError_t launch_conv3_head(const void *in, int in_cs, int in_off, const void *wt,
+                             const float *bias, void *act, int act_cs, int act_off, const float *h,
+                             const float *hb, const float *x, float scale, const float *mask,
+                             float *out, int D, int H, int W, hipStream_t s);
 size_t conv3_wgrad_scratch(int cin, int cout, long long nvox);
 hipError_t launch_conv3_wgrad(const void *in, int in_cs, int in_off, int cin_a, const void *in2,
                               int in2_cs, int in2_off, int cin_b, const void *dout, int dout_cs,
@@ -175,6 +179,24 @@ int ctrex_nn_conv3_cat(ctrex_ctx *c, const void *in_a, int32_t a_cs, int32_t a_o
                                   D, H, W,
                                   flags & CTREX_NN_RELU, flags & CTREX_NN_ACCUMULATE,
                                   flags & CTREX_NN_OUT_F32, static_cast<hipStream_t>(stream)));
+    return CTREX_OK;
+}
+
+int ctrex_nn_conv3_head(ctrex_ctx *c, const void *in, int32_t in_cs, int32_t in_off,
+                        const void *wt, const float *bias, void *act, int32_t act_cs,
+                        int32_t act_off, const float *h, const float *hb, const float *x,
+                        float out_scale, const float *mask, float *out, int32_t D, int32_t H,
+                        int32_t W, void *stream) {
+    int st = begin(c);
+    if (st) return st;
+    if ((st = check_vol(c, D, H, W, false))) return st;
+    if ((st = check_slice(c, "in", in, in_cs, in_off, 16, true))) return st;
+    if (act && (st = check_slice(c, "act", act, act_cs, act_off, 16, false))) return st;
+    if (!wt || !h || !hb || !x || !out) return fail(c, CTREX_EINVAL, "NULL pointer");
+    if (!std::isfinite(out_scale)) return fail(c, CTREX_EINVAL, "out_scale must be finite");
+    CTREX_HIP(c, nn::launch_conv3_head(in, in_cs, in_off, wt, bias, act, act_cs, act_off, h, hb, x,
+                                       out_scale, mask, out, D, H, W,
+                                       static_cast<hipStream_t>(stream)));
     return CTREX_OK;
 }
 

@@ -288,9 +288,10 @@ class UNet:
         D, H, W = dims
         self._call("ctrex_nn_maxpool2", _vp(src), cs, off, c, _vp(dst), D, H, W, self._s())
 
-    def forward(self, x, out=None, train=False, mask=None):
+    def forward(self, x, out=None, train=False, mask=None, keep_acts=False):
         """x + m U(s x) / s for a float32 volume ``x`` [D][H][W] on the device;
-        ``mask``: optional float32 weights m of the same shape."""
+        ``mask``: optional float32 weights m of the same shape.  The last
+        decoder activations are stored only with ``train`` or ``keep_acts``."""
         if x.dtype != torch.float32 or x.device != self.device or not x.is_contiguous():
             raise ValueError("x must be a contiguous float32 tensor on %s" % self.device)
         if mask is not None and (mask.dtype != torch.float32 or mask.shape != x.shape or
@@ -314,19 +315,22 @@ class UNet:
         self._conv("d2b", b["a4"], 32, 0, b["d2"], 32, 0, l2)
         self._up("up1", b["d2"], b["u1"], 16, 0, l2)
         self._conv_cat("d1a", b["u1"], b["e1"], b["a5"], l1)
-        self._conv("d1b", b["a5"], 16, 0, b["d1"], 16, 0, l1)
         if out is None:
             out = torch.empty_like(x)
-        self._call("ctrex_nn_head", _vp(b["d1"]), 16, _vp(self.p("head.w")),
-                   _vp(self.p("head.b")), _vp(x), 1.0 / self.scale,
-                   _vp(mask) if mask is not None else None, _vp(out), n1, self._s())
+        # the last convolution with the head folded in; its activations are
+        # stored only for the backward pass and activations()
+        keep = train or keep_acts
+        self._call("ctrex_nn_conv3_head", _vp(b["a5"]), 16, 0, _vp(self._wt["d1b"]),
+                   _vp(self.p("d1b.b")), _vp(b["d1"]) if keep else None, 16, 0,
+                   _vp(self.p("head.w")), _vp(self.p("head.b")), _vp(x), 1.0 / self.scale,
+                   _vp(mask) if mask is not None else None, _vp(out), D, H, W, self._s())
         self._saved = (b, (l1, l2, l3), mask) if train else None
         return out
 
     def activations(self, x):
         """Run the forward pass and return the BF16 activations by name
         (channels-last [.., C] views), for inspection and tests."""
-        self.forward(x, train=False)
+        self.forward(x, train=False, keep_acts=True)
         D, H, W = x.shape
         b = self._buffers((D, H, W), False)
         dims = {1: (D, H, W), 2: (D // 2, H // 2, W // 2), 3: (D // 4, H // 4, W // 4)}

@@ -424,6 +424,46 @@ def test_maxpool2_relu_backward_is_the_two_calls(L, ctx, cs, off, c):
     np.testing.assert_array_equal(_host(fused), _host(two))
 
 
+@pytest.mark.parametrize("shape", [(4, 8, 16), (3, 10, 32)])
+@pytest.mark.parametrize("with_mask,with_act", [(False, True), (True, True), (True, False)])
+def test_conv3_head_is_conv_then_head(L, ctx, shape, with_mask, with_act):
+    """The 16 -> 16 ReLU convolution with the head folded in: the stored
+    activations equal ctrex_nn_conv3's bit for bit, the output equals
+    ctrex_nn_head on them up to the order of the 16 products' sum."""
+    n = int(np.prod(shape))
+    r = _rng(49, *shape)
+    a5 = _bf(r.normal(size=(n, 16)))
+    w = r.normal(0, 0.1, size=(16, 16, 27))
+    bias = r.normal(size=16).astype(np.float32).astype(np.float64)
+    h = r.normal(size=16).astype(np.float32).astype(np.float64)
+    hb = np.array([0.3])
+    x = r.normal(size=n).astype(np.float32).astype(np.float64)
+    m = (r.uniform(size=n) < 0.7).astype(np.float64)
+    wt, _ = _pack_conv(L, ctx, w)
+    ad, bd, hd, hbd, xd, md = _dev_bf(a5), _dev_f(bias), _dev_f(h), _dev_f(hb), _dev_f(x), _dev_f(m)
+    mp = _vp(md) if with_mask else None
+    d1 = torch.empty(n * 16, dtype=torch.bfloat16, device=DEV)
+    ref = torch.empty(n, dtype=torch.float32, device=DEV)
+    _call(L, ctx, "ctrex_nn_conv3", _vp(ad), 16, 0, 16, _vp(wt), _vp(bd), _vp(d1), 16, 0, 16,
+          *shape, L.NN_RELU, None)
+    _call(L, ctx, "ctrex_nn_head", _vp(d1), 16, _vp(hd), _vp(hbd), _vp(xd), 0.25, mp, _vp(ref), n,
+          None)
+    act = torch.full((n * 24,), 9.0, dtype=torch.bfloat16, device=DEV)   # slice at offset 8
+    out = torch.empty(n, dtype=torch.float32, device=DEV)
+    _call(L, ctx, "ctrex_nn_conv3_head", _vp(ad), 16, 0, _vp(wt), _vp(bd),
+          _vp(act) if with_act else None, 24, 8, _vp(hd), _vp(hbd), _vp(xd), 0.25, mp, _vp(out),
+          *shape, None)
+    got_act = _host(act).reshape(n, 24)
+    if with_act:
+        np.testing.assert_array_equal(got_act[:, 8:], _host(d1).reshape(n, 16))
+        assert np.all(got_act[:, :8] == 9.0)
+    else:
+        assert np.all(got_act == 9.0)
+    g, rf = _host(out), _host(ref)
+    corr = np.abs(rf - x).max()
+    assert np.abs(g - rf).max() <= 1e-6 * max(corr, 1.0), (np.abs(g - rf).max(), corr)
+
+
 @pytest.mark.parametrize("misaligned", [False, True])
 def test_head_relu_backward_is_head_backward_then_relu(L, ctx, misaligned):
     n = 4096
